@@ -1,0 +1,258 @@
+/*
+ * megapf.h -- C-ABI of libmegapf, an MI355X (gfx950) implementation of the
+ * correction hot path of the Gauss-Newton Stein particle filter of
+ * Koide, Oishi, Yokozuka, Banno, "MegaParticles: Range-based 6-DoF Monte
+ * Carlo Localization with GPU-Accelerated Stein Particle Filter", ICRA 2024.
+ *
+ * Problem (Sec. III-A): estimate the sensor pose T_t on a point-cloud map M
+ * from a scan P_t with a set of SE(3) particles X_t = {T_t^i}.
+ *
+ * Conventions shared by every call
+ *   - Status: 0 (MP_OK) or a negative MP_E_* code.  On error nothing the call
+ *     would have produced is modified, and mp_last_error() returns a message
+ *     for the calling thread.  A handle stays valid after an error.
+ *   - Pointers: every array argument may be a host pointer or a device pointer
+ *     of the current HIP device (unified addressing decides).  The library
+ *     never keeps a caller pointer: data is copied in stream order before the
+ *     call returns (host memory) or before the stream passes the copy (device
+ *     memory).  Outputs written to host memory are complete when the call
+ *     returns (the call synchronises the stream first).
+ *   - Streams: `stream` is a hipStream_t passed as void* (NULL = the null
+ *     stream).  From PyTorch on ROCm: torch.cuda.current_stream().cuda_stream.
+ *     Every call is asynchronous on that stream except where host outputs are
+ *     requested.
+ *   - Units: metres and radians.  Poses are (qw, qx, qy, qz, tx, ty, tz):
+ *     a Hamilton unit quaternion and a translation, mapping sensor-frame
+ *     points into the map frame.  Tangent vectors are [omega; v] (rotation
+ *     first, the order of the kernel weight W^K in Eq. 7) and perturb on the
+ *     right: T exp(delta) (Eq. 1 and Eq. 5).
+ *   - Handles are created and freed only by the library.  A map may serve
+ *     several filters and must outlive them.
+ */
+#ifndef MEGAPF_H
+#define MEGAPF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t mp_status;
+enum {
+    MP_OK = 0,
+    MP_E_ARG = -1,         /* invalid argument (null, size, non-finite value) */
+    MP_E_STATE = -2,       /* call not valid in the handle's current state */
+    MP_E_OOM = -3,         /* device allocation failed */
+    MP_E_HIP = -4,         /* HIP runtime error; the HIP message is in mp_last_error() */
+    MP_E_UNSUPPORTED = -5, /* valid request outside the implemented limits */
+    MP_E_NUMERIC = -6      /* a non-finite value appeared in the filter state */
+};
+
+typedef struct mp_map_s* mp_map;
+typedef struct mp_filter_s* mp_filter;
+
+/* ------------------------------------------------------------------ map */
+
+enum { MP_NNF_AUTO = 0, MP_NNF_HASH = 1, MP_NNF_DENSE = 2 };
+
+typedef struct {
+    float voxel;        /* voxel edge r in metres, > 0 */
+    int32_t nnf_radius; /* Chebyshev radius of the nearest-neighbour band, voxels, 0..8 */
+    int32_t min_points; /* voxels holding fewer map points are dropped, >= 3 */
+    float cov_eps;      /* GICP normalisation: Sigma = I - (1 - eps) n n^T, 0 < eps <= 1 */
+    int32_t backend;    /* MP_NNF_*: open-addressing voxel hash map or dense grid;
+                           AUTO picks DENSE when the band grid has <= 2^28 cells */
+} mp_map_params;
+
+typedef struct {
+    int64_t num_gauss;       /* occupied voxels kept (Gaussians) */
+    int64_t num_band;        /* voxels of the nearest-neighbour band */
+    int32_t grid_origin[3];  /* voxel coordinate of band-grid cell (0,0,0) */
+    int32_t grid_dim[3];     /* band-grid extent in voxels */
+    float box_min[3];        /* corners of the kept voxels, metres */
+    float box_max[3];
+    int32_t backend;         /* MP_NNF_HASH or MP_NNF_DENSE actually built */
+    int64_t table_slots;     /* hash slots or dense cells */
+    int64_t device_bytes;    /* device memory held by the map */
+} mp_map_info;
+
+/* Fill defaults: voxel 0.5, nnf_radius 2, min_points 5, cov_eps 1e-3, AUTO. */
+void mp_map_default_params(mp_map_params* p);
+
+/* Build the per-voxel Gaussian map and its nearest-neighbour field
+ * (Sec. III-C "Likelihood evaluation": each map point is a Gaussian
+ * N(mu, Sigma); m^nnf gives, for a voxel of space, the index of the nearest
+ * map Gaussian).
+ *   xyz   n x 3 float32 map points (host or device), row-major.
+ *   Points are grouped by voxel v = floor(p * (1/r)) (FP32).  A voxel with at
+ *   least min_points points yields one Gaussian: mean, and the GICP-normalised
+ *   covariance I - (1-eps) n n^T where n is the eigenvector of the smallest
+ *   eigenvalue of the 1/n sample covariance (Segal et al. 2009).  Gaussian ids
+ *   follow ascending (vz, vy, vx).  Every voxel within Chebyshev distance R of
+ *   a kept voxel maps to the kept voxel at the smallest integer squared
+ *   distance, ties to the smaller id; other voxels are misses.
+ * Errors: MP_E_ARG for n < 0, null, non-finite or out-of-range coordinates
+ * (|p / r| >= 2^30) or bad params; MP_E_UNSUPPORTED when the band grid exceeds
+ * 2^32 - 2 cells (hash) or 2^31 cells (dense).  n = 0 builds an empty map
+ * (every lookup misses). */
+mp_status mp_map_build(const float* xyz, int64_t n, const mp_map_params* params, void* stream, mp_map* out);
+
+mp_status mp_map_get_info(mp_map map, mp_map_info* out);
+
+/* Copy the Gaussians out: mu G x 3, normal G x 3 (unit eigenvector n of the
+ * GICP normalisation), voxel G x 3 (int32), count G (int32).  Any pointer may
+ * be null. */
+mp_status mp_map_get_gauss(mp_map map, float* mu, float* normal, int32_t* voxel, int32_t* count, void* stream);
+
+/* Nearest-neighbour field lookup of n points (the exact path the likelihood
+ * kernel takes): gid_out[i] = Gaussian id or -1. */
+mp_status mp_map_lookup(mp_map map, const float* xyz, int64_t n, int32_t* gid_out, void* stream);
+
+/* MP_E_STATE while a filter still uses the map. */
+mp_status mp_map_destroy(mp_map map);
+
+/* --------------------------------------------------------------- filter */
+
+typedef struct {
+    int32_t n_particles;  /* N^P, 1 .. 2^26 */
+    int32_t k;            /* K, neighbour-list length including the particle itself, 1..32 (Sec. III-C) */
+    int32_t lsh_bits;     /* N^B = 2^lsh_bits buckets, 0..30 (Eq. 9, Alg. 1) */
+    int32_t svgd_iters;   /* SVGD iterations per filter step, >= 0 */
+    int32_t post_iters;   /* rounds of the neighbour-graph propagation (Eq. 11), >= 0 */
+    int32_t window_c;     /* bucket-mates examined per particle and iteration, >= 0 */
+    int32_t scan_k;       /* neighbours for scan covariances, 3..32 */
+    float sigma_r;        /* W^K rotation weight, 1/rad (Eq. 7) */
+    float sigma_t;        /* W^K translation weight, 1/m */
+    float lsh_alpha;      /* alpha of Eq. 10 */
+    float lsh_sigma;      /* per-axis std of delta^LSH, in cells (Eq. 10) */
+    float c_max;          /* per-point cost cap; outliers cost c_max */
+    float d_max;          /* inlier gate on |mu^M - T mu^S|, metres */
+    float lambda_rel;     /* GN damping lambda = lambda_rel tr(H)/6 + lambda_abs */
+    float lambda_abs;
+    float temperature;    /* log-likelihood divisor in the posterior */
+    float prior_floor;    /* prior probabilities below this are raised to it */
+    float cov_eps;        /* GICP epsilon for scan covariances */
+    int32_t lik_chunks;   /* scan-point chunks per particle tile in the likelihood launch; 0 = auto */
+    int32_t reserved;
+    uint64_t seed;        /* Philox4x32-10 key */
+} mp_filter_params;
+
+/* Defaults: k 16, lsh_bits 20, svgd_iters 10, post_iters 10, window_c 32,
+ * scan_k 10, sigma_r 5, sigma_t 2.5, lsh_alpha 1, lsh_sigma 0.3, c_max 9,
+ * d_max 1.0, lambda_rel 1e-3, lambda_abs 1e-6, temperature 1,
+ * prior_floor 1e-30, cov_eps 1e-3, lik_chunks 0, seed 1. */
+void mp_filter_default_params(mp_filter_params* p);
+
+enum { MP_INIT_UNIFORM_BOX = 0, MP_INIT_EXPLICIT = 1 };
+
+typedef struct {
+    int32_t kind;        /* MP_INIT_* */
+    float box_min[3];    /* UNIFORM_BOX: translation box; rotation uniform on SO(3) */
+    float box_max[3];
+    const float* poses;  /* EXPLICIT: n_particles x 7 (host or device) */
+} mp_init_desc;
+
+/* Create a filter on `map`: N particles, prior 1/N, neighbour lists {i},
+ * frame 0 (Sec. III-A).  Uniform poses come from Philox(seed) with Shoemake's
+ * uniform rotations, so they are reproducible.  Explicit quaternions are
+ * normalised on input.  Errors: MP_E_ARG (params out of range, non-finite or
+ * zero quaternions), MP_E_OOM. */
+mp_status mp_filter_init(mp_map map, const mp_filter_params* params, const mp_init_desc* init, void* stream,
+                         mp_filter* out);
+
+mp_status mp_filter_destroy(mp_filter f);
+
+/* Upload the scan P_t (Sec. III-A) for the next filter steps.
+ *   xyz  n x 3 float32 points in the sensor frame.
+ *   cov6 n x 6 (xx, xy, xz, yy, yz, zz) scan covariances or NULL: then each
+ *        point gets the GICP-normalised covariance of itself and its scan_k
+ *        nearest scan points (ties to the lower index) (Sec. III-C, Segal et
+ *        al. 2009).
+ * n = 0 is legal (occlusion): steps then only predict.  Errors: MP_E_ARG for
+ * n < 0, null with n > 0, n > 65536 or non-finite values. */
+mp_status mp_scan_upload(mp_filter f, const float* xyz, const float* cov6, int32_t n, void* stream);
+
+/* One filter step.
+ *   Prediction (Eq. 1): T_i <- T_i dT exp(delta_i), delta_i ~ N(0, cov_dT)
+ *   drawn from Philox(seed; i, frame).  dT = NULL skips prediction; cov_dT =
+ *   NULL means no noise.  cov_dT is 6x6 row-major over [omega; v], symmetric
+ *   positive semi-definite.
+ *   Correction, svgd_iters times: LSH bucketing and neighbour-list refresh
+ *   (Eq. 9-10, Alg. 1), likelihood with Gauss-Newton H, b and psi (Eq. 2-4),
+ *   SVGD update over the neighbour lists (Eq. 5-8).
+ *   Posterior (Eq. 11): prior x likelihood of the last iteration, FP64
+ *   log-sum-exp, post_iters propagation rounds, renormalisation, argmax.
+ * Asynchronous; nothing synchronises the host.  Errors: MP_E_STATE before the
+ * first mp_scan_upload, MP_E_ARG for non-finite dT/cov_dT or a covariance that
+ * is not positive semi-definite. */
+mp_status mp_filter_step(mp_filter f, const float dT[7], const float cov_dT[36], void* stream);
+
+typedef struct {
+    float map_pose[7];     /* pose of the maximum-posterior particle (Sec. III-D) */
+    int32_t map_index;     /* its index */
+    double map_weight;     /* its posterior probability */
+    double n_eff;          /* 1 / sum p^2 */
+    double log_evidence;   /* log sum_i exp(l_i) before normalisation */
+    double max_loglik;     /* largest log-likelihood of the last iteration */
+    int32_t frame;         /* filter steps taken */
+    int32_t fp64_resolves; /* Gauss-Newton solves redone in FP64 in the last step */
+} mp_posterior;
+
+/* Read the representative state and, optionally, all poses (N x 7) and the
+ * posterior weights (N, FP64).  Synchronises `stream`.  MP_E_NUMERIC if a
+ * pose or weight is not finite. */
+mp_status mp_posterior_query(mp_filter f, mp_posterior* out, float* poses_out, double* weights_out, void* stream);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* mp_last_error(void);
+
+/* ----------------------------------------------------------- diagnostics */
+
+enum {
+    MP_STAGE_PREDICT = 0,  /* Eq. 1 */
+    MP_STAGE_LSH = 1,      /* Eq. 9-10: codes */
+    MP_STAGE_SORT = 2,     /* Alg. 1 distribute loop: stable sort + bucket bounds */
+    MP_STAGE_REFRESH = 3,  /* Alg. 1 gather loop: neighbour refresh + kernel values */
+    MP_STAGE_LIK = 4,      /* Eq. 2-4: likelihood, H, b, psi */
+    MP_STAGE_SVGD = 5,     /* Eq. 5-8 */
+    MP_STAGE_POSTERIOR = 6,/* Eq. 11 */
+    MP_STAGE_SCAN = 7,     /* scan covariances (mp_scan_upload) */
+    MP_NUM_STAGES = 8
+};
+
+/* Per-stage device time of the last mp_filter_step, milliseconds, from HIP
+ * events on the filter's stream (synchronises).  ms_out has MP_NUM_STAGES
+ * entries; stages not run read 0. */
+mp_status mp_stage_times(mp_filter f, float* ms_out);
+
+/* Test-only access to the filter state, by name, in the library's own layout:
+ *   "poses"   N x 8 float (qw,qx,qy,qz,tx,ty,tz,0), current buffer
+ *   "psi"     N x 8 float (psi[6], loglik, inlier count as float)
+ *   "hb"      N x 28 float (H upper 21 row-major, b 6, cost) of the last
+ *             likelihood pass; only written after set "capture_hb" = 1
+ *   "codes"   N uint32 LSH codes of the last LSH pass (particle order)
+ *   "sorted"  N int32 particle index at each sorted position
+ *   "scodes"  N uint32 codes in sorted order
+ *   "head", "end"  N int32 bucket bounds per sorted position
+ *   "nbr"     K x N int32 neighbour lists (column-major, -1 pads)
+ *   "kval"    K x N float kernel values k_ij (0 for pads)
+ *   "cnt"     N int32 list lengths
+ *   "prior"   N float prior probabilities
+ *   "post"    N float smoothed posterior of the last step
+ *   "scan"    n x 12 float scan records (mu, Sigma upper 6, pad)
+ *   "tlsh"    8 float T^LSH of the last LSH pass
+ *   "capture_hb"  int32 (set only)
+ * bytes must equal the named buffer's size.  mp_debug_stage runs one stage
+ * on the current state (iteration selects the LSH frame counter; dT/cov_dT as
+ * in mp_filter_step, used by MP_STAGE_PREDICT only). */
+mp_status mp_debug_get(mp_filter f, const char* name, void* dst, int64_t bytes, void* stream);
+mp_status mp_debug_set(mp_filter f, const char* name, const void* src, int64_t bytes, void* stream);
+mp_status mp_debug_stage(mp_filter f, int32_t stage, int32_t iteration, const float dT[7], const float cov_dT[36],
+                         void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MEGAPF_H */

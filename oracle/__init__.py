@@ -1,0 +1,356 @@
+"""CPU oracle for the Gauss-Newton Stein particle filter (Koide et al., ICRA 2024).
+
+TEST INFRASTRUCTURE ONLY.  Only the test-suite, ``__graft_entry__.smoke()`` and
+the CPU-baseline leg of ``bench.py`` import this package.  The product library
+(``paper_2404_16370_amd``) never imports, links or calls it, and this package
+never imports the product library.
+
+The arithmetic lives in ``mpo.c`` (plain C, FP64 for floating results, a
+deterministic FP32 program for every discrete decision).  This module only
+marshals numpy arrays through ctypes and composes the per-stage functions into
+one filter step in the order the paper times them (Table II): neighbour list
+update, likelihood evaluation, particle state update, posterior update.
+
+Parity status (what the CPU tests pin each function to) is listed in
+DESIGN-level documentation and in each test module's docstring; functions with
+no independent pin are called "parity unpinned" there.  Every function here is
+pinned except the end-to-end composition ``filter_step``, whose stages are each
+pinned separately.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+import sys
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "mpo.c")
+_LIB = os.path.join(_HERE, "libmpo.so")
+
+# Deterministic FP32 programs need: no contraction, no fast-math, SSE floats.
+CFLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-mavx2", "-mfma",
+          "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wno-unknown-pragmas"]
+
+
+def build(force: bool = True) -> str:
+    """Compile mpo.c into libmpo.so next to it (gcc)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        cmd = ["gcc", *CFLAGS, _SRC, "-o", tmp, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        _lib = C.CDLL(_LIB)
+        _declare(_lib)
+    return _lib
+
+
+_f32p = np.ctypeslib.ndpointer(dtype=np.float32, flags="C_CONTIGUOUS")
+_f64p = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+_i32p = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+_i64p = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
+_u32p = np.ctypeslib.ndpointer(dtype=np.uint32, flags="C_CONTIGUOUS")
+_vp = C.c_void_p
+
+
+def _declare(L):
+    L.mpo_philox.argtypes = [_u32p, _u32p, _u32p]
+    L.mpo_det_log.argtypes = [C.c_float]; L.mpo_det_log.restype = C.c_float
+    L.mpo_det_sincos2pi.argtypes = [C.c_float, C.POINTER(C.c_float), C.POINTER(C.c_float)]
+    L.mpo_det_rotvec_scale.argtypes = [C.c_float, C.c_float]; L.mpo_det_rotvec_scale.restype = C.c_float
+    L.mpo_det_qdist.argtypes = [_f32p, _f32p, C.c_float, C.c_float]; L.mpo_det_qdist.restype = C.c_float
+    L.mpo_gauss6.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, _f32p]
+    L.mpo_lsh_frame.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, _f32p, _f32p, _f32p]
+    L.mpo_init_uniform.argtypes = [C.c_uint64, C.c_int64, _f32p, _f32p, _f32p]
+    L.mpo_hash6.argtypes = [_i32p]; L.mpo_hash6.restype = C.c_uint32
+    L.mpo_lsh_codes.argtypes = [_f32p, C.c_int64, _f32p, C.c_float, C.c_float, C.c_float, C.c_float, C.c_int,
+                                C.c_uint64, C.c_uint32, C.c_uint32, _u32p, _vp]
+    L.mpo_eig3.argtypes = [_f64p, _f64p, _f64p]
+    L.mpo_voxel_of.argtypes = [_f32p, C.c_int64, C.c_float, _i32p]
+    L.mpo_map_build.argtypes = [_f32p, C.c_int64, C.c_float, C.c_int, C.c_int, C.c_float]
+    L.mpo_map_build.restype = _vp
+    L.mpo_map_free.argtypes = [_vp]
+    L.mpo_map_num_gauss.argtypes = [_vp]; L.mpo_map_num_gauss.restype = C.c_int64
+    L.mpo_map_num_band.argtypes = [_vp]; L.mpo_map_num_band.restype = C.c_int64
+    L.mpo_map_grid.argtypes = [_vp, _i32p, _i32p]
+    L.mpo_map_gauss.argtypes = [_vp, _i32p, _f32p, _f32p, _f64p, _f64p, _i32p]
+    L.mpo_map_band.argtypes = [_vp, _i64p, _i32p]
+    L.mpo_map_lookup.argtypes = [_vp, _f32p, C.c_int64, _i32p]
+    L.mpo_scan_cov.argtypes = [_f32p, C.c_int32, C.c_int32, C.c_float, _i32p, _f32p, _f64p]
+    L.mpo_gn_step.argtypes = [_f64p, _f64p, C.c_double, C.c_double, _f64p]; L.mpo_gn_step.restype = C.c_int
+    L.mpo_likelihood.argtypes = [_vp, _f32p, _f32p, C.c_int32, _f32p, C.c_int64, C.c_float, C.c_float,
+                                 C.c_double, C.c_double, _f64p, _f64p, _f64p, _f64p, _i32p]
+    L.mpo_bucket_sort.argtypes = [_u32p, C.c_int64, _i32p, _i32p, _i32p]
+    L.mpo_refresh.argtypes = [_f32p, C.c_int64, _i32p, _u32p, C.c_int32, C.c_int32, C.c_float, C.c_float, _vp,
+                              _i32p, _f32p, _i32p]
+    L.mpo_se3_exp.argtypes = [_f64p, _f64p]
+    L.mpo_se3_log.argtypes = [_f64p, _f64p]
+    L.mpo_se3_between.argtypes = [_f32p, _f32p, _f64p]
+    L.mpo_svgd.argtypes = [_f32p, C.c_int64, _f64p, _i32p, C.c_int32, C.c_float, C.c_float, _vp, _f64p]
+    L.mpo_posterior.argtypes = [_f64p, _f64p, C.c_int64, _i32p, _f64p, C.c_int32, C.c_int32, C.c_double,
+                                C.c_double, _vp, _f64p, C.POINTER(C.c_double)]
+    L.mpo_posterior.restype = C.c_int64
+    L.mpo_chol6.argtypes = [_f64p, _f64p]; L.mpo_chol6.restype = C.c_int
+    L.mpo_predict.argtypes = [_f32p, C.c_int64, _f32p, _vp, C.c_uint64, C.c_uint32, _f64p]
+    L.mpo_num_threads.restype = C.c_int
+
+
+def _f32(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    return a if shape is None else a.reshape(shape)
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+# --------------------------------------------------------------------- RNG / det math
+def philox(ctr, key):
+    out = np.zeros(4, np.uint32)
+    lib().mpo_philox(np.ascontiguousarray(ctr, np.uint32), np.ascontiguousarray(key, np.uint32), out)
+    return out
+
+
+def det_log(x: float) -> float:
+    return float(lib().mpo_det_log(C.c_float(x)))
+
+
+def det_sincos2pi(u: float):
+    s, c = C.c_float(), C.c_float()
+    lib().mpo_det_sincos2pi(C.c_float(u), C.byref(s), C.byref(c))
+    return float(s.value), float(c.value)
+
+
+def det_rotvec_scale(n: float, w: float) -> float:
+    return float(lib().mpo_det_rotvec_scale(C.c_float(n), C.c_float(w)))
+
+
+def det_qdist(Ti, Tj, sigma_r, sigma_t) -> float:
+    return float(lib().mpo_det_qdist(_f32(Ti), _f32(Tj), sigma_r, sigma_t))
+
+
+def gauss6(seed, a, b, c, purpose):
+    z = np.zeros(6, np.float32)
+    lib().mpo_gauss6(seed, a, b, c, purpose, z)
+    return z
+
+
+def hash6(cell) -> int:
+    return int(lib().mpo_hash6(np.ascontiguousarray(cell, np.int32)))
+
+
+def lsh_frame(seed, frame, it, lo, hi):
+    T = np.zeros(8, np.float32)
+    lib().mpo_lsh_frame(seed, frame, it, _f32(lo), _f32(hi), T)
+    return T
+
+
+def init_uniform(seed, n, lo, hi):
+    P = np.zeros((n, 8), np.float32)
+    lib().mpo_init_uniform(seed, n, _f32(lo), _f32(hi), P)
+    return P
+
+
+def lsh_codes(poses8, TL, alpha, sigma_r, sigma_t, sigma_lsh, bits, seed, frame, it, want_cells=False):
+    P = _f32(poses8)
+    n = P.shape[0]
+    codes = np.zeros(n, np.uint32)
+    cells = np.zeros((n, 6), np.int32) if want_cells else None
+    lib().mpo_lsh_codes(P, n, _f32(TL), alpha, sigma_r, sigma_t, sigma_lsh, bits, seed, frame, it, codes, _ptr(cells))
+    return (codes, cells) if want_cells else codes
+
+
+def eig3(S):
+    S = np.ascontiguousarray(S, np.float64).reshape(9)
+    w = np.zeros(3); V = np.zeros(9)
+    lib().mpo_eig3(S, w, V)
+    return w, V.reshape(3, 3)
+
+
+def voxel_of(p, r):
+    P = _f32(p).reshape(-1, 3)
+    out = np.zeros(P.shape, np.int32)
+    lib().mpo_voxel_of(P, P.shape[0], r, out)
+    return out
+
+
+# --------------------------------------------------------------------- map
+class Map:
+    """Per-voxel Gaussians and the banded nearest-neighbour field."""
+
+    def __init__(self, xyz, voxel, nnf_radius=2, min_points=5, cov_eps=1e-3):
+        P = _f32(xyz).reshape(-1, 3)
+        self.voxel = float(voxel)
+        self.handle = lib().mpo_map_build(P, P.shape[0], voxel, nnf_radius, min_points, cov_eps)
+        self.G = int(lib().mpo_map_num_gauss(self.handle))
+        self.nb = int(lib().mpo_map_num_band(self.handle))
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            lib().mpo_map_free(h)
+            self.handle = None
+
+    def grid(self):
+        org = np.zeros(3, np.int32); dim = np.zeros(3, np.int32)
+        lib().mpo_map_grid(self.handle, org, dim)
+        return org, dim
+
+    def gauss(self):
+        G = max(self.G, 1)
+        vox = np.zeros((G, 3), np.int32); mu = np.zeros((G, 3), np.float32); cov = np.zeros((G, 6), np.float32)
+        mu64 = np.zeros((G, 3)); cov64 = np.zeros((G, 6)); npts = np.zeros(G, np.int32)
+        lib().mpo_map_gauss(self.handle, vox, mu, cov, mu64, cov64, npts)
+        g = self.G
+        return dict(vox=vox[:g], mu=mu[:g], cov=cov[:g], mu64=mu64[:g], cov64=cov64[:g], npts=npts[:g])
+
+    def band(self):
+        nb = max(self.nb, 1)
+        k = np.zeros(nb, np.int64); g = np.zeros(nb, np.int32)
+        lib().mpo_map_band(self.handle, k, g)
+        return k[:self.nb], g[:self.nb]
+
+    def lookup(self, p):
+        P = _f32(p).reshape(-1, 3)
+        out = np.zeros(P.shape[0], np.int32)
+        if P.shape[0]:
+            lib().mpo_map_lookup(self.handle, P, P.shape[0], out)
+        return out
+
+
+# --------------------------------------------------------------------- scan
+def scan_cov(xyz, k=10, eps=1e-3):
+    P = _f32(xyz).reshape(-1, 3)
+    n = P.shape[0]
+    knn = np.zeros((max(n, 1), max(k, 1)), np.int32)
+    cov = np.zeros((max(n, 1), 6), np.float32)
+    cov64 = np.zeros((max(n, 1), 6))
+    if n:
+        lib().mpo_scan_cov(P, n, k, eps, knn, cov, cov64)
+    return knn[:n], cov[:n], cov64[:n]
+
+
+# --------------------------------------------------------------------- likelihood + GN
+def gn_step(H21, b, lam_rel, lam_abs):
+    psi = np.zeros(6)
+    rc = lib().mpo_gn_step(np.ascontiguousarray(H21, np.float64), np.ascontiguousarray(b, np.float64),
+                           lam_rel, lam_abs, psi)
+    return psi, rc
+
+
+def likelihood(m: Map, sxyz, scov, poses8, dmax, cmax, lam_rel=1e-3, lam_abs=1e-6):
+    S = _f32(sxyz).reshape(-1, 3)
+    SC = _f32(scov).reshape(-1, 6)
+    P = _f32(poses8).reshape(-1, 8)
+    n = P.shape[0]
+    out = dict(loglik=np.zeros(n), H21=np.zeros((n, 21)), b=np.zeros((n, 6)), psi=np.zeros((n, 6)),
+               ninl=np.zeros(n, np.int32))
+    if n:
+        lib().mpo_likelihood(m.handle, S, SC, S.shape[0], P, n, dmax, cmax, lam_rel, lam_abs,
+                             out["loglik"], out["H21"], out["b"], out["psi"], out["ninl"])
+    return out
+
+
+# --------------------------------------------------------------------- neighbours
+def bucket_sort(codes):
+    c = np.ascontiguousarray(codes, np.uint32)
+    n = c.shape[0]
+    s = np.zeros(n, np.int32); h = np.zeros(n, np.int32); e = np.zeros(n, np.int32)
+    if n:
+        lib().mpo_bucket_sort(c, n, s, h, e)
+    return s, h, e
+
+
+def refresh(poses8, sorted_idx, codes, K, C_win, sigma_r, sigma_t, old_nbr=None):
+    """old_nbr/nbr are (n, K) row-per-particle; -1 pads."""
+    P = _f32(poses8).reshape(-1, 8)
+    n = P.shape[0]
+    nbr = np.zeros((n, K), np.int32); q = np.zeros((n, K), np.float32); cnt = np.zeros(n, np.int32)
+    old = None if old_nbr is None else np.ascontiguousarray(old_nbr, np.int32).reshape(n, K)
+    lib().mpo_refresh(P, n, np.ascontiguousarray(sorted_idx, np.int32), np.ascontiguousarray(codes, np.uint32),
+                      K, C_win, sigma_r, sigma_t, _ptr(old), nbr, q, cnt)
+    return nbr, q, cnt
+
+
+# --------------------------------------------------------------------- SE(3)
+def se3_exp(xi):
+    T = np.zeros(7)
+    lib().mpo_se3_exp(np.ascontiguousarray(xi, np.float64), T)
+    return T
+
+
+def se3_log(T):
+    xi = np.zeros(6)
+    lib().mpo_se3_log(np.ascontiguousarray(T, np.float64), xi)
+    return xi
+
+
+def se3_between(Ti, Tj):
+    d = np.zeros(6)
+    lib().mpo_se3_between(_f32(Ti), _f32(Tj), d)
+    return d
+
+
+# --------------------------------------------------------------------- SVGD / posterior / prediction
+def svgd(poses8, psi, nbr, sigma_r, sigma_t):
+    P = _f32(poses8).reshape(-1, 8)
+    n = P.shape[0]
+    nb = np.ascontiguousarray(nbr, np.int32).reshape(n, -1)
+    phi = np.zeros((n, 6)); out = np.zeros((n, 7))
+    lib().mpo_svgd(P, n, np.ascontiguousarray(psi, np.float64).reshape(n, 6), nb, nb.shape[1], sigma_r, sigma_t,
+                   _ptr(phi), out)
+    return phi, out
+
+
+def posterior(prior, loglik, nbr, kval, rounds=10, tau=1.0, prior_floor=1e-30):
+    n = len(loglik)
+    nb = np.ascontiguousarray(nbr, np.int32).reshape(n, -1)
+    kv = np.ascontiguousarray(kval, np.float64).reshape(n, -1)
+    p0 = np.zeros(n); post = np.zeros(n); neff = C.c_double()
+    best = lib().mpo_posterior(np.ascontiguousarray(prior, np.float64), np.ascontiguousarray(loglik, np.float64),
+                               n, nb, kv, nb.shape[1], rounds, tau, prior_floor, _ptr(p0), post, C.byref(neff))
+    return dict(p0=p0, post=post, map_index=int(best), n_eff=float(neff.value))
+
+
+def chol6(A):
+    L = np.zeros(36)
+    rc = lib().mpo_chol6(np.ascontiguousarray(A, np.float64).reshape(36), L)
+    return L.reshape(6, 6), rc
+
+
+def predict(poses8, dT, cov, seed, frame):
+    P = _f32(poses8).reshape(-1, 8)
+    n = P.shape[0]
+    out = np.zeros((n, 7))
+    cv = None if cov is None else _f32(cov).reshape(36)
+    lib().mpo_predict(P, n, _f32(dT).reshape(7), _ptr(cv), seed, frame, out)
+    return out
+
+
+def num_threads() -> int:
+    return int(lib().mpo_num_threads())
+
+
+def poses7_to_8(p7):
+    p7 = np.asarray(p7)
+    out = np.zeros((p7.shape[0], 8), np.float32)
+    out[:, :7] = p7
+    return out
+
+
+if __name__ == "__main__":  # pragma: no cover
+    print(build())
+    sys.exit(0)
