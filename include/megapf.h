@@ -34,6 +34,12 @@
 
 #include <stdint.h>
 
+#if defined(__GNUC__)
+#define MP_API __attribute__((visibility("default")))
+#else
+#define MP_API
+#endif
+
 #ifdef __cplusplus
 extern "C" {
 #endif
@@ -78,7 +84,7 @@ typedef struct {
 } mp_map_info;
 
 /* Fill defaults: voxel 0.5, nnf_radius 2, min_points 5, cov_eps 1e-3, AUTO. */
-void mp_map_default_params(mp_map_params* p);
+MP_API void mp_map_default_params(mp_map_params* p);
 
 /* Build the per-voxel Gaussian map and its nearest-neighbour field
  * (Sec. III-C "Likelihood evaluation": each map point is a Gaussian
@@ -96,21 +102,21 @@ void mp_map_default_params(mp_map_params* p);
  * (|p / r| >= 2^30) or bad params; MP_E_UNSUPPORTED when the band grid exceeds
  * 2^32 - 2 cells (hash) or 2^31 cells (dense).  n = 0 builds an empty map
  * (every lookup misses). */
-mp_status mp_map_build(const float* xyz, int64_t n, const mp_map_params* params, void* stream, mp_map* out);
+MP_API mp_status mp_map_build(const float* xyz, int64_t n, const mp_map_params* params, void* stream, mp_map* out);
 
-mp_status mp_map_get_info(mp_map map, mp_map_info* out);
+MP_API mp_status mp_map_get_info(mp_map map, mp_map_info* out);
 
 /* Copy the Gaussians out: mu G x 3, normal G x 3 (unit eigenvector n of the
  * GICP normalisation), voxel G x 3 (int32), count G (int32).  Any pointer may
  * be null. */
-mp_status mp_map_get_gauss(mp_map map, float* mu, float* normal, int32_t* voxel, int32_t* count, void* stream);
+MP_API mp_status mp_map_get_gauss(mp_map map, float* mu, float* normal, int32_t* voxel, int32_t* count, void* stream);
 
 /* Nearest-neighbour field lookup of n points (the exact path the likelihood
  * kernel takes): gid_out[i] = Gaussian id or -1. */
-mp_status mp_map_lookup(mp_map map, const float* xyz, int64_t n, int32_t* gid_out, void* stream);
+MP_API mp_status mp_map_lookup(mp_map map, const float* xyz, int64_t n, int32_t* gid_out, void* stream);
 
 /* MP_E_STATE while a filter still uses the map. */
-mp_status mp_map_destroy(mp_map map);
+MP_API mp_status mp_map_destroy(mp_map map);
 
 /* --------------------------------------------------------------- filter */
 
@@ -142,7 +148,7 @@ typedef struct {
  * scan_k 10, sigma_r 5, sigma_t 2.5, lsh_alpha 1, lsh_sigma 0.3, c_max 9,
  * d_max 1.0, lambda_rel 1e-3, lambda_abs 1e-6, temperature 1,
  * prior_floor 1e-30, cov_eps 1e-3, lik_chunks 0, seed 1. */
-void mp_filter_default_params(mp_filter_params* p);
+MP_API void mp_filter_default_params(mp_filter_params* p);
 
 enum { MP_INIT_UNIFORM_BOX = 0, MP_INIT_EXPLICIT = 1 };
 
@@ -158,10 +164,10 @@ typedef struct {
  * uniform rotations, so they are reproducible.  Explicit quaternions are
  * normalised on input.  Errors: MP_E_ARG (params out of range, non-finite or
  * zero quaternions), MP_E_OOM. */
-mp_status mp_filter_init(mp_map map, const mp_filter_params* params, const mp_init_desc* init, void* stream,
+MP_API mp_status mp_filter_init(mp_map map, const mp_filter_params* params, const mp_init_desc* init, void* stream,
                          mp_filter* out);
 
-mp_status mp_filter_destroy(mp_filter f);
+MP_API mp_status mp_filter_destroy(mp_filter f);
 
 /* Upload the scan P_t (Sec. III-A) for the next filter steps.
  *   xyz  n x 3 float32 points in the sensor frame.
@@ -171,7 +177,7 @@ mp_status mp_filter_destroy(mp_filter f);
  *        al. 2009).
  * n = 0 is legal (occlusion): steps then only predict.  Errors: MP_E_ARG for
  * n < 0, null with n > 0, n > 65536 or non-finite values. */
-mp_status mp_scan_upload(mp_filter f, const float* xyz, const float* cov6, int32_t n, void* stream);
+MP_API mp_status mp_scan_upload(mp_filter f, const float* xyz, const float* cov6, int32_t n, void* stream);
 
 /* One filter step.
  *   Prediction (Eq. 1): T_i <- T_i dT exp(delta_i), delta_i ~ N(0, cov_dT)
@@ -186,7 +192,7 @@ mp_status mp_scan_upload(mp_filter f, const float* xyz, const float* cov6, int32
  * Asynchronous; nothing synchronises the host.  Errors: MP_E_STATE before the
  * first mp_scan_upload, MP_E_ARG for non-finite dT/cov_dT or a covariance that
  * is not positive semi-definite. */
-mp_status mp_filter_step(mp_filter f, const float dT[7], const float cov_dT[36], void* stream);
+MP_API mp_status mp_filter_step(mp_filter f, const float dT[7], const float cov_dT[36], void* stream);
 
 typedef struct {
     float map_pose[7];     /* pose of the maximum-posterior particle (Sec. III-D) */
@@ -202,10 +208,10 @@ typedef struct {
 /* Read the representative state and, optionally, all poses (N x 7) and the
  * posterior weights (N, FP64).  Synchronises `stream`.  MP_E_NUMERIC if a
  * pose or weight is not finite. */
-mp_status mp_posterior_query(mp_filter f, mp_posterior* out, float* poses_out, double* weights_out, void* stream);
+MP_API mp_status mp_posterior_query(mp_filter f, mp_posterior* out, float* poses_out, double* weights_out, void* stream);
 
 /* Message of the last failing call on this thread ("" if none). */
-const char* mp_last_error(void);
+MP_API const char* mp_last_error(void);
 
 /* ----------------------------------------------------------- diagnostics */
 
@@ -218,13 +224,16 @@ enum {
     MP_STAGE_SVGD = 5,     /* Eq. 5-8 */
     MP_STAGE_POSTERIOR = 6,/* Eq. 11 */
     MP_STAGE_SCAN = 7,     /* scan covariances (mp_scan_upload) */
-    MP_NUM_STAGES = 8
+    MP_STAGE_LIK_CORE = 8, /* the likelihood accumulation kernel alone (inside MP_STAGE_LIK) */
+    MP_NUM_STAGES = 9
 };
 
-/* Per-stage device time of the last mp_filter_step, milliseconds, from HIP
- * events on the filter's stream (synchronises).  ms_out has MP_NUM_STAGES
- * entries; stages not run read 0. */
-mp_status mp_stage_times(mp_filter f, float* ms_out);
+/* Per-stage device time of the last mp_filter_step (scan stage: of the last
+ * mp_scan_upload), milliseconds, summed over the step's iterations, from HIP
+ * event pairs recorded on the call's stream around each stage's launches
+ * (synchronises).  ms_out has MP_NUM_STAGES entries; stages not run read 0.
+ * counts_out (nullable, MP_NUM_STAGES) receives the number of timed spans. */
+MP_API mp_status mp_stage_times(mp_filter f, float* ms_out, int32_t* counts_out);
 
 /* Test-only access to the filter state, by name, in the library's own layout:
  *   "poses"   N x 8 float (qw,qx,qy,qz,tx,ty,tz,0), current buffer
@@ -246,9 +255,9 @@ mp_status mp_stage_times(mp_filter f, float* ms_out);
  * bytes must equal the named buffer's size.  mp_debug_stage runs one stage
  * on the current state (iteration selects the LSH frame counter; dT/cov_dT as
  * in mp_filter_step, used by MP_STAGE_PREDICT only). */
-mp_status mp_debug_get(mp_filter f, const char* name, void* dst, int64_t bytes, void* stream);
-mp_status mp_debug_set(mp_filter f, const char* name, const void* src, int64_t bytes, void* stream);
-mp_status mp_debug_stage(mp_filter f, int32_t stage, int32_t iteration, const float dT[7], const float cov_dT[36],
+MP_API mp_status mp_debug_get(mp_filter f, const char* name, void* dst, int64_t bytes, void* stream);
+MP_API mp_status mp_debug_set(mp_filter f, const char* name, const void* src, int64_t bytes, void* stream);
+MP_API mp_status mp_debug_stage(mp_filter f, int32_t stage, int32_t iteration, const float dT[7], const float cov_dT[36],
                          void* stream);
 
 #ifdef __cplusplus

@@ -746,7 +746,7 @@ MPO_API void mpo_scan_cov(const float* xyz, int32_t n, int32_t k, float eps, int
 /*   and -c_max per outlier;  J_k = de_k/d delta for T exp(delta),          */
 /*   delta = [omega; v]  =>  J_k = [R [mu^S]x , -R];                        */
 /*   H = sum J^T Omega J, b = sum J^T Omega e (inliers, Omega held fixed);   */
-/*   psi = -(H + lambda I)^-1 b, lambda = lam_rel tr(H)/6 + lam_abs.         */
+/*   psi = -(H + diag(lam_rel H_ii + lam_abs))^-1 b.                       */
 /* ======================================================================= */
 static int chol6_solve(const double A_in[36], const double b[6], double x[6]) {
     double L[36];
@@ -782,9 +782,8 @@ MPO_API int mpo_gn_step(const double H21[21], const double b[6], double lam_rel,
     int q = 0;
     for (int i = 0; i < 6; ++i)
         for (int j = i; j < 6; ++j) { A[6 * i + j] = H21[q]; A[6 * j + i] = H21[q]; ++q; }
-    double tr = A[0] + A[7] + A[14] + A[21] + A[28] + A[35];
-    double lam = lam_rel * tr / 6.0 + lam_abs;
-    for (int i = 0; i < 6; ++i) A[6 * i + i] += lam;
+    /* Levenberg-Marquardt damping scaled by the diagonal (Marquardt 1963) */
+    for (int i = 0; i < 6; ++i) A[6 * i + i] += lam_rel * A[6 * i + i] + lam_abs;
     double nb[6];
     for (int i = 0; i < 6; ++i) nb[i] = -b[i];
     int rc = chol6_solve(A, nb, psi);

@@ -1,0 +1,359 @@
+// likelihood.hip -- per-particle GICP log-likelihood, Gauss-Newton H, b and
+// the displacement psi (Eq. 2-4).
+//
+// For particle T = (R, t) and scan point k with Gaussian N(mu_k, Sigma^S_k):
+//   p = R mu + t  (FP32, fixed fma order: it decides the voxel)
+//   g = m^nnf(floor(p / r)),  e = mu^M_g - p,  inlier iff g exists and
+//   |e|^2 <= d_max^2 (both FP32 decisions)
+//   Omega = (Sigma^M_g + R Sigma^S R^T)^-1,  c = e^T Omega e
+//   log-lik = -(sum_inliers min(c, c_max) + c_max * outliers)
+//   J = de/d delta for T exp(delta), delta = [omega; v]:  J = R [[mu]x, -I]
+//   H = sum J^T Omega J,  b = sum J^T Omega e  (inliers, Omega held fixed)
+// Everything is evaluated in the body frame of the particle:
+//   e_b = R^T e, Omega_b = R^T Omega R = (Sigma^S + R^T Sigma^M R)^-1 and
+//   J_b = [[mu]x, -I], so H_vv = Omega_b, H_wv = [mu]x Omega_b,
+//   H_ww = -[mu]x Omega_b [mu]x, b_w = (Omega_b e_b) x mu, b_v = -Omega_b e_b.
+// Map Gaussians are GICP-normalised, Sigma^M = I - a n n^T with a = 1 - eps,
+// so R^T Sigma^M R = I - a u u^T with u = R^T n (no 3x3 rotation of Sigma^M).
+//
+// Launch shape: one lane per particle, particles taken in LSH-sorted order so
+// that similar poses share a wavefront (their transformed points hit the same
+// voxels and cache lines); 256 lanes per workgroup; scan points streamed
+// through LDS in tiles of 256 records and read as wave-uniform broadcasts;
+// scan points split into chunks over extra workgroups when N is small, with
+// FP32 partial sums per chunk combined by compensated (Kahan) summation in the
+// solve kernel.  Workgroup ids are remapped so that each of the 8 XCDs (each
+// with its own L2) takes a contiguous range of sorted particles.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "mp_det.hpp"
+#include "mp_internal.hpp"
+#include "mp_lookup.hpp"
+
+namespace {
+
+constexpr int kLanes = 256;   // particles per workgroup
+constexpr int kTile = 256;    // scan records per LDS tile
+constexpr int kNumPartial = 29;  // H 21, b 6, inlier cost, outlier count
+
+struct LikArgs {
+    MapView map;
+    const float4* __restrict__ poses;   // N x 2 float4 (q; t, 0)
+    const int32_t* __restrict__ order;  // sorted position -> particle (or null)
+    const float4* __restrict__ scan;    // ns x 3 float4 records
+    float* __restrict__ partial;        // [chunk][29][N]
+    int32_t n, ns, chunk_len, nchunks, nbx;
+    float dmax2, cmax;
+};
+
+__device__ inline int remap_xcd(int bid, int nb) {
+    // dispatch places workgroup bid on XCD bid % 8; give each XCD a contiguous range
+    const int x = bid & 7, k = bid >> 3;
+    const int q = nb >> 3, r = nb & 7;
+    return x * q + min(x, r) + k;
+}
+
+__global__ __launch_bounds__(kLanes) void k_lik(LikArgs A) {
+    __shared__ float4 tile[kTile * 3];
+    const int nb = A.nbx * A.nchunks;
+    const int logical = remap_xcd(blockIdx.x, nb);
+    const int chunk = logical / A.nbx;
+    const int pblk = logical - chunk * A.nbx;
+    const int s = pblk * kLanes + threadIdx.x;
+    const bool active = s < A.n;
+    const int i = active ? (A.order ? A.order[s] : s) : 0;
+
+    const float4 q4 = A.poses[2 * i];
+    const float4 t4 = A.poses[2 * i + 1];
+    const mpdet::mat3 Rm = mpdet::qmat(mpdet::quat{q4.x, q4.y, q4.z, q4.w});
+    const float* R = Rm.m;
+    const float3 t = make_float3(t4.x, t4.y, t4.z);
+    const float a = A.map.gicp_a;
+
+    float h[21];
+#pragma unroll
+    for (int m = 0; m < 21; ++m) h[m] = 0.0f;
+    float bw0 = 0, bw1 = 0, bw2 = 0, oe0 = 0, oe1 = 0, oe2 = 0;
+    float cost = 0.0f, comp = 0.0f, nout = 0.0f;
+
+    const int k0 = chunk * A.chunk_len;
+    const int k1 = min(A.ns, k0 + A.chunk_len);
+    for (int kt = k0; kt < k1; kt += kTile) {
+        const int cnt = min(kTile, k1 - kt);
+        __syncthreads();
+        for (int j = threadIdx.x; j < cnt * 3; j += kLanes) {
+            float4 v = A.scan[(size_t)kt * 3 + j];
+            // fold the identity of Sigma^M = I - a n n^T into the scan covariance
+            const int c = j % 3;
+            if (c == 0) v.w += 1.0f;
+            else if (c == 1) v.z += 1.0f;
+            else v.x += 1.0f;
+            tile[j] = v;
+        }
+        __syncthreads();
+        if (!active) continue;
+        for (int k = 0; k < cnt; ++k) {
+            const float4 r0 = tile[3 * k], r1 = tile[3 * k + 1], r2 = tile[3 * k + 2];
+            const float3 mu = make_float3(r0.x, r0.y, r0.z);
+            const float3 p = mpdet::xform(R, t, mu);
+            const int32_t g = mp_nnf_lookup(A.map, p.x, p.y, p.z);
+            bool inl = g >= 0;
+            float4 gm = make_float4(0, 0, 0, 0), gn = make_float4(0, 0, 0, 0);
+            float ex = 0, ey = 0, ez = 0;
+            if (inl) {
+                gm = A.map.gauss[2 * g];
+                gn = A.map.gauss[2 * g + 1];
+                ex = gm.x - p.x;
+                ey = gm.y - p.y;
+                ez = gm.z - p.z;
+                const float d2 = __builtin_fmaf(ex, ex, __builtin_fmaf(ey, ey, ez * ez));
+                inl = d2 <= A.dmax2;
+            }
+            if (!inl) {
+                nout += 1.0f;
+                continue;
+            }
+            // ---- tolerance path (contraction allowed by explicit fma) ----
+            const float3 u = mpdet::rot_t(Rm, make_float3(gn.x, gn.y, gn.z));
+            const float3 eb = mpdet::rot_t(Rm, make_float3(ex, ey, ez));
+            const float aux = a * u.x, auy = a * u.y, auz = a * u.z;
+            // C = Sigma^S + I - a u u^T
+            const float c00 = __builtin_fmaf(-aux, u.x, r0.w);
+            const float c01 = __builtin_fmaf(-aux, u.y, r1.x);
+            const float c02 = __builtin_fmaf(-aux, u.z, r1.y);
+            const float c11 = __builtin_fmaf(-auy, u.y, r1.z);
+            const float c12 = __builtin_fmaf(-auy, u.z, r1.w);
+            const float c22 = __builtin_fmaf(-auz, u.z, r2.x);
+            // adjugate and determinant
+            const float i00 = __builtin_fmaf(c11, c22, -c12 * c12);
+            const float i01 = __builtin_fmaf(c02, c12, -c01 * c22);
+            const float i02 = __builtin_fmaf(c01, c12, -c02 * c11);
+            const float i11 = __builtin_fmaf(c00, c22, -c02 * c02);
+            const float i12 = __builtin_fmaf(c01, c02, -c00 * c12);
+            const float i22 = __builtin_fmaf(c00, c11, -c01 * c01);
+            const float det = __builtin_fmaf(c00, i00, __builtin_fmaf(c01, i01, c02 * i02));
+            const float rd = __builtin_amdgcn_rcpf(det);
+            const float o00 = i00 * rd, o01 = i01 * rd, o02 = i02 * rd, o11 = i11 * rd, o12 = i12 * rd,
+                        o22 = i22 * rd;
+            // Omega e and the cost
+            const float w0 = __builtin_fmaf(o00, eb.x, __builtin_fmaf(o01, eb.y, o02 * eb.z));
+            const float w1 = __builtin_fmaf(o01, eb.x, __builtin_fmaf(o11, eb.y, o12 * eb.z));
+            const float w2 = __builtin_fmaf(o02, eb.x, __builtin_fmaf(o12, eb.y, o22 * eb.z));
+            const float cst = __builtin_fmaf(eb.x, w0, __builtin_fmaf(eb.y, w1, eb.z * w2));
+            {
+                const float y = fminf(cst, A.cmax) - comp;
+                const float tt = cost + y;
+                comp = (tt - cost) - y;
+                cost = tt;
+            }
+            // b_v = -Omega e (negated at the end), b_w = (Omega e) x mu
+            oe0 += w0;
+            oe1 += w1;
+            oe2 += w2;
+            bw0 = __builtin_fmaf(w1, mu.z, __builtin_fmaf(-w2, mu.y, bw0));
+            bw1 = __builtin_fmaf(w2, mu.x, __builtin_fmaf(-w0, mu.z, bw1));
+            bw2 = __builtin_fmaf(w0, mu.y, __builtin_fmaf(-w1, mu.x, bw2));
+            // B = [mu]x Omega (rows): row0 = -mu_z O_1 + mu_y O_2, row1 = mu_z O_0 - mu_x O_2,
+            //                          row2 = -mu_y O_0 + mu_x O_1
+            const float B00 = __builtin_fmaf(-mu.z, o01, mu.y * o02);
+            const float B01 = __builtin_fmaf(-mu.z, o11, mu.y * o12);
+            const float B02 = __builtin_fmaf(-mu.z, o12, mu.y * o22);
+            const float B10 = __builtin_fmaf(mu.z, o00, -mu.x * o02);
+            const float B11 = __builtin_fmaf(mu.z, o01, -mu.x * o12);
+            const float B12 = __builtin_fmaf(mu.z, o02, -mu.x * o22);
+            const float B20 = __builtin_fmaf(-mu.y, o00, mu.x * o01);
+            const float B21 = __builtin_fmaf(-mu.y, o01, mu.x * o11);
+            const float B22 = __builtin_fmaf(-mu.y, o02, mu.x * o12);
+            // H_ww = -B [mu]x : (B[mu]x)_{r0} = B_r1 mu_z - B_r2 mu_y, _{r1} = B_r2 mu_x - B_r0 mu_z,
+            //                   _{r2} = B_r0 mu_y - B_r1 mu_x
+            h[0] = __builtin_fmaf(-B01, mu.z, __builtin_fmaf(B02, mu.y, h[0]));
+            h[1] = __builtin_fmaf(-B02, mu.x, __builtin_fmaf(B00, mu.z, h[1]));
+            h[2] = __builtin_fmaf(-B00, mu.y, __builtin_fmaf(B01, mu.x, h[2]));
+            h[6] = __builtin_fmaf(-B12, mu.x, __builtin_fmaf(B10, mu.z, h[6]));
+            h[7] = __builtin_fmaf(-B10, mu.y, __builtin_fmaf(B11, mu.x, h[7]));
+            h[11] = __builtin_fmaf(-B20, mu.y, __builtin_fmaf(B21, mu.x, h[11]));
+            // H_wv = B
+            h[3] += B00; h[4] += B01; h[5] += B02;
+            h[8] += B10; h[9] += B11; h[10] += B12;
+            h[12] += B20; h[13] += B21; h[14] += B22;
+            // H_vv = Omega
+            h[15] += o00; h[16] += o01; h[17] += o02;
+            h[18] += o11; h[19] += o12; h[20] += o22;
+        }
+    }
+    if (!active) return;
+    float* out = A.partial + (size_t)chunk * kNumPartial * A.n + i;
+    const size_t st = (size_t)A.n;
+#pragma unroll
+    for (int m = 0; m < 21; ++m) out[m * st] = h[m];
+    out[21 * st] = bw0;
+    out[22 * st] = bw1;
+    out[23 * st] = bw2;
+    out[24 * st] = -oe0;
+    out[25 * st] = -oe1;
+    out[26 * st] = -oe2;
+    out[27 * st] = cost;
+    out[28 * st] = nout;
+}
+
+struct SolveArgs {
+    const float* __restrict__ partial;
+    float4* __restrict__ psi;   // N x 2 float4: (psi0..3), (psi4, psi5, loglik, inliers)
+    float* __restrict__ hb;     // N x 28 or null
+    int32_t* __restrict__ flags; // [0]: FP64 re-solves
+    int32_t n, nchunks, ns;
+    float cmax, lam_rel, lam_abs;
+};
+
+// Damped Gauss-Newton step psi = -(H + diag(lam_rel H_ii + lam_abs))^-1 b,
+// solved as a Cholesky factorisation of the diagonally scaled system.
+template <class T>
+__device__ bool chol_solve6(const T Hs[21], const T b[6], T lam_rel, T lam_abs, T psi[6], T& kappa) {
+    T A[6][6];
+    int q = 0;
+    for (int r = 0; r < 6; ++r)
+        for (int c = r; c < 6; ++c) {
+            A[r][c] = Hs[q];
+            A[c][r] = Hs[q];
+            ++q;
+        }
+    T d[6];
+    for (int r = 0; r < 6; ++r) {
+        A[r][r] = A[r][r] + (lam_rel * A[r][r] + lam_abs);
+        if (!(A[r][r] > T(0))) return false;
+        d[r] = T(1) / sqrt(A[r][r]);
+    }
+    for (int r = 0; r < 6; ++r)
+        for (int c = 0; c < 6; ++c) A[r][c] = A[r][c] * d[r] * d[c];
+    T L[6][6];
+    T lmin = T(1e30), lmax = T(0);
+    for (int j = 0; j < 6; ++j) {
+        T s = A[j][j];
+        for (int k = 0; k < j; ++k) s -= L[j][k] * L[j][k];
+        if (!(s > T(0))) return false;
+        const T ljj = sqrt(s);
+        L[j][j] = ljj;
+        lmin = ljj < lmin ? ljj : lmin;
+        lmax = ljj > lmax ? ljj : lmax;
+        for (int i = j + 1; i < 6; ++i) {
+            T t = A[i][j];
+            for (int k = 0; k < j; ++k) t -= L[i][k] * L[j][k];
+            L[i][j] = t / ljj;
+        }
+    }
+    kappa = (lmax / lmin) * (lmax / lmin);
+    T y[6];
+    for (int i = 0; i < 6; ++i) {
+        T t = -b[i] * d[i];
+        for (int k = 0; k < i; ++k) t -= L[i][k] * y[k];
+        y[i] = t / L[i][i];
+    }
+    T x[6];
+    for (int i = 5; i >= 0; --i) {
+        T t = y[i];
+        for (int k = i + 1; k < 6; ++k) t -= L[k][i] * x[k];
+        x[i] = t / L[i][i];
+    }
+    for (int i = 0; i < 6; ++i) psi[i] = x[i] * d[i];
+    return true;
+}
+
+__global__ __launch_bounds__(256) void k_solve(SolveArgs A) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= A.n) return;
+    // compensated sum of the chunk partials
+    float v[kNumPartial], c[kNumPartial];
+#pragma unroll
+    for (int m = 0; m < kNumPartial; ++m) {
+        v[m] = 0.0f;
+        c[m] = 0.0f;
+    }
+    for (int ch = 0; ch < A.nchunks; ++ch) {
+        const float* src = A.partial + (size_t)ch * kNumPartial * A.n + i;
+#pragma unroll
+        for (int m = 0; m < kNumPartial; ++m) {
+            const float y = src[(size_t)m * A.n] - c[m];
+            const float t = v[m] + y;
+            c[m] = (t - v[m]) - y;
+            v[m] = t;
+        }
+    }
+    const float nout = v[28];
+    const float loglik = -(v[27] + nout * A.cmax);
+    float psi[6];
+    float kappa = 0.0f;
+    bool ok = chol_solve6<float>(v, v + 21, A.lam_rel, A.lam_abs, psi, kappa);
+    for (int m = 0; m < 6; ++m) ok = ok && isfinite(psi[m]);
+    if (!ok || kappa > 1.0e6f) {
+        double H64[21], b64[6], p64[6], k64 = 0.0;
+        for (int m = 0; m < 21; ++m) H64[m] = v[m];
+        for (int m = 0; m < 6; ++m) b64[m] = v[21 + m];
+        const bool ok64 = chol_solve6<double>(H64, b64, (double)A.lam_rel, (double)A.lam_abs, p64, k64);
+        for (int m = 0; m < 6; ++m) psi[m] = ok64 ? (float)p64[m] : 0.0f;
+        atomicAdd(&A.flags[0], 1);
+    }
+    A.psi[2 * i] = make_float4(psi[0], psi[1], psi[2], psi[3]);
+    A.psi[2 * i + 1] = make_float4(psi[4], psi[5], loglik, (float)A.ns - nout);
+    if (A.hb) {
+        float* o = A.hb + (size_t)i * 28;
+        for (int m = 0; m < 27; ++m) o[m] = v[m];
+        o[27] = v[27] + nout * A.cmax;
+    }
+}
+
+}  // namespace
+
+void mp_launch_likelihood(mp_filter f, hipStream_t s) {
+    const int n = f->n;
+    const int ns = f->scan_n;
+    const int nbx = (n + kLanes - 1) / kLanes;
+    int nch = f->p.lik_chunks;
+    if (nch <= 0) {
+        // enough workgroups to fill 256 CUs several times, chunks of >= 256 points
+        nch = std::max(1, std::min((2048 + nbx - 1) / nbx, (ns + kTile - 1) / kTile));
+    }
+    nch = std::max(1, std::min(nch, std::max(1, ns)));
+    int clen = (ns + nch - 1) / nch;
+    nch = std::max(1, (ns + clen - 1) / std::max(1, clen));
+    f->lik_chunks = nch;
+    f->lik_chunk_len = clen;
+    f->partial.ensure(sizeof(float) * (size_t)kNumPartial * (size_t)nch * (size_t)n);
+    LikArgs A;
+    A.map = f->map->view;
+    A.poses = f->poses[f->cur].as<float4>();
+    A.order = f->sorted.as<int32_t>();
+    A.scan = f->scan.as<float4>();
+    A.partial = f->partial.as<float>();
+    A.n = n;
+    A.ns = ns;
+    A.chunk_len = std::max(1, clen);
+    A.nchunks = nch;
+    A.nbx = nbx;
+    A.dmax2 = f->p.d_max * f->p.d_max;
+    A.cmax = f->p.c_max;
+    if (ns > 0) {
+        mp_tick(f, MP_STAGE_LIK_CORE, true, s);
+        k_lik<<<nbx * nch, kLanes, 0, s>>>(A);
+        MP_CHECK_LAUNCH();
+        mp_tick(f, MP_STAGE_LIK_CORE, false, s);
+    } else {
+        MP_HIP(hipMemsetAsync(A.partial, 0, sizeof(float) * (size_t)kNumPartial * n, s));
+        nch = 1;
+    }
+    SolveArgs S;
+    S.partial = f->partial.as<float>();
+    S.psi = f->psi.as<float4>();
+    S.hb = f->capture_hb ? f->hb.as<float>() : nullptr;
+    S.flags = f->flags.as<int32_t>();
+    S.n = n;
+    S.nchunks = nch;
+    S.ns = ns;
+    S.cmax = f->p.c_max;
+    S.lam_rel = f->p.lambda_rel;
+    S.lam_abs = f->p.lambda_abs;
+    k_solve<<<(n + 255) / 256, 256, 0, s>>>(S);
+    MP_CHECK_LAUNCH();
+}

@@ -1,0 +1,139 @@
+// mp_internal.hpp -- library-internal structures and stage launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "megapf.h"
+
+// ------------------------------------------------------------ errors
+struct MpError {
+    mp_status code;
+    std::string msg;
+};
+
+[[noreturn]] void mp_throw(mp_status code, const char* fmt, ...);
+
+#define MP_HIP(expr)                                                                                  \
+    do {                                                                                              \
+        hipError_t _e = (expr);                                                                       \
+        if (_e != hipSuccess) {                                                                       \
+            if (_e == hipErrorOutOfMemory) mp_throw(MP_E_OOM, "%s: %s", #expr, hipGetErrorString(_e)); \
+            mp_throw(MP_E_HIP, "%s: %s", #expr, hipGetErrorString(_e));                               \
+        }                                                                                             \
+    } while (0)
+
+#define MP_CHECK_LAUNCH() MP_HIP(hipGetLastError())
+
+// ------------------------------------------------------------ device memory
+// Owning device allocation; freed in the destructor.
+struct DevMem {
+    void* p = nullptr;
+    size_t bytes = 0;
+    DevMem() = default;
+    DevMem(const DevMem&) = delete;
+    DevMem& operator=(const DevMem&) = delete;
+    ~DevMem() { release(); }
+    void alloc(size_t b);          // exact size, contents undefined
+    void ensure(size_t b);         // grow if smaller
+    void release();
+    template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+// ------------------------------------------------------------ map
+// What the likelihood kernel needs to look up the nearest-neighbour field
+// and read the Gaussians; passed to kernels by value.
+struct MapView {
+    float inv_r;         // 1/r in FP32
+    float gicp_a;        // 1 - eps: Sigma^M = I - a n n^T
+    int32_t org[3];      // band grid origin (voxel coordinates)
+    int32_t dim[3];      // band grid extent
+    int32_t backend;     // MP_NNF_HASH or MP_NNF_DENSE
+    uint32_t mask;       // hash capacity - 1
+    const int32_t* dense;   // dim product cells, -1 = miss
+    const uint2* table;     // hash slots {key = linear index + 1 (0 empty), gid}
+    const float4* gauss;    // 2 per Gaussian: (mu, count), (n, 0)
+};
+
+struct mp_map_s {
+    mp_map_params params{};
+    mp_map_info info{};
+    MapView view{};
+    DevMem gauss, dense, table, vox;   // vox: G x int3 voxel coordinates
+    float box_lo[3], box_hi[3];
+    int users = 0;
+};
+
+// ------------------------------------------------------------ filter
+struct FilterParamsDev {
+    int32_t n, k, bits, window_c;
+    float sigma_r, sigma_t, lsh_alpha, lsh_sigma, c_max, d_max, lambda_rel, lambda_abs;
+    uint64_t seed;
+};
+
+struct mp_filter_s {
+    mp_map map = nullptr;
+    mp_filter_params p{};
+    hipStream_t last_stream = nullptr;
+    int32_t n = 0, K = 0;
+    int32_t frame = 0;
+    int32_t lsh_counter = 0;  // frame value used by the LSH counter of the next pass
+    int32_t scan_n = -1;      // -1: no scan uploaded yet
+    int32_t cur = 0;          // current pose buffer
+    int32_t capture_hb = 0;
+    int32_t lik_chunks = 1, lik_chunk_len = 0;
+    float lsh_lo[3], lsh_hi[3];
+    // state
+    DevMem poses[2];          // N x 8 float
+    DevMem psi;               // N x 8 float: psi[6], loglik, inliers
+    DevMem hb;                // N x 28 float (debug)
+    DevMem partial;           // chunks x 28 x N float
+    DevMem codes, sorted, scodes, tmp_keys, tmp_vals, head, end, runs, hist;  // LSH / sort
+    DevMem nbr, kval, cnt;    // K x N, K x N, N
+    DevMem prior, post0, post1;   // N float
+    DevMem red;               // reduction scratch
+    DevMem flags;             // per-step counters (int32)
+    DevMem scan;              // n x 12 float
+    DevMem scan_xyz;          // n x 3 float staging
+    DevMem tlsh;              // 8 float
+    DevMem stepinfo;          // posterior summary (doubles)
+    // stage timers: event pairs per stage and span, reused across steps
+    std::vector<hipEvent_t> ev0[MP_NUM_STAGES], ev1[MP_NUM_STAGES];
+    int ev_count[MP_NUM_STAGES] = {};
+};
+
+// record the start (begin = true) or end of span `ev_count[st]` of stage st
+void mp_tick(mp_filter f, int st, bool begin, hipStream_t s);
+
+// ------------------------------------------------------------ launchers
+// sort / scan primitives (sort.hip)
+void mp_scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total_dev, DevMem& scratch,
+                           hipStream_t s);
+// stable LSD radix sort of (key, value) by the low `bits` bits of the key;
+// result in keys/vals (ping-pong with the alternate buffers)
+void mp_radix_sort_u32(uint32_t* keys, int32_t* vals, uint32_t* keys_alt, int32_t* vals_alt, int64_t n, int bits,
+                       DevMem& scratch, hipStream_t s);
+void mp_radix_sort_u64(uint64_t* keys, int32_t* vals, uint64_t* keys_alt, int32_t* vals_alt, int64_t n, int bits,
+                       DevMem& scratch, hipStream_t s);
+size_t mp_radix_scratch_bytes(int64_t n);
+
+// map (map_build.hip)
+void mp_build_map(mp_map m, const float* xyz_dev, int64_t n, hipStream_t s);
+void mp_map_lookup_launch(const MapView& v, const float* xyz_dev, int64_t n, int32_t* gid_dev, hipStream_t s);
+
+// scan covariances (scan.hip)
+void mp_scan_records(const float* xyz_dev, const float* cov6_dev, int32_t n, int32_t k, float eps, float* rec_dev,
+                     hipStream_t s);
+
+// filter stages
+void mp_launch_init_uniform(mp_filter f, const float lo[3], const float hi[3], hipStream_t s);
+void mp_launch_predict(mp_filter f, const float dT[7], const float L[36], bool noise, hipStream_t s);
+void mp_launch_lsh(mp_filter f, uint32_t frame, uint32_t it, hipStream_t s);
+void mp_launch_sort(mp_filter f, hipStream_t s);
+void mp_launch_refresh(mp_filter f, hipStream_t s);
+void mp_launch_likelihood(mp_filter f, hipStream_t s);
+void mp_launch_svgd(mp_filter f, hipStream_t s);
+void mp_launch_posterior(mp_filter f, hipStream_t s);
+void mp_launch_reset_lists(mp_filter f, hipStream_t s);

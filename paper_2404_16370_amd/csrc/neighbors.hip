@@ -1,0 +1,266 @@
+// neighbors.hip -- LSH bucketing and the iterative neighbour-list refresh
+// (Eq. 9-10 and Alg. 1, IterativeNeighborParticleSearch).
+//
+//   k_lsh        per particle: zeta = alpha W^K [log(R_L^T R_i); R_L^T (t_i - t_L)]
+//                + delta_i, cell = floor(zeta) (deterministic FP32), code =
+//                hash6(cell) & (2^bits - 1).  T^LSH is drawn from Philox for
+//                (frame, iteration); every lane derives it, lane 0 records it.
+//   sort         stable radix sort of (code, index)  -> buckets as runs
+//   k_bounds     run starts -> bucket head/end per sorted position
+//   k_refresh    one lane per sorted position: candidates = previous list U
+//                window of up to C bucket-mates after the particle (cyclic in
+//                its bucket); each ranked by q_ij = d^T W^K d (deterministic
+//                FP32), the K-1 smallest (q, j) kept behind the particle itself
+//                in a register-resident insertion network; k_ij = exp(-q_ij)
+//                cached for the SVGD update and the posterior propagation.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "mp_det.hpp"
+#include "mp_internal.hpp"
+
+namespace {
+
+struct LshArgs {
+    const float4* __restrict__ poses;
+    uint32_t* __restrict__ codes;
+    int32_t* __restrict__ idx;
+    float* __restrict__ tlsh;
+    int32_t n;
+    uint32_t mask, frame, it;
+    float ar, at, sl;
+    float lo[3], hi[3];
+    uint64_t seed;
+};
+
+__global__ __launch_bounds__(256) void k_lsh(LshArgs A) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    mpdet::quat qL;
+    float3 tL;
+    mpdet::random_pose(A.seed, 0u, A.frame, A.it, mpdet::PURPOSE_TLSH, A.lo, A.hi, qL, tL);
+    if (i == 0) {
+        A.tlsh[0] = qL.w; A.tlsh[1] = qL.x; A.tlsh[2] = qL.y; A.tlsh[3] = qL.z;
+        A.tlsh[4] = tL.x; A.tlsh[5] = tL.y; A.tlsh[6] = tL.z; A.tlsh[7] = 0.0f;
+    }
+    if (i >= A.n) return;
+    const float4 q4 = A.poses[2 * i], t4 = A.poses[2 * i + 1];
+    const mpdet::quat qi{q4.x, q4.y, q4.z, q4.w};
+    const mpdet::quat qr = mpdet::qmul(mpdet::qconj(qL), qi);
+    float w, sc;
+    const float3 om = mpdet::qlog(qr, w, sc);
+    const mpdet::mat3 RL = mpdet::qmat(qL);
+    const float3 u = mpdet::rot_t(RL, make_float3(t4.x - tL.x, t4.y - tL.y, t4.z - tL.z));
+    float z[6];
+    mpdet::gauss6(A.seed, (uint32_t)i, A.frame, A.it, mpdet::PURPOSE_LSH, z);
+    int32_t c[6];
+    c[0] = mpdet::floor_i32(A.ar * om.x + A.sl * z[0]);
+    c[1] = mpdet::floor_i32(A.ar * om.y + A.sl * z[1]);
+    c[2] = mpdet::floor_i32(A.ar * om.z + A.sl * z[2]);
+    c[3] = mpdet::floor_i32(A.at * u.x + A.sl * z[3]);
+    c[4] = mpdet::floor_i32(A.at * u.y + A.sl * z[4]);
+    c[5] = mpdet::floor_i32(A.at * u.z + A.sl * z[5]);
+    A.codes[i] = mpdet::hash6(c) & A.mask;
+    A.idx[i] = i;
+}
+
+__global__ void k_run_flags(const uint32_t* __restrict__ sc, int n, uint32_t* __restrict__ flag) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    flag[s] = (s == 0 || sc[s] != sc[s - 1]) ? 1u : 0u;
+}
+
+__global__ void k_run_starts(const uint32_t* __restrict__ flag, const uint32_t* __restrict__ rid, int n,
+                             int32_t* __restrict__ start) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    if (flag[s]) start[rid[s]] = s;
+}
+
+__global__ void k_bounds(const uint32_t* __restrict__ flag, const uint32_t* __restrict__ rid,
+                         const int32_t* __restrict__ start, const uint32_t* __restrict__ nruns, int n,
+                         int32_t* __restrict__ head, int32_t* __restrict__ end) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const uint32_t r = rid[s] + flag[s] - 1u;  // run of position s
+    head[s] = start[r];
+    end[s] = (r + 1u < *nruns) ? start[r + 1] : n;
+}
+
+struct RefreshArgs {
+    const float4* __restrict__ poses;
+    const int32_t* __restrict__ sorted;
+    const int32_t* __restrict__ head;
+    const int32_t* __restrict__ end;
+    int32_t* __restrict__ nbr;    // K x N
+    float* __restrict__ kval;     // K x N
+    int32_t* __restrict__ cnt;    // N
+    int32_t n, K, C;
+    float sr, st;
+};
+
+template <int KM>
+struct TopK {
+    float q[KM];
+    int32_t j[KM];
+    __device__ void init() {
+#pragma unroll
+        for (int m = 0; m < KM; ++m) {
+            q[m] = __builtin_inff();
+            j[m] = 0x7FFFFFFF;
+        }
+    }
+    __device__ bool has(int32_t x) const {
+        bool h = false;
+#pragma unroll
+        for (int m = 0; m < KM; ++m) h |= (j[m] == x);
+        return h;
+    }
+    // keep the KM smallest (q, j) in ascending order
+    __device__ void insert(float qv, int32_t jv) {
+#pragma unroll
+        for (int m = KM - 1; m >= 1; --m) {
+            const bool lt_prev = (qv < q[m - 1]) || (qv == q[m - 1] && jv < j[m - 1]);
+            const bool lt_cur = (qv < q[m]) || (qv == q[m] && jv < j[m]);
+            const float nq = lt_prev ? q[m - 1] : (lt_cur ? qv : q[m]);
+            const int32_t nj = lt_prev ? j[m - 1] : (lt_cur ? jv : j[m]);
+            q[m] = nq;
+            j[m] = nj;
+        }
+        const bool lt0 = (qv < q[0]) || (qv == q[0] && jv < j[0]);
+        if (lt0) {
+            q[0] = qv;
+            j[0] = jv;
+        }
+    }
+};
+
+template <int KM>
+__global__ __launch_bounds__(256) void k_refresh(RefreshArgs A) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= A.n) return;
+    const int i = A.sorted[s];
+    const float4 qi4 = A.poses[2 * i], ti4 = A.poses[2 * i + 1];
+    const mpdet::quat qi{qi4.x, qi4.y, qi4.z, qi4.w};
+    const float3 ti = make_float3(ti4.x, ti4.y, ti4.z);
+    TopK<KM> tk;
+    tk.init();
+    auto consider = [&](int32_t j) {
+        if (j < 0 || j >= A.n || j == i || tk.has(j)) return;
+        const float4 qj4 = A.poses[2 * j], tj4 = A.poses[2 * j + 1];
+        const float qv = mpdet::qdist(qi, ti, mpdet::quat{qj4.x, qj4.y, qj4.z, qj4.w},
+                                      make_float3(tj4.x, tj4.y, tj4.z), A.sr, A.st);
+        tk.insert(qv, j);
+    };
+    // bucket window (Alg. 1 gather loop, capped at C mates)
+    const int h = A.head[s], e = A.end[s];
+    const int m = e - h;
+    const int w = min(m - 1, A.C);
+    for (int d = 1; d <= w; ++d) {
+        int pos = s + d;
+        if (pos >= e) pos -= m;
+        consider(A.sorted[pos]);
+    }
+    // previous list (persists across iterations)
+    for (int a = 1; a < A.K; ++a) consider(A.nbr[(size_t)a * A.n + i]);
+    // write: the particle itself first, then the K-1 nearest others
+    A.nbr[i] = i;
+    A.kval[i] = 1.0f;
+    int c = 1;
+#pragma unroll
+    for (int a = 0; a < KM; ++a) {
+        if (a + 1 < A.K) {
+            const bool ok = tk.j[a] != 0x7FFFFFFF;
+            A.nbr[(size_t)(a + 1) * A.n + i] = ok ? tk.j[a] : -1;
+            A.kval[(size_t)(a + 1) * A.n + i] = ok ? expf(-tk.q[a]) : 0.0f;
+            c += ok ? 1 : 0;
+        }
+    }
+    A.cnt[i] = c;
+}
+
+__global__ void k_reset_lists(int32_t* __restrict__ nbr, float* __restrict__ kval, int32_t* __restrict__ cnt,
+                              float* __restrict__ prior, int n, int K) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    nbr[i] = i;
+    kval[i] = 1.0f;
+    for (int a = 1; a < K; ++a) {
+        nbr[(size_t)a * n + i] = -1;
+        kval[(size_t)a * n + i] = 0.0f;
+    }
+    cnt[i] = 1;
+    prior[i] = 1.0f / (float)n;
+}
+
+inline unsigned nblk(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace
+
+void mp_launch_lsh(mp_filter f, uint32_t frame, uint32_t it, hipStream_t s) {
+    LshArgs A;
+    A.poses = f->poses[f->cur].as<float4>();
+    A.codes = f->codes.as<uint32_t>();
+    A.idx = f->sorted.as<int32_t>();
+    A.tlsh = f->tlsh.as<float>();
+    A.n = f->n;
+    A.mask = f->p.lsh_bits >= 32 ? 0xFFFFFFFFu : ((1u << f->p.lsh_bits) - 1u);
+    A.frame = frame;
+    A.it = it;
+    A.ar = f->p.lsh_alpha * f->p.sigma_r;
+    A.at = f->p.lsh_alpha * f->p.sigma_t;
+    A.sl = f->p.lsh_sigma;
+    for (int a = 0; a < 3; ++a) {
+        A.lo[a] = f->lsh_lo[a];
+        A.hi[a] = f->lsh_hi[a];
+    }
+    A.seed = f->p.seed;
+    k_lsh<<<nblk(f->n), 256, 0, s>>>(A);
+    MP_CHECK_LAUNCH();
+}
+
+void mp_launch_sort(mp_filter f, hipStream_t s) {
+    const int n = f->n;
+    // sort (code, index); codes stay in particle order in `codes`, sorted copy in `scodes`
+    MP_HIP(hipMemcpyAsync(f->scodes.p, f->codes.p, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, s));
+    mp_radix_sort_u32(f->scodes.as<uint32_t>(), f->sorted.as<int32_t>(), f->tmp_keys.as<uint32_t>(),
+                      f->tmp_vals.as<int32_t>(), n, f->p.lsh_bits, f->hist, s);
+    // bucket bounds: flags -> run ids (exclusive scan) -> run starts -> head/end per position
+    uint32_t* flag = f->tmp_keys.as<uint32_t>();
+    uint32_t* rid = reinterpret_cast<uint32_t*>(f->tmp_vals.as<int32_t>());
+    uint32_t* nruns = f->flags.as<uint32_t>() + 4;
+    k_run_flags<<<nblk(n), 256, 0, s>>>(f->scodes.as<uint32_t>(), n, flag);
+    MP_CHECK_LAUNCH();
+    mp_scan_exclusive_u32(flag, rid, n, nruns, f->red, s);
+    k_run_starts<<<nblk(n), 256, 0, s>>>(flag, rid, n, f->runs.as<int32_t>());
+    MP_CHECK_LAUNCH();
+    k_bounds<<<nblk(n), 256, 0, s>>>(flag, rid, f->runs.as<int32_t>(), nruns, n, f->head.as<int32_t>(),
+                                     f->end.as<int32_t>());
+    MP_CHECK_LAUNCH();
+}
+
+void mp_launch_refresh(mp_filter f, hipStream_t s) {
+    RefreshArgs A;
+    A.poses = f->poses[f->cur].as<float4>();
+    A.sorted = f->sorted.as<int32_t>();
+    A.head = f->head.as<int32_t>();
+    A.end = f->end.as<int32_t>();
+    A.nbr = f->nbr.as<int32_t>();
+    A.kval = f->kval.as<float>();
+    A.cnt = f->cnt.as<int32_t>();
+    A.n = f->n;
+    A.K = f->K;
+    A.C = f->p.window_c;
+    A.sr = f->p.sigma_r;
+    A.st = f->p.sigma_t;
+    if (f->K <= 8) k_refresh<8><<<nblk(f->n), 256, 0, s>>>(A);
+    else if (f->K <= 16) k_refresh<16><<<nblk(f->n), 256, 0, s>>>(A);
+    else k_refresh<32><<<nblk(f->n), 256, 0, s>>>(A);
+    MP_CHECK_LAUNCH();
+}
+
+void mp_launch_reset_lists(mp_filter f, hipStream_t s) {
+    k_reset_lists<<<nblk(f->n), 256, 0, s>>>(f->nbr.as<int32_t>(), f->kval.as<float>(), f->cnt.as<int32_t>(),
+                                               f->prior.as<float>(), f->n, f->K);
+    MP_CHECK_LAUNCH();
+}

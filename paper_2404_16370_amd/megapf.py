@@ -1,0 +1,323 @@
+"""ctypes binding of libmegapf (include/megapf.h): argument marshalling only.
+
+Every computation happens in the library's HIP kernels.  Arrays may be numpy
+arrays (host memory) or torch tensors (host or device memory: their data
+pointers are passed through unchanged); streams are taken from torch's
+current stream when torch has a GPU.  If the shared library is missing the
+import fails loudly: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmegapf.so")
+
+MP_OK, MP_E_ARG, MP_E_STATE, MP_E_OOM, MP_E_HIP, MP_E_UNSUPPORTED, MP_E_NUMERIC = 0, -1, -2, -3, -4, -5, -6
+MP_NNF_AUTO, MP_NNF_HASH, MP_NNF_DENSE = 0, 1, 2
+MP_INIT_UNIFORM_BOX, MP_INIT_EXPLICIT = 0, 1
+(MP_STAGE_PREDICT, MP_STAGE_LSH, MP_STAGE_SORT, MP_STAGE_REFRESH, MP_STAGE_LIK, MP_STAGE_SVGD,
+ MP_STAGE_POSTERIOR, MP_STAGE_SCAN, MP_STAGE_LIK_CORE) = range(9)
+MP_NUM_STAGES = 9
+STAGE_NAMES = ["predict", "lsh", "sort", "refresh", "likelihood", "svgd", "posterior", "scan", "likelihood_core"]
+
+
+class MegaPFError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("status %d: %s" % (status, msg))
+        self.status = status
+
+
+class mp_map_params(C.Structure):
+    _fields_ = [("voxel", C.c_float), ("nnf_radius", C.c_int32), ("min_points", C.c_int32),
+                ("cov_eps", C.c_float), ("backend", C.c_int32)]
+
+
+class mp_map_info(C.Structure):
+    _fields_ = [("num_gauss", C.c_int64), ("num_band", C.c_int64), ("grid_origin", C.c_int32 * 3),
+                ("grid_dim", C.c_int32 * 3), ("box_min", C.c_float * 3), ("box_max", C.c_float * 3),
+                ("backend", C.c_int32), ("table_slots", C.c_int64), ("device_bytes", C.c_int64)]
+
+
+class mp_filter_params(C.Structure):
+    _fields_ = [("n_particles", C.c_int32), ("k", C.c_int32), ("lsh_bits", C.c_int32), ("svgd_iters", C.c_int32),
+                ("post_iters", C.c_int32), ("window_c", C.c_int32), ("scan_k", C.c_int32),
+                ("sigma_r", C.c_float), ("sigma_t", C.c_float), ("lsh_alpha", C.c_float),
+                ("lsh_sigma", C.c_float), ("c_max", C.c_float), ("d_max", C.c_float),
+                ("lambda_rel", C.c_float), ("lambda_abs", C.c_float), ("temperature", C.c_float),
+                ("prior_floor", C.c_float), ("cov_eps", C.c_float), ("lik_chunks", C.c_int32),
+                ("reserved", C.c_int32), ("seed", C.c_uint64)]
+
+
+class mp_init_desc(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("box_min", C.c_float * 3), ("box_max", C.c_float * 3),
+                ("poses", C.c_void_p)]
+
+
+class mp_posterior(C.Structure):
+    _fields_ = [("map_pose", C.c_float * 7), ("map_index", C.c_int32), ("map_weight", C.c_double),
+                ("n_eff", C.c_double), ("log_evidence", C.c_double), ("max_loglik", C.c_double),
+                ("frame", C.c_int32), ("fp64_resolves", C.c_int32)]
+
+
+EXPORTS = ["mp_map_default_params", "mp_map_build", "mp_map_get_info", "mp_map_get_gauss", "mp_map_lookup",
+           "mp_map_destroy", "mp_filter_default_params", "mp_filter_init", "mp_filter_destroy", "mp_scan_upload",
+           "mp_filter_step", "mp_posterior_query", "mp_last_error", "mp_stage_times", "mp_debug_get",
+           "mp_debug_set", "mp_debug_stage"]
+
+_lib = None
+
+
+def lib():
+    """Load libmegapf.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libmegapf.so is not built: run `python -m paper_2404_16370_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+    L.mp_map_default_params.argtypes = [C.POINTER(mp_map_params)]
+    L.mp_map_default_params.restype = None
+    L.mp_map_build.argtypes = [vp, i64, C.POINTER(mp_map_params), vp, C.POINTER(vp)]
+    L.mp_map_get_info.argtypes = [vp, C.POINTER(mp_map_info)]
+    L.mp_map_get_gauss.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.mp_map_lookup.argtypes = [vp, vp, i64, vp, vp]
+    L.mp_map_destroy.argtypes = [vp]
+    L.mp_filter_default_params.argtypes = [C.POINTER(mp_filter_params)]
+    L.mp_filter_default_params.restype = None
+    L.mp_filter_init.argtypes = [vp, C.POINTER(mp_filter_params), C.POINTER(mp_init_desc), vp, C.POINTER(vp)]
+    L.mp_filter_destroy.argtypes = [vp]
+    L.mp_scan_upload.argtypes = [vp, vp, vp, i32, vp]
+    L.mp_filter_step.argtypes = [vp, vp, vp, vp]
+    L.mp_posterior_query.argtypes = [vp, C.POINTER(mp_posterior), vp, vp, vp]
+    L.mp_last_error.argtypes = []
+    L.mp_last_error.restype = C.c_char_p
+    L.mp_stage_times.argtypes = [vp, vp, vp]
+    L.mp_debug_get.argtypes = [vp, C.c_char_p, vp, i64, vp]
+    L.mp_debug_set.argtypes = [vp, C.c_char_p, vp, i64, vp]
+    L.mp_debug_stage.argtypes = [vp, i32, i32, vp, vp, vp]
+    for name in EXPORTS:
+        if name not in ("mp_map_default_params", "mp_filter_default_params", "mp_last_error"):
+            getattr(L, name).restype = C.c_int32
+    _lib = L
+    return L
+
+
+def _check(status):
+    if status != MP_OK:
+        raise MegaPFError(status, lib().mp_last_error().decode())
+
+
+def _stream(stream):
+    if stream is not None:
+        return C.c_void_p(int(stream))
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    except ImportError:
+        pass
+    return C.c_void_p(0)
+
+
+def _ptr(a, dtype=None, keep=None):
+    """Data pointer of a numpy array or torch tensor (contiguous); None -> NULL."""
+    if a is None:
+        return None
+    if hasattr(a, "data_ptr"):  # torch tensor
+        if not a.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        return C.c_void_p(a.data_ptr())
+    arr = np.ascontiguousarray(a, dtype=dtype)
+    if keep is not None:
+        keep.append(arr)
+    return C.c_void_p(arr.ctypes.data)
+
+
+def _nrows(a):
+    return int(a.shape[0]) if hasattr(a, "shape") else len(a)
+
+
+# ------------------------------------------------------------------ map
+def mp_map_default_params():
+    p = mp_map_params()
+    lib().mp_map_default_params(C.byref(p))
+    return p
+
+
+class Map:
+    """Owner of an mp_map handle (mp_map_build / mp_map_destroy)."""
+
+    def __init__(self, xyz, voxel=0.5, nnf_radius=2, min_points=5, cov_eps=1e-3, backend=MP_NNF_AUTO, stream=None):
+        p = mp_map_default_params()
+        p.voxel, p.nnf_radius, p.min_points, p.cov_eps, p.backend = voxel, nnf_radius, min_points, cov_eps, backend
+        keep = []
+        h = C.c_void_p()
+        n = _nrows(xyz)
+        _check(lib().mp_map_build(_ptr(xyz, np.float32, keep), n, C.byref(p), _stream(stream), C.byref(h)))
+        self.handle = h
+        self.params = p
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _check(lib().mp_map_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            if getattr(self, "handle", None):
+                lib().mp_map_destroy(self.handle)
+                self.handle = None
+        except Exception:
+            pass
+
+    def info(self):
+        i = mp_map_info()
+        _check(lib().mp_map_get_info(self.handle, C.byref(i)))
+        return dict(num_gauss=i.num_gauss, num_band=i.num_band, grid_origin=list(i.grid_origin),
+                    grid_dim=list(i.grid_dim), box_min=list(i.box_min), box_max=list(i.box_max),
+                    backend=i.backend, table_slots=i.table_slots, device_bytes=i.device_bytes)
+
+    def gauss(self, stream=None):
+        G = self.info()["num_gauss"]
+        mu = np.zeros((G, 3), np.float32); nrm = np.zeros((G, 3), np.float32)
+        vox = np.zeros((G, 3), np.int32); cnt = np.zeros(G, np.int32)
+        if G:
+            _check(lib().mp_map_get_gauss(self.handle, _ptr(mu), _ptr(nrm), _ptr(vox), _ptr(cnt), _stream(stream)))
+        return dict(mu=mu, normal=nrm, vox=vox, count=cnt)
+
+    def lookup(self, xyz, out=None, stream=None):
+        n = _nrows(xyz)
+        keep = []
+        res = np.zeros(n, np.int32) if out is None else out
+        if n:
+            _check(lib().mp_map_lookup(self.handle, _ptr(xyz, np.float32, keep), n, _ptr(res), _stream(stream)))
+        return res
+
+
+# ------------------------------------------------------------------ filter
+def mp_filter_default_params(**kw):
+    p = mp_filter_params()
+    lib().mp_filter_default_params(C.byref(p))
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+_DEBUG_LAYOUT = {  # name -> (dtype, shape as a function of (n, K, scan_n))
+    "poses": (np.float32, lambda n, K, s: (n, 8)),
+    "psi": (np.float32, lambda n, K, s: (n, 8)),
+    "hb": (np.float32, lambda n, K, s: (n, 28)),
+    "codes": (np.uint32, lambda n, K, s: (n,)),
+    "sorted": (np.int32, lambda n, K, s: (n,)),
+    "scodes": (np.uint32, lambda n, K, s: (n,)),
+    "head": (np.int32, lambda n, K, s: (n,)),
+    "end": (np.int32, lambda n, K, s: (n,)),
+    "nbr": (np.int32, lambda n, K, s: (K, n)),
+    "kval": (np.float32, lambda n, K, s: (K, n)),
+    "cnt": (np.int32, lambda n, K, s: (n,)),
+    "prior": (np.float32, lambda n, K, s: (n,)),
+    "post": (np.float32, lambda n, K, s: (n,)),
+    "post0": (np.float32, lambda n, K, s: (n,)),
+    "scan": (np.float32, lambda n, K, s: (s, 12)),
+    "tlsh": (np.float32, lambda n, K, s: (8,)),
+}
+
+
+class Filter:
+    """Owner of an mp_filter handle."""
+
+    def __init__(self, map_: Map, params=None, poses=None, box=None, stream=None, **kw):
+        self.map = map_
+        self.params = params if params is not None else mp_filter_default_params(**kw)
+        init = mp_init_desc()
+        keep = []
+        if poses is not None:
+            init.kind = MP_INIT_EXPLICIT
+            p = poses
+            if not hasattr(p, "data_ptr"):
+                p = np.ascontiguousarray(np.asarray(poses, np.float32)[:, :7])
+            init.poses = _ptr(p, np.float32, keep)
+        else:
+            init.kind = MP_INIT_UNIFORM_BOX
+            lo, hi = box if box is not None else (map_.info()["box_min"], map_.info()["box_max"])
+            for a in range(3):
+                init.box_min[a] = lo[a]
+                init.box_max[a] = hi[a]
+        h = C.c_void_p()
+        _check(lib().mp_filter_init(map_.handle, C.byref(self.params), C.byref(init), _stream(stream), C.byref(h)))
+        self.handle = h
+        self.n = self.params.n_particles
+        self.K = self.params.k
+        self.scan_n = 0
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _check(lib().mp_filter_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            if getattr(self, "handle", None):
+                lib().mp_filter_destroy(self.handle)
+                self.handle = None
+        except Exception:
+            pass
+
+    def scan_upload(self, xyz, cov6=None, stream=None):
+        n = _nrows(xyz) if xyz is not None else 0
+        keep = []
+        _check(lib().mp_scan_upload(self.handle, _ptr(xyz, np.float32, keep) if n else None,
+                                    _ptr(cov6, np.float32, keep), n, _stream(stream)))
+        self.scan_n = n
+
+    def step(self, dT=None, cov_dT=None, stream=None):
+        keep = []
+        _check(lib().mp_filter_step(self.handle, _ptr(dT, np.float32, keep), _ptr(cov_dT, np.float32, keep),
+                                    _stream(stream)))
+
+    def posterior_query(self, poses=False, weights=False, stream=None):
+        out = mp_posterior()
+        P = np.zeros((self.n, 7), np.float32) if poses else None
+        W = np.zeros(self.n, np.float64) if weights else None
+        _check(lib().mp_posterior_query(self.handle, C.byref(out), _ptr(P), _ptr(W), _stream(stream)))
+        res = dict(map_pose=np.array(out.map_pose[:], np.float32), map_index=out.map_index,
+                   map_weight=out.map_weight, n_eff=out.n_eff, log_evidence=out.log_evidence,
+                   max_loglik=out.max_loglik, frame=out.frame, fp64_resolves=out.fp64_resolves)
+        if poses:
+            res["poses"] = P
+        if weights:
+            res["weights"] = W
+        return res
+
+    def stage_times(self):
+        ms = np.zeros(MP_NUM_STAGES, np.float32)
+        cnt = np.zeros(MP_NUM_STAGES, np.int32)
+        _check(lib().mp_stage_times(self.handle, _ptr(ms), _ptr(cnt)))
+        return {STAGE_NAMES[k]: (float(ms[k]), int(cnt[k])) for k in range(MP_NUM_STAGES)}
+
+    def debug_get(self, name, stream=None):
+        dt, shp = _DEBUG_LAYOUT[name]
+        out = np.zeros(shp(self.n, self.K, self.scan_n), dt)
+        _check(lib().mp_debug_get(self.handle, name.encode(), _ptr(out), out.nbytes, _stream(stream)))
+        return out
+
+    def debug_set(self, name, value, stream=None):
+        if name == "capture_hb":
+            v = np.array([int(value)], np.int32)
+            _check(lib().mp_debug_set(self.handle, b"capture_hb", _ptr(v), 4, _stream(stream)))
+            return
+        dt, shp = _DEBUG_LAYOUT[name]
+        arr = np.ascontiguousarray(value, dt).reshape(shp(self.n, self.K, self.scan_n))
+        _check(lib().mp_debug_set(self.handle, name.encode(), _ptr(arr), arr.nbytes, _stream(stream)))
+
+    def debug_stage(self, stage, iteration=0, dT=None, cov_dT=None, stream=None):
+        keep = []
+        _check(lib().mp_debug_stage(self.handle, stage, iteration, _ptr(dT, np.float32, keep),
+                                    _ptr(cov_dT, np.float32, keep), _stream(stream)))
