@@ -1,0 +1,210 @@
+"""Throughput of the Stein particle filter hot path on one MI355X.
+
+One step = one mp_filter_step on a fresh scan: prediction, 10 iterations of
+(LSH codes, bucket sort, neighbour refresh, likelihood + Gauss-Newton, SVGD),
+and the posterior propagation, for 1,048,576 particles and 8192 scan points
+on a synthetic 200 x 200 x 15 m campus map (20M points, 1 m voxels).  Scans
+for all timed steps are generated and copied to HBM before timing; the timed
+region covers mp_scan_upload (device-resident points) + mp_filter_step.
+
+Prints one JSON line.  `roofline` refers to the likelihood kernel (k_lik),
+timed with HIP events on the stream it runs on; `cpu_baseline` times the CPU
+oracle on a bounded sample of the same workload on this host's cores.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "filter steps/s and particle-point evals/s at 1M particles, plain vs surrogate"
+PEAK_FP32 = 157.3e12        # MI355X FP32 vector, FLOP/s
+PEAK_HBM = 8.0e12           # bytes/s
+# FP32 operations of one likelihood evaluation in k_lik (an fma counts 2):
+#   inlier:  transform 18, voxel key 3, residual and gate 8, R^T n and R^T e 30,
+#            C 15, adjugate/det/inverse 30, Omega e and cost 20, compensated add 4,
+#            b 15, B 27, H_ww 24, H_wv 9, H_vv 6                      = 209
+#   outlier: transform 18, voxel key 3 (+ residual and gate 8 on an NNF hit) = 21..29
+FLOPS_INLIER = 209
+FLOPS_OUTLIER = 21
+GATHER_BYTES_INLIER = 36    # 4 B NNF cell + 32 B Gaussian record
+
+WORKLOADS = {
+    "campus": dict(particles=1_048_576, scan_points=8192, svgd_iters=10, k=16, lsh_bits=24, voxel=1.0,
+                   map_points=20_000_000, window_c=32, post_iters=10),
+    "floor": dict(particles=65_536, scan_points=4096, svgd_iters=20, k=16, lsh_bits=20, voxel=0.5,
+                  map_points=2_000_000, window_c=32, post_iters=10),
+    "room": dict(particles=4096, scan_points=1024, svgd_iters=10, k=8, lsh_bits=16, voxel=0.5,
+                 map_points=200_000, window_c=16, post_iters=10),
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(wl, w, scan, budget_s=15.0):
+    """Time the oracle's correction iteration on a sample of particles and
+    scale to the workload (particles x iterations)."""
+    import oracle as O
+    O.build(force=False)
+    t0 = time.perf_counter()
+    om = O.Map(w["map_xyz"], wl["voxel"], nnf_radius=2, min_points=5)
+    t_map = time.perf_counter() - t0
+    _, scov, _ = O.scan_cov(scan, k=10)
+    from paper_2404_16370_amd import synth as S
+    # particles as the workload starts them: uniform over the map box and SO(3)
+    poses = S.uniform_particles(65536, w["scene"].lo, w["scene"].hi, 3003)
+    info_lo, info_hi = w["scene"].lo.astype(np.float32), w["scene"].hi.astype(np.float32)
+
+    def one_iteration(P):
+        n = len(P)
+        TL = O.lsh_frame(1, 0, 0, info_lo, info_hi)
+        codes = O.lsh_codes(P, TL, 1.0, 5.0, 2.5, 0.3, wl["lsh_bits"], 1, 0, 0)
+        s, _, _ = O.bucket_sort(codes)
+        nbr, q, cnt = O.refresh(P, s, codes, wl["k"], wl["window_c"], 5.0, 2.5, None)
+        lk = O.likelihood(om, scan, scov, P, dmax=2 * wl["voxel"], cmax=9.0)
+        O.svgd(P, lk["psi"], nbr, 5.0, 2.5)
+        return lk
+
+    m = 64
+    t0 = time.perf_counter()
+    one_iteration(poses[:m])
+    dt = time.perf_counter() - t0
+    m = int(min(len(poses), max(64, m * budget_s / max(dt, 1e-3))))
+    t0 = time.perf_counter()
+    one_iteration(poses[:m])
+    dt = time.perf_counter() - t0
+    per_particle_iter = dt / m
+    step_s = per_particle_iter * wl["particles"] * wl["svgd_iters"]
+    evals = wl["scan_points"] * m
+    return {"value": 1.0 / step_s, "unit": "filter steps/s", "cores": O.num_threads(), "kind": "oracle",
+            "sample": ("one correction iteration (LSH, sort, refresh, likelihood+GN, SVGD) of %d of the "
+                       "workload's particles x %d scan points, %.1f s; scaled to %d particles x %d iterations "
+                       "(posterior and prediction not included)" %
+                       (m, wl["scan_points"], dt, wl["particles"], wl["svgd_iters"])),
+            "evals_per_s": evals / dt, "map_build_s": t_map}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="campus", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one plain 1 GiB device copy before timing (reference for HBM byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build runs the hot path on a single MI355X "
+              "(multi-GPU sharding is a design note, not built); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2404_16370_amd import megapf as M
+    from paper_2404_16370_amd import synth as S
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    wl = WORKLOADS[args.workload]
+    nframes = args.warmup + args.steps + 1
+    t0 = time.perf_counter()
+    w = S.build_workload(args.workload, map_points=wl["map_points"], scan_points=wl["scan_points"],
+                         frames=max(nframes, 2))
+    log("workload generated in %.1f s (%d map points, %d frames)" % (time.perf_counter() - t0,
+                                                                      len(w["map_xyz"]), len(w["scans"])))
+    t0 = time.perf_counter()
+    xyz = torch.from_numpy(w["map_xyz"]).cuda()
+    m = M.Map(xyz, voxel=wl["voxel"], nnf_radius=2, min_points=5)
+    torch.cuda.synchronize()
+    minfo = m.info()
+    log("map built in %.2f s: %s" % (time.perf_counter() - t0, minfo))
+
+    p = M.mp_filter_default_params(n_particles=wl["particles"], k=wl["k"], lsh_bits=wl["lsh_bits"],
+                                   svgd_iters=wl["svgd_iters"], post_iters=wl["post_iters"],
+                                   window_c=wl["window_c"], d_max=2.0 * wl["voxel"], seed=4003)
+    f = M.Filter(m, p, box=(minfo["box_min"], minfo["box_max"]))
+    scans = [torch.from_numpy(np.ascontiguousarray(s)).cuda() for s in w["scans"]]
+    odo = w["odometry"]
+    torch.cuda.synchronize()
+
+    def run(k):
+        dT, cov = odo[k] if k > 0 else (None, None)
+        f.scan_upload(scans[k])
+        f.step(dT, cov)
+
+    if args.copy_calibration:
+        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    for k in range(args.warmup):
+        run(k)
+        log("warmup step %d done" % k)
+    torch.cuda.synchronize()
+    lik_ms, lik_n = [], []
+    t0 = time.perf_counter()
+    for k in range(args.warmup, args.warmup + args.steps):
+        run(k)
+        st = f.stage_times()   # synchronises on this step's events
+        lik_ms.append(st["likelihood_core"][0])
+        lik_n.append(st["likelihood_core"][1])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    stages = f.stage_times()
+    q = f.posterior_query(weights=True)
+    psi = f.debug_get("psi")
+    inl = psi[:, 7].astype(np.float64).sum()
+    ns = wl["scan_points"]
+    n = wl["particles"]
+    evals_iter = float(n) * ns
+    inl_frac = inl / evals_iter
+    t_launch = (sum(lik_ms) / max(sum(lik_n), 1)) * 1e-3
+    flops_launch = evals_iter * (inl_frac * FLOPS_INLIER + (1 - inl_frac) * FLOPS_OUTLIER)
+    achieved = flops_launch / t_launch
+    steps_per_s = args.steps / elapsed
+    evals_per_s = steps_per_s * evals_iter * wl["svgd_iters"]
+    res = {
+        "metric": METRIC,
+        "value": round(steps_per_s, 4),
+        "unit": "filter steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1000 * elapsed / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "%s: %d particles x %d scan points x %d SVGD iterations per step, %d map points "
+                               "at %.1f m voxels, K=%d, %d LSH bits" %
+                               (args.workload, n, ns, wl["svgd_iters"], wl["map_points"], wl["voxel"], wl["k"],
+                                wl["lsh_bits"]),
+                   "particles": n, "scan_points": ns, "svgd_iters": wl["svgd_iters"], "scorer": "plain"},
+        "evals_per_s": evals_per_s,
+        "likelihood_kernel_evals_per_s": evals_iter / t_launch,
+        "inlier_fraction": round(inl_frac, 4),
+        "stage_ms_last_step": {k: round(v[0], 3) for k, v in stages.items() if v[1]},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32, "traffic": None,
+                     "kernel": "k_lik", "launch_ms": t_launch * 1e3,
+                     "logical_gather_GBps": evals_iter * inl_frac * GATHER_BYTES_INLIER / t_launch / 1e9},
+        "posterior": {"map_weight": q["map_weight"], "n_eff": q["n_eff"], "sum_w": float(q["weights"].sum())},
+    }
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(wl, w, w["scans"][-1], args.cpu_budget)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -140,7 +140,7 @@ typedef struct {
     float prior_floor;    /* prior probabilities below this are raised to it */
     float cov_eps;        /* GICP epsilon for scan covariances */
     int32_t lik_chunks;   /* scan-point chunks per particle tile in the likelihood launch; 0 = auto */
-    int32_t reserved;
+    int32_t lik_batch;    /* scan points whose NNF cells are requested together per lane: 4, 8, 16 (0 = 16) or 32 */
     uint64_t seed;        /* Philox4x32-10 key */
 } mp_filter_params;
 
@@ -249,7 +249,9 @@ MP_API mp_status mp_stage_times(mp_filter f, float* ms_out, int32_t* counts_out)
  *   "cnt"     N int32 list lengths
  *   "prior"   N float prior probabilities
  *   "post"    N float smoothed posterior of the last step
- *   "scan"    n x 12 float scan records (mu, Sigma upper 6, pad)
+ *   "scan"    n x 12 float scan records (mu, Sigma upper 6, pad), caller's order
+ *   "scan_walk" the same records in the likelihood's walk order (Morton order
+ *             of the points on a grid of half the map voxel)
  *   "tlsh"    8 float T^LSH of the last LSH pass
  *   "capture_hb"  int32 (set only)
  * bytes must equal the named buffer's size.  mp_debug_stage runs one stage

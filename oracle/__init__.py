@@ -86,7 +86,7 @@ def _declare(L):
     L.mpo_map_num_gauss.argtypes = [_vp]; L.mpo_map_num_gauss.restype = C.c_int64
     L.mpo_map_num_band.argtypes = [_vp]; L.mpo_map_num_band.restype = C.c_int64
     L.mpo_map_grid.argtypes = [_vp, _i32p, _i32p]
-    L.mpo_map_gauss.argtypes = [_vp, _i32p, _f32p, _f32p, _f64p, _f64p, _i32p]
+    L.mpo_map_gauss.argtypes = [_vp, _i32p, _f32p, _f32p, _f64p, _f64p, _i32p, _f32p]
     L.mpo_map_band.argtypes = [_vp, _i64p, _i32p]
     L.mpo_map_lookup.argtypes = [_vp, _f32p, C.c_int64, _i32p]
     L.mpo_scan_cov.argtypes = [_f32p, C.c_int32, C.c_int32, C.c_float, _i32p, _f32p, _f64p]
@@ -213,9 +213,11 @@ class Map:
         G = max(self.G, 1)
         vox = np.zeros((G, 3), np.int32); mu = np.zeros((G, 3), np.float32); cov = np.zeros((G, 6), np.float32)
         mu64 = np.zeros((G, 3)); cov64 = np.zeros((G, 6)); npts = np.zeros(G, np.int32)
-        lib().mpo_map_gauss(self.handle, vox, mu, cov, mu64, cov64, npts)
+        nrm = np.zeros((G, 3), np.float32)
+        lib().mpo_map_gauss(self.handle, vox, mu, cov, mu64, cov64, npts, nrm)
         g = self.G
-        return dict(vox=vox[:g], mu=mu[:g], cov=cov[:g], mu64=mu64[:g], cov64=cov64[:g], npts=npts[:g])
+        return dict(vox=vox[:g], mu=mu[:g], cov=cov[:g], mu64=mu64[:g], cov64=cov64[:g], npts=npts[:g],
+                    normal=nrm[:g])
 
     def band(self):
         nb = max(self.nb, 1)

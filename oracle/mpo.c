@@ -460,10 +460,11 @@ MPO_API void mpo_eig3(const double S_in[9], double w[3], double V[9]) {
 /* GICP plane normalisation (Segal et al. 2009): covariance S of a point
  * neighbourhood -> I - (1-eps) n n^T with n the eigenvector of the smallest
  * eigenvalue.  Output (xx, xy, xz, yy, yz, zz). */
-static void gicp_normalise(const double S[9], double eps, double out6[6]) {
+static void gicp_normalise(const double S[9], double eps, double out6[6], double n_out[3]) {
     double w[3], V[9];
     mpo_eig3(S, w, V);
     double n[3] = {V[0], V[3], V[6]};
+    if (n_out) { n_out[0] = n[0]; n_out[1] = n[1]; n_out[2] = n[2]; }
     double a = 1.0 - eps;
     out6[0] = 1.0 - a * n[0] * n[0];
     out6[1] = -a * n[0] * n[1];
@@ -482,12 +483,14 @@ static void gicp_normalise(const double S[9], double eps, double out6[6]) {
 /* ======================================================================= */
 typedef struct {
     float r, inv_r, eps;
+    float a32;     /* 1 - eps as the FP32 value the GPU uses */
     int R, min_pts;
     int32_t org[3], dim[3]; /* band grid: voxel v -> linear index of v - org */
     int64_t G;
     int32_t* vox;  /* G*3 voxel coordinates */
     float* mu;     /* G*3 FP32 (rounded from FP64) */
     float* cov;    /* G*6 FP32 */
+    float* nrm;    /* G*3 FP32 unit normals: the map covariance is I - a32 n n^T */
     double* mu64;  /* G*3 */
     double* cov64; /* G*6 */
     int32_t* npts; /* G */
@@ -532,6 +535,7 @@ static int64_t grid_key(const mpo_map* m, const int32_t v[3]) {
 MPO_API mpo_map* mpo_map_build(const float* xyz, int64_t n, float r, int R, int min_pts, float eps) {
     mpo_map* m = (mpo_map*)calloc(1, sizeof(mpo_map));
     m->r = r; m->inv_r = 1.0f / r; m->R = R; m->min_pts = min_pts; m->eps = eps;
+    m->a32 = 1.0f - eps;
     vrec* recs = (vrec*)malloc(sizeof(vrec) * (size_t)(n > 0 ? n : 1));
     for (int64_t i = 0; i < n; ++i) {
         for (int k = 0; k < 3; ++k) recs[i].v[k] = floor_to_i32(xyz[3 * i + k] * m->inv_r);
@@ -550,6 +554,7 @@ MPO_API mpo_map* mpo_map_build(const float* xyz, int64_t n, float r, int R, int 
     m->vox = (int32_t*)malloc(sizeof(int32_t) * 3 * (size_t)(G ? G : 1));
     m->mu = (float*)malloc(sizeof(float) * 3 * (size_t)(G ? G : 1));
     m->cov = (float*)malloc(sizeof(float) * 6 * (size_t)(G ? G : 1));
+    m->nrm = (float*)malloc(sizeof(float) * 3 * (size_t)(G ? G : 1));
     m->mu64 = (double*)malloc(sizeof(double) * 3 * (size_t)(G ? G : 1));
     m->cov64 = (double*)malloc(sizeof(double) * 6 * (size_t)(G ? G : 1));
     m->npts = (int32_t*)malloc(sizeof(int32_t) * (size_t)(G ? G : 1));
@@ -576,8 +581,9 @@ MPO_API mpo_map* mpo_map_build(const float* xyz, int64_t n, float r, int R, int 
             double S[9];
             for (int a = 0; a < 6; ++a) S6[a] /= (double)cnt;
             sym6_full(S6, S);
-            double c6[6];
-            gicp_normalise(S, (double)eps, c6);
+            double c6[6], nv[3];
+            gicp_normalise(S, (double)eps, c6, nv);
+            for (int a = 0; a < 3; ++a) m->nrm[3 * g + a] = (float)nv[a];
             for (int a = 0; a < 3; ++a) {
                 m->vox[3 * g + a] = recs[s].v[a];
                 m->mu64[3 * g + a] = mu[a];
@@ -635,7 +641,7 @@ MPO_API mpo_map* mpo_map_build(const float* xyz, int64_t n, float r, int R, int 
 
 MPO_API void mpo_map_free(mpo_map* m) {
     if (!m) return;
-    free(m->vox); free(m->mu); free(m->cov); free(m->mu64); free(m->cov64); free(m->npts);
+    free(m->vox); free(m->mu); free(m->cov); free(m->nrm); free(m->mu64); free(m->cov64); free(m->npts);
     free(m->bkey); free(m->bgid); free(m);
 }
 
@@ -646,8 +652,9 @@ MPO_API void mpo_map_grid(const mpo_map* m, int32_t org[3], int32_t dim[3]) {
     memcpy(dim, m->dim, sizeof(m->dim));
 }
 MPO_API void mpo_map_gauss(const mpo_map* m, int32_t* vox, float* mu, float* cov, double* mu64, double* cov64,
-                           int32_t* npts) {
+                           int32_t* npts, float* nrm) {
     size_t G = (size_t)m->G;
+    if (nrm) memcpy(nrm, m->nrm, sizeof(float) * 3 * G);
     if (vox) memcpy(vox, m->vox, sizeof(int32_t) * 3 * G);
     if (mu) memcpy(mu, m->mu, sizeof(float) * 3 * G);
     if (cov) memcpy(cov, m->cov, sizeof(float) * 6 * G);
@@ -728,7 +735,7 @@ MPO_API void mpo_scan_cov(const float* xyz, int32_t n, int32_t k, float eps, int
             for (int c = 0; c < 6; ++c) S6[c] /= (double)(kk + 1);
             double S[9];
             sym6_full(S6, S);
-            gicp_normalise(S, (double)eps, c6);
+            gicp_normalise(S, (double)eps, c6, NULL);
         }
         for (int c = 0; c < 6; ++c) {
             cov6[6 * (int64_t)i + c] = (float)c6[c];
@@ -828,9 +835,13 @@ MPO_API void mpo_likelihood(const mpo_map* m, const float* sxyz, const float* sc
             double p[3], e[3];
             for (int a = 0; a < 3; ++a) p[a] = R[3 * a] * mu[0] + R[3 * a + 1] * mu[1] + R[3 * a + 2] * mu[2] + t[a];
             for (int a = 0; a < 3; ++a) e[a] = (double)mm[a] - p[a];
-            double SM6[6], SS6[6], SM[9], SS[9], tmp[9], RSR[9], C[9], Om[9];
-            for (int a = 0; a < 6; ++a) { SM6[a] = m->cov[6 * (int64_t)g + a]; SS6[a] = scov[6 * (int64_t)k + a]; }
-            sym6_full(SM6, SM);
+            /* map covariance from the FP32 normal and a = 1 - eps (FP32), in FP64 */
+            double SS6[6], SM[9], SS[9], tmp[9], RSR[9], C[9], Om[9];
+            const float* nv = m->nrm + 3 * (int64_t)g;
+            for (int r2 = 0; r2 < 3; ++r2)
+                for (int c2 = 0; c2 < 3; ++c2)
+                    SM[3 * r2 + c2] = (r2 == c2 ? 1.0 : 0.0) - (double)m->a32 * (double)nv[r2] * (double)nv[c2];
+            for (int a = 0; a < 6; ++a) SS6[a] = scov[6 * (int64_t)k + a];
             sym6_full(SS6, SS);
             mat3_mul(R, SS, tmp);
             mat3_mul(tmp, Rt, RSR);

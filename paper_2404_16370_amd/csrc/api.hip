@@ -2,8 +2,10 @@
 // host/device pointer staging, the filter-step schedule and diagnostics.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
+#include <numeric>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -250,6 +252,8 @@ static void validate_params(const mp_filter_params& p) {
         p.cov_eps > 1)
         mp_throw(MP_E_ARG, "parameter out of range");
     if (p.lik_chunks < 0) mp_throw(MP_E_ARG, "lik_chunks must be >= 0");
+    if (p.lik_batch != 0 && p.lik_batch != 4 && p.lik_batch != 8 && p.lik_batch != 16 && p.lik_batch != 32)
+        mp_throw(MP_E_ARG, "lik_batch must be 0, 4, 8, 16 or 32");
 }
 
 static void destroy_filter(mp_filter f) {
@@ -354,6 +358,36 @@ extern "C" mp_status mp_filter_destroy(mp_filter f) {
     });
 }
 
+// 3-D Morton (Z-order) key of the cell of each point, cells of edge `cell`
+static uint64_t spread3(uint64_t v) {
+    v &= 0x1FFFFF;
+    v = (v | (v << 32)) & 0x1F00000000FFFFull;
+    v = (v | (v << 16)) & 0x1F0000FF0000FFull;
+    v = (v | (v << 8)) & 0x100F00F00F00F00Full;
+    v = (v | (v << 4)) & 0x10C30C30C30C30C3ull;
+    v = (v | (v << 2)) & 0x1249249249249249ull;
+    return v;
+}
+
+static std::vector<int32_t> morton_order(const float* xyz, int n, float cell) {
+    float lo[3] = {xyz[0], xyz[1], xyz[2]};
+    for (int i = 1; i < n; ++i)
+        for (int a = 0; a < 3; ++a) lo[a] = std::min(lo[a], xyz[3 * i + a]);
+    std::vector<uint64_t> key((size_t)n);
+    for (int i = 0; i < n; ++i) {
+        uint64_t c[3];
+        for (int a = 0; a < 3; ++a) {
+            const double q = std::floor(((double)xyz[3 * i + a] - lo[a]) / cell);
+            c[a] = (uint64_t)std::min(std::max(q, 0.0), 2097151.0);
+        }
+        key[(size_t)i] = spread3(c[0]) | (spread3(c[1]) << 1) | (spread3(c[2]) << 2);
+    }
+    std::vector<int32_t> perm((size_t)n);
+    std::iota(perm.begin(), perm.end(), 0);
+    std::stable_sort(perm.begin(), perm.end(), [&](int32_t a, int32_t b) { return key[(size_t)a] < key[(size_t)b]; });
+    return perm;
+}
+
 extern "C" mp_status mp_scan_upload(mp_filter f, const float* xyz, const float* cov6, int32_t n, void* stream) {
     return guarded("mp_scan_upload", [&]() {
         if (!f || n < 0 || (n > 0 && !xyz)) mp_throw(MP_E_ARG, "null argument or n < 0");
@@ -371,6 +405,13 @@ extern "C" mp_status mp_scan_upload(mp_filter f, const float* xyz, const float* 
             }
             f->scan_xyz.ensure(sizeof(float) * 3 * (size_t)n);
             f->scan.ensure(sizeof(float) * 12 * (size_t)n);
+            f->scan_orig.ensure(sizeof(float) * 12 * (size_t)n);
+            f->scan_perm.ensure(sizeof(int32_t) * (size_t)n);
+            // Walk order for the likelihood: Morton order of the points on a grid of half the
+            // map voxel, so that consecutive points of one particle land in the same or
+            // neighbouring voxels (the sum over points does not depend on the order).
+            const std::vector<int32_t> perm = morton_order(hx.data(), n, 0.5f * f->map->params.voxel);
+            MP_HIP(hipMemcpyAsync(f->scan_perm.p, perm.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
             MP_HIP(hipMemcpyAsync(f->scan_xyz.p, hx.data(), sizeof(float) * 3 * n, hipMemcpyHostToDevice, s));
             DevMem tcov;
             const float* dcov = nullptr;
@@ -381,9 +422,10 @@ extern "C" mp_status mp_scan_upload(mp_filter f, const float* xyz, const float* 
             }
             f->ev_count[MP_STAGE_SCAN] = 0;
             mp_tick(f, MP_STAGE_SCAN, true, s);
-            mp_scan_records(f->scan_xyz.as<float>(), dcov, n, f->p.scan_k, f->p.cov_eps, f->scan.as<float>(), s);
+            mp_scan_records(f->scan_xyz.as<float>(), dcov, n, f->p.scan_k, f->p.cov_eps, f->scan_orig.as<float>(), s);
+            mp_scan_permute(f->scan_orig.as<float>(), f->scan_perm.as<int32_t>(), n, f->scan.as<float>(), s);
             mp_tick(f, MP_STAGE_SCAN, false, s);
-            if (cov6) MP_HIP(hipStreamSynchronize(s));  // tcov goes out of scope
+            MP_HIP(hipStreamSynchronize(s));  // staging buffers (perm, tcov) go out of scope
         }
         f->scan_n = n;
         f->last_stream = s;
@@ -590,7 +632,8 @@ static NamedBuf lookup_buf(mp_filter f, const char* name) {
     if (s == "prior") return {f->prior.p, 4 * N, true};
     if (s == "post") return {f->prior.p, 4 * N, false};
     if (s == "post0") return {f->post0.p, 4 * N, false};
-    if (s == "scan") return {f->scan.p, f->scan_n > 0 ? 48 * (size_t)f->scan_n : 0, false};
+    if (s == "scan") return {f->scan_orig.p, f->scan_n > 0 ? 48 * (size_t)f->scan_n : 0, false};
+    if (s == "scan_walk") return {f->scan.p, f->scan_n > 0 ? 48 * (size_t)f->scan_n : 0, false};
     if (s == "tlsh") return {f->tlsh.p, 32, false};
     mp_throw(MP_E_ARG, "unknown buffer '%s'", s.c_str());
 }

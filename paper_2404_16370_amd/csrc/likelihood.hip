@@ -56,6 +56,95 @@ __device__ inline int remap_xcd(int bid, int nb) {
     return x * q + min(x, r) + k;
 }
 
+// One scan point against the lane's particle, given the (possibly missed)
+// Gaussian record; accumulates into the lane's sums.  Outliers are counted
+// (each costs c_max in the solve) and add nothing to the cost sum, H or b
+// (selected, not branched).
+struct Acc {
+    float h[21];
+    float bw0, bw1, bw2, oe0, oe1, oe2;
+    float cost, comp, nout;
+};
+
+__device__ __forceinline__ void accumulate(Acc& S, const mpdet::mat3& Rm, const float a, const float dmax2,
+                                           const float cmax, const float4 r0, const float4 r1, const float4 r2,
+                                           const float3 p, const int32_t g, const float4 gm, const float4 gn) {
+    const float3 mu = make_float3(r0.x, r0.y, r0.z);
+    float ex = gm.x - p.x, ey = gm.y - p.y, ez = gm.z - p.z;
+    const float d2 = __builtin_fmaf(ex, ex, __builtin_fmaf(ey, ey, ez * ez));
+    const bool inl = (g >= 0) && (d2 <= dmax2);
+    // cells outside the band carry mu = +inf: keep their residual out of the sums
+    ex = inl ? ex : 0.0f;
+    ey = inl ? ey : 0.0f;
+    ez = inl ? ez : 0.0f;
+    const float3 u = mpdet::rot_t(Rm, make_float3(gn.x, gn.y, gn.z));
+    const float3 eb = mpdet::rot_t(Rm, make_float3(ex, ey, ez));
+    const float aux = a * u.x, auy = a * u.y, auz = a * u.z;
+    // C = Sigma^S + I - a u u^T  (the identity is folded into r0.w, r1.z, r2.x)
+    const float c00 = __builtin_fmaf(-aux, u.x, r0.w);
+    const float c01 = __builtin_fmaf(-aux, u.y, r1.x);
+    const float c02 = __builtin_fmaf(-aux, u.z, r1.y);
+    const float c11 = __builtin_fmaf(-auy, u.y, r1.z);
+    const float c12 = __builtin_fmaf(-auy, u.z, r1.w);
+    const float c22 = __builtin_fmaf(-auz, u.z, r2.x);
+    const float i00 = __builtin_fmaf(c11, c22, -c12 * c12);
+    const float i01 = __builtin_fmaf(c02, c12, -c01 * c22);
+    const float i02 = __builtin_fmaf(c01, c12, -c02 * c11);
+    const float i11 = __builtin_fmaf(c00, c22, -c02 * c02);
+    const float i12 = __builtin_fmaf(c01, c02, -c00 * c12);
+    const float i22 = __builtin_fmaf(c00, c11, -c01 * c01);
+    const float det = __builtin_fmaf(c00, i00, __builtin_fmaf(c01, i01, c02 * i02));
+    const float rd = inl ? __builtin_amdgcn_rcpf(det) : 0.0f;
+    const float o00 = i00 * rd, o01 = i01 * rd, o02 = i02 * rd, o11 = i11 * rd, o12 = i12 * rd, o22 = i22 * rd;
+    const float w0 = __builtin_fmaf(o00, eb.x, __builtin_fmaf(o01, eb.y, o02 * eb.z));
+    const float w1 = __builtin_fmaf(o01, eb.x, __builtin_fmaf(o11, eb.y, o12 * eb.z));
+    const float w2 = __builtin_fmaf(o02, eb.x, __builtin_fmaf(o12, eb.y, o22 * eb.z));
+    const float cst = __builtin_fmaf(eb.x, w0, __builtin_fmaf(eb.y, w1, eb.z * w2));
+    {
+        const float y = (inl ? fminf(cst, cmax) : 0.0f) - S.comp;   // outliers: counted in nout
+        const float tt = S.cost + y;
+        S.comp = (tt - S.cost) - y;
+        S.cost = tt;
+    }
+    S.nout += inl ? 0.0f : 1.0f;
+    S.oe0 += w0;
+    S.oe1 += w1;
+    S.oe2 += w2;
+    S.bw0 = __builtin_fmaf(w1, mu.z, __builtin_fmaf(-w2, mu.y, S.bw0));
+    S.bw1 = __builtin_fmaf(w2, mu.x, __builtin_fmaf(-w0, mu.z, S.bw1));
+    S.bw2 = __builtin_fmaf(w0, mu.y, __builtin_fmaf(-w1, mu.x, S.bw2));
+    // B = [mu]x Omega: row0 = -mu_z O_1 + mu_y O_2, row1 = mu_z O_0 - mu_x O_2, row2 = -mu_y O_0 + mu_x O_1
+    const float B00 = __builtin_fmaf(-mu.z, o01, mu.y * o02);
+    const float B01 = __builtin_fmaf(-mu.z, o11, mu.y * o12);
+    const float B02 = __builtin_fmaf(-mu.z, o12, mu.y * o22);
+    const float B10 = __builtin_fmaf(mu.z, o00, -mu.x * o02);
+    const float B11 = __builtin_fmaf(mu.z, o01, -mu.x * o12);
+    const float B12 = __builtin_fmaf(mu.z, o02, -mu.x * o22);
+    const float B20 = __builtin_fmaf(-mu.y, o00, mu.x * o01);
+    const float B21 = __builtin_fmaf(-mu.y, o01, mu.x * o11);
+    const float B22 = __builtin_fmaf(-mu.y, o02, mu.x * o12);
+    // H_ww = -B [mu]x
+    S.h[0] = __builtin_fmaf(-B01, mu.z, __builtin_fmaf(B02, mu.y, S.h[0]));
+    S.h[1] = __builtin_fmaf(-B02, mu.x, __builtin_fmaf(B00, mu.z, S.h[1]));
+    S.h[2] = __builtin_fmaf(-B00, mu.y, __builtin_fmaf(B01, mu.x, S.h[2]));
+    S.h[6] = __builtin_fmaf(-B12, mu.x, __builtin_fmaf(B10, mu.z, S.h[6]));
+    S.h[7] = __builtin_fmaf(-B10, mu.y, __builtin_fmaf(B11, mu.x, S.h[7]));
+    S.h[11] = __builtin_fmaf(-B20, mu.y, __builtin_fmaf(B21, mu.x, S.h[11]));
+    // H_wv = B
+    S.h[3] += B00; S.h[4] += B01; S.h[5] += B02;
+    S.h[8] += B10; S.h[9] += B11; S.h[10] += B12;
+    S.h[12] += B20; S.h[13] += B21; S.h[14] += B22;
+    // H_vv = Omega
+    S.h[15] += o00; S.h[16] += o01; S.h[17] += o02;
+    S.h[18] += o11; S.h[19] += o12; S.h[20] += o22;
+}
+
+// Scan points are walked in batches of BATCH per lane: first the NNF cells of
+// the whole batch are requested back to back (BATCH independent gathers in
+// flight), then the batch is evaluated with each Gaussian record fetched two
+// points ahead.  The transform is recomputed in the second pass (same
+// operations, same result) instead of being kept in registers.
+template <int BACKEND, int BATCH>
 __global__ __launch_bounds__(kLanes) void k_lik(LikArgs A) {
     __shared__ float4 tile[kTile * 3];
     const int nb = A.nbx * A.nchunks;
@@ -63,21 +152,22 @@ __global__ __launch_bounds__(kLanes) void k_lik(LikArgs A) {
     const int chunk = logical / A.nbx;
     const int pblk = logical - chunk * A.nbx;
     const int s = pblk * kLanes + threadIdx.x;
-    const bool active = s < A.n;
-    const int i = active ? (A.order ? A.order[s] : s) : 0;
+    int i = s < A.n ? (A.order ? A.order[s] : s) : 0;
+    const bool active = s < A.n && i >= 0 && i < A.n;
+    if (!active) i = 0;
 
     const float4 q4 = A.poses[2 * i];
     const float4 t4 = A.poses[2 * i + 1];
     const mpdet::mat3 Rm = mpdet::qmat(mpdet::quat{q4.x, q4.y, q4.z, q4.w});
-    const float* R = Rm.m;
     const float3 t = make_float3(t4.x, t4.y, t4.z);
     const float a = A.map.gicp_a;
+    const float4* __restrict__ gauss = A.map.gauss;
 
-    float h[21];
+    Acc S;
 #pragma unroll
-    for (int m = 0; m < 21; ++m) h[m] = 0.0f;
-    float bw0 = 0, bw1 = 0, bw2 = 0, oe0 = 0, oe1 = 0, oe2 = 0;
-    float cost = 0.0f, comp = 0.0f, nout = 0.0f;
+    for (int m = 0; m < 21; ++m) S.h[m] = 0.0f;
+    S.bw0 = S.bw1 = S.bw2 = S.oe0 = S.oe1 = S.oe2 = 0.0f;
+    S.cost = S.comp = S.nout = 0.0f;
 
     const int k0 = chunk * A.chunk_len;
     const int k1 = min(A.ns, k0 + A.chunk_len);
@@ -95,108 +185,64 @@ __global__ __launch_bounds__(kLanes) void k_lik(LikArgs A) {
         }
         __syncthreads();
         if (!active) continue;
-        for (int k = 0; k < cnt; ++k) {
-            const float4 r0 = tile[3 * k], r1 = tile[3 * k + 1], r2 = tile[3 * k + 2];
-            const float3 mu = make_float3(r0.x, r0.y, r0.z);
-            const float3 p = mpdet::xform(R, t, mu);
-            const int32_t g = mp_nnf_lookup(A.map, p.x, p.y, p.z);
-            bool inl = g >= 0;
-            float4 gm = make_float4(0, 0, 0, 0), gn = make_float4(0, 0, 0, 0);
-            float ex = 0, ey = 0, ez = 0;
-            if (inl) {
-                gm = A.map.gauss[2 * g];
-                gn = A.map.gauss[2 * g + 1];
-                ex = gm.x - p.x;
-                ey = gm.y - p.y;
-                ez = gm.z - p.z;
-                const float d2 = __builtin_fmaf(ex, ex, __builtin_fmaf(ey, ey, ez * ez));
-                inl = d2 <= A.dmax2;
+        for (int kb = 0; kb < cnt; kb += BATCH) {
+            const int nbat = min(BATCH, cnt - kb);
+            int32_t g[BATCH];
+            // dense: g = band-grid cell (record fetched directly); hash: g = Gaussian id
+            const float4* __restrict__ rec = BACKEND == MP_NNF_DENSE ? A.map.drec : gauss;
+#pragma unroll
+            for (int b = 0; b < BATCH; ++b) {
+                g[b] = -1;
+                if (b < nbat) {
+                    const float4 r0 = tile[3 * (kb + b)];
+                    const float3 p = mpdet::xform(Rm.m, t, make_float3(r0.x, r0.y, r0.z));
+                    g[b] = BACKEND == MP_NNF_DENSE ? mp_nnf_cell(A.map, p.x, p.y, p.z)
+                                                   : mp_nnf_lookup<BACKEND>(A.map, p.x, p.y, p.z);
+                }
             }
-            if (!inl) {
-                nout += 1.0f;
-                continue;
+            float4 gm[BATCH], gn[BATCH];
+#pragma unroll
+            for (int b = 0; b < 2 && b < BATCH; ++b) {
+                gm[b] = rec[2 * (size_t)max(g[b], 0)];
+                gn[b] = rec[2 * (size_t)max(g[b], 0) + 1];
             }
-            // ---- tolerance path (contraction allowed by explicit fma) ----
-            const float3 u = mpdet::rot_t(Rm, make_float3(gn.x, gn.y, gn.z));
-            const float3 eb = mpdet::rot_t(Rm, make_float3(ex, ey, ez));
-            const float aux = a * u.x, auy = a * u.y, auz = a * u.z;
-            // C = Sigma^S + I - a u u^T
-            const float c00 = __builtin_fmaf(-aux, u.x, r0.w);
-            const float c01 = __builtin_fmaf(-aux, u.y, r1.x);
-            const float c02 = __builtin_fmaf(-aux, u.z, r1.y);
-            const float c11 = __builtin_fmaf(-auy, u.y, r1.z);
-            const float c12 = __builtin_fmaf(-auy, u.z, r1.w);
-            const float c22 = __builtin_fmaf(-auz, u.z, r2.x);
-            // adjugate and determinant
-            const float i00 = __builtin_fmaf(c11, c22, -c12 * c12);
-            const float i01 = __builtin_fmaf(c02, c12, -c01 * c22);
-            const float i02 = __builtin_fmaf(c01, c12, -c02 * c11);
-            const float i11 = __builtin_fmaf(c00, c22, -c02 * c02);
-            const float i12 = __builtin_fmaf(c01, c02, -c00 * c12);
-            const float i22 = __builtin_fmaf(c00, c11, -c01 * c01);
-            const float det = __builtin_fmaf(c00, i00, __builtin_fmaf(c01, i01, c02 * i02));
-            const float rd = __builtin_amdgcn_rcpf(det);
-            const float o00 = i00 * rd, o01 = i01 * rd, o02 = i02 * rd, o11 = i11 * rd, o12 = i12 * rd,
-                        o22 = i22 * rd;
-            // Omega e and the cost
-            const float w0 = __builtin_fmaf(o00, eb.x, __builtin_fmaf(o01, eb.y, o02 * eb.z));
-            const float w1 = __builtin_fmaf(o01, eb.x, __builtin_fmaf(o11, eb.y, o12 * eb.z));
-            const float w2 = __builtin_fmaf(o02, eb.x, __builtin_fmaf(o12, eb.y, o22 * eb.z));
-            const float cst = __builtin_fmaf(eb.x, w0, __builtin_fmaf(eb.y, w1, eb.z * w2));
-            {
-                const float y = fminf(cst, A.cmax) - comp;
-                const float tt = cost + y;
-                comp = (tt - cost) - y;
-                cost = tt;
+#pragma unroll
+            for (int b = 0; b < BATCH; ++b) {
+                if (b + 2 < BATCH) {
+                    gm[b + 2] = rec[2 * (size_t)max(g[b + 2], 0)];
+                    gn[b + 2] = rec[2 * (size_t)max(g[b + 2], 0) + 1];
+                }
+                if (b < nbat) {
+                    const float4 r0 = tile[3 * (kb + b)], r1 = tile[3 * (kb + b) + 1], r2 = tile[3 * (kb + b) + 2];
+                    const float3 p = mpdet::xform(Rm.m, t, make_float3(r0.x, r0.y, r0.z));
+                    accumulate(S, Rm, a, A.dmax2, A.cmax, r0, r1, r2, p, g[b], gm[b], gn[b]);
+                }
             }
-            // b_v = -Omega e (negated at the end), b_w = (Omega e) x mu
-            oe0 += w0;
-            oe1 += w1;
-            oe2 += w2;
-            bw0 = __builtin_fmaf(w1, mu.z, __builtin_fmaf(-w2, mu.y, bw0));
-            bw1 = __builtin_fmaf(w2, mu.x, __builtin_fmaf(-w0, mu.z, bw1));
-            bw2 = __builtin_fmaf(w0, mu.y, __builtin_fmaf(-w1, mu.x, bw2));
-            // B = [mu]x Omega (rows): row0 = -mu_z O_1 + mu_y O_2, row1 = mu_z O_0 - mu_x O_2,
-            //                          row2 = -mu_y O_0 + mu_x O_1
-            const float B00 = __builtin_fmaf(-mu.z, o01, mu.y * o02);
-            const float B01 = __builtin_fmaf(-mu.z, o11, mu.y * o12);
-            const float B02 = __builtin_fmaf(-mu.z, o12, mu.y * o22);
-            const float B10 = __builtin_fmaf(mu.z, o00, -mu.x * o02);
-            const float B11 = __builtin_fmaf(mu.z, o01, -mu.x * o12);
-            const float B12 = __builtin_fmaf(mu.z, o02, -mu.x * o22);
-            const float B20 = __builtin_fmaf(-mu.y, o00, mu.x * o01);
-            const float B21 = __builtin_fmaf(-mu.y, o01, mu.x * o11);
-            const float B22 = __builtin_fmaf(-mu.y, o02, mu.x * o12);
-            // H_ww = -B [mu]x : (B[mu]x)_{r0} = B_r1 mu_z - B_r2 mu_y, _{r1} = B_r2 mu_x - B_r0 mu_z,
-            //                   _{r2} = B_r0 mu_y - B_r1 mu_x
-            h[0] = __builtin_fmaf(-B01, mu.z, __builtin_fmaf(B02, mu.y, h[0]));
-            h[1] = __builtin_fmaf(-B02, mu.x, __builtin_fmaf(B00, mu.z, h[1]));
-            h[2] = __builtin_fmaf(-B00, mu.y, __builtin_fmaf(B01, mu.x, h[2]));
-            h[6] = __builtin_fmaf(-B12, mu.x, __builtin_fmaf(B10, mu.z, h[6]));
-            h[7] = __builtin_fmaf(-B10, mu.y, __builtin_fmaf(B11, mu.x, h[7]));
-            h[11] = __builtin_fmaf(-B20, mu.y, __builtin_fmaf(B21, mu.x, h[11]));
-            // H_wv = B
-            h[3] += B00; h[4] += B01; h[5] += B02;
-            h[8] += B10; h[9] += B11; h[10] += B12;
-            h[12] += B20; h[13] += B21; h[14] += B22;
-            // H_vv = Omega
-            h[15] += o00; h[16] += o01; h[17] += o02;
-            h[18] += o11; h[19] += o12; h[20] += o22;
         }
     }
     if (!active) return;
     float* out = A.partial + (size_t)chunk * kNumPartial * A.n + i;
     const size_t st = (size_t)A.n;
 #pragma unroll
-    for (int m = 0; m < 21; ++m) out[m * st] = h[m];
-    out[21 * st] = bw0;
-    out[22 * st] = bw1;
-    out[23 * st] = bw2;
-    out[24 * st] = -oe0;
-    out[25 * st] = -oe1;
-    out[26 * st] = -oe2;
-    out[27 * st] = cost;
-    out[28 * st] = nout;
+    for (int m = 0; m < 21; ++m) out[m * st] = S.h[m];
+    out[21 * st] = S.bw0;
+    out[22 * st] = S.bw1;
+    out[23 * st] = S.bw2;
+    out[24 * st] = -S.oe0;
+    out[25 * st] = -S.oe1;
+    out[26 * st] = -S.oe2;
+    out[27 * st] = S.cost;
+    out[28 * st] = S.nout;
+}
+
+template <int BACKEND>
+void launch_lik_batch(int batch, unsigned grid, hipStream_t s, const LikArgs& A) {
+    switch (batch) {
+        case 4: k_lik<BACKEND, 4><<<grid, kLanes, 0, s>>>(A); break;
+        case 8: k_lik<BACKEND, 8><<<grid, kLanes, 0, s>>>(A); break;
+        case 32: k_lik<BACKEND, 32><<<grid, kLanes, 0, s>>>(A); break;
+        default: k_lik<BACKEND, 16><<<grid, kLanes, 0, s>>>(A); break;
+    }
 }
 
 struct SolveArgs {
@@ -336,7 +382,8 @@ void mp_launch_likelihood(mp_filter f, hipStream_t s) {
     A.cmax = f->p.c_max;
     if (ns > 0) {
         mp_tick(f, MP_STAGE_LIK_CORE, true, s);
-        k_lik<<<nbx * nch, kLanes, 0, s>>>(A);
+        if (A.map.backend == MP_NNF_DENSE) launch_lik_batch<MP_NNF_DENSE>(f->p.lik_batch, nbx * nch, s, A);
+        else launch_lik_batch<MP_NNF_HASH>(f->p.lik_batch, nbx * nch, s, A);
         MP_CHECK_LAUNCH();
         mp_tick(f, MP_STAGE_LIK_CORE, false, s);
     } else {

@@ -237,6 +237,21 @@ __global__ void k_dense_finalize(const unsigned long long* __restrict__ cells, i
     if ((threadIdx.x & 63) == 0 && b) atomicAdd(count, (unsigned long long)__popcll(b));
 }
 
+// per-cell copy of the nearest Gaussian's record (the likelihood's one-fetch path)
+__global__ void k_dense_records(const int32_t* __restrict__ dense, int64_t ncell, const float4* __restrict__ gauss,
+                                float4* __restrict__ drec) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncell) return;
+    const int32_t g = dense[c];
+    if (g >= 0) {
+        drec[2 * c] = gauss[2 * (int64_t)g];
+        drec[2 * c + 1] = gauss[2 * (int64_t)g + 1];
+    } else {
+        drec[2 * c] = make_float4(__builtin_inff(), __builtin_inff(), __builtin_inff(), 0.0f);
+        drec[2 * c + 1] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    }
+}
+
 // wide build table: slot = {key (linear index + 1, 0 empty), value}
 __global__ void k_band_hash(const int3* __restrict__ gvox, int64_t G, int R, BandGrid bg,
                             unsigned long long* __restrict__ tkey, unsigned long long* __restrict__ tval,
@@ -434,7 +449,8 @@ void mp_build_map(mp_map m, const float* xyz, int64_t n, hipStream_t s) {
     }
     const double bcells = (double)bg.dim[0] * (double)bg.dim[1] * (double)bg.dim[2];
     int backend = P.backend;
-    if (backend == MP_NNF_AUTO) backend = bcells <= 268435456.0 ? MP_NNF_DENSE : MP_NNF_HASH;
+    // dense: 4 B id + 32 B record per cell of the band grid's box
+    if (backend == MP_NNF_AUTO) backend = bcells <= 67108864.0 ? MP_NNF_DENSE : MP_NNF_HASH;
     if (backend == MP_NNF_DENSE && bcells > 2147483647.0)
         mp_throw(MP_E_UNSUPPORTED, "mp_map_build: dense band grid exceeds 2^31 cells");
     if (backend == MP_NNF_HASH && bcells > 4294967294.0)
@@ -459,7 +475,13 @@ void mp_build_map(mp_map m, const float* xyz, int64_t n, hipStream_t s) {
         MP_CHECK_LAUNCH();
         MP_HIP(hipMemcpyAsync(&band, d_count.p, 8, hipMemcpyDeviceToHost, s));
         MP_HIP(hipStreamSynchronize(s));
+        m->drec.alloc(sizeof(float4) * 2 * (size_t)nc);
+        k_dense_records<<<nblk(nc), kBlock, 0, s>>>(m->dense.as<int32_t>(), nc, m->gauss.as<float4>(),
+                                                    m->drec.as<float4>());
+        MP_CHECK_LAUNCH();
+        MP_HIP(hipStreamSynchronize(s));
         view.dense = m->dense.as<int32_t>();
+        view.drec = m->drec.as<float4>();
         info.table_slots = nc;
     } else {
         const uint64_t wcap = next_pow2((uint64_t)std::max<int64_t>(2 * emits, 64));
@@ -502,5 +524,5 @@ void mp_build_map(mp_map m, const float* xyz, int64_t n, hipStream_t s) {
     info.num_gauss = G;
     info.num_band = (int64_t)band;
     info.backend = backend;
-    info.device_bytes = (int64_t)(m->gauss.bytes + m->dense.bytes + m->table.bytes);
+    info.device_bytes = (int64_t)(m->gauss.bytes + m->dense.bytes + m->drec.bytes + m->table.bytes + m->vox.bytes);
 }

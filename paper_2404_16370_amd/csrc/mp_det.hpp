@@ -186,10 +186,9 @@ __device__ inline float3 xform(const float* R, const float3 t, const float3 mu) 
     return p;
 }
 
+// floor to int32, clamped to [-2^30, 2^30] (a single med3 for finite input)
 __device__ inline int32_t floor_i32(float z) {
-    float f = floorf(z);
-    f = f > 1073741824.0f ? 1073741824.0f : f;
-    f = f < -1073741824.0f ? -1073741824.0f : f;
+    const float f = __builtin_fminf(__builtin_fmaxf(floorf(z), -1073741824.0f), 1073741824.0f);
     return (int32_t)f;
 }
 

@@ -55,13 +55,15 @@ struct MapView {
     const int32_t* dense;   // dim product cells, -1 = miss
     const uint2* table;     // hash slots {key = linear index + 1 (0 empty), gid}
     const float4* gauss;    // 2 per Gaussian: (mu, count), (n, 0)
+    const float4* drec;     // dense backend: 2 per cell, the nearest Gaussian's record;
+                            // cells outside the band hold mu = +inf
 };
 
 struct mp_map_s {
     mp_map_params params{};
     mp_map_info info{};
     MapView view{};
-    DevMem gauss, dense, table, vox;   // vox: G x int3 voxel coordinates
+    DevMem gauss, dense, drec, table, vox;   // vox: G x int3 voxel coordinates
     float box_lo[3], box_hi[3];
     int users = 0;
 };
@@ -95,7 +97,9 @@ struct mp_filter_s {
     DevMem prior, post0, post1;   // N float
     DevMem red;               // reduction scratch
     DevMem flags;             // per-step counters (int32)
-    DevMem scan;              // n x 12 float
+    DevMem scan;              // n x 12 float records in the likelihood's walk order
+    DevMem scan_orig;         // n x 12 float records in the caller's order
+    DevMem scan_perm;         // n int32: walk position -> caller index
     DevMem scan_xyz;          // n x 3 float staging
     DevMem tlsh;              // 8 float
     DevMem stepinfo;          // posterior summary (doubles)
@@ -126,6 +130,7 @@ void mp_map_lookup_launch(const MapView& v, const float* xyz_dev, int64_t n, int
 // scan covariances (scan.hip)
 void mp_scan_records(const float* xyz_dev, const float* cov6_dev, int32_t n, int32_t k, float eps, float* rec_dev,
                      hipStream_t s);
+void mp_scan_permute(const float* rec_orig, const int32_t* perm, int32_t n, float* rec_out, hipStream_t s);
 
 // filter stages
 void mp_launch_init_uniform(mp_filter f, const float lo[3], const float hi[3], hipStream_t s);

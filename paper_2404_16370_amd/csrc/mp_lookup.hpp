@@ -11,14 +11,17 @@ __host__ __device__ inline uint32_t mp_grid_hash(int32_t x, int32_t y, int32_t z
     return ((uint32_t)x * 73856093u) ^ ((uint32_t)y * 19349663u) ^ ((uint32_t)z * 83492791u);
 }
 
-// Gaussian id of the voxel floor(p * 1/r), or -1 outside the band
+// Gaussian id of the voxel floor(p * 1/r), or -1 outside the band.
+// BACKEND: MP_NNF_DENSE, MP_NNF_HASH, or 0 to branch on v.backend.
+template <int BACKEND = 0>
 __device__ __forceinline__ int32_t mp_nnf_lookup(const MapView& v, float px, float py, float pz) {
     const uint32_t x = (uint32_t)mpdet::floor_i32(px * v.inv_r) - (uint32_t)v.org[0];
     const uint32_t y = (uint32_t)mpdet::floor_i32(py * v.inv_r) - (uint32_t)v.org[1];
     const uint32_t z = (uint32_t)mpdet::floor_i32(pz * v.inv_r) - (uint32_t)v.org[2];
     if (x >= (uint32_t)v.dim[0] || y >= (uint32_t)v.dim[1] || z >= (uint32_t)v.dim[2]) return -1;
+    const bool dense = BACKEND == 0 ? v.backend == MP_NNF_DENSE : BACKEND == MP_NNF_DENSE;
+    if (dense) return v.dense[((uint32_t)z * (uint32_t)v.dim[1] + y) * (uint32_t)v.dim[0] + x];
     const uint64_t L = ((uint64_t)z * (uint32_t)v.dim[1] + y) * (uint32_t)v.dim[0] + x;
-    if (v.backend == MP_NNF_DENSE) return v.dense[L];
     const uint32_t key = (uint32_t)L + 1u;
     uint32_t h = mp_grid_hash((int32_t)x, (int32_t)y, (int32_t)z) & v.mask;
     for (;;) {
@@ -27,4 +30,13 @@ __device__ __forceinline__ int32_t mp_nnf_lookup(const MapView& v, float px, flo
         if (s.x == 0u) return -1;
         h = (h + 1u) & v.mask;
     }
+}
+
+// dense band-grid cell of floor(p * 1/r), or -1 outside the grid's box
+__device__ __forceinline__ int32_t mp_nnf_cell(const MapView& v, float px, float py, float pz) {
+    const uint32_t x = (uint32_t)mpdet::floor_i32(px * v.inv_r) - (uint32_t)v.org[0];
+    const uint32_t y = (uint32_t)mpdet::floor_i32(py * v.inv_r) - (uint32_t)v.org[1];
+    const uint32_t z = (uint32_t)mpdet::floor_i32(pz * v.inv_r) - (uint32_t)v.org[2];
+    if (x >= (uint32_t)v.dim[0] || y >= (uint32_t)v.dim[1] || z >= (uint32_t)v.dim[2]) return -1;
+    return (int32_t)((z * (uint32_t)v.dim[1] + y) * (uint32_t)v.dim[0] + x);
 }

@@ -140,6 +140,7 @@ __global__ __launch_bounds__(256) void k_refresh(RefreshArgs A) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= A.n) return;
     const int i = A.sorted[s];
+    if (i < 0 || i >= A.n) return;
     const float4 qi4 = A.poses[2 * i], ti4 = A.poses[2 * i + 1];
     const mpdet::quat qi{qi4.x, qi4.y, qi4.z, qi4.w};
     const float3 ti = make_float3(ti4.x, ti4.y, ti4.z);
@@ -153,7 +154,11 @@ __global__ __launch_bounds__(256) void k_refresh(RefreshArgs A) {
         tk.insert(qv, j);
     };
     // bucket window (Alg. 1 gather loop, capped at C mates)
-    const int h = A.head[s], e = A.end[s];
+    int h = A.head[s], e = A.end[s];
+    if (!(h >= 0 && h <= s && s < e && e <= A.n)) {
+        h = s;
+        e = s + 1;
+    }
     const int m = e - h;
     const int w = min(m - 1, A.C);
     for (int d = 1; d <= w; ++d) {
@@ -180,9 +185,14 @@ __global__ __launch_bounds__(256) void k_refresh(RefreshArgs A) {
 }
 
 __global__ void k_reset_lists(int32_t* __restrict__ nbr, float* __restrict__ kval, int32_t* __restrict__ cnt,
-                              float* __restrict__ prior, int n, int K) {
+                              float* __restrict__ prior, int32_t* __restrict__ sorted, int32_t* __restrict__ head,
+                              int32_t* __restrict__ end, int n, int K) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    // identity order, one particle per bucket, until the first LSH pass
+    sorted[i] = i;
+    head[i] = i;
+    end[i] = i + 1;
     nbr[i] = i;
     kval[i] = 1.0f;
     for (int a = 1; a < K; ++a) {
@@ -261,6 +271,7 @@ void mp_launch_refresh(mp_filter f, hipStream_t s) {
 
 void mp_launch_reset_lists(mp_filter f, hipStream_t s) {
     k_reset_lists<<<nblk(f->n), 256, 0, s>>>(f->nbr.as<int32_t>(), f->kval.as<float>(), f->cnt.as<int32_t>(),
-                                               f->prior.as<float>(), f->n, f->K);
+                                               f->prior.as<float>(), f->sorted.as<int32_t>(), f->head.as<int32_t>(),
+                                               f->end.as<int32_t>(), f->n, f->K);
     MP_CHECK_LAUNCH();
 }

@@ -161,7 +161,24 @@ __global__ void k_scan_given_cov(const float* __restrict__ xyz, const float* __r
     rec[3 * i + 2] = make_float4(c[5], 0.0f, 0.0f, 0.0f);
 }
 
+__global__ void k_scan_permute(const float4* __restrict__ in, const int32_t* __restrict__ perm, int n,
+                               float4* __restrict__ out) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const int j = perm[k];
+    out[3 * k] = in[3 * j];
+    out[3 * k + 1] = in[3 * j + 1];
+    out[3 * k + 2] = in[3 * j + 2];
+}
+
 }  // namespace
+
+void mp_scan_permute(const float* rec_orig, const int32_t* perm, int32_t n, float* rec_out, hipStream_t s) {
+    if (n <= 0) return;
+    k_scan_permute<<<(n + 255) / 256, 256, 0, s>>>(reinterpret_cast<const float4*>(rec_orig), perm, n,
+                                                    reinterpret_cast<float4*>(rec_out));
+    MP_CHECK_LAUNCH();
+}
 
 void mp_scan_records(const float* xyz, const float* cov6, int32_t n, int32_t k, float eps, float* rec,
                      hipStream_t s) {

@@ -49,7 +49,7 @@ class mp_filter_params(C.Structure):
                 ("lsh_sigma", C.c_float), ("c_max", C.c_float), ("d_max", C.c_float),
                 ("lambda_rel", C.c_float), ("lambda_abs", C.c_float), ("temperature", C.c_float),
                 ("prior_floor", C.c_float), ("cov_eps", C.c_float), ("lik_chunks", C.c_int32),
-                ("reserved", C.c_int32), ("seed", C.c_uint64)]
+                ("lik_batch", C.c_int32), ("seed", C.c_uint64)]
 
 
 class mp_init_desc(C.Structure):
@@ -78,6 +78,12 @@ def lib():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError("libmegapf.so is not built: run `python -m paper_2404_16370_amd.build`")
+    # torch bundles its own HIP runtime under the same soname; loading torch
+    # first makes the library bind to that one instance instead of a second
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = C.CDLL(LIB_PATH)
     vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
     L.mp_map_default_params.argtypes = [C.POINTER(mp_map_params)]
@@ -226,6 +232,7 @@ _DEBUG_LAYOUT = {  # name -> (dtype, shape as a function of (n, K, scan_n))
     "post": (np.float32, lambda n, K, s: (n,)),
     "post0": (np.float32, lambda n, K, s: (n,)),
     "scan": (np.float32, lambda n, K, s: (s, 12)),
+    "scan_walk": (np.float32, lambda n, K, s: (s, 12)),
     "tlsh": (np.float32, lambda n, K, s: (8,)),
 }
 
