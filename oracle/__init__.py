@@ -106,6 +106,16 @@ def _declare(L):
     L.mpo_chol6.argtypes = [_f64p, _f64p]; L.mpo_chol6.restype = C.c_int
     L.mpo_predict.argtypes = [_f32p, C.c_int64, _f32p, _vp, C.c_uint64, C.c_uint32, _f64p]
     L.mpo_num_threads.restype = C.c_int
+    L.mpo_score_field.argtypes = [_vp, _f32p, C.c_int64, C.c_float, C.c_float, C.c_float, _f64p, _f64p]
+    L.mpo_bf16_round.argtypes = [C.c_double]; L.mpo_bf16_round.restype = C.c_double
+    L.mpo_ff_freqs.argtypes = [C.c_float, C.c_int, _f32p]
+    L.mpo_ff_features.argtypes = [_f32p, C.c_int64, _f32p, _f32p, _f32p, C.c_int, C.c_int, _f64p]
+    L.mpo_mlp_nparams.argtypes = [C.c_int, C.c_int, C.c_int]; L.mpo_mlp_nparams.restype = C.c_int64
+    L.mpo_mlp_forward.argtypes = [_f64p, C.c_int, C.c_int, C.c_int, _f64p, C.c_int64, C.c_int, _f64p]
+    L.mpo_mlp_loss_grad.argtypes = [_f64p, C.c_int, C.c_int, C.c_int, _f64p, _f64p, C.c_int64, _vp]
+    L.mpo_mlp_loss_grad.restype = C.c_double
+    L.mpo_adam.argtypes = [_f64p, _f64p, _f64p, _f64p, C.c_int64, C.c_int, C.c_double, C.c_double, C.c_double,
+                           C.c_double]
 
 
 def _f32(a, shape=None):
@@ -340,6 +350,61 @@ def predict(poses8, dT, cov, seed, frame):
     cv = None if cov is None else _f32(cov).reshape(36)
     lib().mpo_predict(P, n, _f32(dT).reshape(7), _ptr(cv), seed, frame, out)
     return out
+
+
+# --------------------------------------------------------------------- surrogate
+def score_field(m: Map, p, sigma_s=0.03, dmax=1.0, cmax=9.0):
+    P = _f32(p).reshape(-1, 3)
+    n = P.shape[0]
+    s = np.zeros(n); g = np.zeros((n, 3))
+    if n:
+        lib().mpo_score_field(m.handle, P, n, sigma_s, dmax, cmax, s, g)
+    return s, g
+
+
+def bf16_round(x):
+    return np.vectorize(lambda v: lib().mpo_bf16_round(float(v)))(np.asarray(x, np.float64))
+
+
+def ff_freqs(fmax, nf=32):
+    f = np.zeros(nf, np.float32)
+    lib().mpo_ff_freqs(fmax, nf, f)
+    return f
+
+
+def ff_features(p, lo, inv_ext, freqs, bf16=False):
+    P = _f32(p).reshape(-1, 3)
+    n = P.shape[0]
+    fr = _f32(freqs)
+    out = np.zeros((n, 6 * len(fr)))
+    lib().mpo_ff_features(P, n, _f32(lo), _f32(inv_ext), fr, len(fr), int(bf16), out)
+    return out
+
+
+def mlp_nparams(d0=192, d1=128, d2=128):
+    return int(lib().mpo_mlp_nparams(d0, d1, d2))
+
+
+def mlp_forward(params, X, dims=(192, 128, 128), bf16=False):
+    X = np.ascontiguousarray(X, np.float64)
+    Y = np.zeros((X.shape[0], 4))
+    lib().mpo_mlp_forward(np.ascontiguousarray(params, np.float64), dims[0], dims[1], dims[2], X, X.shape[0],
+                          int(bf16), Y)
+    return Y
+
+
+def mlp_loss_grad(params, X, T, dims=(192, 128, 128)):
+    X = np.ascontiguousarray(X, np.float64)
+    G = np.zeros(len(params))
+    loss = lib().mpo_mlp_loss_grad(np.ascontiguousarray(params, np.float64), dims[0], dims[1], dims[2], X,
+                                   np.ascontiguousarray(T, np.float64), X.shape[0], _ptr(G))
+    return loss, G
+
+
+def adam(params, grads, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    P = np.array(params, np.float64); Mv = np.array(m, np.float64); Vv = np.array(v, np.float64)
+    lib().mpo_adam(P, np.ascontiguousarray(grads, np.float64), Mv, Vv, len(P), t, lr, b1, b2, eps)
+    return P, Mv, Vv
 
 
 def num_threads() -> int:

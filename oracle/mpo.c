@@ -1196,3 +1196,237 @@ MPO_API int mpo_num_threads(void) {
     return 1;
 #endif
 }
+
+/* ======================================================================= */
+/* Learned surrogate of the map's per-point score.                          */
+/*                                                                          */
+/* Score field (the surrogate's target): the per-point GICP cost with the   */
+/* scan covariance replaced by sigma_s^2 I, so it depends on position only: */
+/*   s(p) = min(e^T (Sigma^M_g + sigma_s^2 I)^-1 e, c_max) for an inlier     */
+/*   (NNF hit and |e| <= d_max, e = mu_g - p), c_max otherwise;             */
+/*   grad s = -2 Omega e for an unsaturated inlier, 0 otherwise.            */
+/* Network: x~ = (p - lo) * inv_ext (FP32), 32 geometric frequencies per    */
+/* axis, features sin/cos(2 pi frac(f_l x~_a)) ordered (axis, frequency,   */
+/* sin|cos) -> 192 -> 128 -> 128 -> 4 with SiLU; outputs (s, grad s).       */
+/* ======================================================================= */
+MPO_API void mpo_score_field(const mpo_map* m, const float* p, int64_t n, float sigma_s, float dmax, float cmax,
+                             double* s_out, double* g_out) {
+    float dmax2 = dmax * dmax;
+    double beta = 1.0 + (double)sigma_s * (double)sigma_s;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        const float* q = p + 3 * i;
+        int32_t v[3];
+        for (int a = 0; a < 3; ++a) v[a] = floor_to_i32(q[a] * m->inv_r);
+        int32_t g = nnf_voxel(m, v);
+        double s = cmax, gr[3] = {0, 0, 0};
+        if (g >= 0) {
+            const float* mm = m->mu + 3 * (int64_t)g;
+            float e32[3] = {mm[0] - q[0], mm[1] - q[1], mm[2] - q[2]};
+            float d2 = fmaf(e32[0], e32[0], fmaf(e32[1], e32[1], e32[2] * e32[2]));
+            if (d2 <= dmax2) {
+                double e[3] = {(double)mm[0] - q[0], (double)mm[1] - q[1], (double)mm[2] - q[2]};
+                const float* nv = m->nrm + 3 * (int64_t)g;
+                double C[9], Om[9];
+                for (int r = 0; r < 3; ++r)
+                    for (int c = 0; c < 3; ++c)
+                        C[3 * r + c] = (r == c ? beta : 0.0) - (double)m->a32 * (double)nv[r] * (double)nv[c];
+                mat3_inv(C, Om);
+                double Oe[3];
+                for (int a = 0; a < 3; ++a) Oe[a] = Om[3 * a] * e[0] + Om[3 * a + 1] * e[1] + Om[3 * a + 2] * e[2];
+                double c = e[0] * Oe[0] + e[1] * Oe[1] + e[2] * Oe[2];
+                if (c < cmax) {
+                    s = c;
+                    for (int a = 0; a < 3; ++a) gr[a] = -2.0 * Oe[a];
+                }
+            }
+        }
+        s_out[i] = s;
+        if (g_out) for (int a = 0; a < 3; ++a) g_out[3 * i + a] = gr[a];
+    }
+}
+
+/* round a double to the nearest bfloat16 (ties to even), returned as double */
+MPO_API double mpo_bf16_round(double x) {
+    float f = (float)x;
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    if ((u & 0x7F800000u) == 0x7F800000u) return (double)f;
+    uint32_t lsb = (u >> 16) & 1u;
+    u = (u + 0x7FFFu + lsb) & 0xFFFF0000u;
+    memcpy(&f, &u, 4);
+    return (double)f;
+}
+
+/* geometric frequencies, cycles per unit of the normalised coordinate */
+MPO_API void mpo_ff_freqs(float fmax, int nf, float* f) {
+    for (int l = 0; l < nf; ++l) f[l] = (float)pow((double)fmax, nf > 1 ? (double)l / (double)(nf - 1) : 0.0);
+}
+
+MPO_API void mpo_ff_features(const float* p, int64_t n, const float lo[3], const float inv_ext[3], const float* freqs,
+                             int nf, int bf16, double* feat /* n x 6 nf */) {
+    const double tau = 6.283185307179586476925;
+    for (int64_t i = 0; i < n; ++i) {
+        for (int a = 0; a < 3; ++a) {
+            float x = (p[3 * i + a] - lo[a]) * inv_ext[a];
+            for (int l = 0; l < nf; ++l) {
+                float t = freqs[l] * x;
+                float fr = t - floorf(t);
+                double ang = tau * (double)fr;
+                double sv = sin(ang), cv = cos(ang);
+                double* o = feat + (size_t)i * 6 * nf + (size_t)(2 * (a * nf + l));
+                o[0] = bf16 ? mpo_bf16_round(sv) : sv;
+                o[1] = bf16 ? mpo_bf16_round(cv) : cv;
+            }
+        }
+    }
+}
+
+static double silu(double z) { return z / (1.0 + exp(-z)); }
+static double silu_d(double z) {
+    double sg = 1.0 / (1.0 + exp(-z));
+    return sg * (1.0 + z * (1.0 - sg));
+}
+
+/* parameter vector layout (all FP64 here, FP32 master copies on the GPU):
+ * W1 [D0][D1] (input-major), b1 [D1], W2 [D1][D2], b2 [D2], W3 [D2][4], b3 [4] */
+MPO_API int64_t mpo_mlp_nparams(int d0, int d1, int d2) {
+    return (int64_t)d0 * d1 + d1 + (int64_t)d1 * d2 + d2 + (int64_t)d2 * 4 + 4;
+}
+
+/* forward; bf16 != 0 rounds the GEMM inputs (weights and activations) to
+ * bfloat16 as the GPU does, accumulating in FP64 */
+MPO_API void mpo_mlp_forward(const double* P, int d0, int d1, int d2, const double* X, int64_t n, int bf16,
+                             double* Y /* n x 4 */) {
+    const double* W1 = P;
+    const double* b1 = W1 + (size_t)d0 * d1;
+    const double* W2 = b1 + d1;
+    const double* b2 = W2 + (size_t)d1 * d2;
+    const double* W3 = b2 + d2;
+    const double* b3 = W3 + (size_t)d2 * 4;
+#pragma omp parallel
+    {
+        double* h1 = (double*)malloc(sizeof(double) * (size_t)d1);
+        double* h2 = (double*)malloc(sizeof(double) * (size_t)d2);
+#pragma omp for schedule(static)
+        for (int64_t i = 0; i < n; ++i) {
+            const double* x = X + (size_t)i * d0;
+            for (int j = 0; j < d1; ++j) {
+                double z = 0.0;
+                for (int k = 0; k < d0; ++k) {
+                    double w = bf16 ? mpo_bf16_round(W1[(size_t)k * d1 + j]) : W1[(size_t)k * d1 + j];
+                    double xv = bf16 ? mpo_bf16_round(x[k]) : x[k];
+                    z += xv * w;
+                }
+                h1[j] = silu(z + b1[j]);
+                if (bf16) h1[j] = mpo_bf16_round(h1[j]);
+            }
+            for (int j = 0; j < d2; ++j) {
+                double z = 0.0;
+                for (int k = 0; k < d1; ++k) {
+                    double w = bf16 ? mpo_bf16_round(W2[(size_t)k * d2 + j]) : W2[(size_t)k * d2 + j];
+                    z += h1[k] * w;
+                }
+                h2[j] = silu(z + b2[j]);
+                if (bf16) h2[j] = mpo_bf16_round(h2[j]);
+            }
+            for (int j = 0; j < 4; ++j) {
+                double z = 0.0;
+                for (int k = 0; k < d2; ++k) {
+                    double w = bf16 ? mpo_bf16_round(W3[(size_t)k * 4 + j]) : W3[(size_t)k * 4 + j];
+                    z += h2[k] * w;
+                }
+                Y[(size_t)i * 4 + j] = z + b3[j];
+            }
+        }
+        free(h1);
+        free(h2);
+    }
+}
+
+/* mean squared error over the 4 outputs, L = (1/n) sum_i |y_i - t_i|^2, and
+ * its gradient with respect to every parameter (FP64, no rounding) */
+MPO_API double mpo_mlp_loss_grad(const double* P, int d0, int d1, int d2, const double* X, const double* T, int64_t n,
+                                 double* G /* nparams, nullable */) {
+    const double* W1 = P;
+    const double* b1 = W1 + (size_t)d0 * d1;
+    const double* W2 = b1 + d1;
+    const double* b2 = W2 + (size_t)d1 * d2;
+    const double* W3 = b2 + d2;
+    const double* b3 = W3 + (size_t)d2 * 4;
+    int64_t np = mpo_mlp_nparams(d0, d1, d2);
+    if (G) memset(G, 0, sizeof(double) * (size_t)np);
+    double* gW1 = G;
+    double* gb1 = G ? gW1 + (size_t)d0 * d1 : NULL;
+    double* gW2 = G ? gb1 + d1 : NULL;
+    double* gb2 = G ? gW2 + (size_t)d1 * d2 : NULL;
+    double* gW3 = G ? gb2 + d2 : NULL;
+    double* gb3 = G ? gW3 + (size_t)d2 * 4 : NULL;
+    double* z1 = (double*)malloc(sizeof(double) * (size_t)d1);
+    double* h1 = (double*)malloc(sizeof(double) * (size_t)d1);
+    double* z2 = (double*)malloc(sizeof(double) * (size_t)d2);
+    double* h2 = (double*)malloc(sizeof(double) * (size_t)d2);
+    double* dz2 = (double*)malloc(sizeof(double) * (size_t)d2);
+    double* dz1 = (double*)malloc(sizeof(double) * (size_t)d1);
+    double loss = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        const double* x = X + (size_t)i * d0;
+        for (int j = 0; j < d1; ++j) {
+            double z = b1[j];
+            for (int k = 0; k < d0; ++k) z += x[k] * W1[(size_t)k * d1 + j];
+            z1[j] = z;
+            h1[j] = silu(z);
+        }
+        for (int j = 0; j < d2; ++j) {
+            double z = b2[j];
+            for (int k = 0; k < d1; ++k) z += h1[k] * W2[(size_t)k * d2 + j];
+            z2[j] = z;
+            h2[j] = silu(z);
+        }
+        double dy[4];
+        for (int j = 0; j < 4; ++j) {
+            double y = b3[j];
+            for (int k = 0; k < d2; ++k) y += h2[k] * W3[(size_t)k * 4 + j];
+            double r = y - T[(size_t)i * 4 + j];
+            loss += r * r;
+            dy[j] = 2.0 * r / (double)n;
+        }
+        if (!G) continue;
+        for (int j = 0; j < 4; ++j) {
+            gb3[j] += dy[j];
+            for (int k = 0; k < d2; ++k) gW3[(size_t)k * 4 + j] += h2[k] * dy[j];
+        }
+        for (int k = 0; k < d2; ++k) {
+            double s = 0.0;
+            for (int j = 0; j < 4; ++j) s += W3[(size_t)k * 4 + j] * dy[j];
+            dz2[k] = s * silu_d(z2[k]);
+        }
+        for (int j = 0; j < d2; ++j) {
+            gb2[j] += dz2[j];
+            for (int k = 0; k < d1; ++k) gW2[(size_t)k * d2 + j] += h1[k] * dz2[j];
+        }
+        for (int k = 0; k < d1; ++k) {
+            double s = 0.0;
+            for (int j = 0; j < d2; ++j) s += W2[(size_t)k * d2 + j] * dz2[j];
+            dz1[k] = s * silu_d(z1[k]);
+        }
+        for (int j = 0; j < d1; ++j) {
+            gb1[j] += dz1[j];
+            for (int k = 0; k < d0; ++k) gW1[(size_t)k * d1 + j] += x[k] * dz1[j];
+        }
+    }
+    free(z1); free(h1); free(z2); free(h2); free(dz2); free(dz1);
+    return loss / (double)n;
+}
+
+/* one Adam step (Kingma & Ba 2015) with bias correction, t >= 1 */
+MPO_API void mpo_adam(double* P, const double* G, double* Mv, double* Vv, int64_t np, int t, double lr, double b1,
+                      double b2, double eps) {
+    double c1 = 1.0 - pow(b1, (double)t), c2 = 1.0 - pow(b2, (double)t);
+    for (int64_t k = 0; k < np; ++k) {
+        Mv[k] = b1 * Mv[k] + (1.0 - b1) * G[k];
+        Vv[k] = b2 * Vv[k] + (1.0 - b2) * G[k] * G[k];
+        double mh = Mv[k] / c1, vh = Vv[k] / c2;
+        P[k] -= lr * mh / (sqrt(vh) + eps);
+    }
+}

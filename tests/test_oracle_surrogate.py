@@ -1,0 +1,246 @@
+"""Pins of the oracle's learned-surrogate functions, CPU only.
+
+  score field   closed form through the eigen-decomposition of Sigma^M (eigen-
+                values 1 - a and 1 along / across the normal); central
+                differences for its gradient; against the oracle's plain
+                likelihood with an isotropic scan covariance sigma_s^2 I at the
+                identity pose (one point per call); outliers and saturation
+  bf16 round    torch's float -> bfloat16 conversion (round to nearest even)
+  features      numpy sin / cos of 2 pi f x in FP64 (the FP32 fractional part
+                only changes the angle by rounding); geometric frequencies
+  MLP forward   torch.nn.functional linear + silu in float64
+  MLP gradient  torch autograd in float64 and central differences
+  BF16 forward  torch float64 forward on bf16-rounded weights and inputs
+  Adam          the first step's closed form (m^ = g, v^ = g^2) and torch.optim.Adam
+"""
+import numpy as np
+import pytest
+import torch
+
+
+@pytest.fixture(scope="module")
+def room(O):
+    from paper_2404_16370_amd import synth as S
+    sc = S.scene_room(1001)
+    xyz = S.sample_map(sc, 60_000, 2001)
+    return O.Map(xyz, 0.5, nnf_radius=2, min_points=5), sc
+
+
+def _near_surface_points(O, m, n, seed, spread=0.15):
+    rng = np.random.default_rng(seed)
+    g = m.gauss()
+    sel = rng.integers(0, m.G, n)
+    return (g["mu"][sel] + rng.normal(0, spread, (n, 3))).astype(np.float32)
+
+
+def test_score_field_closed_form(O, room):
+    m, _ = room
+    sig = float(np.float32(0.03))   # the oracle takes sigma_s as FP32
+    p = _near_surface_points(O, m, 4000, 1)
+    s, g = O.score_field(m, p, sigma_s=sig, dmax=0.3, cmax=9.0)
+    gid = m.lookup(p)
+    G = m.gauss()
+    a = np.float64(np.float32(1.0) - np.float32(1e-3))
+    hit = gid >= 0
+    mu = G["mu"][np.maximum(gid, 0)].astype(np.float64)
+    nv = G["normal"][np.maximum(gid, 0)].astype(np.float64)
+    e = mu - p.astype(np.float64)
+    # the stored FP32 normal is unit only to rounding: Sigma^M = I - a n n^T
+    # has eigenvalue 1 - a |n|^2 along n and 1 across it
+    n2 = np.sum(nv * nv, axis=1)
+    nv = nv / np.sqrt(n2)[:, None]
+    lam = 1.0 - a * n2 + sig ** 2
+    en = np.sum(e * nv, axis=1)
+    e2 = np.sum(e * e, axis=1)
+    c = en ** 2 / lam + (e2 - en ** 2) / (1.0 + sig ** 2)
+    inl = hit & (e2 <= 0.09)
+    # the inlier gate is an FP32 decision: skip points within rounding of it
+    clear = np.abs(e2 - 0.09) > 1e-5
+    ref = np.where(inl, np.minimum(c, 9.0), 9.0)
+    assert inl.sum() > 1000 and (~inl).sum() > 300
+    assert (inl & (c < 9.0)).sum() > 300 and (inl & (c >= 9.0)).sum() > 100
+    np.testing.assert_allclose(s[clear], ref[clear], rtol=1e-9, atol=1e-12)
+    # gradient of c with respect to p: -2 Omega e
+    Oe = en[:, None] * nv / lam[:, None] + (e - en[:, None] * nv) / (1.0 + sig ** 2)
+    gref = np.where((inl & (c < 9.0))[:, None], -2.0 * Oe, 0.0)
+    np.testing.assert_allclose(g[clear], gref[clear], rtol=1e-9, atol=1e-9)
+
+
+def test_score_field_gradient_fd(O, room):
+    m, _ = room
+    p = _near_surface_points(O, m, 3000, 2, spread=0.05).astype(np.float64)
+    s0, g0 = O.score_field(m, p, sigma_s=0.05, dmax=1.0, cmax=9.0)
+    h = 1e-3
+    ok = 0
+    for a in range(3):
+        dp = np.zeros(3); dp[a] = h
+        sp, _ = O.score_field(m, p + dp, sigma_s=0.05, dmax=1.0, cmax=9.0)
+        sm, _ = O.score_field(m, p - dp, sigma_s=0.05, dmax=1.0, cmax=9.0)
+        # keep points whose voxel association and inlier state do not change inside the stencil
+        same = (m.lookup(p + dp) == m.lookup(p)) & (m.lookup(p - dp) == m.lookup(p)) & (s0 < 8.0) & \
+               (sp < 8.0) & (sm < 8.0)
+        fd = (sp - sm) / (2 * h)
+        # the stencil is evaluated at FP32-rounded points: the FD error is
+        # O(h^2) curvature plus O(ulp(p) |grad| / h)
+        err = np.abs(fd[same] - g0[same, a])
+        scale = 1e-3 * (1.0 + np.abs(g0[same, a]))
+        assert np.all(err <= scale + 4e-4 * np.abs(g0[same, a]) + 2e-3), a
+        ok += same.sum()
+    assert ok > 1000
+
+
+def test_score_field_matches_plain_likelihood(O, room):
+    """At the identity pose with scan covariance sigma_s^2 I, the plain
+    per-point cost (Eq. 3) of a single-point scan is the score field."""
+    m, _ = room
+    sig = np.float32(0.2)
+    p = _near_surface_points(O, m, 200, 3, spread=0.3)
+    s, _ = O.score_field(m, p, sigma_s=float(sig), dmax=1.0, cmax=9.0)
+    T = np.array([[1, 0, 0, 0, 0, 0, 0, 0]], np.float32)
+    cov = np.array([[sig * sig, 0, 0, sig * sig, 0, sig * sig]], np.float32)
+    for i in range(len(p)):
+        out = O.likelihood(m, p[i:i + 1], cov, T, dmax=1.0, cmax=9.0)
+        # the plain path builds sigma^2 I in FP32; the score field in FP64
+        np.testing.assert_allclose(-out["loglik"][0], s[i], rtol=2e-6, atol=1e-9)
+
+
+def test_score_field_far_points_are_outliers(O, room):
+    m, sc = room
+    far = np.array([[500.0, 500.0, 500.0], [-300.0, 0.0, 0.0]], np.float32)
+    s, g = O.score_field(m, far, cmax=9.0)
+    assert np.all(s == 9.0) and np.all(g == 0.0)
+
+
+def test_bf16_round_matches_torch(O):
+    rng = np.random.default_rng(5)
+    x = np.concatenate([rng.normal(0, 1, 3000), rng.normal(0, 1e-3, 500), rng.normal(0, 1e4, 500),
+                        [0.0, -0.0, 1.0, 1.00390625, 1.01171875, -3.0e-39, 65504.0]])
+    # exact ties: values halfway between two bfloat16 numbers
+    base = torch.tensor(rng.normal(0, 1, 200), dtype=torch.float32).to(torch.bfloat16).to(torch.float32)
+    ulp = torch.abs(base) * 2.0 ** -8
+    x = np.concatenate([x, (base + 0.5 * ulp).numpy().astype(np.float64)])
+    x32 = x.astype(np.float32).astype(np.float64)
+    ref = torch.tensor(x32, dtype=torch.float32).to(torch.bfloat16).to(torch.float64).numpy()
+    got = O.bf16_round(x32)
+    np.testing.assert_array_equal(got, ref)
+
+
+def test_ff_features(O):
+    f = O.ff_freqs(100.0, 32)
+    assert f[0] == 1.0 and abs(f[-1] - 100.0) < 1e-4
+    r = f[1:].astype(np.float64) / f[:-1]
+    np.testing.assert_allclose(r, 100.0 ** (1 / 31), rtol=1e-6)
+    rng = np.random.default_rng(7)
+    lo = np.array([-10.0, -10.0, -1.0], np.float32)
+    ext = np.array([20.0, 20.0, 4.0], np.float32)
+    inv = (1.0 / ext).astype(np.float32)
+    p = (lo + rng.uniform(0, 1, (300, 3)) * ext).astype(np.float32)
+    F = O.ff_features(p, lo, inv, f)
+    assert F.shape == (300, 192)
+    x = ((p - lo) * inv).astype(np.float32).astype(np.float64)
+    for a in range(3):
+        for l in (0, 5, 17, 31):
+            t = f[l].astype(np.float64) * x[:, a]
+            col = 2 * (a * 32 + l)
+            # FP32 product f*x and fractional part: angle error <= 2 pi (|t| + 1) 2^-23
+            tol = 2 * np.pi * (np.abs(t) + 1) * 2.0 ** -22
+            assert np.all(np.abs(F[:, col] - np.sin(2 * np.pi * t)) <= tol)
+            assert np.all(np.abs(F[:, col + 1] - np.cos(2 * np.pi * t)) <= tol)
+    Fb = O.ff_features(p, lo, inv, f, bf16=True)
+    np.testing.assert_array_equal(Fb, O.bf16_round(F))
+
+
+def _torch_mlp(params, dims):
+    d0, d1, d2 = dims
+    P = torch.as_tensor(params)
+    o = 0
+    W1 = P[o:o + d0 * d1].view(d0, d1); o += d0 * d1
+    b1 = P[o:o + d1]; o += d1
+    W2 = P[o:o + d1 * d2].view(d1, d2); o += d1 * d2
+    b2 = P[o:o + d2]; o += d2
+    W3 = P[o:o + d2 * 4].view(d2, 4); o += d2 * 4
+    b3 = P[o:o + 4]
+    return W1, b1, W2, b2, W3, b3
+
+
+def _init(O, dims, seed):
+    rng = np.random.default_rng(seed)
+    n = O.mlp_nparams(*dims)
+    return rng.normal(0, 0.3, n)
+
+
+def test_mlp_forward_matches_torch(O):
+    dims = (24, 16, 12)
+    P = _init(O, dims, 11)
+    X = np.random.default_rng(12).normal(0, 1, (50, 24))
+    Y = O.mlp_forward(P, X, dims)
+    W1, b1, W2, b2, W3, b3 = _torch_mlp(P, dims)
+    x = torch.as_tensor(X)
+    h1 = torch.nn.functional.silu(x @ W1 + b1)
+    h2 = torch.nn.functional.silu(h1 @ W2 + b2)
+    ref = (h2 @ W3 + b3).numpy()
+    np.testing.assert_allclose(Y, ref, rtol=1e-12, atol=1e-12)
+
+
+def test_mlp_bf16_forward_matches_rounded_torch(O):
+    dims = (24, 16, 12)
+    P = _init(O, dims, 13)
+    X = np.random.default_rng(14).normal(0, 1, (40, 24))
+    Y = O.mlp_forward(P, X, dims, bf16=True)
+
+    def rb(t):
+        return t.to(torch.float32).to(torch.bfloat16).to(torch.float64)
+
+    W1, b1, W2, b2, W3, b3 = _torch_mlp(P, dims)
+    x = rb(torch.as_tensor(X))
+    h1 = rb(torch.nn.functional.silu(x @ rb(W1) + b1))
+    h2 = rb(torch.nn.functional.silu(h1 @ rb(W2) + b2))
+    ref = (h2 @ rb(W3) + b3).numpy()
+    np.testing.assert_allclose(Y, ref, rtol=1e-10, atol=1e-10)
+
+
+def test_mlp_gradient_autograd_and_fd(O):
+    dims = (18, 10, 8)
+    P = _init(O, dims, 15)
+    rng = np.random.default_rng(16)
+    X = rng.normal(0, 1, (30, 18))
+    T = rng.normal(0, 1, (30, 4))
+    L, G = O.mlp_loss_grad(P, X, T, dims)
+    Pt = torch.tensor(P, requires_grad=True)
+    W1, b1, W2, b2, W3, b3 = _torch_mlp(Pt, dims)
+    x = torch.as_tensor(X)
+    y = torch.nn.functional.silu(torch.nn.functional.silu(x @ W1 + b1) @ W2 + b2) @ W3 + b3
+    loss = ((y - torch.as_tensor(T)) ** 2).sum(dim=1).mean()
+    loss.backward()
+    np.testing.assert_allclose(L, loss.item(), rtol=1e-12)
+    np.testing.assert_allclose(G, Pt.grad.numpy(), rtol=1e-9, atol=1e-12)
+    h = 1e-6
+    for k in rng.choice(len(P), 25, replace=False):
+        Pp = P.copy(); Pp[k] += h
+        Pm = P.copy(); Pm[k] -= h
+        fd = (O.mlp_loss_grad(Pp, X, T, dims)[0] - O.mlp_loss_grad(Pm, X, T, dims)[0]) / (2 * h)
+        assert abs(fd - G[k]) <= 1e-6 * (1 + abs(G[k])), k
+
+
+def test_adam_first_step_closed_form(O):
+    rng = np.random.default_rng(17)
+    P = rng.normal(0, 1, 100)
+    g = rng.normal(0, 1, 100)
+    P1, m1, v1 = O.adam(P, g, np.zeros(100), np.zeros(100), 1, lr=1e-2)
+    np.testing.assert_allclose(P1, P - 1e-2 * g / (np.abs(g) + 1e-8), rtol=1e-14, atol=1e-15)
+    np.testing.assert_allclose(m1, 0.1 * g, rtol=1e-15)
+    np.testing.assert_allclose(v1, 0.001 * g * g, rtol=1e-14)
+
+
+def test_adam_matches_torch(O):
+    rng = np.random.default_rng(18)
+    P = rng.normal(0, 1, 64)
+    pt = torch.nn.Parameter(torch.tensor(P))
+    opt = torch.optim.Adam([pt], lr=3e-3, betas=(0.9, 0.999), eps=1e-8)
+    m = np.zeros(64); v = np.zeros(64)
+    for t in range(1, 8):
+        g = rng.normal(0, 1, 64)
+        pt.grad = torch.tensor(g)
+        opt.step()
+        P, m, v = O.adam(P, g, m, v, t, lr=3e-3)
+    np.testing.assert_allclose(P, pt.detach().numpy(), rtol=1e-12, atol=1e-14)
