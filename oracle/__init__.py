@@ -112,8 +112,11 @@ def _declare(L):
     L.mpo_ff_features.argtypes = [_f32p, C.c_int64, _f32p, _f32p, _f32p, C.c_int, C.c_int, _f64p]
     L.mpo_mlp_nparams.argtypes = [C.c_int, C.c_int, C.c_int]; L.mpo_mlp_nparams.restype = C.c_int64
     L.mpo_mlp_forward.argtypes = [_f64p, C.c_int, C.c_int, C.c_int, _f64p, C.c_int64, C.c_int, _f64p]
-    L.mpo_mlp_loss_grad.argtypes = [_f64p, C.c_int, C.c_int, C.c_int, _f64p, _f64p, C.c_int64, _vp]
+    L.mpo_mlp_loss_grad.argtypes = [_f64p, C.c_int, C.c_int, C.c_int, _f64p, _f64p, C.c_int64, C.c_int, _vp]
     L.mpo_mlp_loss_grad.restype = C.c_double
+    L.mpo_likelihood_rank1.argtypes = [_vp, _f32p, C.c_int32, _f32p, C.c_int64, C.c_int, C.c_float, C.c_float,
+                                       C.c_float, _f64p, _f32p, _f32p, _f32p, C.c_int, C.c_double, C.c_double,
+                                       C.c_double, C.c_double, C.c_double, _f64p, _f64p, _f64p, _f64p, _i32p]
     L.mpo_adam.argtypes = [_f64p, _f64p, _f64p, _f64p, C.c_int64, C.c_int, C.c_double, C.c_double, C.c_double,
                            C.c_double]
 
@@ -393,12 +396,34 @@ def mlp_forward(params, X, dims=(192, 128, 128), bf16=False):
     return Y
 
 
-def mlp_loss_grad(params, X, T, dims=(192, 128, 128)):
+def mlp_loss_grad(params, X, T, dims=(192, 128, 128), bf16=False):
     X = np.ascontiguousarray(X, np.float64)
     G = np.zeros(len(params))
     loss = lib().mpo_mlp_loss_grad(np.ascontiguousarray(params, np.float64), dims[0], dims[1], dims[2], X,
-                                   np.ascontiguousarray(T, np.float64), X.shape[0], _ptr(G))
+                                   np.ascontiguousarray(T, np.float64), X.shape[0], int(bf16), _ptr(G))
     return loss, G
+
+
+def likelihood_rank1(m: Map, sxyz, poses8, mode, sigma_s=0.03, dmax=1.0, cmax=9.0, params=None, lo=None,
+                     inv_ext=None, freqs=None, s_scale=1.0, g_scale=1.0, r_floor=1e-2, lam_rel=1e-3,
+                     lam_abs=1e-6):
+    """mode 1: score field scorer; mode 2: network scorer (params, lo, inv_ext, freqs)."""
+    S = _f32(sxyz).reshape(-1, 3)
+    P = _f32(poses8).reshape(-1, 8)
+    n = P.shape[0]
+    out = dict(loglik=np.zeros(n), H21=np.zeros((n, 21)), b=np.zeros((n, 6)), psi=np.zeros((n, 6)),
+               ninl=np.zeros(n, np.int32))
+    if mode == 2:
+        prm = np.ascontiguousarray(params, np.float64)
+        fr = _f32(freqs)
+        lo_, inv_ = _f32(lo), _f32(inv_ext)
+    else:
+        prm = np.zeros(1); fr = np.ones(32, np.float32); lo_ = np.zeros(3, np.float32); inv_ = np.ones(3, np.float32)
+    if n:
+        lib().mpo_likelihood_rank1(m.handle, S, S.shape[0], P, n, mode, sigma_s, dmax, cmax, prm, lo_, inv_, fr,
+                                   len(fr), s_scale, g_scale, r_floor, lam_rel, lam_abs, out["loglik"], out["H21"],
+                                   out["b"], out["psi"], out["ninl"])
+    return out
 
 
 def adam(params, grads, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):

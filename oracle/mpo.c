@@ -1209,39 +1209,43 @@ MPO_API int mpo_num_threads(void) {
 /* axis, features sin/cos(2 pi frac(f_l x~_a)) ordered (axis, frequency,   */
 /* sin|cos) -> 192 -> 128 -> 128 -> 4 with SiLU; outputs (s, grad s).       */
 /* ======================================================================= */
+/* score field at one FP32 point; returns 1 for an unsaturated inlier */
+static int sf_point(const mpo_map* m, const float q[3], float sigma_s, float dmax2, float cmax, double* s_out,
+                    double g_out[3]) {
+    double beta = 1.0 + (double)sigma_s * (double)sigma_s;
+    int32_t v[3];
+    for (int a = 0; a < 3; ++a) v[a] = floor_to_i32(q[a] * m->inv_r);
+    int32_t g = nnf_voxel(m, v);
+    *s_out = cmax;
+    g_out[0] = g_out[1] = g_out[2] = 0.0;
+    if (g < 0) return 0;
+    const float* mm = m->mu + 3 * (int64_t)g;
+    float e32[3] = {mm[0] - q[0], mm[1] - q[1], mm[2] - q[2]};
+    float d2 = fmaf(e32[0], e32[0], fmaf(e32[1], e32[1], e32[2] * e32[2]));
+    if (!(d2 <= dmax2)) return 0;
+    double e[3] = {(double)mm[0] - q[0], (double)mm[1] - q[1], (double)mm[2] - q[2]};
+    const float* nv = m->nrm + 3 * (int64_t)g;
+    double C[9], Om[9];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c)
+            C[3 * r + c] = (r == c ? beta : 0.0) - (double)m->a32 * (double)nv[r] * (double)nv[c];
+    mat3_inv(C, Om);
+    double Oe[3];
+    for (int a = 0; a < 3; ++a) Oe[a] = Om[3 * a] * e[0] + Om[3 * a + 1] * e[1] + Om[3 * a + 2] * e[2];
+    double c = e[0] * Oe[0] + e[1] * Oe[1] + e[2] * Oe[2];
+    if (!(c < cmax)) return 0;
+    *s_out = c;
+    for (int a = 0; a < 3; ++a) g_out[a] = -2.0 * Oe[a];
+    return 1;
+}
+
 MPO_API void mpo_score_field(const mpo_map* m, const float* p, int64_t n, float sigma_s, float dmax, float cmax,
                              double* s_out, double* g_out) {
     float dmax2 = dmax * dmax;
-    double beta = 1.0 + (double)sigma_s * (double)sigma_s;
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
-        const float* q = p + 3 * i;
-        int32_t v[3];
-        for (int a = 0; a < 3; ++a) v[a] = floor_to_i32(q[a] * m->inv_r);
-        int32_t g = nnf_voxel(m, v);
-        double s = cmax, gr[3] = {0, 0, 0};
-        if (g >= 0) {
-            const float* mm = m->mu + 3 * (int64_t)g;
-            float e32[3] = {mm[0] - q[0], mm[1] - q[1], mm[2] - q[2]};
-            float d2 = fmaf(e32[0], e32[0], fmaf(e32[1], e32[1], e32[2] * e32[2]));
-            if (d2 <= dmax2) {
-                double e[3] = {(double)mm[0] - q[0], (double)mm[1] - q[1], (double)mm[2] - q[2]};
-                const float* nv = m->nrm + 3 * (int64_t)g;
-                double C[9], Om[9];
-                for (int r = 0; r < 3; ++r)
-                    for (int c = 0; c < 3; ++c)
-                        C[3 * r + c] = (r == c ? beta : 0.0) - (double)m->a32 * (double)nv[r] * (double)nv[c];
-                mat3_inv(C, Om);
-                double Oe[3];
-                for (int a = 0; a < 3; ++a) Oe[a] = Om[3 * a] * e[0] + Om[3 * a + 1] * e[1] + Om[3 * a + 2] * e[2];
-                double c = e[0] * Oe[0] + e[1] * Oe[1] + e[2] * Oe[2];
-                if (c < cmax) {
-                    s = c;
-                    for (int a = 0; a < 3; ++a) gr[a] = -2.0 * Oe[a];
-                }
-            }
-        }
-        s_out[i] = s;
+        double gr[3];
+        sf_point(m, p + 3 * i, sigma_s, dmax2, cmax, &s_out[i], gr);
         if (g_out) for (int a = 0; a < 3; ++a) g_out[3 * i + a] = gr[a];
     }
 }
@@ -1263,23 +1267,25 @@ MPO_API void mpo_ff_freqs(float fmax, int nf, float* f) {
     for (int l = 0; l < nf; ++l) f[l] = (float)pow((double)fmax, nf > 1 ? (double)l / (double)(nf - 1) : 0.0);
 }
 
-MPO_API void mpo_ff_features(const float* p, int64_t n, const float lo[3], const float inv_ext[3], const float* freqs,
-                             int nf, int bf16, double* feat /* n x 6 nf */) {
+static void ff_point(const float p[3], const float lo[3], const float inv_ext[3], const float* freqs, int nf,
+                     int bf16, double* o) {
     const double tau = 6.283185307179586476925;
-    for (int64_t i = 0; i < n; ++i) {
-        for (int a = 0; a < 3; ++a) {
-            float x = (p[3 * i + a] - lo[a]) * inv_ext[a];
-            for (int l = 0; l < nf; ++l) {
-                float t = freqs[l] * x;
-                float fr = t - floorf(t);
-                double ang = tau * (double)fr;
-                double sv = sin(ang), cv = cos(ang);
-                double* o = feat + (size_t)i * 6 * nf + (size_t)(2 * (a * nf + l));
-                o[0] = bf16 ? mpo_bf16_round(sv) : sv;
-                o[1] = bf16 ? mpo_bf16_round(cv) : cv;
-            }
+    for (int a = 0; a < 3; ++a) {
+        float x = (p[a] - lo[a]) * inv_ext[a];
+        for (int l = 0; l < nf; ++l) {
+            float t = freqs[l] * x;
+            float fr = t - floorf(t);
+            double ang = tau * (double)fr;
+            double sv = sin(ang), cv = cos(ang);
+            o[2 * (a * nf + l)] = bf16 ? mpo_bf16_round(sv) : sv;
+            o[2 * (a * nf + l) + 1] = bf16 ? mpo_bf16_round(cv) : cv;
         }
     }
+}
+
+MPO_API void mpo_ff_features(const float* p, int64_t n, const float lo[3], const float inv_ext[3], const float* freqs,
+                             int nf, int bf16, double* feat /* n x 6 nf */) {
+    for (int64_t i = 0; i < n; ++i) ff_point(p + 3 * i, lo, inv_ext, freqs, nf, bf16, feat + (size_t)i * 6 * nf);
 }
 
 static double silu(double z) { return z / (1.0 + exp(-z)); }
@@ -1294,66 +1300,62 @@ MPO_API int64_t mpo_mlp_nparams(int d0, int d1, int d2) {
     return (int64_t)d0 * d1 + d1 + (int64_t)d1 * d2 + d2 + (int64_t)d2 * 4 + 4;
 }
 
-/* forward; bf16 != 0 rounds the GEMM inputs (weights and activations) to
- * bfloat16 as the GPU does, accumulating in FP64 */
-MPO_API void mpo_mlp_forward(const double* P, int d0, int d1, int d2, const double* X, int64_t n, int bf16,
-                             double* Y /* n x 4 */) {
+static double rnd(double x, int bf16) { return bf16 ? mpo_bf16_round(x) : x; }
+
+/* one sample; bf16 != 0 rounds the GEMM operands (weights and the layer
+ * inputs x, h1, h2) to bfloat16 as the GPU does, accumulating in FP64 */
+static void mlp_fwd1(const double* P, int d0, int d1, int d2, const double* x, int bf16, double* z1, double* h1,
+                     double* z2, double* h2, double y[4]) {
     const double* W1 = P;
     const double* b1 = W1 + (size_t)d0 * d1;
     const double* W2 = b1 + d1;
     const double* b2 = W2 + (size_t)d1 * d2;
     const double* W3 = b2 + d2;
     const double* b3 = W3 + (size_t)d2 * 4;
+    for (int j = 0; j < d1; ++j) {
+        double z = 0.0;
+        for (int k = 0; k < d0; ++k) z += rnd(x[k], bf16) * rnd(W1[(size_t)k * d1 + j], bf16);
+        z1[j] = z + b1[j];
+        h1[j] = rnd(silu(z1[j]), bf16);
+    }
+    for (int j = 0; j < d2; ++j) {
+        double z = 0.0;
+        for (int k = 0; k < d1; ++k) z += h1[k] * rnd(W2[(size_t)k * d2 + j], bf16);
+        z2[j] = z + b2[j];
+        h2[j] = rnd(silu(z2[j]), bf16);
+    }
+    for (int j = 0; j < 4; ++j) {
+        double z = 0.0;
+        for (int k = 0; k < d2; ++k) z += h2[k] * rnd(W3[(size_t)k * 4 + j], bf16);
+        y[j] = z + b3[j];
+    }
+}
+
+MPO_API void mpo_mlp_forward(const double* P, int d0, int d1, int d2, const double* X, int64_t n, int bf16,
+                             double* Y /* n x 4 */) {
 #pragma omp parallel
     {
-        double* h1 = (double*)malloc(sizeof(double) * (size_t)d1);
-        double* h2 = (double*)malloc(sizeof(double) * (size_t)d2);
+        double* buf = (double*)malloc(sizeof(double) * (size_t)(2 * d1 + 2 * d2));
 #pragma omp for schedule(static)
-        for (int64_t i = 0; i < n; ++i) {
-            const double* x = X + (size_t)i * d0;
-            for (int j = 0; j < d1; ++j) {
-                double z = 0.0;
-                for (int k = 0; k < d0; ++k) {
-                    double w = bf16 ? mpo_bf16_round(W1[(size_t)k * d1 + j]) : W1[(size_t)k * d1 + j];
-                    double xv = bf16 ? mpo_bf16_round(x[k]) : x[k];
-                    z += xv * w;
-                }
-                h1[j] = silu(z + b1[j]);
-                if (bf16) h1[j] = mpo_bf16_round(h1[j]);
-            }
-            for (int j = 0; j < d2; ++j) {
-                double z = 0.0;
-                for (int k = 0; k < d1; ++k) {
-                    double w = bf16 ? mpo_bf16_round(W2[(size_t)k * d2 + j]) : W2[(size_t)k * d2 + j];
-                    z += h1[k] * w;
-                }
-                h2[j] = silu(z + b2[j]);
-                if (bf16) h2[j] = mpo_bf16_round(h2[j]);
-            }
-            for (int j = 0; j < 4; ++j) {
-                double z = 0.0;
-                for (int k = 0; k < d2; ++k) {
-                    double w = bf16 ? mpo_bf16_round(W3[(size_t)k * 4 + j]) : W3[(size_t)k * 4 + j];
-                    z += h2[k] * w;
-                }
-                Y[(size_t)i * 4 + j] = z + b3[j];
-            }
-        }
-        free(h1);
-        free(h2);
+        for (int64_t i = 0; i < n; ++i)
+            mlp_fwd1(P, d0, d1, d2, X + (size_t)i * d0, bf16, buf, buf + d1, buf + 2 * d1, buf + 2 * d1 + d2,
+                     Y + (size_t)i * 4);
+        free(buf);
     }
 }
 
 /* mean squared error over the 4 outputs, L = (1/n) sum_i |y_i - t_i|^2, and
- * its gradient with respect to every parameter (FP64, no rounding) */
+ * its gradient with respect to every parameter.  bf16 != 0 follows the GPU
+ * training step: the forward of mlp_fwd1 with rounding, dL/dy and the
+ * layer-3 backward unrounded, and the hidden-layer gradients dz2, dz1
+ * rounded to bfloat16 wherever they enter a product or a bias sum. */
 MPO_API double mpo_mlp_loss_grad(const double* P, int d0, int d1, int d2, const double* X, const double* T, int64_t n,
-                                 double* G /* nparams, nullable */) {
+                                 int bf16, double* G /* nparams, nullable */) {
     const double* W1 = P;
     const double* b1 = W1 + (size_t)d0 * d1;
     const double* W2 = b1 + d1;
     const double* b2 = W2 + (size_t)d1 * d2;
     const double* W3 = b2 + d2;
-    const double* b3 = W3 + (size_t)d2 * 4;
     int64_t np = mpo_mlp_nparams(d0, d1, d2);
     if (G) memset(G, 0, sizeof(double) * (size_t)np);
     double* gW1 = G;
@@ -1371,23 +1373,10 @@ MPO_API double mpo_mlp_loss_grad(const double* P, int d0, int d1, int d2, const 
     double loss = 0.0;
     for (int64_t i = 0; i < n; ++i) {
         const double* x = X + (size_t)i * d0;
-        for (int j = 0; j < d1; ++j) {
-            double z = b1[j];
-            for (int k = 0; k < d0; ++k) z += x[k] * W1[(size_t)k * d1 + j];
-            z1[j] = z;
-            h1[j] = silu(z);
-        }
-        for (int j = 0; j < d2; ++j) {
-            double z = b2[j];
-            for (int k = 0; k < d1; ++k) z += h1[k] * W2[(size_t)k * d2 + j];
-            z2[j] = z;
-            h2[j] = silu(z);
-        }
-        double dy[4];
+        double y[4], dy[4];
+        mlp_fwd1(P, d0, d1, d2, x, bf16, z1, h1, z2, h2, y);
         for (int j = 0; j < 4; ++j) {
-            double y = b3[j];
-            for (int k = 0; k < d2; ++k) y += h2[k] * W3[(size_t)k * 4 + j];
-            double r = y - T[(size_t)i * 4 + j];
+            double r = y[j] - T[(size_t)i * 4 + j];
             loss += r * r;
             dy[j] = 2.0 * r / (double)n;
         }
@@ -1398,8 +1387,8 @@ MPO_API double mpo_mlp_loss_grad(const double* P, int d0, int d1, int d2, const 
         }
         for (int k = 0; k < d2; ++k) {
             double s = 0.0;
-            for (int j = 0; j < 4; ++j) s += W3[(size_t)k * 4 + j] * dy[j];
-            dz2[k] = s * silu_d(z2[k]);
+            for (int j = 0; j < 4; ++j) s += rnd(W3[(size_t)k * 4 + j], bf16) * dy[j];
+            dz2[k] = rnd(s * silu_d(z2[k]), bf16);
         }
         for (int j = 0; j < d2; ++j) {
             gb2[j] += dz2[j];
@@ -1407,12 +1396,12 @@ MPO_API double mpo_mlp_loss_grad(const double* P, int d0, int d1, int d2, const 
         }
         for (int k = 0; k < d1; ++k) {
             double s = 0.0;
-            for (int j = 0; j < d2; ++j) s += W2[(size_t)k * d2 + j] * dz2[j];
-            dz1[k] = s * silu_d(z1[k]);
+            for (int j = 0; j < d2; ++j) s += rnd(W2[(size_t)k * d2 + j], bf16) * dz2[j];
+            dz1[k] = rnd(s * silu_d(z1[k]), bf16);
         }
         for (int j = 0; j < d1; ++j) {
             gb1[j] += dz1[j];
-            for (int k = 0; k < d0; ++k) gW1[(size_t)k * d1 + j] += x[k] * dz1[j];
+            for (int k = 0; k < d0; ++k) gW1[(size_t)k * d1 + j] += rnd(x[k], bf16) * dz1[j];
         }
     }
     free(z1); free(h1); free(z2); free(h2); free(dz2); free(dz1);
@@ -1428,5 +1417,81 @@ MPO_API void mpo_adam(double* P, const double* G, double* Mv, double* Vv, int64_
         Vv[k] = b2 * Vv[k] + (1.0 - b2) * G[k] * G[k];
         double mh = Mv[k] / c1, vh = Vv[k] / c2;
         P[k] -= lr * mh / (sqrt(vh) + eps);
+    }
+}
+
+/* Likelihood with a scalar per-point score s(p') in place of the GICP term
+ * (rank-1 Gauss-Newton).  mode 1: the score field; mode 2: the network
+ * (features of the FP32 point, bf16-emulating forward, outputs scaled by
+ * s_scale and g_scale).  A point with s >= c_max (or outside the gate) is an
+ * outlier costing c_max.  Otherwise, in FP64 with R from the quaternion:
+ *   r = sqrt(max(s, r_floor^2)), w = R^T grad s, u = w / (2 r),
+ *   H += [mu x u; u][mu x u; u]^T, b += [mu x w; w] / 2, loglik -= s. */
+MPO_API void mpo_likelihood_rank1(const mpo_map* m, const float* sxyz, int32_t ns, const float* poses, int64_t n,
+                                  int mode, float sigma_s, float dmax, float cmax, const double* P, const float lo[3],
+                                  const float inv_ext[3], const float* freqs, int nf, double s_scale, double g_scale,
+                                  double r_floor, double lam_rel, double lam_abs, double* loglik, double* H21,
+                                  double* b6, double* psi6, int32_t* ninl) {
+    float dmax2 = dmax * dmax;
+    const int d0 = 6 * nf, d1 = 128, d2 = 128;
+#pragma omp parallel
+    {
+        double* buf = (double*)malloc(sizeof(double) * (size_t)(d0 + 2 * d1 + 2 * d2));
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t i = 0; i < n; ++i) {
+            const float* T = poses + 8 * i;
+            q32 q = {T[0], T[1], T[2], T[3]};
+            float R32[9];
+            q32_to_R(q, R32);
+            float t32[3] = {T[4], T[5], T[6]};
+            double qd[4] = {T[0], T[1], T[2], T[3]}, R[9];
+            qd_to_R(qd, R);
+            double ll = 0.0, H[36], b[6];
+            memset(H, 0, sizeof(H));
+            memset(b, 0, sizeof(b));
+            int32_t ni = 0;
+            for (int32_t k = 0; k < ns; ++k) {
+                const float* ms = sxyz + 3 * (int64_t)k;
+                float p32[3];
+                xform32(R32, t32, ms, p32);
+                double s, gr[3];
+                int inl;
+                if (mode == 1) {
+                    inl = sf_point(m, p32, sigma_s, dmax2, cmax, &s, gr);
+                } else {
+                    double* x = buf;
+                    double y[4];
+                    ff_point(p32, lo, inv_ext, freqs, nf, 1, x);
+                    mlp_fwd1(P, d0, d1, d2, x, 1, buf + d0, buf + d0 + d1, buf + d0 + 2 * d1,
+                             buf + d0 + 2 * d1 + d2, y);
+                    s = y[0] * s_scale;
+                    for (int a = 0; a < 3; ++a) gr[a] = y[1 + a] * g_scale;
+                    inl = s < (double)cmax;
+                    if (s < 0.0) s = 0.0;
+                }
+                if (!inl) { ll -= (double)cmax; continue; }
+                ++ni;
+                ll -= s;
+                double r = sqrt(s > r_floor * r_floor ? s : r_floor * r_floor);
+                double w[3], mu[3] = {ms[0], ms[1], ms[2]};
+                for (int a = 0; a < 3; ++a) w[a] = R[a] * gr[0] + R[3 + a] * gr[1] + R[6 + a] * gr[2];
+                double gw[6] = {mu[1] * w[2] - mu[2] * w[1], mu[2] * w[0] - mu[0] * w[2], mu[0] * w[1] - mu[1] * w[0],
+                                w[0], w[1], w[2]};
+                for (int r1 = 0; r1 < 6; ++r1) {
+                    b[r1] += 0.5 * gw[r1];
+                    for (int c1 = 0; c1 < 6; ++c1) H[6 * r1 + c1] += gw[r1] * gw[c1] / (4.0 * r * r);
+                }
+            }
+            double h21[21];
+            int q2 = 0;
+            for (int r1 = 0; r1 < 6; ++r1)
+                for (int c1 = r1; c1 < 6; ++c1) h21[q2++] = H[6 * r1 + c1];
+            if (loglik) loglik[i] = ll;
+            if (H21) memcpy(H21 + 21 * i, h21, sizeof(h21));
+            if (b6) memcpy(b6 + 6 * i, b, sizeof(b));
+            if (ninl) ninl[i] = ni;
+            if (psi6) mpo_gn_step(h21, b, lam_rel, lam_abs, psi6 + 6 * i);
+        }
+        free(buf);
     }
 }

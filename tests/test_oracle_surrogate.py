@@ -244,3 +244,125 @@ def test_adam_matches_torch(O):
         opt.step()
         P, m, v = O.adam(P, g, m, v, t, lr=3e-3)
     np.testing.assert_allclose(P, pt.detach().numpy(), rtol=1e-12, atol=1e-14)
+
+
+def test_mlp_bf16_gradient_close_to_exact(O):
+    """The BF16-emulating gradient rounds operands to 8 significant bits:
+    against the exact FP64 gradient its relative error stays at the level of
+    a few bfloat16 ulps (2^-8), with the loss in the forward's tolerance."""
+    dims = (192, 128, 128)
+    rng = np.random.default_rng(21)
+    n = O.mlp_nparams(*dims)
+    P = np.zeros(n)
+    o = 0
+    for fi, fo in ((192, 128), (128, 128), (128, 4)):
+        P[o:o + fi * fo] = rng.uniform(-1, 1, fi * fo) / np.sqrt(fi); o += fi * fo
+        P[o:o + fo] = rng.uniform(-0.1, 0.1, fo); o += fo
+    X = np.sin(rng.uniform(0, 6.3, (64, 192)))
+    T = rng.normal(0, 0.3, (64, 4))
+    L0, G0 = O.mlp_loss_grad(P, X, T, dims)
+    L1, G1 = O.mlp_loss_grad(P, X, T, dims, bf16=True)
+    assert abs(L1 - L0) <= 2e-2 * L0
+    rel = np.linalg.norm(G1 - G0) / np.linalg.norm(G0)
+    assert 1e-5 < rel < 2e-2, rel   # rounded, but only by bfloat16 rounding
+
+
+def _pose_exp(T8, xi):
+    from _pinutil import M_to_pose8, pose_to_M, se3_exp_ref
+    return M_to_pose8(pose_to_M(T8) @ se3_exp_ref(xi))
+
+
+def test_rank1_scorefield_b_and_H_by_differences(O, room):
+    """Score-field scorer, single-point scans: 2 b = d(-loglik)/d delta under
+    T exp(delta) (central differences), and the rank-1 H = b b^T / s."""
+    m, _ = room
+    rng = np.random.default_rng(22)
+    pts = _near_surface_points(O, m, 400, 23, spread=0.04)
+    T = np.array([0.9961947, 0.0, 0.0, 0.08715574, 0.05, -0.03, 0.02, 0.0], np.float32)   # 10 deg yaw
+    from _pinutil import pose_to_M
+    M = pose_to_M(T)
+    # scan points in the sensor frame such that R mu + t lands near the surface
+    mus = ((pts.astype(np.float64) - M[:3, 3]) @ M[:3, :3]).astype(np.float32)
+    checked = 0
+    h = 1e-4
+    for k in range(len(mus)):
+        mu = mus[k:k + 1]
+        out = O.likelihood_rank1(m, mu, T[None], 1, sigma_s=0.05, dmax=1.0, cmax=9.0)
+        if out["ninl"][0] != 1 or -out["loglik"][0] < 0.05:
+            continue
+        s = -out["loglik"][0]
+        b = out["b"][0]
+        fd = np.zeros(6)
+        stable = True
+        for a in range(6):
+            xi = np.zeros(6); xi[a] = h
+            lp = O.likelihood_rank1(m, mu, _pose_exp(T, xi)[None], 1, sigma_s=0.05, dmax=1.0, cmax=9.0)
+            lm = O.likelihood_rank1(m, mu, _pose_exp(T, -xi)[None], 1, sigma_s=0.05, dmax=1.0, cmax=9.0)
+            if lp["ninl"][0] != 1 or lm["ninl"][0] != 1:
+                stable = False
+                break
+            fd[a] = (-lp["loglik"][0] + lm["loglik"][0]) / (2 * h)
+        if not stable:
+            continue
+        # FP32 point rounding bounds the difference quotient's accuracy
+        assert np.allclose(fd, 2 * b, rtol=2e-2, atol=2e-2 * np.abs(b).max() + 1e-3), (fd, 2 * b)
+        H = np.zeros((6, 6))
+        q = 0
+        for i in range(6):
+            for j in range(i, 6):
+                H[i, j] = H[j, i] = out["H21"][0][q]; q += 1
+        np.testing.assert_allclose(H, np.outer(b, b) / max(s, 1e-4), rtol=1e-9, atol=1e-12)
+        checked += 1
+        if checked >= 40:
+            break
+    assert checked >= 20
+
+
+def test_rank1_network_constant_output_closed_form(O, room):
+    """Network scorer with W3 = 0: every point scores the bias b3, so
+    loglik = -ns s0, b = sum [mu x w; w] / 2 with w = R^T g, H = sum g g^T / (4 s0)."""
+    m, _ = room
+    dims = (192, 128, 128)
+    n = O.mlp_nparams(*dims)
+    rng = np.random.default_rng(24)
+    P = rng.normal(0, 0.2, n)
+    P[n - 4 - 512:n - 4] = 0.0                    # W3
+    s_scale, g_scale = 9.0, 100.0
+    s0, g = 2.25, np.array([0.3, -1.2, 0.5])
+    P[n - 4:] = [s0 / s_scale, *(g / g_scale)]    # b3 (exact in FP64; s0 / 9 rounds)
+    f = O.ff_freqs(40.0)
+    lo = np.array([-12, -12, -2], np.float32); inv = np.full(3, 1 / 24.0, np.float32)
+    mu = rng.uniform(-3, 3, (50, 3)).astype(np.float32)
+    T = np.array([[0.9238795, 0.0, 0.3826834, 0.0, 1.0, 2.0, 0.5, 0.0]], np.float32)
+    out = O.likelihood_rank1(m, mu, T, 2, cmax=9.0, params=P, lo=lo, inv_ext=inv, freqs=f, s_scale=s_scale,
+                             g_scale=g_scale)
+    from _pinutil import pose_to_M
+    R = pose_to_M(T[0])[:3, :3]
+    w = R.T @ g
+    mu64 = mu.astype(np.float64)
+    gw = np.concatenate([np.cross(mu64, w), np.tile(w, (50, 1))], axis=1)
+    s_eff = (s0 / s_scale) * s_scale
+    assert out["ninl"][0] == 50
+    np.testing.assert_allclose(out["loglik"][0], -50 * s_eff, rtol=1e-14)
+    np.testing.assert_allclose(out["b"][0], 0.5 * gw.sum(0), rtol=1e-12, atol=1e-12)
+    H = np.zeros((6, 6)); q = 0
+    for i in range(6):
+        for j in range(i, 6):
+            H[i, j] = H[j, i] = out["H21"][0][q]; q += 1
+    np.testing.assert_allclose(H, gw.T @ gw / (4 * s_eff), rtol=1e-12, atol=1e-12)
+
+
+def test_rank1_network_matches_forward_at_identity(O, room):
+    m, _ = room
+    dims = (192, 128, 128)
+    rng = np.random.default_rng(25)
+    P = rng.normal(0, 0.1, O.mlp_nparams(*dims))
+    f = O.ff_freqs(40.0)
+    lo = np.array([-12, -12, -2], np.float32); inv = np.full(3, 1 / 24.0, np.float32)
+    p = rng.uniform(-5, 5, (30, 3)).astype(np.float32)
+    Y = O.mlp_forward(P, O.ff_features(p, lo, inv, f, bf16=True), dims, bf16=True)
+    T = np.array([[1, 0, 0, 0, 0, 0, 0, 0]], np.float32)
+    for k in range(len(p)):
+        out = O.likelihood_rank1(m, p[k:k + 1], T, 2, cmax=1e6, params=P, lo=lo, inv_ext=inv, freqs=f,
+                                 s_scale=3.0, g_scale=1.0)
+        np.testing.assert_allclose(-out["loglik"][0], max(Y[k, 0] * 3.0, 0.0), rtol=1e-13, atol=1e-15)
