@@ -134,20 +134,35 @@ typedef struct {
     float lsh_sigma;      /* per-axis std of delta^LSH, in cells (Eq. 10) */
     float c_max;          /* per-point cost cap; outliers cost c_max */
     float d_max;          /* inlier gate on |mu^M - T mu^S|, metres */
-    float lambda_rel;     /* GN damping lambda = lambda_rel tr(H)/6 + lambda_abs */
+    float lambda_rel;     /* Marquardt damping of the GN step: H + diag(lambda_rel H_ii + lambda_abs) */
     float lambda_abs;
     float temperature;    /* log-likelihood divisor in the posterior */
     float prior_floor;    /* prior probabilities below this are raised to it */
     float cov_eps;        /* GICP epsilon for scan covariances */
     int32_t lik_chunks;   /* scan-point chunks per particle tile in the likelihood launch; 0 = auto */
-    int32_t lik_batch;    /* scan points whose NNF cells are requested together per lane: 4, 8, 16 (0 = 16) or 32 */
+    int32_t lik_batch;    /* scan points whose NNF cells are requested together per lane: 1..32 (power of 2), 0 = 4 */
+    int32_t scorer;       /* MP_SCORER_*: per-point term of the likelihood */
+    float sigma_s;        /* MP_SCORER_SCOREFIELD: isotropic sensor std of the score field, metres */
     uint64_t seed;        /* Philox4x32-10 key */
 } mp_filter_params;
+
+/* Per-point term of the likelihood.
+ *   PLAIN       the GICP cost of Eq. (3) with full Gauss-Newton H, b (Eq. 4).
+ *   SCOREFIELD  the score field s(p') = min(e^T (Sigma^M + sigma_s^2 I)^-1 e, c_max)
+ *               of the transformed point (scan covariances unused), entering
+ *               Gauss-Newton as the scalar residual r = sqrt(s):
+ *                 H += (J^T grad r)(J^T grad r)^T,  b += J^T grad s / 2,
+ *               J = dp'/d delta, grad r = grad s / (2 max(r, 1e-2)).
+ *   SURROGATE   the same with s and grad s predicted by a trained network
+ *               (mp_surrogate_*), attached by mp_filter_set_surrogate.
+ * A point with s >= c_max (or outside the NNF gate) is an outlier costing c_max. */
+enum { MP_SCORER_PLAIN = 0, MP_SCORER_SCOREFIELD = 1, MP_SCORER_SURROGATE = 2 };
 
 /* Defaults: k 16, lsh_bits 20, svgd_iters 10, post_iters 10, window_c 32,
  * scan_k 10, sigma_r 5, sigma_t 2.5, lsh_alpha 1, lsh_sigma 0.3, c_max 9,
  * d_max 1.0, lambda_rel 1e-3, lambda_abs 1e-6, temperature 1,
- * prior_floor 1e-30, cov_eps 1e-3, lik_chunks 0, seed 1. */
+ * prior_floor 1e-30, cov_eps 1e-3, lik_chunks 0, lik_batch 4, scorer PLAIN,
+ * sigma_s 0.03, seed 1. */
 MP_API void mp_filter_default_params(mp_filter_params* p);
 
 enum { MP_INIT_UNIFORM_BOX = 0, MP_INIT_EXPLICIT = 1 };
@@ -261,6 +276,133 @@ MP_API mp_status mp_debug_get(mp_filter f, const char* name, void* dst, int64_t 
 MP_API mp_status mp_debug_set(mp_filter f, const char* name, const void* src, int64_t bytes, void* stream);
 MP_API mp_status mp_debug_stage(mp_filter f, int32_t stage, int32_t iteration, const float dT[7], const float cov_dT[36],
                          void* stream);
+
+/* ------------------------------------------------------------ batch */
+/* Several independent filters (instances: different maps, particle counts,
+ * scans and parameters) stepped by one call.  The first step captures every
+ * instance's whole filter step (prediction, correction iterations, posterior;
+ * exactly the launches of mp_filter_step) into one HIP graph, each instance on
+ * its own branch, and every call replays it: per-step values (frame counter,
+ * odometry increment, noise factor) are uploaded to device memory before the
+ * replay, so the graph itself never changes.  A new capture happens when an
+ * instance's scan size or buffers changed (mp_scan_upload with another n).
+ * Results equal those of mp_filter_step on each instance, bit for bit.
+ * The filters stay usable alone; they cannot be destroyed while in a batch. */
+typedef struct mp_batch_s* mp_batch;
+
+typedef struct {
+    int32_t n_instances;
+    int32_t captures;        /* graphs captured so far */
+    int64_t evals_per_step;  /* particle-point evaluations of one batch step */
+} mp_batch_info;
+
+/* autotune != 0 times the likelihood launch of each instance for lik_batch in
+ * {2, 4, 8, 16} and keeps the fastest (it changes only how gathers are grouped,
+ * not the arithmetic).  Every filter needs a scan uploaded.  Errors: MP_E_ARG,
+ * MP_E_STATE (no scan, a filter given twice, SURROGATE scorer without a network). */
+MP_API mp_status mp_batch_create(const mp_filter* filters, int32_t n, int32_t autotune, void* stream, mp_batch* out);
+
+/* One step of every instance.  dT: n x 7 (NULL: no prediction for any
+ * instance); cov_dT: n x 36 (NULL: no noise); as in mp_filter_step.  Host
+ * arrays.  Asynchronous except for waiting until the previous call's step
+ * values have been copied. */
+MP_API mp_status mp_batch_step(mp_batch b, const float* dT, const float* cov_dT, void* stream);
+
+/* lik_batch_out (nullable): n chosen lik_batch values. */
+MP_API mp_status mp_batch_get_info(mp_batch b, mp_batch_info* out, int32_t* lik_batch_out);
+
+MP_API mp_status mp_batch_destroy(mp_batch b);
+
+/* ------------------------------------------------------------ surrogate */
+/* A learned replacement of the map's per-point score (the score field of
+ * MP_SCORER_SCOREFIELD) by a small network evaluated on the matrix cores:
+ *   x = (p - box_min) / L, L = the box's largest extent;
+ *   features sin, cos(2 pi frac(f_l x_a)), f_l = f_max^(l/31), l = 0..31,
+ *   per axis a, ordered (axis, frequency, sin|cos): 192 inputs;
+ *   192 -> 128 -> 128 -> 4, SiLU after the two hidden layers;
+ *   outputs (s / s_scale, grad s / g_scale), s_scale = c_max,
+ *   g_scale = 2 sqrt(c_max / (eps + sigma_s^2)) (the largest unsaturated
+ *   gradient).
+ * Products take bfloat16 operands with FP32 accumulation; weights are kept
+ * in FP32 (master) with bfloat16 copies; training is Adam on the mean squared
+ * error of the 4 scaled outputs against score-field labels. */
+typedef struct mp_surrogate_s* mp_surrogate;
+
+#define MP_SUR_NPARAMS 41732       /* 192*128 + 128 + 128*128 + 128 + 128*4 + 4 */
+#define MP_SUR_IMAGE_BYTES 84112   /* inference weights as held in LDS */
+
+typedef struct {
+    float box_min[3], box_max[3];  /* feature box; box_min == box_max: the map's voxel box */
+    float f_max;          /* highest frequency, cycles per L; 0: L / voxel */
+    float sigma_s;        /* score-field sensor std, metres */
+    float d_max, c_max;   /* inlier gate (0: two voxels) and saturation of the labels */
+    float lr, lr_min;     /* Adam step, cosine-decayed from lr to lr_min over total_steps */
+    float beta1, beta2, adam_eps;
+    int32_t total_steps;  /* length of the cosine schedule */
+    int32_t batch;        /* samples per Adam step, 256 .. 2^20 */
+    uint64_t seed;        /* Philox key of the initial weights and the batch draws */
+} mp_surrogate_params;
+
+typedef struct {
+    int64_t n_params;       /* 41732 */
+    int64_t n_data;         /* training samples held */
+    int64_t steps;          /* Adam steps taken */
+    float lo[3], inv_ext[3];/* feature normalisation x = (p - lo) * inv_ext (FP32) */
+    float freqs[32];        /* f_l, cycles per normalised unit (FP32) */
+    float s_scale, g_scale; /* output scales */
+    int32_t weight_bytes;   /* bytes of the inference image held in LDS per workgroup */
+} mp_surrogate_info;
+
+/* Defaults: box from the map, f_max 0, sigma_s 0.03, d_max 0, c_max 9,
+ * lr 1e-3, lr_min 1e-5, betas 0.9 / 0.999, eps 1e-8, total_steps 20000,
+ * batch 65536, seed 1. */
+MP_API void mp_surrogate_default_params(mp_surrogate_params* p);
+
+/* Create a network for `map` (which must outlive it).  Weights are drawn
+ * uniform in +-1/sqrt(fan_in) from Philox(seed), biases zero.  Errors:
+ * MP_E_ARG (bad params), MP_E_OOM. */
+MP_API mp_status mp_surrogate_create(mp_map map, const mp_surrogate_params* params, void* stream, mp_surrogate* out);
+
+/* MP_E_STATE while a filter still uses the network. */
+MP_API mp_status mp_surrogate_destroy(mp_surrogate sur);
+
+MP_API mp_status mp_surrogate_get_info(mp_surrogate sur, mp_surrogate_info* out);
+
+/* Exact score-field labels of n points: out4 = (s, grad s) per point, n x 4
+ * float, physical units (the training targets before scaling). */
+MP_API mp_status mp_surrogate_label(mp_surrogate sur, const float* xyz, int64_t n, float* out4, void* stream);
+
+/* Network prediction of n points: out4 = (s, grad s), n x 4 float, physical
+ * units, unclamped. */
+MP_API mp_status mp_surrogate_eval(mp_surrogate sur, const float* xyz, int64_t n, float* out4, void* stream);
+
+/* Replace the training set by n points (n x 3); labels are computed on the
+ * device.  n >= 1. */
+MP_API mp_status mp_surrogate_set_data(mp_surrogate sur, const float* xyz, int64_t n, void* stream);
+
+/* Take `steps` Adam steps.  Each batch is `batch` samples drawn uniformly
+ * with replacement from the training set by Philox(seed; step); when the set
+ * holds no more than `batch` samples every step uses the whole set.
+ * loss_out (host, nullable) receives each step's loss and makes the call
+ * synchronous.  Errors: MP_E_STATE without training data. */
+MP_API mp_status mp_surrogate_train(mp_surrogate sur, int32_t steps, float* loss_out, void* stream);
+
+/* Loss and gradient of the current weights over n given samples with given
+ * targets (n x 4, physical units), without an update.  grad_out: n_params
+ * float (host or device) in the parameter layout below; loss_out: host float.
+ * n <= batch. */
+MP_API mp_status mp_surrogate_grad(mp_surrogate sur, const float* xyz, const float* target4, int64_t n,
+                                   float* grad_out, float* loss_out, void* stream);
+
+/* FP32 weights in the layout W1[192][128], b1[128], W2[128][128], b2[128],
+ * W3[128][4], b3[4] (input-major matrices).  Setting them clears the Adam
+ * moments and the step count. */
+MP_API mp_status mp_surrogate_get_params(mp_surrogate sur, float* params, void* stream);
+MP_API mp_status mp_surrogate_set_params(mp_surrogate sur, const float* params, void* stream);
+
+/* Attach (or detach with NULL) the network the filter's SURROGATE scorer
+ * uses; the network must outlive the attachment. */
+MP_API mp_status mp_filter_set_surrogate(mp_filter f, mp_surrogate sur);
 
 #ifdef __cplusplus
 }

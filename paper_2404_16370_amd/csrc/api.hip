@@ -8,6 +8,7 @@
 #include <numeric>
 #include <cstdio>
 #include <cstring>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -41,6 +42,11 @@ static mp_status guarded(const char* where, F&& fn) {
 }
 
 extern "C" const char* mp_last_error(void) { return g_err.c_str(); }
+
+// error handling of the other translation units' entry points
+mp_status mp_guarded_call(const char* where, void (*fn)(void*), void* ctx) {
+    return guarded(where, [&]() { fn(ctx); });
+}
 
 // ------------------------------------------------------------ device memory
 void DevMem::alloc(size_t b) {
@@ -234,6 +240,9 @@ extern "C" void mp_filter_default_params(mp_filter_params* p) {
     p->prior_floor = 1e-30f;
     p->cov_eps = 1e-3f;
     p->lik_chunks = 0;
+    p->lik_batch = 0;
+    p->scorer = MP_SCORER_PLAIN;
+    p->sigma_s = 0.03f;
     p->seed = 1;
 }
 
@@ -252,8 +261,11 @@ static void validate_params(const mp_filter_params& p) {
         p.cov_eps > 1)
         mp_throw(MP_E_ARG, "parameter out of range");
     if (p.lik_chunks < 0) mp_throw(MP_E_ARG, "lik_chunks must be >= 0");
-    if (p.lik_batch != 0 && p.lik_batch != 4 && p.lik_batch != 8 && p.lik_batch != 16 && p.lik_batch != 32)
-        mp_throw(MP_E_ARG, "lik_batch must be 0, 4, 8, 16 or 32");
+    if (p.lik_batch != 0 && p.lik_batch != 1 && p.lik_batch != 2 && p.lik_batch != 4 && p.lik_batch != 8 &&
+        p.lik_batch != 16 && p.lik_batch != 32)
+        mp_throw(MP_E_ARG, "lik_batch must be 0, 1, 2, 4, 8, 16 or 32");
+    if (p.scorer < MP_SCORER_PLAIN || p.scorer > MP_SCORER_SURROGATE) mp_throw(MP_E_ARG, "unknown scorer");
+    if (!std::isfinite(p.sigma_s) || !(p.sigma_s > 0.0f)) mp_throw(MP_E_ARG, "sigma_s must be positive");
 }
 
 static void destroy_filter(mp_filter f) {
@@ -263,6 +275,7 @@ static void destroy_filter(mp_filter f) {
         for (hipEvent_t e : f->ev1[st]) (void)hipEventDestroy(e);
     }
     if (f->map) f->map->users--;
+    if (f->sur) f->sur->users--;
     delete f;
 }
 
@@ -353,6 +366,7 @@ extern "C" mp_status mp_filter_init(mp_map map, const mp_filter_params* params, 
 extern "C" mp_status mp_filter_destroy(mp_filter f) {
     return guarded("mp_filter_destroy", [&]() {
         if (!f) return;
+        if (f->batch_users > 0) mp_throw(MP_E_STATE, "filter still held by %d batch(es)", f->batch_users);
         MP_HIP(hipDeviceSynchronize());
         destroy_filter(f);
     });
@@ -433,6 +447,7 @@ extern "C" mp_status mp_scan_upload(mp_filter f, const float* xyz, const float* 
 }
 
 void mp_tick(mp_filter f, int st, bool begin, hipStream_t s) {
+    if (f->capturing) return;
     const int k = f->ev_count[st];
     auto& v = begin ? f->ev0[st] : f->ev1[st];
     while ((int)v.size() <= k) {
@@ -465,7 +480,7 @@ static bool chol6_host(const double A[36], double L[36]) {
     return true;
 }
 
-static void prepare_prediction(const float dT[7], const float cov[36], float dq[7], float Lf[36], bool& noise) {
+void mp_prepare_prediction(const float dT[7], const float cov[36], float dq[7], float Lf[36], bool& noise) {
     if (!all_finite(dT, 7)) mp_throw(MP_E_ARG, "non-finite dT");
     const double nq = std::sqrt((double)dT[0] * dT[0] + (double)dT[1] * dT[1] + (double)dT[2] * dT[2] +
                                 (double)dT[3] * dT[3]);
@@ -502,38 +517,54 @@ static void run_stage(mp_filter f, int st, int it, hipStream_t s) {
     }
 }
 
+void mp_reserve_step(mp_filter f) {
+    f->partial.ensure(mp_lik_partial_bytes(f));
+    f->red.ensure(std::max(mp_post_scratch_bytes(f), sizeof(uint32_t) * ((size_t)f->n + 64)));
+    f->hist.ensure(mp_radix_scratch_bytes(f->n));
+}
+
+void mp_step_launches(mp_filter f, bool pred, const float dq[7], const float L[36], bool noise, hipStream_t s) {
+    mp_fill_u32(f->flags.p, 0u, 4, s);
+    // a captured step always holds the prediction node; it reads whether to
+    // predict from the step values
+    if (pred || f->dyn) {
+        static const float ident[7] = {1, 0, 0, 0, 0, 0, 0};
+        static const float zero[36] = {};
+        mp_tick(f, MP_STAGE_PREDICT, true, s);
+        mp_launch_predict(f, pred ? dq : ident, pred ? L : zero, pred && noise, s);
+        mp_tick(f, MP_STAGE_PREDICT, false, s);
+    }
+    if (f->scan_n > 0) {
+        // per iteration, in the order of Table II: neighbour list update
+        // (LSH, sort, refresh), likelihood evaluation, particle state update
+        for (int it = 0; it < f->p.svgd_iters; ++it) {
+            for (int st : {MP_STAGE_LSH, MP_STAGE_SORT, MP_STAGE_REFRESH, MP_STAGE_LIK, MP_STAGE_SVGD}) {
+                mp_tick(f, st, true, s);
+                run_stage(f, st, it, s);
+                mp_tick(f, st, false, s);
+            }
+        }
+        if (f->p.svgd_iters > 0) {
+            mp_tick(f, MP_STAGE_POSTERIOR, true, s);
+            mp_launch_posterior(f, s);
+            mp_tick(f, MP_STAGE_POSTERIOR, false, s);
+        }
+    }
+}
+
 extern "C" mp_status mp_filter_step(mp_filter f, const float dT[7], const float cov_dT[36], void* stream) {
     return guarded("mp_filter_step", [&]() {
         if (!f) mp_throw(MP_E_ARG, "null filter");
         if (f->scan_n < 0) mp_throw(MP_E_STATE, "mp_filter_step before the first mp_scan_upload");
+        if (f->p.scorer == MP_SCORER_SURROGATE && !f->sur)
+            mp_throw(MP_E_STATE, "SURROGATE scorer without a network (mp_filter_set_surrogate)");
         hipStream_t s = as_stream(stream);
         float dq[7], L[36];
         bool noise = false;
-        if (dT) prepare_prediction(dT, cov_dT, dq, L, noise);
+        if (dT) mp_prepare_prediction(dT, cov_dT, dq, L, noise);
         for (int st = 0; st < MP_NUM_STAGES; ++st)
             if (st != MP_STAGE_SCAN) f->ev_count[st] = 0;
-        MP_HIP(hipMemsetAsync(f->flags.p, 0, 16, s));
-        if (dT) {
-            mp_tick(f, MP_STAGE_PREDICT, true, s);
-            mp_launch_predict(f, dq, L, noise, s);
-            mp_tick(f, MP_STAGE_PREDICT, false, s);
-        }
-        if (f->scan_n > 0) {
-            // per iteration, in the order of Table II: neighbour list update
-            // (LSH, sort, refresh), likelihood evaluation, particle state update
-            for (int it = 0; it < f->p.svgd_iters; ++it) {
-                for (int st : {MP_STAGE_LSH, MP_STAGE_SORT, MP_STAGE_REFRESH, MP_STAGE_LIK, MP_STAGE_SVGD}) {
-                    mp_tick(f, st, true, s);
-                    run_stage(f, st, it, s);
-                    mp_tick(f, st, false, s);
-                }
-            }
-            if (f->p.svgd_iters > 0) {
-                mp_tick(f, MP_STAGE_POSTERIOR, true, s);
-                mp_launch_posterior(f, s);
-                mp_tick(f, MP_STAGE_POSTERIOR, false, s);
-            }
-        }
+        mp_step_launches(f, dT != nullptr, dq, L, noise, s);
         f->frame++;
         f->last_stream = s;
     });
@@ -678,7 +709,7 @@ extern "C" mp_status mp_debug_stage(mp_filter f, int32_t stage, int32_t iteratio
             if (!dT) mp_throw(MP_E_ARG, "prediction needs dT");
             float dq[7], L[36];
             bool noise = false;
-            prepare_prediction(dT, cov_dT, dq, L, noise);
+            mp_prepare_prediction(dT, cov_dT, dq, L, noise);
             mp_launch_predict(f, dq, L, noise, s);
         } else {
             if ((stage == MP_STAGE_LIK) && f->scan_n < 0) mp_throw(MP_E_STATE, "no scan uploaded");
@@ -686,5 +717,243 @@ extern "C" mp_status mp_debug_stage(mp_filter f, int32_t stage, int32_t iteratio
             run_stage(f, stage, iteration, s);
         }
         MP_HIP(hipStreamSynchronize(s));
+    });
+}
+
+// ------------------------------------------------------------ surrogate
+extern "C" void mp_surrogate_default_params(mp_surrogate_params* p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->f_max = 0.0f;
+    p->sigma_s = 0.03f;
+    p->d_max = 0.0f;
+    p->c_max = 9.0f;
+    p->lr = 1e-3f;
+    p->lr_min = 1e-5f;
+    p->beta1 = 0.9f;
+    p->beta2 = 0.999f;
+    p->adam_eps = 1e-8f;
+    p->total_steps = 20000;
+    p->batch = 65536;
+    p->seed = 1;
+}
+
+extern "C" mp_status mp_surrogate_create(mp_map map, const mp_surrogate_params* params, void* stream,
+                                         mp_surrogate* out) {
+    return guarded("mp_surrogate_create", [&]() {
+        if (!map || !params || !out) mp_throw(MP_E_ARG, "null argument");
+        mp_surrogate_params p = *params;
+        const float fs[] = {p.box_min[0], p.box_min[1], p.box_min[2], p.box_max[0], p.box_max[1], p.box_max[2],
+                            p.f_max, p.sigma_s, p.d_max, p.c_max, p.lr, p.lr_min, p.beta1, p.beta2, p.adam_eps};
+        for (float v : fs)
+            if (!std::isfinite(v)) mp_throw(MP_E_ARG, "non-finite parameter");
+        if (!(p.sigma_s > 0) || p.d_max < 0 || !(p.c_max > 0) || p.f_max < 0 || !(p.lr > 0) || p.lr_min < 0 ||
+            !(p.beta1 >= 0 && p.beta1 < 1) || !(p.beta2 >= 0 && p.beta2 < 1) || !(p.adam_eps > 0) ||
+            p.total_steps < 1 || p.batch < 256 || p.batch > (1 << 20))
+            mp_throw(MP_E_ARG, "parameter out of range");
+        const float r = map->params.voxel;
+        if (p.d_max == 0.0f) p.d_max = 2.0f * r;
+        bool box_given = false;
+        for (int a = 0; a < 3; ++a) box_given = box_given || p.box_min[a] != p.box_max[a];
+        if (!box_given) {
+            if (map->info.num_gauss <= 0) mp_throw(MP_E_ARG, "empty map and no feature box");
+            for (int a = 0; a < 3; ++a) {
+                p.box_min[a] = map->info.box_min[a];
+                p.box_max[a] = map->info.box_max[a];
+            }
+        }
+        double ext = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            if (!(p.box_max[a] > p.box_min[a])) mp_throw(MP_E_ARG, "empty feature box");
+            ext = std::max(ext, (double)p.box_max[a] - (double)p.box_min[a]);
+        }
+        if (p.f_max == 0.0f) p.f_max = (float)(ext / (double)r);
+        if (!(p.f_max >= 1.0f)) mp_throw(MP_E_ARG, "f_max below one cycle per box");
+        auto S = std::make_unique<mp_surrogate_s>();
+        S->map = map;
+        S->p = p;
+        mp_surrogate_info& I = S->info;
+        std::memset(&I, 0, sizeof(I));
+        I.n_params = MP_SUR_NPARAMS;
+        for (int a = 0; a < 3; ++a) {
+            I.lo[a] = p.box_min[a];
+            I.inv_ext[a] = (float)(1.0 / ext);
+        }
+        for (int l = 0; l < 32; ++l) I.freqs[l] = (float)std::pow((double)p.f_max, (double)l / 31.0);
+        const double eps = map->params.cov_eps, s2 = (double)p.sigma_s * (double)p.sigma_s;
+        I.s_scale = p.c_max;
+        I.g_scale = (float)(2.0 * std::sqrt((double)p.c_max / (eps + s2)));
+        I.weight_bytes = MP_SUR_IMAGE_BYTES;
+        hipStream_t s = as_stream(stream);
+        mp_sur_alloc(S.get(), s);
+        mp_sur_init_weights(S.get(), s);
+        MP_HIP(hipStreamSynchronize(s));
+        map->users++;
+        *out = S.release();
+    });
+}
+
+extern "C" mp_status mp_surrogate_destroy(mp_surrogate sur) {
+    return guarded("mp_surrogate_destroy", [&]() {
+        if (!sur) return;
+        if (sur->users > 0) mp_throw(MP_E_STATE, "network still used by %d filter(s)", sur->users);
+        MP_HIP(hipDeviceSynchronize());
+        if (sur->map) sur->map->users--;
+        delete sur;
+    });
+}
+
+extern "C" mp_status mp_surrogate_get_info(mp_surrogate sur, mp_surrogate_info* out) {
+    return guarded("mp_surrogate_get_info", [&]() {
+        if (!sur || !out) mp_throw(MP_E_ARG, "null argument");
+        *out = sur->info;
+    });
+}
+
+static void check_points(const float* xyz, int64_t n) {
+    if (n < 0 || (n > 0 && !xyz)) mp_throw(MP_E_ARG, "bad point array");
+    if (n > ((int64_t)1 << 31)) mp_throw(MP_E_ARG, "too many points");
+}
+
+extern "C" mp_status mp_surrogate_label(mp_surrogate sur, const float* xyz, int64_t n, float* out4, void* stream) {
+    return guarded("mp_surrogate_label", [&]() {
+        if (!sur) mp_throw(MP_E_ARG, "null surrogate");
+        check_points(xyz, n);
+        if (n > 0 && !out4) mp_throw(MP_E_ARG, "null output");
+        if (n == 0) return;
+        hipStream_t s = as_stream(stream);
+        DevMem tin, tout;
+        const float* d = static_cast<const float*>(stage_in(xyz, sizeof(float) * 3 * (size_t)n, tin, s));
+        const bool dev_out = is_device_ptr(out4);
+        float* o = out4;
+        if (!dev_out) {
+            tout.alloc(sizeof(float) * 4 * (size_t)n);
+            o = tout.as<float>();
+        }
+        mp_sur_label(sur, d, n, o, false, s);
+        if (!dev_out) copy_out(out4, o, sizeof(float) * 4 * (size_t)n, s);
+        MP_HIP(hipStreamSynchronize(s));
+    });
+}
+
+extern "C" mp_status mp_surrogate_eval(mp_surrogate sur, const float* xyz, int64_t n, float* out4, void* stream) {
+    return guarded("mp_surrogate_eval", [&]() {
+        if (!sur) mp_throw(MP_E_ARG, "null surrogate");
+        check_points(xyz, n);
+        if (n > 0 && !out4) mp_throw(MP_E_ARG, "null output");
+        if (n == 0) return;
+        hipStream_t s = as_stream(stream);
+        DevMem tin, tout;
+        const float* d = static_cast<const float*>(stage_in(xyz, sizeof(float) * 3 * (size_t)n, tin, s));
+        const bool dev_out = is_device_ptr(out4);
+        float* o = out4;
+        if (!dev_out) {
+            tout.alloc(sizeof(float) * 4 * (size_t)n);
+            o = tout.as<float>();
+        }
+        mp_sur_eval(sur, d, n, o, s);
+        if (!dev_out) copy_out(out4, o, sizeof(float) * 4 * (size_t)n, s);
+        MP_HIP(hipStreamSynchronize(s));
+    });
+}
+
+extern "C" mp_status mp_surrogate_set_data(mp_surrogate sur, const float* xyz, int64_t n, void* stream) {
+    return guarded("mp_surrogate_set_data", [&]() {
+        if (!sur) mp_throw(MP_E_ARG, "null surrogate");
+        check_points(xyz, n);
+        if (n < 1) mp_throw(MP_E_ARG, "training set must hold at least one point");
+        hipStream_t s = as_stream(stream);
+        sur->dxyz.alloc(sizeof(float) * 3 * (size_t)n);
+        sur->dlab.alloc(sizeof(float) * 4 * (size_t)n);
+        MP_HIP(hipMemcpyAsync(sur->dxyz.p, xyz, sizeof(float) * 3 * (size_t)n, hipMemcpyDefault, s));
+        mp_sur_label(sur, sur->dxyz.as<float>(), n, sur->dlab.as<float>(), true, s);
+        sur->info.n_data = n;
+        MP_HIP(hipStreamSynchronize(s));
+    });
+}
+
+extern "C" mp_status mp_surrogate_train(mp_surrogate sur, int32_t steps, float* loss_out, void* stream) {
+    return guarded("mp_surrogate_train", [&]() {
+        if (!sur) mp_throw(MP_E_ARG, "null surrogate");
+        if (steps < 0) mp_throw(MP_E_ARG, "negative step count");
+        if (sur->info.n_data < 1) mp_throw(MP_E_STATE, "no training data (mp_surrogate_set_data)");
+        if (steps == 0) return;
+        hipStream_t s = as_stream(stream);
+        const bool full = sur->info.n_data <= sur->p.batch;
+        const int32_t n_real = full ? (int32_t)sur->info.n_data : sur->p.batch;
+        mp_sur_ensure_batch(sur, n_real);
+        sur->losses.ensure(sizeof(float) * (size_t)steps);
+        const mp_surrogate_params& p = sur->p;
+        for (int32_t k = 0; k < steps; ++k) {
+            const int64_t t = sur->info.steps;   // steps taken before this one
+            const double frac = std::min(1.0, (double)t / (double)p.total_steps);
+            const double lr = p.lr_min + 0.5 * ((double)p.lr - p.lr_min) * (1.0 + std::cos(M_PI * frac));
+            mp_sur_draw_batch(sur, n_real, full, (uint32_t)t, s);
+            mp_sur_grad_step(sur, n_real, true, (float)lr, sur->losses.as<float>() + k, s);
+        }
+        if (loss_out) {
+            MP_HIP(hipMemcpyAsync(loss_out, sur->losses.p, sizeof(float) * (size_t)steps, hipMemcpyDeviceToHost, s));
+            MP_HIP(hipStreamSynchronize(s));
+        }
+    });
+}
+
+extern "C" mp_status mp_surrogate_grad(mp_surrogate sur, const float* xyz, const float* target4, int64_t n,
+                                       float* grad_out, float* loss_out, void* stream) {
+    return guarded("mp_surrogate_grad", [&]() {
+        if (!sur || !xyz || !target4) mp_throw(MP_E_ARG, "null argument");
+        if (n < 1 || n > sur->p.batch) mp_throw(MP_E_ARG, "n must be 1..batch");
+        hipStream_t s = as_stream(stream);
+        mp_sur_ensure_batch(sur, n);
+        std::vector<float> tgt(4 * (size_t)n);
+        fetch_host(target4, sizeof(float) * 4 * (size_t)n, tgt.data(), s);
+        const float is = 1.0f / sur->info.s_scale, ig = 1.0f / sur->info.g_scale;
+        for (int64_t i = 0; i < n; ++i) {
+            tgt[4 * i] *= is;
+            for (int a = 1; a < 4; ++a) tgt[4 * i + a] *= ig;
+        }
+        const int32_t bp = sur->cap;
+        MP_HIP(hipMemsetAsync(sur->bxyz.p, 0, sizeof(float) * 3 * (size_t)bp, s));
+        MP_HIP(hipMemsetAsync(sur->btgt.p, 0, sizeof(float) * 4 * (size_t)bp, s));
+        MP_HIP(hipMemcpyAsync(sur->bxyz.p, xyz, sizeof(float) * 3 * (size_t)n, hipMemcpyDefault, s));
+        MP_HIP(hipMemcpyAsync(sur->btgt.p, tgt.data(), sizeof(float) * 4 * (size_t)n, hipMemcpyHostToDevice, s));
+        sur->losses.ensure(sizeof(float));
+        mp_sur_grad_step(sur, (int32_t)n, false, 0.0f, sur->losses.as<float>(), s);
+        if (grad_out) copy_out(grad_out, sur->G.p, sizeof(float) * MP_SUR_NPARAMS, s);
+        if (loss_out) MP_HIP(hipMemcpyAsync(loss_out, sur->losses.p, sizeof(float), hipMemcpyDeviceToHost, s));
+        MP_HIP(hipStreamSynchronize(s));
+    });
+}
+
+extern "C" mp_status mp_surrogate_get_params(mp_surrogate sur, float* params, void* stream) {
+    return guarded("mp_surrogate_get_params", [&]() {
+        if (!sur || !params) mp_throw(MP_E_ARG, "null argument");
+        hipStream_t s = as_stream(stream);
+        copy_out(params, sur->P.p, sizeof(float) * MP_SUR_NPARAMS, s);
+        MP_HIP(hipStreamSynchronize(s));
+    });
+}
+
+extern "C" mp_status mp_surrogate_set_params(mp_surrogate sur, const float* params, void* stream) {
+    return guarded("mp_surrogate_set_params", [&]() {
+        if (!sur || !params) mp_throw(MP_E_ARG, "null argument");
+        hipStream_t s = as_stream(stream);
+        std::vector<float> h(MP_SUR_NPARAMS);
+        fetch_host(params, sizeof(float) * MP_SUR_NPARAMS, h.data(), s);
+        if (!all_finite(h.data(), h.size())) mp_throw(MP_E_ARG, "non-finite weights");
+        MP_HIP(hipMemcpyAsync(sur->P.p, h.data(), sizeof(float) * MP_SUR_NPARAMS, hipMemcpyHostToDevice, s));
+        mp_sur_reset_adam(sur, s);
+        mp_sur_publish(sur, s);
+        MP_HIP(hipStreamSynchronize(s));
+    });
+}
+
+extern "C" mp_status mp_filter_set_surrogate(mp_filter f, mp_surrogate sur) {
+    return guarded("mp_filter_set_surrogate", [&]() {
+        if (!f) mp_throw(MP_E_ARG, "null filter");
+        if (sur && sur->map != f->map) mp_throw(MP_E_ARG, "network built for another map");
+        if (f->sur) f->sur->users--;
+        f->sur = sur;
+        if (sur) sur->users++;
     });
 }

@@ -1,0 +1,320 @@
+// batch.hip -- several filter instances stepped by one HIP graph replay.
+//
+// Capture: every instance's step is recorded on its own stream, forked from
+// and joined back into the capturing stream, so the graph holds one branch per
+// instance.  The kernels of a captured step read the step counter, odometry
+// increment and noise factor from a device block (StepDyn per instance) that
+// the host refreshes before each replay; every buffer a step touches is sized
+// before capture, and the step holds no host synchronisation, allocation or
+// memset, so the same graph serves every later step.  Pose buffers ping-pong
+// once per SVGD iteration: a captured step with an odd iteration count copies
+// the result back to the buffer it started from.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "megapf.h"
+#include "mp_internal.hpp"
+
+struct mp_batch_s {
+    std::vector<mp_filter> f;
+    hipStream_t cap = nullptr;          // capture stream (the caller's may be the null stream)
+    std::vector<hipStream_t> branch;
+    std::vector<hipEvent_t> join;
+    hipEvent_t fork = nullptr, uploaded = nullptr;
+    bool upload_pending = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    StepDyn* host_dyn = nullptr;   // pinned
+    DevMem dyn;
+    // what each instance looked like when the graph was captured
+    struct Shape {
+        const void* scan;
+        int32_t scan_n, cur;
+        const void* partial;
+        const void* red;
+        const void* hist;
+        mp_surrogate sur;
+        int32_t lik_batch;
+        bool operator!=(const Shape& o) const { return std::memcmp(this, &o, sizeof(Shape)) != 0; }
+    };
+    std::vector<Shape> shape;
+    int32_t captures = 0;
+};
+
+namespace {
+
+void release(mp_batch b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    for (hipStream_t s : b->branch) (void)hipStreamDestroy(s);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    for (hipEvent_t e : b->join) (void)hipEventDestroy(e);
+    if (b->fork) (void)hipEventDestroy(b->fork);
+    if (b->uploaded) (void)hipEventDestroy(b->uploaded);
+    if (b->host_dyn) (void)hipHostFree(b->host_dyn);
+    for (mp_filter f : b->f) f->batch_users--;
+    delete b;
+}
+
+mp_batch_s::Shape shape_of(mp_filter f) {
+    mp_batch_s::Shape s;
+    std::memset(&s, 0, sizeof(s));
+    s.scan = f->scan.p;
+    s.scan_n = f->scan_n;
+    s.cur = f->cur;
+    s.partial = f->partial.p;
+    s.red = f->red.p;
+    s.hist = f->hist.p;
+    s.sur = f->sur;
+    s.lik_batch = f->p.lik_batch;
+    return s;
+}
+
+void check_ready(mp_filter f) {
+    if (f->scan_n < 0) mp_throw(MP_E_STATE, "every instance needs a scan (mp_scan_upload)");
+    if (f->p.scorer == MP_SCORER_SURROGATE && !f->sur)
+        mp_throw(MP_E_STATE, "SURROGATE scorer without a network (mp_filter_set_surrogate)");
+}
+
+void capture(mp_batch b, hipStream_t caller) {
+    for (mp_filter f : b->f) mp_reserve_step(f);
+    // buffers just sized may still be in use by queued work of the caller
+    MP_HIP(hipStreamSynchronize(caller));
+    hipStream_t s = b->cap;
+    if (b->exec) {
+        MP_HIP(hipGraphExecDestroy(b->exec));
+        b->exec = nullptr;
+    }
+    if (b->graph) {
+        MP_HIP(hipGraphDestroy(b->graph));
+        b->graph = nullptr;
+    }
+    b->shape.clear();
+    MP_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    try {
+        MP_HIP(hipEventRecord(b->fork, s));
+        for (size_t i = 0; i < b->f.size(); ++i) {
+            mp_filter f = b->f[i];
+            hipStream_t bs = b->branch[i];
+            MP_HIP(hipStreamWaitEvent(bs, b->fork, 0));
+            const int start = f->cur;
+            b->shape.push_back(shape_of(f));
+            f->capturing = true;
+            f->dyn = b->dyn.as<StepDyn>() + i;
+            mp_step_launches(f, false, nullptr, nullptr, false, bs);
+            if (f->cur != start) {
+                mp_copy_poses(f, f->cur, start, bs);
+                f->cur = start;
+            }
+            f->capturing = false;
+            f->dyn = nullptr;
+            MP_HIP(hipEventRecord(b->join[i], bs));
+            MP_HIP(hipStreamWaitEvent(s, b->join[i], 0));
+        }
+    } catch (...) {
+        for (mp_filter f : b->f) {
+            f->capturing = false;
+            f->dyn = nullptr;
+        }
+        hipGraph_t g = nullptr;
+        (void)hipStreamEndCapture(s, &g);
+        if (g) (void)hipGraphDestroy(g);
+        b->shape.clear();
+        throw;
+    }
+    MP_HIP(hipStreamEndCapture(s, &b->graph));
+    MP_HIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    b->captures++;
+}
+
+void autotune(mp_filter f, hipStream_t s) {
+    if (f->scan_n <= 0 || f->p.scorer != MP_SCORER_PLAIN) return;
+    hipEvent_t e0, e1;
+    MP_HIP(hipEventCreate(&e0));
+    MP_HIP(hipEventCreate(&e1));
+    const int32_t keep = f->p.lik_batch;
+    int32_t best = keep;
+    float best_ms = 1e30f;
+    try {
+        for (int32_t c : {2, 4, 8, 16}) {
+            f->p.lik_batch = c;
+            mp_launch_likelihood(f, s);   // warm-up
+            MP_HIP(hipEventRecord(e0, s));
+            mp_launch_likelihood(f, s);
+            mp_launch_likelihood(f, s);
+            MP_HIP(hipEventRecord(e1, s));
+            MP_HIP(hipEventSynchronize(e1));
+            float ms = 0.0f;
+            MP_HIP(hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = c;
+            }
+        }
+    } catch (...) {
+        f->p.lik_batch = keep;
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        throw;
+    }
+    f->p.lik_batch = best;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+}
+
+}  // namespace
+
+extern "C" mp_status mp_batch_create(const mp_filter* filters, int32_t n, int32_t tune, void* stream,
+                                     mp_batch* out);
+extern "C" mp_status mp_batch_step(mp_batch b, const float* dT, const float* cov_dT, void* stream);
+extern "C" mp_status mp_batch_get_info(mp_batch b, mp_batch_info* out, int32_t* lik_batch_out);
+extern "C" mp_status mp_batch_destroy(mp_batch b);
+
+mp_status mp_guarded_call(const char* where, void (*fn)(void*), void* ctx);
+
+namespace {
+struct CreateCtx {
+    const mp_filter* filters;
+    int32_t n, tune;
+    hipStream_t s;
+    mp_batch* out;
+};
+void create_impl(void* p) {
+    CreateCtx& c = *static_cast<CreateCtx*>(p);
+    if (!c.filters || !c.out || c.n < 1) mp_throw(MP_E_ARG, "need at least one filter");
+    for (int32_t i = 0; i < c.n; ++i) {
+        if (!c.filters[i]) mp_throw(MP_E_ARG, "null filter");
+        check_ready(c.filters[i]);
+        for (int32_t j = 0; j < i; ++j)
+            if (c.filters[j] == c.filters[i]) mp_throw(MP_E_STATE, "a filter appears twice in the batch");
+    }
+    mp_batch b = new mp_batch_s();
+    try {
+        for (int32_t i = 0; i < c.n; ++i) {
+            b->f.push_back(c.filters[i]);
+            c.filters[i]->batch_users++;
+            hipStream_t st;
+            MP_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+            b->branch.push_back(st);
+            hipEvent_t e;
+            MP_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+            b->join.push_back(e);
+        }
+        MP_HIP(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+        MP_HIP(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming));
+        MP_HIP(hipEventCreateWithFlags(&b->uploaded, hipEventDisableTiming));
+        MP_HIP(hipHostMalloc(reinterpret_cast<void**>(&b->host_dyn), sizeof(StepDyn) * (size_t)c.n,
+                             hipHostMallocDefault));
+        b->dyn.alloc(sizeof(StepDyn) * (size_t)c.n);
+        if (c.tune)
+            for (mp_filter f : b->f) autotune(f, c.s);
+        MP_HIP(hipStreamSynchronize(c.s));
+    } catch (...) {
+        release(b);
+        throw;
+    }
+    *c.out = b;
+}
+
+struct StepCtx {
+    mp_batch b;
+    const float* dT;
+    const float* cov;
+    hipStream_t s;
+};
+void step_impl(void* p) {
+    StepCtx& c = *static_cast<StepCtx*>(p);
+    mp_batch b = c.b;
+    if (!b) mp_throw(MP_E_ARG, "null batch");
+    const size_t n = b->f.size();
+    for (mp_filter f : b->f) check_ready(f);
+    // step values of every instance (validated before anything is launched)
+    std::vector<StepDyn> d(n);
+    for (size_t i = 0; i < n; ++i) {
+        mp_filter f = b->f[i];
+        std::memset(&d[i], 0, sizeof(StepDyn));
+        d[i].frame = (uint32_t)f->frame;
+        d[i].dq[0] = 1.0f;
+        if (c.dT) {
+            float dq[7], L[36];
+            bool noise = false;
+            mp_prepare_prediction(c.dT + 7 * i, c.cov ? c.cov + 36 * i : nullptr, dq, L, noise);
+            d[i].do_pred = 1;
+            d[i].noise = noise ? 1 : 0;
+            for (int k = 0; k < 4; ++k) d[i].dq[k] = dq[k];
+            for (int k = 0; k < 3; ++k) d[i].dt[k] = dq[4 + k];
+            int q = 0;
+            for (int r = 0; r < 6; ++r)
+                for (int cc = 0; cc <= r; ++cc) d[i].L[q++] = noise ? L[6 * r + cc] : 0.0f;
+        }
+    }
+    bool recapture = !b->exec || b->shape.size() != n;
+    for (size_t i = 0; i < n && !recapture; ++i) {
+        mp_reserve_step(b->f[i]);
+        recapture = shape_of(b->f[i]) != b->shape[i];
+    }
+    if (recapture) capture(b, c.s);
+    // the pinned block may still be read by the previous call's copy
+    if (b->upload_pending) MP_HIP(hipEventSynchronize(b->uploaded));
+    std::memcpy(b->host_dyn, d.data(), sizeof(StepDyn) * n);
+    MP_HIP(hipMemcpyAsync(b->dyn.p, b->host_dyn, sizeof(StepDyn) * n, hipMemcpyHostToDevice, c.s));
+    MP_HIP(hipEventRecord(b->uploaded, c.s));
+    b->upload_pending = true;
+    MP_HIP(hipGraphLaunch(b->exec, c.s));
+    for (size_t i = 0; i < n; ++i) {
+        mp_filter f = b->f[i];
+        for (int st = 0; st < MP_NUM_STAGES; ++st)
+            if (st != MP_STAGE_SCAN) f->ev_count[st] = 0;
+        f->frame++;
+        f->last_stream = c.s;
+    }
+}
+}  // namespace
+
+extern "C" mp_status mp_batch_create(const mp_filter* filters, int32_t n, int32_t tune, void* stream,
+                                     mp_batch* out) {
+    CreateCtx c{filters, n, tune, static_cast<hipStream_t>(stream), out};
+    return mp_guarded_call("mp_batch_create", create_impl, &c);
+}
+
+extern "C" mp_status mp_batch_step(mp_batch b, const float* dT, const float* cov_dT, void* stream) {
+    StepCtx c{b, dT, cov_dT, static_cast<hipStream_t>(stream)};
+    return mp_guarded_call("mp_batch_step", step_impl, &c);
+}
+
+namespace {
+struct InfoCtx {
+    mp_batch b;
+    mp_batch_info* out;
+    int32_t* lb;
+};
+void info_impl(void* p) {
+    InfoCtx& c = *static_cast<InfoCtx*>(p);
+    if (!c.b || !c.out) mp_throw(MP_E_ARG, "null argument");
+    c.out->n_instances = (int32_t)c.b->f.size();
+    c.out->captures = c.b->captures;
+    int64_t ev = 0;
+    for (size_t i = 0; i < c.b->f.size(); ++i) {
+        mp_filter f = c.b->f[i];
+        ev += (int64_t)f->n * std::max(0, f->scan_n) * f->p.svgd_iters;
+        if (c.lb) c.lb[i] = f->p.lik_batch;
+    }
+    c.out->evals_per_step = ev;
+}
+void destroy_impl(void* p) {
+    mp_batch b = static_cast<mp_batch>(p);
+    if (!b) return;
+    MP_HIP(hipDeviceSynchronize());
+    release(b);
+}
+}  // namespace
+
+extern "C" mp_status mp_batch_get_info(mp_batch b, mp_batch_info* out, int32_t* lik_batch_out) {
+    InfoCtx c{b, out, lik_batch_out};
+    return mp_guarded_call("mp_batch_get_info", info_impl, &c);
+}
+
+extern "C" mp_status mp_batch_destroy(mp_batch b) { return mp_guarded_call("mp_batch_destroy", destroy_impl, b); }

@@ -126,11 +126,20 @@ struct PredArgs {
     float dq[4], dt[3];
     float L[21];  // lower-triangular Cholesky factor of the noise covariance, row-major packed
     int32_t noise;
+    const StepDyn* __restrict__ dyn;  // captured step: frame, increment and noise from here
 };
 
 __global__ __launch_bounds__(256) void k_predict(PredArgs A) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= A.n) return;
+    if (A.dyn) {
+        if (!A.dyn->do_pred) return;
+        A.frame = A.dyn->frame;
+        A.noise = A.dyn->noise;
+        for (int k = 0; k < 4; ++k) A.dq[k] = A.dyn->dq[k];
+        for (int k = 0; k < 3; ++k) A.dt[k] = A.dyn->dt[k];
+        for (int k = 0; k < 21; ++k) A.L[k] = A.dyn->L[k];
+    }
     mpdet::quat q;
     float3 t;
     load_pose(A.poses, i, q, t);
@@ -401,6 +410,7 @@ void mp_launch_predict(mp_filter f, const float dT[7], const float L[36], bool n
     for (int r = 0; r < 6; ++r)
         for (int c = 0; c <= r; ++c) A.L[p++] = noise ? L[6 * r + c] : 0.0f;
     A.noise = noise ? 1 : 0;
+    A.dyn = f->dyn;
     k_predict<<<nblk(f->n), 256, 0, s>>>(A);
     MP_CHECK_LAUNCH();
 }
@@ -418,11 +428,38 @@ void mp_launch_init_uniform(mp_filter f, const float lo[3], const float hi[3], h
     MP_CHECK_LAUNCH();
 }
 
+size_t mp_post_scratch_bytes(mp_filter f) {
+    // l (n doubles), partials (3 nb doubles), index partials (nb ints)
+    const int nb = (int)nblk(f->n, kRB);
+    return sizeof(double) * ((size_t)f->n + 3 * (size_t)nb) + sizeof(int) * (size_t)nb + 64;
+}
+
+__global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t v, size_t n) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+void mp_fill_u32(void* p, uint32_t v, size_t n, hipStream_t s) {
+    if (n == 0) return;
+    k_fill_u32<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(static_cast<uint32_t*>(p), v, n);
+    MP_CHECK_LAUNCH();
+}
+
+__global__ void k_copy_f4(const float4* __restrict__ src, float4* __restrict__ dst, size_t n) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
+void mp_copy_poses(mp_filter f, int from, int to, hipStream_t s) {
+    const size_t n = 2 * (size_t)f->n;
+    k_copy_f4<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(f->poses[from].as<float4>(), f->poses[to].as<float4>(), n);
+    MP_CHECK_LAUNCH();
+}
+
 void mp_launch_posterior(mp_filter f, hipStream_t s) {
     const int n = f->n;
     const int nb = (int)nblk(n, kRB);
-    // scratch: l (n doubles), partials (3 nb doubles), index partials (nb ints)
-    f->red.ensure(sizeof(double) * ((size_t)n + 3 * (size_t)nb) + sizeof(int) * (size_t)nb + 64);
+    f->red.ensure(mp_post_scratch_bytes(f));
     PostArgs A;
     A.prior = f->prior.as<float>();
     A.psi = f->psi.as<float4>();

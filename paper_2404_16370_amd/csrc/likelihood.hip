@@ -47,6 +47,7 @@ struct LikArgs {
     float* __restrict__ partial;        // [chunk][29][N]
     int32_t n, ns, chunk_len, nchunks, nbx;
     float dmax2, cmax;
+    float sig2, ib, r_floor2;   // score-field scorer: sigma_s^2, 1 / (1 + sigma_s^2), floor of r^2
 };
 
 __device__ inline int remap_xcd(int bid, int nb) {
@@ -139,12 +140,67 @@ __device__ __forceinline__ void accumulate(Acc& S, const mpdet::mat3& Rm, const 
     S.h[18] += o11; S.h[19] += o12; S.h[20] += o22;
 }
 
+// Score-field scorer (rank-1 Gauss-Newton on r = sqrt(s)):
+//   s = e^T Omega e, Omega = I / beta + kappa n n^T (beta = 1 + sigma_s^2,
+//   kappa = a / (beta (lam_n + sigma_s^2)), lam_n = 1 - a |n|^2 from the record),
+//   grad s = -2 Omega e (map frame), w = R^T grad s, u = w / (2 max(r, r_floor)),
+//   H += [mu x u; u][mu x u; u]^T, b += [mu x w; w] / 2.
+// A point outside the gate or with s >= c_max counts as an outlier.
+__device__ __forceinline__ void accumulate_sf(Acc& S, const mpdet::mat3& Rm, const float a, const float dmax2,
+                                              const float cmax, const float sig2, const float ib,
+                                              const float r_floor2, const float4 r0, const float3 p, const int32_t g,
+                                              const float4 gm, const float4 gn) {
+    const float3 mu = make_float3(r0.x, r0.y, r0.z);
+    float ex = gm.x - p.x, ey = gm.y - p.y, ez = gm.z - p.z;
+    const float d2 = __builtin_fmaf(ex, ex, __builtin_fmaf(ey, ey, ez * ez));
+    const bool gate = (g >= 0) && (d2 <= dmax2);
+    ex = gate ? ex : 0.0f;
+    ey = gate ? ey : 0.0f;
+    ez = gate ? ez : 0.0f;
+    const float kap = a / ((1.0f + sig2) * (gn.w + sig2));
+    const float ne = __builtin_fmaf(gn.x, ex, __builtin_fmaf(gn.y, ey, gn.z * ez));
+    const float ee = __builtin_fmaf(ex, ex, __builtin_fmaf(ey, ey, ez * ez));
+    const float c = __builtin_fmaf(kap * ne, ne, ee * ib);
+    const bool inl = gate && c < cmax;
+    const float kn = kap * ne;
+    const float gx = -2.0f * __builtin_fmaf(kn, gn.x, ex * ib);
+    const float gy = -2.0f * __builtin_fmaf(kn, gn.y, ey * ib);
+    const float gz = -2.0f * __builtin_fmaf(kn, gn.z, ez * ib);
+    const float3 w = mpdet::rot_t(Rm, make_float3(gx, gy, gz));
+    const float ir = inl ? 0.5f * __builtin_amdgcn_rsqf(fmaxf(c, r_floor2)) : 0.0f;
+    const float hw = inl ? 0.5f : 0.0f;
+    const float ux = w.x * ir, uy = w.y * ir, uz = w.z * ir;
+    const float g6[6] = {mu.y * uz - mu.z * uy, mu.z * ux - mu.x * uz, mu.x * uy - mu.y * ux, ux, uy, uz};
+    int q = 0;
+#pragma unroll
+    for (int r = 0; r < 6; ++r)
+#pragma unroll
+        for (int cc = r; cc < 6; ++cc) {
+            S.h[q] = __builtin_fmaf(g6[r], g6[cc], S.h[q]);
+            ++q;
+        }
+    // b_w is kept in bw*, b_v in -oe* (the solve's partial layout stores -oe)
+    S.bw0 = __builtin_fmaf(hw, mu.y * w.z - mu.z * w.y, S.bw0);
+    S.bw1 = __builtin_fmaf(hw, mu.z * w.x - mu.x * w.z, S.bw1);
+    S.bw2 = __builtin_fmaf(hw, mu.x * w.y - mu.y * w.x, S.bw2);
+    S.oe0 = __builtin_fmaf(-hw, w.x, S.oe0);
+    S.oe1 = __builtin_fmaf(-hw, w.y, S.oe1);
+    S.oe2 = __builtin_fmaf(-hw, w.z, S.oe2);
+    {
+        const float y = (inl ? c : 0.0f) - S.comp;
+        const float tt = S.cost + y;
+        S.comp = (tt - S.cost) - y;
+        S.cost = tt;
+    }
+    S.nout += inl ? 0.0f : 1.0f;
+}
+
 // Scan points are walked in batches of BATCH per lane: first the NNF cells of
 // the whole batch are requested back to back (BATCH independent gathers in
 // flight), then the batch is evaluated with each Gaussian record fetched two
 // points ahead.  The transform is recomputed in the second pass (same
 // operations, same result) instead of being kept in registers.
-template <int BACKEND, int BATCH>
+template <int BACKEND, int BATCH, int SC = MP_SCORER_PLAIN>
 __global__ __launch_bounds__(kLanes) void k_lik(LikArgs A) {
     __shared__ float4 tile[kTile * 3];
     const int nb = A.nbx * A.nchunks;
@@ -215,7 +271,10 @@ __global__ __launch_bounds__(kLanes) void k_lik(LikArgs A) {
                 if (b < nbat) {
                     const float4 r0 = tile[3 * (kb + b)], r1 = tile[3 * (kb + b) + 1], r2 = tile[3 * (kb + b) + 2];
                     const float3 p = mpdet::xform(Rm.m, t, make_float3(r0.x, r0.y, r0.z));
-                    accumulate(S, Rm, a, A.dmax2, A.cmax, r0, r1, r2, p, g[b], gm[b], gn[b]);
+                    if (SC == MP_SCORER_SCOREFIELD)
+                        accumulate_sf(S, Rm, a, A.dmax2, A.cmax, A.sig2, A.ib, A.r_floor2, r0, p, g[b], gm[b], gn[b]);
+                    else
+                        accumulate(S, Rm, a, A.dmax2, A.cmax, r0, r1, r2, p, g[b], gm[b], gn[b]);
                 }
             }
         }
@@ -238,10 +297,13 @@ __global__ __launch_bounds__(kLanes) void k_lik(LikArgs A) {
 template <int BACKEND>
 void launch_lik_batch(int batch, unsigned grid, hipStream_t s, const LikArgs& A) {
     switch (batch) {
+        case 1: k_lik<BACKEND, 1><<<grid, kLanes, 0, s>>>(A); break;
+        case 2: k_lik<BACKEND, 2><<<grid, kLanes, 0, s>>>(A); break;
         case 4: k_lik<BACKEND, 4><<<grid, kLanes, 0, s>>>(A); break;
         case 8: k_lik<BACKEND, 8><<<grid, kLanes, 0, s>>>(A); break;
         case 32: k_lik<BACKEND, 32><<<grid, kLanes, 0, s>>>(A); break;
-        default: k_lik<BACKEND, 16><<<grid, kLanes, 0, s>>>(A); break;
+        case 16: k_lik<BACKEND, 16><<<grid, kLanes, 0, s>>>(A); break;
+        default: k_lik<BACKEND, 4><<<grid, kLanes, 0, s>>>(A); break;
     }
 }
 
@@ -352,9 +414,10 @@ __global__ __launch_bounds__(256) void k_solve(SolveArgs A) {
 
 }  // namespace
 
-void mp_launch_likelihood(mp_filter f, hipStream_t s) {
+// scan-point chunks per particle tile and the chunk length
+static int lik_chunks(mp_filter f, int& clen) {
     const int n = f->n;
-    const int ns = f->scan_n;
+    const int ns = std::max(0, f->scan_n);
     const int nbx = (n + kLanes - 1) / kLanes;
     int nch = f->p.lik_chunks;
     if (nch <= 0) {
@@ -362,11 +425,25 @@ void mp_launch_likelihood(mp_filter f, hipStream_t s) {
         nch = std::max(1, std::min((2048 + nbx - 1) / nbx, (ns + kTile - 1) / kTile));
     }
     nch = std::max(1, std::min(nch, std::max(1, ns)));
-    int clen = (ns + nch - 1) / nch;
-    nch = std::max(1, (ns + clen - 1) / std::max(1, clen));
+    clen = (ns + nch - 1) / nch;
+    return std::max(1, (ns + clen - 1) / std::max(1, clen));
+}
+
+size_t mp_lik_partial_bytes(mp_filter f) {
+    int clen = 0;
+    const int nch = lik_chunks(f, clen);
+    return sizeof(float) * (size_t)kNumPartial * (size_t)nch * (size_t)f->n;
+}
+
+void mp_launch_likelihood(mp_filter f, hipStream_t s) {
+    const int n = f->n;
+    const int ns = f->scan_n;
+    const int nbx = (n + kLanes - 1) / kLanes;
+    int clen = 0;
+    int nch = lik_chunks(f, clen);
     f->lik_chunks = nch;
     f->lik_chunk_len = clen;
-    f->partial.ensure(sizeof(float) * (size_t)kNumPartial * (size_t)nch * (size_t)n);
+    f->partial.ensure(mp_lik_partial_bytes(f));
     LikArgs A;
     A.map = f->map->view;
     A.poses = f->poses[f->cur].as<float4>();
@@ -380,14 +457,34 @@ void mp_launch_likelihood(mp_filter f, hipStream_t s) {
     A.nbx = nbx;
     A.dmax2 = f->p.d_max * f->p.d_max;
     A.cmax = f->p.c_max;
-    if (ns > 0) {
+    A.sig2 = f->p.sigma_s * f->p.sigma_s;
+    A.ib = 1.0f / (1.0f + A.sig2);
+    A.r_floor2 = 1e-4f;
+    if (f->p.scorer == MP_SCORER_SURROGATE && !f->sur)
+        mp_throw(MP_E_STATE, "SURROGATE scorer without a network (mp_filter_set_surrogate)");
+    if (ns > 0 && f->p.scorer == MP_SCORER_SURROGATE) {
+        nch = 1;
+        f->lik_chunks = 1;
+        f->lik_chunk_len = ns;
+        mp_tick(f, MP_STAGE_LIK_CORE, true, s);
+        mp_sur_likelihood(f, A.partial, s);
+        mp_tick(f, MP_STAGE_LIK_CORE, false, s);
+    } else if (ns > 0 && f->p.scorer == MP_SCORER_SCOREFIELD) {
+        mp_tick(f, MP_STAGE_LIK_CORE, true, s);
+        if (A.map.backend == MP_NNF_DENSE)
+            k_lik<MP_NNF_DENSE, 4, MP_SCORER_SCOREFIELD><<<nbx * nch, kLanes, 0, s>>>(A);
+        else
+            k_lik<MP_NNF_HASH, 4, MP_SCORER_SCOREFIELD><<<nbx * nch, kLanes, 0, s>>>(A);
+        MP_CHECK_LAUNCH();
+        mp_tick(f, MP_STAGE_LIK_CORE, false, s);
+    } else if (ns > 0) {
         mp_tick(f, MP_STAGE_LIK_CORE, true, s);
         if (A.map.backend == MP_NNF_DENSE) launch_lik_batch<MP_NNF_DENSE>(f->p.lik_batch, nbx * nch, s, A);
         else launch_lik_batch<MP_NNF_HASH>(f->p.lik_batch, nbx * nch, s, A);
         MP_CHECK_LAUNCH();
         mp_tick(f, MP_STAGE_LIK_CORE, false, s);
     } else {
-        MP_HIP(hipMemsetAsync(A.partial, 0, sizeof(float) * (size_t)kNumPartial * n, s));
+        mp_fill_u32(A.partial, 0u, (size_t)kNumPartial * n, s);
         nch = 1;
     }
     SolveArgs S;

@@ -148,8 +148,8 @@ __device__ void jacobi_min_vec(double A[9], double nrm[3]) {
 
 __global__ void k_voxel_stats(const float* __restrict__ xyz, const int32_t* __restrict__ order,
                               const int32_t* __restrict__ start, int64_t nruns, int64_t n, int32_t min_pts,
-                              const int3* __restrict__ vox, float4* __restrict__ st_mu, float4* __restrict__ st_n,
-                              int3* __restrict__ st_vox, uint32_t* __restrict__ keep) {
+                              const int3* __restrict__ vox, float gicp_a, float4* __restrict__ st_mu,
+                              float4* __restrict__ st_n, int3* __restrict__ st_vox, uint32_t* __restrict__ keep) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= nruns) return;
     const int64_t s = start[j];
@@ -183,7 +183,11 @@ __global__ void k_voxel_stats(const float* __restrict__ xyz, const int32_t* __re
     double nv[3];
     jacobi_min_vec(A, nv);
     st_mu[j] = make_float4((float)mu[0], (float)mu[1], (float)mu[2], (float)cnt);
-    st_n[j] = make_float4((float)nv[0], (float)nv[1], (float)nv[2], 0.0f);
+    // the record also carries lam_n = 1 - a |n|^2 of the stored FP32 normal (FP64, then rounded): the
+    // eigenvalue of Sigma^M along n, which FP32 arithmetic cannot form without cancellation
+    const float n0 = (float)nv[0], n1 = (float)nv[1], n2 = (float)nv[2];
+    const double nn = (double)n0 * (double)n0 + (double)n1 * (double)n1 + (double)n2 * (double)n2;
+    st_n[j] = make_float4(n0, n1, n2, (float)(1.0 - (double)gicp_a * nn));
     st_vox[j] = vox[order[s]];
 }
 
@@ -413,8 +417,8 @@ void mp_build_map(mp_map m, const float* xyz, int64_t n, hipStream_t s) {
     keep.alloc(sizeof(uint32_t) * nruns);
     gid.alloc(sizeof(uint32_t) * nruns);
     k_voxel_stats<<<nblk(nruns, 64), 64, 0, s>>>(xyz, d_vals.as<int32_t>(), d_start.as<int32_t>(), nruns, n,
-                                                  P.min_points, d_vox.as<int3>(), st_mu.as<float4>(), st_n.as<float4>(),
-                                                  st_vox.as<int3>(), keep.as<uint32_t>());
+                                                  P.min_points, d_vox.as<int3>(), 1.0f - P.cov_eps, st_mu.as<float4>(),
+                                                  st_n.as<float4>(), st_vox.as<int3>(), keep.as<uint32_t>());
     MP_CHECK_LAUNCH();
     mp_scan_exclusive_u32(keep.as<uint32_t>(), gid.as<uint32_t>(), nruns, d_total.as<uint32_t>(), scratch, s);
     uint32_t G = 0;

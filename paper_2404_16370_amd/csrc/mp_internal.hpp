@@ -68,7 +68,35 @@ struct mp_map_s {
     int users = 0;
 };
 
+// ------------------------------------------------------------ surrogate
+struct mp_surrogate_s {
+    mp_map map = nullptr;
+    mp_surrogate_params p{};
+    mp_surrogate_info info{};
+    DevMem P, Mo, Vo, G;            // FP32 weights, Adam moments, last gradient
+    DevMem img;                     // inference image (bf16 fragments, FP32 biases and frequencies)
+    DevMem w1t, w2t, w2n, w3b;      // bf16 copies for the training products
+    DevMem dxyz, dlab;              // training set: points, scaled labels (float4)
+    int32_t cap = 0;                // padded batch rows the work buffers hold
+    DevMem bxyz, btgt, X, XT, Z1, H1, H1T, Z2, H2, dY, sse, dZ2, dZ2T, dZ1T;
+    DevMem pw1, pw2, pl3;           // split-K and chunk partial sums
+    DevMem losses;                  // per-step loss (float)
+    int users = 0;
+};
+
 // ------------------------------------------------------------ filter
+// Values that change from one filter step to the next.  Kernels captured in a
+// graph read them from device memory, written before each replay; eager
+// launches pass them as kernel arguments instead.
+struct StepDyn {
+    uint32_t frame;      // filter step index: prediction and LSH counters
+    int32_t do_pred;     // 0: this step has no prediction
+    int32_t noise;       // prediction noise on
+    int32_t pad;
+    float dq[4], dt[4];  // odometry increment (quaternion w, x, y, z; translation)
+    float L[24];         // packed lower-triangular noise factor (21 used)
+};
+
 struct FilterParamsDev {
     int32_t n, k, bits, window_c;
     float sigma_r, sigma_t, lsh_alpha, lsh_sigma, c_max, d_max, lambda_rel, lambda_abs;
@@ -77,6 +105,10 @@ struct FilterParamsDev {
 
 struct mp_filter_s {
     mp_map map = nullptr;
+    mp_surrogate sur = nullptr;   // network of the SURROGATE scorer
+    const StepDyn* dyn = nullptr; // set while a step is captured into a graph
+    bool capturing = false;       // no timers, no host work that a graph cannot hold
+    int batch_users = 0;          // batches holding this filter
     mp_filter_params p{};
     hipStream_t last_stream = nullptr;
     int32_t n = 0, K = 0;
@@ -142,3 +174,26 @@ void mp_launch_likelihood(mp_filter f, hipStream_t s);
 void mp_launch_svgd(mp_filter f, hipStream_t s);
 void mp_launch_posterior(mp_filter f, hipStream_t s);
 void mp_launch_reset_lists(mp_filter f, hipStream_t s);
+// device fill (graph-safe replacement of hipMemsetAsync)
+void mp_fill_u32(void* p, uint32_t v, size_t n, hipStream_t s);
+void mp_copy_poses(mp_filter f, int from, int to, hipStream_t s);
+// size every buffer a step needs, so that a captured step allocates nothing
+void mp_reserve_step(mp_filter f);
+size_t mp_lik_partial_bytes(mp_filter f);
+size_t mp_post_scratch_bytes(mp_filter f);
+// the whole step on stream s (eager: dT/L as arguments; captured: from f->dyn)
+// validate an odometry increment and factor its covariance (host)
+void mp_prepare_prediction(const float dT[7], const float cov[36], float dq[7], float Lf[36], bool& noise);
+void mp_step_launches(mp_filter f, bool pred, const float dq[7], const float L[36], bool noise, hipStream_t s);
+
+// surrogate (surrogate.hip)
+void mp_sur_alloc(mp_surrogate S, hipStream_t s);
+void mp_sur_init_weights(mp_surrogate S, hipStream_t s);
+void mp_sur_reset_adam(mp_surrogate S, hipStream_t s);
+void mp_sur_publish(mp_surrogate S, hipStream_t s);
+void mp_sur_label(mp_surrogate S, const float* xyz_dev, int64_t n, float* out4_dev, bool scaled, hipStream_t s);
+void mp_sur_eval(mp_surrogate S, const float* xyz_dev, int64_t n, float* out4_dev, hipStream_t s);
+void mp_sur_ensure_batch(mp_surrogate S, int64_t cap);
+void mp_sur_draw_batch(mp_surrogate S, int32_t n_real, bool full, uint32_t step, hipStream_t s);
+void mp_sur_grad_step(mp_surrogate S, int32_t n_real, bool update, float lr, float* loss_dev, hipStream_t s);
+void mp_sur_likelihood(mp_filter f, float* partial, hipStream_t s);

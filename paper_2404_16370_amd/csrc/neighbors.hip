@@ -32,10 +32,12 @@ struct LshArgs {
     float ar, at, sl;
     float lo[3], hi[3];
     uint64_t seed;
+    const StepDyn* __restrict__ dyn;   // captured step: frame from here
 };
 
 __global__ __launch_bounds__(256) void k_lsh(LshArgs A) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (A.dyn) A.frame = A.dyn->frame;
     mpdet::quat qL;
     float3 tL;
     mpdet::random_pose(A.seed, 0u, A.frame, A.it, mpdet::PURPOSE_TLSH, A.lo, A.hi, qL, tL);
@@ -225,6 +227,7 @@ void mp_launch_lsh(mp_filter f, uint32_t frame, uint32_t it, hipStream_t s) {
         A.hi[a] = f->lsh_hi[a];
     }
     A.seed = f->p.seed;
+    A.dyn = f->dyn;
     k_lsh<<<nblk(f->n), 256, 0, s>>>(A);
     MP_CHECK_LAUNCH();
 }

@@ -100,7 +100,7 @@ size_t scan_scratch_words(int64_t n) {
 
 void scan_rec(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total, uint32_t* scratch, hipStream_t s) {
     if (n <= 0) {
-        if (total) MP_HIP(hipMemsetAsync(total, 0, 4, s));
+        if (total) mp_fill_u32(total, 0u, 1, s);
         return;
     }
     if (n <= kTile) {

@@ -1,0 +1,1026 @@
+// surrogate.hip -- learned surrogate of the per-point score, its training
+// step, and the scorer that evaluates it inside the likelihood.
+//
+// Target (score field): with e = mu_g - p for the NNF Gaussian g of p,
+//   s(p) = e^T (Sigma^M_g + sigma_s^2 I)^-1 e  for an inlier below c_max,
+//   grad s = -2 Omega e;  s = c_max, grad s = 0 otherwise.
+// Sigma^M = I - a n n^T, so with beta = 1 + sigma_s^2 and lam_n = 1 - a|n|^2
+// (kept per Gaussian in the normal record):
+//   Omega = I / beta + kappa n n^T,  kappa = a / (beta (lam_n + sigma_s^2)).
+//
+// Network: x = (p - lo) * inv_ext; features sin / cos(2 pi frac(f_l x_a)),
+// 32 geometric frequencies per axis, ordered (axis, frequency, sin|cos);
+// 192 -> 128 -> 128 -> 4 with SiLU; outputs (s / s_scale, grad s / g_scale).
+// Products run on the matrix cores (v_mfma_f32_32x32x16_bf16: bfloat16
+// operands, FP32 accumulation); FP32 master weights, Adam in FP32.
+//
+// Inference keeps all weights of one workgroup in LDS (an image of about
+// 82 KB laid out as MFMA operand fragments) and works in the transposed
+// form Z^T = W^T X^T: a wave evaluates 64 points at once, hidden units run
+// along the MFMA rows, points along its columns, so the accumulators of one
+// layer are already the next layer's B operand (after SiLU and conversion)
+// with no data exchange between lanes.  The K ordering of layers 2 and 3 is
+// permuted to match the accumulator layout; the weight fragments are stored
+// in the same permuted order.
+//
+// Training runs each product as a general bf16 "NT" GEMM (both operands
+// K-contiguous) with activations kept in HBM in the layouts the backward
+// products need; weight gradients are split-K partial sums reduced in a fixed
+// order by the Adam kernel, so a step is deterministic.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "mp_det.hpp"
+#include "mp_internal.hpp"
+#include "mp_lookup.hpp"
+
+namespace {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
+
+constexpr int kD0 = 192, kD1 = 128, kD2 = 128;
+constexpr int kOffW1 = 0, kOffB1 = kOffW1 + kD0 * kD1, kOffW2 = kOffB1 + kD1, kOffB2 = kOffW2 + kD1 * kD2,
+              kOffW3 = kOffB2 + kD2, kOffB3 = kOffW3 + kD2 * 4, kNParams = kOffB3 + 4;
+static_assert(kNParams == MP_SUR_NPARAMS, "parameter count");
+
+// inference image, byte offsets
+constexpr int kImgF1 = 0;                          // [4 row tiles][12 k-steps][64 lanes][8] bf16
+constexpr int kImgF2 = kImgF1 + 4 * 12 * 64 * 16;  // [4 row tiles][8 k-steps][64 lanes][8] bf16
+constexpr int kImgF3 = kImgF2 + 4 * 8 * 64 * 16;   // [8 k-steps][4 outputs][2 lane halves][8] bf16
+constexpr int kImgB1 = kImgF3 + 8 * 4 * 2 * 16;    // 128 f32
+constexpr int kImgB2 = kImgB1 + 512;               // 128 f32
+constexpr int kImgB3 = kImgB2 + 512;               // 4 f32
+constexpr int kImgFQ = kImgB3 + 16;                // 32 f32 frequencies
+constexpr int kImgBytes = kImgFQ + 128;
+static_assert(kImgBytes == MP_SUR_IMAGE_BYTES, "image size");
+static_assert(kImgBytes % 16 == 0, "image in uint4 units");
+
+// per-chunk sums of the small reductions: dW3 (512), db3 (4), db2 (128), db1 (128), squared error (1)
+constexpr int kL3W3 = 0, kL3B3 = 512, kL3B2 = 516, kL3B1 = 644, kL3SSE = 772, kL3Len = 773;
+constexpr int kRedChunk = 512;  // samples per reduction chunk; also the split-K slice
+
+__device__ __forceinline__ f32x16 mfma32(const bf16x8 a, const bf16x8 b, const f32x16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ float sigmoid_f(float z) {
+    return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-1.44269504088896341f * z));
+}
+__device__ __forceinline__ float silu_f(float z) { return z * sigmoid_f(z); }
+__device__ __forceinline__ float silu_grad_f(float z) {
+    const float s = sigmoid_f(z);
+    return s * __builtin_fmaf(z, 1.0f - s, 1.0f);
+}
+
+// sin and cos of 2 pi frac(f x): v_sin / v_cos take revolutions
+__device__ __forceinline__ void feature_pair(float f, float x, __bf16& s, __bf16& c) {
+    const float u = __builtin_amdgcn_fractf(f * x);
+    s = (__bf16)__builtin_amdgcn_sinf(u);
+    c = (__bf16)__builtin_amdgcn_cosf(u);
+}
+
+// ------------------------------------------------------------ fragment layouts
+// Layer-1 A operand (W1^T, rows = hidden o, k = feature f): element (o, f) of
+// row tile o/32 and k-step f/16 sits at lane (o%32) + 32 ((f%16)/8), slot f%8.
+__host__ __device__ inline int frag1_index(int f, int o) {
+    const int r = o >> 5, m = o & 31, s = f >> 4, kk = f & 15;
+    return ((r * 12 + s) * 64 + m + 32 * (kk >> 3)) * 8 + (kk & 7);
+}
+// Hidden unit i of a layer-1/2 accumulator tile: lane half h, register jj of
+// row tile r hold unit 32 r + 8 (jj/4) + 4 h + jj%4.  As the next layer's B
+// operand, k-step s2 takes registers 8 (s2%2) .. +7 of row tile s2/2, so
+// slot j of lane half h at k-step s2 is unit 32 (s2/2) + 16 (s2%2) + 8 (j/4) + 4 h + j%4.
+__host__ __device__ inline void hid_slot(int i, int& s2, int& h, int& j) {
+    s2 = 2 * (i >> 5) + ((i >> 4) & 1);
+    h = (i >> 2) & 1;
+    j = 4 * ((i >> 3) & 1) + (i & 3);
+}
+__host__ __device__ inline int frag2_index(int i, int o) {  // W2[i][o]
+    int s2, h, j;
+    hid_slot(i, s2, h, j);
+    return (((o >> 5) * 8 + s2) * 64 + (o & 31) + 32 * h) * 8 + j;
+}
+__host__ __device__ inline int frag3_index(int i, int o) {  // W3[i][o]
+    int s2, h, j;
+    hid_slot(i, s2, h, j);
+    return ((s2 * 4 + o) * 2 + h) * 8 + j;
+}
+
+// ------------------------------------------------------------ network on 64 points
+// Lane L supplies the normalised coordinates of point L%32 of tile 0 (xa[0])
+// and tile 1 (xa[1]); on return lane L holds the 4 outputs of point L%32 of
+// tile L/32.  img points at the inference image (LDS).
+__device__ __forceinline__ void mlp64(const char* __restrict__ img, const float xa[2][3], float y[4]) {
+    const int lane = threadIdx.x & 63, m = lane & 31, h = lane >> 5;
+    const bf16x8* f1 = reinterpret_cast<const bf16x8*>(img + kImgF1);
+    const bf16x8* f2 = reinterpret_cast<const bf16x8*>(img + kImgF2);
+    const bf16x8* f3 = reinterpret_cast<const bf16x8*>(img + kImgF3);
+    const float* b1 = reinterpret_cast<const float*>(img + kImgB1);
+    const float* b2 = reinterpret_cast<const float*>(img + kImgB2);
+    const float* b3 = reinterpret_cast<const float*>(img + kImgB3);
+    const float* fq = reinterpret_cast<const float*>(img + kImgFQ);
+
+    f32x16 acc[2][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float4 bb = *reinterpret_cast<const float4*>(b1 + 32 * r + 8 * q + 4 * h);
+#pragma unroll
+            for (int tt = 0; tt < 2; ++tt) {
+                acc[tt][r][4 * q] = bb.x;
+                acc[tt][r][4 * q + 1] = bb.y;
+                acc[tt][r][4 * q + 2] = bb.z;
+                acc[tt][r][4 * q + 3] = bb.w;
+            }
+        }
+    // layer 1: k-step s covers axis s/4, frequencies 8 (s%4) + 4 h + 0..3 (sin, cos each)
+#pragma unroll
+    for (int s = 0; s < 12; ++s) {
+        const float4 fr = *reinterpret_cast<const float4*>(fq + 8 * (s & 3) + 4 * h);
+        bf16x8 bx[2];
+#pragma unroll
+        for (int tt = 0; tt < 2; ++tt) {
+            const float x = xa[tt][s >> 2];
+            __bf16 v0, v1, v2, v3, v4, v5, v6, v7;
+            feature_pair(fr.x, x, v0, v1);
+            feature_pair(fr.y, x, v2, v3);
+            feature_pair(fr.z, x, v4, v5);
+            feature_pair(fr.w, x, v6, v7);
+            bx[tt] = bf16x8{v0, v1, v2, v3, v4, v5, v6, v7};
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const bf16x8 af = f1[(r * 12 + s) * 64 + lane];
+            acc[0][r] = mfma32(af, bx[0], acc[0][r]);
+            acc[1][r] = mfma32(af, bx[1], acc[1][r]);
+        }
+    }
+    bf16x8 hb[2][8];
+#pragma unroll
+    for (int tt = 0; tt < 2; ++tt)
+#pragma unroll
+        for (int s2 = 0; s2 < 8; ++s2)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) hb[tt][s2][j] = (__bf16)silu_f(acc[tt][s2 >> 1][8 * (s2 & 1) + j]);
+    // layer 2
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float4 bb = *reinterpret_cast<const float4*>(b2 + 32 * r + 8 * q + 4 * h);
+#pragma unroll
+            for (int tt = 0; tt < 2; ++tt) {
+                acc[tt][r][4 * q] = bb.x;
+                acc[tt][r][4 * q + 1] = bb.y;
+                acc[tt][r][4 * q + 2] = bb.z;
+                acc[tt][r][4 * q + 3] = bb.w;
+            }
+        }
+#pragma unroll
+    for (int s2 = 0; s2 < 8; ++s2)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const bf16x8 af = f2[(r * 8 + s2) * 64 + lane];
+            acc[0][r] = mfma32(af, hb[0][s2], acc[0][r]);
+            acc[1][r] = mfma32(af, hb[1][s2], acc[1][r]);
+        }
+#pragma unroll
+    for (int tt = 0; tt < 2; ++tt)
+#pragma unroll
+        for (int s2 = 0; s2 < 8; ++s2)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) hb[tt][s2][j] = (__bf16)silu_f(acc[tt][s2 >> 1][8 * (s2 & 1) + j]);
+    // layer 3: tile tt's outputs in rows 4 tt .. 4 tt + 3 (other A rows zero),
+    // both tiles accumulated into one tile: lane half h then holds tile h
+    f32x16 o = {};
+    const bf16x8 zero = {};
+#pragma unroll
+    for (int s2 = 0; s2 < 8; ++s2)
+#pragma unroll
+        for (int tt = 0; tt < 2; ++tt) {
+            const int o3 = m - 4 * tt;
+            const bf16x8 af = (o3 >= 0 && o3 < 4) ? f3[(s2 * 4 + o3) * 2 + h] : zero;
+            o = mfma32(af, hb[tt][s2], o);
+        }
+    y[0] = o[0] + b3[0];
+    y[1] = o[1] + b3[1];
+    y[2] = o[2] + b3[2];
+    y[3] = o[3] + b3[3];
+}
+
+__device__ __forceinline__ void load_image(const uint4* __restrict__ src, uint4* dst) {
+    for (int q = threadIdx.x; q < kImgBytes / 16; q += blockDim.x) dst[q] = src[q];
+    __syncthreads();
+}
+
+// ------------------------------------------------------------ score field
+__device__ __forceinline__ bool score_point(float ex, float ey, float ez, const float4 gn, float a, float sig2,
+                                            float ib, float cmax, float& s, float& gx, float& gy, float& gz) {
+    const float kap = a / ((1.0f + sig2) * (gn.w + sig2));
+    const float ne = __builtin_fmaf(gn.x, ex, __builtin_fmaf(gn.y, ey, gn.z * ez));
+    const float ee = __builtin_fmaf(ex, ex, __builtin_fmaf(ey, ey, ez * ez));
+    const float c = __builtin_fmaf(kap * ne, ne, ee * ib);
+    const float kn = kap * ne;
+    gx = -2.0f * __builtin_fmaf(kn, gn.x, ex * ib);
+    gy = -2.0f * __builtin_fmaf(kn, gn.y, ey * ib);
+    gz = -2.0f * __builtin_fmaf(kn, gn.z, ez * ib);
+    s = c;
+    return c < cmax;
+}
+
+struct LabelArgs {
+    MapView map;
+    const float* __restrict__ xyz;
+    float4* __restrict__ out;
+    int64_t n;
+    float sig2, ib, dmax2, cmax, inv_s, inv_g;
+};
+
+__global__ void k_label(LabelArgs A) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= A.n) return;
+    const float px = A.xyz[3 * i], py = A.xyz[3 * i + 1], pz = A.xyz[3 * i + 2];
+    const int32_t g = mp_nnf_lookup<0>(A.map, px, py, pz);
+    float s = A.cmax, gx = 0.0f, gy = 0.0f, gz = 0.0f;
+    if (g >= 0) {
+        const float4 gm = A.map.gauss[2 * (int64_t)g];
+        const float4 gn = A.map.gauss[2 * (int64_t)g + 1];
+        const float ex = gm.x - px, ey = gm.y - py, ez = gm.z - pz;
+        const float d2 = __builtin_fmaf(ex, ex, __builtin_fmaf(ey, ey, ez * ez));
+        if (d2 <= A.dmax2) {
+            float c, ux, uy, uz;
+            if (score_point(ex, ey, ez, gn, A.map.gicp_a, A.sig2, A.ib, A.cmax, c, ux, uy, uz)) {
+                s = c;
+                gx = ux;
+                gy = uy;
+                gz = uz;
+            }
+        }
+    }
+    A.out[i] = make_float4(s * A.inv_s, gx * A.inv_g, gy * A.inv_g, gz * A.inv_g);
+}
+
+// ------------------------------------------------------------ weights
+__global__ void k_init_weights(float* __restrict__ P, uint64_t seed) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= kNParams) return;
+    float bound = 0.0f;
+    if (q < kOffB1) bound = 0.07216878364870322f;        // 1 / sqrt(192)
+    else if (q >= kOffW2 && q < kOffB2) bound = 0.08838834764831845f;  // 1 / sqrt(128)
+    else if (q >= kOffW3 && q < kOffB3) bound = 0.08838834764831845f;
+    const mpdet::u32x4 r = mpdet::rng(seed, (uint32_t)q, 0u, 0u, mpdet::PURPOSE_WINIT, 0u);
+    P[q] = bound * (2.0f * mpdet::unit_co(r.v[0]) - 1.0f);
+}
+
+struct PublishArgs {
+    __bf16* w1t;  // [128][192]
+    __bf16* w2t;  // [128 out][128 in]
+    __bf16* w2n;  // [128 in][128 out]
+    __bf16* w3b;  // [128][4]
+    char* img;
+};
+
+__device__ __forceinline__ void publish(const PublishArgs& W, int q, float w) {
+    const __bf16 wb = (__bf16)w;
+    __bf16* f1 = reinterpret_cast<__bf16*>(W.img + kImgF1);
+    __bf16* f2 = reinterpret_cast<__bf16*>(W.img + kImgF2);
+    __bf16* f3 = reinterpret_cast<__bf16*>(W.img + kImgF3);
+    if (q < kOffB1) {
+        const int f = q / kD1, o = q % kD1;
+        W.w1t[o * kD0 + f] = wb;
+        f1[frag1_index(f, o)] = wb;
+    } else if (q < kOffW2) {
+        reinterpret_cast<float*>(W.img + kImgB1)[q - kOffB1] = w;
+    } else if (q < kOffB2) {
+        const int i = (q - kOffW2) / kD2, o = (q - kOffW2) % kD2;
+        W.w2t[o * kD1 + i] = wb;
+        W.w2n[i * kD2 + o] = wb;
+        f2[frag2_index(i, o)] = wb;
+    } else if (q < kOffW3) {
+        reinterpret_cast<float*>(W.img + kImgB2)[q - kOffB2] = w;
+    } else if (q < kOffB3) {
+        const int i = (q - kOffW3) / 4, o = (q - kOffW3) % 4;
+        W.w3b[i * 4 + o] = wb;
+        f3[frag3_index(i, o)] = wb;
+    } else {
+        reinterpret_cast<float*>(W.img + kImgB3)[q - kOffB3] = w;
+    }
+}
+
+__global__ void k_publish(const float* __restrict__ P, PublishArgs W) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= kNParams) return;
+    publish(W, q, P[q]);
+}
+
+// ------------------------------------------------------------ training kernels
+struct BatchArgs {
+    const float* __restrict__ dxyz;
+    const float4* __restrict__ dlab;
+    float* __restrict__ bxyz;
+    float4* __restrict__ btgt;
+    int64_t n_data;
+    int32_t n_real, bp, full;
+    uint32_t step;
+    uint64_t seed;
+};
+
+__global__ void k_draw_batch(BatchArgs A) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= A.bp) return;
+    if (b >= A.n_real) {
+        A.bxyz[3 * b] = A.bxyz[3 * b + 1] = A.bxyz[3 * b + 2] = 0.0f;
+        A.btgt[b] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        return;
+    }
+    int64_t idx = b;
+    if (!A.full) {
+        const mpdet::u32x4 r = mpdet::rng(A.seed, (uint32_t)b, A.step, 0u, mpdet::PURPOSE_BATCH, 0u);
+        const uint64_t x = ((uint64_t)r.v[1] << 32) | r.v[0];
+        idx = (int64_t)__umul64hi(x, (uint64_t)A.n_data);   // floor(x n / 2^64), uniform in [0, n)
+    }
+    A.bxyz[3 * b] = A.dxyz[3 * idx];
+    A.bxyz[3 * b + 1] = A.dxyz[3 * idx + 1];
+    A.bxyz[3 * b + 2] = A.dxyz[3 * idx + 2];
+    A.btgt[b] = A.dlab[idx];
+}
+
+struct FeatArgs {
+    const float* __restrict__ xyz;
+    __bf16* __restrict__ X;    // [bp][192]
+    __bf16* __restrict__ XT;   // [192][bp]
+    int32_t bp;
+    float lo[3], inv[3];
+    float fq[32];
+};
+
+__global__ void k_features(FeatArgs A) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= A.bp) return;
+    __bf16* row = A.X + (size_t)b * kD0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float x = (A.xyz[3 * b + a] - A.lo[a]) * A.inv[a];
+#pragma unroll 4
+        for (int l = 0; l < 32; l += 4) {
+            bf16x8 v;
+            __bf16 s0, c0, s1, c1, s2, c2, s3, c3;
+            feature_pair(A.fq[l], x, s0, c0);
+            feature_pair(A.fq[l + 1], x, s1, c1);
+            feature_pair(A.fq[l + 2], x, s2, c2);
+            feature_pair(A.fq[l + 3], x, s3, c3);
+            v = bf16x8{s0, c0, s1, c1, s2, c2, s3, c3};
+            const int f = 2 * (a * 32 + l);
+            *reinterpret_cast<bf16x8*>(row + f) = v;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) A.XT[(size_t)(f + j) * A.bp + b] = v[j];
+        }
+    }
+}
+
+enum { EPI_ACT = 0, EPI_BACK = 1, EPI_PARTIAL = 2 };
+
+struct GemmArgs {
+    const __bf16* __restrict__ A;  // [M][K]
+    const __bf16* __restrict__ B;  // [N][K]
+    int32_t M, N, K, kslice;
+    const float* __restrict__ bias;  // EPI_ACT: [N]
+    float* __restrict__ Z;           // EPI_ACT: pre-activation [M][N] (FP32)
+    __bf16* __restrict__ H;          // EPI_ACT: silu(Z) [M][N]
+    __bf16* __restrict__ HT;         // EPI_ACT (optional), EPI_BACK: [N][M]
+    const float* __restrict__ Zin;   // EPI_BACK: pre-activation [M][N]
+    float* __restrict__ out;         // EPI_PARTIAL: [slices][M][N]
+};
+
+// C[m][n] = sum_k A[m][k] B[n][k]; block tile 64 x 128, four waves of 32 x 64.
+// Requires M % 64 == 0, N % 128 == 0, K % 16 == 0, kslice % 16 == 0.
+template <int EPI>
+__global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r = lane & 31, h = lane >> 5;
+    const int m0 = blockIdx.x * 64 + (wave & 1) * 32;
+    const int n0 = blockIdx.y * 128 + (wave >> 1) * 64;
+    const int kb = blockIdx.z * g.kslice;
+    const int ke = min(g.K, kb + g.kslice);
+    const bf16x8* pa = reinterpret_cast<const bf16x8*>(g.A + (size_t)(m0 + r) * g.K + 8 * h);
+    const bf16x8* pb0 = reinterpret_cast<const bf16x8*>(g.B + (size_t)(n0 + r) * g.K + 8 * h);
+    const bf16x8* pb1 = reinterpret_cast<const bf16x8*>(g.B + (size_t)(n0 + 32 + r) * g.K + 8 * h);
+    f32x16 c0 = {}, c1 = {};
+    for (int k = kb; k < ke; k += 16) {
+        const int kq = k >> 3;
+        const bf16x8 a = pa[kq], b0 = pb0[kq], b1 = pb1[kq];
+        c0 = mfma32(a, b0, c0);
+        c1 = mfma32(a, b1, c1);
+    }
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+        const f32x16& c = half ? c1 : c0;
+        const int n = n0 + 32 * half + r;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int mb = m0 + 8 * q + 4 * h;   // rows mb .. mb + 3 in registers 4q .. 4q + 3
+            if (EPI == EPI_PARTIAL) {
+                float* o = g.out + ((size_t)blockIdx.z * g.M + mb) * g.N + n;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) o[(size_t)i * g.N] = c[4 * q + i];
+            } else if (EPI == EPI_ACT) {
+                __bf16 hv[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const float z = c[4 * q + i] + g.bias[n];
+                    g.Z[(size_t)(mb + i) * g.N + n] = z;
+                    hv[i] = (__bf16)silu_f(z);
+                    g.H[(size_t)(mb + i) * g.N + n] = hv[i];
+                }
+                if (g.HT) {
+                    __bf16* t = g.HT + (size_t)n * g.M + mb;
+                    t[0] = hv[0];
+                    t[1] = hv[1];
+                    t[2] = hv[2];
+                    t[3] = hv[3];
+                }
+            } else {
+                __bf16* t = g.HT + (size_t)n * g.M + mb;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const float z = g.Zin[(size_t)(mb + i) * g.N + n];
+                    t[i] = (__bf16)(c[4 * q + i] * silu_grad_f(z));
+                }
+            }
+        }
+    }
+}
+
+// Output layer forward and backward, one thread per sample: y = h2 W3 + b3,
+// squared error, dy = 2 (y - t) / n, dz2 = (W3 dy) silu'(z2) rounded to bf16.
+struct L3Args {
+    const __bf16* __restrict__ H2;    // [bp][128]
+    const float* __restrict__ Z2;     // [bp][128]
+    const __bf16* __restrict__ w3b;   // [128][4]
+    const float* __restrict__ b3;     // [4] (FP32 master)
+    const float4* __restrict__ tgt;   // [bp]
+    float4* __restrict__ dY;          // [bp]
+    float* __restrict__ sse;          // [bp]
+    __bf16* __restrict__ dZ2;         // [bp][128]
+    __bf16* __restrict__ dZ2T;        // [128][bp]
+    int32_t bp, n_real;
+    float two_over_n;
+};
+
+__global__ __launch_bounds__(256) void k_out_layer(L3Args A) {
+    __shared__ float w3[kD2 * 4];
+    for (int q = threadIdx.x; q < kD2 * 4; q += blockDim.x) w3[q] = (float)A.w3b[q];
+    __syncthreads();
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= A.bp) return;
+    const bool valid = b < A.n_real;
+    const bf16x8* hrow = reinterpret_cast<const bf16x8*>(A.H2 + (size_t)b * kD2);
+    float y0 = A.b3[0], y1 = A.b3[1], y2 = A.b3[2], y3 = A.b3[3];
+    for (int c = 0; c < kD2 / 8; ++c) {
+        const bf16x8 hv = hrow[c];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const float hj = (float)hv[j];
+            const float* w = w3 + 4 * (8 * c + j);
+            y0 = __builtin_fmaf(hj, w[0], y0);
+            y1 = __builtin_fmaf(hj, w[1], y1);
+            y2 = __builtin_fmaf(hj, w[2], y2);
+            y3 = __builtin_fmaf(hj, w[3], y3);
+        }
+    }
+    const float4 t = A.tgt[b];
+    const float r0 = y0 - t.x, r1 = y1 - t.y, r2 = y2 - t.z, r3 = y3 - t.w;
+    const float e = valid ? __builtin_fmaf(r0, r0, __builtin_fmaf(r1, r1, __builtin_fmaf(r2, r2, r3 * r3))) : 0.0f;
+    const float k = valid ? A.two_over_n : 0.0f;
+    const float d0 = r0 * k, d1 = r1 * k, d2 = r2 * k, d3 = r3 * k;
+    A.sse[b] = e;
+    A.dY[b] = make_float4(d0, d1, d2, d3);
+    const float* z = A.Z2 + (size_t)b * kD2;
+    bf16x8* drow = reinterpret_cast<bf16x8*>(A.dZ2 + (size_t)b * kD2);
+    for (int c = 0; c < kD2 / 8; ++c) {
+        bf16x8 v;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int i = 8 * c + j;
+            const float* w = w3 + 4 * i;
+            const float dh = __builtin_fmaf(w[0], d0, __builtin_fmaf(w[1], d1, __builtin_fmaf(w[2], d2, w[3] * d3)));
+            v[j] = (__bf16)(dh * silu_grad_f(z[i]));
+            A.dZ2T[(size_t)i * A.bp + b] = v[j];
+        }
+        drow[c] = v;
+    }
+}
+
+// Per-chunk sums over kRedChunk samples: dW3 = sum h2 dy, db3 = sum dy,
+// db2 = sum dz2, db1 = sum dz1, squared error.
+struct RedArgs {
+    const __bf16* __restrict__ H2;    // [bp][128]
+    const float4* __restrict__ dY;    // [bp]
+    const float* __restrict__ sse;    // [bp]
+    const __bf16* __restrict__ dZ2;   // [bp][128]
+    const __bf16* __restrict__ dZ1T;  // [128][bp]
+    float* __restrict__ out;          // [chunks][kL3Len]
+    int32_t bp;
+};
+
+__global__ __launch_bounds__(256) void k_reduce_small(RedArgs A) {
+    const int b0 = blockIdx.x * kRedChunk;
+    float* o = A.out + (size_t)blockIdx.x * kL3Len;
+    for (int item = threadIdx.x; item < kL3Len; item += blockDim.x) {
+        float acc = 0.0f;
+        if (item < kL3B3) {
+            const int j = item >> 2, c = item & 3;
+            for (int b = b0; b < b0 + kRedChunk; ++b) {
+                const float4 d = A.dY[b];
+                const float dv = c == 0 ? d.x : (c == 1 ? d.y : (c == 2 ? d.z : d.w));
+                acc = __builtin_fmaf((float)A.H2[(size_t)b * kD2 + j], dv, acc);
+            }
+        } else if (item < kL3B2) {
+            const int c = item - kL3B3;
+            for (int b = b0; b < b0 + kRedChunk; ++b) {
+                const float4 d = A.dY[b];
+                acc += c == 0 ? d.x : (c == 1 ? d.y : (c == 2 ? d.z : d.w));
+            }
+        } else if (item < kL3B1) {
+            const int j = item - kL3B2;
+            for (int b = b0; b < b0 + kRedChunk; ++b) acc += (float)A.dZ2[(size_t)b * kD2 + j];
+        } else if (item < kL3SSE) {
+            const int j = item - kL3B1;
+            const __bf16* row = A.dZ1T + (size_t)j * A.bp;
+            for (int b = b0; b < b0 + kRedChunk; ++b) acc += (float)row[b];
+        } else {
+            for (int b = b0; b < b0 + kRedChunk; ++b) acc += A.sse[b];
+        }
+        o[item] = acc;
+    }
+}
+
+struct AdamArgs {
+    float* __restrict__ P;
+    float* __restrict__ Mo;
+    float* __restrict__ Vo;
+    float* __restrict__ G;
+    const float* __restrict__ pw1;   // [nsplit][192][128]
+    const float* __restrict__ pw2;   // [nsplit][128][128]
+    const float* __restrict__ pl3;   // [nsplit][kL3Len]
+    float* __restrict__ loss_out;    // one float
+    int32_t nsplit, update;
+    float inv_n, lr, beta1, beta2, eps, c1, c2;
+    PublishArgs W;
+};
+
+__global__ void k_adam(AdamArgs A) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q == 0 && A.loss_out) {
+        float s = 0.0f;
+        for (int z = 0; z < A.nsplit; ++z) s += A.pl3[(size_t)z * kL3Len + kL3SSE];
+        *A.loss_out = s * A.inv_n;
+    }
+    if (q >= kNParams) return;
+    float g = 0.0f;
+    if (q < kOffB1) {
+        for (int z = 0; z < A.nsplit; ++z) g += A.pw1[(size_t)z * (kD0 * kD1) + q];
+    } else if (q < kOffW2) {
+        for (int z = 0; z < A.nsplit; ++z) g += A.pl3[(size_t)z * kL3Len + kL3B1 + (q - kOffB1)];
+    } else if (q < kOffB2) {
+        for (int z = 0; z < A.nsplit; ++z) g += A.pw2[(size_t)z * (kD1 * kD2) + (q - kOffW2)];
+    } else if (q < kOffW3) {
+        for (int z = 0; z < A.nsplit; ++z) g += A.pl3[(size_t)z * kL3Len + kL3B2 + (q - kOffB2)];
+    } else if (q < kOffB3) {
+        for (int z = 0; z < A.nsplit; ++z) g += A.pl3[(size_t)z * kL3Len + kL3W3 + (q - kOffW3)];
+    } else {
+        for (int z = 0; z < A.nsplit; ++z) g += A.pl3[(size_t)z * kL3Len + kL3B3 + (q - kOffB3)];
+    }
+    A.G[q] = g;
+    if (!A.update) return;
+    const float m = __builtin_fmaf(A.beta1, A.Mo[q], (1.0f - A.beta1) * g);
+    const float v = __builtin_fmaf(A.beta2, A.Vo[q], (1.0f - A.beta2) * g * g);
+    A.Mo[q] = m;
+    A.Vo[q] = v;
+    const float mh = m / A.c1, vh = v / A.c2;
+    const float w = A.P[q] - A.lr * mh / (sqrtf(vh) + A.eps);
+    A.P[q] = w;
+    publish(A.W, q, w);
+}
+
+// ------------------------------------------------------------ inference kernels
+constexpr int kInferThreads = 256;
+
+struct EvalArgs {
+    const uint4* __restrict__ img;
+    const float* __restrict__ xyz;
+    float4* __restrict__ out;
+    int64_t n;
+    float lo[3], inv[3];
+    float s_scale, g_scale;
+};
+
+__global__ __launch_bounds__(kInferThreads) void k_sur_eval(EvalArgs A) {
+    __shared__ uint4 simg[kImgBytes / 16];
+    load_image(A.img, simg);
+    const char* img = reinterpret_cast<const char*>(simg);
+    const int lane = threadIdx.x & 63, m = lane & 31, h = lane >> 5;
+    const int64_t nw = (int64_t)gridDim.x * (kInferThreads / 64);
+    for (int64_t g = (int64_t)blockIdx.x * (kInferThreads / 64) + (threadIdx.x >> 6); g * 64 < A.n; g += nw) {
+        // keeps the weight-fragment reads inside the loop (hoisting them would
+        // need some 320 registers per lane)
+        asm volatile("" ::: "memory");
+        float xa[2][3];
+#pragma unroll
+        for (int tt = 0; tt < 2; ++tt) {
+            const int64_t k = g * 64 + 32 * tt + m;
+            const bool v = k < A.n;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) xa[tt][a] = ((v ? A.xyz[3 * k + a] : A.lo[a]) - A.lo[a]) * A.inv[a];
+        }
+        float y[4];
+        mlp64(img, xa, y);
+        const int64_t k = g * 64 + 32 * h + m;
+        if (k < A.n) A.out[k] = make_float4(y[0] * A.s_scale, y[1] * A.g_scale, y[2] * A.g_scale, y[3] * A.g_scale);
+    }
+}
+
+struct SurLikArgs {
+    const uint4* __restrict__ img;
+    const float4* __restrict__ poses;   // N x 2 float4 (q; t, 0)
+    const int32_t* __restrict__ order;  // sorted position -> particle (or null)
+    const float4* __restrict__ scan;    // ns x 3 float4 records (mu in the first)
+    float* __restrict__ partial;        // [29][N]
+    int32_t n, ns;
+    float cmax, s_scale, g_scale, r_floor2;
+    float lo[3], inv[3];
+};
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// One wave per particle at a time (persistent over particles); 64 scan points
+// per network evaluation.  Per-lane sums of H (21), b (6), cost and outliers
+// are reduced across the wave once per particle.
+__global__ __launch_bounds__(kInferThreads) void k_lik_sur(SurLikArgs A) {
+    __shared__ uint4 simg[kImgBytes / 16];
+    load_image(A.img, simg);
+    const char* img = reinterpret_cast<const char*>(simg);
+    const int lane = threadIdx.x & 63, m = lane & 31, h = lane >> 5;
+    const int nw = gridDim.x * (kInferThreads / 64);
+    for (int sidx = blockIdx.x * (kInferThreads / 64) + (threadIdx.x >> 6); sidx < A.n; sidx += nw) {
+        const int i = A.order ? A.order[sidx] : sidx;
+        if (i < 0 || i >= A.n) continue;
+        const float4 q4 = A.poses[2 * i];
+        const float4 t4 = A.poses[2 * i + 1];
+        const mpdet::mat3 Rm = mpdet::qmat(mpdet::quat{q4.x, q4.y, q4.z, q4.w});
+        const float3 t = make_float3(t4.x, t4.y, t4.z);
+        float hs[21], bs[6];
+#pragma unroll
+        for (int k = 0; k < 21; ++k) hs[k] = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) bs[k] = 0.0f;
+        float cost = 0.0f, comp = 0.0f, nout = 0.0f;
+        for (int k0 = 0; k0 < A.ns; k0 += 64) {
+            asm volatile("" ::: "memory");   // as in k_sur_eval: no hoisting of fragment reads
+            float xa[2][3];
+            float3 mu_mine = make_float3(0.0f, 0.0f, 0.0f);
+#pragma unroll
+            for (int tt = 0; tt < 2; ++tt) {
+                const int k = k0 + 32 * tt + m;
+                const float4 r0 = k < A.ns ? A.scan[3 * k] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                const float3 mu = make_float3(r0.x, r0.y, r0.z);
+                const float3 p = mpdet::xform(Rm.m, t, mu);
+                xa[tt][0] = (p.x - A.lo[0]) * A.inv[0];
+                xa[tt][1] = (p.y - A.lo[1]) * A.inv[1];
+                xa[tt][2] = (p.z - A.lo[2]) * A.inv[2];
+                if (tt == h) mu_mine = mu;
+            }
+            float y[4];
+            mlp64(img, xa, y);
+            const bool valid = k0 + 32 * h + m < A.ns;
+            float s = y[0] * A.s_scale;
+            const bool inl = valid && s < A.cmax;
+            nout += (valid && !inl) ? 1.0f : 0.0f;
+            s = fmaxf(s, 0.0f);
+            const float3 w = mpdet::rot_t(Rm, make_float3(y[1] * A.g_scale, y[2] * A.g_scale, y[3] * A.g_scale));
+            const float ir = inl ? 0.5f * __builtin_amdgcn_rsqf(fmaxf(s, A.r_floor2)) : 0.0f;
+            const float hw = inl ? 0.5f : 0.0f;
+            const float ux = w.x * ir, uy = w.y * ir, uz = w.z * ir;
+            const float3 mu = mu_mine;
+            const float g6[6] = {mu.y * uz - mu.z * uy, mu.z * ux - mu.x * uz, mu.x * uy - mu.y * ux, ux, uy, uz};
+            int q = 0;
+#pragma unroll
+            for (int r = 0; r < 6; ++r)
+#pragma unroll
+                for (int c = r; c < 6; ++c) {
+                    hs[q] = __builtin_fmaf(g6[r], g6[c], hs[q]);
+                    ++q;
+                }
+            bs[0] = __builtin_fmaf(hw, mu.y * w.z - mu.z * w.y, bs[0]);
+            bs[1] = __builtin_fmaf(hw, mu.z * w.x - mu.x * w.z, bs[1]);
+            bs[2] = __builtin_fmaf(hw, mu.x * w.y - mu.y * w.x, bs[2]);
+            bs[3] = __builtin_fmaf(hw, w.x, bs[3]);
+            bs[4] = __builtin_fmaf(hw, w.y, bs[4]);
+            bs[5] = __builtin_fmaf(hw, w.z, bs[5]);
+            const float yv = (inl ? s : 0.0f) - comp;
+            const float tv = cost + yv;
+            comp = (tv - cost) - yv;
+            cost = tv;
+        }
+        float* out = A.partial + i;
+        const size_t st = (size_t)A.n;
+#pragma unroll
+        for (int k = 0; k < 21; ++k) {
+            const float v = wave_sum(hs[k]);
+            if (lane == 0) out[k * st] = v;
+        }
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const float v = wave_sum(bs[k]);
+            if (lane == 0) out[(21 + k) * st] = v;
+        }
+        const float cs = wave_sum(cost - comp);
+        const float no = wave_sum(nout);
+        if (lane == 0) {
+            out[27 * st] = cs;
+            out[28 * st] = no;
+        }
+    }
+}
+
+int num_cus() {
+    int dev = 0, cus = 0;
+    MP_HIP(hipGetDevice(&dev));
+    MP_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    return std::max(1, cus);
+}
+
+PublishArgs publish_args(mp_surrogate S) {
+    PublishArgs W;
+    W.w1t = S->w1t.as<__bf16>();
+    W.w2t = S->w2t.as<__bf16>();
+    W.w2n = S->w2n.as<__bf16>();
+    W.w3b = S->w3b.as<__bf16>();
+    W.img = S->img.as<char>();
+    return W;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------ host launchers
+void mp_sur_alloc(mp_surrogate S, hipStream_t s) {
+    S->P.alloc(sizeof(float) * kNParams);
+    S->Mo.alloc(sizeof(float) * kNParams);
+    S->Vo.alloc(sizeof(float) * kNParams);
+    S->G.alloc(sizeof(float) * kNParams);
+    S->img.alloc(kImgBytes);
+    S->w1t.alloc(2 * kD0 * kD1);
+    S->w2t.alloc(2 * kD1 * kD2);
+    S->w2n.alloc(2 * kD1 * kD2);
+    S->w3b.alloc(2 * kD2 * 4);
+    MP_HIP(hipMemsetAsync(S->img.p, 0, kImgBytes, s));
+    MP_HIP(hipMemcpyAsync(S->img.as<char>() + kImgFQ, S->info.freqs, sizeof(float) * 32, hipMemcpyHostToDevice, s));
+    MP_HIP(hipStreamSynchronize(s));
+}
+
+void mp_sur_reset_adam(mp_surrogate S, hipStream_t s) {
+    MP_HIP(hipMemsetAsync(S->Mo.p, 0, sizeof(float) * kNParams, s));
+    MP_HIP(hipMemsetAsync(S->Vo.p, 0, sizeof(float) * kNParams, s));
+    S->info.steps = 0;
+}
+
+void mp_sur_publish(mp_surrogate S, hipStream_t s) {
+    k_publish<<<(kNParams + 255) / 256, 256, 0, s>>>(S->P.as<float>(), publish_args(S));
+    MP_CHECK_LAUNCH();
+}
+
+void mp_sur_init_weights(mp_surrogate S, hipStream_t s) {
+    k_init_weights<<<(kNParams + 255) / 256, 256, 0, s>>>(S->P.as<float>(), S->p.seed);
+    MP_CHECK_LAUNCH();
+    mp_sur_reset_adam(S, s);
+    mp_sur_publish(S, s);
+}
+
+void mp_sur_label(mp_surrogate S, const float* xyz_dev, int64_t n, float* out4_dev, bool scaled, hipStream_t s) {
+    if (n <= 0) return;
+    LabelArgs A;
+    A.map = S->map->view;
+    A.xyz = xyz_dev;
+    A.out = reinterpret_cast<float4*>(out4_dev);
+    A.n = n;
+    A.sig2 = S->p.sigma_s * S->p.sigma_s;
+    A.ib = 1.0f / (1.0f + A.sig2);
+    A.dmax2 = S->p.d_max * S->p.d_max;
+    A.cmax = S->p.c_max;
+    A.inv_s = scaled ? 1.0f / S->info.s_scale : 1.0f;
+    A.inv_g = scaled ? 1.0f / S->info.g_scale : 1.0f;
+    k_label<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(A);
+    MP_CHECK_LAUNCH();
+}
+
+void mp_sur_eval(mp_surrogate S, const float* xyz_dev, int64_t n, float* out4_dev, hipStream_t s) {
+    if (n <= 0) return;
+    EvalArgs A;
+    A.img = S->img.as<uint4>();
+    A.xyz = xyz_dev;
+    A.out = reinterpret_cast<float4*>(out4_dev);
+    A.n = n;
+    for (int a = 0; a < 3; ++a) {
+        A.lo[a] = S->info.lo[a];
+        A.inv[a] = S->info.inv_ext[a];
+    }
+    A.s_scale = S->info.s_scale;
+    A.g_scale = S->info.g_scale;
+    const int64_t groups = (n + 63) / 64;
+    const int64_t blocks = std::min<int64_t>((int64_t)num_cus(), (groups + 3) / 4);
+    k_sur_eval<<<(unsigned)std::max<int64_t>(1, blocks), kInferThreads, 0, s>>>(A);
+    MP_CHECK_LAUNCH();
+}
+
+// padded batch rows: a multiple of the reduction chunk
+static int32_t padded_rows(int64_t n) { return (int32_t)((n + kRedChunk - 1) / kRedChunk * kRedChunk); }
+
+void mp_sur_ensure_batch(mp_surrogate S, int64_t cap) {
+    const int32_t bp = padded_rows(cap);
+    if (bp <= S->cap) return;
+    const size_t b = (size_t)bp;
+    S->bxyz.alloc(sizeof(float) * 3 * b);
+    S->btgt.alloc(sizeof(float) * 4 * b);
+    S->X.alloc(2 * kD0 * b);
+    S->XT.alloc(2 * kD0 * b);
+    S->Z1.alloc(sizeof(float) * kD1 * b);
+    S->H1.alloc(2 * kD1 * b);
+    S->H1T.alloc(2 * kD1 * b);
+    S->Z2.alloc(sizeof(float) * kD2 * b);
+    S->H2.alloc(2 * kD2 * b);
+    S->dY.alloc(sizeof(float) * 4 * b);
+    S->sse.alloc(sizeof(float) * b);
+    S->dZ2.alloc(2 * kD2 * b);
+    S->dZ2T.alloc(2 * kD2 * b);
+    S->dZ1T.alloc(2 * kD1 * b);
+    const size_t ns = b / kRedChunk;
+    S->pw1.alloc(sizeof(float) * ns * kD0 * kD1);
+    S->pw2.alloc(sizeof(float) * ns * kD1 * kD2);
+    S->pl3.alloc(sizeof(float) * ns * kL3Len);
+    S->cap = bp;
+}
+
+// One gradient evaluation over the staged batch (bxyz, btgt; n_real rows),
+// optionally followed by an Adam step with learning rate lr.
+void mp_sur_grad_step(mp_surrogate S, int32_t n_real, bool update, float lr, float* loss_dev, hipStream_t s) {
+    const int32_t bp = padded_rows(n_real);
+    if (bp > S->cap) mp_throw(MP_E_STATE, "surrogate batch buffers too small");
+    FeatArgs F;
+    F.xyz = S->bxyz.as<float>();
+    F.X = S->X.as<__bf16>();
+    F.XT = S->XT.as<__bf16>();
+    F.bp = bp;
+    for (int a = 0; a < 3; ++a) {
+        F.lo[a] = S->info.lo[a];
+        F.inv[a] = S->info.inv_ext[a];
+    }
+    for (int l = 0; l < 32; ++l) F.fq[l] = S->info.freqs[l];
+    k_features<<<(bp + 255) / 256, 256, 0, s>>>(F);
+    MP_CHECK_LAUNCH();
+    const float* P = S->P.as<float>();
+
+    GemmArgs g{};
+    // Z1 = X W1 (+ b1), H1 = silu(Z1), H1T
+    g.A = S->X.as<__bf16>();
+    g.B = S->w1t.as<__bf16>();
+    g.M = bp; g.N = kD1; g.K = kD0; g.kslice = kD0;
+    g.bias = P + kOffB1;
+    g.Z = S->Z1.as<float>();
+    g.H = S->H1.as<__bf16>();
+    g.HT = S->H1T.as<__bf16>();
+    k_gemm_nt<EPI_ACT><<<dim3(bp / 64, 1, 1), 256, 0, s>>>(g);
+    MP_CHECK_LAUNCH();
+    // Z2 = H1 W2 (+ b2), H2 = silu(Z2)
+    g = GemmArgs{};
+    g.A = S->H1.as<__bf16>();
+    g.B = S->w2t.as<__bf16>();
+    g.M = bp; g.N = kD2; g.K = kD1; g.kslice = kD1;
+    g.bias = P + kOffB2;
+    g.Z = S->Z2.as<float>();
+    g.H = S->H2.as<__bf16>();
+    g.HT = nullptr;
+    k_gemm_nt<EPI_ACT><<<dim3(bp / 64, 1, 1), 256, 0, s>>>(g);
+    MP_CHECK_LAUNCH();
+    // output layer and its backward
+    L3Args L;
+    L.H2 = S->H2.as<__bf16>();
+    L.Z2 = S->Z2.as<float>();
+    L.w3b = S->w3b.as<__bf16>();
+    L.b3 = P + kOffB3;
+    L.tgt = S->btgt.as<float4>();
+    L.dY = S->dY.as<float4>();
+    L.sse = S->sse.as<float>();
+    L.dZ2 = S->dZ2.as<__bf16>();
+    L.dZ2T = S->dZ2T.as<__bf16>();
+    L.bp = bp;
+    L.n_real = n_real;
+    L.two_over_n = (float)(2.0 / (double)n_real);
+    k_out_layer<<<bp / 256, 256, 0, s>>>(L);
+    MP_CHECK_LAUNCH();
+    // dZ1 = (dZ2 W2^T) silu'(Z1), stored transposed
+    g = GemmArgs{};
+    g.A = S->dZ2.as<__bf16>();
+    g.B = S->w2n.as<__bf16>();
+    g.M = bp; g.N = kD1; g.K = kD2; g.kslice = kD2;
+    g.Zin = S->Z1.as<float>();
+    g.HT = S->dZ1T.as<__bf16>();
+    k_gemm_nt<EPI_BACK><<<dim3(bp / 64, 1, 1), 256, 0, s>>>(g);
+    MP_CHECK_LAUNCH();
+    const int nsplit = bp / kRedChunk;
+    // dW2 = H1^T dZ2 (split over samples)
+    g = GemmArgs{};
+    g.A = S->H1T.as<__bf16>();
+    g.B = S->dZ2T.as<__bf16>();
+    g.M = kD1; g.N = kD2; g.K = bp; g.kslice = kRedChunk;
+    g.out = S->pw2.as<float>();
+    k_gemm_nt<EPI_PARTIAL><<<dim3(kD1 / 64, kD2 / 128, nsplit), 256, 0, s>>>(g);
+    MP_CHECK_LAUNCH();
+    // dW1 = X^T dZ1
+    g = GemmArgs{};
+    g.A = S->XT.as<__bf16>();
+    g.B = S->dZ1T.as<__bf16>();
+    g.M = kD0; g.N = kD1; g.K = bp; g.kslice = kRedChunk;
+    g.out = S->pw1.as<float>();
+    k_gemm_nt<EPI_PARTIAL><<<dim3(kD0 / 64, kD1 / 128, nsplit), 256, 0, s>>>(g);
+    MP_CHECK_LAUNCH();
+    RedArgs R;
+    R.H2 = S->H2.as<__bf16>();
+    R.dY = S->dY.as<float4>();
+    R.sse = S->sse.as<float>();
+    R.dZ2 = S->dZ2.as<__bf16>();
+    R.dZ1T = S->dZ1T.as<__bf16>();
+    R.out = S->pl3.as<float>();
+    R.bp = bp;
+    k_reduce_small<<<nsplit, 256, 0, s>>>(R);
+    MP_CHECK_LAUNCH();
+    AdamArgs A;
+    A.P = S->P.as<float>();
+    A.Mo = S->Mo.as<float>();
+    A.Vo = S->Vo.as<float>();
+    A.G = S->G.as<float>();
+    A.pw1 = S->pw1.as<float>();
+    A.pw2 = S->pw2.as<float>();
+    A.pl3 = S->pl3.as<float>();
+    A.loss_out = loss_dev;
+    A.nsplit = nsplit;
+    A.update = update ? 1 : 0;
+    A.inv_n = (float)(1.0 / (double)n_real);
+    A.lr = lr;
+    A.beta1 = S->p.beta1;
+    A.beta2 = S->p.beta2;
+    A.eps = S->p.adam_eps;
+    const double t = (double)(S->info.steps + 1);
+    A.c1 = (float)(1.0 - std::pow((double)S->p.beta1, t));
+    A.c2 = (float)(1.0 - std::pow((double)S->p.beta2, t));
+    A.W = publish_args(S);
+    k_adam<<<(kNParams + 255) / 256, 256, 0, s>>>(A);
+    MP_CHECK_LAUNCH();
+    if (update) S->info.steps += 1;
+}
+
+void mp_sur_draw_batch(mp_surrogate S, int32_t n_real, bool full, uint32_t step, hipStream_t s) {
+    BatchArgs B;
+    B.dxyz = S->dxyz.as<float>();
+    B.dlab = S->dlab.as<float4>();
+    B.bxyz = S->bxyz.as<float>();
+    B.btgt = S->btgt.as<float4>();
+    B.n_data = S->info.n_data;
+    B.n_real = n_real;
+    B.bp = padded_rows(n_real);
+    B.full = full ? 1 : 0;
+    B.step = step;
+    B.seed = S->p.seed;
+    k_draw_batch<<<(B.bp + 255) / 256, 256, 0, s>>>(B);
+    MP_CHECK_LAUNCH();
+}
+
+void mp_sur_likelihood(mp_filter f, float* partial, hipStream_t s) {
+    mp_surrogate S = f->sur;
+    SurLikArgs A;
+    A.img = S->img.as<uint4>();
+    A.poses = f->poses[f->cur].as<float4>();
+    A.order = f->sorted.as<int32_t>();
+    A.scan = f->scan.as<float4>();
+    A.partial = partial;
+    A.n = f->n;
+    A.ns = f->scan_n;
+    A.cmax = f->p.c_max;
+    A.s_scale = S->info.s_scale;
+    A.g_scale = S->info.g_scale;
+    A.r_floor2 = 1e-4f;
+    for (int a = 0; a < 3; ++a) {
+        A.lo[a] = S->info.lo[a];
+        A.inv[a] = S->info.inv_ext[a];
+    }
+    const int blocks = std::min(num_cus(), (f->n + 3) / 4);
+    k_lik_sur<<<std::max(1, blocks), kInferThreads, 0, s>>>(A);
+    MP_CHECK_LAUNCH();
+}

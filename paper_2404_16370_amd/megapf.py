@@ -49,7 +49,25 @@ class mp_filter_params(C.Structure):
                 ("lsh_sigma", C.c_float), ("c_max", C.c_float), ("d_max", C.c_float),
                 ("lambda_rel", C.c_float), ("lambda_abs", C.c_float), ("temperature", C.c_float),
                 ("prior_floor", C.c_float), ("cov_eps", C.c_float), ("lik_chunks", C.c_int32),
-                ("lik_batch", C.c_int32), ("seed", C.c_uint64)]
+                ("lik_batch", C.c_int32), ("scorer", C.c_int32), ("sigma_s", C.c_float),
+                ("seed", C.c_uint64)]
+
+
+class mp_batch_info(C.Structure):
+    _fields_ = [("n_instances", C.c_int32), ("captures", C.c_int32), ("evals_per_step", C.c_int64)]
+
+
+class mp_surrogate_params(C.Structure):
+    _fields_ = [("box_min", C.c_float * 3), ("box_max", C.c_float * 3), ("f_max", C.c_float),
+                ("sigma_s", C.c_float), ("d_max", C.c_float), ("c_max", C.c_float), ("lr", C.c_float),
+                ("lr_min", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float), ("adam_eps", C.c_float),
+                ("total_steps", C.c_int32), ("batch", C.c_int32), ("seed", C.c_uint64)]
+
+
+class mp_surrogate_info(C.Structure):
+    _fields_ = [("n_params", C.c_int64), ("n_data", C.c_int64), ("steps", C.c_int64), ("lo", C.c_float * 3),
+                ("inv_ext", C.c_float * 3), ("freqs", C.c_float * 32), ("s_scale", C.c_float),
+                ("g_scale", C.c_float), ("weight_bytes", C.c_int32)]
 
 
 class mp_init_desc(C.Structure):
@@ -66,7 +84,14 @@ class mp_posterior(C.Structure):
 EXPORTS = ["mp_map_default_params", "mp_map_build", "mp_map_get_info", "mp_map_get_gauss", "mp_map_lookup",
            "mp_map_destroy", "mp_filter_default_params", "mp_filter_init", "mp_filter_destroy", "mp_scan_upload",
            "mp_filter_step", "mp_posterior_query", "mp_last_error", "mp_stage_times", "mp_debug_get",
-           "mp_debug_set", "mp_debug_stage"]
+           "mp_debug_set", "mp_debug_stage", "mp_surrogate_default_params", "mp_surrogate_create",
+           "mp_surrogate_destroy", "mp_surrogate_get_info", "mp_surrogate_label", "mp_surrogate_eval",
+           "mp_surrogate_set_data", "mp_surrogate_train", "mp_surrogate_grad", "mp_surrogate_get_params",
+           "mp_surrogate_set_params", "mp_filter_set_surrogate", "mp_batch_create", "mp_batch_step",
+           "mp_batch_get_info", "mp_batch_destroy"]
+
+MP_SCORER_PLAIN, MP_SCORER_SCOREFIELD, MP_SCORER_SURROGATE = 0, 1, 2
+MP_SUR_NPARAMS = 41732
 
 _lib = None
 
@@ -106,8 +131,26 @@ def lib():
     L.mp_debug_get.argtypes = [vp, C.c_char_p, vp, i64, vp]
     L.mp_debug_set.argtypes = [vp, C.c_char_p, vp, i64, vp]
     L.mp_debug_stage.argtypes = [vp, i32, i32, vp, vp, vp]
+    L.mp_surrogate_default_params.argtypes = [C.POINTER(mp_surrogate_params)]
+    L.mp_surrogate_default_params.restype = None
+    L.mp_surrogate_create.argtypes = [vp, C.POINTER(mp_surrogate_params), vp, C.POINTER(vp)]
+    L.mp_surrogate_destroy.argtypes = [vp]
+    L.mp_surrogate_get_info.argtypes = [vp, C.POINTER(mp_surrogate_info)]
+    L.mp_surrogate_label.argtypes = [vp, vp, i64, vp, vp]
+    L.mp_surrogate_eval.argtypes = [vp, vp, i64, vp, vp]
+    L.mp_surrogate_set_data.argtypes = [vp, vp, i64, vp]
+    L.mp_surrogate_train.argtypes = [vp, i32, vp, vp]
+    L.mp_surrogate_grad.argtypes = [vp, vp, vp, i64, vp, vp, vp]
+    L.mp_surrogate_get_params.argtypes = [vp, vp, vp]
+    L.mp_surrogate_set_params.argtypes = [vp, vp, vp]
+    L.mp_filter_set_surrogate.argtypes = [vp, vp]
+    L.mp_batch_create.argtypes = [vp, i32, i32, vp, C.POINTER(vp)]
+    L.mp_batch_step.argtypes = [vp, vp, vp, vp]
+    L.mp_batch_get_info.argtypes = [vp, C.POINTER(mp_batch_info), vp]
+    L.mp_batch_destroy.argtypes = [vp]
     for name in EXPORTS:
-        if name not in ("mp_map_default_params", "mp_filter_default_params", "mp_last_error"):
+        if name not in ("mp_map_default_params", "mp_filter_default_params", "mp_last_error",
+                        "mp_surrogate_default_params"):
             getattr(L, name).restype = C.c_int32
     _lib = L
     return L
@@ -277,6 +320,10 @@ class Filter:
         except Exception:
             pass
 
+    def set_surrogate(self, sur):
+        _check(lib().mp_filter_set_surrogate(self.handle, sur.handle if sur is not None else None))
+        self._sur = sur   # keeps the network alive while attached
+
     def scan_upload(self, xyz, cov6=None, stream=None):
         n = _nrows(xyz) if xyz is not None else 0
         keep = []
@@ -328,3 +375,135 @@ class Filter:
         keep = []
         _check(lib().mp_debug_stage(self.handle, stage, iteration, _ptr(dT, np.float32, keep),
                                     _ptr(cov_dT, np.float32, keep), _stream(stream)))
+
+
+# ------------------------------------------------------------------ surrogate
+def mp_surrogate_default_params(**kw):
+    p = mp_surrogate_params()
+    lib().mp_surrogate_default_params(C.byref(p))
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise KeyError(k)
+        if k in ("box_min", "box_max"):
+            for a in range(3):
+                getattr(p, k)[a] = v[a]
+        else:
+            setattr(p, k, v)
+    return p
+
+
+class Surrogate:
+    """Owner of an mp_surrogate handle (network replacing the map's per-point score)."""
+
+    def __init__(self, map_: Map, params=None, stream=None, **kw):
+        self.map = map_
+        self.params = params if params is not None else mp_surrogate_default_params(**kw)
+        h = C.c_void_p()
+        _check(lib().mp_surrogate_create(map_.handle, C.byref(self.params), _stream(stream), C.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _check(lib().mp_surrogate_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            if getattr(self, "handle", None):
+                lib().mp_surrogate_destroy(self.handle)
+                self.handle = None
+        except Exception:
+            pass
+
+    def info(self):
+        i = mp_surrogate_info()
+        _check(lib().mp_surrogate_get_info(self.handle, C.byref(i)))
+        return dict(n_params=i.n_params, n_data=i.n_data, steps=i.steps, lo=np.array(i.lo[:], np.float32),
+                    inv_ext=np.array(i.inv_ext[:], np.float32), freqs=np.array(i.freqs[:], np.float32),
+                    s_scale=i.s_scale, g_scale=i.g_scale, weight_bytes=i.weight_bytes)
+
+    def _points_call(self, fn, xyz, stream):
+        n = _nrows(xyz)
+        keep = []
+        if hasattr(xyz, "data_ptr"):
+            import torch
+            out = torch.empty((n, 4), dtype=torch.float32, device=xyz.device)
+        else:
+            out = np.zeros((n, 4), np.float32)
+        _check(fn(self.handle, _ptr(xyz, np.float32, keep), n, _ptr(out), _stream(stream)))
+        return out
+
+    def label(self, xyz, stream=None):
+        return self._points_call(lib().mp_surrogate_label, xyz, stream)
+
+    def eval(self, xyz, stream=None):
+        return self._points_call(lib().mp_surrogate_eval, xyz, stream)
+
+    def set_data(self, xyz, stream=None):
+        keep = []
+        _check(lib().mp_surrogate_set_data(self.handle, _ptr(xyz, np.float32, keep), _nrows(xyz), _stream(stream)))
+
+    def train(self, steps, losses=True, stream=None):
+        out = np.zeros(max(steps, 1), np.float32) if losses else None
+        _check(lib().mp_surrogate_train(self.handle, steps, _ptr(out), _stream(stream)))
+        return out[:steps] if losses else None
+
+    def grad(self, xyz, target4, stream=None):
+        keep = []
+        g = np.zeros(MP_SUR_NPARAMS, np.float32)
+        loss = np.zeros(1, np.float32)
+        _check(lib().mp_surrogate_grad(self.handle, _ptr(xyz, np.float32, keep), _ptr(target4, np.float32, keep),
+                                       _nrows(xyz), _ptr(g), _ptr(loss), _stream(stream)))
+        return float(loss[0]), g
+
+    def get_params(self, stream=None):
+        P = np.zeros(MP_SUR_NPARAMS, np.float32)
+        _check(lib().mp_surrogate_get_params(self.handle, _ptr(P), _stream(stream)))
+        return P
+
+    def set_params(self, P, stream=None):
+        keep = []
+        P = np.ascontiguousarray(P, np.float32)
+        if P.shape != (MP_SUR_NPARAMS,):
+            raise ValueError("expected %d parameters" % MP_SUR_NPARAMS)
+        _check(lib().mp_surrogate_set_params(self.handle, _ptr(P, np.float32, keep), _stream(stream)))
+
+
+# ------------------------------------------------------------------ batch
+class Batch:
+    """Owner of an mp_batch handle: several filters stepped by one graph replay."""
+
+    def __init__(self, filters, autotune=True, stream=None):
+        self.filters = list(filters)
+        arr = (C.c_void_p * len(self.filters))(*[f.handle.value for f in self.filters])
+        h = C.c_void_p()
+        _check(lib().mp_batch_create(arr, len(self.filters), int(bool(autotune)), _stream(stream), C.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _check(lib().mp_batch_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            if getattr(self, "handle", None):
+                lib().mp_batch_destroy(self.handle)
+                self.handle = None
+        except Exception:
+            pass
+
+    def step(self, dT=None, cov_dT=None, stream=None):
+        keep = []
+        n = len(self.filters)
+        d = None if dT is None else np.ascontiguousarray(np.asarray(dT, np.float32).reshape(n, 7))
+        c = None if cov_dT is None else np.ascontiguousarray(np.asarray(cov_dT, np.float32).reshape(n, 36))
+        _check(lib().mp_batch_step(self.handle, _ptr(d, np.float32, keep), _ptr(c, np.float32, keep),
+                                   _stream(stream)))
+
+    def info(self):
+        i = mp_batch_info()
+        lb = np.zeros(len(self.filters), np.int32)
+        _check(lib().mp_batch_get_info(self.handle, C.byref(i), _ptr(lb)))
+        return dict(n_instances=i.n_instances, captures=i.captures, evals_per_step=i.evals_per_step,
+                    lik_batch=[int(x) for x in lb])

@@ -1,0 +1,119 @@
+"""Batched multi-instance step (one HIP graph replay per step) against the
+same filters stepped one by one with mp_filter_step, through the C-ABI.
+
+Each instance has a twin built with identical parameters, initial poses and
+scans.  The batch replays its graph; the twins run eagerly; between replays
+the test reads state back (eager work on the same stream).  The graph runs the
+same kernels on the same inputs, so poses, psi, neighbour lists and posterior
+weights must agree bit for bit, for steps without prediction, with prediction
+and noise (step values uploaded to the device before each replay), with an
+odd SVGD iteration count (pose buffer copied back), with the score-field
+scorer, on a hashed map, and after a scan of another size forces a new
+capture.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+from paper_2404_16370_amd import megapf as M
+from paper_2404_16370_amd import synth as S
+
+
+@pytest.fixture(scope="module")
+def world():
+    w = S.build_workload("room", map_points=200_000, scan_points=1000, frames=4)
+    dense = M.Map(w["map_xyz"], voxel=0.5)
+    hashed = M.Map(w["map_xyz"], voxel=0.5, backend=M.MP_NNF_HASH)
+    return dict(w=w, dense=dense, hashed=hashed)
+
+
+def _poses(w, n, seed):
+    sc = w["scene"]
+    R, t = w["traj"][0]
+    P = S.uniform_particles(n - n // 2, sc.lo, sc.hi, seed)
+    G = S.gaussian_particles(n // 2, S.pose8(R, t), 0.05, 0.1, seed + 1)
+    return np.concatenate([P, G]).astype(np.float32)
+
+
+SPECS = [
+    # (map, n, svgd_iters, k, scorer, scan slice)
+    ("dense", 1000, 3, 8, M.MP_SCORER_PLAIN, slice(0, 1000)),
+    ("dense", 4096, 2, 16, M.MP_SCORER_PLAIN, slice(0, 700)),
+    ("hashed", 300, 1, 8, M.MP_SCORER_SCOREFIELD, slice(100, 900)),
+]
+
+
+def _make(world, spec, seed):
+    mp, n, iters, k, scorer, sl = spec
+    p = M.mp_filter_default_params(n_particles=n, k=k, lsh_bits=12, svgd_iters=iters, post_iters=10, window_c=16,
+                                   d_max=1.0, seed=seed, scorer=scorer)
+    f = M.Filter(world[mp], p, poses=_poses(world["w"], n, seed))
+    f.scan_upload(np.ascontiguousarray(world["w"]["scans"][0][sl]))
+    return f
+
+
+def _state(f):
+    return {k: f.debug_get(k) for k in ("poses", "psi", "nbr", "post", "prior")}
+
+
+def _assert_same(a, b, what):
+    for k in a:
+        assert np.array_equal(a[k], b[k]), "%s: %s differs" % (what, k)
+
+
+def test_batch_replay_matches_eager(world):
+    batch_f = [_make(world, s, 900 + i) for i, s in enumerate(SPECS)]
+    twins = [_make(world, s, 900 + i) for i, s in enumerate(SPECS)]
+    b = M.Batch(batch_f, autotune=True)
+    info = b.info()
+    assert info["n_instances"] == 3
+    assert set(info["lik_batch"]).issubset({2, 4, 8, 16, 0})
+    # the twins keep the default lik_batch: the grouping of gathers does not
+    # change the order of the arithmetic, so results must still agree
+    rng = np.random.default_rng(5)
+    odo = world["w"]["odometry"]
+    for step in range(4):
+        if step == 0:
+            dT = cov = None
+        else:
+            dT = np.stack([odo[1][0] for _ in SPECS]).astype(np.float32)
+            cov = np.stack([np.diag(rng.uniform(1e-5, 1e-3, 6)) for _ in SPECS]).astype(np.float32)
+        b.step(dT, cov)
+        for i, t in enumerate(twins):
+            t.step(None if dT is None else dT[i], None if cov is None else cov[i])
+        for i, (f, t) in enumerate(zip(batch_f, twins)):
+            _assert_same(_state(f), _state(t), "step %d instance %d" % (step, i))
+            qa, qb = f.posterior_query(), t.posterior_query()
+            assert qa["map_index"] == qb["map_index"] and qa["frame"] == qb["frame"] == step + 1
+    assert b.info()["captures"] == 1
+    # a scan of another size forces a new capture
+    new_scan = np.ascontiguousarray(world["w"]["scans"][1][:850])
+    batch_f[1].scan_upload(new_scan)
+    twins[1].scan_upload(new_scan)
+    b.step(None, None)
+    for t in twins:
+        t.step()
+    assert b.info()["captures"] == 2
+    for i, (f, t) in enumerate(zip(batch_f, twins)):
+        _assert_same(_state(f), _state(t), "after recapture, instance %d" % i)
+    # filters stay usable alone and cannot be destroyed while batched
+    batch_f[0].step()
+    with pytest.raises(M.MegaPFError):
+        batch_f[0].close()
+    b.close()
+    batch_f[0].close()
+
+
+def test_batch_errors(world):
+    f = M.Filter(world["dense"], M.mp_filter_default_params(n_particles=64, svgd_iters=1))
+    with pytest.raises(M.MegaPFError):
+        M.Batch([f])            # no scan yet
+    f.scan_upload(world["w"]["scans"][0][:100])
+    with pytest.raises(M.MegaPFError):
+        M.Batch([f, f])         # the same filter twice
+    b = M.Batch([f], autotune=False)
+    with pytest.raises(M.MegaPFError):
+        b.step(np.array([[1, 0, 0, 0, np.nan, 0, 0]], np.float32), None)
+    b.step(None, None)
+    b.close()
