@@ -106,7 +106,9 @@ def _declare(L):
     L.mpo_chol6.argtypes = [_f64p, _f64p]; L.mpo_chol6.restype = C.c_int
     L.mpo_predict.argtypes = [_f32p, C.c_int64, _f32p, _vp, C.c_uint64, C.c_uint32, _f64p]
     L.mpo_num_threads.restype = C.c_int
-    L.mpo_score_field.argtypes = [_vp, _f32p, C.c_int64, C.c_float, C.c_float, C.c_float, _f64p, _f64p]
+    L.mpo_score_field.argtypes = [_vp, _f32p, C.c_int64, C.c_float, C.c_float, _f64p, _f64p, _i32p]
+    L.mpo_residual_field.argtypes = [_vp, _f32p, C.c_int64, C.c_float, C.c_float, C.c_double, C.c_double, _f64p,
+                                     _f64p]
     L.mpo_bf16_round.argtypes = [C.c_double]; L.mpo_bf16_round.restype = C.c_double
     L.mpo_ff_freqs.argtypes = [C.c_float, C.c_int, _f32p]
     L.mpo_ff_features.argtypes = [_f32p, C.c_int64, _f32p, _f32p, _f32p, C.c_int, C.c_int, _f64p]
@@ -116,7 +118,8 @@ def _declare(L):
     L.mpo_mlp_loss_grad.restype = C.c_double
     L.mpo_likelihood_rank1.argtypes = [_vp, _f32p, C.c_int32, _f32p, C.c_int64, C.c_int, C.c_float, C.c_float,
                                        C.c_float, _f64p, _f32p, _f32p, _f32p, C.c_int, C.c_double, C.c_double,
-                                       C.c_double, C.c_double, C.c_double, _f64p, _f64p, _f64p, _f64p, _i32p]
+                                       C.c_double, C.c_double, C.c_double, C.c_double, _f64p, _f64p, _f64p, _f64p,
+                                       _i32p]
     L.mpo_adam.argtypes = [_f64p, _f64p, _f64p, _f64p, C.c_int64, C.c_int, C.c_double, C.c_double, C.c_double,
                            C.c_double]
 
@@ -356,13 +359,29 @@ def predict(poses8, dT, cov, seed, frame):
 
 
 # --------------------------------------------------------------------- surrogate
-def score_field(m: Map, p, sigma_s=0.03, dmax=1.0, cmax=9.0):
+def score_field(m: Map, p, sigma_s=0.03, dmax=1.0):
+    """untruncated score field: (s, grad s, inlier flag); s = grad s = 0 for outliers"""
     P = _f32(p).reshape(-1, 3)
     n = P.shape[0]
-    s = np.zeros(n); g = np.zeros((n, 3))
+    s = np.zeros(n); g = np.zeros((n, 3)); inl = np.zeros(n, np.int32)
     if n:
-        lib().mpo_score_field(m.handle, P, n, sigma_s, dmax, cmax, s, g)
-    return s, g
+        lib().mpo_score_field(m.handle, P, n, sigma_s, dmax, s, g, inl)
+    return s, g, inl.astype(bool)
+
+
+def r_out(dmax=1.0, sigma_s=0.03, eps=1e-3):
+    return float(dmax / np.sqrt(eps + np.float64(np.float32(sigma_s)) ** 2))
+
+
+def residual_field(m: Map, p, sigma_s=0.03, dmax=1.0, r_floor=1e-2, rout=None):
+    """(r, grad r): r = sqrt(s) for inliers, r_out (and grad 0) otherwise"""
+    P = _f32(p).reshape(-1, 3)
+    n = P.shape[0]
+    r = np.zeros(n); g = np.zeros((n, 3))
+    ro = r_out(dmax, sigma_s) if rout is None else rout
+    if n:
+        lib().mpo_residual_field(m.handle, P, n, sigma_s, dmax, r_floor, ro, r, g)
+    return r, g
 
 
 def bf16_round(x):
@@ -405,9 +424,10 @@ def mlp_loss_grad(params, X, T, dims=(192, 128, 128), bf16=False):
 
 
 def likelihood_rank1(m: Map, sxyz, poses8, mode, sigma_s=0.03, dmax=1.0, cmax=9.0, params=None, lo=None,
-                     inv_ext=None, freqs=None, s_scale=1.0, g_scale=1.0, r_floor=1e-2, lam_rel=1e-3,
+                     inv_ext=None, freqs=None, r_scale=1.0, g_scale=1.0, r_floor=1e-2, rout=None, lam_rel=1e-3,
                      lam_abs=1e-6):
-    """mode 1: score field scorer; mode 2: network scorer (params, lo, inv_ext, freqs)."""
+    """mode 1: residual-field scorer; mode 2: network scorer (params, lo, inv_ext, freqs)."""
+    ro = r_out(dmax, sigma_s) if rout is None else rout
     S = _f32(sxyz).reshape(-1, 3)
     P = _f32(poses8).reshape(-1, 8)
     n = P.shape[0]
@@ -421,7 +441,7 @@ def likelihood_rank1(m: Map, sxyz, poses8, mode, sigma_s=0.03, dmax=1.0, cmax=9.
         prm = np.zeros(1); fr = np.ones(32, np.float32); lo_ = np.zeros(3, np.float32); inv_ = np.ones(3, np.float32)
     if n:
         lib().mpo_likelihood_rank1(m.handle, S, S.shape[0], P, n, mode, sigma_s, dmax, cmax, prm, lo_, inv_, fr,
-                                   len(fr), s_scale, g_scale, r_floor, lam_rel, lam_abs, out["loglik"], out["H21"],
+                                   len(fr), r_scale, g_scale, r_floor, ro, lam_rel, lam_abs, out["loglik"], out["H21"],
                                    out["b"], out["psi"], out["ninl"])
     return out
 

@@ -1200,23 +1200,26 @@ MPO_API int mpo_num_threads(void) {
 /* ======================================================================= */
 /* Learned surrogate of the map's per-point score.                          */
 /*                                                                          */
-/* Score field (the surrogate's target): the per-point GICP cost with the   */
-/* scan covariance replaced by sigma_s^2 I, so it depends on position only: */
-/*   s(p) = min(e^T (Sigma^M_g + sigma_s^2 I)^-1 e, c_max) for an inlier     */
-/*   (NNF hit and |e| <= d_max, e = mu_g - p), c_max otherwise;             */
-/*   grad s = -2 Omega e for an unsaturated inlier, 0 otherwise.            */
+/* Score field: the per-point GICP cost with the scan covariance replaced   */
+/* by sigma_s^2 I, so it depends on position only.  For an inlier (NNF hit  */
+/* and |e| <= d_max, e = mu_g - p): s = e^T (Sigma^M_g + sigma_s^2 I)^-1 e,  */
+/* grad s = -2 Omega e, untruncated, as the plain path's H and b are.       */
+/* Residual field (the surrogate's target): r = sqrt(s),                    */
+/* grad r = grad s / (2 max(r, r_floor)) for an inlier; r = r_out, grad r = */
+/* 0 otherwise (r_out = d_max / sqrt(eps + sigma_s^2), the largest r inside */
+/* the gate).                                                               */
 /* Network: x~ = (p - lo) * inv_ext (FP32), 32 geometric frequencies per    */
 /* axis, features sin/cos(2 pi frac(f_l x~_a)) ordered (axis, frequency,   */
-/* sin|cos) -> 192 -> 128 -> 128 -> 4 with SiLU; outputs (s, grad s).       */
+/* sin|cos) -> 192 -> 128 -> 128 -> 4 with SiLU; outputs (r, grad r) scaled.*/
 /* ======================================================================= */
-/* score field at one FP32 point; returns 1 for an unsaturated inlier */
-static int sf_point(const mpo_map* m, const float q[3], float sigma_s, float dmax2, float cmax, double* s_out,
-                    double g_out[3]) {
+
+/* score field at one FP32 point; returns 1 for an inlier (s, grad s set) */
+static int sf_point(const mpo_map* m, const float q[3], float sigma_s, float dmax2, double* s_out, double g_out[3]) {
     double beta = 1.0 + (double)sigma_s * (double)sigma_s;
     int32_t v[3];
     for (int a = 0; a < 3; ++a) v[a] = floor_to_i32(q[a] * m->inv_r);
     int32_t g = nnf_voxel(m, v);
-    *s_out = cmax;
+    *s_out = 0.0;
     g_out[0] = g_out[1] = g_out[2] = 0.0;
     if (g < 0) return 0;
     const float* mm = m->mu + 3 * (int64_t)g;
@@ -1232,21 +1235,48 @@ static int sf_point(const mpo_map* m, const float q[3], float sigma_s, float dma
     mat3_inv(C, Om);
     double Oe[3];
     for (int a = 0; a < 3; ++a) Oe[a] = Om[3 * a] * e[0] + Om[3 * a + 1] * e[1] + Om[3 * a + 2] * e[2];
-    double c = e[0] * Oe[0] + e[1] * Oe[1] + e[2] * Oe[2];
-    if (!(c < cmax)) return 0;
-    *s_out = c;
+    *s_out = e[0] * Oe[0] + e[1] * Oe[1] + e[2] * Oe[2];
     for (int a = 0; a < 3; ++a) g_out[a] = -2.0 * Oe[a];
     return 1;
 }
 
-MPO_API void mpo_score_field(const mpo_map* m, const float* p, int64_t n, float sigma_s, float dmax, float cmax,
-                             double* s_out, double* g_out) {
+/* residual field at one FP32 point */
+static int rf_point(const mpo_map* m, const float q[3], float sigma_s, float dmax2, double r_floor, double r_out,
+                    double* r_ret, double g_ret[3]) {
+    double s, gs[3];
+    int inl = sf_point(m, q, sigma_s, dmax2, &s, gs);
+    if (!inl) {
+        *r_ret = r_out;
+        g_ret[0] = g_ret[1] = g_ret[2] = 0.0;
+        return 0;
+    }
+    double r = sqrt(s);
+    double d = 2.0 * (r > r_floor ? r : r_floor);
+    *r_ret = r;
+    for (int a = 0; a < 3; ++a) g_ret[a] = gs[a] / d;
+    return 1;
+}
+
+MPO_API void mpo_score_field(const mpo_map* m, const float* p, int64_t n, float sigma_s, float dmax, double* s_out,
+                             double* g_out, int32_t* inl_out) {
     float dmax2 = dmax * dmax;
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
         double gr[3];
-        sf_point(m, p + 3 * i, sigma_s, dmax2, cmax, &s_out[i], gr);
+        int inl = sf_point(m, p + 3 * i, sigma_s, dmax2, &s_out[i], gr);
         if (g_out) for (int a = 0; a < 3; ++a) g_out[3 * i + a] = gr[a];
+        if (inl_out) inl_out[i] = inl;
+    }
+}
+
+MPO_API void mpo_residual_field(const mpo_map* m, const float* p, int64_t n, float sigma_s, float dmax,
+                                double r_floor, double r_out, double* r_ret, double* g_ret) {
+    float dmax2 = dmax * dmax;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double gr[3];
+        rf_point(m, p + 3 * i, sigma_s, dmax2, r_floor, r_out, &r_ret[i], gr);
+        for (int a = 0; a < 3; ++a) g_ret[3 * i + a] = gr[a];
     }
 }
 
@@ -1420,18 +1450,18 @@ MPO_API void mpo_adam(double* P, const double* G, double* Mv, double* Vv, int64_
     }
 }
 
-/* Likelihood with a scalar per-point score s(p') in place of the GICP term
- * (rank-1 Gauss-Newton).  mode 1: the score field; mode 2: the network
- * (features of the FP32 point, bf16-emulating forward, outputs scaled by
- * s_scale and g_scale).  A point with s >= c_max (or outside the gate) is an
- * outlier costing c_max.  Otherwise, in FP64 with R from the quaternion:
- *   r = sqrt(max(s, r_floor^2)), w = R^T grad s, u = w / (2 r),
- *   H += [mu x u; u][mu x u; u]^T, b += [mu x w; w] / 2, loglik -= s. */
+/* Likelihood with a scalar residual r(p') per point in place of the GICP
+ * term (rank-1 Gauss-Newton).  mode 1: the residual field; mode 2: the
+ * network (features of the FP32 point, bf16-emulating forward, outputs
+ * scaled by r_scale and g_scale, r clamped at 0).  In FP64 with R from the
+ * quaternion: w = R^T grad r, g = [mu x w; w], H += g g^T, b += r g
+ * (= J_p^T grad s / 2), loglik -= min(r^2, c_max); points with r^2 < c_max
+ * are counted as inliers. */
 MPO_API void mpo_likelihood_rank1(const mpo_map* m, const float* sxyz, int32_t ns, const float* poses, int64_t n,
                                   int mode, float sigma_s, float dmax, float cmax, const double* P, const float lo[3],
-                                  const float inv_ext[3], const float* freqs, int nf, double s_scale, double g_scale,
-                                  double r_floor, double lam_rel, double lam_abs, double* loglik, double* H21,
-                                  double* b6, double* psi6, int32_t* ninl) {
+                                  const float inv_ext[3], const float* freqs, int nf, double r_scale, double g_scale,
+                                  double r_floor, double r_out, double lam_rel, double lam_abs, double* loglik,
+                                  double* H21, double* b6, double* psi6, int32_t* ninl) {
     float dmax2 = dmax * dmax;
     const int d0 = 6 * nf, d1 = 128, d2 = 128;
 #pragma omp parallel
@@ -1454,32 +1484,29 @@ MPO_API void mpo_likelihood_rank1(const mpo_map* m, const float* sxyz, int32_t n
                 const float* ms = sxyz + 3 * (int64_t)k;
                 float p32[3];
                 xform32(R32, t32, ms, p32);
-                double s, gr[3];
-                int inl;
+                double r, gr[3];
                 if (mode == 1) {
-                    inl = sf_point(m, p32, sigma_s, dmax2, cmax, &s, gr);
+                    rf_point(m, p32, sigma_s, dmax2, r_floor, r_out, &r, gr);
                 } else {
                     double* x = buf;
                     double y[4];
                     ff_point(p32, lo, inv_ext, freqs, nf, 1, x);
                     mlp_fwd1(P, d0, d1, d2, x, 1, buf + d0, buf + d0 + d1, buf + d0 + 2 * d1,
                              buf + d0 + 2 * d1 + d2, y);
-                    s = y[0] * s_scale;
+                    r = y[0] * r_scale;
+                    if (r < 0.0) r = 0.0;
                     for (int a = 0; a < 3; ++a) gr[a] = y[1 + a] * g_scale;
-                    inl = s < (double)cmax;
-                    if (s < 0.0) s = 0.0;
                 }
-                if (!inl) { ll -= (double)cmax; continue; }
-                ++ni;
-                ll -= s;
-                double r = sqrt(s > r_floor * r_floor ? s : r_floor * r_floor);
+                double s = r * r;
+                ll -= s < (double)cmax ? s : (double)cmax;
+                if (s < (double)cmax) ++ni;
                 double w[3], mu[3] = {ms[0], ms[1], ms[2]};
                 for (int a = 0; a < 3; ++a) w[a] = R[a] * gr[0] + R[3 + a] * gr[1] + R[6 + a] * gr[2];
                 double gw[6] = {mu[1] * w[2] - mu[2] * w[1], mu[2] * w[0] - mu[0] * w[2], mu[0] * w[1] - mu[1] * w[0],
                                 w[0], w[1], w[2]};
                 for (int r1 = 0; r1 < 6; ++r1) {
-                    b[r1] += 0.5 * gw[r1];
-                    for (int c1 = 0; c1 < 6; ++c1) H[6 * r1 + c1] += gw[r1] * gw[c1] / (4.0 * r * r);
+                    b[r1] += r * gw[r1];
+                    for (int c1 = 0; c1 < 6; ++c1) H[6 * r1 + c1] += gw[r1] * gw[c1];
                 }
             }
             double h21[21];

@@ -4,7 +4,9 @@
                 values 1 - a and 1 along / across the normal); central
                 differences for its gradient; against the oracle's plain
                 likelihood with an isotropic scan covariance sigma_s^2 I at the
-                identity pose (one point per call); outliers and saturation
+                identity pose (one point per call); outliers
+  residual field  r = sqrt(s), grad r = grad s / (2 max(r, floor)), r_out and
+                zero gradient outside the gate
   bf16 round    torch's float -> bfloat16 conversion (round to nearest even)
   features      numpy sin / cos of 2 pi f x in FP64 (the FP32 fractional part
                 only changes the angle by rounding); geometric frequencies
@@ -37,7 +39,7 @@ def test_score_field_closed_form(O, room):
     m, _ = room
     sig = float(np.float32(0.03))   # the oracle takes sigma_s as FP32
     p = _near_surface_points(O, m, 4000, 1)
-    s, g = O.score_field(m, p, sigma_s=sig, dmax=0.3, cmax=9.0)
+    s, g, inl = O.score_field(m, p, sigma_s=sig, dmax=0.3)
     gid = m.lookup(p)
     G = m.gauss()
     a = np.float64(np.float32(1.0) - np.float32(1e-3))
@@ -53,40 +55,54 @@ def test_score_field_closed_form(O, room):
     en = np.sum(e * nv, axis=1)
     e2 = np.sum(e * e, axis=1)
     c = en ** 2 / lam + (e2 - en ** 2) / (1.0 + sig ** 2)
-    inl = hit & (e2 <= 0.09)
+    ref_inl = hit & (e2 <= 0.09)
     # the inlier gate is an FP32 decision: skip points within rounding of it
     clear = np.abs(e2 - 0.09) > 1e-5
-    ref = np.where(inl, np.minimum(c, 9.0), 9.0)
-    assert inl.sum() > 1000 and (~inl).sum() > 300
-    assert (inl & (c < 9.0)).sum() > 300 and (inl & (c >= 9.0)).sum() > 100
-    np.testing.assert_allclose(s[clear], ref[clear], rtol=1e-9, atol=1e-12)
-    # gradient of c with respect to p: -2 Omega e
+    assert np.array_equal(inl[clear], ref_inl[clear])
+    assert ref_inl.sum() > 1000 and (~ref_inl).sum() > 300 and (ref_inl & (c > 9.0)).sum() > 100
+    k = clear & ref_inl
+    np.testing.assert_allclose(s[k], c[k], rtol=1e-9, atol=1e-12)
+    assert np.all(s[~inl] == 0) and np.all(g[~inl] == 0)
+    # gradient of c with respect to p: -2 Omega e (untruncated)
     Oe = en[:, None] * nv / lam[:, None] + (e - en[:, None] * nv) / (1.0 + sig ** 2)
-    gref = np.where((inl & (c < 9.0))[:, None], -2.0 * Oe, 0.0)
-    np.testing.assert_allclose(g[clear], gref[clear], rtol=1e-9, atol=1e-9)
+    np.testing.assert_allclose(g[k], -2.0 * Oe[k], rtol=1e-9, atol=1e-9)
 
 
 def test_score_field_gradient_fd(O, room):
     m, _ = room
     p = _near_surface_points(O, m, 3000, 2, spread=0.05).astype(np.float64)
-    s0, g0 = O.score_field(m, p, sigma_s=0.05, dmax=1.0, cmax=9.0)
+    s0, g0, i0 = O.score_field(m, p, sigma_s=0.05, dmax=1.0)
     h = 1e-3
     ok = 0
     for a in range(3):
         dp = np.zeros(3); dp[a] = h
-        sp, _ = O.score_field(m, p + dp, sigma_s=0.05, dmax=1.0, cmax=9.0)
-        sm, _ = O.score_field(m, p - dp, sigma_s=0.05, dmax=1.0, cmax=9.0)
+        sp, _, ip = O.score_field(m, p + dp, sigma_s=0.05, dmax=1.0)
+        sm, _, im = O.score_field(m, p - dp, sigma_s=0.05, dmax=1.0)
         # keep points whose voxel association and inlier state do not change inside the stencil
-        same = (m.lookup(p + dp) == m.lookup(p)) & (m.lookup(p - dp) == m.lookup(p)) & (s0 < 8.0) & \
-               (sp < 8.0) & (sm < 8.0)
+        same = (m.lookup(p + dp) == m.lookup(p)) & (m.lookup(p - dp) == m.lookup(p)) & i0 & ip & im
         fd = (sp - sm) / (2 * h)
         # the stencil is evaluated at FP32-rounded points: the FD error is
         # O(h^2) curvature plus O(ulp(p) |grad| / h)
         err = np.abs(fd[same] - g0[same, a])
-        scale = 1e-3 * (1.0 + np.abs(g0[same, a]))
-        assert np.all(err <= scale + 4e-4 * np.abs(g0[same, a]) + 2e-3), a
+        assert np.all(err <= 1e-3 * (1.0 + np.abs(g0[same, a])) + 4e-4 * np.abs(g0[same, a]) + 2e-3), a
         ok += same.sum()
     assert ok > 1000
+
+
+def test_residual_field(O, room):
+    m, _ = room
+    p = _near_surface_points(O, m, 3000, 3, spread=0.6)
+    s, g, inl = O.score_field(m, p, sigma_s=0.03, dmax=1.0)
+    ro = O.r_out(1.0, 0.03)
+    np.testing.assert_allclose(ro, 1.0 / np.sqrt(1e-3 + np.float64(np.float32(0.03)) ** 2))
+    r, gr = O.residual_field(m, p, sigma_s=0.03, dmax=1.0, r_floor=1e-2)
+    assert inl.sum() > 1000 and (~inl).sum() > 100
+    np.testing.assert_allclose(r[inl], np.sqrt(s[inl]), rtol=1e-14)
+    d = 2 * np.maximum(np.sqrt(s[inl]), 1e-2)
+    np.testing.assert_allclose(gr[inl], g[inl] / d[:, None], rtol=1e-14)
+    assert np.all(r[~inl] == ro) and np.all(gr[~inl] == 0)
+    # inside the gate r never exceeds r_out (the largest eigenvalue of Omega is 1/(eps + sigma^2))
+    assert r[inl].max() <= ro * (1 + 1e-6)
 
 
 def test_score_field_matches_plain_likelihood(O, room):
@@ -95,20 +111,25 @@ def test_score_field_matches_plain_likelihood(O, room):
     m, _ = room
     sig = np.float32(0.2)
     p = _near_surface_points(O, m, 200, 3, spread=0.3)
-    s, _ = O.score_field(m, p, sigma_s=float(sig), dmax=1.0, cmax=9.0)
+    s, _, inl = O.score_field(m, p, sigma_s=float(sig), dmax=1.0)
     T = np.array([[1, 0, 0, 0, 0, 0, 0, 0]], np.float32)
     cov = np.array([[sig * sig, 0, 0, sig * sig, 0, sig * sig]], np.float32)
+    assert inl.sum() > 100
     for i in range(len(p)):
-        out = O.likelihood(m, p[i:i + 1], cov, T, dmax=1.0, cmax=9.0)
-        # the plain path builds sigma^2 I in FP32; the score field in FP64
-        np.testing.assert_allclose(-out["loglik"][0], s[i], rtol=2e-6, atol=1e-9)
+        out = O.likelihood(m, p[i:i + 1], cov, T, dmax=1.0, cmax=1e9)
+        assert out["ninl"][0] == int(inl[i])
+        if inl[i]:
+            # the plain path builds sigma^2 I in FP32; the score field in FP64
+            np.testing.assert_allclose(-out["loglik"][0], s[i], rtol=2e-6, atol=1e-9)
 
 
 def test_score_field_far_points_are_outliers(O, room):
     m, sc = room
     far = np.array([[500.0, 500.0, 500.0], [-300.0, 0.0, 0.0]], np.float32)
-    s, g = O.score_field(m, far, cmax=9.0)
-    assert np.all(s == 9.0) and np.all(g == 0.0)
+    s, g, inl = O.score_field(m, far)
+    assert not inl.any() and np.all(g == 0.0)
+    r, gr = O.residual_field(m, far)
+    assert np.all(r == O.r_out()) and np.all(gr == 0.0)
 
 
 def test_bf16_round_matches_torch(O):
@@ -273,10 +294,10 @@ def _pose_exp(T8, xi):
 
 
 def test_rank1_scorefield_b_and_H_by_differences(O, room):
-    """Score-field scorer, single-point scans: 2 b = d(-loglik)/d delta under
-    T exp(delta) (central differences), and the rank-1 H = b b^T / s."""
+    """Residual-field scorer, single-point scans below saturation: 2 b =
+    d(-loglik)/d delta under T exp(delta) (central differences), and the
+    rank-1 H = b b^T / r^2."""
     m, _ = room
-    rng = np.random.default_rng(22)
     pts = _near_surface_points(O, m, 400, 23, spread=0.04)
     T = np.array([0.9961947, 0.0, 0.0, 0.08715574, 0.05, -0.03, 0.02, 0.0], np.float32)   # 10 deg yaw
     from _pinutil import pose_to_M
@@ -288,9 +309,9 @@ def test_rank1_scorefield_b_and_H_by_differences(O, room):
     for k in range(len(mus)):
         mu = mus[k:k + 1]
         out = O.likelihood_rank1(m, mu, T[None], 1, sigma_s=0.05, dmax=1.0, cmax=9.0)
-        if out["ninl"][0] != 1 or -out["loglik"][0] < 0.05:
-            continue
         s = -out["loglik"][0]
+        if out["ninl"][0] != 1 or s < 0.05 or s > 8.0:
+            continue
         b = out["b"][0]
         fd = np.zeros(6)
         stable = True
@@ -318,38 +339,66 @@ def test_rank1_scorefield_b_and_H_by_differences(O, room):
     assert checked >= 20
 
 
+def test_rank1_untruncated_beyond_saturation(O, room):
+    """An inlier above c_max still contributes H and b (as the plain path's
+    untruncated terms), its log-likelihood saturates at c_max, and an
+    outlier contributes nothing but -c_max."""
+    m, _ = room
+    g = m.gauss()
+    rng = np.random.default_rng(26)
+    sel = rng.integers(0, m.G, 200)
+    # 0.4 m along the normal: inside the gate, far above c_max for sigma_s = 0.03
+    p = (g["mu"][sel] + 0.4 * g["normal"][sel]).astype(np.float32)
+    T = np.array([[1, 0, 0, 0, 0, 0, 0, 0]], np.float32)
+    seen = 0
+    for i in range(len(p)):
+        s, _, inl = O.score_field(m, p[i:i + 1], sigma_s=0.03, dmax=1.0)
+        out = O.likelihood_rank1(m, p[i:i + 1], T, 1, sigma_s=0.03, dmax=1.0, cmax=9.0)
+        if inl[0] and s[0] > 9.0:
+            assert out["loglik"][0] == -9.0 and out["ninl"][0] == 0
+            assert np.abs(out["b"][0]).max() > 0 and out["H21"][0][0] + out["H21"][0][15] > 0
+            seen += 1
+        elif inl[0]:
+            np.testing.assert_allclose(out["loglik"][0], -s[0], rtol=1e-12)
+        else:
+            assert out["loglik"][0] == -9.0 and np.all(out["b"][0] == 0) and np.all(out["H21"][0] == 0)
+    assert seen > 20
+
+
 def test_rank1_network_constant_output_closed_form(O, room):
-    """Network scorer with W3 = 0: every point scores the bias b3, so
-    loglik = -ns s0, b = sum [mu x w; w] / 2 with w = R^T g, H = sum g g^T / (4 s0)."""
+    """Network scorer with W3 = 0: every point gets the bias b3, so
+    loglik = -ns min(r0^2, c_max), b = sum r0 g, H = sum g g^T with
+    g = [mu x w; w], w = R^T grad r."""
     m, _ = room
     dims = (192, 128, 128)
     n = O.mlp_nparams(*dims)
     rng = np.random.default_rng(24)
     P = rng.normal(0, 0.2, n)
     P[n - 4 - 512:n - 4] = 0.0                    # W3
-    s_scale, g_scale = 9.0, 100.0
-    s0, g = 2.25, np.array([0.3, -1.2, 0.5])
-    P[n - 4:] = [s0 / s_scale, *(g / g_scale)]    # b3 (exact in FP64; s0 / 9 rounds)
+    r_scale, g_scale = 20.0, 10.0
+    r0, gv = 1.5, np.array([0.3, -1.2, 0.5])
+    P[n - 4:] = [r0 / r_scale, *(gv / g_scale)]   # b3
     f = O.ff_freqs(40.0)
     lo = np.array([-12, -12, -2], np.float32); inv = np.full(3, 1 / 24.0, np.float32)
     mu = rng.uniform(-3, 3, (50, 3)).astype(np.float32)
     T = np.array([[0.9238795, 0.0, 0.3826834, 0.0, 1.0, 2.0, 0.5, 0.0]], np.float32)
-    out = O.likelihood_rank1(m, mu, T, 2, cmax=9.0, params=P, lo=lo, inv_ext=inv, freqs=f, s_scale=s_scale,
+    out = O.likelihood_rank1(m, mu, T, 2, cmax=9.0, params=P, lo=lo, inv_ext=inv, freqs=f, r_scale=r_scale,
                              g_scale=g_scale)
     from _pinutil import pose_to_M
     R = pose_to_M(T[0])[:3, :3]
-    w = R.T @ g
+    gvec = (P[n - 3:] * g_scale)
+    w = R.T @ gvec
     mu64 = mu.astype(np.float64)
     gw = np.concatenate([np.cross(mu64, w), np.tile(w, (50, 1))], axis=1)
-    s_eff = (s0 / s_scale) * s_scale
+    r_eff = P[n - 4] * r_scale
     assert out["ninl"][0] == 50
-    np.testing.assert_allclose(out["loglik"][0], -50 * s_eff, rtol=1e-14)
-    np.testing.assert_allclose(out["b"][0], 0.5 * gw.sum(0), rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(out["loglik"][0], -50 * r_eff ** 2, rtol=1e-13)
+    np.testing.assert_allclose(out["b"][0], r_eff * gw.sum(0), rtol=1e-12, atol=1e-12)
     H = np.zeros((6, 6)); q = 0
     for i in range(6):
         for j in range(i, 6):
             H[i, j] = H[j, i] = out["H21"][0][q]; q += 1
-    np.testing.assert_allclose(H, gw.T @ gw / (4 * s_eff), rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(H, gw.T @ gw, rtol=1e-12, atol=1e-12)
 
 
 def test_rank1_network_matches_forward_at_identity(O, room):
@@ -364,5 +413,5 @@ def test_rank1_network_matches_forward_at_identity(O, room):
     T = np.array([[1, 0, 0, 0, 0, 0, 0, 0]], np.float32)
     for k in range(len(p)):
         out = O.likelihood_rank1(m, p[k:k + 1], T, 2, cmax=1e6, params=P, lo=lo, inv_ext=inv, freqs=f,
-                                 s_scale=3.0, g_scale=1.0)
-        np.testing.assert_allclose(-out["loglik"][0], max(Y[k, 0] * 3.0, 0.0), rtol=1e-13, atol=1e-15)
+                                 r_scale=3.0, g_scale=1.0)
+        np.testing.assert_allclose(-out["loglik"][0], max(Y[k, 0] * 3.0, 0.0) ** 2, rtol=1e-13, atol=1e-15)
