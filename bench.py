@@ -25,6 +25,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "filter steps/s and particle-point evals/s at 1M particles, plain vs surrogate"
 PEAK_FP32 = 157.3e12        # MI355X FP32 vector, FLOP/s
+PEAK_BF16 = 2.5e15          # MI355X dense bf16 matrix, FLOP/s
+MLP_MACS = 192 * 128 + 128 * 128 + 128 * 4        # one network evaluation
+TRAIN_MACS = 192 * 128 * 2 + 128 * 128 * 3        # matrix-core MACs per training sample (2 forward, 3 backward GEMMs)
 PEAK_HBM = 8.0e12           # bytes/s
 # FP32 operations of one likelihood evaluation in k_lik (an fma counts 2):
 #   inlier:  transform 18, voxel key 3, residual and gate 8, R^T n and R^T e 30,
@@ -119,14 +122,305 @@ def cpu_baseline(wl, w, scan, budget_s=15.0):
             "evals_per_s": evals / dt, "map_build_s": t_map}
 
 
+def surrogate_leg(M, m, wl, minfo, scans, odo, warmup, steps):
+    """The same filter step with the network scorer (weights as initialised:
+    the step's cost does not depend on their values)."""
+    import torch
+    sur = M.Surrogate(m, M.mp_surrogate_default_params(seed=5003))
+    p = M.mp_filter_default_params(n_particles=wl["particles"], k=wl["k"], lsh_bits=wl["lsh_bits"],
+                                   svgd_iters=wl["svgd_iters"], post_iters=wl["post_iters"],
+                                   window_c=wl["window_c"], d_max=2.0 * wl["voxel"], seed=4003,
+                                   scorer=M.MP_SCORER_SURROGATE)
+    f = M.Filter(m, p, box=(minfo["box_min"], minfo["box_max"]))
+    f.set_surrogate(sur)
+
+    def run(k):
+        dT, cov = odo[k] if k > 0 else (None, None)
+        f.scan_upload(scans[k])
+        f.step(dT, cov)
+
+    for k in range(warmup):
+        run(k)
+        log("surrogate warmup step %d done" % k)
+    torch.cuda.synchronize()
+    lik_ms, lik_n = [], []
+    t0 = time.perf_counter()
+    for k in range(warmup, warmup + steps):
+        run(k)
+        st = f.stage_times()
+        lik_ms.append(st["likelihood_core"][0])
+        lik_n.append(st["likelihood_core"][1])
+        log("surrogate step %d done" % k)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    evals_iter = float(wl["particles"]) * wl["scan_points"]
+    t_launch = (sum(lik_ms) / max(sum(lik_n), 1)) * 1e-3
+    achieved = evals_iter * 2 * MLP_MACS / t_launch
+    f.set_surrogate(None)
+    res = {"steps_per_s": steps / elapsed, "evals_per_s": steps * evals_iter * wl["svgd_iters"] / elapsed,
+           "kernel": "k_lik_sur", "launch_ms": t_launch * 1e3,
+           "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_BF16 / 1e12, "unit": "TFLOP/s",
+                        "frac": achieved / PEAK_BF16, "traffic": None},
+           "weights": "initial (untrained); cost independent of values"}
+    del f
+    sur.close()
+    return res
+
+
+def train_leg(M, S, m, w, minfo, steps=50):
+    """Adam steps of the surrogate at batch 65,536 over 4M labelled samples."""
+    import torch
+    sur = M.Surrogate(m, M.mp_surrogate_default_params(seed=5004))
+    xyz = S.surrogate_samples(w["map_xyz"], minfo["box_min"], minfo["box_max"], 4_000_000, 5005)
+    sur.set_data(torch.from_numpy(xyz).cuda())
+    sur.train(3, losses=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = sur.train(steps)          # copies the losses back: synchronises
+    dt = time.perf_counter() - t0
+    batch = sur.params.batch
+    achieved = steps * batch * 2 * TRAIN_MACS / dt
+    res = {"ms_per_step": 1e3 * dt / steps, "samples_per_s": steps * batch / dt, "batch": batch,
+           "train_samples": len(xyz), "loss_first": float(losses[0]), "loss_last": float(losses[-1]),
+           "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_BF16 / 1e12, "unit": "TFLOP/s",
+                        "frac": achieved / PEAK_BF16, "traffic": None, "kernel": "whole training step"}}
+    sur.close()
+    return res
+
+
+def batch_main(args):
+    """32 independent filters on 4 scenes (2 room-type, 2 floor-type), N
+    log-uniform in [4096, 262144], scans of 1024..8192 points, stepped by one
+    graph replay per step; the same instances stepped one by one for reference."""
+    import torch
+    from paper_2404_16370_amd import megapf as M
+    from paper_2404_16370_amd import synth as S
+    torch.cuda.set_device(0)
+    rng = np.random.default_rng(5000)
+    scenes = []
+    t0 = time.perf_counter()
+    for j, (kind, seed) in enumerate((("room", 5001), ("room", 5002), ("floor", 5003), ("floor", 5004))):
+        sc = S.scene_room(seed) if kind == "room" else S.scene_floor(seed)
+        xyz = S.sample_map(sc, 200_000 if kind == "room" else 2_000_000, seed + 100)
+        r = np.random.default_rng(seed + 200)
+        pos = S.random_free_point(sc, r)
+        scan = S.make_scan(sc, S.random_rotation(r), pos, 8192, 0.02 if kind == "room" else 0.03, seed + 300)
+        m = M.Map(torch.from_numpy(xyz).cuda(), voxel=0.5)
+        scenes.append(dict(kind=kind, scene=sc, map=m, scan=scan))
+    log("scenes built in %.1f s" % (time.perf_counter() - t0))
+    n_inst = 32
+    Ns = np.exp(rng.uniform(np.log(4096), np.log(262144), n_inst)).astype(np.int64)
+    NSs = rng.integers(1024, 8193, n_inst)
+    filters = []
+    for i in range(n_inst):
+        sd = scenes[i % 4]
+        iters = 10 if sd["kind"] == "room" else 20
+        p = M.mp_filter_default_params(n_particles=int(Ns[i]), k=8 if sd["kind"] == "room" else 16,
+                                       lsh_bits=16 if sd["kind"] == "room" else 20, svgd_iters=iters, post_iters=10,
+                                       window_c=16 if sd["kind"] == "room" else 32, d_max=1.0, seed=6000 + i)
+        f = M.Filter(sd["map"], p, box=(sd["scene"].lo, sd["scene"].hi))
+        f.scan_upload(np.ascontiguousarray(sd["scan"][:int(NSs[i])]))
+        filters.append(f)
+    b = M.Batch(filters, autotune=True)
+    info = b.info()
+    evals = info["evals_per_step"]
+    for k in range(args.warmup):
+        b.step()
+    torch.cuda.synchronize()
+    log("batch warm-up done (%d captures)" % b.info()["captures"])
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        b.step()
+    torch.cuda.synchronize()
+    t_graph = (time.perf_counter() - t0) / args.steps
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        for f in filters:
+            f.step()
+    torch.cuda.synchronize()
+    t_seq = (time.perf_counter() - t0) / args.steps
+    res = {"metric": "batched multi-instance filter steps: particle-point evals/s across 32 instances",
+           "value": evals / t_graph, "unit": "evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": 1e3 * t_graph, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "batch: 32 filters on 2 room-type (200k points) and 2 floor-type (2M points) "
+                                  "maps, N log-uniform 4096..262144 (sum %d), scans 1024..8192 points, 10 / 20 "
+                                  "SVGD iterations" % int(Ns.sum())},
+           "graph_step_ms": 1e3 * t_graph, "sequential_step_ms": 1e3 * t_seq, "speedup": t_seq / t_graph,
+           "evals_per_step": evals, "lik_batch": info["lik_batch"], "captures": b.info()["captures"]}
+    b.close()
+    print(json.dumps(res), flush=True)
+
+
+def _rot_angle_deg(q_a, q_b):
+    """angle between unit quaternions (w, x, y, z), degrees"""
+    d = np.abs(np.sum(np.asarray(q_a, np.float64) * np.asarray(q_b, np.float64), axis=-1))
+    return np.degrees(2.0 * np.arccos(np.clip(d, 0.0, 1.0)))
+
+
+def surrogate_eval_main(args):
+    """Quality of the learned surrogate on the floor workload (60 x 60 x 8 m,
+    2M map points, 0.5 m voxels): held-out score error, pose error of
+    65,536-particle filters with the plain, score-field and network scorers,
+    convergence basin of single Gauss-Newton particles, mode recall, and the
+    weight footprint against the map's."""
+    import torch
+    from paper_2404_16370_amd import megapf as M
+    from paper_2404_16370_amd import synth as S
+    torch.cuda.set_device(0)
+    frames = args.frames
+    w = S.build_workload("floor", frames=frames)
+    m = M.Map(torch.from_numpy(w["map_xyz"]).cuda(), voxel=0.5)
+    minfo = m.info()
+    lo, hi = w["scene"].lo, w["scene"].hi
+    L = max(minfo["box_max"][a] - minfo["box_min"][a] for a in range(3))
+    sur = M.Surrogate(m, M.mp_surrogate_default_params(seed=5002, total_steps=args.train_steps, sigma_s=args.sigma_s,
+                                                       lr=args.lr, f_max=args.fmax_scale * L / 0.5))
+    xyz = S.surrogate_samples(w["map_xyz"], minfo["box_min"], minfo["box_max"], 4_000_000, 5006)
+    n_hold = len(xyz) // 20
+    hold, train = xyz[:n_hold], xyz[n_hold:]
+    sur.set_data(torch.from_numpy(train).cuda())
+    t0 = time.perf_counter()
+    losses = []
+    done = 0
+    while done < args.train_steps:
+        k = min(2000, args.train_steps - done)
+        losses.extend(sur.train(k).tolist())
+        done += k
+        log("trained %d / %d steps, loss %.4g" % (done, args.train_steps, losses[-1]))
+    t_train = time.perf_counter() - t0
+    lab = sur.label(hold)          # residual field (r, grad r)
+    pred = sur.eval(hold)
+    r_out = sur.info()["r_scale"]
+    dr = np.abs(pred[:, 0] - lab[:, 0])
+    gate = lab[:, 0] < r_out                       # inside the gate
+    near = gate & (lab[:, 0] ** 2 < 9.0)           # below saturation
+    gl, gp = lab[gate, 1:].astype(np.float64), pred[gate, 1:].astype(np.float64)
+    cosang = np.sum(gl * gp, 1) / (np.linalg.norm(gl, axis=1) * np.linalg.norm(gp, axis=1) + 1e-30)
+    ang = np.degrees(np.arccos(np.clip(cosang, -1, 1)))
+    ds = np.abs(np.minimum(pred[:, 0].astype(np.float64) ** 2, 9.0) - np.minimum(lab[:, 0].astype(np.float64) ** 2, 9.0))
+    quality = {"heldout_points": int(n_hold), "abs_dr_mean": float(dr.mean()), "abs_dr_p90": float(np.percentile(dr, 90)),
+               "abs_dr_mean_below_saturation": float(dr[near].mean()) if near.any() else None,
+               "abs_ds_mean (s = min(r^2, c_max))": float(ds.mean()), "abs_ds_p90": float(np.percentile(ds, 90)),
+               "grad_angle_deg_median": float(np.median(ang)), "grad_angle_deg_p90": float(np.percentile(ang, 90)),
+               "train_steps": args.train_steps, "train_s": t_train, "loss_first": losses[0],
+               "loss_last": float(np.mean(losses[-100:]))}
+
+    # filters from the same uniform start, same odometry
+    def run_filter(scorer):
+        p = M.mp_filter_default_params(n_particles=65536, k=16, lsh_bits=20, svgd_iters=20, post_iters=10,
+                                       window_c=32, d_max=1.0, seed=4002, scorer=scorer, sigma_s=args.sigma_s)
+        f = M.Filter(m, p, box=(lo, hi))
+        if scorer == M.MP_SCORER_SURROGATE:
+            f.set_surrogate(sur)
+        errs = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(frames):
+            dT, cov = w["odometry"][k]
+            f.scan_upload(w["scans"][k])
+            f.step(dT, cov)
+            q = f.posterior_query()
+            R, t = w["traj"][k]
+            gt = S.pose8(R, t)
+            errs.append((float(np.linalg.norm(q["map_pose"][4:7] - gt[4:7])),
+                         float(_rot_angle_deg(q["map_pose"][:4], gt[:4]))))
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        poses = f.debug_get("poses")
+        post = f.debug_get("post").astype(np.float64)
+        nbr = f.debug_get("nbr")
+        if scorer == M.MP_SCORER_SURROGATE:
+            f.set_surrogate(None)
+        return dict(errors=errs, s_per_frame=dt / frames, poses=poses, post=post, nbr=nbr)
+
+    runs = {name: run_filter(sc) for name, sc in (("plain", M.MP_SCORER_PLAIN),
+                                                  ("scorefield", M.MP_SCORER_SCOREFIELD),
+                                                  ("surrogate", M.MP_SCORER_SURROGATE))}
+    for name, r in runs.items():
+        log("%s: final error %.3f m %.2f deg, %.3f s/frame" % (name, r["errors"][-1][0], r["errors"][-1][1],
+                                                             r["s_per_frame"]))
+
+    def modes(r):
+        post, nbr = r["post"], r["nbr"]
+        nb = np.where(nbr >= 0, nbr, np.arange(nbr.shape[1])[None, :])
+        is_mode = (post >= 1e-3) & np.all(post[None, :] >= post[nb], axis=0)
+        return r["poses"][is_mode]
+
+    mp_, ms_ = modes(runs["plain"]), modes(runs["surrogate"])
+    hit = 0
+    for P in mp_:
+        if len(ms_) == 0:
+            break
+        dt_ = np.linalg.norm(ms_[:, 4:7] - P[4:7], axis=1)
+        da = _rot_angle_deg(ms_[:, :4], P[None, :4])
+        hit += bool(np.any((dt_ <= 0.25) & (da <= 5.0)))
+    recall = hit / len(mp_) if len(mp_) else None
+
+    # convergence basin: independent Gauss-Newton particles (K = 1) around the truth
+    R0, t0_ = w["traj"][0]
+    gt0 = S.pose8(R0, t0_)
+    rng = np.random.default_rng(7)
+    nb_ = 2000
+    dist = rng.uniform(0.5, 3.0, nb_)
+    angd = rng.uniform(5.0, 30.0, nb_)
+    dirs = rng.normal(size=(nb_, 3)); dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    axes = rng.normal(size=(nb_, 3)); axes /= np.linalg.norm(axes, axis=1, keepdims=True)
+    start = np.zeros((nb_, 8), np.float32)
+    for i in range(nb_):
+        Rp = S.rotvec_to_mat(axes[i] * np.radians(angd[i])) @ R0
+        start[i] = S.pose8(Rp, t0_ + dirs[i] * dist[i])
+    basin = {}
+    for name, sc in (("plain", M.MP_SCORER_PLAIN), ("scorefield", M.MP_SCORER_SCOREFIELD),
+                     ("surrogate", M.MP_SCORER_SURROGATE)):
+        p = M.mp_filter_default_params(n_particles=nb_, k=1, lsh_bits=8, svgd_iters=30, post_iters=0, window_c=0,
+                                       d_max=1.0, seed=4012, scorer=sc, sigma_s=args.sigma_s)
+        f = M.Filter(m, p, poses=start)
+        if sc == M.MP_SCORER_SURROGATE:
+            f.set_surrogate(sur)
+        f.scan_upload(w["scans"][0])
+        f.step()
+        P = f.debug_get("poses")
+        et = np.linalg.norm(P[:, 4:7] - gt0[4:7], axis=1)
+        ea = _rot_angle_deg(P[:, :4], gt0[None, :4])
+        basin[name] = float(np.mean((et < 0.1) & (ea < 2.0)))
+        if sc == M.MP_SCORER_SURROGATE:
+            f.set_surrogate(None)
+    fin = {k: r["errors"][-1] for k, r in runs.items()}
+    res = {"metric": "surrogate quality on the floor workload (final pose error, held-out score error)",
+           "value": fin["surrogate"][0], "unit": "m", "n_gpus": 1, "steps": frames, "warmup": 0,
+           "ms_per_step": 1e3 * runs["surrogate"]["s_per_frame"], "higher_is_better": False, "scaling": "weak",
+           "vs_baseline": None, "dtype": "bf16 network, f32 filter", "data": "synthetic",
+           "config": {"workload": "floor: 65536 particles x 4096 scan points x 20 SVGD iterations, %d frames, "
+                                  "2M map points at 0.5 m voxels; network trained on 3.8M of 4M samples" % frames,
+                      "sigma_s": args.sigma_s, "lr": args.lr, "f_max": args.fmax_scale * L / 0.5},
+           "final_error_m_deg": fin,
+           "added_error_vs_plain": {"m": fin["surrogate"][0] - fin["plain"][0],
+                                    "deg": fin["surrogate"][1] - fin["plain"][1]},
+           "per_frame_errors": {k: r["errors"] for k, r in runs.items()},
+           "s_per_frame": {k: r["s_per_frame"] for k, r in runs.items()},
+           "heldout": quality, "mode_recall": recall, "modes_plain": int(len(mp_)), "modes_surrogate": int(len(ms_)),
+           "basin_fraction": basin,
+           "footprint_bytes": {"network_image": sur.info()["weight_bytes"], "map": minfo["device_bytes"]}}
+    sur.close()
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="campus", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="campus", choices=sorted(WORKLOADS) + ["batch", "surrogate-eval"])
+    ap.add_argument("--frames", type=int, default=10, help="surrogate-eval: filter frames")
+    ap.add_argument("--train-steps", type=int, default=20000, help="surrogate-eval: Adam steps")
+    ap.add_argument("--sigma-s", type=float, default=0.03, help="surrogate-eval: sensor std of the score field")
+    ap.add_argument("--lr", type=float, default=1e-3, help="surrogate-eval: Adam step")
+    ap.add_argument("--fmax-scale", type=float, default=1.0, help="surrogate-eval: f_max in units of L / voxel")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate scorer and training legs")
+    ap.add_argument("--surrogate-steps", type=int, default=1)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 1 GiB device copy before timing (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -135,6 +429,10 @@ def main():
               "(multi-GPU sharding is a design note, not built); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
+    if args.workload == "batch":
+        return batch_main(args)
+    if args.workload == "surrogate-eval":
+        return surrogate_eval_main(args)
     import torch
     from paper_2404_16370_amd import megapf as M
     from paper_2404_16370_amd import synth as S
@@ -142,7 +440,7 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     wl = WORKLOADS[args.workload]
-    nframes = args.warmup + args.steps + 1
+    nframes = max(args.warmup + args.steps, 1 + args.surrogate_steps) + 1
     t0 = time.perf_counter()
     w = S.build_workload(args.workload, map_points=wl["map_points"], scan_points=wl["scan_points"],
                          frames=max(nframes, 2))
@@ -229,6 +527,10 @@ def main():
                      "logical_gather_GBps": evals_iter * inl_frac * GATHER_BYTES_INLIER / t_launch / 1e9},
         "posterior": {"map_weight": q["map_weight"], "n_eff": q["n_eff"], "sum_w": float(q["weights"].sum())},
     }
+    if not args.no_surrogate:
+        res["surrogate"] = surrogate_leg(M, m, wl, minfo, scans, odo, 1, args.surrogate_steps)
+        res["surrogate"]["vs_plain"] = res["surrogate"]["steps_per_s"] / steps_per_s
+        res["surrogate_training"] = train_leg(M, S, m, w, minfo)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(wl, w, w["scans"][-1], args.cpu_budget)
     print(json.dumps(res), flush=True)

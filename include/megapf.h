@@ -148,14 +148,16 @@ typedef struct {
 
 /* Per-point term of the likelihood.
  *   PLAIN       the GICP cost of Eq. (3) with full Gauss-Newton H, b (Eq. 4).
- *   SCOREFIELD  the score field s(p') = min(e^T (Sigma^M + sigma_s^2 I)^-1 e, c_max)
- *               of the transformed point (scan covariances unused), entering
- *               Gauss-Newton as the scalar residual r = sqrt(s):
- *                 H += (J^T grad r)(J^T grad r)^T,  b += J^T grad s / 2,
- *               J = dp'/d delta, grad r = grad s / (2 max(r, 1e-2)).
- *   SURROGATE   the same with s and grad s predicted by a trained network
+ *   SCOREFIELD  the residual field of the transformed point p' (scan
+ *               covariances unused): inside the gate (NNF hit, |e| <= d_max)
+ *               s = e^T (Sigma^M + sigma_s^2 I)^-1 e untruncated, r = sqrt(s),
+ *               grad r = grad s / (2 max(r, 1e-2)); outside r = r_out =
+ *               d_max / sqrt(cov_eps + sigma_s^2) and grad r = 0.  Rank-1
+ *               Gauss-Newton: g = J^T grad r (J = dp'/d delta), H += g g^T,
+ *               b += r g; log-likelihood -min(r^2, c_max).
+ *   SURROGATE   the same with r and grad r predicted by a trained network
  *               (mp_surrogate_*), attached by mp_filter_set_surrogate.
- * A point with s >= c_max (or outside the NNF gate) is an outlier costing c_max. */
+ * Points with r^2 >= c_max are counted as outliers. */
 enum { MP_SCORER_PLAIN = 0, MP_SCORER_SCOREFIELD = 1, MP_SCORER_SURROGATE = 2 };
 
 /* Defaults: k 16, lsh_bits 20, svgd_iters 10, post_iters 10, window_c 32,
@@ -314,18 +316,19 @@ MP_API mp_status mp_batch_get_info(mp_batch b, mp_batch_info* out, int32_t* lik_
 MP_API mp_status mp_batch_destroy(mp_batch b);
 
 /* ------------------------------------------------------------ surrogate */
-/* A learned replacement of the map's per-point score (the score field of
+/* A learned replacement of the map's per-point residual (the residual field of
  * MP_SCORER_SCOREFIELD) by a small network evaluated on the matrix cores:
  *   x = (p - box_min) / L, L = the box's largest extent;
  *   features sin, cos(2 pi frac(f_l x_a)), f_l = f_max^(l/31), l = 0..31,
  *   per axis a, ordered (axis, frequency, sin|cos): 192 inputs;
  *   192 -> 128 -> 128 -> 4, SiLU after the two hidden layers;
- *   outputs (s / s_scale, grad s / g_scale), s_scale = c_max,
- *   g_scale = 2 sqrt(c_max / (eps + sigma_s^2)) (the largest unsaturated
- *   gradient).
+ *   outputs (r / r_scale, grad r / g_scale) of the residual field of
+ *   MP_SCORER_SCOREFIELD, r_scale = r_out = d_max / sqrt(eps + sigma_s^2) and
+ *   g_scale = 1 / sqrt(eps + sigma_s^2) (the largest |grad r|), eps the
+ *   map's cov_eps.
  * Products take bfloat16 operands with FP32 accumulation; weights are kept
  * in FP32 (master) with bfloat16 copies; training is Adam on the mean squared
- * error of the 4 scaled outputs against score-field labels. */
+ * error of the 4 scaled outputs against residual-field labels. */
 typedef struct mp_surrogate_s* mp_surrogate;
 
 #define MP_SUR_NPARAMS 41732       /* 192*128 + 128 + 128*128 + 128 + 128*4 + 4 */
@@ -335,7 +338,7 @@ typedef struct {
     float box_min[3], box_max[3];  /* feature box; box_min == box_max: the map's voxel box */
     float f_max;          /* highest frequency, cycles per L; 0: L / voxel */
     float sigma_s;        /* score-field sensor std, metres */
-    float d_max, c_max;   /* inlier gate (0: two voxels) and saturation of the labels */
+    float d_max, c_max;   /* inlier gate (0: two voxels); c_max is kept for reference (the scorer uses the filter's) */
     float lr, lr_min;     /* Adam step, cosine-decayed from lr to lr_min over total_steps */
     float beta1, beta2, adam_eps;
     int32_t total_steps;  /* length of the cosine schedule */
@@ -349,7 +352,7 @@ typedef struct {
     int64_t steps;          /* Adam steps taken */
     float lo[3], inv_ext[3];/* feature normalisation x = (p - lo) * inv_ext (FP32) */
     float freqs[32];        /* f_l, cycles per normalised unit (FP32) */
-    float s_scale, g_scale; /* output scales */
+    float r_scale, g_scale; /* output scales */
     int32_t weight_bytes;   /* bytes of the inference image held in LDS per workgroup */
 } mp_surrogate_info;
 
@@ -368,11 +371,11 @@ MP_API mp_status mp_surrogate_destroy(mp_surrogate sur);
 
 MP_API mp_status mp_surrogate_get_info(mp_surrogate sur, mp_surrogate_info* out);
 
-/* Exact score-field labels of n points: out4 = (s, grad s) per point, n x 4
- * float, physical units (the training targets before scaling). */
+/* Exact residual-field labels of n points: out4 = (r, grad r) per point,
+ * n x 4 float, physical units (the training targets before scaling). */
 MP_API mp_status mp_surrogate_label(mp_surrogate sur, const float* xyz, int64_t n, float* out4, void* stream);
 
-/* Network prediction of n points: out4 = (s, grad s), n x 4 float, physical
+/* Network prediction of n points: out4 = (r, grad r), n x 4 float, physical
  * units, unclamped. */
 MP_API mp_status mp_surrogate_eval(mp_surrogate sur, const float* xyz, int64_t n, float* out4, void* stream);
 

@@ -781,8 +781,8 @@ extern "C" mp_status mp_surrogate_create(mp_map map, const mp_surrogate_params* 
         }
         for (int l = 0; l < 32; ++l) I.freqs[l] = (float)std::pow((double)p.f_max, (double)l / 31.0);
         const double eps = map->params.cov_eps, s2 = (double)p.sigma_s * (double)p.sigma_s;
-        I.s_scale = p.c_max;
-        I.g_scale = (float)(2.0 * std::sqrt((double)p.c_max / (eps + s2)));
+        I.r_scale = mp_residual_r_out(p.d_max, p.sigma_s, map->params.cov_eps);
+        I.g_scale = (float)(1.0 / std::sqrt(eps + s2));
         I.weight_bytes = MP_SUR_IMAGE_BYTES;
         hipStream_t s = as_stream(stream);
         mp_sur_alloc(S.get(), s);
@@ -907,7 +907,7 @@ extern "C" mp_status mp_surrogate_grad(mp_surrogate sur, const float* xyz, const
         mp_sur_ensure_batch(sur, n);
         std::vector<float> tgt(4 * (size_t)n);
         fetch_host(target4, sizeof(float) * 4 * (size_t)n, tgt.data(), s);
-        const float is = 1.0f / sur->info.s_scale, ig = 1.0f / sur->info.g_scale;
+        const float is = 1.0f / sur->info.r_scale, ig = 1.0f / sur->info.g_scale;
         for (int64_t i = 0; i < n; ++i) {
             tgt[4 * i] *= is;
             for (int a = 1; a < 4; ++a) tgt[4 * i + a] *= ig;

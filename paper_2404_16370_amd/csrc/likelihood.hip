@@ -47,7 +47,7 @@ struct LikArgs {
     float* __restrict__ partial;        // [chunk][29][N]
     int32_t n, ns, chunk_len, nchunks, nbx;
     float dmax2, cmax;
-    float sig2, ib, r_floor2;   // score-field scorer: sigma_s^2, 1 / (1 + sigma_s^2), floor of r^2
+    float sig2, ib, r_floor, r_out;   // residual-field scorer: sigma_s^2, 1 / (1 + sigma_s^2), floor of r, r outside the gate
 };
 
 __device__ inline int remap_xcd(int bid, int nb) {
@@ -140,16 +140,18 @@ __device__ __forceinline__ void accumulate(Acc& S, const mpdet::mat3& Rm, const 
     S.h[18] += o11; S.h[19] += o12; S.h[20] += o22;
 }
 
-// Score-field scorer (rank-1 Gauss-Newton on r = sqrt(s)):
-//   s = e^T Omega e, Omega = I / beta + kappa n n^T (beta = 1 + sigma_s^2,
-//   kappa = a / (beta (lam_n + sigma_s^2)), lam_n = 1 - a |n|^2 from the record),
-//   grad s = -2 Omega e (map frame), w = R^T grad s, u = w / (2 max(r, r_floor)),
-//   H += [mu x u; u][mu x u; u]^T, b += [mu x w; w] / 2.
-// A point outside the gate or with s >= c_max counts as an outlier.
+// Residual-field scorer (rank-1 Gauss-Newton on r = sqrt(s)):
+//   inside the gate (NNF hit, |e| <= d_max): s = e^T Omega e with
+//   Omega = I / beta + kappa n n^T (beta = 1 + sigma_s^2, kappa =
+//   a / (beta (lam_n + sigma_s^2)), lam_n = 1 - a |n|^2 from the record),
+//   r = sqrt(s), grad r = -Omega e / max(r, r_floor) (map frame);
+//   outside: r = r_out, grad r = 0.
+// Every point: w = R^T grad r, g = [mu x w; w], H += g g^T, b += r g,
+// log-lik -min(r^2, c_max); r^2 >= c_max counts as an outlier (cost c_max).
 __device__ __forceinline__ void accumulate_sf(Acc& S, const mpdet::mat3& Rm, const float a, const float dmax2,
                                               const float cmax, const float sig2, const float ib,
-                                              const float r_floor2, const float4 r0, const float3 p, const int32_t g,
-                                              const float4 gm, const float4 gn) {
+                                              const float r_floor, const float r_out, const float4 r0,
+                                              const float3 p, const int32_t g, const float4 gm, const float4 gn) {
     const float3 mu = make_float3(r0.x, r0.y, r0.z);
     float ex = gm.x - p.x, ey = gm.y - p.y, ez = gm.z - p.z;
     const float d2 = __builtin_fmaf(ex, ex, __builtin_fmaf(ey, ey, ez * ez));
@@ -161,45 +163,44 @@ __device__ __forceinline__ void accumulate_sf(Acc& S, const mpdet::mat3& Rm, con
     const float ne = __builtin_fmaf(gn.x, ex, __builtin_fmaf(gn.y, ey, gn.z * ez));
     const float ee = __builtin_fmaf(ex, ex, __builtin_fmaf(ey, ey, ez * ez));
     const float c = __builtin_fmaf(kap * ne, ne, ee * ib);
-    const bool inl = gate && c < cmax;
+    const float r = gate ? __builtin_sqrtf(c) : r_out;
+    const float id = gate ? 1.0f / fmaxf(r, r_floor) : 0.0f;     // grad r = -Omega e / max(r, floor)
     const float kn = kap * ne;
-    const float gx = -2.0f * __builtin_fmaf(kn, gn.x, ex * ib);
-    const float gy = -2.0f * __builtin_fmaf(kn, gn.y, ey * ib);
-    const float gz = -2.0f * __builtin_fmaf(kn, gn.z, ez * ib);
+    const float gx = -id * __builtin_fmaf(kn, gn.x, ex * ib);
+    const float gy = -id * __builtin_fmaf(kn, gn.y, ey * ib);
+    const float gz = -id * __builtin_fmaf(kn, gn.z, ez * ib);
     const float3 w = mpdet::rot_t(Rm, make_float3(gx, gy, gz));
-    const float ir = inl ? 0.5f * __builtin_amdgcn_rsqf(fmaxf(c, r_floor2)) : 0.0f;
-    const float hw = inl ? 0.5f : 0.0f;
-    const float ux = w.x * ir, uy = w.y * ir, uz = w.z * ir;
-    const float g6[6] = {mu.y * uz - mu.z * uy, mu.z * ux - mu.x * uz, mu.x * uy - mu.y * ux, ux, uy, uz};
+    const float g6[6] = {mu.y * w.z - mu.z * w.y, mu.z * w.x - mu.x * w.z, mu.x * w.y - mu.y * w.x, w.x, w.y, w.z};
     int q = 0;
 #pragma unroll
-    for (int r = 0; r < 6; ++r)
+    for (int rr = 0; rr < 6; ++rr)
 #pragma unroll
-        for (int cc = r; cc < 6; ++cc) {
-            S.h[q] = __builtin_fmaf(g6[r], g6[cc], S.h[q]);
+        for (int cc = rr; cc < 6; ++cc) {
+            S.h[q] = __builtin_fmaf(g6[rr], g6[cc], S.h[q]);
             ++q;
         }
     // b_w is kept in bw*, b_v in -oe* (the solve's partial layout stores -oe)
-    S.bw0 = __builtin_fmaf(hw, mu.y * w.z - mu.z * w.y, S.bw0);
-    S.bw1 = __builtin_fmaf(hw, mu.z * w.x - mu.x * w.z, S.bw1);
-    S.bw2 = __builtin_fmaf(hw, mu.x * w.y - mu.y * w.x, S.bw2);
-    S.oe0 = __builtin_fmaf(-hw, w.x, S.oe0);
-    S.oe1 = __builtin_fmaf(-hw, w.y, S.oe1);
-    S.oe2 = __builtin_fmaf(-hw, w.z, S.oe2);
+    S.bw0 = __builtin_fmaf(r, g6[0], S.bw0);
+    S.bw1 = __builtin_fmaf(r, g6[1], S.bw1);
+    S.bw2 = __builtin_fmaf(r, g6[2], S.bw2);
+    S.oe0 = __builtin_fmaf(-r, g6[3], S.oe0);
+    S.oe1 = __builtin_fmaf(-r, g6[4], S.oe1);
+    S.oe2 = __builtin_fmaf(-r, g6[5], S.oe2);
+    const float sq = r * r;
+    const bool below = sq < cmax;
     {
-        const float y = (inl ? c : 0.0f) - S.comp;
+        const float y = (below ? sq : 0.0f) - S.comp;
         const float tt = S.cost + y;
         S.comp = (tt - S.cost) - y;
         S.cost = tt;
     }
-    S.nout += inl ? 0.0f : 1.0f;
+    S.nout += below ? 0.0f : 1.0f;
 }
 
 // Scan points are walked in batches of BATCH per lane: first the NNF cells of
 // the whole batch are requested back to back (BATCH independent gathers in
 // flight), then the batch is evaluated with each Gaussian record fetched two
-// points ahead.  The transform is recomputed in the second pass (same
-// operations, same result) instead of being kept in registers.
+// points ahead; the transformed points of the batch stay in registers.
 template <int BACKEND, int BATCH, int SC = MP_SCORER_PLAIN>
 __global__ __launch_bounds__(kLanes) void k_lik(LikArgs A) {
     __shared__ float4 tile[kTile * 3];
@@ -244,16 +245,18 @@ __global__ __launch_bounds__(kLanes) void k_lik(LikArgs A) {
         for (int kb = 0; kb < cnt; kb += BATCH) {
             const int nbat = min(BATCH, cnt - kb);
             int32_t g[BATCH];
+            float3 pk[BATCH];   // transformed points, kept for the second pass
             // dense: g = band-grid cell (record fetched directly); hash: g = Gaussian id
             const float4* __restrict__ rec = BACKEND == MP_NNF_DENSE ? A.map.drec : gauss;
 #pragma unroll
             for (int b = 0; b < BATCH; ++b) {
                 g[b] = -1;
+                pk[b] = make_float3(0.0f, 0.0f, 0.0f);
                 if (b < nbat) {
                     const float4 r0 = tile[3 * (kb + b)];
-                    const float3 p = mpdet::xform(Rm.m, t, make_float3(r0.x, r0.y, r0.z));
-                    g[b] = BACKEND == MP_NNF_DENSE ? mp_nnf_cell(A.map, p.x, p.y, p.z)
-                                                   : mp_nnf_lookup<BACKEND>(A.map, p.x, p.y, p.z);
+                    pk[b] = mpdet::xform(Rm.m, t, make_float3(r0.x, r0.y, r0.z));
+                    g[b] = BACKEND == MP_NNF_DENSE ? mp_nnf_cell(A.map, pk[b].x, pk[b].y, pk[b].z)
+                                                   : mp_nnf_lookup<BACKEND>(A.map, pk[b].x, pk[b].y, pk[b].z);
                 }
             }
             float4 gm[BATCH], gn[BATCH];
@@ -270,11 +273,11 @@ __global__ __launch_bounds__(kLanes) void k_lik(LikArgs A) {
                 }
                 if (b < nbat) {
                     const float4 r0 = tile[3 * (kb + b)], r1 = tile[3 * (kb + b) + 1], r2 = tile[3 * (kb + b) + 2];
-                    const float3 p = mpdet::xform(Rm.m, t, make_float3(r0.x, r0.y, r0.z));
                     if (SC == MP_SCORER_SCOREFIELD)
-                        accumulate_sf(S, Rm, a, A.dmax2, A.cmax, A.sig2, A.ib, A.r_floor2, r0, p, g[b], gm[b], gn[b]);
+                        accumulate_sf(S, Rm, a, A.dmax2, A.cmax, A.sig2, A.ib, A.r_floor, A.r_out, r0, pk[b], g[b],
+                                      gm[b], gn[b]);
                     else
-                        accumulate(S, Rm, a, A.dmax2, A.cmax, r0, r1, r2, p, g[b], gm[b], gn[b]);
+                        accumulate(S, Rm, a, A.dmax2, A.cmax, r0, r1, r2, pk[b], g[b], gm[b], gn[b]);
                 }
             }
         }
@@ -459,7 +462,8 @@ void mp_launch_likelihood(mp_filter f, hipStream_t s) {
     A.cmax = f->p.c_max;
     A.sig2 = f->p.sigma_s * f->p.sigma_s;
     A.ib = 1.0f / (1.0f + A.sig2);
-    A.r_floor2 = 1e-4f;
+    A.r_floor = 1e-2f;
+    A.r_out = mp_residual_r_out(f->p.d_max, f->p.sigma_s, f->map->params.cov_eps);
     if (f->p.scorer == MP_SCORER_SURROGATE && !f->sur)
         mp_throw(MP_E_STATE, "SURROGATE scorer without a network (mp_filter_set_surrogate)");
     if (ns > 0 && f->p.scorer == MP_SCORER_SURROGATE) {

@@ -186,6 +186,11 @@ size_t mp_post_scratch_bytes(mp_filter f);
 void mp_prepare_prediction(const float dT[7], const float cov[36], float dq[7], float Lf[36], bool& noise);
 void mp_step_launches(mp_filter f, bool pred, const float dq[7], const float L[36], bool noise, hipStream_t s);
 
+// residual field outside the gate: d_max / sqrt(eps + sigma_s^2), the largest r inside it
+inline float mp_residual_r_out(float d_max, float sigma_s, float eps) {
+    return (float)((double)d_max / __builtin_sqrt((double)eps + (double)sigma_s * (double)sigma_s));
+}
+
 // surrogate (surrogate.hip)
 void mp_sur_alloc(mp_surrogate S, hipStream_t s);
 void mp_sur_init_weights(mp_surrogate S, hipStream_t s);

@@ -1,16 +1,17 @@
 // surrogate.hip -- learned surrogate of the per-point score, its training
 // step, and the scorer that evaluates it inside the likelihood.
 //
-// Target (score field): with e = mu_g - p for the NNF Gaussian g of p,
-//   s(p) = e^T (Sigma^M_g + sigma_s^2 I)^-1 e  for an inlier below c_max,
-//   grad s = -2 Omega e;  s = c_max, grad s = 0 otherwise.
+// Target (residual field): with e = mu_g - p for the NNF Gaussian g of p and
+// an inlier (|e| <= d_max), s(p) = e^T (Sigma^M_g + sigma_s^2 I)^-1 e
+// untruncated, r = sqrt(s), grad r = -Omega e / max(r, 1e-2); outside the
+// gate r = r_out = d_max / sqrt(eps + sigma_s^2) and grad r = 0.
 // Sigma^M = I - a n n^T, so with beta = 1 + sigma_s^2 and lam_n = 1 - a|n|^2
 // (kept per Gaussian in the normal record):
 //   Omega = I / beta + kappa n n^T,  kappa = a / (beta (lam_n + sigma_s^2)).
 //
 // Network: x = (p - lo) * inv_ext; features sin / cos(2 pi frac(f_l x_a)),
 // 32 geometric frequencies per axis, ordered (axis, frequency, sin|cos);
-// 192 -> 128 -> 128 -> 4 with SiLU; outputs (s / s_scale, grad s / g_scale).
+// 192 -> 128 -> 128 -> 4 with SiLU; outputs (r / r_scale, grad r / g_scale).
 // Products run on the matrix cores (v_mfma_f32_32x32x16_bf16: bfloat16
 // operands, FP32 accumulation); FP32 master weights, Adam in FP32.
 //
@@ -217,27 +218,13 @@ __device__ __forceinline__ void load_image(const uint4* __restrict__ src, uint4*
     __syncthreads();
 }
 
-// ------------------------------------------------------------ score field
-__device__ __forceinline__ bool score_point(float ex, float ey, float ez, const float4 gn, float a, float sig2,
-                                            float ib, float cmax, float& s, float& gx, float& gy, float& gz) {
-    const float kap = a / ((1.0f + sig2) * (gn.w + sig2));
-    const float ne = __builtin_fmaf(gn.x, ex, __builtin_fmaf(gn.y, ey, gn.z * ez));
-    const float ee = __builtin_fmaf(ex, ex, __builtin_fmaf(ey, ey, ez * ez));
-    const float c = __builtin_fmaf(kap * ne, ne, ee * ib);
-    const float kn = kap * ne;
-    gx = -2.0f * __builtin_fmaf(kn, gn.x, ex * ib);
-    gy = -2.0f * __builtin_fmaf(kn, gn.y, ey * ib);
-    gz = -2.0f * __builtin_fmaf(kn, gn.z, ez * ib);
-    s = c;
-    return c < cmax;
-}
-
+// ------------------------------------------------------------ residual field
 struct LabelArgs {
     MapView map;
     const float* __restrict__ xyz;
     float4* __restrict__ out;
     int64_t n;
-    float sig2, ib, dmax2, cmax, inv_s, inv_g;
+    float sig2, ib, dmax2, r_floor, r_out, inv_r, inv_g;
 };
 
 __global__ void k_label(LabelArgs A) {
@@ -245,23 +232,26 @@ __global__ void k_label(LabelArgs A) {
     if (i >= A.n) return;
     const float px = A.xyz[3 * i], py = A.xyz[3 * i + 1], pz = A.xyz[3 * i + 2];
     const int32_t g = mp_nnf_lookup<0>(A.map, px, py, pz);
-    float s = A.cmax, gx = 0.0f, gy = 0.0f, gz = 0.0f;
+    float r = A.r_out, gx = 0.0f, gy = 0.0f, gz = 0.0f;
     if (g >= 0) {
         const float4 gm = A.map.gauss[2 * (int64_t)g];
         const float4 gn = A.map.gauss[2 * (int64_t)g + 1];
         const float ex = gm.x - px, ey = gm.y - py, ez = gm.z - pz;
         const float d2 = __builtin_fmaf(ex, ex, __builtin_fmaf(ey, ey, ez * ez));
         if (d2 <= A.dmax2) {
-            float c, ux, uy, uz;
-            if (score_point(ex, ey, ez, gn, A.map.gicp_a, A.sig2, A.ib, A.cmax, c, ux, uy, uz)) {
-                s = c;
-                gx = ux;
-                gy = uy;
-                gz = uz;
-            }
+            const float kap = A.map.gicp_a / ((1.0f + A.sig2) * (gn.w + A.sig2));
+            const float ne = __builtin_fmaf(gn.x, ex, __builtin_fmaf(gn.y, ey, gn.z * ez));
+            const float ee = __builtin_fmaf(ex, ex, __builtin_fmaf(ey, ey, ez * ez));
+            const float c = __builtin_fmaf(kap * ne, ne, ee * A.ib);
+            r = __builtin_sqrtf(c);
+            const float id = 1.0f / fmaxf(r, A.r_floor);
+            const float kn = kap * ne;
+            gx = -id * __builtin_fmaf(kn, gn.x, ex * A.ib);
+            gy = -id * __builtin_fmaf(kn, gn.y, ey * A.ib);
+            gz = -id * __builtin_fmaf(kn, gn.z, ez * A.ib);
         }
     }
-    A.out[i] = make_float4(s * A.inv_s, gx * A.inv_g, gy * A.inv_g, gz * A.inv_g);
+    A.out[i] = make_float4(r * A.inv_r, gx * A.inv_g, gy * A.inv_g, gz * A.inv_g);
 }
 
 // ------------------------------------------------------------ weights
@@ -616,7 +606,7 @@ struct EvalArgs {
     float4* __restrict__ out;
     int64_t n;
     float lo[3], inv[3];
-    float s_scale, g_scale;
+    float r_scale, g_scale;
 };
 
 __global__ __launch_bounds__(kInferThreads) void k_sur_eval(EvalArgs A) {
@@ -640,7 +630,7 @@ __global__ __launch_bounds__(kInferThreads) void k_sur_eval(EvalArgs A) {
         float y[4];
         mlp64(img, xa, y);
         const int64_t k = g * 64 + 32 * h + m;
-        if (k < A.n) A.out[k] = make_float4(y[0] * A.s_scale, y[1] * A.g_scale, y[2] * A.g_scale, y[3] * A.g_scale);
+        if (k < A.n) A.out[k] = make_float4(y[0] * A.r_scale, y[1] * A.g_scale, y[2] * A.g_scale, y[3] * A.g_scale);
     }
 }
 
@@ -651,7 +641,7 @@ struct SurLikArgs {
     const float4* __restrict__ scan;    // ns x 3 float4 records (mu in the first)
     float* __restrict__ partial;        // [29][N]
     int32_t n, ns;
-    float cmax, s_scale, g_scale, r_floor2;
+    float cmax, r_scale, g_scale;
     float lo[3], inv[3];
 };
 
@@ -700,32 +690,29 @@ __global__ __launch_bounds__(kInferThreads) void k_lik_sur(SurLikArgs A) {
             }
             float y[4];
             mlp64(img, xa, y);
+            // rank-1 terms of the predicted residual: g = [mu x w; w], w = R^T grad r,
+            // H += g g^T, b += r g, cost min(r^2, c_max) (r^2 >= c_max: outlier)
             const bool valid = k0 + 32 * h + m < A.ns;
-            float s = y[0] * A.s_scale;
-            const bool inl = valid && s < A.cmax;
-            nout += (valid && !inl) ? 1.0f : 0.0f;
-            s = fmaxf(s, 0.0f);
-            const float3 w = mpdet::rot_t(Rm, make_float3(y[1] * A.g_scale, y[2] * A.g_scale, y[3] * A.g_scale));
-            const float ir = inl ? 0.5f * __builtin_amdgcn_rsqf(fmaxf(s, A.r_floor2)) : 0.0f;
-            const float hw = inl ? 0.5f : 0.0f;
-            const float ux = w.x * ir, uy = w.y * ir, uz = w.z * ir;
+            const float r = valid ? fmaxf(y[0] * A.r_scale, 0.0f) : 0.0f;
+            const float gs = valid ? A.g_scale : 0.0f;
+            const float3 w = mpdet::rot_t(Rm, make_float3(y[1] * gs, y[2] * gs, y[3] * gs));
             const float3 mu = mu_mine;
-            const float g6[6] = {mu.y * uz - mu.z * uy, mu.z * ux - mu.x * uz, mu.x * uy - mu.y * ux, ux, uy, uz};
+            const float g6[6] = {mu.y * w.z - mu.z * w.y, mu.z * w.x - mu.x * w.z, mu.x * w.y - mu.y * w.x,
+                                 w.x, w.y, w.z};
             int q = 0;
 #pragma unroll
-            for (int r = 0; r < 6; ++r)
+            for (int rr = 0; rr < 6; ++rr)
 #pragma unroll
-                for (int c = r; c < 6; ++c) {
-                    hs[q] = __builtin_fmaf(g6[r], g6[c], hs[q]);
+                for (int c = rr; c < 6; ++c) {
+                    hs[q] = __builtin_fmaf(g6[rr], g6[c], hs[q]);
                     ++q;
                 }
-            bs[0] = __builtin_fmaf(hw, mu.y * w.z - mu.z * w.y, bs[0]);
-            bs[1] = __builtin_fmaf(hw, mu.z * w.x - mu.x * w.z, bs[1]);
-            bs[2] = __builtin_fmaf(hw, mu.x * w.y - mu.y * w.x, bs[2]);
-            bs[3] = __builtin_fmaf(hw, w.x, bs[3]);
-            bs[4] = __builtin_fmaf(hw, w.y, bs[4]);
-            bs[5] = __builtin_fmaf(hw, w.z, bs[5]);
-            const float yv = (inl ? s : 0.0f) - comp;
+#pragma unroll
+            for (int k = 0; k < 6; ++k) bs[k] = __builtin_fmaf(r, g6[k], bs[k]);
+            const float sq = r * r;
+            const bool below = valid && sq < A.cmax;
+            nout += (valid && !below) ? 1.0f : 0.0f;
+            const float yv = (below ? sq : 0.0f) - comp;
             const float tv = cost + yv;
             comp = (tv - cost) - yv;
             cost = tv;
@@ -814,8 +801,9 @@ void mp_sur_label(mp_surrogate S, const float* xyz_dev, int64_t n, float* out4_d
     A.sig2 = S->p.sigma_s * S->p.sigma_s;
     A.ib = 1.0f / (1.0f + A.sig2);
     A.dmax2 = S->p.d_max * S->p.d_max;
-    A.cmax = S->p.c_max;
-    A.inv_s = scaled ? 1.0f / S->info.s_scale : 1.0f;
+    A.r_floor = 1e-2f;
+    A.r_out = S->info.r_scale;
+    A.inv_r = scaled ? 1.0f / S->info.r_scale : 1.0f;
     A.inv_g = scaled ? 1.0f / S->info.g_scale : 1.0f;
     k_label<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(A);
     MP_CHECK_LAUNCH();
@@ -832,7 +820,7 @@ void mp_sur_eval(mp_surrogate S, const float* xyz_dev, int64_t n, float* out4_de
         A.lo[a] = S->info.lo[a];
         A.inv[a] = S->info.inv_ext[a];
     }
-    A.s_scale = S->info.s_scale;
+    A.r_scale = S->info.r_scale;
     A.g_scale = S->info.g_scale;
     const int64_t groups = (n + 63) / 64;
     const int64_t blocks = std::min<int64_t>((int64_t)num_cus(), (groups + 3) / 4);
@@ -1013,9 +1001,8 @@ void mp_sur_likelihood(mp_filter f, float* partial, hipStream_t s) {
     A.n = f->n;
     A.ns = f->scan_n;
     A.cmax = f->p.c_max;
-    A.s_scale = S->info.s_scale;
+    A.r_scale = S->info.r_scale;
     A.g_scale = S->info.g_scale;
-    A.r_floor2 = 1e-4f;
     for (int a = 0; a < 3; ++a) {
         A.lo[a] = S->info.lo[a];
         A.inv[a] = S->info.inv_ext[a];

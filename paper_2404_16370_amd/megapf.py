@@ -66,7 +66,7 @@ class mp_surrogate_params(C.Structure):
 
 class mp_surrogate_info(C.Structure):
     _fields_ = [("n_params", C.c_int64), ("n_data", C.c_int64), ("steps", C.c_int64), ("lo", C.c_float * 3),
-                ("inv_ext", C.c_float * 3), ("freqs", C.c_float * 32), ("s_scale", C.c_float),
+                ("inv_ext", C.c_float * 3), ("freqs", C.c_float * 32), ("r_scale", C.c_float),
                 ("g_scale", C.c_float), ("weight_bytes", C.c_int32)]
 
 
@@ -420,7 +420,7 @@ class Surrogate:
         _check(lib().mp_surrogate_get_info(self.handle, C.byref(i)))
         return dict(n_params=i.n_params, n_data=i.n_data, steps=i.steps, lo=np.array(i.lo[:], np.float32),
                     inv_ext=np.array(i.inv_ext[:], np.float32), freqs=np.array(i.freqs[:], np.float32),
-                    s_scale=i.s_scale, g_scale=i.g_scale, weight_bytes=i.weight_bytes)
+                    r_scale=i.r_scale, g_scale=i.g_scale, weight_bytes=i.weight_bytes)
 
     def _points_call(self, fn, xyz, stream):
         n = _nrows(xyz)

@@ -587,6 +587,18 @@ WORKLOADS = {
 SEEDS = {"room": 1, "floor": 2, "campus": 3}
 
 
+def surrogate_samples(map_xyz, lo, hi, n, seed, sigma=0.25, uniform_frac=0.1) -> np.ndarray:
+    """Training positions for the score-field surrogate: map points displaced
+    by N(0, sigma^2 I) and a fraction drawn uniformly in the box [lo, hi]."""
+    rng = np.random.default_rng(seed)
+    k = int(round(n * uniform_frac))
+    sel = rng.integers(0, len(map_xyz), n - k)
+    near = map_xyz[sel].astype(np.float64) + rng.normal(0.0, sigma, (n - k, 3))
+    far = rng.uniform(np.asarray(lo, np.float64), np.asarray(hi, np.float64), (k, 3))
+    out = np.concatenate([near, far]).astype(np.float32)
+    return out[rng.permutation(n)]
+
+
 def build_workload(name, map_points=None, scan_points=None, frames=None, seed_offset=0):
     """Scene, map points, ground-truth trajectory, scans and odometry of a workload."""
     w = dict(WORKLOADS[name])
