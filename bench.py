@@ -36,7 +36,7 @@ PEAK_HBM = 8.0e12           # bytes/s
 #   outlier: transform 18, voxel key 3 (+ residual and gate 8 on an NNF hit) = 21..29
 FLOPS_INLIER = 209
 FLOPS_OUTLIER = 21
-GATHER_BYTES_INLIER = 36    # 4 B NNF cell + 32 B Gaussian record
+GATHER_BYTES = 32           # one Gaussian record of the dense NNF per evaluation (the cell index is computed)
 
 WORKLOADS = {
     "campus": dict(particles=1_048_576, scan_points=8192, svgd_iters=10, k=16, lsh_bits=24, voxel=1.0,
@@ -524,7 +524,9 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32, "traffic": measured_traffic(args.workload),
                      "kernel": "k_lik", "launch_ms": t_launch * 1e3,
-                     "logical_gather_GBps": evals_iter * inl_frac * GATHER_BYTES_INLIER / t_launch / 1e9},
+                     "logical_gather_GBps": evals_iter * GATHER_BYTES / t_launch / 1e9,
+                     "logical_gather_frac_of_hbm": evals_iter * GATHER_BYTES / t_launch / PEAK_HBM,
+                     "valu_frac_unpacked": achieved / (PEAK_FP32 / 2)},
         "posterior": {"map_weight": q["map_weight"], "n_eff": q["n_eff"], "sum_w": float(q["weights"].sum())},
     }
     if not args.no_surrogate:

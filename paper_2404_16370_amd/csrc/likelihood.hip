@@ -64,7 +64,7 @@ __device__ inline int remap_xcd(int bid, int nb) {
 struct Acc {
     float h[21];
     float bw0, bw1, bw2, oe0, oe1, oe2;
-    float cost, comp, nout;
+    float cost, comp, nout;   // compensated (Kahan) sum of the per-point costs
 };
 
 __device__ __forceinline__ void accumulate(Acc& S, const mpdet::mat3& Rm, const float a, const float dmax2,

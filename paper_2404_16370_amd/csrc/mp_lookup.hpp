@@ -32,11 +32,20 @@ __device__ __forceinline__ int32_t mp_nnf_lookup(const MapView& v, float px, flo
     }
 }
 
+// floor to int32 in one instruction (saturating outside the int32 range);
+// for |z| >= 2^30 both this and the clamped floor put the point outside any
+// band grid (|origin| < 2^30, extent < 2^30), so the lookup decisions agree
+__device__ __forceinline__ int32_t floor_cell(float z) {
+    int32_t r;
+    asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(z));
+    return r;
+}
+
 // dense band-grid cell of floor(p * 1/r), or -1 outside the grid's box
 __device__ __forceinline__ int32_t mp_nnf_cell(const MapView& v, float px, float py, float pz) {
-    const uint32_t x = (uint32_t)mpdet::floor_i32(px * v.inv_r) - (uint32_t)v.org[0];
-    const uint32_t y = (uint32_t)mpdet::floor_i32(py * v.inv_r) - (uint32_t)v.org[1];
-    const uint32_t z = (uint32_t)mpdet::floor_i32(pz * v.inv_r) - (uint32_t)v.org[2];
+    const uint32_t x = (uint32_t)floor_cell(px * v.inv_r) - (uint32_t)v.org[0];
+    const uint32_t y = (uint32_t)floor_cell(py * v.inv_r) - (uint32_t)v.org[1];
+    const uint32_t z = (uint32_t)floor_cell(pz * v.inv_r) - (uint32_t)v.org[2];
     if (x >= (uint32_t)v.dim[0] || y >= (uint32_t)v.dim[1] || z >= (uint32_t)v.dim[2]) return -1;
     return (int32_t)((z * (uint32_t)v.dim[1] + y) * (uint32_t)v.dim[0] + x);
 }

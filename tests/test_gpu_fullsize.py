@@ -5,7 +5,10 @@ one by one:
   bit-exact   map Gaussians (ids, voxels, means, normals), LSH codes of all
               particles, the complete bucket order and bounds, neighbour lists
               of 2048 sampled particles
-  1e-4 rel    log-likelihoods of 256 sampled particles (inlier counts exact)
+  1e-4 rel    log-likelihoods of 256 sampled particles (inlier counts exact);
+              H within 1e-4 of max|H| and b within 1e-4 of sqrt(H_ii sum c)
+              per particle: the plain FP32 sums over all 8192 points of a
+              lane (one chunk) against the FP64 oracle
   property    posterior weights sum to 1 and the MAP weight is the largest
 """
 import numpy as np
@@ -67,13 +70,26 @@ def test_campus_stages(campus, O):
     assert np.array_equal(nbr[pick], nref[pick])
     assert np.array_equal(f.debug_get("cnt")[pick], cref[pick])
     # likelihood of 256 sampled particles, scan covariances as the library computed them from the scan
+    f.debug_set("capture_hb", 1)
     f.debug_stage(M.MP_STAGE_LIK)
     psi = f.debug_get("psi")
+    hb = f.debug_get("hb")
     _, scov, _ = O.scan_cov(scan, k=10)
     pick = rng.choice(N, 256, replace=False)
     lk = O.likelihood(campus["ora"], scan, scov, poses[pick], dmax=2.0, cmax=9.0)
     assert np.array_equal(psi[pick, 7].astype(np.int64), lk["ninl"].astype(np.int64))
     assert np.all(np.abs(psi[pick, 6] - lk["loglik"]) <= 1e-4 * np.abs(lk["loglik"]) + 1e-3)
+    H = hb[pick, :21].astype(np.float64)
+    b = hb[pick, 21:27].astype(np.float64)
+    hn = np.abs(lk["H21"]).max(1, keepdims=True) + 1e-12
+    herr = np.abs(H - lk["H21"]) / hn
+    unt = O.likelihood(campus["ora"], scan, scov, poses[pick], dmax=2.0, cmax=1e9)
+    cost = (-unt["loglik"] - 1e9 * (NS - unt["ninl"]))[:, None]
+    diag = lk["H21"][:, [0, 6, 11, 15, 18, 20]]
+    berr = np.abs(b - lk["b"]) / (np.sqrt(np.maximum(diag, 0) * np.maximum(cost, 0)) + 1e-9)
+    print("full size, FP32 sums over 8192 points: max H error %.2e of max|H|, max b error %.2e of its scale"
+          % (herr.max(), berr.max()), flush=True)
+    assert herr.max() <= 1e-4 and berr.max() <= 1e-4
     # full step: posterior is a distribution with its MAP on top
     f.step()
     q = f.posterior_query(weights=True)
