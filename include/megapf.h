@@ -141,6 +141,7 @@ typedef struct {
     float cov_eps;        /* GICP epsilon for scan covariances */
     int32_t lik_chunks;   /* scan-point chunks per particle tile in the likelihood launch; 0 = auto */
     int32_t lik_batch;    /* scan points whose NNF cells are requested together per lane: 1..32 (power of 2), 0 = 4 */
+    int32_t lik_layout;   /* MP_LIK_LAYOUT_*: lanes per particle in the likelihood launch */
     int32_t scorer;       /* MP_SCORER_*: per-point term of the likelihood */
     float sigma_s;        /* MP_SCORER_SCOREFIELD: isotropic sensor std of the score field, metres */
     uint64_t seed;        /* Philox4x32-10 key */
@@ -160,11 +161,20 @@ typedef struct {
  * Points with r^2 >= c_max are counted as outliers. */
 enum { MP_SCORER_PLAIN = 0, MP_SCORER_SCOREFIELD = 1, MP_SCORER_SURROGATE = 2 };
 
+/* Likelihood launch layout (results agree to rounding; the choice is speed):
+ *   PARTICLE  one lane per particle, 256 particles per workgroup, scan tiles
+ *             broadcast from LDS (suits few particles or short scans);
+ *   GROUPED   16 lanes per particle walking consecutive scan points, so a
+ *             wave's gathers fall in a few compact clusters of map cells;
+ *             scan chunks of 1024 points held in LDS (lik_chunks ignored);
+ *   AUTO      GROUPED when N >= 2048 and the scan has >= 512 points. */
+enum { MP_LIK_LAYOUT_AUTO = 0, MP_LIK_LAYOUT_PARTICLE = 1, MP_LIK_LAYOUT_GROUPED = 2 };
+
 /* Defaults: k 16, lsh_bits 20, svgd_iters 10, post_iters 10, window_c 32,
  * scan_k 10, sigma_r 5, sigma_t 2.5, lsh_alpha 1, lsh_sigma 0.3, c_max 9,
  * d_max 1.0, lambda_rel 1e-3, lambda_abs 1e-6, temperature 1,
- * prior_floor 1e-30, cov_eps 1e-3, lik_chunks 0, lik_batch 4, scorer PLAIN,
- * sigma_s 0.03, seed 1. */
+ * prior_floor 1e-30, cov_eps 1e-3, lik_chunks 0, lik_batch 4, lik_layout AUTO,
+ * scorer PLAIN, sigma_s 0.03, seed 1. */
 MP_API void mp_filter_default_params(mp_filter_params* p);
 
 enum { MP_INIT_UNIFORM_BOX = 0, MP_INIT_EXPLICIT = 1 };

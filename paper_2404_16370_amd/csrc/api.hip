@@ -265,6 +265,7 @@ static void validate_params(const mp_filter_params& p) {
         p.lik_batch != 16 && p.lik_batch != 32)
         mp_throw(MP_E_ARG, "lik_batch must be 0, 1, 2, 4, 8, 16 or 32");
     if (p.scorer < MP_SCORER_PLAIN || p.scorer > MP_SCORER_SURROGATE) mp_throw(MP_E_ARG, "unknown scorer");
+    if (p.lik_layout < MP_LIK_LAYOUT_AUTO || p.lik_layout > MP_LIK_LAYOUT_GROUPED) mp_throw(MP_E_ARG, "unknown lik_layout");
     if (!std::isfinite(p.sigma_s) || !(p.sigma_s > 0.0f)) mp_throw(MP_E_ARG, "sigma_s must be positive");
 }
 

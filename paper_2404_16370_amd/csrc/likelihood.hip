@@ -297,6 +297,120 @@ __global__ __launch_bounds__(kLanes) void k_lik(LikArgs A) {
     out[28 * st] = S.nout;
 }
 
+// Grouped layout: 16 lanes per particle.  A workgroup (8 waves) keeps a
+// chunk of 1024 scan records in LDS and takes 256 LSH-sorted particles, 32 at
+// a time; the 16 lanes of a particle walk its points with stride 16, so one
+// gather instruction of a wave touches the records of 4 particles x 16
+// consecutive (Morton-ordered) scan points: a few compact clusters of cells
+// instead of 64 scattered ones.  The 29 sums of a particle are reduced across
+// its 16 lanes by shuffles and written per (chunk, sorted position).
+constexpr int kGLanes = 16;
+constexpr int kGChunk = 1024;
+constexpr int kGThreads = 512;
+constexpr int kGParticles = 256;
+
+template <int BACKEND, int BATCH, int SC>
+__global__ __launch_bounds__(kGThreads) void k_lik_grp(LikArgs A) {
+    __shared__ float4 tile[kGChunk * 3];
+    const int nb = A.nbx * A.nchunks;
+    const int logical = remap_xcd(blockIdx.x, nb);
+    const int chunk = logical / A.nbx;
+    const int pblk = logical - chunk * A.nbx;
+    const int k0 = chunk * kGChunk;
+    const int cnt = min(kGChunk, A.ns - k0);
+    for (int j = threadIdx.x; j < cnt * 3; j += kGThreads) {
+        float4 v = A.scan[(size_t)k0 * 3 + j];
+        // fold the identity of Sigma^M = I - a n n^T into the scan covariance
+        const int c = j % 3;
+        if (c == 0) v.w += 1.0f;
+        else if (c == 1) v.z += 1.0f;
+        else v.x += 1.0f;
+        tile[j] = v;
+    }
+    __syncthreads();
+    const int grp = threadIdx.x / kGLanes;   // particle slot in the workgroup (0..31)
+    const int gl = threadIdx.x % kGLanes;    // lane within the particle's group
+    const float a = A.map.gicp_a;
+    const float4* __restrict__ rec = BACKEND == MP_NNF_DENSE ? A.map.drec : A.map.gauss;
+    constexpr int kSlots = kGThreads / kGLanes;
+    for (int round = 0; round < kGParticles / kSlots; ++round) {
+        const int sp = pblk * kGParticles + round * kSlots + grp;   // sorted position
+        int i = sp < A.n ? (A.order ? A.order[sp] : sp) : 0;
+        const bool active = sp < A.n && i >= 0 && i < A.n;
+        if (!active) i = 0;
+        const float4 q4 = A.poses[2 * i];
+        const float4 t4 = A.poses[2 * i + 1];
+        const mpdet::mat3 Rm = mpdet::qmat(mpdet::quat{q4.x, q4.y, q4.z, q4.w});
+        const float3 t = make_float3(t4.x, t4.y, t4.z);
+        Acc S;
+#pragma unroll
+        for (int m = 0; m < 21; ++m) S.h[m] = 0.0f;
+        S.bw0 = S.bw1 = S.bw2 = S.oe0 = S.oe1 = S.oe2 = 0.0f;
+        S.cost = S.comp = S.nout = 0.0f;
+        for (int kb = 0; kb < cnt; kb += kGLanes * BATCH) {
+            int32_t g[BATCH];
+            float3 pk[BATCH];
+            bool ok[BATCH];
+#pragma unroll
+            for (int b = 0; b < BATCH; ++b) {
+                const int k = kb + gl + kGLanes * b;
+                ok[b] = active && k < cnt;
+                g[b] = -1;
+                pk[b] = make_float3(0.0f, 0.0f, 0.0f);
+                if (ok[b]) {
+                    const float4 r0 = tile[3 * k];
+                    pk[b] = mpdet::xform(Rm.m, t, make_float3(r0.x, r0.y, r0.z));
+                    g[b] = BACKEND == MP_NNF_DENSE ? mp_nnf_cell(A.map, pk[b].x, pk[b].y, pk[b].z)
+                                                   : mp_nnf_lookup<BACKEND>(A.map, pk[b].x, pk[b].y, pk[b].z);
+                }
+            }
+            float4 gm[BATCH], gn[BATCH];
+#pragma unroll
+            for (int b = 0; b < 2 && b < BATCH; ++b) {
+                gm[b] = rec[2 * (size_t)max(g[b], 0)];
+                gn[b] = rec[2 * (size_t)max(g[b], 0) + 1];
+            }
+#pragma unroll
+            for (int b = 0; b < BATCH; ++b) {
+                if (b + 2 < BATCH) {
+                    gm[b + 2] = rec[2 * (size_t)max(g[b + 2], 0)];
+                    gn[b + 2] = rec[2 * (size_t)max(g[b + 2], 0) + 1];
+                }
+                if (ok[b]) {
+                    const int k = kb + gl + kGLanes * b;
+                    const float4 r0 = tile[3 * k], r1 = tile[3 * k + 1], r2 = tile[3 * k + 2];
+                    if (SC == MP_SCORER_SCOREFIELD)
+                        accumulate_sf(S, Rm, a, A.dmax2, A.cmax, A.sig2, A.ib, A.r_floor, A.r_out, r0, pk[b], g[b],
+                                      gm[b], gn[b]);
+                    else
+                        accumulate(S, Rm, a, A.dmax2, A.cmax, r0, r1, r2, pk[b], g[b], gm[b], gn[b]);
+                }
+            }
+        }
+        // the group's 16 partial sums, combined by a butterfly within the group
+        float v[kNumPartial];
+#pragma unroll
+        for (int m = 0; m < 21; ++m) v[m] = S.h[m];
+        v[21] = S.bw0;
+        v[22] = S.bw1;
+        v[23] = S.bw2;
+        v[24] = -S.oe0;
+        v[25] = -S.oe1;
+        v[26] = -S.oe2;
+        v[27] = S.cost - S.comp;
+        v[28] = S.nout;
+#pragma unroll
+        for (int m = 0; m < kNumPartial; ++m)
+#pragma unroll
+            for (int off = kGLanes / 2; off >= 1; off >>= 1) v[m] += __shfl_xor(v[m], off, 64);
+        if (gl == 0 && active) {
+            float* out = A.partial + (size_t)chunk * kNumPartial * A.n + sp;
+#pragma unroll
+            for (int m = 0; m < kNumPartial; ++m) out[(size_t)m * A.n] = v[m];
+        }
+    }
+}
+
 template <int BACKEND>
 void launch_lik_batch(int batch, unsigned grid, hipStream_t s, const LikArgs& A) {
     switch (batch) {
@@ -312,6 +426,7 @@ void launch_lik_batch(int batch, unsigned grid, hipStream_t s, const LikArgs& A)
 
 struct SolveArgs {
     const float* __restrict__ partial;
+    const int32_t* __restrict__ order;   // partials indexed by sorted position (or null: by particle)
     float4* __restrict__ psi;   // N x 2 float4: (psi0..3), (psi4, psi5, loglik, inliers)
     float* __restrict__ hb;     // N x 28 or null
     int32_t* __restrict__ flags; // [0]: FP64 re-solves
@@ -373,8 +488,10 @@ __device__ bool chol_solve6(const T Hs[21], const T b[6], T lam_rel, T lam_abs, 
 }
 
 __global__ __launch_bounds__(256) void k_solve(SolveArgs A) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= A.n) return;
+    const int col = blockIdx.x * blockDim.x + threadIdx.x;   // partial column
+    if (col >= A.n) return;
+    const int i = A.order ? A.order[col] : col;
+    if (i < 0 || i >= A.n) return;
     // compensated sum of the chunk partials
     float v[kNumPartial], c[kNumPartial];
 #pragma unroll
@@ -383,7 +500,7 @@ __global__ __launch_bounds__(256) void k_solve(SolveArgs A) {
         c[m] = 0.0f;
     }
     for (int ch = 0; ch < A.nchunks; ++ch) {
-        const float* src = A.partial + (size_t)ch * kNumPartial * A.n + i;
+        const float* src = A.partial + (size_t)ch * kNumPartial * A.n + col;
 #pragma unroll
         for (int m = 0; m < kNumPartial; ++m) {
             const float y = src[(size_t)m * A.n] - c[m];
@@ -417,10 +534,21 @@ __global__ __launch_bounds__(256) void k_solve(SolveArgs A) {
 
 }  // namespace
 
+// layout of the likelihood launch: lane per particle, or 16 lanes per particle
+static bool lik_grouped(mp_filter f) {
+    if (f->p.lik_layout == MP_LIK_LAYOUT_PARTICLE) return false;
+    if (f->p.lik_layout == MP_LIK_LAYOUT_GROUPED) return true;
+    return f->n >= 2048 && f->scan_n >= 512;
+}
+
 // scan-point chunks per particle tile and the chunk length
 static int lik_chunks(mp_filter f, int& clen) {
     const int n = f->n;
     const int ns = std::max(0, f->scan_n);
+    if (lik_grouped(f)) {
+        clen = kGChunk;
+        return std::max(1, (ns + kGChunk - 1) / kGChunk);
+    }
     const int nbx = (n + kLanes - 1) / kLanes;
     int nch = f->p.lik_chunks;
     if (nch <= 0) {
@@ -441,7 +569,8 @@ size_t mp_lik_partial_bytes(mp_filter f) {
 void mp_launch_likelihood(mp_filter f, hipStream_t s) {
     const int n = f->n;
     const int ns = f->scan_n;
-    const int nbx = (n + kLanes - 1) / kLanes;
+    const bool grouped = lik_grouped(f) && f->p.scorer != MP_SCORER_SURROGATE;
+    const int nbx = grouped ? (n + kGParticles - 1) / kGParticles : (n + kLanes - 1) / kLanes;
     int clen = 0;
     int nch = lik_chunks(f, clen);
     f->lik_chunks = nch;
@@ -473,6 +602,25 @@ void mp_launch_likelihood(mp_filter f, hipStream_t s) {
         mp_tick(f, MP_STAGE_LIK_CORE, true, s);
         mp_sur_likelihood(f, A.partial, s);
         mp_tick(f, MP_STAGE_LIK_CORE, false, s);
+    } else if (ns > 0 && grouped) {
+        mp_tick(f, MP_STAGE_LIK_CORE, true, s);
+        const unsigned grid = (unsigned)(A.nbx * nch);
+        const bool dense = A.map.backend == MP_NNF_DENSE;
+        if (f->p.scorer == MP_SCORER_SCOREFIELD) {
+            if (dense) k_lik_grp<MP_NNF_DENSE, 4, MP_SCORER_SCOREFIELD><<<grid, kGThreads, 0, s>>>(A);
+            else k_lik_grp<MP_NNF_HASH, 4, MP_SCORER_SCOREFIELD><<<grid, kGThreads, 0, s>>>(A);
+        } else if (f->p.lik_batch == 8) {
+            if (dense) k_lik_grp<MP_NNF_DENSE, 8, MP_SCORER_PLAIN><<<grid, kGThreads, 0, s>>>(A);
+            else k_lik_grp<MP_NNF_HASH, 8, MP_SCORER_PLAIN><<<grid, kGThreads, 0, s>>>(A);
+        } else if (f->p.lik_batch == 2) {
+            if (dense) k_lik_grp<MP_NNF_DENSE, 2, MP_SCORER_PLAIN><<<grid, kGThreads, 0, s>>>(A);
+            else k_lik_grp<MP_NNF_HASH, 2, MP_SCORER_PLAIN><<<grid, kGThreads, 0, s>>>(A);
+        } else {
+            if (dense) k_lik_grp<MP_NNF_DENSE, 4, MP_SCORER_PLAIN><<<grid, kGThreads, 0, s>>>(A);
+            else k_lik_grp<MP_NNF_HASH, 4, MP_SCORER_PLAIN><<<grid, kGThreads, 0, s>>>(A);
+        }
+        MP_CHECK_LAUNCH();
+        mp_tick(f, MP_STAGE_LIK_CORE, false, s);
     } else if (ns > 0 && f->p.scorer == MP_SCORER_SCOREFIELD) {
         mp_tick(f, MP_STAGE_LIK_CORE, true, s);
         if (A.map.backend == MP_NNF_DENSE)
@@ -493,6 +641,7 @@ void mp_launch_likelihood(mp_filter f, hipStream_t s) {
     }
     SolveArgs S;
     S.partial = f->partial.as<float>();
+    S.order = (grouped && ns > 0) ? f->sorted.as<int32_t>() : nullptr;
     S.psi = f->psi.as<float4>();
     S.hb = f->capture_hb ? f->hb.as<float>() : nullptr;
     S.flags = f->flags.as<int32_t>();

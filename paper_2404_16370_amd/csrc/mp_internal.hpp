@@ -81,6 +81,7 @@ struct mp_surrogate_s {
     DevMem bxyz, btgt, X, XT, Z1, H1, H1T, Z2, H2, dY, sse, dZ2, dZ2T, dZ1T;
     DevMem pw1, pw2, pl3;           // split-K and chunk partial sums
     DevMem losses;                  // per-step loss (float)
+    int cus = 1;                    // compute units of the device (persistent-grid size)
     int users = 0;
 };
 

@@ -517,34 +517,57 @@ struct RedArgs {
     int32_t bp;
 };
 
-__global__ __launch_bounds__(256) void k_reduce_small(RedArgs A) {
-    const int b0 = blockIdx.x * kRedChunk;
+__device__ __forceinline__ float wave_sum64(float v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// One thread per sample of the chunk; each sum is reduced across the wave by
+// shuffles, then the 8 wave partials are added in a fixed order.
+constexpr int kRedThreads = kRedChunk;
+__global__ __launch_bounds__(kRedThreads) void k_reduce_small(RedArgs A) {
+    __shared__ float red[kRedThreads / 64][kL3Len];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int b = blockIdx.x * kRedChunk + threadIdx.x;
+    const float4 d = A.dY[b];
+    const bf16x8* h2 = reinterpret_cast<const bf16x8*>(A.H2 + (size_t)b * kD2);
+    const bf16x8* z2 = reinterpret_cast<const bf16x8*>(A.dZ2 + (size_t)b * kD2);
+    for (int c8 = 0; c8 < kD2 / 8; ++c8) {
+        const bf16x8 hv = h2[c8], zv = z2[c8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int j = 8 * c8 + q;
+            const float h = (float)hv[q];
+            const float w0 = wave_sum64(h * d.x), w1 = wave_sum64(h * d.y);
+            const float w2 = wave_sum64(h * d.z), w3 = wave_sum64(h * d.w);
+            const float s2 = wave_sum64((float)zv[q]);
+            const float s1 = wave_sum64((float)A.dZ1T[(size_t)j * A.bp + b]);
+            if (lane == 0) {
+                red[wv][kL3W3 + 4 * j] = w0;
+                red[wv][kL3W3 + 4 * j + 1] = w1;
+                red[wv][kL3W3 + 4 * j + 2] = w2;
+                red[wv][kL3W3 + 4 * j + 3] = w3;
+                red[wv][kL3B2 + j] = s2;
+                red[wv][kL3B1 + j] = s1;
+            }
+        }
+    }
+    const float e0 = wave_sum64(d.x), e1 = wave_sum64(d.y), e2 = wave_sum64(d.z), e3 = wave_sum64(d.w);
+    const float se = wave_sum64(A.sse[b]);
+    if (lane == 0) {
+        red[wv][kL3B3] = e0;
+        red[wv][kL3B3 + 1] = e1;
+        red[wv][kL3B3 + 2] = e2;
+        red[wv][kL3B3 + 3] = e3;
+        red[wv][kL3SSE] = se;
+    }
+    __syncthreads();
     float* o = A.out + (size_t)blockIdx.x * kL3Len;
     for (int item = threadIdx.x; item < kL3Len; item += blockDim.x) {
         float acc = 0.0f;
-        if (item < kL3B3) {
-            const int j = item >> 2, c = item & 3;
-            for (int b = b0; b < b0 + kRedChunk; ++b) {
-                const float4 d = A.dY[b];
-                const float dv = c == 0 ? d.x : (c == 1 ? d.y : (c == 2 ? d.z : d.w));
-                acc = __builtin_fmaf((float)A.H2[(size_t)b * kD2 + j], dv, acc);
-            }
-        } else if (item < kL3B2) {
-            const int c = item - kL3B3;
-            for (int b = b0; b < b0 + kRedChunk; ++b) {
-                const float4 d = A.dY[b];
-                acc += c == 0 ? d.x : (c == 1 ? d.y : (c == 2 ? d.z : d.w));
-            }
-        } else if (item < kL3B1) {
-            const int j = item - kL3B2;
-            for (int b = b0; b < b0 + kRedChunk; ++b) acc += (float)A.dZ2[(size_t)b * kD2 + j];
-        } else if (item < kL3SSE) {
-            const int j = item - kL3B1;
-            const __bf16* row = A.dZ1T + (size_t)j * A.bp;
-            for (int b = b0; b < b0 + kRedChunk; ++b) acc += (float)row[b];
-        } else {
-            for (int b = b0; b < b0 + kRedChunk; ++b) acc += A.sse[b];
-        }
+#pragma unroll
+        for (int w = 0; w < kRedThreads / 64; ++w) acc += red[w][item];
         o[item] = acc;
     }
 }
@@ -759,6 +782,7 @@ PublishArgs publish_args(mp_surrogate S) {
 
 // ------------------------------------------------------------ host launchers
 void mp_sur_alloc(mp_surrogate S, hipStream_t s) {
+    S->cus = num_cus();
     S->P.alloc(sizeof(float) * kNParams);
     S->Mo.alloc(sizeof(float) * kNParams);
     S->Vo.alloc(sizeof(float) * kNParams);
@@ -823,7 +847,7 @@ void mp_sur_eval(mp_surrogate S, const float* xyz_dev, int64_t n, float* out4_de
     A.r_scale = S->info.r_scale;
     A.g_scale = S->info.g_scale;
     const int64_t groups = (n + 63) / 64;
-    const int64_t blocks = std::min<int64_t>((int64_t)num_cus(), (groups + 3) / 4);
+    const int64_t blocks = std::min<int64_t>((int64_t)S->cus, (groups + 3) / 4);
     k_sur_eval<<<(unsigned)std::max<int64_t>(1, blocks), kInferThreads, 0, s>>>(A);
     MP_CHECK_LAUNCH();
 }
@@ -947,7 +971,7 @@ void mp_sur_grad_step(mp_surrogate S, int32_t n_real, bool update, float lr, flo
     R.dZ1T = S->dZ1T.as<__bf16>();
     R.out = S->pl3.as<float>();
     R.bp = bp;
-    k_reduce_small<<<nsplit, 256, 0, s>>>(R);
+    k_reduce_small<<<nsplit, kRedThreads, 0, s>>>(R);
     MP_CHECK_LAUNCH();
     AdamArgs A;
     A.P = S->P.as<float>();
@@ -1007,7 +1031,7 @@ void mp_sur_likelihood(mp_filter f, float* partial, hipStream_t s) {
         A.lo[a] = S->info.lo[a];
         A.inv[a] = S->info.inv_ext[a];
     }
-    const int blocks = std::min(num_cus(), (f->n + 3) / 4);
+    const int blocks = std::min(S->cus, (f->n + 3) / 4);   // no device query: this may run under graph capture
     k_lik_sur<<<std::max(1, blocks), kInferThreads, 0, s>>>(A);
     MP_CHECK_LAUNCH();
 }

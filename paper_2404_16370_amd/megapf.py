@@ -49,7 +49,7 @@ class mp_filter_params(C.Structure):
                 ("lsh_sigma", C.c_float), ("c_max", C.c_float), ("d_max", C.c_float),
                 ("lambda_rel", C.c_float), ("lambda_abs", C.c_float), ("temperature", C.c_float),
                 ("prior_floor", C.c_float), ("cov_eps", C.c_float), ("lik_chunks", C.c_int32),
-                ("lik_batch", C.c_int32), ("scorer", C.c_int32), ("sigma_s", C.c_float),
+                ("lik_batch", C.c_int32), ("lik_layout", C.c_int32), ("scorer", C.c_int32), ("sigma_s", C.c_float),
                 ("seed", C.c_uint64)]
 
 
@@ -91,6 +91,7 @@ EXPORTS = ["mp_map_default_params", "mp_map_build", "mp_map_get_info", "mp_map_g
            "mp_batch_get_info", "mp_batch_destroy"]
 
 MP_SCORER_PLAIN, MP_SCORER_SCOREFIELD, MP_SCORER_SURROGATE = 0, 1, 2
+MP_LIK_LAYOUT_AUTO, MP_LIK_LAYOUT_PARTICLE, MP_LIK_LAYOUT_GROUPED = 0, 1, 2
 MP_SUR_NPARAMS = 41732
 
 _lib = None

@@ -7,8 +7,9 @@ the test reads state back (eager work on the same stream).  The graph runs the
 same kernels on the same inputs, so poses, psi, neighbour lists and posterior
 weights must agree bit for bit, for steps without prediction, with prediction
 and noise (step values uploaded to the device before each replay), with an
-odd SVGD iteration count (pose buffer copied back), with the score-field
-scorer, on a hashed map, and after a scan of another size forces a new
+odd SVGD iteration count (pose buffer copied back), with the residual-field
+scorer, with the network scorer (its likelihood kernel captured in the
+graph), on a hashed map, and after a scan of another size forces a new
 capture.
 """
 import numpy as np
@@ -25,7 +26,8 @@ def world():
     w = S.build_workload("room", map_points=200_000, scan_points=1000, frames=4)
     dense = M.Map(w["map_xyz"], voxel=0.5)
     hashed = M.Map(w["map_xyz"], voxel=0.5, backend=M.MP_NNF_HASH)
-    return dict(w=w, dense=dense, hashed=hashed)
+    sur = M.Surrogate(dense, M.mp_surrogate_default_params(seed=11))
+    return dict(w=w, dense=dense, hashed=hashed, sur=sur)
 
 
 def _poses(w, n, seed):
@@ -41,6 +43,7 @@ SPECS = [
     ("dense", 1000, 3, 8, M.MP_SCORER_PLAIN, slice(0, 1000)),
     ("dense", 4096, 2, 16, M.MP_SCORER_PLAIN, slice(0, 700)),
     ("hashed", 300, 1, 8, M.MP_SCORER_SCOREFIELD, slice(100, 900)),
+    ("dense", 500, 2, 8, M.MP_SCORER_SURROGATE, slice(0, 300)),
 ]
 
 
@@ -49,6 +52,8 @@ def _make(world, spec, seed):
     p = M.mp_filter_default_params(n_particles=n, k=k, lsh_bits=12, svgd_iters=iters, post_iters=10, window_c=16,
                                    d_max=1.0, seed=seed, scorer=scorer)
     f = M.Filter(world[mp], p, poses=_poses(world["w"], n, seed))
+    if scorer == M.MP_SCORER_SURROGATE:
+        f.set_surrogate(world["sur"])
     f.scan_upload(np.ascontiguousarray(world["w"]["scans"][0][sl]))
     return f
 
@@ -67,7 +72,7 @@ def test_batch_replay_matches_eager(world):
     twins = [_make(world, s, 900 + i) for i, s in enumerate(SPECS)]
     b = M.Batch(batch_f, autotune=True)
     info = b.info()
-    assert info["n_instances"] == 3
+    assert info["n_instances"] == len(SPECS)
     assert set(info["lik_batch"]).issubset({2, 4, 8, 16, 0})
     # the twins keep the default lik_batch: the grouping of gathers does not
     # change the order of the arithmetic, so results must still agree
@@ -103,6 +108,9 @@ def test_batch_replay_matches_eager(world):
         batch_f[0].close()
     b.close()
     batch_f[0].close()
+    for f in batch_f[1:] + twins:
+        f.set_surrogate(None)
+        f.close()
 
 
 def test_batch_errors(world):

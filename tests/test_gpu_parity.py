@@ -97,17 +97,28 @@ def test_uniform_init_bitexact(room, O):
     assert np.array_equal(P, ref)
 
 
-@pytest.mark.parametrize("n,chunks,batch,backend", [(1000, 0, 0, M.MP_NNF_DENSE), (1000, 1, 4, M.MP_NNF_DENSE),
-                                                     (257, 3, 32, M.MP_NNF_DENSE), (1, 0, 8, M.MP_NNF_DENSE),
-                                                     (1000, 0, 0, M.MP_NNF_HASH), (300, 2, 4, M.MP_NNF_HASH)])
-def test_likelihood_parity(room, O, n, chunks, batch, backend):
+P_, G_ = M.MP_LIK_LAYOUT_PARTICLE, M.MP_LIK_LAYOUT_GROUPED
+
+
+@pytest.mark.parametrize("n,chunks,batch,backend,layout,nscan", [
+    (1000, 0, 0, M.MP_NNF_DENSE, P_, 1000), (1000, 1, 4, M.MP_NNF_DENSE, P_, 1000),
+    (257, 3, 32, M.MP_NNF_DENSE, P_, 1000), (1, 0, 8, M.MP_NNF_DENSE, P_, 1000),
+    (1000, 0, 0, M.MP_NNF_HASH, P_, 1000), (300, 2, 4, M.MP_NNF_HASH, P_, 1000),
+    # grouped layout: chunks of 1024 points (2 chunks, ragged), partials by sorted position
+    (1000, 0, 0, M.MP_NNF_DENSE, G_, 1700), (257, 0, 8, M.MP_NNF_DENSE, G_, 1700), (1, 0, 2, M.MP_NNF_DENSE, G_, 1000),
+    (300, 0, 4, M.MP_NNF_HASH, G_, 1700)])
+def test_likelihood_parity(room, O, n, chunks, batch, backend, layout, nscan):
     w = room["w"]
     scan = w["scans"][0]
+    if nscan > len(scan):
+        # a longer scan: the first points again, shifted by 1 cm so that no point repeats exactly
+        extra = scan[:nscan - len(scan)] + np.float32(0.01)
+        scan = np.ascontiguousarray(np.concatenate([scan, extra]).astype(np.float32))
     _, scov, _ = O.scan_cov(scan, k=10)
     poses = _poses_mixed(w, n, 10 + n)
     gmap = room["gpu"] if backend == M.MP_NNF_DENSE else M.Map(w["map_xyz"], voxel=0.5, backend=backend)
     assert gmap.info()["backend"] == backend
-    f2 = M.Filter(gmap, _params(n, lik_chunks=chunks, lik_batch=batch), poses=poses)
+    f2 = M.Filter(gmap, _params(n, lik_chunks=chunks, lik_batch=batch, lik_layout=layout), poses=poses)
     f2.scan_upload(scan, cov6=scov)
     f2.debug_set("capture_hb", 1)
     f2.debug_stage(M.MP_STAGE_LIK)

@@ -159,6 +159,7 @@ def test_training_reduces_loss(room):
 
 
 def _lik_filter(room, n, poses, scan, scorer, **kw):
+    kw.setdefault("lik_layout", M.MP_LIK_LAYOUT_AUTO)
     p = M.mp_filter_default_params(n_particles=n, k=8, lsh_bits=16, svgd_iters=1, post_iters=10, window_c=16,
                                    d_max=1.0, c_max=9.0, seed=4001, scorer=scorer, sigma_s=0.03, **kw)
     f = M.Filter(room["gpu"], p, poses=poses)
@@ -190,12 +191,13 @@ def _check_hb(hb, ref, unt_cost, tol_h, tol_b):
     assert np.all(np.abs(b - ref["b"]) <= tol_b * bscale)
 
 
-@pytest.mark.parametrize("n", [300, 1])
-def test_scorefield_likelihood(room, O, n):
+@pytest.mark.parametrize("n,layout", [(300, M.MP_LIK_LAYOUT_PARTICLE), (1, M.MP_LIK_LAYOUT_PARTICLE),
+                                      (300, M.MP_LIK_LAYOUT_GROUPED)])
+def test_scorefield_likelihood(room, O, n, layout):
     w = room["w"]
     scan = w["scans"][0]
     poses = _poses(w, n, 11)
-    psi, hb = _lik_filter(room, n, poses, scan, M.MP_SCORER_SCOREFIELD)
+    psi, hb = _lik_filter(room, n, poses, scan, M.MP_SCORER_SCOREFIELD, lik_layout=layout)
     ref = O.likelihood_rank1(room["ora"], scan, poses, 1, sigma_s=0.03, dmax=1.0, cmax=9.0)
     unt = -O.likelihood_rank1(room["ora"], scan, poses, 1, sigma_s=0.03, dmax=1.0, cmax=1e30)["loglik"]
     ninl = psi[:, 7].astype(np.int64)
