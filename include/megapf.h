@@ -308,9 +308,11 @@ typedef struct {
     int64_t evals_per_step;  /* particle-point evaluations of one batch step */
 } mp_batch_info;
 
-/* autotune != 0 times the likelihood launch of each instance for lik_batch in
- * {2, 4, 8, 16} and keeps the fastest (it changes only how gathers are grouped,
- * not the arithmetic).  Every filter needs a scan uploaded.  Errors: MP_E_ARG,
+/* autotune != 0 times the likelihood launch of each instance for every
+ * (lik_layout, lik_batch) candidate (PARTICLE with 2, 4, 8, 16; GROUPED with
+ * 2, 4, 8) and keeps the fastest in the instance's parameters (speed only:
+ * the per-point arithmetic is the same; sums are ordered differently by the
+ * two layouts).  Every filter needs a scan uploaded.  Errors: MP_E_ARG,
  * MP_E_STATE (no scan, a filter given twice, SURROGATE scorer without a network). */
 MP_API mp_status mp_batch_create(const mp_filter* filters, int32_t n, int32_t autotune, void* stream, mp_batch* out);
 
@@ -320,8 +322,8 @@ MP_API mp_status mp_batch_create(const mp_filter* filters, int32_t n, int32_t au
  * values have been copied. */
 MP_API mp_status mp_batch_step(mp_batch b, const float* dT, const float* cov_dT, void* stream);
 
-/* lik_batch_out (nullable): n chosen lik_batch values. */
-MP_API mp_status mp_batch_get_info(mp_batch b, mp_batch_info* out, int32_t* lik_batch_out);
+/* lik_batch_out, lik_layout_out (nullable): the n instances' values in use. */
+MP_API mp_status mp_batch_get_info(mp_batch b, mp_batch_info* out, int32_t* lik_batch_out, int32_t* lik_layout_out);
 
 MP_API mp_status mp_batch_destroy(mp_batch b);
 

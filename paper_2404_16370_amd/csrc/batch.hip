@@ -37,7 +37,7 @@ struct mp_batch_s {
         const void* red;
         const void* hist;
         mp_surrogate sur;
-        int32_t lik_batch;
+        int32_t lik_batch, lik_layout;
         bool operator!=(const Shape& o) const { return std::memcmp(this, &o, sizeof(Shape)) != 0; }
     };
     std::vector<Shape> shape;
@@ -70,6 +70,7 @@ mp_batch_s::Shape shape_of(mp_filter f) {
     s.hist = f->hist.p;
     s.sur = f->sur;
     s.lik_batch = f->p.lik_batch;
+    s.lik_layout = f->p.lik_layout;
     return s;
 }
 
@@ -130,18 +131,25 @@ void capture(mp_batch b, hipStream_t caller) {
     b->captures++;
 }
 
+// time the likelihood launch of each (layout, gather batch) candidate and keep
+// the fastest; both choices change speed only (same per-point arithmetic)
 void autotune(mp_filter f, hipStream_t s) {
     if (f->scan_n <= 0 || f->p.scorer != MP_SCORER_PLAIN) return;
     hipEvent_t e0, e1;
     MP_HIP(hipEventCreate(&e0));
     MP_HIP(hipEventCreate(&e1));
-    const int32_t keep = f->p.lik_batch;
-    int32_t best = keep;
+    const int32_t keep_b = f->p.lik_batch, keep_l = f->p.lik_layout;
+    int32_t best_b = keep_b, best_l = keep_l;
     float best_ms = 1e30f;
+    static const int32_t cand[][2] = {{MP_LIK_LAYOUT_PARTICLE, 2}, {MP_LIK_LAYOUT_PARTICLE, 4},
+                                      {MP_LIK_LAYOUT_PARTICLE, 8}, {MP_LIK_LAYOUT_PARTICLE, 16},
+                                      {MP_LIK_LAYOUT_GROUPED, 2},  {MP_LIK_LAYOUT_GROUPED, 4},
+                                      {MP_LIK_LAYOUT_GROUPED, 8}};
     try {
-        for (int32_t c : {2, 4, 8, 16}) {
-            f->p.lik_batch = c;
-            mp_launch_likelihood(f, s);   // warm-up
+        for (const auto& c : cand) {
+            f->p.lik_layout = c[0];
+            f->p.lik_batch = c[1];
+            mp_launch_likelihood(f, s);   // warm-up (sizes the partial buffer)
             MP_HIP(hipEventRecord(e0, s));
             mp_launch_likelihood(f, s);
             mp_launch_likelihood(f, s);
@@ -151,27 +159,24 @@ void autotune(mp_filter f, hipStream_t s) {
             MP_HIP(hipEventElapsedTime(&ms, e0, e1));
             if (ms < best_ms) {
                 best_ms = ms;
-                best = c;
+                best_l = c[0];
+                best_b = c[1];
             }
         }
     } catch (...) {
-        f->p.lik_batch = keep;
+        f->p.lik_batch = keep_b;
+        f->p.lik_layout = keep_l;
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         throw;
     }
-    f->p.lik_batch = best;
+    f->p.lik_batch = best_b;
+    f->p.lik_layout = best_l;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
 }
 
 }  // namespace
-
-extern "C" mp_status mp_batch_create(const mp_filter* filters, int32_t n, int32_t tune, void* stream,
-                                     mp_batch* out);
-extern "C" mp_status mp_batch_step(mp_batch b, const float* dT, const float* cov_dT, void* stream);
-extern "C" mp_status mp_batch_get_info(mp_batch b, mp_batch_info* out, int32_t* lik_batch_out);
-extern "C" mp_status mp_batch_destroy(mp_batch b);
 
 mp_status mp_guarded_call(const char* where, void (*fn)(void*), void* ctx);
 
@@ -290,6 +295,7 @@ struct InfoCtx {
     mp_batch b;
     mp_batch_info* out;
     int32_t* lb;
+    int32_t* ll;
 };
 void info_impl(void* p) {
     InfoCtx& c = *static_cast<InfoCtx*>(p);
@@ -301,6 +307,7 @@ void info_impl(void* p) {
         mp_filter f = c.b->f[i];
         ev += (int64_t)f->n * std::max(0, f->scan_n) * f->p.svgd_iters;
         if (c.lb) c.lb[i] = f->p.lik_batch;
+        if (c.ll) c.ll[i] = f->p.lik_layout;
     }
     c.out->evals_per_step = ev;
 }
@@ -312,8 +319,9 @@ void destroy_impl(void* p) {
 }
 }  // namespace
 
-extern "C" mp_status mp_batch_get_info(mp_batch b, mp_batch_info* out, int32_t* lik_batch_out) {
-    InfoCtx c{b, out, lik_batch_out};
+extern "C" mp_status mp_batch_get_info(mp_batch b, mp_batch_info* out, int32_t* lik_batch_out,
+                                       int32_t* lik_layout_out) {
+    InfoCtx c{b, out, lik_batch_out, lik_layout_out};
     return mp_guarded_call("mp_batch_get_info", info_impl, &c);
 }
 

@@ -147,7 +147,7 @@ def lib():
     L.mp_filter_set_surrogate.argtypes = [vp, vp]
     L.mp_batch_create.argtypes = [vp, i32, i32, vp, C.POINTER(vp)]
     L.mp_batch_step.argtypes = [vp, vp, vp, vp]
-    L.mp_batch_get_info.argtypes = [vp, C.POINTER(mp_batch_info), vp]
+    L.mp_batch_get_info.argtypes = [vp, C.POINTER(mp_batch_info), vp, vp]
     L.mp_batch_destroy.argtypes = [vp]
     for name in EXPORTS:
         if name not in ("mp_map_default_params", "mp_filter_default_params", "mp_last_error",
@@ -505,6 +505,7 @@ class Batch:
     def info(self):
         i = mp_batch_info()
         lb = np.zeros(len(self.filters), np.int32)
-        _check(lib().mp_batch_get_info(self.handle, C.byref(i), _ptr(lb)))
+        ll = np.zeros(len(self.filters), np.int32)
+        _check(lib().mp_batch_get_info(self.handle, C.byref(i), _ptr(lb), _ptr(ll)))
         return dict(n_instances=i.n_instances, captures=i.captures, evals_per_step=i.evals_per_step,
-                    lik_batch=[int(x) for x in lb])
+                    lik_batch=[int(x) for x in lb], lik_layout=[int(x) for x in ll])

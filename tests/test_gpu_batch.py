@@ -47,10 +47,10 @@ SPECS = [
 ]
 
 
-def _make(world, spec, seed):
+def _make(world, spec, seed, **kw):
     mp, n, iters, k, scorer, sl = spec
     p = M.mp_filter_default_params(n_particles=n, k=k, lsh_bits=12, svgd_iters=iters, post_iters=10, window_c=16,
-                                   d_max=1.0, seed=seed, scorer=scorer)
+                                   d_max=1.0, seed=seed, scorer=scorer, **kw)
     f = M.Filter(world[mp], p, poses=_poses(world["w"], n, seed))
     if scorer == M.MP_SCORER_SURROGATE:
         f.set_surrogate(world["sur"])
@@ -69,13 +69,14 @@ def _assert_same(a, b, what):
 
 def test_batch_replay_matches_eager(world):
     batch_f = [_make(world, s, 900 + i) for i, s in enumerate(SPECS)]
-    twins = [_make(world, s, 900 + i) for i, s in enumerate(SPECS)]
     b = M.Batch(batch_f, autotune=True)
     info = b.info()
     assert info["n_instances"] == len(SPECS)
     assert set(info["lik_batch"]).issubset({2, 4, 8, 16, 0})
-    # the twins keep the default lik_batch: the grouping of gathers does not
-    # change the order of the arithmetic, so results must still agree
+    print("autotuned (layout, batch):", list(zip(info["lik_layout"], info["lik_batch"])))
+    # twins with the layout the tuner picked (the gather batch does not change
+    # the order of the arithmetic; the layout does)
+    twins = [_make(world, s, 900 + i, lik_layout=info["lik_layout"][i]) for i, s in enumerate(SPECS)]
     rng = np.random.default_rng(5)
     odo = world["w"]["odometry"]
     for step in range(4):
