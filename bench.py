@@ -188,6 +188,9 @@ def train_leg(M, S, m, w, minfo, steps=50):
     return res
 
 
+LAYOUT_NAMES = {0: "auto", 1: "particle", 2: "grouped"}
+
+
 def batch_main(args):
     """32 independent filters on 4 scenes (2 room-type, 2 floor-type), N
     log-uniform in [4096, 262144], scans of 1024..8192 points, stepped by one
@@ -247,7 +250,10 @@ def batch_main(args):
                                   "maps, N log-uniform 4096..262144 (sum %d), scans 1024..8192 points, 10 / 20 "
                                   "SVGD iterations" % int(Ns.sum())},
            "graph_step_ms": 1e3 * t_graph, "sequential_step_ms": 1e3 * t_seq, "speedup": t_seq / t_graph,
-           "evals_per_step": evals, "lik_batch": info["lik_batch"], "captures": b.info()["captures"]}
+           "evals_per_step": evals, "lik_batch": info["lik_batch"],
+           "lik_layout": [LAYOUT_NAMES.get(v, str(v)) for v in info["lik_layout"]],
+           "particles": [int(v) for v in Ns], "scan_points": [int(v) for v in NSs],
+           "captures": b.info()["captures"]}
     b.close()
     print(json.dumps(res), flush=True)
 
