@@ -68,7 +68,9 @@ typedef struct {
     int32_t min_points; /* voxels holding fewer map points are dropped, >= 3 */
     float cov_eps;      /* GICP normalisation: Sigma = I - (1 - eps) n n^T, 0 < eps <= 1 */
     int32_t backend;    /* MP_NNF_*: open-addressing voxel hash map or dense grid;
-                           AUTO picks DENSE when the band grid has <= 2^28 cells */
+                           AUTO picks DENSE when the band grid has <= 2^26 cells and
+                           < 2^24 cells per z plane; DENSE beyond 2^27 - 2 cells or
+                           2^24 per plane fails with MP_E_UNSUPPORTED */
 } mp_map_params;
 
 typedef struct {
@@ -140,7 +142,8 @@ typedef struct {
     float prior_floor;    /* prior probabilities below this are raised to it */
     float cov_eps;        /* GICP epsilon for scan covariances */
     int32_t lik_chunks;   /* scan-point chunks per particle tile in the likelihood launch; 0 = auto */
-    int32_t lik_batch;    /* scan points whose NNF cells are requested together per lane: 1..32 (power of 2), 0 = 4 */
+    int32_t lik_batch;    /* scan points whose NNF cells are requested together per lane: 1..32 (power of 2);
+                             0 = 4 in the PARTICLE layout, 2 in the GROUPED one (GROUPED takes 2, 4 or 8) */
     int32_t lik_layout;   /* MP_LIK_LAYOUT_*: lanes per particle in the likelihood launch */
     int32_t scorer;       /* MP_SCORER_*: per-point term of the likelihood */
     float sigma_s;        /* MP_SCORER_SCOREFIELD: isotropic sensor std of the score field, metres */
@@ -173,7 +176,7 @@ enum { MP_LIK_LAYOUT_AUTO = 0, MP_LIK_LAYOUT_PARTICLE = 1, MP_LIK_LAYOUT_GROUPED
 /* Defaults: k 16, lsh_bits 20, svgd_iters 10, post_iters 10, window_c 32,
  * scan_k 10, sigma_r 5, sigma_t 2.5, lsh_alpha 1, lsh_sigma 0.3, c_max 9,
  * d_max 1.0, lambda_rel 1e-3, lambda_abs 1e-6, temperature 1,
- * prior_floor 1e-30, cov_eps 1e-3, lik_chunks 0, lik_batch 4, lik_layout AUTO,
+ * prior_floor 1e-30, cov_eps 1e-3, lik_chunks 0, lik_batch 0, lik_layout AUTO,
  * scorer PLAIN, sigma_s 0.03, seed 1. */
 MP_API void mp_filter_default_params(mp_filter_params* p);
 

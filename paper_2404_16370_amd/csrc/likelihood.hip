@@ -58,59 +58,75 @@ __device__ inline int remap_xcd(int bid, int nb) {
 }
 
 // One scan point against the lane's particle, given the (possibly missed)
-// Gaussian record; accumulates into the lane's sums.  Outliers are counted
-// (each costs c_max in the solve) and add nothing to the cost sum, H or b
-// (selected, not branched).
+// Gaussian record; accumulates into the lane's sums.  Outliers add nothing to
+// the cost sum, H or b and are not counted as inliers (each costs c_max in the
+// solve: outliers = points - inliers).  Nothing is branched: an outlier's mean
+// is replaced by 0 in the Jacobian and its Omega, cost and b terms are
+// multiplied or selected by the inlier flag.  Every record is finite (cells
+// outside the band carry a far sentinel mean), so the masked terms are finite.
+// KAHAN: compensated cost sum, for lanes that sum long runs of points.
 struct Acc {
     float h[21];
     float bw0, bw1, bw2, oe0, oe1, oe2;
-    float cost, comp, nout;   // compensated (Kahan) sum of the per-point costs
+    float cost, comp;   // comp: compensation of the (optional) Kahan cost sum
+    int32_t nin;        // inliers (plain) / points below c_max (residual field)
 };
 
+__device__ __forceinline__ void acc_zero(Acc& S) {
+#pragma unroll
+    for (int m = 0; m < 21; ++m) S.h[m] = 0.0f;
+    S.bw0 = S.bw1 = S.bw2 = S.oe0 = S.oe1 = S.oe2 = 0.0f;
+    S.cost = S.comp = 0.0f;
+    S.nin = 0;
+}
+
+template <bool KAHAN>
+__device__ __forceinline__ void add_cost(Acc& S, float y) {
+    if (KAHAN) {
+        const float yy = y - S.comp;
+        const float tt = S.cost + yy;
+        S.comp = (tt - S.cost) - yy;
+        S.cost = tt;
+    } else {
+        S.cost += y;
+    }
+}
+
+// Staged scan record: r0 = (mu, P00), r1 = (P01, P02, P11, P12), r2 = (P22, ..)
+// with P = (Sigma^S + I)^-1.  In the body frame C = Sigma^S + I - a u u^T
+// (u = R^T n), so Omega = C^-1 = P + beta q q^T with q = P u and
+// beta = a / (1 - a u^T q) (Sherman-Morrison; 1 - a u^T q > 0 whenever C is
+// positive definite).
+template <bool KAHAN>
 __device__ __forceinline__ void accumulate(Acc& S, const mpdet::mat3& Rm, const float a, const float dmax2,
                                            const float cmax, const float4 r0, const float4 r1, const float4 r2,
-                                           const float3 p, const int32_t g, const float4 gm, const float4 gn) {
-    const float3 mu = make_float3(r0.x, r0.y, r0.z);
-    float ex = gm.x - p.x, ey = gm.y - p.y, ez = gm.z - p.z;
+                                           const float3 p, const bool hit, const float4 gm, const float4 gn) {
+    const float ex = gm.x - p.x, ey = gm.y - p.y, ez = gm.z - p.z;
     const float d2 = __builtin_fmaf(ex, ex, __builtin_fmaf(ey, ey, ez * ez));
-    const bool inl = (g >= 0) && (d2 <= dmax2);
-    // cells outside the band carry mu = +inf: keep their residual out of the sums
-    ex = inl ? ex : 0.0f;
-    ey = inl ? ey : 0.0f;
-    ez = inl ? ez : 0.0f;
+    const bool inl = hit && (d2 <= dmax2);
+    const float m = inl ? 1.0f : 0.0f;
+    const float3 mu = make_float3(inl ? r0.x : 0.0f, inl ? r0.y : 0.0f, inl ? r0.z : 0.0f);
     const float3 u = mpdet::rot_t(Rm, make_float3(gn.x, gn.y, gn.z));
     const float3 eb = mpdet::rot_t(Rm, make_float3(ex, ey, ez));
-    const float aux = a * u.x, auy = a * u.y, auz = a * u.z;
-    // C = Sigma^S + I - a u u^T  (the identity is folded into r0.w, r1.z, r2.x)
-    const float c00 = __builtin_fmaf(-aux, u.x, r0.w);
-    const float c01 = __builtin_fmaf(-aux, u.y, r1.x);
-    const float c02 = __builtin_fmaf(-aux, u.z, r1.y);
-    const float c11 = __builtin_fmaf(-auy, u.y, r1.z);
-    const float c12 = __builtin_fmaf(-auy, u.z, r1.w);
-    const float c22 = __builtin_fmaf(-auz, u.z, r2.x);
-    const float i00 = __builtin_fmaf(c11, c22, -c12 * c12);
-    const float i01 = __builtin_fmaf(c02, c12, -c01 * c22);
-    const float i02 = __builtin_fmaf(c01, c12, -c02 * c11);
-    const float i11 = __builtin_fmaf(c00, c22, -c02 * c02);
-    const float i12 = __builtin_fmaf(c01, c02, -c00 * c12);
-    const float i22 = __builtin_fmaf(c00, c11, -c01 * c01);
-    const float det = __builtin_fmaf(c00, i00, __builtin_fmaf(c01, i01, c02 * i02));
-    const float rd = inl ? __builtin_amdgcn_rcpf(det) : 0.0f;
-    const float o00 = i00 * rd, o01 = i01 * rd, o02 = i02 * rd, o11 = i11 * rd, o12 = i12 * rd, o22 = i22 * rd;
+    const float p00 = r0.w, p01 = r1.x, p02 = r1.y, p11 = r1.z, p12 = r1.w, p22 = r2.x;
+    const float q0 = __builtin_fmaf(p00, u.x, __builtin_fmaf(p01, u.y, p02 * u.z));
+    const float q1 = __builtin_fmaf(p01, u.x, __builtin_fmaf(p11, u.y, p12 * u.z));
+    const float q2 = __builtin_fmaf(p02, u.x, __builtin_fmaf(p12, u.y, p22 * u.z));
+    const float uq = __builtin_fmaf(u.x, q0, __builtin_fmaf(u.y, q1, u.z * q2));
+    const float beta = a * __builtin_amdgcn_rcpf(__builtin_fmaf(-a, uq, 1.0f));
+    const float v0 = beta * q0, v1 = beta * q1, v2 = beta * q2;
+    const float o00 = __builtin_fmaf(v0, q0, p00), o01 = __builtin_fmaf(v0, q1, p01);
+    const float o02 = __builtin_fmaf(v0, q2, p02), o11 = __builtin_fmaf(v1, q1, p11);
+    const float o12 = __builtin_fmaf(v1, q2, p12), o22 = __builtin_fmaf(v2, q2, p22);
     const float w0 = __builtin_fmaf(o00, eb.x, __builtin_fmaf(o01, eb.y, o02 * eb.z));
     const float w1 = __builtin_fmaf(o01, eb.x, __builtin_fmaf(o11, eb.y, o12 * eb.z));
     const float w2 = __builtin_fmaf(o02, eb.x, __builtin_fmaf(o12, eb.y, o22 * eb.z));
     const float cst = __builtin_fmaf(eb.x, w0, __builtin_fmaf(eb.y, w1, eb.z * w2));
-    {
-        const float y = (inl ? fminf(cst, cmax) : 0.0f) - S.comp;   // outliers: counted in nout
-        const float tt = S.cost + y;
-        S.comp = (tt - S.cost) - y;
-        S.cost = tt;
-    }
-    S.nout += inl ? 0.0f : 1.0f;
-    S.oe0 += w0;
-    S.oe1 += w1;
-    S.oe2 += w2;
+    add_cost<KAHAN>(S, inl ? fminf(cst, cmax) : 0.0f);
+    S.nin += inl ? 1 : 0;
+    S.oe0 = __builtin_fmaf(m, w0, S.oe0);
+    S.oe1 = __builtin_fmaf(m, w1, S.oe1);
+    S.oe2 = __builtin_fmaf(m, w2, S.oe2);
     S.bw0 = __builtin_fmaf(w1, mu.z, __builtin_fmaf(-w2, mu.y, S.bw0));
     S.bw1 = __builtin_fmaf(w2, mu.x, __builtin_fmaf(-w0, mu.z, S.bw1));
     S.bw2 = __builtin_fmaf(w0, mu.y, __builtin_fmaf(-w1, mu.x, S.bw2));
@@ -131,13 +147,31 @@ __device__ __forceinline__ void accumulate(Acc& S, const mpdet::mat3& Rm, const 
     S.h[6] = __builtin_fmaf(-B12, mu.x, __builtin_fmaf(B10, mu.z, S.h[6]));
     S.h[7] = __builtin_fmaf(-B10, mu.y, __builtin_fmaf(B11, mu.x, S.h[7]));
     S.h[11] = __builtin_fmaf(-B20, mu.y, __builtin_fmaf(B21, mu.x, S.h[11]));
-    // H_wv = B
+    // H_wv = B (zero for outliers: mu was replaced by 0)
     S.h[3] += B00; S.h[4] += B01; S.h[5] += B02;
     S.h[8] += B10; S.h[9] += B11; S.h[10] += B12;
     S.h[12] += B20; S.h[13] += B21; S.h[14] += B22;
-    // H_vv = Omega
-    S.h[15] += o00; S.h[16] += o01; S.h[17] += o02;
-    S.h[18] += o11; S.h[19] += o12; S.h[20] += o22;
+    // H_vv = Omega (inliers)
+    S.h[15] = __builtin_fmaf(m, o00, S.h[15]); S.h[16] = __builtin_fmaf(m, o01, S.h[16]);
+    S.h[17] = __builtin_fmaf(m, o02, S.h[17]); S.h[18] = __builtin_fmaf(m, o11, S.h[18]);
+    S.h[19] = __builtin_fmaf(m, o12, S.h[19]); S.h[20] = __builtin_fmaf(m, o22, S.h[20]);
+}
+
+// (Sigma^S + I)^-1 of a raw scan record r0 = (mu, S00), r1 = (S01, S02, S11,
+// S12), r2 = (S22, ..), written back into the same slots (adjugate / det; the
+// eigenvalues of Sigma^S + I are >= 1 for a positive semi-definite Sigma^S).
+__device__ __forceinline__ void stage_inverse(float4& r0, float4& r1, float4& r2) {
+    const float c00 = r0.w + 1.0f, c01 = r1.x, c02 = r1.y, c11 = r1.z + 1.0f, c12 = r1.w, c22 = r2.x + 1.0f;
+    const float i00 = __builtin_fmaf(c11, c22, -c12 * c12);
+    const float i01 = __builtin_fmaf(c02, c12, -c01 * c22);
+    const float i02 = __builtin_fmaf(c01, c12, -c02 * c11);
+    const float i11 = __builtin_fmaf(c00, c22, -c02 * c02);
+    const float i12 = __builtin_fmaf(c01, c02, -c00 * c12);
+    const float i22 = __builtin_fmaf(c00, c11, -c01 * c01);
+    const float rd = 1.0f / __builtin_fmaf(c00, i00, __builtin_fmaf(c01, i01, c02 * i02));
+    r0.w = i00 * rd;
+    r1 = make_float4(i01 * rd, i02 * rd, i11 * rd, i12 * rd);
+    r2.x = i22 * rd;
 }
 
 // Residual-field scorer (rank-1 Gauss-Newton on r = sqrt(s)):
@@ -148,21 +182,19 @@ __device__ __forceinline__ void accumulate(Acc& S, const mpdet::mat3& Rm, const 
 //   outside: r = r_out, grad r = 0.
 // Every point: w = R^T grad r, g = [mu x w; w], H += g g^T, b += r g,
 // log-lik -min(r^2, c_max); r^2 >= c_max counts as an outlier (cost c_max).
+template <bool KAHAN>
 __device__ __forceinline__ void accumulate_sf(Acc& S, const mpdet::mat3& Rm, const float a, const float dmax2,
                                               const float cmax, const float sig2, const float ib,
                                               const float r_floor, const float r_out, const float4 r0,
-                                              const float3 p, const int32_t g, const float4 gm, const float4 gn) {
+                                              const float3 p, const bool hit, const float4 gm, const float4 gn,
+                                              const bool valid) {
     const float3 mu = make_float3(r0.x, r0.y, r0.z);
-    float ex = gm.x - p.x, ey = gm.y - p.y, ez = gm.z - p.z;
+    const float ex = gm.x - p.x, ey = gm.y - p.y, ez = gm.z - p.z;   // finite (far sentinel outside the band)
     const float d2 = __builtin_fmaf(ex, ex, __builtin_fmaf(ey, ey, ez * ez));
-    const bool gate = (g >= 0) && (d2 <= dmax2);
-    ex = gate ? ex : 0.0f;
-    ey = gate ? ey : 0.0f;
-    ez = gate ? ez : 0.0f;
+    const bool gate = hit && (d2 <= dmax2);
     const float kap = a / ((1.0f + sig2) * (gn.w + sig2));
     const float ne = __builtin_fmaf(gn.x, ex, __builtin_fmaf(gn.y, ey, gn.z * ez));
-    const float ee = __builtin_fmaf(ex, ex, __builtin_fmaf(ey, ey, ez * ez));
-    const float c = __builtin_fmaf(kap * ne, ne, ee * ib);
+    const float c = __builtin_fmaf(kap * ne, ne, d2 * ib);
     const float r = gate ? __builtin_sqrtf(c) : r_out;
     const float id = gate ? 1.0f / fmaxf(r, r_floor) : 0.0f;     // grad r = -Omega e / max(r, floor)
     const float kn = kap * ne;
@@ -187,14 +219,40 @@ __device__ __forceinline__ void accumulate_sf(Acc& S, const mpdet::mat3& Rm, con
     S.oe1 = __builtin_fmaf(-r, g6[4], S.oe1);
     S.oe2 = __builtin_fmaf(-r, g6[5], S.oe2);
     const float sq = r * r;
-    const bool below = sq < cmax;
-    {
-        const float y = (below ? sq : 0.0f) - S.comp;
-        const float tt = S.cost + y;
-        S.comp = (tt - S.cost) - y;
-        S.cost = tt;
+    const bool below = valid && sq < cmax;
+    add_cost<KAHAN>(S, below ? sq : 0.0f);
+    S.nin += below ? 1 : 0;
+}
+
+// Map access of the likelihood kernels.  DENSE: g is a record index of the
+// band grid, points outside the grid take the miss record (far sentinel mean,
+// so every point "hits" and the residual gate rejects); HASH: g is a Gaussian
+// id or -1.
+template <int BACKEND>
+__device__ __forceinline__ int32_t lik_cell(const MapView& v, const float3 p) {
+    return BACKEND == MP_NNF_DENSE ? (int32_t)mp_nnf_cell_or(v, p.x, p.y, p.z, v.dmiss)
+                                   : mp_nnf_lookup<BACKEND>(v, p.x, p.y, p.z);
+}
+
+template <int BACKEND>
+__device__ __forceinline__ int32_t lik_none(const MapView& v) {
+    return BACKEND == MP_NNF_DENSE ? (int32_t)v.dmiss : -1;
+}
+
+template <int BACKEND>
+__device__ __forceinline__ bool lik_hit(int32_t g) {
+    return BACKEND == MP_NNF_DENSE || g >= 0;
+}
+
+template <int BACKEND>
+__device__ __forceinline__ void lik_record(const MapView& v, int32_t g, float4& m, float4& n) {
+    if (BACKEND == MP_NNF_DENSE) {
+        mp_dense_record(v, (uint32_t)g, m, n);
+    } else {
+        const float4* r = v.gauss + 2 * (size_t)max(g, 0);
+        m = r[0];
+        n = r[1];
     }
-    S.nout += below ? 0.0f : 1.0f;
 }
 
 // Scan points are walked in batches of BATCH per lane: first the NNF cells of
@@ -218,27 +276,22 @@ __global__ __launch_bounds__(kLanes) void k_lik(LikArgs A) {
     const mpdet::mat3 Rm = mpdet::qmat(mpdet::quat{q4.x, q4.y, q4.z, q4.w});
     const float3 t = make_float3(t4.x, t4.y, t4.z);
     const float a = A.map.gicp_a;
-    const float4* __restrict__ gauss = A.map.gauss;
 
     Acc S;
-#pragma unroll
-    for (int m = 0; m < 21; ++m) S.h[m] = 0.0f;
-    S.bw0 = S.bw1 = S.bw2 = S.oe0 = S.oe1 = S.oe2 = 0.0f;
-    S.cost = S.comp = S.nout = 0.0f;
+    acc_zero(S);
 
     const int k0 = chunk * A.chunk_len;
     const int k1 = min(A.ns, k0 + A.chunk_len);
     for (int kt = k0; kt < k1; kt += kTile) {
         const int cnt = min(kTile, k1 - kt);
         __syncthreads();
-        for (int j = threadIdx.x; j < cnt * 3; j += kLanes) {
-            float4 v = A.scan[(size_t)kt * 3 + j];
-            // fold the identity of Sigma^M = I - a n n^T into the scan covariance
-            const int c = j % 3;
-            if (c == 0) v.w += 1.0f;
-            else if (c == 1) v.z += 1.0f;
-            else v.x += 1.0f;
-            tile[j] = v;
+        for (int j = threadIdx.x; j < cnt; j += kLanes) {
+            float4 r0 = A.scan[(size_t)(kt + j) * 3], r1 = A.scan[(size_t)(kt + j) * 3 + 1];
+            float4 r2 = A.scan[(size_t)(kt + j) * 3 + 2];
+            if (SC != MP_SCORER_SCOREFIELD) stage_inverse(r0, r1, r2);
+            tile[3 * j] = r0;
+            tile[3 * j + 1] = r1;
+            tile[3 * j + 2] = r2;
         }
         __syncthreads();
         if (!active) continue;
@@ -246,38 +299,30 @@ __global__ __launch_bounds__(kLanes) void k_lik(LikArgs A) {
             const int nbat = min(BATCH, cnt - kb);
             int32_t g[BATCH];
             float3 pk[BATCH];   // transformed points, kept for the second pass
-            // dense: g = band-grid cell (record fetched directly); hash: g = Gaussian id
-            const float4* __restrict__ rec = BACKEND == MP_NNF_DENSE ? A.map.drec : gauss;
 #pragma unroll
             for (int b = 0; b < BATCH; ++b) {
-                g[b] = -1;
+                g[b] = lik_none<BACKEND>(A.map);
                 pk[b] = make_float3(0.0f, 0.0f, 0.0f);
                 if (b < nbat) {
                     const float4 r0 = tile[3 * (kb + b)];
                     pk[b] = mpdet::xform(Rm.m, t, make_float3(r0.x, r0.y, r0.z));
-                    g[b] = BACKEND == MP_NNF_DENSE ? mp_nnf_cell(A.map, pk[b].x, pk[b].y, pk[b].z)
-                                                   : mp_nnf_lookup<BACKEND>(A.map, pk[b].x, pk[b].y, pk[b].z);
+                    g[b] = lik_cell<BACKEND>(A.map, pk[b]);
                 }
             }
             float4 gm[BATCH], gn[BATCH];
 #pragma unroll
-            for (int b = 0; b < 2 && b < BATCH; ++b) {
-                gm[b] = rec[2 * (size_t)max(g[b], 0)];
-                gn[b] = rec[2 * (size_t)max(g[b], 0) + 1];
-            }
+            for (int b = 0; b < 2 && b < BATCH; ++b) lik_record<BACKEND>(A.map, g[b], gm[b], gn[b]);
 #pragma unroll
             for (int b = 0; b < BATCH; ++b) {
-                if (b + 2 < BATCH) {
-                    gm[b + 2] = rec[2 * (size_t)max(g[b + 2], 0)];
-                    gn[b + 2] = rec[2 * (size_t)max(g[b + 2], 0) + 1];
-                }
+                if (b + 2 < BATCH) lik_record<BACKEND>(A.map, g[b + 2], gm[b + 2], gn[b + 2]);
                 if (b < nbat) {
                     const float4 r0 = tile[3 * (kb + b)], r1 = tile[3 * (kb + b) + 1], r2 = tile[3 * (kb + b) + 2];
                     if (SC == MP_SCORER_SCOREFIELD)
-                        accumulate_sf(S, Rm, a, A.dmax2, A.cmax, A.sig2, A.ib, A.r_floor, A.r_out, r0, pk[b], g[b],
-                                      gm[b], gn[b]);
+                        accumulate_sf<true>(S, Rm, a, A.dmax2, A.cmax, A.sig2, A.ib, A.r_floor, A.r_out, r0, pk[b],
+                                            lik_hit<BACKEND>(g[b]), gm[b], gn[b], true);
                     else
-                        accumulate(S, Rm, a, A.dmax2, A.cmax, r0, r1, r2, pk[b], g[b], gm[b], gn[b]);
+                        accumulate<true>(S, Rm, a, A.dmax2, A.cmax, r0, r1, r2, pk[b], lik_hit<BACKEND>(g[b]), gm[b],
+                                         gn[b]);
                 }
             }
         }
@@ -293,8 +338,8 @@ __global__ __launch_bounds__(kLanes) void k_lik(LikArgs A) {
     out[24 * st] = -S.oe0;
     out[25 * st] = -S.oe1;
     out[26 * st] = -S.oe2;
-    out[27 * st] = S.cost;
-    out[28 * st] = S.nout;
+    out[27 * st] = S.cost - S.comp;
+    out[28 * st] = (float)(k1 - k0 - S.nin);   // outliers of this chunk
 }
 
 // Grouped layout: 16 lanes per particle.  A workgroup (8 waves) keeps a
@@ -318,76 +363,68 @@ __global__ __launch_bounds__(kGThreads) void k_lik_grp(LikArgs A) {
     const int pblk = logical - chunk * A.nbx;
     const int k0 = chunk * kGChunk;
     const int cnt = min(kGChunk, A.ns - k0);
-    for (int j = threadIdx.x; j < cnt * 3; j += kGThreads) {
-        float4 v = A.scan[(size_t)k0 * 3 + j];
-        // fold the identity of Sigma^M = I - a n n^T into the scan covariance
-        const int c = j % 3;
-        if (c == 0) v.w += 1.0f;
-        else if (c == 1) v.z += 1.0f;
-        else v.x += 1.0f;
-        tile[j] = v;
+    // the whole chunk is staged; records past the scan's end are zero (a
+    // finite point at the origin that the walk below marks invalid)
+    for (int j = threadIdx.x; j < kGChunk; j += kGThreads) {
+        float4 r0 = make_float4(0.0f, 0.0f, 0.0f, 0.0f), r1 = r0, r2 = r0;
+        if (j < cnt) {
+            r0 = A.scan[(size_t)(k0 + j) * 3];
+            r1 = A.scan[(size_t)(k0 + j) * 3 + 1];
+            r2 = A.scan[(size_t)(k0 + j) * 3 + 2];
+            if (SC != MP_SCORER_SCOREFIELD) stage_inverse(r0, r1, r2);
+        }
+        tile[3 * j] = r0;
+        tile[3 * j + 1] = r1;
+        tile[3 * j + 2] = r2;
     }
     __syncthreads();
     const int grp = threadIdx.x / kGLanes;   // particle slot in the workgroup (0..31)
     const int gl = threadIdx.x % kGLanes;    // lane within the particle's group
     const float a = A.map.gicp_a;
-    const float4* __restrict__ rec = BACKEND == MP_NNF_DENSE ? A.map.drec : A.map.gauss;
     constexpr int kSlots = kGThreads / kGLanes;
+    static_assert(kGChunk % (kGLanes * BATCH) == 0, "a batch never runs past the staged chunk");
     for (int round = 0; round < kGParticles / kSlots; ++round) {
         const int sp = pblk * kGParticles + round * kSlots + grp;   // sorted position
         int i = sp < A.n ? (A.order ? A.order[sp] : sp) : 0;
         const bool active = sp < A.n && i >= 0 && i < A.n;
-        if (!active) i = 0;
+        if (!active) i = 0;   // evaluated like particle 0, never written
         const float4 q4 = A.poses[2 * i];
         const float4 t4 = A.poses[2 * i + 1];
         const mpdet::mat3 Rm = mpdet::qmat(mpdet::quat{q4.x, q4.y, q4.z, q4.w});
         const float3 t = make_float3(t4.x, t4.y, t4.z);
         Acc S;
-#pragma unroll
-        for (int m = 0; m < 21; ++m) S.h[m] = 0.0f;
-        S.bw0 = S.bw1 = S.bw2 = S.oe0 = S.oe1 = S.oe2 = 0.0f;
-        S.cost = S.comp = S.nout = 0.0f;
+        acc_zero(S);
+        // every lane walks whole batches; a point past the chunk's end gets
+        // no Gaussian (g = -1) and is excluded from the sums and counts
         for (int kb = 0; kb < cnt; kb += kGLanes * BATCH) {
             int32_t g[BATCH];
             float3 pk[BATCH];
-            bool ok[BATCH];
 #pragma unroll
             for (int b = 0; b < BATCH; ++b) {
                 const int k = kb + gl + kGLanes * b;
-                ok[b] = active && k < cnt;
-                g[b] = -1;
-                pk[b] = make_float3(0.0f, 0.0f, 0.0f);
-                if (ok[b]) {
-                    const float4 r0 = tile[3 * k];
-                    pk[b] = mpdet::xform(Rm.m, t, make_float3(r0.x, r0.y, r0.z));
-                    g[b] = BACKEND == MP_NNF_DENSE ? mp_nnf_cell(A.map, pk[b].x, pk[b].y, pk[b].z)
-                                                   : mp_nnf_lookup<BACKEND>(A.map, pk[b].x, pk[b].y, pk[b].z);
-                }
+                const float4 r0 = tile[3 * k];
+                pk[b] = mpdet::xform(Rm.m, t, make_float3(r0.x, r0.y, r0.z));
+                const int32_t c = lik_cell<BACKEND>(A.map, pk[b]);
+                g[b] = k < cnt ? c : lik_none<BACKEND>(A.map);
             }
             float4 gm[BATCH], gn[BATCH];
 #pragma unroll
-            for (int b = 0; b < 2 && b < BATCH; ++b) {
-                gm[b] = rec[2 * (size_t)max(g[b], 0)];
-                gn[b] = rec[2 * (size_t)max(g[b], 0) + 1];
-            }
+            for (int b = 0; b < 2 && b < BATCH; ++b) lik_record<BACKEND>(A.map, g[b], gm[b], gn[b]);
 #pragma unroll
             for (int b = 0; b < BATCH; ++b) {
-                if (b + 2 < BATCH) {
-                    gm[b + 2] = rec[2 * (size_t)max(g[b + 2], 0)];
-                    gn[b + 2] = rec[2 * (size_t)max(g[b + 2], 0) + 1];
-                }
-                if (ok[b]) {
-                    const int k = kb + gl + kGLanes * b;
-                    const float4 r0 = tile[3 * k], r1 = tile[3 * k + 1], r2 = tile[3 * k + 2];
-                    if (SC == MP_SCORER_SCOREFIELD)
-                        accumulate_sf(S, Rm, a, A.dmax2, A.cmax, A.sig2, A.ib, A.r_floor, A.r_out, r0, pk[b], g[b],
-                                      gm[b], gn[b]);
-                    else
-                        accumulate(S, Rm, a, A.dmax2, A.cmax, r0, r1, r2, pk[b], g[b], gm[b], gn[b]);
-                }
+                if (b + 2 < BATCH) lik_record<BACKEND>(A.map, g[b + 2], gm[b + 2], gn[b + 2]);
+                const int k = kb + gl + kGLanes * b;
+                const float4 r0 = tile[3 * k], r1 = tile[3 * k + 1], r2 = tile[3 * k + 2];
+                if (SC == MP_SCORER_SCOREFIELD)
+                    accumulate_sf<false>(S, Rm, a, A.dmax2, A.cmax, A.sig2, A.ib, A.r_floor, A.r_out, r0, pk[b],
+                                         lik_hit<BACKEND>(g[b]), gm[b], gn[b], k < cnt);
+                else
+                    accumulate<false>(S, Rm, a, A.dmax2, A.cmax, r0, r1, r2, pk[b], lik_hit<BACKEND>(g[b]), gm[b],
+                                      gn[b]);
             }
         }
         // the group's 16 partial sums, combined by a butterfly within the group
+        // (per-lane runs are at most 64 points: plain FP32 sums)
         float v[kNumPartial];
 #pragma unroll
         for (int m = 0; m < 21; ++m) v[m] = S.h[m];
@@ -397,14 +434,15 @@ __global__ __launch_bounds__(kGThreads) void k_lik_grp(LikArgs A) {
         v[24] = -S.oe0;
         v[25] = -S.oe1;
         v[26] = -S.oe2;
-        v[27] = S.cost - S.comp;
-        v[28] = S.nout;
+        v[27] = S.cost;
+        v[28] = (float)S.nin;   // exact: at most kGChunk
 #pragma unroll
         for (int m = 0; m < kNumPartial; ++m)
 #pragma unroll
             for (int off = kGLanes / 2; off >= 1; off >>= 1) v[m] += __shfl_xor(v[m], off, 64);
         if (gl == 0 && active) {
             float* out = A.partial + (size_t)chunk * kNumPartial * A.n + sp;
+            v[28] = (float)cnt - v[28];   // outliers of this chunk
 #pragma unroll
             for (int m = 0; m < kNumPartial; ++m) out[(size_t)m * A.n] = v[m];
         }
@@ -612,12 +650,12 @@ void mp_launch_likelihood(mp_filter f, hipStream_t s) {
         } else if (f->p.lik_batch == 8) {
             if (dense) k_lik_grp<MP_NNF_DENSE, 8, MP_SCORER_PLAIN><<<grid, kGThreads, 0, s>>>(A);
             else k_lik_grp<MP_NNF_HASH, 8, MP_SCORER_PLAIN><<<grid, kGThreads, 0, s>>>(A);
-        } else if (f->p.lik_batch == 2) {
-            if (dense) k_lik_grp<MP_NNF_DENSE, 2, MP_SCORER_PLAIN><<<grid, kGThreads, 0, s>>>(A);
-            else k_lik_grp<MP_NNF_HASH, 2, MP_SCORER_PLAIN><<<grid, kGThreads, 0, s>>>(A);
-        } else {
+        } else if (f->p.lik_batch == 4) {
             if (dense) k_lik_grp<MP_NNF_DENSE, 4, MP_SCORER_PLAIN><<<grid, kGThreads, 0, s>>>(A);
             else k_lik_grp<MP_NNF_HASH, 4, MP_SCORER_PLAIN><<<grid, kGThreads, 0, s>>>(A);
+        } else {   // 2, and the default: two records in flight keep the kernel at 94 VGPRs
+            if (dense) k_lik_grp<MP_NNF_DENSE, 2, MP_SCORER_PLAIN><<<grid, kGThreads, 0, s>>>(A);
+            else k_lik_grp<MP_NNF_HASH, 2, MP_SCORER_PLAIN><<<grid, kGThreads, 0, s>>>(A);
         }
         MP_CHECK_LAUNCH();
         mp_tick(f, MP_STAGE_LIK_CORE, false, s);

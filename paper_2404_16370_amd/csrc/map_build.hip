@@ -241,17 +241,22 @@ __global__ void k_dense_finalize(const unsigned long long* __restrict__ cells, i
     if ((threadIdx.x & 63) == 0 && b) atomicAdd(count, (unsigned long long)__popcll(b));
 }
 
-// per-cell copy of the nearest Gaussian's record (the likelihood's one-fetch path)
+constexpr float kFarMean = 1.0e15f;
+
+// per-cell copy of the nearest Gaussian's record (the likelihood's one-fetch
+// path), followed by one record for points outside the grid
 __global__ void k_dense_records(const int32_t* __restrict__ dense, int64_t ncell, const float4* __restrict__ gauss,
                                 float4* __restrict__ drec) {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= ncell) return;
-    const int32_t g = dense[c];
+    if (c > ncell) return;
+    const int32_t g = c < ncell ? dense[c] : -1;   // record ncell: the miss record
     if (g >= 0) {
         drec[2 * c] = gauss[2 * (int64_t)g];
         drec[2 * c + 1] = gauss[2 * (int64_t)g + 1];
     } else {
-        drec[2 * c] = make_float4(__builtin_inff(), __builtin_inff(), __builtin_inff(), 0.0f);
+        // no Gaussian: a mean 1e15 m away fails every residual gate, while
+        // squares and products of the residual stay finite in FP32
+        drec[2 * c] = make_float4(kFarMean, kFarMean, kFarMean, 0.0f);
         drec[2 * c + 1] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     }
 }
@@ -454,9 +459,13 @@ void mp_build_map(mp_map m, const float* xyz, int64_t n, hipStream_t s) {
     const double bcells = (double)bg.dim[0] * (double)bg.dim[1] * (double)bg.dim[2];
     int backend = P.backend;
     // dense: 4 B id + 32 B record per cell of the band grid's box
-    if (backend == MP_NNF_AUTO) backend = bcells <= 67108864.0 ? MP_NNF_DENSE : MP_NNF_HASH;
-    if (backend == MP_NNF_DENSE && bcells > 2147483647.0)
-        mp_throw(MP_E_UNSUPPORTED, "mp_map_build: dense band grid exceeds 2^31 cells");
+    // (cell indices are formed with 24-bit multiplies and records addressed by
+    // 32-bit byte offsets: dim_x dim_y < 2^24 and cells + 1 < 2^27)
+    const double bplane = (double)bg.dim[0] * (double)bg.dim[1];
+    if (backend == MP_NNF_AUTO)
+        backend = (bcells <= 67108864.0 && bplane < 16777216.0) ? MP_NNF_DENSE : MP_NNF_HASH;
+    if (backend == MP_NNF_DENSE && (bcells > 134217726.0 || bplane >= 16777216.0))
+        mp_throw(MP_E_UNSUPPORTED, "mp_map_build: dense band grid exceeds 2^27 - 2 cells or 2^24 cells per plane");
     if (backend == MP_NNF_HASH && bcells > 4294967294.0)
         mp_throw(MP_E_UNSUPPORTED, "mp_map_build: hashed band grid exceeds 2^32 - 2 cells");
 
@@ -479,13 +488,15 @@ void mp_build_map(mp_map m, const float* xyz, int64_t n, hipStream_t s) {
         MP_CHECK_LAUNCH();
         MP_HIP(hipMemcpyAsync(&band, d_count.p, 8, hipMemcpyDeviceToHost, s));
         MP_HIP(hipStreamSynchronize(s));
-        m->drec.alloc(sizeof(float4) * 2 * (size_t)nc);
-        k_dense_records<<<nblk(nc), kBlock, 0, s>>>(m->dense.as<int32_t>(), nc, m->gauss.as<float4>(),
-                                                    m->drec.as<float4>());
+        m->drec.alloc(sizeof(float4) * 2 * (size_t)(nc + 1));   // + the miss record
+        k_dense_records<<<nblk(nc + 1), kBlock, 0, s>>>(m->dense.as<int32_t>(), nc, m->gauss.as<float4>(),
+                                                        m->drec.as<float4>());
         MP_CHECK_LAUNCH();
         MP_HIP(hipStreamSynchronize(s));
         view.dense = m->dense.as<int32_t>();
         view.drec = m->drec.as<float4>();
+        view.dxy = (uint32_t)bg.dim[0] * (uint32_t)bg.dim[1];
+        view.dmiss = (uint32_t)nc;
         info.table_slots = nc;
     } else {
         const uint64_t wcap = next_pow2((uint64_t)std::max<int64_t>(2 * emits, 64));

@@ -55,8 +55,11 @@ struct MapView {
     const int32_t* dense;   // dim product cells, -1 = miss
     const uint2* table;     // hash slots {key = linear index + 1 (0 empty), gid}
     const float4* gauss;    // 2 per Gaussian: (mu, count), (n, 0)
-    const float4* drec;     // dense backend: 2 per cell, the nearest Gaussian's record;
-                            // cells outside the band hold mu = +inf
+    const float4* drec;     // dense backend: 2 per cell, the nearest Gaussian's record
+                            // (cells outside the band: a far sentinel mean), then one
+                            // more record (index dmiss) for points outside the grid
+    uint32_t dxy;           // dense backend: dim[0] * dim[1] (< 2^24)
+    uint32_t dmiss;         // dense backend: cells of the grid (< 2^27 - 1)
 };
 
 struct mp_map_s {

@@ -41,11 +41,27 @@ __device__ __forceinline__ int32_t floor_cell(float z) {
     return r;
 }
 
-// dense band-grid cell of floor(p * 1/r), or -1 outside the grid's box
-__device__ __forceinline__ int32_t mp_nnf_cell(const MapView& v, float px, float py, float pz) {
+// dense band-grid cell of floor(p * 1/r) (x fastest), or `miss` outside the
+// grid's box.  The map build keeps dim_x dim_y < 2^24, so for in-box cells the
+// 24-bit products are exact; outside the box the index is discarded.
+__device__ __forceinline__ uint32_t mp_nnf_cell_or(const MapView& v, float px, float py, float pz, uint32_t miss) {
     const uint32_t x = (uint32_t)floor_cell(px * v.inv_r) - (uint32_t)v.org[0];
     const uint32_t y = (uint32_t)floor_cell(py * v.inv_r) - (uint32_t)v.org[1];
     const uint32_t z = (uint32_t)floor_cell(pz * v.inv_r) - (uint32_t)v.org[2];
-    if (x >= (uint32_t)v.dim[0] || y >= (uint32_t)v.dim[1] || z >= (uint32_t)v.dim[2]) return -1;
-    return (int32_t)((z * (uint32_t)v.dim[1] + y) * (uint32_t)v.dim[0] + x);
+    const bool in = (x < (uint32_t)v.dim[0]) & (y < (uint32_t)v.dim[1]) & (z < (uint32_t)v.dim[2]);
+    const uint32_t c = __umul24(z, v.dxy) + __umul24(y, (uint32_t)v.dim[0]) + x;
+    return in ? c : miss;
+}
+
+// dense band-grid cell of floor(p * 1/r), or -1 outside the grid's box
+__device__ __forceinline__ int32_t mp_nnf_cell(const MapView& v, float px, float py, float pz) {
+    return (int32_t)mp_nnf_cell_or(v, px, py, pz, 0xFFFFFFFFu);
+}
+
+// the two float4 of dense record c (a cell, or the miss record), addressed by
+// a 32-bit byte offset from the array's base
+__device__ __forceinline__ void mp_dense_record(const MapView& v, uint32_t c, float4& m, float4& n) {
+    const char* b = reinterpret_cast<const char*>(v.drec) + (c << 5);
+    m = *reinterpret_cast<const float4*>(b);
+    n = *reinterpret_cast<const float4*>(b + 16);
 }
