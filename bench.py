@@ -412,6 +412,44 @@ def surrogate_eval_main(args):
     print(json.dumps(res), flush=True)
 
 
+def _med_p90(v):
+    a = np.asarray(v, np.float64)
+    return {"median_ms": round(float(np.median(a)), 3), "p90_ms": round(float(np.percentile(a, 90)), 3),
+            "n": int(a.size)}
+
+
+def stage_roofline(stages, wl, lik_flops_launch, t_step):
+    """Each stage of one filter step against the resource that bounds it:
+    algorithmic bytes per step over HBM bandwidth for the data-movement stages
+    (per-particle figures of their kernels), algorithmic flops over the FP32
+    peak for the likelihood and the scan's k-NN.  `step` sums the stages'
+    roofline times over the measured step time."""
+    n, it, K, C, R = wl["particles"], wl["svgd_iters"], wl["k"], wl["window_c"], wl["post_iters"]
+    ns, passes = wl["scan_points"], (wl["lsh_bits"] + 7) // 8
+    work = {
+        "predict": ("hbm", 64.0 * n),
+        "lsh": ("hbm", 40.0 * n * it),
+        "sort": ("hbm", (16.0 * passes + 12.0) * n * it),
+        "refresh": ("hbm", (32.0 + 4 * K + 32.0 * (K + C) + 8 * K) * n * it),
+        "likelihood": ("alu", lik_flops_launch * it),
+        "svgd": ("hbm", (32.0 + K * (8 + 32 + 32) + 32.0) * n * it),
+        "posterior": ("hbm", (36.0 + R * (8.0 * K + 8)) * n),
+        "scan": ("alu", 8.0 * ns * (ns - 1)),
+    }
+    out, t_min = {}, 0.0
+    for name, (bound, w) in work.items():
+        ms = stages.get(name, (0.0, 0))[0]
+        peak = PEAK_HBM if bound == "hbm" else PEAK_FP32
+        t = w / peak
+        t_min += t
+        if ms > 0:
+            out[name] = {"bound": bound, "ms": round(ms, 3), "roofline_ms": round(1e3 * t, 4),
+                         "frac": round(t / (ms * 1e-3), 4)}
+    out["step"] = {"roofline_ms": round(1e3 * t_min, 3), "ms": round(1e3 * t_step, 3),
+                   "frac": round(t_min / t_step, 4)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -483,13 +521,21 @@ def main():
         run(k)
         log("warmup step %d done" % k)
     torch.cuda.synchronize()
-    lik_ms, lik_n = [], []
+    lik_ms, lik_n, up_ms, step_ms = [], [], [], []
     t0 = time.perf_counter()
     for k in range(args.warmup, args.warmup + args.steps):
-        run(k)
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        dT, cov = odo[k] if k > 0 else (None, None)
+        e0.record()
+        f.scan_upload(scans[k])
+        e1.record()
+        f.step(dT, cov)
+        e2.record()
         st = f.stage_times()   # synchronises on this step's events
         lik_ms.append(st["likelihood_core"][0])
         lik_n.append(st["likelihood_core"][1])
+        up_ms.append(e0.elapsed_time(e1))
+        step_ms.append(e1.elapsed_time(e2))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     stages = f.stage_times()
@@ -527,6 +573,9 @@ def main():
         "likelihood_kernel_evals_per_s": evals_iter / t_launch,
         "inlier_fraction": round(inl_frac, 4),
         "stage_ms_last_step": {k: round(v[0], 3) for k, v in stages.items() if v[1]},
+        "step_ms_events": {"with_scan_upload": _med_p90([a + b for a, b in zip(up_ms, step_ms)]),
+                           "without_scan_upload": _med_p90(step_ms), "scan_upload": _med_p90(up_ms)},
+        "stage_roofline": stage_roofline(stages, wl, flops_launch, elapsed / args.steps),
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32, "traffic": measured_traffic(args.workload),
                      "kernel": "k_lik_grp (grouped layout)", "launch_ms": t_launch * 1e3,

@@ -373,74 +373,45 @@ extern "C" mp_status mp_filter_destroy(mp_filter f) {
     });
 }
 
-// 3-D Morton (Z-order) key of the cell of each point, cells of edge `cell`
-static uint64_t spread3(uint64_t v) {
-    v &= 0x1FFFFF;
-    v = (v | (v << 32)) & 0x1F00000000FFFFull;
-    v = (v | (v << 16)) & 0x1F0000FF0000FFull;
-    v = (v | (v << 8)) & 0x100F00F00F00F00Full;
-    v = (v | (v << 4)) & 0x10C30C30C30C30C3ull;
-    v = (v | (v << 2)) & 0x1249249249249249ull;
-    return v;
-}
-
-static std::vector<int32_t> morton_order(const float* xyz, int n, float cell) {
-    float lo[3] = {xyz[0], xyz[1], xyz[2]};
-    for (int i = 1; i < n; ++i)
-        for (int a = 0; a < 3; ++a) lo[a] = std::min(lo[a], xyz[3 * i + a]);
-    std::vector<uint64_t> key((size_t)n);
-    for (int i = 0; i < n; ++i) {
-        uint64_t c[3];
-        for (int a = 0; a < 3; ++a) {
-            const double q = std::floor(((double)xyz[3 * i + a] - lo[a]) / cell);
-            c[a] = (uint64_t)std::min(std::max(q, 0.0), 2097151.0);
-        }
-        key[(size_t)i] = spread3(c[0]) | (spread3(c[1]) << 1) | (spread3(c[2]) << 2);
-    }
-    std::vector<int32_t> perm((size_t)n);
-    std::iota(perm.begin(), perm.end(), 0);
-    std::stable_sort(perm.begin(), perm.end(), [&](int32_t a, int32_t b) { return key[(size_t)a] < key[(size_t)b]; });
-    return perm;
-}
-
 extern "C" mp_status mp_scan_upload(mp_filter f, const float* xyz, const float* cov6, int32_t n, void* stream) {
     return guarded("mp_scan_upload", [&]() {
         if (!f || n < 0 || (n > 0 && !xyz)) mp_throw(MP_E_ARG, "null argument or n < 0");
         if (n > 65536) mp_throw(MP_E_ARG, "more than 65536 scan points");
         hipStream_t s = as_stream(stream);
         if (n > 0) {
-            std::vector<float> hx((size_t)n * 3);
-            fetch_host(xyz, sizeof(float) * 3 * (size_t)n, hx.data(), s);
-            if (!all_finite(hx.data(), hx.size())) mp_throw(MP_E_ARG, "non-finite scan point");
-            std::vector<float> hc;
-            if (cov6) {
-                hc.resize((size_t)n * 6);
-                fetch_host(cov6, sizeof(float) * 6 * (size_t)n, hc.data(), s);
-                if (!all_finite(hc.data(), hc.size())) mp_throw(MP_E_ARG, "non-finite scan covariance");
-            }
             f->scan_xyz.ensure(sizeof(float) * 3 * (size_t)n);
             f->scan.ensure(sizeof(float) * 12 * (size_t)n);
             f->scan_orig.ensure(sizeof(float) * 12 * (size_t)n);
             f->scan_perm.ensure(sizeof(int32_t) * (size_t)n);
+            f->scan_work.ensure(sizeof(uint32_t) * (4 * (size_t)n + 4));
+            f->scan_sort.ensure(mp_radix_scratch_bytes(n));
+            // caller data (host or device) into the filter's staging buffers
+            MP_HIP(hipMemcpyAsync(f->scan_xyz.p, xyz, sizeof(float) * 3 * (size_t)n, hipMemcpyDefault, s));
+            const float* dcov = nullptr;
+            if (cov6) {
+                f->scan_cov.ensure(sizeof(float) * 6 * (size_t)n);
+                MP_HIP(hipMemcpyAsync(f->scan_cov.p, cov6, sizeof(float) * 6 * (size_t)n, hipMemcpyDefault, s));
+                dcov = f->scan_cov.as<float>();
+            }
+            uint32_t* work = f->scan_work.as<uint32_t>();
+            float* lo_bad = reinterpret_cast<float*>(work + 4 * (size_t)n);
+            // validation on the device; only its 4-byte verdict comes back
+            mp_scan_check(f->scan_xyz.as<float>(), dcov, n, lo_bad, s);
+            float bad = 0.0f;
+            MP_HIP(hipMemcpyAsync(&bad, lo_bad + 3, sizeof(float), hipMemcpyDeviceToHost, s));
+            MP_HIP(hipStreamSynchronize(s));
+            if (bad != 0.0f) mp_throw(MP_E_ARG, cov6 ? "non-finite scan point or covariance" : "non-finite scan point");
+            f->ev_count[MP_STAGE_SCAN] = 0;
+            mp_tick(f, MP_STAGE_SCAN, true, s);
             // Walk order for the likelihood: Morton order of the points on a grid of half the
             // map voxel, so that consecutive points of one particle land in the same or
             // neighbouring voxels (the sum over points does not depend on the order).
-            const std::vector<int32_t> perm = morton_order(hx.data(), n, 0.5f * f->map->params.voxel);
-            MP_HIP(hipMemcpyAsync(f->scan_perm.p, perm.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
-            MP_HIP(hipMemcpyAsync(f->scan_xyz.p, hx.data(), sizeof(float) * 3 * n, hipMemcpyHostToDevice, s));
-            DevMem tcov;
-            const float* dcov = nullptr;
-            if (cov6) {
-                tcov.alloc(sizeof(float) * 6 * (size_t)n);
-                MP_HIP(hipMemcpyAsync(tcov.p, hc.data(), sizeof(float) * 6 * n, hipMemcpyHostToDevice, s));
-                dcov = tcov.as<float>();
-            }
-            f->ev_count[MP_STAGE_SCAN] = 0;
-            mp_tick(f, MP_STAGE_SCAN, true, s);
+            mp_scan_walk_order(f->scan_xyz.as<float>(), n, 0.5f * f->map->params.voxel, lo_bad, work, work + n,
+                               f->scan_perm.as<int32_t>(), reinterpret_cast<int32_t*>(work + 2 * (size_t)n),
+                               f->scan_sort, s);
             mp_scan_records(f->scan_xyz.as<float>(), dcov, n, f->p.scan_k, f->p.cov_eps, f->scan_orig.as<float>(), s);
             mp_scan_permute(f->scan_orig.as<float>(), f->scan_perm.as<int32_t>(), n, f->scan.as<float>(), s);
             mp_tick(f, MP_STAGE_SCAN, false, s);
-            MP_HIP(hipStreamSynchronize(s));  // staging buffers (perm, tcov) go out of scope
         }
         f->scan_n = n;
         f->last_stream = s;

@@ -137,6 +137,9 @@ struct mp_filter_s {
     DevMem scan_orig;         // n x 12 float records in the caller's order
     DevMem scan_perm;         // n int32: walk position -> caller index
     DevMem scan_xyz;          // n x 3 float staging
+    DevMem scan_cov;          // n x 6 float staging of caller covariances
+    DevMem scan_work;         // walk-order keys and work arrays (4n words) + lo/bad (4 floats)
+    DevMem scan_sort;         // radix-sort scratch of the walk order
     DevMem tlsh;              // 8 float
     DevMem stepinfo;          // posterior summary (doubles)
     // stage timers: event pairs per stage and span, reused across steps
@@ -167,6 +170,13 @@ void mp_map_lookup_launch(const MapView& v, const float* xyz_dev, int64_t n, int
 void mp_scan_records(const float* xyz_dev, const float* cov6_dev, int32_t n, int32_t k, float eps, float* rec_dev,
                      hipStream_t s);
 void mp_scan_permute(const float* rec_orig, const int32_t* perm, int32_t n, float* rec_out, hipStream_t s);
+// lo_bad_dev (4 floats): bounding-box minimum corner of the points, then 1 if any
+// point or covariance entry is not finite (else 0)
+void mp_scan_check(const float* xyz_dev, const float* cov6_dev, int32_t n, float* lo_bad_dev, hipStream_t s);
+// walk order of the likelihood: stable sort of the points by the Morton key of
+// their cell (edge `cell`); keys/keys_alt/perm_alt are n-entry work arrays
+void mp_scan_walk_order(const float* xyz_dev, int32_t n, float cell, const float* lo_bad_dev, uint32_t* keys,
+                        uint32_t* keys_alt, int32_t* perm, int32_t* perm_alt, DevMem& scratch, hipStream_t s);
 
 // filter stages
 void mp_launch_init_uniform(mp_filter f, const float lo[3], const float hi[3], hipStream_t s);

@@ -4,7 +4,7 @@
 // mu is the point itself.  Without caller covariances, Sigma is the
 // GICP-normalised covariance I - (1-eps) n n^T of the point and its k nearest
 // other scan points: k-NN by FP32 squared distance (fixed fma order, ties to
-// the lower index; scan tiles staged in LDS), FP64 mean and 1/(k+1)
+// the lower index; scan tiles staged in LDS, 16 lanes per point), FP64 mean and 1/(k+1)
 // covariance summed self-first in neighbour order, FP64 cyclic Jacobi with a
 // fixed operation order.  Fewer than 5 points give Sigma = I.
 //
@@ -67,17 +67,26 @@ __device__ void jacobi_min_vec(double A[9], double nrm[3]) {
     nrm[2] = V[6 + o[0]];
 }
 
+// k nearest other scan points of each point, 16 lanes per point: lane l
+// keeps the KC best (d2, j) of the candidates j = l, l + 16, ... (ascending j
+// with a strict comparison, so equal distances stay in index order); the 16
+// sorted lists are then merged by k rounds of a (d2, j) minimum across the
+// group.  Then the FP64 Gaussian of the point and its neighbours.
+constexpr int kQLanes = 16;
+
+template <int KC>
 __global__ __launch_bounds__(kB) void k_scan_knn_cov(const float* __restrict__ xyz, int n, int k, float eps,
                                                      float4* __restrict__ rec) {
     __shared__ float3 tile[kPtsTile];
-    const int i = blockIdx.x * kB + threadIdx.x;
-    const bool active = i < n;
+    const int grp = threadIdx.x / kQLanes, gl = threadIdx.x % kQLanes;
+    const int i = blockIdx.x * (kB / kQLanes) + grp;
+    const bool active = i < n;   // uniform over the point's 16 lanes
     const float3 pi = active ? make_float3(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2]) : make_float3(0, 0, 0);
     const int kk = min(k, n - 1);
-    float bd[kKMax];
-    int bj[kKMax];
+    float bd[KC];
+    int bj[KC];
 #pragma unroll
-    for (int m = 0; m < kKMax; ++m) {
+    for (int m = 0; m < KC; ++m) {
         bd[m] = __builtin_inff();
         bj[m] = 0x7FFFFFFF;
     }
@@ -88,16 +97,15 @@ __global__ __launch_bounds__(kB) void k_scan_knn_cov(const float* __restrict__ x
             tile[t] = make_float3(xyz[3 * (base + t)], xyz[3 * (base + t) + 1], xyz[3 * (base + t) + 2]);
         __syncthreads();
         if (!active) continue;
-        for (int t = 0; t < cnt; ++t) {
+        for (int t = gl; t < cnt; t += kQLanes) {
             const int j = base + t;
             if (j == i) continue;
             const float3 pj = tile[t];
             const float dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
             const float d2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
-            // candidates arrive in ascending j, so a strict comparison keeps (d2, j) order
-            if (d2 < bd[kKMax - 1]) {
+            if (d2 < bd[KC - 1]) {
 #pragma unroll
-                for (int m = kKMax - 1; m >= 1; --m) {
+                for (int m = KC - 1; m >= 1; --m) {
                     const bool sh = d2 < bd[m - 1];
                     const bool here = d2 < bd[m];
                     bd[m] = sh ? bd[m - 1] : (here ? d2 : bd[m]);
@@ -111,14 +119,40 @@ __global__ __launch_bounds__(kB) void k_scan_knn_cov(const float* __restrict__ x
         }
     }
     if (!active) return;
+    // merge: round r takes the smallest head of the 16 lists and pops it
+    int nb[KC];
+#pragma unroll
+    for (int r = 0; r < KC; ++r) {
+        float d = bd[0];
+        int j = bj[0];
+#pragma unroll
+        for (int off = kQLanes / 2; off >= 1; off >>= 1) {
+            const float od = __shfl_xor(d, off, 64);
+            const int oj = __shfl_xor(j, off, 64);
+            const bool take = od < d || (od == d && oj < j);
+            d = take ? od : d;
+            j = take ? oj : j;
+        }
+        nb[r] = j;
+        if (bj[0] == j) {   // this lane held the minimum (indices are unique)
+#pragma unroll
+            for (int m = 0; m + 1 < KC; ++m) {
+                bd[m] = bd[m + 1];
+                bj[m] = bj[m + 1];
+            }
+            bd[KC - 1] = __builtin_inff();
+            bj[KC - 1] = 0x7FFFFFFF;
+        }
+    }
+    if (gl != 0) return;
     double c6[6];
     if (kk + 1 < 5) {
         c6[0] = 1; c6[1] = 0; c6[2] = 0; c6[3] = 1; c6[4] = 0; c6[5] = 1;
     } else {
         double sm[3] = {(double)pi.x, (double)pi.y, (double)pi.z};
-        for (int a = 0; a < kKMax; ++a) {
+        for (int a = 0; a < KC; ++a) {
             if (a >= kk) break;
-            const int j = bj[a];
+            const int j = nb[a];
             sm[0] = sm[0] + (double)xyz[3 * j];
             sm[1] = sm[1] + (double)xyz[3 * j + 1];
             sm[2] = sm[2] + (double)xyz[3 * j + 2];
@@ -127,7 +161,7 @@ __global__ __launch_bounds__(kB) void k_scan_knn_cov(const float* __restrict__ x
         const double mu[3] = {sm[0] / dn, sm[1] / dn, sm[2] / dn};
         double S[6] = {0, 0, 0, 0, 0, 0};
         for (int a = -1; a < kk; ++a) {
-            const int j = a < 0 ? i : bj[a];
+            const int j = a < 0 ? i : nb[a];
             const double d0 = (double)xyz[3 * j] - mu[0];
             const double d1 = (double)xyz[3 * j + 1] - mu[1];
             const double d2 = (double)xyz[3 * j + 2] - mu[2];
@@ -171,6 +205,71 @@ __global__ void k_scan_permute(const float4* __restrict__ in, const int32_t* __r
     out[3 * k + 2] = in[3 * j + 2];
 }
 
+// Finiteness of the points (and covariances) and the minimum corner of the
+// points' bounding box: one workgroup (n <= 65536), deterministic (min and or).
+constexpr int kChk = 1024;
+__global__ __launch_bounds__(kChk) void k_scan_check(const float* __restrict__ xyz, const float* __restrict__ cov,
+                                                     int n, float* __restrict__ lo_bad) {
+    __shared__ float red[3][kChk];
+    __shared__ int rbad[kChk];
+    float lo[3] = {__builtin_inff(), __builtin_inff(), __builtin_inff()};
+    int bad = 0;
+    for (int i = threadIdx.x; i < n; i += kChk) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const float v = xyz[3 * i + a];
+            bad |= !__builtin_isfinite(v);
+            lo[a] = fminf(lo[a], v);
+        }
+        if (cov)
+#pragma unroll
+            for (int a = 0; a < 6; ++a) bad |= !__builtin_isfinite(cov[6 * i + a]);
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) red[a][threadIdx.x] = lo[a];
+    rbad[threadIdx.x] = bad;
+    __syncthreads();
+    for (int h = kChk / 2; h >= 1; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) red[a][threadIdx.x] = fminf(red[a][threadIdx.x], red[a][threadIdx.x + h]);
+            rbad[threadIdx.x] |= rbad[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        lo_bad[0] = red[0][0];
+        lo_bad[1] = red[1][0];
+        lo_bad[2] = red[2][0];
+        lo_bad[3] = rbad[0] ? 1.0f : 0.0f;
+    }
+}
+
+__device__ inline uint32_t spread10(uint32_t v) {
+    v &= 0x3FFu;
+    v = (v | (v << 16)) & 0x030000FFu;
+    v = (v | (v << 8)) & 0x0300F00Fu;
+    v = (v | (v << 4)) & 0x030C30C3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+
+// 30-bit Morton (Z-order) key of each point's cell (edge `cell`, 1024 cells
+// per axis from the box corner, clamped) and the identity permutation
+__global__ void k_morton_keys(const float* __restrict__ xyz, int n, const float* __restrict__ lo_bad, float inv_cell,
+                              uint32_t* __restrict__ key, int32_t* __restrict__ idx) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t c[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float q = floorf((xyz[3 * i + a] - lo_bad[a]) * inv_cell);
+        c[a] = (uint32_t)fminf(fmaxf(q, 0.0f), 1023.0f);
+    }
+    key[i] = spread10(c[0]) | (spread10(c[1]) << 1) | (spread10(c[2]) << 2);
+    idx[i] = i;
+}
+
 }  // namespace
 
 void mp_scan_permute(const float* rec_orig, const int32_t* perm, int32_t n, float* rec_out, hipStream_t s) {
@@ -187,7 +286,25 @@ void mp_scan_records(const float* xyz, const float* cov6, int32_t n, int32_t k, 
         k_scan_given_cov<<<(n + 255) / 256, 256, 0, s>>>(xyz, cov6, n, reinterpret_cast<float4*>(rec));
     } else {
         if (k > kKMax) mp_throw(MP_E_UNSUPPORTED, "scan_k above %d", kKMax);
-        k_scan_knn_cov<<<(n + kB - 1) / kB, kB, 0, s>>>(xyz, n, k, eps, reinterpret_cast<float4*>(rec));
+        constexpr int per = kB / kQLanes;
+        const unsigned grid = (unsigned)((n + per - 1) / per);
+        float4* r4 = reinterpret_cast<float4*>(rec);
+        if (k <= 8) k_scan_knn_cov<8><<<grid, kB, 0, s>>>(xyz, n, k, eps, r4);
+        else if (k <= 16) k_scan_knn_cov<16><<<grid, kB, 0, s>>>(xyz, n, k, eps, r4);
+        else k_scan_knn_cov<32><<<grid, kB, 0, s>>>(xyz, n, k, eps, r4);
     }
     MP_CHECK_LAUNCH();
+}
+
+void mp_scan_check(const float* xyz_dev, const float* cov6_dev, int32_t n, float* lo_bad_dev, hipStream_t s) {
+    k_scan_check<<<1, kChk, 0, s>>>(xyz_dev, cov6_dev, n, lo_bad_dev);
+    MP_CHECK_LAUNCH();
+}
+
+void mp_scan_walk_order(const float* xyz_dev, int32_t n, float cell, const float* lo_bad_dev, uint32_t* keys,
+                        uint32_t* keys_alt, int32_t* perm, int32_t* perm_alt, DevMem& scratch, hipStream_t s) {
+    if (n <= 0) return;
+    k_morton_keys<<<(n + 255) / 256, 256, 0, s>>>(xyz_dev, n, lo_bad_dev, 1.0f / cell, keys, perm);
+    MP_CHECK_LAUNCH();
+    mp_radix_sort_u32(keys, perm, keys_alt, perm_alt, n, 30, scratch, s);
 }

@@ -90,6 +90,50 @@ def test_scan_covariances_bitexact(room, O):
     assert np.median(step) < np.median(np.linalg.norm(np.diff(rec[:, :3], axis=0), axis=1))
 
 
+@pytest.mark.parametrize("k,n", [(4, 500), (20, 700), (32, 300), (10, 7), (3, 1)])
+def test_scan_covariances_k_bitexact(room, O, k, n):
+    # every neighbour-list capacity (k <= 8, <= 16, <= 32) and scans with
+    # fewer than k + 1 points (fewer than 5 points give the identity)
+    scan = np.ascontiguousarray(room["w"]["scans"][0][:n])
+    f = M.Filter(room["gpu"], _params(64, scan_k=k))
+    f.scan_upload(scan)
+    rec = f.debug_get("scan")
+    _, cov, _ = O.scan_cov(scan, k=k, eps=1e-3)
+    got = np.stack([rec[:, 3], rec[:, 4], rec[:, 5], rec[:, 6], rec[:, 7], rec[:, 8]], 1)
+    assert np.array_equal(got, cov)
+
+
+def test_scan_upload_device_and_rejects(room, O):
+    import torch
+    w = room["w"]
+    f = M.Filter(room["gpu"], _params(64))
+    f.scan_upload(w["scans"][0])
+    before = f.debug_get("scan").copy()
+    # a device-resident scan gives the same records as the host copy
+    alt = np.ascontiguousarray(w["scans"][0][::-1][:900])
+    dev = torch.from_numpy(alt).cuda()
+    f.scan_upload(dev)
+    ref = M.Filter(room["gpu"], _params(64))
+    ref.scan_upload(alt)
+    assert np.array_equal(f.debug_get("scan"), ref.debug_get("scan"))
+    assert np.array_equal(f.debug_get("scan_walk"), ref.debug_get("scan_walk"))
+    # non-finite input on the device: MP_E_ARG and the uploaded scan is kept
+    f.scan_upload(w["scans"][0])
+    bad = dev.clone()
+    bad[5, 2] = float("inf")
+    with pytest.raises(M.MegaPFError) as e:
+        f.scan_upload(bad)
+    assert e.value.status == M.MP_E_ARG
+    cov = torch.zeros((dev.shape[0], 6), dtype=torch.float32, device="cuda")
+    cov[:, 0] = cov[:, 3] = cov[:, 5] = 1.0
+    cov[7, 1] = float("nan")
+    with pytest.raises(M.MegaPFError) as e:
+        f.scan_upload(dev, cov)
+    assert e.value.status == M.MP_E_ARG
+    assert np.array_equal(f.debug_get("scan"), before)
+    f.step()
+
+
 def test_uniform_init_bitexact(room, O):
     f = M.Filter(room["gpu"], _params(3000, seed=77), box=([-1, 0, 2], [5, 6, 3]))
     P = f.debug_get("poses")
