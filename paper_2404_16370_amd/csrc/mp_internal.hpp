@@ -161,6 +161,12 @@ void mp_radix_sort_u32(uint32_t* keys, int32_t* vals, uint32_t* keys_alt, int32_
 void mp_radix_sort_u64(uint64_t* keys, int32_t* vals, uint64_t* keys_alt, int32_t* vals_alt, int64_t n, int bits,
                        DevMem& scratch, hipStream_t s);
 size_t mp_radix_scratch_bytes(int64_t n);
+// number of 8-bit passes mp_radix_sort_* makes for n keys of `bits` bits
+int mp_radix_passes(int64_t n, int bits);
+// as mp_radix_sort_u32 without the final copy: after an odd number of passes
+// the result is in (keys_alt, vals_alt)
+void mp_radix_sort_u32_inplace_parity(uint32_t* keys, int32_t* vals, uint32_t* keys_alt, int32_t* vals_alt, int64_t n,
+                                      int bits, DevMem& scratch, hipStream_t s);
 
 // map (map_build.hip)
 void mp_build_map(mp_map m, const float* xyz_dev, int64_t n, hipStream_t s);

@@ -6,7 +6,7 @@
 //                hash6(cell) & (2^bits - 1).  T^LSH is drawn from Philox for
 //                (frame, iteration); every lane derives it, lane 0 records it.
 //   sort         stable radix sort of (code, index)  -> buckets as runs
-//   k_bounds     run starts -> bucket head/end per sorted position
+//   k_bucket_bounds  bucket head/end per sorted position (search of the runs)
 //   k_refresh    one lane per sorted position: candidates = previous list U
 //                window of up to C bucket-mates after the particle (cyclic in
 //                its bucket); each ranked by q_ij = d^T W^K d (deterministic
@@ -24,8 +24,9 @@ namespace {
 
 struct LshArgs {
     const float4* __restrict__ poses;
-    uint32_t* __restrict__ codes;
-    int32_t* __restrict__ idx;
+    uint32_t* __restrict__ codes;     // particle order
+    uint32_t* __restrict__ keys;      // the bucket sort's input keys (a copy of codes)
+    int32_t* __restrict__ idx;        // the bucket sort's input values (0..n-1)
     float* __restrict__ tlsh;
     int32_t n;
     uint32_t mask, frame, it;
@@ -62,31 +63,48 @@ __global__ __launch_bounds__(256) void k_lsh(LshArgs A) {
     c[3] = mpdet::floor_i32(A.at * u.x + A.sl * z[3]);
     c[4] = mpdet::floor_i32(A.at * u.y + A.sl * z[4]);
     c[5] = mpdet::floor_i32(A.at * u.z + A.sl * z[5]);
-    A.codes[i] = mpdet::hash6(c) & A.mask;
+    const uint32_t code = mpdet::hash6(c) & A.mask;
+    A.codes[i] = code;
+    A.keys[i] = code;
     A.idx[i] = i;
 }
 
-__global__ void k_run_flags(const uint32_t* __restrict__ sc, int n, uint32_t* __restrict__ flag) {
+// Bucket head and end of every sorted position: the run of equal codes around
+// s, found by an exponential then binary search on each side (a bucket of m
+// particles costs about 2 log2(m) reads per position).
+__global__ void k_bucket_bounds(const uint32_t* __restrict__ sc, int n, int32_t* __restrict__ head,
+                                int32_t* __restrict__ end) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
-    flag[s] = (s == 0 || sc[s] != sc[s - 1]) ? 1u : 0u;
-}
-
-__global__ void k_run_starts(const uint32_t* __restrict__ flag, const uint32_t* __restrict__ rid, int n,
-                             int32_t* __restrict__ start) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n) return;
-    if (flag[s]) start[rid[s]] = s;
-}
-
-__global__ void k_bounds(const uint32_t* __restrict__ flag, const uint32_t* __restrict__ rid,
-                         const int32_t* __restrict__ start, const uint32_t* __restrict__ nruns, int n,
-                         int32_t* __restrict__ head, int32_t* __restrict__ end) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n) return;
-    const uint32_t r = rid[s] + flag[s] - 1u;  // run of position s
-    head[s] = start[r];
-    end[s] = (r + 1u < *nruns) ? start[r + 1] : n;
+    const uint32_t c = sc[s];
+    // left: lo is known to hold c, the first position holding c is in (lo - step, lo]
+    int lo = s, step = 1;
+    while (lo - step >= 0 && sc[lo - step] == c) {
+        lo -= step;
+        step <<= 1;
+    }
+    int a = max(lo - step, -1), b = lo;   // sc[a] != c (or a = -1), sc[b] == c
+    while (b - a > 1) {
+        const int mid = a + (b - a) / 2;
+        if (sc[mid] == c) b = mid;
+        else a = mid;
+    }
+    head[s] = b;
+    // right: the last position holding c is in [hi, hi + step)
+    int hi = s;
+    step = 1;
+    while (hi + step < n && sc[hi + step] == c) {
+        hi += step;
+        step <<= 1;
+    }
+    a = hi;
+    b = min(hi + step, n);   // sc[a] == c, sc[b] != c (or b = n)
+    while (b - a > 1) {
+        const int mid = a + (b - a) / 2;
+        if (sc[mid] == c) a = mid;
+        else b = mid;
+    }
+    end[s] = b;
 }
 
 struct RefreshArgs {
@@ -213,7 +231,11 @@ void mp_launch_lsh(mp_filter f, uint32_t frame, uint32_t it, hipStream_t s) {
     LshArgs A;
     A.poses = f->poses[f->cur].as<float4>();
     A.codes = f->codes.as<uint32_t>();
-    A.idx = f->sorted.as<int32_t>();
+    // the sort ping-pongs between (tmp_keys, tmp_vals) and (scodes, sorted);
+    // start it on the side that makes its last pass land in (scodes, sorted)
+    const bool odd = mp_radix_passes(f->n, f->p.lsh_bits) % 2 == 1;
+    A.keys = odd ? f->tmp_keys.as<uint32_t>() : f->scodes.as<uint32_t>();
+    A.idx = odd ? f->tmp_vals.as<int32_t>() : f->sorted.as<int32_t>();
     A.tlsh = f->tlsh.as<float>();
     A.n = f->n;
     A.mask = f->p.lsh_bits >= 32 ? 0xFFFFFFFFu : ((1u << f->p.lsh_bits) - 1u);
@@ -234,21 +256,17 @@ void mp_launch_lsh(mp_filter f, uint32_t frame, uint32_t it, hipStream_t s) {
 
 void mp_launch_sort(mp_filter f, hipStream_t s) {
     const int n = f->n;
-    // sort (code, index); codes stay in particle order in `codes`, sorted copy in `scodes`
-    MP_HIP(hipMemcpyAsync(f->scodes.p, f->codes.p, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, s));
-    mp_radix_sort_u32(f->scodes.as<uint32_t>(), f->sorted.as<int32_t>(), f->tmp_keys.as<uint32_t>(),
-                      f->tmp_vals.as<int32_t>(), n, f->p.lsh_bits, f->hist, s);
-    // bucket bounds: flags -> run ids (exclusive scan) -> run starts -> head/end per position
-    uint32_t* flag = f->tmp_keys.as<uint32_t>();
-    uint32_t* rid = reinterpret_cast<uint32_t*>(f->tmp_vals.as<int32_t>());
-    uint32_t* nruns = f->flags.as<uint32_t>() + 4;
-    k_run_flags<<<nblk(n), 256, 0, s>>>(f->scodes.as<uint32_t>(), n, flag);
-    MP_CHECK_LAUNCH();
-    mp_scan_exclusive_u32(flag, rid, n, nruns, f->red, s);
-    k_run_starts<<<nblk(n), 256, 0, s>>>(flag, rid, n, f->runs.as<int32_t>());
-    MP_CHECK_LAUNCH();
-    k_bounds<<<nblk(n), 256, 0, s>>>(flag, rid, f->runs.as<int32_t>(), nruns, n, f->head.as<int32_t>(),
-                                     f->end.as<int32_t>());
+    // stable sort of (code, index) from the buffers the LSH kernel filled;
+    // the result lands in (scodes, sorted) with no copy
+    const bool odd = mp_radix_passes(n, f->p.lsh_bits) % 2 == 1;
+    if (odd)
+        mp_radix_sort_u32_inplace_parity(f->tmp_keys.as<uint32_t>(), f->tmp_vals.as<int32_t>(),
+                                         f->scodes.as<uint32_t>(), f->sorted.as<int32_t>(), n, f->p.lsh_bits, f->hist,
+                                         s);
+    else
+        mp_radix_sort_u32_inplace_parity(f->scodes.as<uint32_t>(), f->sorted.as<int32_t>(), f->tmp_keys.as<uint32_t>(),
+                                         f->tmp_vals.as<int32_t>(), n, f->p.lsh_bits, f->hist, s);
+    k_bucket_bounds<<<nblk(n), 256, 0, s>>>(f->scodes.as<uint32_t>(), n, f->head.as<int32_t>(), f->end.as<int32_t>());
     MP_CHECK_LAUNCH();
 }
 

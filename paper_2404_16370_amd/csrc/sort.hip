@@ -182,9 +182,13 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(const K* __restrict_
     }
 }
 
+// Sorts (keys, vals) in 8-bit passes, ping-ponging with the alt arrays.  With
+// copy_back the result is always left in (keys, vals); without it the result
+// stays where the last pass wrote it, (keys_alt, vals_alt) after an odd
+// number of passes.
 template <class K>
 void radix_sort(K* keys, int32_t* vals, K* keys_alt, int32_t* vals_alt, int64_t n, int bits, DevMem& scratch,
-                hipStream_t s) {
+                hipStream_t s, bool copy_back = true) {
     if (n <= 1 || bits <= 0) return;
     const int passes = (bits + 7) / 8;
     const int64_t nb = (n + kTile - 1) / kTile;
@@ -207,7 +211,7 @@ void radix_sort(K* keys, int32_t* vals, K* keys_alt, int32_t* vals_alt, int64_t 
         std::swap(ka, kb);
         std::swap(va, vb);
     }
-    if (ka != keys) {
+    if (copy_back && ka != keys) {
         MP_HIP(hipMemcpyAsync(keys, ka, sizeof(K) * (size_t)n, hipMemcpyDeviceToDevice, s));
         MP_HIP(hipMemcpyAsync(vals, va, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToDevice, s));
     }
@@ -230,6 +234,15 @@ size_t mp_radix_scratch_bytes(int64_t n) {
 void mp_radix_sort_u32(uint32_t* keys, int32_t* vals, uint32_t* keys_alt, int32_t* vals_alt, int64_t n, int bits,
                        DevMem& scratch, hipStream_t s) {
     radix_sort<uint32_t>(keys, vals, keys_alt, vals_alt, n, bits, scratch, s);
+}
+
+int mp_radix_passes(int64_t n, int bits) {
+    return (n <= 1 || bits <= 0) ? 0 : (bits + 7) / 8;
+}
+
+void mp_radix_sort_u32_inplace_parity(uint32_t* keys, int32_t* vals, uint32_t* keys_alt, int32_t* vals_alt, int64_t n,
+                                      int bits, DevMem& scratch, hipStream_t s) {
+    radix_sort<uint32_t>(keys, vals, keys_alt, vals_alt, n, bits, scratch, s, false);
 }
 
 void mp_radix_sort_u64(uint64_t* keys, int32_t* vals, uint64_t* keys_alt, int32_t* vals_alt, int64_t n, int bits,

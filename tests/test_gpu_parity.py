@@ -190,11 +190,14 @@ def test_likelihood_parity(room, O, n, chunks, batch, backend, layout, nscan):
     print("psi max abs err %.3g, median rel %.3g" % (dpsi.max(), np.median(dpsi / (big + 1e-3))))
 
 
-def test_lsh_codes_and_sort_bitexact(room, O):
+@pytest.mark.parametrize("bits", [12, 20, 0])
+def test_lsh_codes_and_sort_bitexact(room, O, bits):
+    # 12 bits: two radix passes, 20: three (the sort starts from the other
+    # buffer pair), 0: one bucket holding every particle
     n = 5000
     w = room["w"]
     poses = _poses_mixed(w, n, 21)
-    p = _params(n, lsh_bits=12, lsh_sigma=0.3, lsh_alpha=1.0)
+    p = _params(n, lsh_bits=bits, lsh_sigma=0.3, lsh_alpha=1.0)
     f = M.Filter(room["gpu"], p, poses=poses)
     for it in (0, 3):
         f.debug_stage(M.MP_STAGE_LSH, it)
@@ -204,7 +207,7 @@ def test_lsh_codes_and_sort_bitexact(room, O):
         lo = np.array(info["box_min"], np.float32); hi = np.array(info["box_max"], np.float32)
         TLo = O.lsh_frame(4001, 0, it, lo, hi)
         assert np.array_equal(TL, TLo)
-        ref = O.lsh_codes(poses, TLo, 1.0, 5.0, 2.5, 0.3, 12, 4001, 0, it)
+        ref = O.lsh_codes(poses, TLo, 1.0, 5.0, 2.5, 0.3, bits, 4001, 0, it)
         assert np.array_equal(codes, ref)
         f.debug_stage(M.MP_STAGE_SORT)
         s, h, e = O.bucket_sort(ref)
