@@ -313,12 +313,14 @@ def surrogate_eval_main(args):
                "loss_last": float(np.mean(losses[-100:]))}
 
     # filters from the same uniform start, same odometry
-    def run_filter(scorer):
+    def run_filter(scorer, check=None):
         p = M.mp_filter_default_params(n_particles=65536, k=16, lsh_bits=20, svgd_iters=20, post_iters=10,
                                        window_c=32, d_max=1.0, seed=4002, scorer=scorer, sigma_s=args.sigma_s)
         f = M.Filter(m, p, box=(lo, hi))
         if scorer == M.MP_SCORER_SURROGATE:
             f.set_surrogate(sur)
+        if check is not None:
+            f.set_surrogate_check(*check)
         errs = []
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -336,13 +338,20 @@ def surrogate_eval_main(args):
         poses = f.debug_get("poses")
         post = f.debug_get("post").astype(np.float64)
         nbr = f.debug_get("nbr")
+        q = f.posterior_query()
         if scorer == M.MP_SCORER_SURROGATE:
             f.set_surrogate(None)
-        return dict(errors=errs, s_per_frame=dt / frames, poses=poses, post=post, nbr=nbr)
+        return dict(errors=errs, s_per_frame=dt / frames, poses=poses, post=post, nbr=nbr,
+                    fallback_steps=q["fallback_steps"], checks=q["sur_checks"], last_check_ds=q["sur_check_ds"])
 
-    runs = {name: run_filter(sc) for name, sc in (("plain", M.MP_SCORER_PLAIN),
-                                                  ("scorefield", M.MP_SCORER_SCOREFIELD),
-                                                  ("surrogate", M.MP_SCORER_SURROGATE))}
+    # the network alone, and with its check against the exact field every 10
+    # frames on 1% of the particles (fallback to PLAIN for 10 frames when the
+    # mean |delta s| exceeds 0.5)
+    runs = {name: run_filter(sc, ck) for name, sc, ck in (("plain", M.MP_SCORER_PLAIN, None),
+                                                          ("scorefield", M.MP_SCORER_SCOREFIELD, None),
+                                                          ("surrogate", M.MP_SCORER_SURROGATE, None),
+                                                          ("surrogate_checked", M.MP_SCORER_SURROGATE,
+                                                           (10, 100, 0.5, 10)))}
     for name, r in runs.items():
         log("%s: final error %.3f m %.2f deg, %.3f s/frame" % (name, r["errors"][-1][0], r["errors"][-1][1],
                                                              r["s_per_frame"]))
@@ -403,6 +412,11 @@ def surrogate_eval_main(args):
            "final_error_m_deg": fin,
            "added_error_vs_plain": {"m": fin["surrogate"][0] - fin["plain"][0],
                                     "deg": fin["surrogate"][1] - fin["plain"][1]},
+           "checked": {"added_error_vs_plain": {"m": fin["surrogate_checked"][0] - fin["plain"][0],
+                                                "deg": fin["surrogate_checked"][1] - fin["plain"][1]},
+                       "fallback_frames": runs["surrogate_checked"]["fallback_steps"],
+                       "checks": runs["surrogate_checked"]["checks"],
+                       "last_check_mean_abs_ds": runs["surrogate_checked"]["last_check_ds"]},
            "per_frame_errors": {k: r["errors"] for k, r in runs.items()},
            "s_per_frame": {k: r["s_per_frame"] for k, r in runs.items()},
            "heldout": quality, "mode_recall": recall, "modes_plain": int(len(mp_)), "modes_surrogate": int(len(ms_)),
@@ -456,7 +470,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="campus", choices=sorted(WORKLOADS) + ["batch", "surrogate-eval"])
-    ap.add_argument("--frames", type=int, default=10, help="surrogate-eval: filter frames")
+    ap.add_argument("--frames", type=int, default=30, help="surrogate-eval: filter frames")
     ap.add_argument("--train-steps", type=int, default=20000, help="surrogate-eval: Adam steps")
     ap.add_argument("--sigma-s", type=float, default=0.03, help="surrogate-eval: sensor std of the score field")
     ap.add_argument("--lr", type=float, default=1e-3, help="surrogate-eval: Adam step")

@@ -233,6 +233,9 @@ typedef struct {
     double max_loglik;     /* largest log-likelihood of the last iteration */
     int32_t frame;         /* filter steps taken */
     int32_t fp64_resolves; /* Gauss-Newton solves redone in FP64 in the last step */
+    int32_t fallback_steps; /* steps the SURROGATE scorer ran as PLAIN (mp_filter_set_surrogate_check) */
+    int32_t sur_checks;    /* surrogate checks made */
+    float sur_check_ds;    /* mean |delta s| of the last check, -1 before the first */
 } mp_posterior;
 
 /* Read the representative state and, optionally, all poses (N x 7) and the
@@ -421,6 +424,23 @@ MP_API mp_status mp_surrogate_set_params(mp_surrogate sur, const float* params, 
 /* Attach (or detach with NULL) the network the filter's SURROGATE scorer
  * uses; the network must outlive the attachment. */
 MP_API mp_status mp_filter_set_surrogate(mp_filter f, mp_surrogate sur);
+
+/* Check of the SURROGATE scorer against the exact residual field it
+ * approximates (a safeguard of the learned configuration, not of the paper):
+ * when a filter step starts at a multiple of `period` steps (period 0, the
+ * default, turns the check off) and no fallback is running, the scan points
+ * transformed by every `stride`-th particle (walk order, thinned to at most
+ * 2^22 pairs) are scored by the network and by the exact field; if the mean
+ * |min(r_net^2, c_max) - min(r^2, c_max)| exceeds `threshold` (or is not a
+ * number), that step and the next fallback - 1 run the PLAIN scorer.  Each
+ * check synchronises the stream once; mp_posterior reports the steps run as
+ * PLAIN, the checks made and the last mean difference.  Example: period 10,
+ * stride 100 (1% of the particles), threshold 0.5, fallback 10.  A filter with
+ * the check on cannot join a batch (mp_batch_create: MP_E_UNSUPPORTED).
+ * Errors: MP_E_ARG (period < 0, stride < 1, fallback < 0, threshold negative
+ * or not finite), MP_E_STATE (filter held by a batch). */
+MP_API mp_status mp_filter_set_surrogate_check(mp_filter f, int32_t period, int32_t stride, float threshold,
+                                               int32_t fallback);
 
 #ifdef __cplusplus
 }

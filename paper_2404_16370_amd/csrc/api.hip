@@ -536,7 +536,23 @@ extern "C" mp_status mp_filter_step(mp_filter f, const float dT[7], const float 
         if (dT) mp_prepare_prediction(dT, cov_dT, dq, L, noise);
         for (int st = 0; st < MP_NUM_STAGES; ++st)
             if (st != MP_STAGE_SCAN) f->ev_count[st] = 0;
+        // check of the learned scorer (before the step, on the current particles)
+        f->sur_fallback = false;
+        SurCheck& c = f->chk;
+        if (f->p.scorer == MP_SCORER_SURROGATE && c.period > 0 && f->scan_n > 0) {
+            if (c.left == 0 && f->frame % c.period == 0) {
+                c.last = mp_sur_check(f, c.stride, s);
+                ++c.checks;
+                if (!(c.last <= c.threshold)) c.left = c.fallback;
+            }
+            if (c.left > 0) {
+                f->sur_fallback = true;
+                --c.left;
+                ++c.fallback_steps;
+            }
+        }
         mp_step_launches(f, dT != nullptr, dq, L, noise, s);
+        f->sur_fallback = false;
         f->frame++;
         f->last_stream = s;
     });
@@ -566,6 +582,9 @@ extern "C" mp_status mp_posterior_query(mp_filter f, mp_posterior* out, float* p
         out->max_loglik = info[6];
         out->frame = f->frame;
         out->fp64_resolves = flags[0];
+        out->fallback_steps = f->chk.fallback_steps;
+        out->sur_checks = f->chk.checks;
+        out->sur_check_ds = f->chk.last;
         bool finite = all_finite(pose, 7) && std::isfinite(info[4]);
         const size_t N = (size_t)f->n;
         if (poses_out) {
@@ -917,6 +936,22 @@ extern "C" mp_status mp_surrogate_set_params(mp_surrogate sur, const float* para
         mp_sur_reset_adam(sur, s);
         mp_sur_publish(sur, s);
         MP_HIP(hipStreamSynchronize(s));
+    });
+}
+
+extern "C" mp_status mp_filter_set_surrogate_check(mp_filter f, int32_t period, int32_t stride, float threshold,
+                                                   int32_t fallback) {
+    return guarded("mp_filter_set_surrogate_check", [&]() {
+        if (!f) mp_throw(MP_E_ARG, "null filter");
+        if (period < 0 || stride < 1 || fallback < 0 || !(threshold >= 0.0f) || !std::isfinite(threshold))
+            mp_throw(MP_E_ARG, "period >= 0, stride >= 1, fallback >= 0 and a finite threshold >= 0 expected");
+        if (f->batch_users > 0) mp_throw(MP_E_STATE, "filter held by a batch");
+        SurCheck& c = f->chk;
+        c.period = period;
+        c.stride = stride;
+        c.threshold = threshold;
+        c.fallback = fallback;
+        c.left = 0;
     });
 }
 

@@ -78,6 +78,8 @@ void check_ready(mp_filter f) {
     if (f->scan_n < 0) mp_throw(MP_E_STATE, "every instance needs a scan (mp_scan_upload)");
     if (f->p.scorer == MP_SCORER_SURROGATE && !f->sur)
         mp_throw(MP_E_STATE, "SURROGATE scorer without a network (mp_filter_set_surrogate)");
+    if (f->p.scorer == MP_SCORER_SURROGATE && f->chk.period > 0)
+        mp_throw(MP_E_UNSUPPORTED, "the surrogate check reads its verdict on the host: not in a batch");
 }
 
 void capture(mp_batch b, hipStream_t caller) {

@@ -605,9 +605,11 @@ size_t mp_lik_partial_bytes(mp_filter f) {
 }
 
 void mp_launch_likelihood(mp_filter f, hipStream_t s) {
+    // the scorer of this step: SURROGATE runs as PLAIN while its check has it fall back
+    const int scorer = (f->p.scorer == MP_SCORER_SURROGATE && f->sur_fallback) ? (int)MP_SCORER_PLAIN : f->p.scorer;
     const int n = f->n;
     const int ns = f->scan_n;
-    const bool grouped = lik_grouped(f) && f->p.scorer != MP_SCORER_SURROGATE;
+    const bool grouped = lik_grouped(f) && scorer != MP_SCORER_SURROGATE;
     const int nbx = grouped ? (n + kGParticles - 1) / kGParticles : (n + kLanes - 1) / kLanes;
     int clen = 0;
     int nch = lik_chunks(f, clen);
@@ -631,9 +633,9 @@ void mp_launch_likelihood(mp_filter f, hipStream_t s) {
     A.ib = 1.0f / (1.0f + A.sig2);
     A.r_floor = 1e-2f;
     A.r_out = mp_residual_r_out(f->p.d_max, f->p.sigma_s, f->map->params.cov_eps);
-    if (f->p.scorer == MP_SCORER_SURROGATE && !f->sur)
+    if (scorer == MP_SCORER_SURROGATE && !f->sur)
         mp_throw(MP_E_STATE, "SURROGATE scorer without a network (mp_filter_set_surrogate)");
-    if (ns > 0 && f->p.scorer == MP_SCORER_SURROGATE) {
+    if (ns > 0 && scorer == MP_SCORER_SURROGATE) {
         nch = 1;
         f->lik_chunks = 1;
         f->lik_chunk_len = ns;
@@ -644,7 +646,7 @@ void mp_launch_likelihood(mp_filter f, hipStream_t s) {
         mp_tick(f, MP_STAGE_LIK_CORE, true, s);
         const unsigned grid = (unsigned)(A.nbx * nch);
         const bool dense = A.map.backend == MP_NNF_DENSE;
-        if (f->p.scorer == MP_SCORER_SCOREFIELD) {
+        if (scorer == MP_SCORER_SCOREFIELD) {
             if (dense) k_lik_grp<MP_NNF_DENSE, 4, MP_SCORER_SCOREFIELD><<<grid, kGThreads, 0, s>>>(A);
             else k_lik_grp<MP_NNF_HASH, 4, MP_SCORER_SCOREFIELD><<<grid, kGThreads, 0, s>>>(A);
         } else if (f->p.lik_batch == 8) {
@@ -659,7 +661,7 @@ void mp_launch_likelihood(mp_filter f, hipStream_t s) {
         }
         MP_CHECK_LAUNCH();
         mp_tick(f, MP_STAGE_LIK_CORE, false, s);
-    } else if (ns > 0 && f->p.scorer == MP_SCORER_SCOREFIELD) {
+    } else if (ns > 0 && scorer == MP_SCORER_SCOREFIELD) {
         mp_tick(f, MP_STAGE_LIK_CORE, true, s);
         if (A.map.backend == MP_NNF_DENSE)
             k_lik<MP_NNF_DENSE, 4, MP_SCORER_SCOREFIELD><<<nbx * nch, kLanes, 0, s>>>(A);

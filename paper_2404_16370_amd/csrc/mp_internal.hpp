@@ -107,9 +107,24 @@ struct FilterParamsDev {
     uint64_t seed;
 };
 
+// Check of the SURROGATE scorer against the exact residual field (off while
+// period is 0): every `period` steps; fall back to PLAIN for `fallback` steps
+// when the mean score difference exceeds `threshold`.
+struct SurCheck {
+    int32_t period = 0, stride = 100, fallback = 10;
+    float threshold = 0.5f;
+    int32_t left = 0;              // steps still to run with the PLAIN scorer
+    int32_t fallback_steps = 0;    // steps run with PLAIN in place of SURROGATE
+    int32_t checks = 0;
+    float last = -1.0f;            // mean |delta s| of the last check
+};
+
 struct mp_filter_s {
     mp_map map = nullptr;
     mp_surrogate sur = nullptr;   // network of the SURROGATE scorer
+    SurCheck chk;
+    bool sur_fallback = false;    // this step: SURROGATE scorer replaced by PLAIN
+    DevMem chk_buf;               // work arrays of the check
     const StepDyn* dyn = nullptr; // set while a step is captured into a graph
     bool capturing = false;       // no timers, no host work that a graph cannot hold
     int batch_users = 0;          // batches holding this filter
@@ -218,6 +233,9 @@ void mp_sur_reset_adam(mp_surrogate S, hipStream_t s);
 void mp_sur_publish(mp_surrogate S, hipStream_t s);
 void mp_sur_label(mp_surrogate S, const float* xyz_dev, int64_t n, float* out4_dev, bool scaled, hipStream_t s);
 void mp_sur_eval(mp_surrogate S, const float* xyz_dev, int64_t n, float* out4_dev, hipStream_t s);
+// mean |min(r_net^2, c_max) - min(r^2, c_max)| over the scan points transformed
+// by every pstride-th particle (synchronises the stream)
+float mp_sur_check(mp_filter f, int32_t pstride, hipStream_t s);
 void mp_sur_ensure_batch(mp_surrogate S, int64_t cap);
 void mp_sur_draw_batch(mp_surrogate S, int32_t n_real, bool full, uint32_t step, hipStream_t s);
 void mp_sur_grad_step(mp_surrogate S, int32_t n_real, bool update, float lr, float* loss_dev, hipStream_t s);

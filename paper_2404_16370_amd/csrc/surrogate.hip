@@ -778,6 +778,59 @@ PublishArgs publish_args(mp_surrogate S) {
     return W;
 }
 
+// ------------------------------------------------------------ scorer check
+// Scan points (every kstride-th record of the walk order) transformed by
+// every pstride-th particle: the sample on which the network is compared with
+// the exact residual field.
+struct CheckPtsArgs {
+    const float4* __restrict__ poses;
+    const float4* __restrict__ scan;
+    float* __restrict__ xyz;
+    int32_t n, pstride, ns, kstride, nk;
+    int64_t m;
+};
+
+__global__ void k_check_points(CheckPtsArgs A) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= A.m) return;
+    const int i = (int)(q / A.nk) * A.pstride;
+    const int k = (int)(q % A.nk) * A.kstride;
+    const float4 q4 = A.poses[2 * i], t4 = A.poses[2 * i + 1];
+    const mpdet::mat3 Rm = mpdet::qmat(mpdet::quat{q4.x, q4.y, q4.z, q4.w});
+    const float4 r0 = A.scan[3 * k];
+    const float3 p = mpdet::xform(Rm.m, make_float3(t4.x, t4.y, t4.z), make_float3(r0.x, r0.y, r0.z));
+    A.xyz[3 * q] = p.x;
+    A.xyz[3 * q + 1] = p.y;
+    A.xyz[3 * q + 2] = p.z;
+}
+
+constexpr int kChkBlocks = 256;
+
+// per-block sums of |min(r_net^2, c) - min(r^2, c)| (fixed grid: deterministic)
+__global__ __launch_bounds__(256) void k_check_sum(const float4* __restrict__ net, const float4* __restrict__ ref,
+                                                   int64_t m, float cmax, double* __restrict__ part) {
+    __shared__ double red[256];
+    double acc = 0.0;
+    for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < m; q += (int64_t)kChkBlocks * 256) {
+        const float a = net[q].x, b = ref[q].x;
+        acc += (double)fabsf(fminf(a * a, cmax) - fminf(b * b, cmax));
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = 128; h >= 1; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void k_check_final(const double* __restrict__ part, int64_t m, float* __restrict__ out) {
+    if (threadIdx.x != 0) return;
+    double t = 0.0;
+    for (int b = 0; b < kChkBlocks; ++b) t += part[b];
+    out[0] = (float)(t / (double)m);
+}
+
 }  // namespace
 
 // ------------------------------------------------------------ host launchers
@@ -1034,4 +1087,45 @@ void mp_sur_likelihood(mp_filter f, float* partial, hipStream_t s) {
     const int blocks = std::min(S->cus, (f->n + 3) / 4);   // no device query: this may run under graph capture
     k_lik_sur<<<std::max(1, blocks), kInferThreads, 0, s>>>(A);
     MP_CHECK_LAUNCH();
+}
+
+float mp_sur_check(mp_filter f, int32_t pstride, hipStream_t s) {
+    const int n = f->n, ns = f->scan_n;
+    if (!f->sur || n <= 0 || ns <= 0) return 0.0f;
+    const int np = (n + pstride - 1) / pstride;
+    int kstride = 1;   // keep the sample at most 2^22 pairs
+    while ((int64_t)np * ((ns + kstride - 1) / kstride) > ((int64_t)1 << 22)) ++kstride;
+    const int nk = (ns + kstride - 1) / kstride;
+    const int64_t m = (int64_t)np * nk;
+    // layout: net and ref outputs (float4), block sums (double), result, points
+    f->chk_buf.ensure(32 * (size_t)m + sizeof(double) * kChkBlocks + 16 + 12 * (size_t)m);
+    char* base = f->chk_buf.as<char>();
+    float* net = reinterpret_cast<float*>(base);
+    float* ref = reinterpret_cast<float*>(base + 16 * (size_t)m);
+    double* part = reinterpret_cast<double*>(base + 32 * (size_t)m);
+    float* res = reinterpret_cast<float*>(part + kChkBlocks);
+    float* xyz = res + 4;
+    CheckPtsArgs A;
+    A.poses = f->poses[f->cur].as<float4>();
+    A.scan = f->scan.as<float4>();
+    A.xyz = xyz;
+    A.n = n;
+    A.pstride = pstride;
+    A.ns = ns;
+    A.kstride = kstride;
+    A.nk = nk;
+    A.m = m;
+    k_check_points<<<(unsigned)((m + 255) / 256), 256, 0, s>>>(A);
+    MP_CHECK_LAUNCH();
+    mp_sur_eval(f->sur, xyz, m, net, s);
+    mp_sur_label(f->sur, xyz, m, ref, false, s);
+    k_check_sum<<<kChkBlocks, 256, 0, s>>>(reinterpret_cast<const float4*>(net), reinterpret_cast<const float4*>(ref),
+                                           m, f->p.c_max, part);
+    MP_CHECK_LAUNCH();
+    k_check_final<<<1, 64, 0, s>>>(part, m, res);
+    MP_CHECK_LAUNCH();
+    float out = 0.0f;
+    MP_HIP(hipMemcpyAsync(&out, res, sizeof(float), hipMemcpyDeviceToHost, s));
+    MP_HIP(hipStreamSynchronize(s));
+    return out;
 }

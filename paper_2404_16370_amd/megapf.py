@@ -78,7 +78,8 @@ class mp_init_desc(C.Structure):
 class mp_posterior(C.Structure):
     _fields_ = [("map_pose", C.c_float * 7), ("map_index", C.c_int32), ("map_weight", C.c_double),
                 ("n_eff", C.c_double), ("log_evidence", C.c_double), ("max_loglik", C.c_double),
-                ("frame", C.c_int32), ("fp64_resolves", C.c_int32)]
+                ("frame", C.c_int32), ("fp64_resolves", C.c_int32), ("fallback_steps", C.c_int32),
+                ("sur_checks", C.c_int32), ("sur_check_ds", C.c_float)]
 
 
 EXPORTS = ["mp_map_default_params", "mp_map_build", "mp_map_get_info", "mp_map_get_gauss", "mp_map_lookup",
@@ -87,7 +88,7 @@ EXPORTS = ["mp_map_default_params", "mp_map_build", "mp_map_get_info", "mp_map_g
            "mp_debug_set", "mp_debug_stage", "mp_surrogate_default_params", "mp_surrogate_create",
            "mp_surrogate_destroy", "mp_surrogate_get_info", "mp_surrogate_label", "mp_surrogate_eval",
            "mp_surrogate_set_data", "mp_surrogate_train", "mp_surrogate_grad", "mp_surrogate_get_params",
-           "mp_surrogate_set_params", "mp_filter_set_surrogate", "mp_batch_create", "mp_batch_step",
+           "mp_surrogate_set_params", "mp_filter_set_surrogate", "mp_filter_set_surrogate_check", "mp_batch_create", "mp_batch_step",
            "mp_batch_get_info", "mp_batch_destroy"]
 
 MP_SCORER_PLAIN, MP_SCORER_SCOREFIELD, MP_SCORER_SURROGATE = 0, 1, 2
@@ -145,6 +146,7 @@ def lib():
     L.mp_surrogate_get_params.argtypes = [vp, vp, vp]
     L.mp_surrogate_set_params.argtypes = [vp, vp, vp]
     L.mp_filter_set_surrogate.argtypes = [vp, vp]
+    L.mp_filter_set_surrogate_check.argtypes = [vp, i32, i32, C.c_float, i32]
     L.mp_batch_create.argtypes = [vp, i32, i32, vp, C.POINTER(vp)]
     L.mp_batch_step.argtypes = [vp, vp, vp, vp]
     L.mp_batch_get_info.argtypes = [vp, C.POINTER(mp_batch_info), vp, vp]
@@ -325,6 +327,11 @@ class Filter:
         _check(lib().mp_filter_set_surrogate(self.handle, sur.handle if sur is not None else None))
         self._sur = sur   # keeps the network alive while attached
 
+    def set_surrogate_check(self, period=10, stride=100, threshold=0.5, fallback=10):
+        """mp_filter_set_surrogate_check (period 0 turns the check off)"""
+        _check(lib().mp_filter_set_surrogate_check(self.handle, int(period), int(stride), float(threshold),
+                                                   int(fallback)))
+
     def scan_upload(self, xyz, cov6=None, stream=None):
         n = _nrows(xyz) if xyz is not None else 0
         keep = []
@@ -344,7 +351,8 @@ class Filter:
         _check(lib().mp_posterior_query(self.handle, C.byref(out), _ptr(P), _ptr(W), _stream(stream)))
         res = dict(map_pose=np.array(out.map_pose[:], np.float32), map_index=out.map_index,
                    map_weight=out.map_weight, n_eff=out.n_eff, log_evidence=out.log_evidence,
-                   max_loglik=out.max_loglik, frame=out.frame, fp64_resolves=out.fp64_resolves)
+                   max_loglik=out.max_loglik, frame=out.frame, fp64_resolves=out.fp64_resolves,
+                   fallback_steps=out.fallback_steps, sur_checks=out.sur_checks, sur_check_ds=out.sur_check_ds)
         if poses:
             res["poses"] = P
         if weights:

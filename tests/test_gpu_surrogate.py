@@ -249,3 +249,68 @@ def test_surrogate_filter_step(room):
     with pytest.raises(M.MegaPFError):
         sur.close()       # still attached
     f.set_surrogate(None)
+
+
+def test_surrogate_check(room, O):
+    """The scorer check (mp_filter_set_surrogate_check): its mean |delta s|
+    against the oracle (network with bf16 operands, exact residual field) on
+    the same sample; a failed check runs the PLAIN scorer (bit-identical to a
+    PLAIN filter), a passed one leaves the SURROGATE step untouched."""
+    w, info, sur = room["w"], room["info"], room["sur"]
+    P = _random_params(21, scale=0.5)
+    sur.set_params(P)
+    n, stride = 600, 10
+    scan = w["scans"][0]
+    poses = _poses(w, n, 22)
+
+    def make(scorer, check=None):
+        p = M.mp_filter_default_params(n_particles=n, k=8, lsh_bits=12, svgd_iters=2, post_iters=5, window_c=16,
+                                       d_max=1.0, c_max=9.0, seed=4003, scorer=scorer, sigma_s=0.03)
+        f = M.Filter(room["gpu"], p, poses=poses)
+        if scorer == M.MP_SCORER_SURROGATE:
+            f.set_surrogate(sur)
+        if check is not None:
+            f.set_surrogate_check(*check)
+        f.scan_upload(scan)
+        return f
+
+    plain = make(M.MP_SCORER_PLAIN)
+    guarded = make(M.MP_SCORER_SURROGATE, (3, stride, 0.0, 2))     # every check fails
+    free = make(M.MP_SCORER_SURROGATE)
+    never = make(M.MP_SCORER_SURROGATE, (3, stride, 1e30, 2))      # every check passes
+    with pytest.raises(M.MegaPFError):
+        guarded.set_surrogate_check(3, 0, 0.5, 2)
+    # expected value of the first check: every 10th particle x every scan point
+    P8 = guarded.debug_get("poses").astype(np.float64)[::stride]
+    mu = guarded.debug_get("scan_walk")[:, :3].astype(np.float64)
+    pts = []
+    for q in P8:
+        R = S.quat_to_mat(q[:4] / np.linalg.norm(q[:4]))
+        pts.append(mu @ R.T + q[4:7])
+    pts = np.concatenate(pts).astype(np.float32)
+    r_ref, _ = O.residual_field(room["ora"], pts, sigma_s=0.03, dmax=1.0)
+    r_net = _oracle_forward(O, info, P, pts)[:, 0] * info["r_scale"]
+    ds_ref = np.mean(np.abs(np.minimum(r_net ** 2, 9.0) - np.minimum(r_ref ** 2, 9.0)))
+    for step in range(4):
+        for f in (plain, guarded, free, never):
+            f.step()
+        qg = guarded.posterior_query()
+        if step == 0:
+            print("check: GPU mean |ds| %.5f, oracle %.5f" % (qg["sur_check_ds"], ds_ref))
+            assert abs(qg["sur_check_ds"] - ds_ref) <= 2e-2 * ds_ref + 2e-2
+        if step < 2:   # frames 0 and 1 fall back to PLAIN
+            assert np.array_equal(guarded.debug_get("poses"), plain.debug_get("poses"))
+            assert np.array_equal(guarded.debug_get("psi"), plain.debug_get("psi"))
+        assert np.array_equal(never.debug_get("poses"), free.debug_get("poses"))
+    qg, qn, qf = guarded.posterior_query(), never.posterior_query(), free.posterior_query()
+    # frame 0: check, fallback for 2 steps; frame 2: no check; frame 3: check, fallback
+    assert (qg["sur_checks"], qg["fallback_steps"]) == (2, 3)
+    assert (qn["sur_checks"], qn["fallback_steps"]) == (2, 0) and qn["sur_check_ds"] >= 0
+    assert (qf["sur_checks"], qf["fallback_steps"], qf["sur_check_ds"]) == (0, 0, -1.0)
+    with pytest.raises(M.MegaPFError) as e:
+        M.Batch([guarded], autotune=False)
+    assert e.value.status == M.MP_E_UNSUPPORTED
+    for f in (guarded, free, never):
+        f.set_surrogate(None)
+    for f in (plain, guarded, free, never):
+        f.close()
