@@ -73,6 +73,24 @@ def test_nnf_lookup_bitexact(room, O, backend):
     assert np.array_equal(m.lookup(q), room["ora"].lookup(q))
 
 
+def test_dense_grid_limits():
+    # two clusters 2100 m apart along x and y: a 4200 x 4200-cell z plane at
+    # 0.5 m voxels is more than 2^24 cells, beyond the dense grid's indexing
+    rng = np.random.default_rng(0)
+    a = rng.normal(0, 0.05, (200, 3))
+    pts = np.concatenate([a, a + np.array([2100.0, 2100.0, 0.0])]).astype(np.float32)
+    m = M.Map(pts, voxel=0.5)
+    assert m.info()["backend"] == M.MP_NNF_HASH
+    with pytest.raises(M.MegaPFError) as e:
+        M.Map(pts, voxel=0.5, backend=M.MP_NNF_DENSE)
+    assert e.value.status == M.MP_E_UNSUPPORTED
+    # a small map stays dense and answers lookups like the hashed one
+    small = M.Map(a.astype(np.float32), voxel=0.5)
+    assert small.info()["backend"] == M.MP_NNF_DENSE
+    q = rng.uniform(-2, 2, (5000, 3)).astype(np.float32)
+    assert np.array_equal(small.lookup(q), M.Map(a.astype(np.float32), voxel=0.5, backend=M.MP_NNF_HASH).lookup(q))
+
+
 def test_scan_covariances_bitexact(room, O):
     w = room["w"]
     scan = w["scans"][0]
@@ -150,15 +168,25 @@ P_, G_ = M.MP_LIK_LAYOUT_PARTICLE, M.MP_LIK_LAYOUT_GROUPED
     (1000, 0, 0, M.MP_NNF_HASH, P_, 1000), (300, 2, 4, M.MP_NNF_HASH, P_, 1000),
     # grouped layout: chunks of 1024 points (2 chunks, ragged), partials by sorted position
     (1000, 0, 0, M.MP_NNF_DENSE, G_, 1700), (257, 0, 8, M.MP_NNF_DENSE, G_, 1700), (1, 0, 2, M.MP_NNF_DENSE, G_, 1000),
-    (300, 0, 4, M.MP_NNF_HASH, G_, 1700)])
+    (300, 0, 4, M.MP_NNF_HASH, G_, 1700),
+    # scans shorter than one grouped batch step (5 points, 1 point), and the
+    # largest scan the library takes (65,536 points: 64 chunks)
+    (100, 0, 2, M.MP_NNF_DENSE, G_, 5), (64, 0, 0, M.MP_NNF_DENSE, G_, 1), (40, 0, 0, M.MP_NNF_DENSE, G_, 65536),
+    (40, 0, 0, M.MP_NNF_DENSE, P_, 65536)])
 def test_likelihood_parity(room, O, n, chunks, batch, backend, layout, nscan):
     w = room["w"]
     scan = w["scans"][0]
-    if nscan > len(scan):
-        # a longer scan: the first points again, shifted by 1 cm so that no point repeats exactly
-        extra = scan[:nscan - len(scan)] + np.float32(0.01)
-        scan = np.ascontiguousarray(np.concatenate([scan, extra]).astype(np.float32))
-    _, scov, _ = O.scan_cov(scan, k=10)
+    if nscan <= len(scan):
+        scan = np.ascontiguousarray(scan[:nscan])
+        _, scov, _ = O.scan_cov(scan, k=10)
+    else:
+        # a longer scan: the points again, shifted by 1 cm per repetition so
+        # that no point repeats exactly, with the covariances of their originals
+        _, cov0, _ = O.scan_cov(scan, k=10)
+        reps = -(-nscan // len(scan))
+        scan = np.concatenate([scan + np.float32(0.01 * r) for r in range(reps)])[:nscan]
+        scan = np.ascontiguousarray(scan.astype(np.float32))
+        scov = np.ascontiguousarray(np.tile(cov0, (reps, 1))[:nscan])
     poses = _poses_mixed(w, n, 10 + n)
     gmap = room["gpu"] if backend == M.MP_NNF_DENSE else M.Map(w["map_xyz"], voxel=0.5, backend=backend)
     assert gmap.info()["backend"] == backend
