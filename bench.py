@@ -114,12 +114,22 @@ def cpu_baseline(wl, w, scan, budget_s=15.0):
     per_particle_iter = dt / m
     step_s = per_particle_iter * wl["particles"] * wl["svgd_iters"]
     evals = wl["scan_points"] * m
-    return {"value": 1.0 / step_s, "unit": "filter steps/s", "cores": O.num_threads(), "kind": "oracle",
+    cores = O.num_threads()
+    # the same iteration on one thread, on a sample sized for about a quarter of the budget
+    m1 = int(max(16, min(m, m * 0.25 * budget_s / max(dt * cores, 1e-3))))
+    O.set_threads(1)
+    t0 = time.perf_counter()
+    one_iteration(poses[:m1])
+    dt1 = time.perf_counter() - t0
+    O.set_threads(cores)
+    single = {"evals_per_s": wl["scan_points"] * m1 / dt1,
+              "steps_per_s": 1.0 / (dt1 / m1 * wl["particles"] * wl["svgd_iters"]), "sample_particles": m1}
+    return {"value": 1.0 / step_s, "unit": "filter steps/s", "cores": cores, "kind": "oracle",
             "sample": ("one correction iteration (LSH, sort, refresh, likelihood+GN, SVGD) of %d of the "
                        "workload's particles x %d scan points, %.1f s; scaled to %d particles x %d iterations "
                        "(posterior and prediction not included)" %
                        (m, wl["scan_points"], dt, wl["particles"], wl["svgd_iters"])),
-            "evals_per_s": evals / dt, "map_build_s": t_map}
+            "evals_per_s": evals / dt, "map_build_s": t_map, "single_core": single}
 
 
 def surrogate_leg(M, m, wl, minfo, scans, odo, warmup, steps):

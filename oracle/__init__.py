@@ -106,6 +106,8 @@ def _declare(L):
     L.mpo_chol6.argtypes = [_f64p, _f64p]; L.mpo_chol6.restype = C.c_int
     L.mpo_predict.argtypes = [_f32p, C.c_int64, _f32p, _vp, C.c_uint64, C.c_uint32, _f64p]
     L.mpo_num_threads.restype = C.c_int
+    L.mpo_set_threads.argtypes = [C.c_int]
+    L.mpo_set_threads.restype = None
     L.mpo_score_field.argtypes = [_vp, _f32p, C.c_int64, C.c_float, C.c_float, _f64p, _f64p, _i32p]
     L.mpo_residual_field.argtypes = [_vp, _f32p, C.c_int64, C.c_float, C.c_float, C.c_double, C.c_double, _f64p,
                                      _f64p]
@@ -454,6 +456,11 @@ def adam(params, grads, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
 
 def num_threads() -> int:
     return int(lib().mpo_num_threads())
+
+
+def set_threads(n: int) -> None:
+    """OpenMP threads of the oracle's parallel loops (timing only)"""
+    lib().mpo_set_threads(int(n))
 
 
 def poses7_to_8(p7):

@@ -1197,6 +1197,15 @@ MPO_API int mpo_num_threads(void) {
 #endif
 }
 
+/* threads of the timing loops (results do not depend on it) */
+MPO_API void mpo_set_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ======================================================================= */
 /* Learned surrogate of the map's per-point score.                          */
 /*                                                                          */
