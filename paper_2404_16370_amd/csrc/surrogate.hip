@@ -110,11 +110,14 @@ __host__ __device__ inline int frag3_index(int i, int o) {  // W3[i][o]
     return ((s2 * 4 + o) * 2 + h) * 8 + j;
 }
 
-// ------------------------------------------------------------ network on 64 points
-// Lane L supplies the normalised coordinates of point L%32 of tile 0 (xa[0])
-// and tile 1 (xa[1]); on return lane L holds the 4 outputs of point L%32 of
-// tile L/32.  img points at the inference image (LDS).
-__device__ __forceinline__ void mlp64(const char* __restrict__ img, const float xa[2][3], float y[4]) {
+// ------------------------------------------------------------ network on 32 points
+// One tile of 32 points per call (accumulators and activations of one tile
+// only, so that two waves share each SIMD).  Lane L supplies the normalised
+// coordinates x of point L%32 of tile tt; the output layer writes the tile's
+// 4 outputs into accumulator rows 4 tt .. 4 tt + 3, which lane half tt holds:
+// on return the lanes L with L/32 == tt hold the outputs of point L%32 (the
+// other half's y is left as it was).  img points at the inference image (LDS).
+__device__ __forceinline__ void mlp32(const char* __restrict__ img, const float x[3], const int tt, float y[4]) {
     const int lane = threadIdx.x & 63, m = lane & 31, h = lane >> 5;
     const bf16x8* f1 = reinterpret_cast<const bf16x8*>(img + kImgF1);
     const bf16x8* f2 = reinterpret_cast<const bf16x8*>(img + kImgF2);
@@ -124,93 +127,68 @@ __device__ __forceinline__ void mlp64(const char* __restrict__ img, const float 
     const float* b3 = reinterpret_cast<const float*>(img + kImgB3);
     const float* fq = reinterpret_cast<const float*>(img + kImgFQ);
 
-    f32x16 acc[2][4];
+    f32x16 acc[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const float4 bb = *reinterpret_cast<const float4*>(b1 + 32 * r + 8 * q + 4 * h);
-#pragma unroll
-            for (int tt = 0; tt < 2; ++tt) {
-                acc[tt][r][4 * q] = bb.x;
-                acc[tt][r][4 * q + 1] = bb.y;
-                acc[tt][r][4 * q + 2] = bb.z;
-                acc[tt][r][4 * q + 3] = bb.w;
-            }
+            acc[r][4 * q] = bb.x;
+            acc[r][4 * q + 1] = bb.y;
+            acc[r][4 * q + 2] = bb.z;
+            acc[r][4 * q + 3] = bb.w;
         }
     // layer 1: k-step s covers axis s/4, frequencies 8 (s%4) + 4 h + 0..3 (sin, cos each)
 #pragma unroll
     for (int s = 0; s < 12; ++s) {
         const float4 fr = *reinterpret_cast<const float4*>(fq + 8 * (s & 3) + 4 * h);
-        bf16x8 bx[2];
+        const float xs = x[s >> 2];
+        __bf16 v0, v1, v2, v3, v4, v5, v6, v7;
+        feature_pair(fr.x, xs, v0, v1);
+        feature_pair(fr.y, xs, v2, v3);
+        feature_pair(fr.z, xs, v4, v5);
+        feature_pair(fr.w, xs, v6, v7);
+        const bf16x8 bx = bf16x8{v0, v1, v2, v3, v4, v5, v6, v7};
 #pragma unroll
-        for (int tt = 0; tt < 2; ++tt) {
-            const float x = xa[tt][s >> 2];
-            __bf16 v0, v1, v2, v3, v4, v5, v6, v7;
-            feature_pair(fr.x, x, v0, v1);
-            feature_pair(fr.y, x, v2, v3);
-            feature_pair(fr.z, x, v4, v5);
-            feature_pair(fr.w, x, v6, v7);
-            bx[tt] = bf16x8{v0, v1, v2, v3, v4, v5, v6, v7};
-        }
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const bf16x8 af = f1[(r * 12 + s) * 64 + lane];
-            acc[0][r] = mfma32(af, bx[0], acc[0][r]);
-            acc[1][r] = mfma32(af, bx[1], acc[1][r]);
-        }
+        for (int r = 0; r < 4; ++r) acc[r] = mfma32(f1[(r * 12 + s) * 64 + lane], bx, acc[r]);
     }
-    bf16x8 hb[2][8];
+    bf16x8 hb[8];
 #pragma unroll
-    for (int tt = 0; tt < 2; ++tt)
+    for (int s2 = 0; s2 < 8; ++s2)
 #pragma unroll
-        for (int s2 = 0; s2 < 8; ++s2)
-#pragma unroll
-            for (int j = 0; j < 8; ++j) hb[tt][s2][j] = (__bf16)silu_f(acc[tt][s2 >> 1][8 * (s2 & 1) + j]);
+        for (int j = 0; j < 8; ++j) hb[s2][j] = (__bf16)silu_f(acc[s2 >> 1][8 * (s2 & 1) + j]);
     // layer 2
 #pragma unroll
     for (int r = 0; r < 4; ++r)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const float4 bb = *reinterpret_cast<const float4*>(b2 + 32 * r + 8 * q + 4 * h);
-#pragma unroll
-            for (int tt = 0; tt < 2; ++tt) {
-                acc[tt][r][4 * q] = bb.x;
-                acc[tt][r][4 * q + 1] = bb.y;
-                acc[tt][r][4 * q + 2] = bb.z;
-                acc[tt][r][4 * q + 3] = bb.w;
-            }
+            acc[r][4 * q] = bb.x;
+            acc[r][4 * q + 1] = bb.y;
+            acc[r][4 * q + 2] = bb.z;
+            acc[r][4 * q + 3] = bb.w;
         }
 #pragma unroll
     for (int s2 = 0; s2 < 8; ++s2)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const bf16x8 af = f2[(r * 8 + s2) * 64 + lane];
-            acc[0][r] = mfma32(af, hb[0][s2], acc[0][r]);
-            acc[1][r] = mfma32(af, hb[1][s2], acc[1][r]);
-        }
+        for (int r = 0; r < 4; ++r) acc[r] = mfma32(f2[(r * 8 + s2) * 64 + lane], hb[s2], acc[r]);
 #pragma unroll
-    for (int tt = 0; tt < 2; ++tt)
+    for (int s2 = 0; s2 < 8; ++s2)
 #pragma unroll
-        for (int s2 = 0; s2 < 8; ++s2)
-#pragma unroll
-            for (int j = 0; j < 8; ++j) hb[tt][s2][j] = (__bf16)silu_f(acc[tt][s2 >> 1][8 * (s2 & 1) + j]);
-    // layer 3: tile tt's outputs in rows 4 tt .. 4 tt + 3 (other A rows zero),
-    // both tiles accumulated into one tile: lane half h then holds tile h
+        for (int j = 0; j < 8; ++j) hb[s2][j] = (__bf16)silu_f(acc[s2 >> 1][8 * (s2 & 1) + j]);
+    // layer 3: outputs in rows 4 tt .. 4 tt + 3 (other A rows zero)
     f32x16 o = {};
     const bf16x8 zero = {};
+    const int o3 = m - 4 * tt;
+    const bool row = o3 >= 0 && o3 < 4;
 #pragma unroll
-    for (int s2 = 0; s2 < 8; ++s2)
-#pragma unroll
-        for (int tt = 0; tt < 2; ++tt) {
-            const int o3 = m - 4 * tt;
-            const bf16x8 af = (o3 >= 0 && o3 < 4) ? f3[(s2 * 4 + o3) * 2 + h] : zero;
-            o = mfma32(af, hb[tt][s2], o);
-        }
-    y[0] = o[0] + b3[0];
-    y[1] = o[1] + b3[1];
-    y[2] = o[2] + b3[2];
-    y[3] = o[3] + b3[3];
+    for (int s2 = 0; s2 < 8; ++s2) o = mfma32(row ? f3[(s2 * 4 + o3) * 2 + h] : zero, hb[s2], o);
+    if (h == tt) {
+        y[0] = o[0] + b3[0];
+        y[1] = o[1] + b3[1];
+        y[2] = o[2] + b3[2];
+        y[3] = o[3] + b3[3];
+    }
 }
 
 __device__ __forceinline__ void load_image(const uint4* __restrict__ src, uint4* dst) {
@@ -621,7 +599,7 @@ __global__ void k_adam(AdamArgs A) {
 }
 
 // ------------------------------------------------------------ inference kernels
-constexpr int kInferThreads = 256;
+constexpr int kInferThreads = 512;   // 8 waves: two per SIMD share one LDS copy of the weights
 
 struct EvalArgs {
     const uint4* __restrict__ img;
@@ -650,8 +628,10 @@ __global__ __launch_bounds__(kInferThreads) void k_sur_eval(EvalArgs A) {
 #pragma unroll
             for (int a = 0; a < 3; ++a) xa[tt][a] = ((v ? A.xyz[3 * k + a] : A.lo[a]) - A.lo[a]) * A.inv[a];
         }
-        float y[4];
-        mlp64(img, xa, y);
+        float y[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        mlp32(img, xa[0], 0, y);
+        asm volatile("" ::: "memory");
+        mlp32(img, xa[1], 1, y);
         const int64_t k = g * 64 + 32 * h + m;
         if (k < A.n) A.out[k] = make_float4(y[0] * A.r_scale, y[1] * A.g_scale, y[2] * A.g_scale, y[3] * A.g_scale);
     }
@@ -711,8 +691,10 @@ __global__ __launch_bounds__(kInferThreads) void k_lik_sur(SurLikArgs A) {
                 xa[tt][2] = (p.z - A.lo[2]) * A.inv[2];
                 if (tt == h) mu_mine = mu;
             }
-            float y[4];
-            mlp64(img, xa, y);
+            float y[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+            mlp32(img, xa[0], 0, y);
+            asm volatile("" ::: "memory");
+            mlp32(img, xa[1], 1, y);
             // rank-1 terms of the predicted residual: g = [mu x w; w], w = R^T grad r,
             // H += g g^T, b += r g, cost min(r^2, c_max) (r^2 >= c_max: outlier)
             const bool valid = k0 + 32 * h + m < A.ns;
@@ -900,7 +882,7 @@ void mp_sur_eval(mp_surrogate S, const float* xyz_dev, int64_t n, float* out4_de
     A.r_scale = S->info.r_scale;
     A.g_scale = S->info.g_scale;
     const int64_t groups = (n + 63) / 64;
-    const int64_t blocks = std::min<int64_t>((int64_t)S->cus, (groups + 3) / 4);
+    const int64_t blocks = std::min<int64_t>((int64_t)S->cus, (groups + kInferThreads / 64 - 1) / (kInferThreads / 64));
     k_sur_eval<<<(unsigned)std::max<int64_t>(1, blocks), kInferThreads, 0, s>>>(A);
     MP_CHECK_LAUNCH();
 }
@@ -1084,7 +1066,8 @@ void mp_sur_likelihood(mp_filter f, float* partial, hipStream_t s) {
         A.lo[a] = S->info.lo[a];
         A.inv[a] = S->info.inv_ext[a];
     }
-    const int blocks = std::min(S->cus, (f->n + 3) / 4);   // no device query: this may run under graph capture
+    // one workgroup per CU (the weights fill its LDS); no device query: this may run under graph capture
+    const int blocks = std::min(S->cus, (f->n + kInferThreads / 64 - 1) / (kInferThreads / 64));
     k_lik_sur<<<std::max(1, blocks), kInferThreads, 0, s>>>(A);
     MP_CHECK_LAUNCH();
 }
