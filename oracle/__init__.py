@@ -108,6 +108,12 @@ def _declare(L):
     L.mpo_num_threads.restype = C.c_int
     L.mpo_set_threads.argtypes = [C.c_int]
     L.mpo_set_threads.restype = None
+    L.mpo_gicp_terms.argtypes = [_f32p, _f32p, C.c_int32, _f32p, _f32p, C.c_int32, _f32p, C.c_float, _i32p, _f64p,
+                                 _f64p, _f64p, _i32p]
+    L.mpo_gicp_terms.restype = None
+    L.mpo_gicp_align.argtypes = [_f32p, _f32p, C.c_int32, _f32p, _f32p, C.c_int32, _f64p, C.c_int32, C.c_float,
+                                 C.c_double, C.c_double, C.c_double, _f64p, _f64p, _f64p, _i32p]
+    L.mpo_gicp_align.restype = C.c_int
     L.mpo_score_field.argtypes = [_vp, _f32p, C.c_int64, C.c_float, C.c_float, _f64p, _f64p, _i32p]
     L.mpo_residual_field.argtypes = [_vp, _f32p, C.c_int64, C.c_float, C.c_float, C.c_double, C.c_double, _f64p,
                                      _f64p]
@@ -473,3 +479,28 @@ def poses7_to_8(p7):
 if __name__ == "__main__":  # pragma: no cover
     print(build())
     sys.exit(0)
+
+
+def gicp_terms(target_xyz, target_cov, source_xyz, source_cov, pose7, dmax=1.0):
+    """GICP terms of the current (source) scan against the previous (target)
+    scan at pose dT (7: qw qx qy qz tx ty tz): correspondences (-1 outside
+    d_max), H (21 upper entries), b, cost, inliers"""
+    TX = _f32(target_xyz).reshape(-1, 3); TC = _f32(target_cov).reshape(-1, 6)
+    SX = _f32(source_xyz).reshape(-1, 3); SC = _f32(source_cov).reshape(-1, 6)
+    nn = np.zeros(max(SX.shape[0], 1), np.int32)
+    H = np.zeros(21); b = np.zeros(6); c = np.zeros(1); ni = np.zeros(1, np.int32)
+    lib().mpo_gicp_terms(TX, TC, TX.shape[0], SX, SC, SX.shape[0], _f32(pose7), dmax, nn, H, b, c, ni)
+    return dict(nn=nn[:SX.shape[0]], H21=H, b=b, cost=float(c[0]), ninl=int(ni[0]))
+
+
+def gicp_align(target_xyz, target_cov, source_xyz, source_cov, init7=None, iters=20, dmax=1.0, lam_rel=1e-3,
+               lam_abs=1e-6, cov_scale=1.0):
+    """dT after `iters` damped Gauss-Newton updates from init7 (identity if
+    None), Sigma^dT = cov_scale * H^-1 at the final pose, and H, cost, inliers there"""
+    TX = _f32(target_xyz).reshape(-1, 3); TC = _f32(target_cov).reshape(-1, 6)
+    SX = _f32(source_xyz).reshape(-1, 3); SC = _f32(source_cov).reshape(-1, 6)
+    pose = np.array([1, 0, 0, 0, 0, 0, 0], np.float64) if init7 is None else np.array(init7[:7], np.float64)
+    cov = np.zeros(36); H = np.zeros(21); c = np.zeros(1); ni = np.zeros(1, np.int32)
+    rc = lib().mpo_gicp_align(TX, TC, TX.shape[0], SX, SC, SX.shape[0], pose, iters, dmax, lam_rel, lam_abs,
+                              cov_scale, cov, H, c, ni)
+    return dict(pose=pose, cov=cov.reshape(6, 6), H21=H, cost=float(c[0]), ninl=int(ni[0]), ok=rc == 0)

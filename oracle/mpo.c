@@ -1531,3 +1531,138 @@ MPO_API void mpo_likelihood_rank1(const mpo_map* m, const float* sxyz, int32_t n
         free(buf);
     }
 }
+
+/* ======================================================================= */
+/* GICP scan-to-scan odometry (Sec. III-B: the motion estimate dT and its  */
+/* covariance that feed Eq. (1); GICP after Segal et al. 2009).            */
+/* Source = the current scan (points mu_k, covariances S_k), target = the  */
+/* previous scan (points q_j, covariances T_j); dT maps current-frame      */
+/* points into the previous frame.  For pose (R, t):                       */
+/*   p_k = R mu_k + t (FP32, the filter's transform program);              */
+/*   j(k) = argmin_j |q_j - p_k|^2 in FP32 with the fma order of the        */
+/*          likelihood's residual gate, ties to the lower index;           */
+/*   inlier iff that distance^2 <= d_max^2;                                 */
+/*   then in FP64: e = q_j - p, C = T_j + R S_k R^T, Omega = C^-1,          */
+/*   J = [R [mu]x, -R], H += J^T Omega J, b += J^T Omega e,                 */
+/*   cost += e^T Omega e.                                                   */
+/* Gauss-Newton: psi from the damped system of the filter, dT <- dT exp(psi)*/
+/* for a fixed number of iterations; Sigma^dT = scale * H^-1 at the final   */
+/* pose (the covariance "based on the Hessian").                            */
+/* ======================================================================= */
+static int32_t gicp_nn(const float* txyz, int32_t nt, const float p[3], float* d2_out) {
+    int32_t best = -1;
+    float bd = INFINITY;
+    for (int32_t j = 0; j < nt; ++j) {
+        const float dx = txyz[3 * (int64_t)j] - p[0], dy = txyz[3 * (int64_t)j + 1] - p[1],
+                    dz = txyz[3 * (int64_t)j + 2] - p[2];
+        const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+        if (d2 < bd) { bd = d2; best = j; }
+    }
+    *d2_out = bd;
+    return best;
+}
+
+MPO_API void mpo_gicp_terms(const float* txyz, const float* tcov, int32_t nt, const float* sxyz, const float* scov,
+                            int32_t ns, const float pose[7], float dmax, int32_t* nn, double H21[21], double b6[6],
+                            double* cost, int32_t* ninl) {
+    const float dmax2 = dmax * dmax;
+    q32 q = {pose[0], pose[1], pose[2], pose[3]};
+    float R32[9];
+    q32_to_R(q, R32);
+    const float t32[3] = {pose[4], pose[5], pose[6]};
+    double qd[4] = {pose[0], pose[1], pose[2], pose[3]}, R[9], Rt[9];
+    qd_to_R(qd, R);
+    mat3_T(R, Rt);
+    const double t[3] = {pose[4], pose[5], pose[6]};
+    double H[36], b[6], c = 0.0;
+    memset(H, 0, sizeof(H));
+    memset(b, 0, sizeof(b));
+    int32_t ni = 0;
+    /* correspondences (independent per point), then the sums in point order */
+    int32_t* jj = (int32_t*)malloc(sizeof(int32_t) * (size_t)(ns > 0 ? ns : 1));
+#pragma omp parallel for schedule(static)
+    for (int32_t k = 0; k < ns; ++k) {
+        float p32[3], d2;
+        xform32(R32, t32, sxyz + 3 * (int64_t)k, p32);
+        const int32_t j = gicp_nn(txyz, nt, p32, &d2);
+        jj[k] = (j >= 0 && d2 <= dmax2) ? j : -1;
+    }
+    for (int32_t k = 0; k < ns; ++k) {
+        const float* ms = sxyz + 3 * (int64_t)k;
+        const int32_t j = jj[k];
+        if (nn) nn[k] = j;
+        if (j < 0) continue;
+        ++ni;
+        const double mu[3] = {ms[0], ms[1], ms[2]};
+        double p[3], e[3];
+        for (int a = 0; a < 3; ++a) p[a] = R[3 * a] * mu[0] + R[3 * a + 1] * mu[1] + R[3 * a + 2] * mu[2] + t[a];
+        for (int a = 0; a < 3; ++a) e[a] = (double)txyz[3 * (int64_t)j + a] - p[a];
+        double T6[6], S6[6], TT[9], SS[9], tmp[9], RSR[9], C[9], Om[9];
+        for (int a = 0; a < 6; ++a) { T6[a] = tcov[6 * (int64_t)j + a]; S6[a] = scov[6 * (int64_t)k + a]; }
+        sym6_full(T6, TT);
+        sym6_full(S6, SS);
+        mat3_mul(R, SS, tmp);
+        mat3_mul(tmp, Rt, RSR);
+        for (int a = 0; a < 9; ++a) C[a] = TT[a] + RSR[a];
+        mat3_inv(C, Om);
+        double Oe[3];
+        for (int a = 0; a < 3; ++a) Oe[a] = Om[3 * a] * e[0] + Om[3 * a + 1] * e[1] + Om[3 * a + 2] * e[2];
+        c += e[0] * Oe[0] + e[1] * Oe[1] + e[2] * Oe[2];
+        const double Sk[9] = {0, -mu[2], mu[1], mu[2], 0, -mu[0], -mu[1], mu[0], 0};
+        double RS[9], J[18], OJ[18];
+        mat3_mul(R, Sk, RS);
+        for (int a = 0; a < 3; ++a)
+            for (int cc = 0; cc < 3; ++cc) { J[6 * a + cc] = RS[3 * a + cc]; J[6 * a + 3 + cc] = -R[3 * a + cc]; }
+        for (int a = 0; a < 3; ++a)
+            for (int cc = 0; cc < 6; ++cc)
+                OJ[6 * a + cc] = Om[3 * a] * J[cc] + Om[3 * a + 1] * J[6 + cc] + Om[3 * a + 2] * J[12 + cc];
+        for (int r = 0; r < 6; ++r) {
+            for (int cc = 0; cc < 6; ++cc) H[6 * r + cc] += J[r] * OJ[cc] + J[6 + r] * OJ[6 + cc] + J[12 + r] * OJ[12 + cc];
+            b[r] += J[r] * Oe[0] + J[6 + r] * Oe[1] + J[12 + r] * Oe[2];
+        }
+    }
+    free(jj);
+    int q2 = 0;
+    for (int r = 0; r < 6; ++r)
+        for (int cc = r; cc < 6; ++cc) H21[q2++] = H[6 * r + cc];
+    memcpy(b6, b, sizeof(b));
+    *cost = c;
+    *ninl = ni;
+}
+
+/* pose_io: in = initial dT (7), out = final dT (FP64, normalised quaternion);
+   decisions of every iteration use the pose rounded to FP32 */
+MPO_API int mpo_gicp_align(const float* txyz, const float* tcov, int32_t nt, const float* sxyz, const float* scov,
+                           int32_t ns, double pose_io[7], int32_t iters, float dmax, double lam_rel, double lam_abs,
+                           double cov_scale, double cov36[36], double H21_out[21], double* cost_out, int32_t* ninl_out) {
+    double H21[21], b6[6], c = 0.0;
+    int32_t ni = 0;
+    for (int it = 0; it <= iters; ++it) {
+        float p32[7];
+        for (int k = 0; k < 7; ++k) p32[k] = (float)pose_io[k];
+        mpo_gicp_terms(txyz, tcov, nt, sxyz, scov, ns, p32, dmax, NULL, H21, b6, &c, &ni);
+        if (it == iters) break;
+        double psi[6], D[7], T[7];
+        mpo_gn_step(H21, b6, lam_rel, lam_abs, psi);
+        mpo_se3_exp(psi, D);
+        se3_compose(pose_io, D, T);
+        const double nq = sqrt(T[0] * T[0] + T[1] * T[1] + T[2] * T[2] + T[3] * T[3]);
+        for (int k = 0; k < 4; ++k) T[k] /= nq;
+        memcpy(pose_io, T, sizeof(T));
+    }
+    if (H21_out) memcpy(H21_out, H21, sizeof(H21));
+    if (cost_out) *cost_out = c;
+    if (ninl_out) *ninl_out = ni;
+    /* Sigma = scale * H^-1 (columns by Cholesky solves) */
+    double A[36], e[6], col[6];
+    int q = 0;
+    for (int i = 0; i < 6; ++i)
+        for (int j = i; j < 6; ++j) { A[6 * i + j] = H21[q]; A[6 * j + i] = H21[q]; ++q; }
+    int rc = 0;
+    for (int jcol = 0; jcol < 6; ++jcol) {
+        for (int i = 0; i < 6; ++i) e[i] = (i == jcol) ? 1.0 : 0.0;
+        if (chol6_solve(A, e, col) != 0) { rc = -1; memset(col, 0, sizeof(col)); }
+        for (int i = 0; i < 6; ++i) cov36[6 * i + jcol] = cov_scale * col[i];
+    }
+    return rc;
+}
