@@ -425,6 +425,52 @@ MP_API mp_status mp_surrogate_set_params(mp_surrogate sur, const float* params, 
  * uses; the network must outlive the attachment. */
 MP_API mp_status mp_filter_set_surrogate(mp_filter f, mp_surrogate sur);
 
+/* ------------------------------------------------------------ odometry */
+
+/* GICP scan-to-scan odometry (Sec. III-B): the sensor motion dT between the
+ * filter's previous and current scan (the last two non-empty mp_scan_upload
+ * calls) and its covariance from the Hessian of the match, the dT and
+ * Sigma^dT that mp_filter_step's prediction takes (Eq. 1).  dT maps points of
+ * the current scan's frame into the previous scan's frame (T_t = T_{t-1} dT).
+ * Each scan point p_k = R mu_k + t is matched to the nearest point of the
+ * previous scan (FP32 squared distance, ties to the lower index; a match
+ * farther than d_max is dropped); GICP term with C = T_j + R S_k R^T (both
+ * scans' GICP-normalised covariances); `iterations` damped Gauss-Newton
+ * updates dT <- dT exp(psi) with the filter's damping; then
+ * Sigma^dT = cov_scale * H^-1 at the final pose (the paper gives no scale;
+ * with GICP-normalised covariances H^-1 is in units of the normalised
+ * residuals, so the scale sets the prediction noise). */
+typedef struct {
+    int32_t iterations;   /* Gauss-Newton updates, 0..1000 (0: evaluate at the initial dT) */
+    float d_max;          /* correspondence gate, metres, > 0 */
+    float lambda_rel;     /* damping: H_ii (1 + lambda_rel) + lambda_abs */
+    float lambda_abs;
+    float cov_scale;      /* Sigma^dT = cov_scale * H^-1, > 0 */
+} mp_odometry_params;
+
+typedef struct {
+    double H[21];         /* GICP Hessian at the final dT (upper triangle, row-major, [omega; v]) */
+    double b[6];          /* gradient there */
+    double cost;          /* sum of e^T Omega e over the matches */
+    int32_t inliers;      /* matches within d_max */
+    int32_t iterations;
+    int32_t cov_ok;       /* 0 if H was not positive definite (covariance zeroed) */
+    double dT64[7];       /* the final dT before rounding to FP32 */
+} mp_odometry_result;
+
+/* Defaults: iterations 20, d_max 1.0, lambda_rel 1e-3, lambda_abs 1e-6,
+ * cov_scale 1. */
+MP_API void mp_odometry_default_params(mp_odometry_params* p);
+
+/* init_dT (nullable: identity) is the starting motion; dT_out (7 floats,
+ * required), cov_out (36 floats, nullable, row-major over [omega; v]) and
+ * result (nullable) are host pointers; synchronises the stream.  Errors:
+ * MP_E_ARG (null filter / params / dT_out, parameters out of range, non-finite
+ * or zero-quaternion init_dT), MP_E_STATE (fewer than two non-empty scans
+ * uploaded). */
+MP_API mp_status mp_odometry(mp_filter f, const mp_odometry_params* params, const float init_dT[7], float dT_out[7],
+                             float cov_out[36], mp_odometry_result* result, void* stream);
+
 /* Check of the SURROGATE scorer against the exact residual field it
  * approximates (a safeguard of the learned configuration, not of the paper):
  * when a filter step starts at a multiple of `period` steps (period 0, the

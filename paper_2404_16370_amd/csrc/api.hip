@@ -381,7 +381,6 @@ extern "C" mp_status mp_scan_upload(mp_filter f, const float* xyz, const float* 
         if (n > 0) {
             f->scan_xyz.ensure(sizeof(float) * 3 * (size_t)n);
             f->scan.ensure(sizeof(float) * 12 * (size_t)n);
-            f->scan_orig.ensure(sizeof(float) * 12 * (size_t)n);
             f->scan_perm.ensure(sizeof(int32_t) * (size_t)n);
             f->scan_work.ensure(sizeof(uint32_t) * (4 * (size_t)n + 4));
             f->scan_sort.ensure(mp_radix_scratch_bytes(n));
@@ -401,6 +400,13 @@ extern "C" mp_status mp_scan_upload(mp_filter f, const float* xyz, const float* 
             MP_HIP(hipMemcpyAsync(&bad, lo_bad + 3, sizeof(float), hipMemcpyDeviceToHost, s));
             MP_HIP(hipStreamSynchronize(s));
             if (bad != 0.0f) mp_throw(MP_E_ARG, cov6 ? "non-finite scan point or covariance" : "non-finite scan point");
+            // the current records become the previous scan's (odometry)
+            if (f->orig_n > 0) {
+                f->scan_orig.swap(f->prev_orig);
+                f->prev_n = f->orig_n;
+            }
+            f->scan_orig.ensure(sizeof(float) * 12 * (size_t)n);
+            f->orig_n = n;
             f->ev_count[MP_STAGE_SCAN] = 0;
             mp_tick(f, MP_STAGE_SCAN, true, s);
             // Walk order for the likelihood: Morton order of the points on a grid of half the
@@ -656,6 +662,7 @@ static NamedBuf lookup_buf(mp_filter f, const char* name) {
     if (s == "post0") return {f->post0.p, 4 * N, false};
     if (s == "scan") return {f->scan_orig.p, f->scan_n > 0 ? 48 * (size_t)f->scan_n : 0, false};
     if (s == "scan_walk") return {f->scan.p, f->scan_n > 0 ? 48 * (size_t)f->scan_n : 0, false};
+    if (s == "odo_nn") return {f->odo_nn.p, f->odo_nn.p && f->scan_n > 0 ? 4 * (size_t)f->scan_n : 0, false};
     if (s == "tlsh") return {f->tlsh.p, 32, false};
     mp_throw(MP_E_ARG, "unknown buffer '%s'", s.c_str());
 }

@@ -1,5 +1,6 @@
 // mp_internal.hpp -- library-internal structures and stage launchers.
 #pragma once
+#include <utility>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -40,6 +41,10 @@ struct DevMem {
     void ensure(size_t b);         // grow if smaller
     void release();
     template <class T> T* as() const { return static_cast<T*>(p); }
+    void swap(DevMem& o) {
+        std::swap(p, o.p);
+        std::swap(bytes, o.bytes);
+    }
 };
 
 // ------------------------------------------------------------ map
@@ -152,6 +157,10 @@ struct mp_filter_s {
     DevMem scan_orig;         // n x 12 float records in the caller's order
     DevMem scan_perm;         // n int32: walk position -> caller index
     DevMem scan_xyz;          // n x 3 float staging
+    DevMem prev_orig;         // the previous non-empty scan's records (caller order), for odometry
+    int32_t prev_n = 0;       // its points (0: none yet)
+    int32_t orig_n = 0;       // points of the records in scan_orig (the last non-empty scan)
+    DevMem odo_terms, odo_nn, odo_state;   // odometry work arrays
     DevMem scan_cov;          // n x 6 float staging of caller covariances
     DevMem scan_work;         // walk-order keys and work arrays (4n words) + lo/bad (4 floats)
     DevMem scan_sort;         // radix-sort scratch of the walk order

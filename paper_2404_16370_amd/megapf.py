@@ -53,6 +53,16 @@ class mp_filter_params(C.Structure):
                 ("seed", C.c_uint64)]
 
 
+class mp_odometry_params(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("d_max", C.c_float), ("lambda_rel", C.c_float),
+                ("lambda_abs", C.c_float), ("cov_scale", C.c_float)]
+
+
+class mp_odometry_result(C.Structure):
+    _fields_ = [("H", C.c_double * 21), ("b", C.c_double * 6), ("cost", C.c_double), ("inliers", C.c_int32),
+                ("iterations", C.c_int32), ("cov_ok", C.c_int32), ("dT64", C.c_double * 7)]
+
+
 class mp_batch_info(C.Structure):
     _fields_ = [("n_instances", C.c_int32), ("captures", C.c_int32), ("evals_per_step", C.c_int64)]
 
@@ -88,7 +98,7 @@ EXPORTS = ["mp_map_default_params", "mp_map_build", "mp_map_get_info", "mp_map_g
            "mp_debug_set", "mp_debug_stage", "mp_surrogate_default_params", "mp_surrogate_create",
            "mp_surrogate_destroy", "mp_surrogate_get_info", "mp_surrogate_label", "mp_surrogate_eval",
            "mp_surrogate_set_data", "mp_surrogate_train", "mp_surrogate_grad", "mp_surrogate_get_params",
-           "mp_surrogate_set_params", "mp_filter_set_surrogate", "mp_filter_set_surrogate_check", "mp_batch_create", "mp_batch_step",
+           "mp_surrogate_set_params", "mp_filter_set_surrogate", "mp_filter_set_surrogate_check", "mp_odometry_default_params", "mp_odometry", "mp_batch_create", "mp_batch_step",
            "mp_batch_get_info", "mp_batch_destroy"]
 
 MP_SCORER_PLAIN, MP_SCORER_SCOREFIELD, MP_SCORER_SURROGATE = 0, 1, 2
@@ -147,6 +157,9 @@ def lib():
     L.mp_surrogate_set_params.argtypes = [vp, vp, vp]
     L.mp_filter_set_surrogate.argtypes = [vp, vp]
     L.mp_filter_set_surrogate_check.argtypes = [vp, i32, i32, C.c_float, i32]
+    L.mp_odometry_default_params.argtypes = [C.POINTER(mp_odometry_params)]
+    L.mp_odometry_default_params.restype = None
+    L.mp_odometry.argtypes = [vp, C.POINTER(mp_odometry_params), vp, vp, vp, C.POINTER(mp_odometry_result), vp]
     L.mp_batch_create.argtypes = [vp, i32, i32, vp, C.POINTER(vp)]
     L.mp_batch_step.argtypes = [vp, vp, vp, vp]
     L.mp_batch_get_info.argtypes = [vp, C.POINTER(mp_batch_info), vp, vp]
@@ -279,6 +292,7 @@ _DEBUG_LAYOUT = {  # name -> (dtype, shape as a function of (n, K, scan_n))
     "post0": (np.float32, lambda n, K, s: (n,)),
     "scan": (np.float32, lambda n, K, s: (s, 12)),
     "scan_walk": (np.float32, lambda n, K, s: (s, 12)),
+    "odo_nn": (np.int32, lambda n, K, s: (s,)),
     "tlsh": (np.float32, lambda n, K, s: (8,)),
 }
 
@@ -331,6 +345,26 @@ class Filter:
         """mp_filter_set_surrogate_check (period 0 turns the check off)"""
         _check(lib().mp_filter_set_surrogate_check(self.handle, int(period), int(stride), float(threshold),
                                                    int(fallback)))
+
+    def odometry(self, init=None, stream=None, **kw):
+        """mp_odometry: dT (7), Sigma^dT (6 x 6) and the match's H, b, cost,
+        inliers between the last two non-empty scans; keywords override
+        mp_odometry_params fields"""
+        p = mp_odometry_params()
+        lib().mp_odometry_default_params(C.byref(p))
+        for k, v in kw.items():
+            if not hasattr(p, k):
+                raise TypeError("unknown odometry parameter %r" % k)
+            setattr(p, k, v)
+        keep = []
+        dT = np.zeros(7, np.float32)
+        cov = np.zeros(36, np.float32)
+        res = mp_odometry_result()
+        _check(lib().mp_odometry(self.handle, C.byref(p), _ptr(init, np.float32, keep), _ptr(dT), _ptr(cov),
+                                 C.byref(res), _stream(stream)))
+        return dict(dT=dT, cov=cov.reshape(6, 6), H21=np.array(res.H[:]), b=np.array(res.b[:]), cost=res.cost,
+                    inliers=res.inliers, iterations=res.iterations, cov_ok=bool(res.cov_ok),
+                    dT64=np.array(res.dT64[:]))
 
     def scan_upload(self, xyz, cov6=None, stream=None):
         n = _nrows(xyz) if xyz is not None else 0
