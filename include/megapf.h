@@ -471,6 +471,36 @@ MP_API void mp_odometry_default_params(mp_odometry_params* p);
 MP_API mp_status mp_odometry(mp_filter f, const mp_odometry_params* params, const float init_dT[7], float dT_out[7],
                              float cov_out[36], mp_odometry_result* result, void* stream);
 
+/* ------------------------------------------------------------ smoothing */
+
+/* Smoothing of the representative pose (Sec. IV-A: the maximum-posterior
+ * particle jitters from frame to frame; simple trajectory smoothing removes
+ * it).  Host code, no GPU work.  mp_smoother_push takes a frame's
+ * representative pose (e.g. mp_posterior.map_pose) and the motion dT since
+ * the previous push (nullable: none).  The track keeps the last `window`
+ * accepted poses, each carried forward by the reported motion (T <- T dT).
+ * A pose within jump_m / jump_rad of the carried newest one is accepted; a
+ * farther one (the maximum on another mode for a frame, or a recovery after
+ * a kidnap) is held back until switch_frames consecutive far poses agree
+ * with each other, which then replace the track.  The output is
+ * T_new exp(mean_i log(T_new^-1 T_i)) over the track (FP64 inside). */
+typedef struct {
+    int32_t window;        /* poses averaged, 1..1024 */
+    float jump_m;          /* a pose farther than this translation, metres (> 0), */
+    float jump_rad;        /* ... or this rotation, radians (> 0), is far */
+    int32_t switch_frames; /* consecutive agreeing far poses that move the track, 1..1024 */
+} mp_smoother_params;
+typedef struct mp_smoother_s* mp_smoother;
+
+/* Defaults: window 5, jump_m 1.0, jump_rad 0.2, switch_frames 3. */
+MP_API void mp_smoother_default_params(mp_smoother_params* p);
+/* Errors: MP_E_ARG (null, window, switch_frames or thresholds out of range), MP_E_OOM. */
+MP_API mp_status mp_smoother_create(const mp_smoother_params* params, mp_smoother* out);
+/* pose, dT, out: host arrays of 7 floats (qw qx qy qz tx ty tz).  Errors:
+ * MP_E_ARG (null smoother / pose / out, non-finite values, zero quaternion). */
+MP_API mp_status mp_smoother_push(mp_smoother s, const float pose[7], const float dT[7], float out[7]);
+MP_API mp_status mp_smoother_destroy(mp_smoother s);
+
 /* Check of the SURROGATE scorer against the exact residual field it
  * approximates (a safeguard of the learned configuration, not of the paper):
  * when a filter step starts at a multiple of `period` steps (period 0, the

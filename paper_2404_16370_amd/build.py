@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmegapf.so")
 SOURCES = ["api.hip", "map_build.hip", "scan.hip", "sort.hip", "neighbors.hip", "likelihood.hip",
-           "filter_kernels.hip", "surrogate.hip", "batch.hip", "odometry.hip"]
+           "filter_kernels.hip", "surrogate.hip", "batch.hip", "odometry.hip", "smoother.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off",

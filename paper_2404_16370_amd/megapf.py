@@ -63,6 +63,10 @@ class mp_odometry_result(C.Structure):
                 ("iterations", C.c_int32), ("cov_ok", C.c_int32), ("dT64", C.c_double * 7)]
 
 
+class mp_smoother_params(C.Structure):
+    _fields_ = [("window", C.c_int32), ("jump_m", C.c_float), ("jump_rad", C.c_float), ("switch_frames", C.c_int32)]
+
+
 class mp_batch_info(C.Structure):
     _fields_ = [("n_instances", C.c_int32), ("captures", C.c_int32), ("evals_per_step", C.c_int64)]
 
@@ -98,7 +102,8 @@ EXPORTS = ["mp_map_default_params", "mp_map_build", "mp_map_get_info", "mp_map_g
            "mp_debug_set", "mp_debug_stage", "mp_surrogate_default_params", "mp_surrogate_create",
            "mp_surrogate_destroy", "mp_surrogate_get_info", "mp_surrogate_label", "mp_surrogate_eval",
            "mp_surrogate_set_data", "mp_surrogate_train", "mp_surrogate_grad", "mp_surrogate_get_params",
-           "mp_surrogate_set_params", "mp_filter_set_surrogate", "mp_filter_set_surrogate_check", "mp_odometry_default_params", "mp_odometry", "mp_batch_create", "mp_batch_step",
+           "mp_surrogate_set_params", "mp_filter_set_surrogate", "mp_filter_set_surrogate_check", "mp_odometry_default_params", "mp_odometry", "mp_smoother_default_params",
+           "mp_smoother_create", "mp_smoother_push", "mp_smoother_destroy", "mp_batch_create", "mp_batch_step",
            "mp_batch_get_info", "mp_batch_destroy"]
 
 MP_SCORER_PLAIN, MP_SCORER_SCOREFIELD, MP_SCORER_SURROGATE = 0, 1, 2
@@ -160,6 +165,11 @@ def lib():
     L.mp_odometry_default_params.argtypes = [C.POINTER(mp_odometry_params)]
     L.mp_odometry_default_params.restype = None
     L.mp_odometry.argtypes = [vp, C.POINTER(mp_odometry_params), vp, vp, vp, C.POINTER(mp_odometry_result), vp]
+    L.mp_smoother_default_params.argtypes = [C.POINTER(mp_smoother_params)]
+    L.mp_smoother_default_params.restype = None
+    L.mp_smoother_create.argtypes = [C.POINTER(mp_smoother_params), C.POINTER(vp)]
+    L.mp_smoother_push.argtypes = [vp, vp, vp, vp]
+    L.mp_smoother_destroy.argtypes = [vp]
     L.mp_batch_create.argtypes = [vp, i32, i32, vp, C.POINTER(vp)]
     L.mp_batch_step.argtypes = [vp, vp, vp, vp]
     L.mp_batch_get_info.argtypes = [vp, C.POINTER(mp_batch_info), vp, vp]
@@ -551,3 +561,36 @@ class Batch:
         _check(lib().mp_batch_get_info(self.handle, C.byref(i), _ptr(lb), _ptr(ll)))
         return dict(n_instances=i.n_instances, captures=i.captures, evals_per_step=i.evals_per_step,
                     lik_batch=[int(x) for x in lb], lik_layout=[int(x) for x in ll])
+
+
+class Smoother:
+    """mp_smoother_*: smoothing of the representative pose"""
+
+    def __init__(self, **kw):
+        p = mp_smoother_params()
+        lib().mp_smoother_default_params(C.byref(p))
+        for k, v in kw.items():
+            if not hasattr(p, k):
+                raise TypeError("unknown smoother parameter %r" % k)
+            setattr(p, k, v)
+        h = C.c_void_p()
+        _check(lib().mp_smoother_create(C.byref(p), C.byref(h)))
+        self.handle = h
+
+    def push(self, pose, dT=None):
+        keep = []
+        out = np.zeros(7, np.float32)
+        _check(lib().mp_smoother_push(self.handle, _ptr(pose, np.float32, keep), _ptr(dT, np.float32, keep),
+                                      _ptr(out)))
+        return out
+
+    def close(self):
+        if self.handle:
+            _check(lib().mp_smoother_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

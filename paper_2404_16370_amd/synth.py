@@ -599,9 +599,19 @@ def surrogate_samples(map_xyz, lo, hi, n, seed, sigma=0.25, uniform_frac=0.1) ->
     return out[rng.permutation(n)]
 
 
-def build_workload(name, map_points=None, scan_points=None, frames=None, seed_offset=0):
-    """Scene, map points, ground-truth trajectory, scans and odometry of a workload."""
+def build_workload(name, map_points=None, scan_points=None, frames=None, seed_offset=0, kidnap_frame=None,
+                   kidnap_dist=None, occlusion=None):
+    """Scene, map points, ground-truth trajectory, scans and odometry of a workload.
+
+    kidnap_frame / kidnap_dist override the workload's teleport (the odometry
+    keeps reporting an ordinary step there); occlusion = (first, end) blanks
+    the scans of frames first .. end - 1 (the sensor view is blocked, the
+    odometry keeps reporting the motion)."""
     w = dict(WORKLOADS[name])
+    if kidnap_frame is not None:
+        w["kidnap_frame"] = kidnap_frame
+    if kidnap_dist is not None:
+        w["kidnap_dist"] = kidnap_dist
     c = SEEDS[name] + seed_offset
     scene = w["scene"](1000 + c)
     n_map = map_points or w["map_points"]
@@ -613,10 +623,14 @@ def build_workload(name, map_points=None, scan_points=None, frames=None, seed_of
         p = random_free_point(scene, rng)
         traj = [(random_rotation(rng), p)]
     else:
-        traj = trajectory(scene, n_frames, w["step"], w["yaw_deg"], 2200 + c, w.get("kidnap_frame"))
+        traj = trajectory(scene, n_frames, w["step"], w["yaw_deg"], 2200 + c, w.get("kidnap_frame"),
+                          kidnap_dist=w.get("kidnap_dist", 80.0))
     scans, odo = [], []
     for f, (R, t) in enumerate(traj):
-        scans.append(make_scan(scene, R, t, n_scan, w["scan_sigma"], 2300 + c + 7919 * f))
+        if occlusion is not None and occlusion[0] <= f < occlusion[1]:
+            scans.append(np.zeros((0, 3), np.float32))
+        else:
+            scans.append(make_scan(scene, R, t, n_scan, w["scan_sigma"], 2300 + c + 7919 * f))
         if f > 0:
             kid = w.get("kidnap_frame") is not None and f == w.get("kidnap_frame")
             hint = None
