@@ -77,7 +77,7 @@ def _declare(L):
     L.mpo_init_uniform.argtypes = [C.c_uint64, C.c_int64, _f32p, _f32p, _f32p]
     L.mpo_hash6.argtypes = [_i32p]; L.mpo_hash6.restype = C.c_uint32
     L.mpo_lsh_codes.argtypes = [_f32p, C.c_int64, _f32p, C.c_float, C.c_float, C.c_float, C.c_float, C.c_int,
-                                C.c_uint64, C.c_uint32, C.c_uint32, _u32p, _vp]
+                                C.c_uint64, C.c_uint32, C.c_uint32, C.c_int32, _u32p, _vp]
     L.mpo_eig3.argtypes = [_f64p, _f64p, _f64p]
     L.mpo_voxel_of.argtypes = [_f32p, C.c_int64, C.c_float, _i32p]
     L.mpo_map_build.argtypes = [_f32p, C.c_int64, C.c_float, C.c_int, C.c_int, C.c_float]
@@ -99,7 +99,9 @@ def _declare(L):
     L.mpo_se3_exp.argtypes = [_f64p, _f64p]
     L.mpo_se3_log.argtypes = [_f64p, _f64p]
     L.mpo_se3_between.argtypes = [_f32p, _f32p, _f64p]
-    L.mpo_svgd.argtypes = [_f32p, C.c_int64, _f64p, _i32p, C.c_int32, C.c_float, C.c_float, _vp, _f64p]
+    L.mpo_svgd.argtypes = [_f32p, C.c_int64, _f64p, _i32p, C.c_int32, C.c_float, C.c_float, C.c_int32, C.c_int32,
+                           _vp, _f64p]
+    L.mpo_se3_jr_inv.argtypes = [_f64p, _f64p]; L.mpo_se3_jr_inv.restype = C.c_int32
     L.mpo_posterior.argtypes = [_f64p, _f64p, C.c_int64, _i32p, _f64p, C.c_int32, C.c_int32, C.c_double,
                                 C.c_double, _vp, _f64p, C.POINTER(C.c_double)]
     L.mpo_posterior.restype = C.c_int64
@@ -188,12 +190,14 @@ def init_uniform(seed, n, lo, hi):
     return P
 
 
-def lsh_codes(poses8, TL, alpha, sigma_r, sigma_t, sigma_lsh, bits, seed, frame, it, want_cells=False):
+def lsh_codes(poses8, TL, alpha, sigma_r, sigma_t, sigma_lsh, bits, seed, frame, it, want_cells=False, tangent=0):
+    """tangent 0: decoupled [log(R_L^T R_i); R_L^T (t_i - t_L)]; 1: coupled log(T_LSH^-1 T_i)"""
     P = _f32(poses8)
     n = P.shape[0]
     codes = np.zeros(n, np.uint32)
     cells = np.zeros((n, 6), np.int32) if want_cells else None
-    lib().mpo_lsh_codes(P, n, _f32(TL), alpha, sigma_r, sigma_t, sigma_lsh, bits, seed, frame, it, codes, _ptr(cells))
+    lib().mpo_lsh_codes(P, n, _f32(TL), alpha, sigma_r, sigma_t, sigma_lsh, bits, seed, frame, it, int(tangent), codes,
+                        _ptr(cells))
     return (codes, cells) if want_cells else codes
 
 
@@ -331,13 +335,21 @@ def se3_between(Ti, Tj):
 
 
 # --------------------------------------------------------------------- SVGD / posterior / prediction
-def svgd(poses8, psi, nbr, sigma_r, sigma_t):
+def se3_jr_inv(xi):
+    """inverse right Jacobian of SE(3), tangent order [rotation; translation]"""
+    J = np.zeros((6, 6))
+    if lib().mpo_se3_jr_inv(np.ascontiguousarray(xi, np.float64), J) != 0:
+        raise ValueError("J_r singular")
+    return J
+
+
+def svgd(poses8, psi, nbr, sigma_r, sigma_t, grad_exact=False, transport=False):
     P = _f32(poses8).reshape(-1, 8)
     n = P.shape[0]
     nb = np.ascontiguousarray(nbr, np.int32).reshape(n, -1)
     phi = np.zeros((n, 6)); out = np.zeros((n, 7))
     lib().mpo_svgd(P, n, np.ascontiguousarray(psi, np.float64).reshape(n, 6), nb, nb.shape[1], sigma_r, sigma_t,
-                   _ptr(phi), out)
+                   int(bool(grad_exact)), int(bool(transport)), _ptr(phi), out)
     return phi, out
 
 

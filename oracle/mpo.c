@@ -226,9 +226,11 @@ static void q32_log(q32 q, float om[3], float* w_out, float* scale_out) {
     if (scale_out) *scale_out = sc;
 }
 
-/* Kernel distance key q_ij = d^T W d with d = log(T_i^-1 T_j) (Eq. 7-8).
- * Deterministic FP32: it ranks neighbours (Alg. 1). */
-MPO_API float mpo_det_qdist(const float* Ti, const float* Tj, float sigma_r, float sigma_t) {
+/* d = log(T_i^-1 T_j) with the coupled SE(3) logarithm (Eq. 8): the
+ * rotation vector om of conj(q_i) q_j and rho = V(om)^-1 R_i^T (t_j - t_i).
+ * Deterministic FP32: it decides neighbour ranks and, in the coupled LSH
+ * tangent, cells. */
+static void se3_between32(const float* Ti, const float* Tj, float om[3], float rho[3]) {
     q32 qi = {Ti[0], Ti[1], Ti[2], Ti[3]}, qj = {Tj[0], Tj[1], Tj[2], Tj[3]};
     q32 qr = q32_mul(q32_conj(qi), qj);
     float R[9];
@@ -236,7 +238,7 @@ MPO_API float mpo_det_qdist(const float* Ti, const float* Tj, float sigma_r, flo
     float dt[3] = {Tj[4] - Ti[4], Tj[5] - Ti[5], Tj[6] - Ti[6]};
     float tr[3];
     rotT32(R, dt, tr);
-    float om[3], w, sc;
+    float w, sc;
     q32_log(qr, om, &w, &sc);
     float th2 = (om[0] * om[0] + om[1] * om[1]) + om[2] * om[2];
     float beta;
@@ -250,8 +252,15 @@ MPO_API float mpo_det_qdist(const float* Ti, const float* Tj, float sigma_r, flo
     /* rho = V^-1 t = t - 1/2 om x t + beta om x (om x t) */
     float c1[3] = {om[1] * tr[2] - om[2] * tr[1], om[2] * tr[0] - om[0] * tr[2], om[0] * tr[1] - om[1] * tr[0]};
     float c2[3] = {om[1] * c1[2] - om[2] * c1[1], om[2] * c1[0] - om[0] * c1[2], om[0] * c1[1] - om[1] * c1[0]};
-    float rho[3];
     for (int k = 0; k < 3; ++k) rho[k] = (tr[k] - 0.5f * c1[k]) + beta * c2[k];
+}
+
+/* Kernel distance key q_ij = d^T W d with d = log(T_i^-1 T_j) (Eq. 7-8).
+ * Deterministic FP32: it ranks neighbours (Alg. 1). */
+MPO_API float mpo_det_qdist(const float* Ti, const float* Tj, float sigma_r, float sigma_t) {
+    float om[3], rho[3];
+    se3_between32(Ti, Tj, om, rho);
+    float th2 = (om[0] * om[0] + om[1] * om[1]) + om[2] * om[2];
     float rr = (rho[0] * rho[0] + rho[1] * rho[1]) + rho[2] * rho[2];
     return sigma_r * th2 + sigma_t * rr;
 }
@@ -321,13 +330,17 @@ static int32_t floor_to_i32(float z) {
     return (int32_t)f;
 }
 
-/* LSH code of Eq. (9)-(10) with the decoupled tangent
- *   zeta = alpha * W^K [log(R_L^T R_i); R_L^T (t_i - t_L)] + delta_i,
- * delta_i = sigma_lsh * N(0, I6) drawn per particle, cell = floor(zeta),
- * code = hash6(cell) & (2^bits - 1).  Deterministic FP32. */
+/* LSH code of Eq. (9)-(10):
+ *   zeta = alpha * W^K x_i + delta_i,  delta_i = sigma_lsh * N(0, I6) drawn
+ *   per particle,  cell = floor(zeta),  code = hash6(cell) & (2^bits - 1),
+ * with the tangent x_i of T_i at T^LSH either
+ *   tangent 0 (decoupled)  [log(R_L^T R_i); R_L^T (t_i - t_L)]
+ *   tangent 1 (coupled)    log(T_LSH^-1 T_i), the SE(3) logarithm of Eq. (8).
+ * Deterministic FP32.  Pinned by cells of zeta computed in FP64 (rotation
+ * vectors, matrix logarithm) away from cell boundaries. */
 MPO_API void mpo_lsh_codes(const float* poses, int64_t n, const float TL[8], float alpha, float sigma_r,
                            float sigma_t, float sigma_lsh, int bits, uint64_t seed, uint32_t frame, uint32_t it,
-                           uint32_t* codes, int32_t* cells /* nullable n*6 */) {
+                           int32_t tangent, uint32_t* codes, int32_t* cells /* nullable n*6 */) {
     uint32_t mask = bits >= 32 ? 0xFFFFFFFFu : ((1u << bits) - 1u);
     float ar = alpha * sigma_r, at = alpha * sigma_t;
     q32 qL = {TL[0], TL[1], TL[2], TL[3]};
@@ -336,13 +349,16 @@ MPO_API void mpo_lsh_codes(const float* poses, int64_t n, const float TL[8], flo
     q32 qLc = q32_conj(qL);
     for (int64_t i = 0; i < n; ++i) {
         const float* T = poses + 8 * i;
-        q32 qi = {T[0], T[1], T[2], T[3]};
-        q32 qr = q32_mul(qLc, qi);
-        float om[3];
-        q32_log(qr, om, NULL, NULL);
-        float dt[3] = {T[4] - TL[4], T[5] - TL[5], T[6] - TL[6]};
-        float u[3];
-        rotT32(RL, dt, u);
+        float om[3], u[3];
+        if (tangent == 1) {
+            se3_between32(TL, T, om, u);
+        } else {
+            q32 qi = {T[0], T[1], T[2], T[3]};
+            q32 qr = q32_mul(qLc, qi);
+            q32_log(qr, om, NULL, NULL);
+            float dt[3] = {T[4] - TL[4], T[5] - TL[5], T[6] - TL[6]};
+            rotT32(RL, dt, u);
+        }
         float z6[6];
         mpo_gauss6(seed, (uint32_t)i, frame, it, MPO_PURPOSE_LSH, z6);
         int32_t c[6];
@@ -1034,24 +1050,127 @@ static void se3_inv(const double A[7], double B[7]) {
 
 static void pose_to_d(const float* p, double T[7]) { for (int k = 0; k < 7; ++k) T[k] = (double)p[k]; }
 
-/* d_ij = log(T_i^-1 T_j) in FP64 (Eq. 8) */
-MPO_API void mpo_se3_between(const float* Ti, const float* Tj, double d[6]) {
-    double A[7], B[7], Ai[7], C[7];
+/* T_i^-1 T_j in FP64 */
+static void se3_rel(const float* Ti, const float* Tj, double C[7]) {
+    double A[7], B[7], Ai[7];
     pose_to_d(Ti, A);
     pose_to_d(Tj, B);
     se3_inv(A, Ai);
     se3_compose(Ai, B, C);
+}
+
+/* d_ij = log(T_i^-1 T_j) in FP64 (Eq. 8) */
+MPO_API void mpo_se3_between(const float* Ti, const float* Tj, double d[6]) {
+    double C[7];
+    se3_rel(Ti, Tj, C);
     mpo_se3_log(C, d);
+}
+
+/* ad of xi = [om; rho] in the tangent order [rotation; translation]:
+ * [[om^, 0], [rho^, om^]], row-major 6x6 */
+static void se3_ad(const double xi[6], double A[36]) {
+    memset(A, 0, sizeof(double) * 36);
+    for (int blk = 0; blk < 3; ++blk) {
+        const double* v = blk == 1 ? xi + 3 : xi;
+        int r0 = blk == 0 ? 0 : 3, c0 = blk == 2 ? 3 : 0;
+        A[6 * (r0 + 0) + c0 + 1] = -v[2]; A[6 * (r0 + 0) + c0 + 2] = v[1];
+        A[6 * (r0 + 1) + c0 + 0] = v[2];  A[6 * (r0 + 1) + c0 + 2] = -v[0];
+        A[6 * (r0 + 2) + c0 + 0] = -v[1]; A[6 * (r0 + 2) + c0 + 1] = v[0];
+    }
+}
+
+/* inverse of a 6x6 matrix by Gauss-Jordan elimination with partial pivoting;
+ * returns 0 when a pivot vanishes */
+static int inv6(const double A_in[36], double X[36]) {
+    double A[36];
+    memcpy(A, A_in, sizeof(A));
+    for (int r = 0; r < 6; ++r)
+        for (int c = 0; c < 6; ++c) X[6 * r + c] = r == c ? 1.0 : 0.0;
+    for (int c = 0; c < 6; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < 6; ++r)
+            if (fabs(A[6 * r + c]) > fabs(A[6 * piv + c])) piv = r;
+        if (A[6 * piv + c] == 0.0) return 0;
+        for (int k = 0; k < 6; ++k) {
+            double t = A[6 * c + k]; A[6 * c + k] = A[6 * piv + k]; A[6 * piv + k] = t;
+            t = X[6 * c + k]; X[6 * c + k] = X[6 * piv + k]; X[6 * piv + k] = t;
+        }
+        double ip = 1.0 / A[6 * c + c];
+        for (int k = 0; k < 6; ++k) { A[6 * c + k] *= ip; X[6 * c + k] *= ip; }
+        for (int r = 0; r < 6; ++r) {
+            if (r == c) continue;
+            double f = A[6 * r + c];
+            if (f == 0.0) continue;
+            for (int k = 0; k < 6; ++k) { A[6 * r + k] -= f * A[6 * c + k]; X[6 * r + k] -= f * X[6 * c + k]; }
+        }
+    }
+    return 1;
+}
+
+/* Inverse right Jacobian of SE(3): J_r(xi) = sum_{n >= 0} (-ad_xi)^n / (n+1)!
+ * is the derivative of exp(xi + e) against exp(xi) exp(J_r e); its inverse
+ * gives log(exp(xi) exp(e)) = xi + J_r^-1(xi) e + O(e^2).  The series is
+ * summed until its terms vanish in FP64, then inverted (|om| < 2 pi).
+ * Pinned by central differences of log(exp(xi) exp(e)) through matrix
+ * exponential and logarithm, and by I + ad/2 for small xi. */
+MPO_API int32_t mpo_se3_jr_inv(const double xi[6], double Ji[36]) {
+    double ad[36], term[36], Jr[36], nxt[36];
+    se3_ad(xi, ad);
+    for (int k = 0; k < 36; ++k) { term[k] = (k % 7 == 0) ? 1.0 : 0.0; Jr[k] = term[k]; }
+    for (int n = 1; n <= 200; ++n) {
+        double mx = 0.0;
+        for (int r = 0; r < 6; ++r)
+            for (int c = 0; c < 6; ++c) {
+                double s = 0.0;
+                for (int m = 0; m < 6; ++m) s += term[6 * r + m] * ad[6 * m + c];
+                nxt[6 * r + c] = -s / (double)(n + 1);
+            }
+        for (int k = 0; k < 36; ++k) {
+            term[k] = nxt[k];
+            Jr[k] += term[k];
+            if (fabs(term[k]) > mx) mx = fabs(term[k]);
+        }
+        if (mx < 1e-300 || (n > 6 && mx < 1e-18)) break;
+    }
+    return inv6(Jr, Ji) ? 0 : -1;
+}
+
+/* Adjoint of T = (R, t) in the tangent order [rotation; translation]:
+ * T exp(xi) T^-1 = exp(Ad_T xi),  Ad_T = [[R, 0], [t^ R, R]] */
+static void se3_Ad(const double T[7], double Ad[36]) {
+    double R[9];
+    qd_to_R(T, R);
+    const double* t = T + 4;
+    double tx[9] = {0, -t[2], t[1], t[2], 0, -t[0], -t[1], t[0], 0};
+    memset(Ad, 0, sizeof(double) * 36);
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) {
+            Ad[6 * r + c] = R[3 * r + c];
+            Ad[6 * (r + 3) + c + 3] = R[3 * r + c];
+            double s = 0.0;
+            for (int m = 0; m < 3; ++m) s += tx[3 * r + m] * R[3 * m + c];
+            Ad[6 * (r + 3) + c] = s;
+        }
 }
 
 /* ======================================================================= */
 /* Modified SVGD update (Eq. 5-8):                                          */
 /*   phi_i = sum_j (k_ij psi_j + grad_{T_j} k_ij) / sum_j k_ij,             */
-/*   k_ij = exp(-d_ij^T W d_ij), grad_{T_j} k_ij = -2 k_ij W d_ij,          */
+/*   k_ij = exp(-d_ij^T W d_ij),  d_ij = log(T_i^-1 T_j),                    */
 /*   T_i <- T_i exp(phi_i), all neighbours at the pre-update poses.          */
+/* The kernel gradient with respect to a right perturbation of T_j is       */
+/*   grad_exact 0:  -2 k_ij W d_ij            (J_r^-1(d_ij) taken as I)     */
+/*   grad_exact 1:  -2 k_ij J_r^-1(d_ij)^T W d_ij                           */
+/* and with transport 1 each neighbour's vector k_ij psi_j + grad, which    */
+/* lives in the tangent at T_j, is carried to the tangent at T_i by         */
+/* Ad_{T_i^-1 T_j} before the sum.                                          */
+/* Pinned by: K = 1 gives psi; two-particle closed form; full-set direct    */
+/* sums whose gradient is a finite difference of k and whose transport is   */
+/* M_ij xi^ M_ij^-1, all through matrix exponential and logarithm.          */
 /* ======================================================================= */
 MPO_API void mpo_svgd(const float* poses, int64_t n, const double* psi /* n*6 */, const int32_t* nbr, int32_t K,
-                      float sigma_r, float sigma_t, double* phi_out /* n*6 nullable */, double* poses_out /* n*7 */) {
+                      float sigma_r, float sigma_t, int32_t grad_exact, int32_t transport,
+                      double* phi_out /* n*6 nullable */, double* poses_out /* n*7 */) {
     double W[6] = {sigma_r, sigma_r, sigma_r, sigma_t, sigma_t, sigma_t};
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
@@ -1059,13 +1178,38 @@ MPO_API void mpo_svgd(const float* poses, int64_t n, const double* psi /* n*6 */
         for (int32_t a = 0; a < K; ++a) {
             int32_t j = nbr[i * K + a];
             if (j < 0) continue;
-            double d[6];
-            mpo_se3_between(poses + 8 * i, poses + 8 * (int64_t)j, d);
+            double Tij[7], d[6];
+            se3_rel(poses + 8 * i, poses + 8 * (int64_t)j, Tij);
+            mpo_se3_log(Tij, d);
             double qv = 0.0;
             for (int c = 0; c < 6; ++c) qv += W[c] * d[c] * d[c];
             double kij = exp(-qv);
             den += kij;
-            for (int c = 0; c < 6; ++c) num[c] += kij * psi[6 * (int64_t)j + c] - 2.0 * kij * W[c] * d[c];
+            double wd[6], g[6], v[6];
+            for (int c = 0; c < 6; ++c) wd[c] = W[c] * d[c];
+            if (grad_exact) {
+                double Ji[36];
+                mpo_se3_jr_inv(d, Ji);
+                for (int c = 0; c < 6; ++c) {
+                    double s = 0.0;
+                    for (int m = 0; m < 6; ++m) s += Ji[6 * m + c] * wd[m];
+                    g[c] = -2.0 * kij * s;
+                }
+            } else {
+                for (int c = 0; c < 6; ++c) g[c] = -2.0 * kij * wd[c];
+            }
+            for (int c = 0; c < 6; ++c) v[c] = kij * psi[6 * (int64_t)j + c] + g[c];
+            if (transport) {
+                double Ad[36], u[6];
+                se3_Ad(Tij, Ad);
+                for (int r = 0; r < 6; ++r) {
+                    double s = 0.0;
+                    for (int m = 0; m < 6; ++m) s += Ad[6 * r + m] * v[m];
+                    u[r] = s;
+                }
+                memcpy(v, u, sizeof(v));
+            }
+            for (int c = 0; c < 6; ++c) num[c] += v[c];
         }
         double phi[6];
         for (int c = 0; c < 6; ++c) phi[c] = den > 0 ? num[c] / den : 0.0;

@@ -4,13 +4,19 @@
   hash6        single-coordinate special cases reduce to the published
                constants (Teschner et al. primes); XOR combination; negative
                coordinates wrap as two's complement
-  LSH cells    floor of zeta (Eq. 10) computed in FP64 with scipy rotations,
-               away from cell boundaries; equal poses without noise share a code
+  LSH cells    floor of zeta (Eq. 10) computed in FP64 with scipy rotations
+               (decoupled tangent) or scipy logm (coupled SE(3) tangent), away
+               from cell boundaries; equal poses without noise share a code
   bucket sort  numpy stable argsort; bucket bounds
   refresh      one bucket (lsh_bits = 0) and window >= N-1 equals brute-force
                K-nearest by FP64 q_ij; persistence of the old list; set semantics
   SVGD         K = 1 gives phi = psi; two-particle translation-only closed form;
-               full neighbour sets against a direct O(N^2) sum with scipy logm
+               full neighbour sets against a direct O(N^2) sum with scipy logm;
+               the exact kernel gradient against finite differences of k through
+               expm/logm, the adjoint transport against M xi^ M^-1; J_r^-1 against
+               finite differences of log(exp(xi) exp(e)); with W isotropic,
+               transport leaves the approximate gradient term unchanged
+               (Ad_exp(d) d = d)
   posterior    sums to 1; uniform fixed point; K = 1 identity; two-node closed
                form of one round; shift invariance; long-double softmax
   prediction   zero covariance gives T dT; sample covariance of the noise
@@ -62,10 +68,39 @@ def test_lsh_cells_against_fp64(O):
     assert checked > 0.99 * n
 
 
+def test_lsh_coupled_cells_against_fp64(O):
+    rng = np.random.default_rng(11)
+    n = 2000
+    poses = np.stack([random_pose8(rng, tscale=8) for _ in range(n)])
+    TL = O.lsh_frame(9, 1, 4, np.array([-10, -10, -2], np.float32), np.array([10, 10, 2], np.float32))
+    alpha, sr, st, sl, seed = 0.8, 5.0, 2.5, 0.3, 78
+    codes, cells = O.lsh_codes(poses, TL, alpha, sr, st, sl, 20, seed, 1, 4, want_cells=True, tangent=1)
+    _, cells_dec = O.lsh_codes(poses, TL, alpha, sr, st, sl, 20, seed, 1, 4, want_cells=True, tangent=0)
+    # the rotation part of the tangent is the same program in both forms
+    assert np.array_equal(cells[:, :3], cells_dec[:, :3])
+    checked = 0
+    for i in range(n):
+        d = between_ref(TL, poses[i])          # log(T_LSH^-1 T_i) by scipy logm
+        if np.linalg.norm(d[:3]) > 3.0:        # logm branch near pi
+            continue
+        z = O.gauss6(seed, i, 1, 4, 2).astype(np.float64)
+        zeta = alpha * np.concatenate([sr * d[:3], st * d[3:]]) + sl * z
+        frac = zeta - np.floor(zeta)
+        if np.all((frac > 1e-4) & (frac < 1 - 1e-4)):
+            assert np.array_equal(cells[i], np.floor(zeta).astype(np.int32)), (i, cells[i], zeta)
+            checked += 1
+        assert codes[i] == (O.hash6(cells[i]) & ((1 << 20) - 1))
+    assert checked > 0.9 * n
+    # the coupled translation cells differ from the decoupled ones once rotations differ
+    assert not np.array_equal(cells[:, 3:], cells_dec[:, 3:])
+
+
 def test_lsh_equal_poses_share_code(O):
     T = np.tile(random_pose8(np.random.default_rng(3)), (100, 1))
     TL = O.lsh_frame(1, 0, 0, np.zeros(3, np.float32), np.ones(3, np.float32))
     codes = O.lsh_codes(T, TL, 1.0, 5.0, 2.5, 0.0, 16, 1, 0, 0)
+    assert len(np.unique(codes)) == 1
+    codes = O.lsh_codes(T, TL, 1.0, 5.0, 2.5, 0.0, 16, 1, 0, 0, tangent=1)
     assert len(np.unique(codes)) == 1
 
 
@@ -246,3 +281,96 @@ def test_predict_no_noise_and_noise_covariance(O):
     deltas = np.stack([se3_log_ref(np.linalg.inv(TD) @ pose_to_M(out[i])) for i in range(0, n, 4)])
     C = np.cov(deltas.T)
     assert np.allclose(C, cov, atol=0.1 * np.abs(cov).max())
+
+
+def _vee(M):
+    return np.array([M[2, 1], M[0, 2], M[1, 0], M[0, 3], M[1, 3], M[2, 3]])
+
+
+def test_jr_inv_against_finite_differences(O):
+    rng = np.random.default_rng(12)
+    h = 1e-5
+    for trial in range(12):
+        xi = np.concatenate([rng.normal(size=3) * (0.3 + 0.2 * trial), rng.normal(size=3) * 2.0])
+        if np.linalg.norm(xi[:3]) > 2.8:
+            xi[:3] *= 2.8 / np.linalg.norm(xi[:3])
+        J = O.se3_jr_inv(xi)
+        E = se3_exp_ref(xi)
+        Jfd = np.zeros((6, 6))
+        for c in range(6):
+            e = np.zeros(6); e[c] = h
+            Jfd[:, c] = (se3_log_ref(E @ se3_exp_ref(e)) - se3_log_ref(E @ se3_exp_ref(-e))) / (2 * h)
+        assert np.abs(J - Jfd).max() < 1e-6 * (1 + np.abs(J).max()), (trial, np.abs(J - Jfd).max())
+    # small argument: J_r^-1 = I + ad/2 + O(|xi|^2)
+    xi = np.array([1e-4, -2e-4, 1.5e-4, 3e-4, 1e-4, -2e-4])
+    ad = np.zeros((6, 6))
+    from _pinutil import hat
+    ad[:3, :3] = hat(xi[:3]); ad[3:, :3] = hat(xi[3:]); ad[3:, 3:] = hat(xi[:3])
+    assert np.abs(O.se3_jr_inv(xi) - (np.eye(6) + 0.5 * ad)).max() < 1e-7
+
+
+def _svgd_direct(poses, psi, sr, st, grad_exact, transport):
+    """phi of every particle over the full set, each term from scipy expm/logm:
+    the kernel gradient by central differences of k(T_i, T_j exp(e)), the
+    transport as vee(M_ij (v^) M_ij^-1)"""
+    from _pinutil import twist_M
+    n = len(poses)
+    W = np.array([sr] * 3 + [st] * 3)
+    h = 1e-5
+    Ms = [pose_to_M(p) for p in poses]
+    phi = np.zeros((n, 6))
+    for i in range(n):
+        num = np.zeros(6); den = 0.0
+        Mi_inv = np.linalg.inv(Ms[i])
+        for j in range(n):
+            Mij = Mi_inv @ Ms[j]
+            d = se3_log_ref(Mij)
+            k = math.exp(-np.sum(W * d * d))
+            if grad_exact:
+                g = np.zeros(6)
+                for c in range(6):
+                    e = np.zeros(6); e[c] = h
+                    dp = se3_log_ref(Mij @ se3_exp_ref(e)); dm = se3_log_ref(Mij @ se3_exp_ref(-e))
+                    g[c] = (math.exp(-np.sum(W * dp * dp)) - math.exp(-np.sum(W * dm * dm))) / (2 * h)
+            else:
+                g = -2 * k * W * d
+            v = k * psi[j] + g
+            if transport:
+                v = _vee(Mij @ twist_M(v) @ np.linalg.inv(Mij))
+            num += v
+            den += k
+        phi[i] = num / den
+    return phi
+
+
+@pytest.mark.parametrize("grad_exact,transport", [(True, False), (False, True), (True, True)])
+def test_svgd_variants_direct_sum(O, grad_exact, transport):
+    rng = np.random.default_rng(13)
+    n = 16
+    poses = np.stack([random_pose8(rng, tscale=0.4, rot=0.8) for _ in range(n)])
+    psi = rng.normal(scale=0.1, size=(n, 6))
+    nbr = np.array([[i] + [j for j in range(n) if j != i] for i in range(n)], np.int32)
+    phi, _ = O.svgd(poses, psi, nbr, 5.0, 2.5, grad_exact=grad_exact, transport=transport)
+    ref = _svgd_direct(poses, psi, 5.0, 2.5, grad_exact, transport)
+    assert np.abs(phi - ref).max() < 2e-6, np.abs(phi - ref).max()
+    # the variant changes the result at this spread
+    phi0, _ = O.svgd(poses, psi, nbr, 5.0, 2.5)
+    assert np.abs(phi - phi0).max() > 1e-3
+
+
+def test_svgd_transport_keeps_gradient_term(O):
+    # Ad_{exp(d)} d = d: with psi = 0, the approximate gradient and an isotropic
+    # W (sigma_r = sigma_t), transport is the identity
+    rng = np.random.default_rng(14)
+    n = 40
+    poses = np.stack([random_pose8(rng, tscale=1.0, rot=1.0) for _ in range(n)])
+    nbr = np.array([[i] + list(rng.choice([j for j in range(n) if j != i], 7, replace=False)) for i in range(n)],
+                   np.int32)
+    psi = np.zeros((n, 6))
+    a, _ = O.svgd(poses, psi, nbr, 3.0, 3.0)
+    b, _ = O.svgd(poses, psi, nbr, 3.0, 3.0, transport=True)
+    assert np.abs(a - b).max() < 1e-12
+    # with W anisotropic it is not (the translation row mixes in t x omega)
+    a, _ = O.svgd(poses, psi, nbr, 5.0, 2.5)
+    b, _ = O.svgd(poses, psi, nbr, 5.0, 2.5, transport=True)
+    assert np.abs(a - b).max() > 1e-3
