@@ -285,7 +285,7 @@ def sequence_main(args):
     m = M.Map(torch.from_numpy(w["map_xyz"]).cuda(), voxel=0.5)
     info = m.info()
     p = M.mp_filter_default_params(n_particles=65536, k=16, lsh_bits=20, svgd_iters=20, post_iters=10, window_c=32,
-                                   d_max=1.0, seed=4002)
+                                   d_max=1.0, seed=4002, **VARIANTS[args.variant])
     f = M.Filter(m, p, box=(info["box_min"], info["box_max"]))
     sm = M.Smoother(window=5, jump_m=1.0, jump_rad=0.2)
 
@@ -352,7 +352,8 @@ def sequence_main(args):
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": "floor: 65536 particles x 4096 scan points x 20 SVGD iterations, %d frames, "
                                   "uniform start, scans blocked for frames %d..%d, 20 m kidnap at frame %d" %
-                                  (frames, occl[0], occl[1] - 1, kid)},
+                                  (frames, occl[0], occl[1] - 1, kid),
+                      "variant": args.variant, "variant_params": VARIANTS[args.variant]},
            "converged_frame": conv, "scans_return_frame": occl[1], "scored_frames": len(scored),
            "raw": raw_s, "smoothed": sm_s, "frames_with_scan_odometry": used_odo,
            "per_frame_error_raw": raw, "per_frame_error_smoothed": smooth}
@@ -599,6 +600,59 @@ def surrogate_eval_main(args):
     print(json.dumps(res), flush=True)
 
 
+VARIANTS = {
+    "default": {},
+    "lsh_tangent_se3": {"lsh_tangent": 1},
+    "lsh_tables_2": {"lsh_tables": 2},
+    "svgd_grad_exact": {"svgd_grad": 1},
+    "svgd_transport_adjoint": {"svgd_transport": 1},
+    "svgd_exact_and_adjoint": {"svgd_grad": 1, "svgd_transport": 1},
+}
+
+
+def variants_leg(M, m, wl, minfo, scans, odo, warmup=1, steps=1):
+    """One full-size filter step per accuracy variant of the neighbour search
+    and the Stein update (same map, scans and seed); stage times of the last
+    step, and the SVGD kernel against its HBM roofline."""
+    import torch
+    n, K, it = wl["particles"], wl["k"], wl["svgd_iters"]
+    svgd_bytes = svgd_refresh_bytes(K)[0] * n * it
+    out = {}
+    for name, kw in VARIANTS.items():
+        p = M.mp_filter_default_params(n_particles=n, k=K, lsh_bits=wl["lsh_bits"], svgd_iters=it,
+                                       post_iters=wl["post_iters"], window_c=wl["window_c"], d_max=2.0 * wl["voxel"],
+                                       seed=4003, **kw)
+        f = M.Filter(m, p, box=(minfo["box_min"], minfo["box_max"]))
+        ms = []
+        for k in range(warmup + steps):
+            dT, cov = odo[k] if k > 0 else (None, None)
+            f.scan_upload(scans[k])
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            f.step(dT, cov)
+            e1.record()
+            torch.cuda.synchronize()
+            if k >= warmup:
+                ms.append(e0.elapsed_time(e1))
+        st = f.stage_times()
+        sv = st["svgd"][0]
+        out[name] = {"params": kw, "step_ms": round(float(np.median(ms)), 3),
+                     "stage_ms": {k: round(st[k][0], 3) for k in ("lsh", "sort", "refresh", "svgd")},
+                     "svgd_hbm_frac": round(svgd_bytes / PEAK_HBM / (sv * 1e-3), 4) if sv > 0 else None}
+        f.close()
+        torch.cuda.synchronize()
+        log("variant %s: %.1f ms per step" % (name, out[name]["step_ms"]))
+    return out
+
+
+def svgd_refresh_bytes(K):
+    """compulsory bytes per particle and launch: SVGD reads K neighbour ids and
+    kernel values, its own pose and psi, writes its pose; the refresh reads its
+    sorted slot, bucket bounds, pose and old list, writes list, kernel values
+    and count"""
+    return 8.0 * K + 96.0, 48.0 + 12.0 * K
+
+
 def _med_p90(v):
     a = np.asarray(v, np.float64)
     return {"median_ms": round(float(np.median(a)), 3), "p90_ms": round(float(np.percentile(a, 90)), 3),
@@ -607,19 +661,21 @@ def _med_p90(v):
 
 def stage_roofline(stages, wl, lik_flops_launch, t_step):
     """Each stage of one filter step against the resource that bounds it:
-    algorithmic bytes per step over HBM bandwidth for the data-movement stages
-    (per-particle figures of their kernels), algorithmic flops over the FP32
-    peak for the likelihood and the scan's k-NN.  `step` sums the stages'
-    roofline times over the measured step time."""
+    compulsory bytes per step over HBM bandwidth for the data-movement stages
+    (each array a launch touches moved once per launch; a neighbour's pose or
+    psi, gathered K times, counted once, since those gathers are served by the
+    caches), algorithmic flops over the FP32 peak for the likelihood and the
+    scan's k-NN.  `step` sums the stages' roofline times over the measured
+    step time."""
     n, it, K, C, R = wl["particles"], wl["svgd_iters"], wl["k"], wl["window_c"], wl["post_iters"]
     ns, passes = wl["scan_points"], (wl["lsh_bits"] + 7) // 8
     work = {
         "predict": ("hbm", 64.0 * n),
-        "lsh": ("hbm", 40.0 * n * it),
+        "lsh": ("hbm", 44.0 * n * it),
         "sort": ("hbm", (16.0 * passes + 12.0) * n * it),
-        "refresh": ("hbm", (32.0 + 4 * K + 32.0 * (K + C) + 8 * K) * n * it),
+        "refresh": ("hbm", svgd_refresh_bytes(K)[1] * n * it),
         "likelihood": ("alu", lik_flops_launch * it),
-        "svgd": ("hbm", (32.0 + K * (8 + 32 + 32) + 32.0) * n * it),
+        "svgd": ("hbm", svgd_refresh_bytes(K)[0] * n * it),
         "posterior": ("hbm", (36.0 + R * (8.0 * K + 8)) * n),
         "scan": ("alu", 8.0 * ns * (ns - 1)),
     }
@@ -654,6 +710,10 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate scorer and training legs")
     ap.add_argument("--surrogate-steps", type=int, default=1)
+    ap.add_argument("--variant", default="default", choices=sorted(VARIANTS),
+                    help="sequence: LSH / SVGD accuracy variant of the filter")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the leg timing the LSH tangent / tables and SVGD gradient / transport variants")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 1 GiB device copy before timing (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -781,6 +841,9 @@ def main():
         res["surrogate"] = surrogate_leg(M, m, wl, minfo, scans, odo, 1, args.surrogate_steps)
         res["surrogate"]["vs_plain"] = res["surrogate"]["steps_per_s"] / steps_per_s
         res["surrogate_training"] = train_leg(M, S, m, w, minfo)
+    if not args.no_variants:
+        f.close()
+        res["variants"] = variants_leg(M, m, wl, minfo, scans, odo)
     res["odometry"] = odometry_leg(M, m, w, scans, not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(wl, w, w["scans"][-1], args.cpu_budget)

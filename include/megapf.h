@@ -147,8 +147,33 @@ typedef struct {
     int32_t lik_layout;   /* MP_LIK_LAYOUT_*: lanes per particle in the likelihood launch */
     int32_t scorer;       /* MP_SCORER_*: per-point term of the likelihood */
     float sigma_s;        /* MP_SCORER_SCOREFIELD: isotropic sensor std of the score field, metres */
+    int32_t lsh_tangent;  /* MP_LSH_TANGENT_*: tangent of T_i at T^LSH that Eq. (10) hashes */
+    int32_t lsh_tables;   /* hash tables per SVGD iteration, 0..16 (0 = 1): each draws its own T^LSH and
+                             delta^LSH and refreshes the neighbour lists once */
+    int32_t svgd_grad;    /* MP_SVGD_GRAD_*: kernel gradient in the update of Eq. (5)-(6) */
+    int32_t svgd_transport; /* MP_SVGD_TRANSPORT_*: tangent frame of neighbour j's term */
     uint64_t seed;        /* Philox4x32-10 key */
 } mp_filter_params;
+
+/* Tangent hashed by the LSH (Eq. 10), x_i with zeta = alpha W^K x_i + delta_i:
+ *   DECOUPLED  [log(R_L^T R_i); R_L^T (t_i - t_L)]  (rotation vector and
+ *              rotated translation offset);
+ *   SE3        log(T_LSH^-1 T_i), the coupled SE(3) logarithm of Eq. (8)
+ *              (same rotation part; translation V(omega)^-1 R_L^T (t_i - t_L)). */
+enum { MP_LSH_TANGENT_DECOUPLED = 0, MP_LSH_TANGENT_SE3 = 1 };
+
+/* Kernel gradient of the Stein update, with respect to a right perturbation
+ * of T_j (Eq. 5-8):
+ *   APPROX  -2 k_ij W^K d_ij   (the inverse right Jacobian of the logarithm
+ *           taken as the identity);
+ *   EXACT   -2 k_ij J_r^-1(d_ij)^T W^K d_ij, J_r^-1 in closed form. */
+enum { MP_SVGD_GRAD_APPROX = 0, MP_SVGD_GRAD_EXACT = 1 };
+
+/* Frame of neighbour j's term k_ij psi_j + grad in the sum for particle i:
+ *   NONE     added as it is;
+ *   ADJOINT  carried from the tangent at T_j to the tangent at T_i by
+ *            Ad_{T_i^-1 T_j} = [[R, 0], [t^ R, R]] of T_i^-1 T_j = (R, t). */
+enum { MP_SVGD_TRANSPORT_NONE = 0, MP_SVGD_TRANSPORT_ADJOINT = 1 };
 
 /* Per-point term of the likelihood.
  *   PLAIN       the GICP cost of Eq. (3) with full Gauss-Newton H, b (Eq. 4).
@@ -177,7 +202,8 @@ enum { MP_LIK_LAYOUT_AUTO = 0, MP_LIK_LAYOUT_PARTICLE = 1, MP_LIK_LAYOUT_GROUPED
  * scan_k 10, sigma_r 5, sigma_t 2.5, lsh_alpha 1, lsh_sigma 0.3, c_max 9,
  * d_max 1.0, lambda_rel 1e-3, lambda_abs 1e-6, temperature 1,
  * prior_floor 1e-30, cov_eps 1e-3, lik_chunks 0, lik_batch 0, lik_layout AUTO,
- * scorer PLAIN, sigma_s 0.03, seed 1. */
+ * scorer PLAIN, sigma_s 0.03, lsh_tangent DECOUPLED, lsh_tables 1, svgd_grad
+ * APPROX, svgd_transport NONE, seed 1. */
 MP_API void mp_filter_default_params(mp_filter_params* p);
 
 enum { MP_INIT_UNIFORM_BOX = 0, MP_INIT_EXPLICIT = 1 };

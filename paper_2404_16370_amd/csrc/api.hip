@@ -243,6 +243,10 @@ extern "C" void mp_filter_default_params(mp_filter_params* p) {
     p->lik_batch = 0;
     p->scorer = MP_SCORER_PLAIN;
     p->sigma_s = 0.03f;
+    p->lsh_tangent = MP_LSH_TANGENT_DECOUPLED;
+    p->lsh_tables = 1;
+    p->svgd_grad = MP_SVGD_GRAD_APPROX;
+    p->svgd_transport = MP_SVGD_TRANSPORT_NONE;
     p->seed = 1;
 }
 
@@ -267,6 +271,12 @@ static void validate_params(const mp_filter_params& p) {
     if (p.scorer < MP_SCORER_PLAIN || p.scorer > MP_SCORER_SURROGATE) mp_throw(MP_E_ARG, "unknown scorer");
     if (p.lik_layout < MP_LIK_LAYOUT_AUTO || p.lik_layout > MP_LIK_LAYOUT_GROUPED) mp_throw(MP_E_ARG, "unknown lik_layout");
     if (!std::isfinite(p.sigma_s) || !(p.sigma_s > 0.0f)) mp_throw(MP_E_ARG, "sigma_s must be positive");
+    if (p.lsh_tangent != MP_LSH_TANGENT_DECOUPLED && p.lsh_tangent != MP_LSH_TANGENT_SE3)
+        mp_throw(MP_E_ARG, "unknown lsh_tangent");
+    if (p.lsh_tables < 0 || p.lsh_tables > 16) mp_throw(MP_E_ARG, "lsh_tables must be 0..16");
+    if (p.svgd_grad != MP_SVGD_GRAD_APPROX && p.svgd_grad != MP_SVGD_GRAD_EXACT) mp_throw(MP_E_ARG, "unknown svgd_grad");
+    if (p.svgd_transport != MP_SVGD_TRANSPORT_NONE && p.svgd_transport != MP_SVGD_TRANSPORT_ADJOINT)
+        mp_throw(MP_E_ARG, "unknown svgd_transport");
 }
 
 static void destroy_filter(mp_filter f) {
@@ -514,9 +524,18 @@ void mp_step_launches(mp_filter f, bool pred, const float dq[7], const float L[3
     }
     if (f->scan_n > 0) {
         // per iteration, in the order of Table II: neighbour list update
-        // (LSH, sort, refresh), likelihood evaluation, particle state update
+        // (LSH, sort, refresh; once per hash table, table l of iteration it
+        // drawing with counter it * tables + l), likelihood evaluation,
+        // particle state update
+        const int tables = std::max(1, f->p.lsh_tables);
         for (int it = 0; it < f->p.svgd_iters; ++it) {
-            for (int st : {MP_STAGE_LSH, MP_STAGE_SORT, MP_STAGE_REFRESH, MP_STAGE_LIK, MP_STAGE_SVGD}) {
+            for (int l = 0; l < tables; ++l)
+                for (int st : {MP_STAGE_LSH, MP_STAGE_SORT, MP_STAGE_REFRESH}) {
+                    mp_tick(f, st, true, s);
+                    run_stage(f, st, it * tables + l, s);
+                    mp_tick(f, st, false, s);
+                }
+            for (int st : {MP_STAGE_LIK, MP_STAGE_SVGD}) {
                 mp_tick(f, st, true, s);
                 run_stage(f, st, it, s);
                 mp_tick(f, st, false, s);

@@ -78,8 +78,71 @@ struct SvgdArgs {
     float sr, st;
 };
 
-// phi_i = sum_j (k_ij psi_j - 2 k_ij W d_ij) / sum_j k_ij over the list of i,
-// d_ij = log(T_i^-1 T_j); T_i <- T_i exp(phi_i) (Jacobi: all j at pre-update poses)
+__device__ inline float3 cross3(const float3 a, const float3 b) {
+    return float3{a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+__device__ inline float3 axpy3(float s, const float3 x, const float3 y) {
+    return float3{s * x.x + y.x, s * x.y + y.y, s * x.z + y.z};
+}
+
+// J_r^-1(d)^T a for d = [om; rho], a = [aw; ar] (tangent order rotation
+// first).  With M = I + 1/2 om^ + beta om^2 (the SO(3) inverse right
+// Jacobian; beta as in the SE(3) logarithm) and Q(rho, om) the off-diagonal
+// block of the SE(3) left Jacobian (Barfoot and Furgale, IEEE T-RO 2014):
+//   J_r^-1(d) = [[M, 0], [-M Q(-rho, -om) M, M]],  Q(-rho, -om)^T = Q(rho, om),
+// so that  v_r = M^T ar,  v_w = M^T (aw - Q(rho, om) v_r),
+// M^T x = x - 1/2 om x x + beta om x (om x x).
+__device__ inline void jr_inv_t(const float3 om, const float3 rho, float beta, const float3 aw, const float3 ar,
+                                float3& vw, float3& vr) {
+    auto mt = [&](const float3 x) {
+        const float3 c1 = cross3(om, x);
+        const float3 c2 = cross3(om, c1);
+        return float3{(x.x - 0.5f * c1.x) + beta * c2.x, (x.y - 0.5f * c1.y) + beta * c2.y,
+                      (x.z - 0.5f * c1.z) + beta * c2.z};
+    };
+    vr = mt(ar);
+    const float th2 = (om.x * om.x + om.y * om.y) + om.z * om.z;
+    float c1, c2, c3;   // (th - sin th)/th^3, (th^2 + 2 cos th - 2)/(2 th^4), (2 th - 3 sin th + th cos th)/(2 th^5)
+    if (th2 < 1.0f) {   // Taylor series (cancellation in the closed forms below th = 1)
+        c1 = fmaf(fmaf(fmaf(-1.0f / 362880.0f, th2, 1.0f / 5040.0f), th2, -1.0f / 120.0f), th2, 1.0f / 6.0f);
+        c2 = fmaf(fmaf(fmaf(-1.0f / 3628800.0f, th2, 1.0f / 40320.0f), th2, -1.0f / 720.0f), th2, 1.0f / 24.0f);
+        c3 = fmaf(fmaf(fmaf(-1.0f / 9979200.0f, th2, 1.0f / 120960.0f), th2, -1.0f / 2520.0f), th2, 1.0f / 120.0f);
+    } else {
+        const float th = sqrtf(th2);
+        float sn, cs;
+        sincosf(th, &sn, &cs);
+        const float th4 = th2 * th2;
+        c1 = (th - sn) / (th2 * th);
+        c2 = (th2 + 2.0f * cs - 2.0f) / (2.0f * th4);
+        c3 = (2.0f * th - 3.0f * sn + th * cs) / (2.0f * th4 * th);
+    }
+    // Q(rho, om) x = 1/2 rho^x + c1 (om^rho^ + rho^om^ + om^rho^om^) x
+    //   + c2 (om^om^rho^ + rho^om^om^ - 3 om^rho^om^) x + c3 (om^rho^om^om^ + om^om^rho^om^) x
+    const float3 b0 = cross3(rho, vr);
+    const float3 a1 = cross3(om, vr);
+    const float3 a2 = cross3(om, a1);
+    const float3 b1 = cross3(rho, a1);
+    const float3 b2 = cross3(rho, a2);
+    const float3 wb0 = cross3(om, b0);
+    const float3 wb1 = cross3(om, b1);
+    const float3 wwb0 = cross3(om, wb0);
+    const float3 wb2 = cross3(om, b2);
+    const float3 wwb1 = cross3(om, wb1);
+    float3 y;
+    y.x = 0.5f * b0.x + c1 * (wb0.x + b1.x + wb1.x) + c2 * (wwb0.x + b2.x - 3.0f * wb1.x) + c3 * (wb2.x + wwb1.x);
+    y.y = 0.5f * b0.y + c1 * (wb0.y + b1.y + wb1.y) + c2 * (wwb0.y + b2.y - 3.0f * wb1.y) + c3 * (wb2.y + wwb1.y);
+    y.z = 0.5f * b0.z + c1 * (wb0.z + b1.z + wb1.z) + c2 * (wwb0.z + b2.z - 3.0f * wb1.z) + c3 * (wb2.z + wwb1.z);
+    vw = mt(float3{aw.x - y.x, aw.y - y.y, aw.z - y.z});
+}
+
+// phi_i = sum_j v_ij / sum_j k_ij over the list of i, d_ij = log(T_i^-1 T_j),
+// v_ij = k_ij psi_j + g_ij with the kernel gradient
+//   EXACT = false   g = -2 k W d
+//   EXACT = true    g = -2 k J_r^-1(d)^T W d
+// and, with TRANSPORT, v_ij carried to T_i's tangent by Ad_{T_i^-1 T_j}:
+//   [R v_w; t x (R v_w) + R v_r] with (R, t) = T_i^-1 T_j.
+// T_i <- T_i exp(phi_i) (Jacobi: all j at pre-update poses).
+template <bool EXACT, bool TRANSPORT>
 __global__ __launch_bounds__(256) void k_svgd(SvgdArgs A) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= A.n) return;
@@ -95,16 +158,45 @@ __global__ __launch_bounds__(256) void k_svgd(SvgdArgs A) {
         mpdet::quat qj;
         float3 tj;
         load_pose(A.pin, j, qj, tj);
-        float3 om, rho;
-        mpdet::se3_between(qi, ti, qj, tj, om, rho);
+        float3 om, rho, tr;
+        mpdet::quat qr;
+        float beta;
+        mpdet::se3_between_ex(qi, ti, qj, tj, om, rho, qr, tr, beta);
         const float4 p0 = A.psi[2 * j], p1 = A.psi[2 * j + 1];
-        const float k2r = 2.0f * k * A.sr, k2t = 2.0f * k * A.st;
-        num[0] += k * p0.x - k2r * om.x;
-        num[1] += k * p0.y - k2r * om.y;
-        num[2] += k * p0.z - k2r * om.z;
-        num[3] += k * p0.w - k2t * rho.x;
-        num[4] += k * p1.x - k2t * rho.y;
-        num[5] += k * p1.y - k2t * rho.z;
+        if (!EXACT && !TRANSPORT) {
+            const float k2r = 2.0f * k * A.sr, k2t = 2.0f * k * A.st;
+            num[0] += k * p0.x - k2r * om.x;
+            num[1] += k * p0.y - k2r * om.y;
+            num[2] += k * p0.z - k2r * om.z;
+            num[3] += k * p0.w - k2t * rho.x;
+            num[4] += k * p1.x - k2t * rho.y;
+            num[5] += k * p1.y - k2t * rho.z;
+        } else {
+            float3 gw = float3{A.sr * om.x, A.sr * om.y, A.sr * om.z};
+            float3 gr = float3{A.st * rho.x, A.st * rho.y, A.st * rho.z};
+            if (EXACT) jr_inv_t(om, rho, beta, gw, gr, gw, gr);
+            const float m2k = -2.0f * k;
+            float3 vw = axpy3(m2k, gw, float3{k * p0.x, k * p0.y, k * p0.z});
+            float3 vr = axpy3(m2k, gr, float3{k * p0.w, k * p1.x, k * p1.y});
+            if (TRANSPORT) {
+                const mpdet::mat3 R = mpdet::qmat(qr);
+                const float3 rw = float3{R.m[0] * vw.x + R.m[1] * vw.y + R.m[2] * vw.z,
+                                         R.m[3] * vw.x + R.m[4] * vw.y + R.m[5] * vw.z,
+                                         R.m[6] * vw.x + R.m[7] * vw.y + R.m[8] * vw.z};
+                const float3 rr = float3{R.m[0] * vr.x + R.m[1] * vr.y + R.m[2] * vr.z,
+                                         R.m[3] * vr.x + R.m[4] * vr.y + R.m[5] * vr.z,
+                                         R.m[6] * vr.x + R.m[7] * vr.y + R.m[8] * vr.z};
+                const float3 tx = cross3(tr, rw);
+                vw = rw;
+                vr = float3{tx.x + rr.x, tx.y + rr.y, tx.z + rr.z};
+            }
+            num[0] += vw.x;
+            num[1] += vw.y;
+            num[2] += vw.z;
+            num[3] += vr.x;
+            num[4] += vr.y;
+            num[5] += vr.z;
+        }
         den += k;
     }
     float phi[6];
@@ -393,7 +485,12 @@ void mp_launch_svgd(mp_filter f, hipStream_t s) {
     A.K = f->K;
     A.sr = f->p.sigma_r;
     A.st = f->p.sigma_t;
-    k_svgd<<<nblk(f->n), 256, 0, s>>>(A);
+    const bool exact = f->p.svgd_grad == MP_SVGD_GRAD_EXACT;
+    const bool transport = f->p.svgd_transport == MP_SVGD_TRANSPORT_ADJOINT;
+    if (exact && transport) k_svgd<true, true><<<nblk(f->n), 256, 0, s>>>(A);
+    else if (exact) k_svgd<true, false><<<nblk(f->n), 256, 0, s>>>(A);
+    else if (transport) k_svgd<false, true><<<nblk(f->n), 256, 0, s>>>(A);
+    else k_svgd<false, false><<<nblk(f->n), 256, 0, s>>>(A);
     MP_CHECK_LAUNCH();
     f->cur = 1 - f->cur;
 }

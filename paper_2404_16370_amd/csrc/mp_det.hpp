@@ -203,17 +203,18 @@ __device__ inline float3 qlog(quat q, float& w_out, float& scale_out) {
 }
 
 // d = log(T_i^-1 T_j) with the coupled SE(3) logarithm: rotation vector
-// omega of conj(q_i) q_j and rho = V(omega)^-1 R_i^T (t_j - t_i).
-__device__ inline void se3_between(const quat qi, const float3 ti, const quat qj, const float3 tj, float3& om,
-                                   float3& rho) {
-    const quat qr = qmul(qconj(qi), qj);
+// omega of qr = conj(q_i) q_j and rho = V(omega)^-1 tr, tr = R_i^T (t_j - t_i).
+// Also hands back qr, tr and beta, the coefficient of V^-1 = I - 1/2 omega^ +
+// beta omega^2.
+__device__ inline void se3_between_ex(const quat qi, const float3 ti, const quat qj, const float3 tj, float3& om,
+                                      float3& rho, quat& qr, float3& tr, float& beta) {
+    qr = qmul(qconj(qi), qj);
     const mat3 Ri = qmat(qi);
     const float3 dt = float3{tj.x - ti.x, tj.y - ti.y, tj.z - ti.z};
-    const float3 tr = rot_t(Ri, dt);
+    tr = rot_t(Ri, dt);
     float w, sc;
     om = qlog(qr, w, sc);
     const float th2 = (om.x * om.x + om.y * om.y) + om.z * om.z;
-    float beta;
     if (th2 < 0.0025f) {
         beta = 1.0f / 30240.0f;
         beta = beta * th2 + 1.0f / 720.0f;
@@ -226,6 +227,14 @@ __device__ inline void se3_between(const quat qi, const float3 ti, const quat qj
     rho.x = (tr.x - 0.5f * c1x) + beta * c2x;
     rho.y = (tr.y - 0.5f * c1y) + beta * c2y;
     rho.z = (tr.z - 0.5f * c1z) + beta * c2z;
+}
+
+__device__ inline void se3_between(const quat qi, const float3 ti, const quat qj, const float3 tj, float3& om,
+                                   float3& rho) {
+    quat qr;
+    float3 tr;
+    float beta;
+    se3_between_ex(qi, ti, qj, tj, om, rho, qr, tr, beta);
 }
 
 // q_ij = d^T W d with W = diag(sigma_r I3, sigma_t I3) (Eq. 7-8): ranks neighbours

@@ -1,8 +1,10 @@
 // neighbors.hip -- LSH bucketing and the iterative neighbour-list refresh
 // (Eq. 9-10 and Alg. 1, IterativeNeighborParticleSearch).
 //
-//   k_lsh        per particle: zeta = alpha W^K [log(R_L^T R_i); R_L^T (t_i - t_L)]
-//                + delta_i, cell = floor(zeta) (deterministic FP32), code =
+//   k_lsh        per particle: zeta = alpha W^K x_i + delta_i with the tangent
+//                x_i = [log(R_L^T R_i); R_L^T (t_i - t_L)] (decoupled) or
+//                log(T_LSH^-1 T_i) (coupled SE(3) logarithm),
+//                cell = floor(zeta) (deterministic FP32), code =
 //                hash6(cell) & (2^bits - 1).  T^LSH is drawn from Philox for
 //                (frame, iteration); every lane derives it, lane 0 records it.
 //   sort         stable radix sort of (code, index)  -> buckets as runs
@@ -31,6 +33,7 @@ struct LshArgs {
     int32_t n;
     uint32_t mask, frame, it;
     float ar, at, sl;
+    int32_t coupled;                  // tangent: 0 decoupled, 1 coupled SE(3) log
     float lo[3], hi[3];
     uint64_t seed;
     const StepDyn* __restrict__ dyn;   // captured step: frame from here
@@ -49,11 +52,16 @@ __global__ __launch_bounds__(256) void k_lsh(LshArgs A) {
     if (i >= A.n) return;
     const float4 q4 = A.poses[2 * i], t4 = A.poses[2 * i + 1];
     const mpdet::quat qi{q4.x, q4.y, q4.z, q4.w};
-    const mpdet::quat qr = mpdet::qmul(mpdet::qconj(qL), qi);
-    float w, sc;
-    const float3 om = mpdet::qlog(qr, w, sc);
-    const mpdet::mat3 RL = mpdet::qmat(qL);
-    const float3 u = mpdet::rot_t(RL, make_float3(t4.x - tL.x, t4.y - tL.y, t4.z - tL.z));
+    float3 om, u;
+    if (A.coupled) {
+        mpdet::se3_between(qL, tL, qi, make_float3(t4.x, t4.y, t4.z), om, u);
+    } else {
+        const mpdet::quat qr = mpdet::qmul(mpdet::qconj(qL), qi);
+        float w, sc;
+        om = mpdet::qlog(qr, w, sc);
+        const mpdet::mat3 RL = mpdet::qmat(qL);
+        u = mpdet::rot_t(RL, make_float3(t4.x - tL.x, t4.y - tL.y, t4.z - tL.z));
+    }
     float z[6];
     mpdet::gauss6(A.seed, (uint32_t)i, A.frame, A.it, mpdet::PURPOSE_LSH, z);
     int32_t c[6];
@@ -244,6 +252,7 @@ void mp_launch_lsh(mp_filter f, uint32_t frame, uint32_t it, hipStream_t s) {
     A.ar = f->p.lsh_alpha * f->p.sigma_r;
     A.at = f->p.lsh_alpha * f->p.sigma_t;
     A.sl = f->p.lsh_sigma;
+    A.coupled = f->p.lsh_tangent == MP_LSH_TANGENT_SE3 ? 1 : 0;
     for (int a = 0; a < 3; ++a) {
         A.lo[a] = f->lsh_lo[a];
         A.hi[a] = f->lsh_hi[a];

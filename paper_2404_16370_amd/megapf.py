@@ -50,7 +50,8 @@ class mp_filter_params(C.Structure):
                 ("lambda_rel", C.c_float), ("lambda_abs", C.c_float), ("temperature", C.c_float),
                 ("prior_floor", C.c_float), ("cov_eps", C.c_float), ("lik_chunks", C.c_int32),
                 ("lik_batch", C.c_int32), ("lik_layout", C.c_int32), ("scorer", C.c_int32), ("sigma_s", C.c_float),
-                ("seed", C.c_uint64)]
+                ("lsh_tangent", C.c_int32), ("lsh_tables", C.c_int32), ("svgd_grad", C.c_int32),
+                ("svgd_transport", C.c_int32), ("seed", C.c_uint64)]
 
 
 class mp_odometry_params(C.Structure):
@@ -108,6 +109,9 @@ EXPORTS = ["mp_map_default_params", "mp_map_build", "mp_map_get_info", "mp_map_g
 
 MP_SCORER_PLAIN, MP_SCORER_SCOREFIELD, MP_SCORER_SURROGATE = 0, 1, 2
 MP_LIK_LAYOUT_AUTO, MP_LIK_LAYOUT_PARTICLE, MP_LIK_LAYOUT_GROUPED = 0, 1, 2
+MP_LSH_TANGENT_DECOUPLED, MP_LSH_TANGENT_SE3 = 0, 1
+MP_SVGD_GRAD_APPROX, MP_SVGD_GRAD_EXACT = 0, 1
+MP_SVGD_TRANSPORT_NONE, MP_SVGD_TRANSPORT_ADJOINT = 0, 1
 MP_SUR_NPARAMS = 41732
 
 _lib = None

@@ -4,9 +4,11 @@ Each test feeds the GPU path and the oracle the same seeded inputs (set into
 the filter with mp_debug_set) and runs one stage (mp_debug_stage):
   bit-exact   map Gaussian ids, voxels and means; NNF lookups (dense and
               hashed); scan k-NN covariances; uniform initial poses; T^LSH;
-              LSH codes; bucket order and bounds; neighbour indices
+              LSH codes (decoupled and coupled tangent); bucket order and
+              bounds; neighbour indices (one and several hash tables)
   1e-4 rel    log-likelihoods (and H, b relative to their norm)
-  1e-4        updated poses (rad / m) after SVGD and prediction
+  1e-4        updated poses (rad / m) after SVGD (every gradient / transport
+              variant) and prediction
   1e-6 abs    posterior weights
 Sizes span several tiles with ragged tails (N = 1000, 1 scan tile + tail).
 """
@@ -245,6 +247,27 @@ def test_lsh_codes_and_sort_bitexact(room, O, bits):
         assert np.array_equal(f.debug_get("end"), e)
 
 
+def test_lsh_coupled_tangent_bitexact(room, O):
+    n = 5000
+    w = room["w"]
+    poses = _poses_mixed(w, n, 22)
+    p = _params(n, lsh_bits=20, lsh_sigma=0.3, lsh_alpha=1.0, lsh_tangent=M.MP_LSH_TANGENT_SE3)
+    f = M.Filter(room["gpu"], p, poses=poses)
+    info = room["gpu"].info()
+    lo = np.array(info["box_min"], np.float32); hi = np.array(info["box_max"], np.float32)
+    for it in (0, 5):
+        f.debug_stage(M.MP_STAGE_LSH, it)
+        TL = O.lsh_frame(4001, 0, it, lo, hi)
+        assert np.array_equal(f.debug_get("tlsh"), TL)
+        ref = O.lsh_codes(poses, TL, 1.0, 5.0, 2.5, 0.3, 20, 4001, 0, it, tangent=1)
+        assert np.array_equal(f.debug_get("codes"), ref)
+        assert not np.array_equal(ref, O.lsh_codes(poses, TL, 1.0, 5.0, 2.5, 0.3, 20, 4001, 0, it))
+        f.debug_stage(M.MP_STAGE_SORT)
+        s, h, e = O.bucket_sort(ref)
+        assert np.array_equal(f.debug_get("sorted"), s)
+        assert np.array_equal(f.debug_get("head"), h)
+
+
 @pytest.mark.parametrize("K,bits", [(8, 6), (16, 4), (5, 0)])
 def test_refresh_bitexact(room, O, K, bits):
     n = 1500
@@ -300,6 +323,57 @@ def test_svgd_parity(room, O):
     _, ref = O.svgd(poses, psi[:, :6].astype(np.float64), np.ascontiguousarray(nbr.T), 5.0, 2.5)
     assert _rot_err(out[:, :4], ref[:, :4]).max() < 1e-4
     assert np.abs(out[:, 4:7] - ref[:, 4:7]).max() < 1e-4
+
+
+@pytest.mark.parametrize("grad,transport", [(1, 0), (0, 1), (1, 1)])
+def test_svgd_variants_parity(room, O, grad, transport):
+    n, K = 2000, 8
+    w = room["w"]
+    rng = np.random.default_rng(6 + 2 * grad + transport)
+    poses = _poses_mixed(w, n, 42)
+    p = _params(n, k=K, lsh_bits=4, window_c=16, svgd_grad=grad, svgd_transport=transport)
+    f = M.Filter(room["gpu"], p, poses=poses)
+    f.debug_stage(M.MP_STAGE_LSH, 0)
+    f.debug_stage(M.MP_STAGE_SORT)
+    f.debug_stage(M.MP_STAGE_REFRESH)
+    nbr = np.ascontiguousarray(f.debug_get("nbr").T)
+    psi = np.zeros((n, 8), np.float32)
+    psi[:, :6] = rng.normal(scale=0.05, size=(n, 6))
+    f.debug_set("psi", psi)
+    f.debug_stage(M.MP_STAGE_SVGD)
+    out = f.debug_get("poses")
+    psi64 = psi[:, :6].astype(np.float64)
+    _, ref = O.svgd(poses, psi64, nbr, 5.0, 2.5, grad_exact=bool(grad), transport=bool(transport))
+    assert _rot_err(out[:, :4], ref[:, :4]).max() < 1e-4
+    assert np.abs(out[:, 4:7] - ref[:, 4:7]).max() < 1e-4
+    # the variant moves the result well beyond the tolerance
+    _, ref0 = O.svgd(poses, psi64, nbr, 5.0, 2.5)
+    assert np.abs(ref[:, 4:7] - ref0[:, 4:7]).max() > 1e-2
+
+
+def test_lsh_tables_in_step(room, O):
+    # three hash tables in one iteration: the lists after the step are those
+    # of three refreshes in a row, table l drawn with counter l
+    n, K, L = 3000, 8, 3
+    w = room["w"]
+    poses = _poses_mixed(w, n, 43)
+    p = _params(n, k=K, lsh_bits=6, window_c=K, svgd_iters=1, lsh_tables=L)
+    f = M.Filter(room["gpu"], p, poses=poses)
+    f.scan_upload(w["scans"][0])
+    f.step()
+    times = f.stage_times()
+    assert times["lsh"][1] == L and times["refresh"][1] == L and times["svgd"][1] == 1
+    info = room["gpu"].info()
+    lo = np.array(info["box_min"], np.float32); hi = np.array(info["box_max"], np.float32)
+    old = np.full((n, K), -1, np.int32)
+    old[:, 0] = np.arange(n)            # the lists a new filter starts from
+    for l in range(L):
+        codes = O.lsh_codes(poses, O.lsh_frame(4001, 0, l, lo, hi), 1.0, 5.0, 2.5, 0.3, 6, 4001, 0, l)
+        s, _, _ = O.bucket_sort(codes)
+        old, q, _ = O.refresh(poses, s, codes, K, K, 5.0, 2.5, old)
+    assert np.array_equal(f.debug_get("nbr").T, old)
+    kv = f.debug_get("kval").T.astype(np.float64)
+    assert np.abs(kv - np.where(old >= 0, np.exp(-q.astype(np.float64)), 0.0)).max() < 1e-6
 
 
 def test_posterior_parity(room, O):
