@@ -82,6 +82,8 @@ def _declare(L):
     L.mpo_voxel_of.argtypes = [_f32p, C.c_int64, C.c_float, _i32p]
     L.mpo_map_build.argtypes = [_f32p, C.c_int64, C.c_float, C.c_int, C.c_int, C.c_float]
     L.mpo_map_build.restype = _vp
+    L.mpo_map_build_points.argtypes = [_f32p, C.c_int64, C.c_float, C.c_int, C.c_int, C.c_int, C.c_int, C.c_float, _vp]
+    L.mpo_map_build_points.restype = _vp
     L.mpo_map_free.argtypes = [_vp]
     L.mpo_map_num_gauss.argtypes = [_vp]; L.mpo_map_num_gauss.restype = C.c_int64
     L.mpo_map_num_band.argtypes = [_vp]; L.mpo_map_num_band.restype = C.c_int64
@@ -217,12 +219,28 @@ def voxel_of(p, r):
 
 # --------------------------------------------------------------------- map
 class Map:
-    """Per-voxel Gaussians and the banded nearest-neighbour field."""
+    """Gaussians and the banded nearest-neighbour field.
 
-    def __init__(self, xyz, voxel, nnf_radius=2, min_points=5, cov_eps=1e-3):
+    per_point=False: one Gaussian per voxel of >= min_points points, band
+    voxels map to the occupied voxel at the smallest integer offset.
+    per_point=True: one Gaussian per map point (its point_k nearest
+    neighbours within Chebyshev point_search voxels, kept when the
+    neighbourhood holds >= min_points points), cells map to the kept point
+    nearest their centre within nnf_radius * voxel (knn: the neighbour lists)."""
+
+    def __init__(self, xyz, voxel, nnf_radius=2, min_points=5, cov_eps=1e-3, per_point=False, point_k=10,
+                 point_search=2, want_knn=False):
         P = _f32(xyz).reshape(-1, 3)
         self.voxel = float(voxel)
-        self.handle = lib().mpo_map_build(P, P.shape[0], voxel, nnf_radius, min_points, cov_eps)
+        self.knn = None
+        if per_point:
+            self.knn = np.zeros((max(P.shape[0], 1), point_k), np.int32) if want_knn else None
+            self.handle = lib().mpo_map_build_points(P, P.shape[0], voxel, nnf_radius, point_k, point_search,
+                                                     min_points, cov_eps, _ptr(self.knn))
+            if want_knn:
+                self.knn = self.knn[:P.shape[0]]
+        else:
+            self.handle = lib().mpo_map_build(P, P.shape[0], voxel, nnf_radius, min_points, cov_eps)
         self.G = int(lib().mpo_map_num_gauss(self.handle))
         self.nb = int(lib().mpo_map_num_band(self.handle))
 

@@ -655,6 +655,176 @@ MPO_API mpo_map* mpo_map_build(const float* xyz, int64_t n, float r, int R, int 
     return m;
 }
 
+/* ======================================================================= */
+/* Map of per-point Gaussians and its nearest-neighbour field, the paper's */
+/* own construction (Sec. III-C): every map point p_k is a Gaussian        */
+/* N(p_k, Sigma_k), Sigma_k from the point's neighbourhood (GICP, Segal et */
+/* al. 2009), and the field, a grid of cell edge r, stores for each cell   */
+/* the map point nearest to the cell's centre.                             */
+/*   neighbourhood  the k nearest other points j, by the FP32 program       */
+/*                  d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz)), dx = x_j - x_i */
+/*                  (the scan covariances' program), ties to the lower      */
+/*                  index, among the points whose voxel floor(p / r) lies   */
+/*                  within Chebyshev distance S of the point's voxel        */
+/*   Gaussian       FP64 mean and 1/(m) covariance of {p_i} U neighbours    */
+/*                  (m = count, summed self first then in list order),      */
+/*                  GICP-normalised: I - (1 - eps) n n^T; mu = p_i itself;  */
+/*                  the point is kept when m >= min_pts                     */
+/*   ids            kept points in ascending (vz, vy, vx, index)            */
+/*   field          cell c (voxel coordinates) maps to the kept point       */
+/*                  minimising (d2, id) with d2 = (ex*ex + ey*ey) + ez*ez,  */
+/*                  e = p - ((float)c + 0.5) r (FP32), over points with     */
+/*                  d2 <= (R r)^2; a point within R r of the centre has its */
+/*                  voxel within Chebyshev R of c, so each kept point       */
+/*                  proposes to the cells of that block only               */
+/* Band keys carry d2 as its IEEE bit pattern (monotone for d2 >= 0).      */
+/* ======================================================================= */
+MPO_API mpo_map* mpo_map_build_points(const float* xyz, int64_t n, float r, int R, int k, int S, int min_pts,
+                                      float eps, int32_t* knn_out /* n*k nullable, -1 pads */) {
+    mpo_map* m = (mpo_map*)calloc(1, sizeof(mpo_map));
+    m->r = r; m->inv_r = 1.0f / r; m->R = R; m->min_pts = min_pts; m->eps = eps;
+    m->a32 = 1.0f - eps;
+    int32_t* vx = (int32_t*)malloc(sizeof(int32_t) * 3 * (size_t)(n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; ++i)
+        for (int a = 0; a < 3; ++a) vx[3 * i + a] = floor_to_i32(xyz[3 * i + a] * m->inv_r);
+    double* c64 = (double*)malloc(sizeof(double) * 6 * (size_t)(n > 0 ? n : 1));
+    double* nv64 = (double*)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
+    int32_t* cnt = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+#pragma omp parallel
+    {
+        float* bd = (float*)malloc(sizeof(float) * (size_t)(k > 0 ? k : 1));
+        int64_t* bj = (int64_t*)malloc(sizeof(int64_t) * (size_t)(k > 0 ? k : 1));
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t i = 0; i < n; ++i) {
+            int32_t c = 0;
+            for (int64_t j = 0; j < n; ++j) {
+                if (j == i) continue;
+                int far = 0;
+                for (int a = 0; a < 3; ++a) {
+                    int64_t dv = (int64_t)vx[3 * j + a] - vx[3 * i + a];
+                    if (dv > S || dv < -S) far = 1;
+                }
+                if (far) continue;
+                float dx = xyz[3 * j] - xyz[3 * i], dy = xyz[3 * j + 1] - xyz[3 * i + 1];
+                float dz = xyz[3 * j + 2] - xyz[3 * i + 2];
+                float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                int32_t p;
+                if (c < k) p = c++;
+                else if (d2 < bd[k - 1] || (d2 == bd[k - 1] && j < bj[k - 1])) p = k - 1;
+                else continue;
+                while (p > 0 && (bd[p - 1] > d2 || (bd[p - 1] == d2 && bj[p - 1] > j))) {
+                    bd[p] = bd[p - 1]; bj[p] = bj[p - 1]; --p;
+                }
+                bd[p] = d2; bj[p] = j;
+            }
+            if (knn_out)
+                for (int32_t a = 0; a < k; ++a) knn_out[i * k + a] = a < c ? (int32_t)bj[a] : -1;
+            cnt[i] = c + 1;
+            if (c + 1 < min_pts) continue;
+            double sm[3] = {xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2]};
+            for (int32_t a = 0; a < c; ++a)
+                for (int q = 0; q < 3; ++q) sm[q] = sm[q] + (double)xyz[3 * bj[a] + q];
+            double mu[3];
+            for (int q = 0; q < 3; ++q) mu[q] = sm[q] / (double)(c + 1);
+            double S6[6] = {0, 0, 0, 0, 0, 0};
+            for (int32_t a = -1; a < c; ++a) {
+                int64_t j = a < 0 ? i : bj[a];
+                double d[3];
+                for (int q = 0; q < 3; ++q) d[q] = (double)xyz[3 * j + q] - mu[q];
+                S6[0] += d[0] * d[0]; S6[1] += d[0] * d[1]; S6[2] += d[0] * d[2];
+                S6[3] += d[1] * d[1]; S6[4] += d[1] * d[2]; S6[5] += d[2] * d[2];
+            }
+            for (int q = 0; q < 6; ++q) S6[q] /= (double)(c + 1);
+            double Sf[9];
+            sym6_full(S6, Sf);
+            gicp_normalise(Sf, (double)eps, c64 + 6 * i, nv64 + 3 * i);
+        }
+        free(bd);
+        free(bj);
+    }
+    /* ids: kept points in ascending (vz, vy, vx, index) */
+    vrec* recs = (vrec*)malloc(sizeof(vrec) * (size_t)(n > 0 ? n : 1));
+    int64_t G = 0;
+    for (int64_t i = 0; i < n; ++i)
+        if (cnt[i] >= min_pts) {
+            memcpy(recs[G].v, vx + 3 * i, sizeof(recs[G].v));
+            recs[G].idx = i;
+            ++G;
+        }
+    qsort(recs, (size_t)G, sizeof(vrec), cmp_vrec);
+    m->G = G;
+    size_t Ga = (size_t)(G ? G : 1);
+    m->vox = (int32_t*)malloc(sizeof(int32_t) * 3 * Ga);
+    m->mu = (float*)malloc(sizeof(float) * 3 * Ga);
+    m->cov = (float*)malloc(sizeof(float) * 6 * Ga);
+    m->nrm = (float*)malloc(sizeof(float) * 3 * Ga);
+    m->mu64 = (double*)malloc(sizeof(double) * 3 * Ga);
+    m->cov64 = (double*)malloc(sizeof(double) * 6 * Ga);
+    m->npts = (int32_t*)malloc(sizeof(int32_t) * Ga);
+    for (int64_t g = 0; g < G; ++g) {
+        int64_t i = recs[g].idx;
+        for (int a = 0; a < 3; ++a) {
+            m->vox[3 * g + a] = recs[g].v[a];
+            m->mu[3 * g + a] = xyz[3 * i + a];
+            m->mu64[3 * g + a] = (double)xyz[3 * i + a];
+            m->nrm[3 * g + a] = (float)nv64[3 * i + a];
+        }
+        for (int a = 0; a < 6; ++a) { m->cov64[6 * g + a] = c64[6 * i + a]; m->cov[6 * g + a] = (float)c64[6 * i + a]; }
+        m->npts[g] = cnt[i];
+    }
+    free(c64); free(nv64); free(cnt); free(vx);
+    /* field */
+    if (G > 0) {
+        int32_t lo[3], hi[3];
+        for (int a = 0; a < 3; ++a) { lo[a] = m->vox[a]; hi[a] = m->vox[a]; }
+        for (int64_t g = 0; g < G; ++g)
+            for (int a = 0; a < 3; ++a) {
+                if (m->vox[3 * g + a] < lo[a]) lo[a] = m->vox[3 * g + a];
+                if (m->vox[3 * g + a] > hi[a]) hi[a] = m->vox[3 * g + a];
+            }
+        for (int a = 0; a < 3; ++a) { m->org[a] = lo[a] - R; m->dim[a] = hi[a] - lo[a] + 1 + 2 * R; }
+        float lim = (float)R * r;
+        float lim2 = lim * lim;
+        int side = 2 * R + 1;
+        int64_t ne = G * (int64_t)side * side * side;
+        brec* br = (brec*)malloc(sizeof(brec) * (size_t)(ne > 0 ? ne : 1));
+        int64_t q = 0;
+        for (int64_t g = 0; g < G; ++g)
+            for (int dz = -R; dz <= R; ++dz)
+                for (int dy = -R; dy <= R; ++dy)
+                    for (int dx = -R; dx <= R; ++dx) {
+                        int32_t v[3] = {m->vox[3 * g] + dx, m->vox[3 * g + 1] + dy, m->vox[3 * g + 2] + dz};
+                        float e[3];
+                        for (int a = 0; a < 3; ++a) e[a] = m->mu[3 * g + a] - ((float)v[a] + 0.5f) * r;
+                        float d2 = (e[0] * e[0] + e[1] * e[1]) + e[2] * e[2];
+                        if (!(d2 <= lim2)) continue;
+                        uint32_t bits;
+                        memcpy(&bits, &d2, 4);
+                        br[q].key = grid_key(m, v);
+                        br[q].d2 = (int32_t)bits;
+                        br[q].gid = (int32_t)g;
+                        ++q;
+                    }
+        qsort(br, (size_t)q, sizeof(brec), cmp_brec);
+        int64_t nb = 0;
+        for (int64_t t = 0; t < q; ++t)
+            if (t == 0 || br[t].key != br[t - 1].key) ++nb;
+        m->nb = nb;
+        m->bkey = (int64_t*)malloc(sizeof(int64_t) * (size_t)(nb ? nb : 1));
+        m->bgid = (int32_t*)malloc(sizeof(int32_t) * (size_t)(nb ? nb : 1));
+        int64_t j = 0;
+        for (int64_t t = 0; t < q; ++t)
+            if (t == 0 || br[t].key != br[t - 1].key) { m->bkey[j] = br[t].key; m->bgid[j] = br[t].gid; ++j; }
+        free(br);
+    } else {
+        m->nb = 0;
+        m->bkey = (int64_t*)malloc(sizeof(int64_t));
+        m->bgid = (int32_t*)malloc(sizeof(int32_t));
+    }
+    free(recs);
+    return m;
+}
+
 MPO_API void mpo_map_free(mpo_map* m) {
     if (!m) return;
     free(m->vox); free(m->mu); free(m->cov); free(m->nrm); free(m->mu64); free(m->cov64); free(m->npts);

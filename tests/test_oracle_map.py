@@ -8,6 +8,11 @@
                   smallest integer squared distance, ties to the smaller id)
   scan covariances  numpy k-NN by squared distance (ties to lower index),
                   numpy covariance of the point and its neighbours
+  per-point map   neighbour lists against scipy cKDTree (search block covering
+                  the map) and numpy brute force within the Chebyshev voxel
+                  block; covariances against numpy; a plane's normal;
+                  the field against a KD-tree nearest kept point of every
+                  cell centre within R r; ids in (vz, vy, vx, index) order
 """
 import numpy as np
 import pytest
@@ -153,3 +158,121 @@ def test_scan_cov_planar_and_tiny(O):
     assert np.allclose(cov64[:, [0, 3]], 1.0, atol=1e-12)
     _, cov, _ = O.scan_cov(P[:4], k=10)                   # fewer than 5 points -> identity
     assert np.allclose(cov, [1, 0, 0, 1, 0, 1])
+
+
+def _surface_points(rng, n, r):
+    """points on two perpendicular planes and a sphere cap, spacing ~ r / 3"""
+    a = rng.uniform(0, 3, size=(n // 3, 2))
+    p1 = np.c_[a, np.zeros(n // 3)]
+    b = rng.uniform(0, 3, size=(n // 3, 2))
+    p2 = np.c_[b[:, 0], np.zeros(n // 3) + 0.01, b[:, 1]]
+    m = n - 2 * (n // 3)
+    u = rng.normal(size=(m, 3))
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    p3 = np.array([1.5, 1.5, 1.5]) + 0.8 * u
+    return np.concatenate([p1, p2, p3]).astype(np.float32) + rng.normal(scale=0.002, size=(n, 3)).astype(np.float32)
+
+
+def test_point_map_knn_against_kdtree(O):
+    from scipy.spatial import cKDTree
+    rng = np.random.default_rng(20)
+    P = _surface_points(rng, 3000, 0.2)
+    k = 10
+    m = O.Map(P, 0.2, nnf_radius=2, min_points=5, per_point=True, point_k=k, point_search=1000, want_knn=True)
+    d, j = cKDTree(P.astype(np.float64)).query(P.astype(np.float64), k=k + 2)
+    checked = 0
+    for i in range(len(P)):
+        # the query returns the point itself first (distance 0)
+        nb = [x for x in j[i] if x != i][:k]
+        dd = [dx for dx, x in zip(d[i], j[i]) if x != i]
+        if dd[k] - dd[k - 1] > 1e-5 and np.all(np.diff(dd[:k]) > 1e-5):
+            assert list(m.knn[i]) == nb, i
+            checked += 1
+    assert checked > 0.9 * len(P)
+
+
+def test_point_map_voxel_block_bruteforce(O):
+    rng = np.random.default_rng(21)
+    P = _surface_points(rng, 1500, 0.25)
+    r, k, S = 0.25, 8, 1
+    m = O.Map(P, r, nnf_radius=2, min_points=5, per_point=True, point_k=k, point_search=S, want_knn=True)
+    P64 = P.astype(np.float64)
+    V = np.floor(P * np.float32(1.0 / r)).astype(np.int64)
+    for i in range(0, len(P), 7):
+        inblk = np.all(np.abs(V - V[i]) <= S, axis=1)
+        inblk[i] = False
+        cand = np.nonzero(inblk)[0]
+        dd = np.sum((P64[cand] - P64[i]) ** 2, axis=1)
+        order = cand[np.lexsort((cand, dd))]
+        want = list(order[:k]) + [-1] * max(0, k - len(order))
+        ds = np.sort(dd)
+        if len(ds) <= k or ds[k] - ds[k - 1] > 1e-9:
+            assert list(m.knn[i]) == want, i
+
+
+def test_point_map_gaussians_against_numpy(O):
+    rng = np.random.default_rng(22)
+    P = _surface_points(rng, 2000, 0.2)
+    m = O.Map(P, 0.2, nnf_radius=2, min_points=6, per_point=True, point_k=9, point_search=2, want_knn=True)
+    g = m.gauss()
+    V = np.floor(P * np.float32(1.0 / 0.2)).astype(np.int64)
+    kept = [i for i in range(len(P)) if np.sum(m.knn[i] >= 0) + 1 >= 6]
+    order = sorted(kept, key=lambda i: (V[i, 2], V[i, 1], V[i, 0], i))
+    assert m.G == len(order)
+    assert np.array_equal(g["mu"], P[order])
+    assert np.array_equal(g["vox"], V[order].astype(np.int32))
+    for gi in range(0, m.G, 11):
+        i = order[gi]
+        nb = m.knn[i][m.knn[i] >= 0]
+        X = np.concatenate([P[i:i + 1], P[nb]]).astype(np.float64)
+        C = np.cov(X.T, bias=True)
+        w, U = np.linalg.eigh(C)
+        n = U[:, 0]
+        assert g["npts"][gi] == len(X)
+        if w[1] - w[0] > 1e-6 * max(w[2], 1e-12):
+            assert abs(abs(float(g["normal"][gi] @ n)) - 1) < 1e-6
+            a = 1 - 1e-3
+            ref = np.eye(3) - a * np.outer(n, n)
+            cov = g["cov64"][gi]
+            full = np.array([[cov[0], cov[1], cov[2]], [cov[1], cov[3], cov[4]], [cov[2], cov[4], cov[5]]])
+            assert np.allclose(full, ref, atol=1e-9)
+
+
+def test_point_map_plane_normal(O):
+    rng = np.random.default_rng(23)
+    P = np.c_[rng.uniform(0, 2, size=(800, 2)), np.full(800, 0.3)].astype(np.float32)
+    m = O.Map(P, 0.2, nnf_radius=1, min_points=5, per_point=True, point_k=10, point_search=2)
+    g = m.gauss()
+    assert m.G == 800
+    assert np.allclose(np.abs(g["normal"][:, 2]), 1.0, atol=1e-6)
+
+
+def test_point_map_field_against_kdtree(O):
+    from scipy.spatial import cKDTree
+    rng = np.random.default_rng(24)
+    r, R = 0.2, 2
+    P = _surface_points(rng, 2500, r)
+    m = O.Map(P, r, nnf_radius=R, min_points=5, per_point=True, point_k=10, point_search=2)
+    g = m.gauss()
+    org, dim = m.grid()
+    keys, gids = m.band()
+    tree = cKDTree(g["mu"].astype(np.float64))
+    zz, yy, xx = np.meshgrid(np.arange(dim[2]), np.arange(dim[1]), np.arange(dim[0]), indexing="ij")
+    lin = ((zz * dim[1] + yy) * dim[0] + xx).ravel()
+    cells = np.stack([xx.ravel() + org[0], yy.ravel() + org[1], zz.ravel() + org[2]], 1)
+    centres = (cells.astype(np.float64) + 0.5) * r
+    d, j = tree.query(centres, k=2)
+    field = np.full(lin.size, -1, np.int64)
+    field[keys] = gids
+    lim = R * r
+    clear = (np.abs(d[:, 0] - lim) > 1e-5) & (d[:, 1] - d[:, 0] > 1e-6)
+    want = np.where(d[:, 0] <= lim, j[:, 0], -1)
+    assert np.array_equal(field[clear], want[clear])
+    assert clear.mean() > 0.99
+    # lookups go through the same field
+    q = rng.uniform(P.min(0) - 0.5, P.max(0) + 0.5, size=(5000, 3)).astype(np.float32)
+    cq = np.floor(q * np.float32(1.0 / r)).astype(np.int64) - org
+    inside = np.all((cq >= 0) & (cq < dim), axis=1)
+    lq = (cq[:, 2] * dim[1] + cq[:, 1]) * dim[0] + cq[:, 0]
+    exp = np.where(inside, field[np.where(inside, lq, 0)], -1)
+    assert np.array_equal(m.lookup(q), exp)
