@@ -282,10 +282,17 @@ def sequence_main(args):
     t0 = time.perf_counter()
     w = S.build_workload("floor", frames=frames, kidnap_frame=kid, kidnap_dist=20.0, occlusion=occl)
     log("sequence generated in %.1f s" % (time.perf_counter() - t0))
-    m = M.Map(torch.from_numpy(w["map_xyz"]).cuda(), voxel=0.5)
+    if args.map == "point":
+        # the paper's indoor field: 0.1 m cells; coverage and inlier gate 0.5 m
+        m = M.Map(torch.from_numpy(w["map_xyz"]).cuda(), voxel=0.1, nnf_radius=5, gauss_mode=M.MP_GAUSS_POINT)
+        dmax = 0.5
+    else:
+        m = M.Map(torch.from_numpy(w["map_xyz"]).cuda(), voxel=0.5)
+        dmax = 1.0
     info = m.info()
+    log("map: %s" % info)
     p = M.mp_filter_default_params(n_particles=65536, k=16, lsh_bits=20, svgd_iters=20, post_iters=10, window_c=32,
-                                   d_max=1.0, seed=4002, **VARIANTS[args.variant])
+                                   d_max=dmax, seed=4002, **VARIANTS[args.variant])
     f = M.Filter(m, p, box=(info["box_min"], info["box_max"]))
     sm = M.Smoother(window=5, jump_m=1.0, jump_rad=0.2)
 
@@ -353,7 +360,8 @@ def sequence_main(args):
            "config": {"workload": "floor: 65536 particles x 4096 scan points x 20 SVGD iterations, %d frames, "
                                   "uniform start, scans blocked for frames %d..%d, 20 m kidnap at frame %d" %
                                   (frames, occl[0], occl[1] - 1, kid),
-                      "variant": args.variant, "variant_params": VARIANTS[args.variant]},
+                      "variant": args.variant, "variant_params": VARIANTS[args.variant],
+                      "map": args.map, "map_gaussians": info["num_gauss"], "d_max": dmax},
            "converged_frame": conv, "scans_return_frame": occl[1], "scored_frames": len(scored),
            "raw": raw_s, "smoothed": sm_s, "frames_with_scan_odometry": used_odo,
            "per_frame_error_raw": raw, "per_frame_error_smoothed": smooth}
@@ -653,6 +661,50 @@ def svgd_refresh_bytes(K):
     return 8.0 * K + 96.0, 48.0 + 12.0 * K
 
 
+def point_map_leg(M, xyz, wl, scans, odo, cell=0.2, radius=5, warmup=1, steps=2):
+    """The same filter step on the paper's own map: one Gaussian per map point
+    (10 nearest neighbours within 2 voxels), a dense nearest-point field of
+    `cell` m cells covering radius * cell around the map (the inlier gate d_max
+    set to that coverage).  Build time and bytes, step and likelihood times."""
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pm = M.Map(xyz, voxel=cell, nnf_radius=radius, min_points=5, gauss_mode=M.MP_GAUSS_POINT, point_k=10,
+               point_search=2)
+    torch.cuda.synchronize()
+    t_build = time.perf_counter() - t0
+    info = pm.info()
+    log("per-point map built in %.2f s: %s" % (t_build, info))
+    dmax = radius * cell
+    p = M.mp_filter_default_params(n_particles=wl["particles"], k=wl["k"], lsh_bits=wl["lsh_bits"],
+                                   svgd_iters=wl["svgd_iters"], post_iters=wl["post_iters"],
+                                   window_c=wl["window_c"], d_max=dmax, seed=4003)
+    f = M.Filter(pm, p, box=(info["box_min"], info["box_max"]))
+    ms, lik, nlik = [], [], []
+    for k in range(warmup + steps):
+        dT, cov = odo[k] if k > 0 else (None, None)
+        f.scan_upload(scans[k])
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        f.step(dT, cov)
+        e1.record()
+        torch.cuda.synchronize()
+        if k >= warmup:
+            st = f.stage_times()
+            ms.append(e0.elapsed_time(e1))
+            lik.append(st["likelihood_core"][0])
+            nlik.append(st["likelihood_core"][1])
+    psi = f.debug_get("psi")
+    inl = float(psi[:, 7].astype(np.float64).sum()) / (float(wl["particles"]) * wl["scan_points"])
+    f.close()
+    pm.close()
+    torch.cuda.synchronize()
+    return {"cell_m": cell, "nnf_radius": radius, "d_max": dmax, "build_s": round(t_build, 3),
+            "num_gauss": info["num_gauss"], "field_cells": info["table_slots"], "band_cells": info["num_band"],
+            "device_bytes": info["device_bytes"], "step_ms": round(float(np.median(ms)), 3),
+            "likelihood_launch_ms": round(sum(lik) / max(sum(nlik), 1), 3), "inlier_fraction": round(inl, 4)}
+
+
 def _med_p90(v):
     a = np.asarray(v, np.float64)
     return {"median_ms": round(float(np.median(a)), 3), "p90_ms": round(float(np.percentile(a, 90)), 3),
@@ -712,6 +764,10 @@ def main():
     ap.add_argument("--surrogate-steps", type=int, default=1)
     ap.add_argument("--variant", default="default", choices=sorted(VARIANTS),
                     help="sequence: LSH / SVGD accuracy variant of the filter")
+    ap.add_argument("--no-point-map", action="store_true",
+                    help="skip the leg on the map of per-point Gaussians (0.2 m nearest-point field)")
+    ap.add_argument("--map", default="voxel", choices=["voxel", "point"],
+                    help="sequence: per-voxel Gaussians (0.5 m) or per-point Gaussians (0.1 m field)")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the leg timing the LSH tangent / tables and SVGD gradient / transport variants")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -844,6 +900,11 @@ def main():
     if not args.no_variants:
         f.close()
         res["variants"] = variants_leg(M, m, wl, minfo, scans, odo)
+    if not args.no_point_map:
+        f.close()
+        res["map_per_voxel"] = {"voxel_m": wl["voxel"], "num_gauss": minfo["num_gauss"],
+                                "device_bytes": minfo["device_bytes"], "d_max": 2.0 * wl["voxel"]}
+        res["map_per_point"] = point_map_leg(M, xyz, wl, scans, odo)
     res["odometry"] = odometry_leg(M, m, w, scans, not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(wl, w, w["scans"][-1], args.cpu_budget)

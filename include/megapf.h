@@ -62,15 +62,30 @@ typedef struct mp_filter_s* mp_filter;
 
 enum { MP_NNF_AUTO = 0, MP_NNF_HASH = 1, MP_NNF_DENSE = 2 };
 
+/* Map elements (Sec. III-C):
+ *   VOXEL  one Gaussian per voxel holding >= min_points map points; the field
+ *          maps each voxel within Chebyshev distance R of a kept voxel to the
+ *          kept voxel at the smallest integer squared offset.
+ *   POINT  the paper's construction: one Gaussian per map point, from the
+ *          point and its point_k nearest other map points among those whose
+ *          voxel lies within Chebyshev distance point_search (kept when that
+ *          neighbourhood holds >= min_points points); the field, a grid of
+ *          cell edge `voxel`, maps each cell to the kept point nearest to the
+ *          cell's centre within nnf_radius * voxel (DENSE backend only). */
+enum { MP_GAUSS_VOXEL = 0, MP_GAUSS_POINT = 1 };
+
 typedef struct {
-    float voxel;        /* voxel edge r in metres, > 0 */
+    float voxel;        /* voxel edge r in metres, > 0 (POINT: the field's cell edge) */
     int32_t nnf_radius; /* Chebyshev radius of the nearest-neighbour band, voxels, 0..8 */
-    int32_t min_points; /* voxels holding fewer map points are dropped, >= 3 */
+    int32_t min_points; /* voxels (POINT: neighbourhoods) holding fewer map points are dropped, >= 3 */
     float cov_eps;      /* GICP normalisation: Sigma = I - (1 - eps) n n^T, 0 < eps <= 1 */
     int32_t backend;    /* MP_NNF_*: open-addressing voxel hash map or dense grid;
                            AUTO picks DENSE when the band grid has <= 2^26 cells and
                            < 2^24 cells per z plane; DENSE beyond 2^27 - 2 cells or
                            2^24 per plane fails with MP_E_UNSUPPORTED */
+    int32_t gauss_mode;   /* MP_GAUSS_*: map elements */
+    int32_t point_k;      /* POINT: neighbours per point, 3..32 */
+    int32_t point_search; /* POINT: Chebyshev voxel radius of the neighbour search, 1..4 */
 } mp_map_params;
 
 typedef struct {
@@ -85,7 +100,8 @@ typedef struct {
     int64_t device_bytes;    /* device memory held by the map */
 } mp_map_info;
 
-/* Fill defaults: voxel 0.5, nnf_radius 2, min_points 5, cov_eps 1e-3, AUTO. */
+/* Fill defaults: voxel 0.5, nnf_radius 2, min_points 5, cov_eps 1e-3, AUTO,
+ * VOXEL Gaussians, point_k 10, point_search 2. */
 MP_API void mp_map_default_params(mp_map_params* p);
 
 /* Build the per-voxel Gaussian map and its nearest-neighbour field
@@ -100,10 +116,17 @@ MP_API void mp_map_default_params(mp_map_params* p);
  *   follow ascending (vz, vy, vx).  Every voxel within Chebyshev distance R of
  *   a kept voxel maps to the kept voxel at the smallest integer squared
  *   distance, ties to the smaller id; other voxels are misses.
+ * With gauss_mode POINT the Gaussians are the map points themselves (mu = p,
+ * count = size of the neighbourhood) in ascending (vz, vy, vx, point index);
+ * a point's neighbours are ranked by the FP32 squared distance
+ * fmaf(dx, dx, fmaf(dy, dy, dz * dz)), ties to the lower index; the field's
+ * key of a point for cell c is e^T e in FP32 ((ex ex + ey ey) + ez ez), e = p -
+ * ((float)c + 0.5) r, ties to the smaller id.
  * Errors: MP_E_ARG for n < 0, null, non-finite or out-of-range coordinates
  * (|p / r| >= 2^30) or bad params; MP_E_UNSUPPORTED when the band grid exceeds
- * 2^32 - 2 cells (hash) or 2^31 cells (dense).  n = 0 builds an empty map
- * (every lookup misses). */
+ * 2^32 - 2 cells (hash) or 2^27 - 2 cells or 2^24 cells per plane (dense), for
+ * POINT with the HASH backend, and for POINT when the box of all map voxels
+ * exceeds 2^28 cells.  n = 0 builds an empty map (every lookup misses). */
 MP_API mp_status mp_map_build(const float* xyz, int64_t n, const mp_map_params* params, void* stream, mp_map* out);
 
 MP_API mp_status mp_map_get_info(mp_map map, mp_map_info* out);

@@ -122,6 +122,9 @@ extern "C" void mp_map_default_params(mp_map_params* p) {
     p->min_points = 5;
     p->cov_eps = 1e-3f;
     p->backend = MP_NNF_AUTO;
+    p->gauss_mode = MP_GAUSS_VOXEL;
+    p->point_k = 10;
+    p->point_search = 2;
 }
 
 extern "C" mp_status mp_map_build(const float* xyz, int64_t n, const mp_map_params* params, void* stream,
@@ -133,6 +136,14 @@ extern "C" mp_status mp_map_build(const float* xyz, int64_t n, const mp_map_para
         if (params->min_points < 3) mp_throw(MP_E_ARG, "min_points must be >= 3");
         if (!(params->cov_eps > 0.0f && params->cov_eps <= 1.0f)) mp_throw(MP_E_ARG, "cov_eps must be in (0, 1]");
         if (params->backend < MP_NNF_AUTO || params->backend > MP_NNF_DENSE) mp_throw(MP_E_ARG, "bad backend");
+        if (params->gauss_mode != MP_GAUSS_VOXEL && params->gauss_mode != MP_GAUSS_POINT)
+            mp_throw(MP_E_ARG, "bad gauss_mode");
+        if (params->gauss_mode == MP_GAUSS_POINT) {
+            if (params->point_k < 3 || params->point_k > 32) mp_throw(MP_E_ARG, "point_k must be 3..32");
+            if (params->point_search < 1 || params->point_search > 4) mp_throw(MP_E_ARG, "point_search must be 1..4");
+            if (params->backend == MP_NNF_HASH)
+                mp_throw(MP_E_UNSUPPORTED, "per-point Gaussians take the dense field only");
+        }
         if (n > (int64_t)INT32_MAX) mp_throw(MP_E_UNSUPPORTED, "more than 2^31-1 map points");
         hipStream_t s = as_stream(stream);
         mp_map m = new mp_map_s();

@@ -6,6 +6,16 @@
 // Here the elements are per-voxel Gaussians and the field covers the band of
 // voxels within Chebyshev radius R of an occupied voxel.
 //
+// Per-point Gaussians (gauss_mode POINT, the paper's own construction):
+// after the same voxel sort, a dense grid of the occupied voxels' runs lets
+// each point search the voxel shells around its own for its k nearest other
+// points (register-resident sorted list; the search stops after shell s once
+// the k-th distance is below s r less a margin, since every point of an outer
+// shell is at least s r away); FP64 mean and covariance of the point and its
+// list, the same Jacobi normal; kept points compacted in sorted order; each
+// kept point proposes (FP32 |p - cell centre|^2 bits << 32 | id) to the cells
+// of the block within R around its voxel when that distance is <= R r.
+//
 // Build pipeline (one-time; synchronises the stream to size its outputs):
 //   voxel of each point (FP32 floor(p * 1/r)) and bounds
 //   -> linear key in the bounds grid, stable radix sort of (key, point index)
@@ -206,26 +216,187 @@ __global__ void k_compact(const uint32_t* __restrict__ keep, const uint32_t* __r
     atomicMax(&bounds[3], v.x); atomicMax(&bounds[4], v.y); atomicMax(&bounds[5], v.z);
 }
 
+// ------------------------------------------------------------ per-point Gaussians
+__device__ __forceinline__ bool knn_less(float d, int32_t j, float e, int32_t k) {
+    return d < e || (d == e && j < k);
+}
+
+// One lane per sorted map point: its k nearest other points among the voxels
+// within Chebyshev distance S (occupancy grid `occ` over the box lo + [0, dims)
+// holds the run of each occupied voxel), then the point's Gaussian.
+template <int KC>
+__global__ __launch_bounds__(256) void k_point_gauss(const float* __restrict__ xyz, const int32_t* __restrict__ order,
+                                                    const int32_t* __restrict__ start, int64_t nruns, int64_t n,
+                                                    const int3* __restrict__ vox, const int32_t* __restrict__ occ,
+                                                    int3 lo, int3 dims, int k, int S, float r, int32_t min_pts,
+                                                    float gicp_a, float4* __restrict__ st_mu, float4* __restrict__ st_n,
+                                                    int3* __restrict__ st_vox, uint32_t* __restrict__ keep) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const int32_t i = order[t];
+    const float px = xyz[3 * (int64_t)i], py = xyz[3 * (int64_t)i + 1], pz = xyz[3 * (int64_t)i + 2];
+    const int3 v = vox[i];
+    float bd[KC];
+    int32_t bj[KC];
+#pragma unroll
+    for (int a = 0; a < KC; ++a) {
+        bd[a] = INFINITY;
+        bj[a] = INT32_MAX;
+    }
+    float thd = INFINITY;      // entry k - 1 of the sorted list: the admission bound
+    int32_t thj = INT32_MAX;
+    int cnt = 0;
+    // a point of a voxel outside shell s lies more than s r away; the margin
+    // covers the FP32 voxelisation and squared-distance rounding
+    const float slop = 1e-3f * r + 5e-7f * (fabsf(px) + fabsf(py) + fabsf(pz));
+    for (int sh = 0; sh <= S; ++sh) {
+        for (int dz = -sh; dz <= sh; ++dz)
+            for (int dy = -sh; dy <= sh; ++dy)
+                for (int dx = -sh; dx <= sh; ++dx) {
+                    if (max(abs(dx), max(abs(dy), abs(dz))) != sh) continue;
+                    const int64_t ux = (int64_t)v.x + dx - lo.x, uy = (int64_t)v.y + dy - lo.y,
+                                  uz = (int64_t)v.z + dz - lo.z;
+                    if (ux < 0 || uy < 0 || uz < 0 || ux >= dims.x || uy >= dims.y || uz >= dims.z) continue;
+                    const int32_t run = occ[(uz * dims.y + uy) * dims.x + ux];
+                    if (run < 0) continue;
+                    const int64_t q0 = start[run], q1 = run + 1 < nruns ? start[run + 1] : n;
+                    for (int64_t q = q0; q < q1; ++q) {
+                        const int32_t j = order[q];
+                        if (j == i) continue;
+                        const float ex = xyz[3 * (int64_t)j] - px, ey = xyz[3 * (int64_t)j + 1] - py,
+                                    ez = xyz[3 * (int64_t)j + 2] - pz;
+                        float d = __builtin_fmaf(ex, ex, __builtin_fmaf(ey, ey, ez * ez));
+                        if (!knn_less(d, j, thd, thj)) continue;
+                        int32_t jj = j;
+#pragma unroll
+                        for (int a = 0; a < KC; ++a) {
+                            if (knn_less(d, jj, bd[a], bj[a])) {
+                                const float td = bd[a];
+                                const int32_t tj = bj[a];
+                                bd[a] = d;
+                                bj[a] = jj;
+                                d = td;
+                                jj = tj;
+                            }
+                        }
+                        cnt = min(cnt + 1, k);
+                        if (cnt == k) {
+#pragma unroll
+                            for (int a = 0; a < KC; ++a)
+                                if (a == k - 1) {
+                                    thd = bd[a];
+                                    thj = bj[a];
+                                }
+                        }
+                    }
+                }
+        if (sh >= 1 && cnt == k) {
+            const float b = (float)sh * r - slop;
+            if (thd < b * b) break;
+        }
+    }
+    const int m = cnt + 1;
+    st_vox[t] = v;
+    if (m < min_pts) {
+        keep[t] = 0;
+        return;
+    }
+    keep[t] = 1;
+    double sm[3] = {(double)px, (double)py, (double)pz};
+#pragma unroll
+    for (int a = 0; a < KC; ++a)
+        if (a < cnt) {
+            const int64_t j = bj[a];
+            sm[0] = sm[0] + (double)xyz[3 * j];
+            sm[1] = sm[1] + (double)xyz[3 * j + 1];
+            sm[2] = sm[2] + (double)xyz[3 * j + 2];
+        }
+    const double dm = (double)m;
+    const double mu[3] = {sm[0] / dm, sm[1] / dm, sm[2] / dm};
+    double S6[6];
+    {
+        const double d0 = (double)px - mu[0], d1 = (double)py - mu[1], d2 = (double)pz - mu[2];
+        S6[0] = 0.0 + d0 * d0; S6[1] = 0.0 + d0 * d1; S6[2] = 0.0 + d0 * d2;
+        S6[3] = 0.0 + d1 * d1; S6[4] = 0.0 + d1 * d2; S6[5] = 0.0 + d2 * d2;
+    }
+#pragma unroll
+    for (int a = 0; a < KC; ++a)
+        if (a < cnt) {
+            const int64_t j = bj[a];
+            const double d0 = (double)xyz[3 * j] - mu[0], d1 = (double)xyz[3 * j + 1] - mu[1],
+                         d2 = (double)xyz[3 * j + 2] - mu[2];
+            S6[0] += d0 * d0; S6[1] += d0 * d1; S6[2] += d0 * d2;
+            S6[3] += d1 * d1; S6[4] += d1 * d2; S6[5] += d2 * d2;
+        }
+    for (int a = 0; a < 6; ++a) S6[a] /= dm;
+    double A[9] = {S6[0], S6[1], S6[2], S6[1], S6[3], S6[4], S6[2], S6[4], S6[5]};
+    double nv[3];
+    jacobi_min_vec(A, nv);
+    st_mu[t] = make_float4(px, py, pz, (float)m);
+    const float n0 = (float)nv[0], n1 = (float)nv[1], n2 = (float)nv[2];
+    const double nn = (double)n0 * (double)n0 + (double)n1 * (double)n1 + (double)n2 * (double)n2;
+    st_n[t] = make_float4(n0, n1, n2, (float)(1.0 - (double)gicp_a * nn));
+}
+
+// occupancy grid: the run index of every occupied voxel (keys are the linear
+// index of the voxel in the box of all map voxels)
+__global__ void k_occ_fill(const uint64_t* __restrict__ keys, const int32_t* __restrict__ start, int64_t nruns,
+                           int32_t* __restrict__ occ) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nruns) return;
+    occ[keys[start[j]]] = (int32_t)j;
+}
+
 struct BandGrid {
     int32_t org[3];
     int32_t dim[3];
 };
 
 // every (Gaussian, offset) proposes (d2 << 32 | gid) to its band voxel
+// (grid-stride: G (2R+1)^3 proposals can exceed the 2^32 work-items of one dispatch)
 __global__ void k_band_dense(const int3* __restrict__ gvox, int64_t G, int R, BandGrid bg,
                              unsigned long long* __restrict__ cells) {
     const int side = 2 * R + 1;
     const int64_t vol = (int64_t)side * side * side;
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= G * vol) return;
-    const int64_t g = t / vol;
-    const int o = (int)(t - g * vol);
-    const int dx = o % side - R, dy = (o / side) % side - R, dz = o / (side * side) - R;
-    const int3 u = gvox[g];
-    const int64_t x = (int64_t)u.x + dx - bg.org[0], y = (int64_t)u.y + dy - bg.org[1], z = (int64_t)u.z + dz - bg.org[2];
-    const int64_t L = (z * bg.dim[1] + y) * bg.dim[0] + x;
-    const unsigned long long val = ((unsigned long long)(dx * dx + dy * dy + dz * dz) << 32) | (unsigned long long)g;
-    atomicMin(&cells[L], val);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < G * vol; t += stride) {
+        const int64_t g = t / vol;
+        const int o = (int)(t - g * vol);
+        const int dx = o % side - R, dy = (o / side) % side - R, dz = o / (side * side) - R;
+        const int3 u = gvox[g];
+        const int64_t x = (int64_t)u.x + dx - bg.org[0], y = (int64_t)u.y + dy - bg.org[1],
+                      z = (int64_t)u.z + dz - bg.org[2];
+        const int64_t L = (z * bg.dim[1] + y) * bg.dim[0] + x;
+        const unsigned long long val =
+            ((unsigned long long)(dx * dx + dy * dy + dz * dz) << 32) | (unsigned long long)g;
+        atomicMin(&cells[L], val);
+    }
+}
+
+// per-point field: every (kept point, offset) proposes (bits of the FP32
+// squared distance to the cell's centre << 32 | id) when within R r
+__global__ void k_band_points_dense(const int3* __restrict__ gvox, const float4* __restrict__ gauss, int64_t G,
+                                    int R, float r, float lim2, BandGrid bg, unsigned long long* __restrict__ cells) {
+    const int side = 2 * R + 1;
+    const int64_t vol = (int64_t)side * side * side;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < G * vol; t += stride) {
+        const int64_t g = t / vol;
+        const int o = (int)(t - g * vol);
+        const int dx = o % side - R, dy = (o / side) % side - R, dz = o / (side * side) - R;
+        const int3 u = gvox[g];
+        const float4 p = gauss[2 * g];
+        const int32_t cx = u.x + dx, cy = u.y + dy, cz = u.z + dz;
+        const float ex = p.x - ((float)cx + 0.5f) * r;
+        const float ey = p.y - ((float)cy + 0.5f) * r;
+        const float ez = p.z - ((float)cz + 0.5f) * r;
+        const float d2 = (ex * ex + ey * ey) + ez * ez;
+        if (!(d2 <= lim2)) continue;
+        const int64_t x = (int64_t)cx - bg.org[0], y = (int64_t)cy - bg.org[1], z = (int64_t)cz - bg.org[2];
+        const int64_t L = (z * bg.dim[1] + y) * bg.dim[0] + x;
+        const unsigned long long val = ((unsigned long long)__float_as_uint(d2) << 32) | (unsigned long long)g;
+        atomicMin(&cells[L], val);
+    }
 }
 
 __global__ void k_dense_finalize(const unsigned long long* __restrict__ cells, int64_t ncell,
@@ -267,58 +438,72 @@ __global__ void k_band_hash(const int3* __restrict__ gvox, int64_t G, int R, Ban
                             uint64_t mask) {
     const int side = 2 * R + 1;
     const int64_t vol = (int64_t)side * side * side;
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= G * vol) return;
-    const int64_t g = t / vol;
-    const int o = (int)(t - g * vol);
-    const int dx = o % side - R, dy = (o / side) % side - R, dz = o / (side * side) - R;
-    const int3 u = gvox[g];
-    const int32_t x = u.x + dx - bg.org[0], y = u.y + dy - bg.org[1], z = u.z + dz - bg.org[2];
-    const unsigned long long key = (((unsigned long long)z * bg.dim[1] + y) * bg.dim[0] + x) + 1ull;
-    const unsigned long long val = ((unsigned long long)(dx * dx + dy * dy + dz * dz) << 32) | (unsigned long long)g;
-    uint64_t h = grid_hash(x, y, z) & mask;
-    for (;;) {
-        const unsigned long long prev = atomicCAS(&tkey[h], 0ull, key);
-        if (prev == 0ull || prev == key) {
-            atomicMin(&tval[h], val);
-            return;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < G * vol; t += stride) {
+        const int64_t g = t / vol;
+        const int o = (int)(t - g * vol);
+        const int dx = o % side - R, dy = (o / side) % side - R, dz = o / (side * side) - R;
+        const int3 u = gvox[g];
+        const int32_t x = u.x + dx - bg.org[0], y = u.y + dy - bg.org[1], z = u.z + dz - bg.org[2];
+        const unsigned long long key = (((unsigned long long)z * bg.dim[1] + y) * bg.dim[0] + x) + 1ull;
+        const unsigned long long val =
+            ((unsigned long long)(dx * dx + dy * dy + dz * dz) << 32) | (unsigned long long)g;
+        uint64_t h = grid_hash(x, y, z) & mask;
+        for (;;) {
+            const unsigned long long prev = atomicCAS(&tkey[h], 0ull, key);
+            if (prev == 0ull || prev == key) {
+                atomicMin(&tval[h], val);
+                break;
+            }
+            h = (h + 1) & mask;
         }
-        h = (h + 1) & mask;
     }
 }
 
+// grid-stride over the slots; lane 0 holds the wave's smallest index, so it is
+// active in every iteration any lane of its wave takes
 __global__ void k_count_slots(const unsigned long long* __restrict__ tkey, int64_t cap,
                               unsigned long long* __restrict__ count) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int hit = (i < cap) && tkey[i] != 0ull;
-    const uint64_t b = __ballot(hit);
-    if ((threadIdx.x & 63) == 0 && b) atomicAdd(count, (unsigned long long)__popcll(b));
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < cap; i0 += stride) {
+        const int64_t i = i0 + threadIdx.x;
+        const int hit = (i < cap) && tkey[i] != 0ull;
+        const uint64_t b = __ballot(hit);
+        if ((threadIdx.x & 63) == 0 && b) atomicAdd(count, (unsigned long long)__popcll(b));
+    }
 }
 
 __global__ void k_rehash(const unsigned long long* __restrict__ tkey, const unsigned long long* __restrict__ tval,
                          int64_t cap, BandGrid bg, uint2* __restrict__ table, uint32_t mask) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= cap) return;
-    const unsigned long long k = tkey[i];
-    if (k == 0ull) return;
-    const uint64_t L = k - 1ull;
-    const int32_t x = (int32_t)(L % (uint64_t)bg.dim[0]);
-    const int32_t y = (int32_t)((L / (uint64_t)bg.dim[0]) % (uint64_t)bg.dim[1]);
-    const int32_t z = (int32_t)(L / ((uint64_t)bg.dim[0] * (uint64_t)bg.dim[1]));
-    uint32_t h = grid_hash(x, y, z) & mask;
-    const uint32_t key32 = (uint32_t)k;
-    const uint32_t gid = (uint32_t)(tval[i] & 0xFFFFFFFFull);
-    for (;;) {
-        const uint32_t prev = atomicCAS(&table[h].x, 0u, key32);
-        if (prev == 0u) {
-            table[h].y = gid;
-            return;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cap; i += stride) {
+        const unsigned long long k = tkey[i];
+        if (k == 0ull) continue;
+        const uint64_t L = k - 1ull;
+        const int32_t x = (int32_t)(L % (uint64_t)bg.dim[0]);
+        const int32_t y = (int32_t)((L / (uint64_t)bg.dim[0]) % (uint64_t)bg.dim[1]);
+        const int32_t z = (int32_t)(L / ((uint64_t)bg.dim[0] * (uint64_t)bg.dim[1]));
+        uint32_t h = grid_hash(x, y, z) & mask;
+        const uint32_t key32 = (uint32_t)k;
+        const uint32_t gid = (uint32_t)(tval[i] & 0xFFFFFFFFull);
+        for (;;) {
+            const uint32_t prev = atomicCAS(&table[h].x, 0u, key32);
+            if (prev == 0u) {
+                table[h].y = gid;
+                break;
+            }
+            h = (h + 1) & mask;
         }
-        h = (h + 1) & mask;
     }
 }
 
 inline unsigned nblk(int64_t n, int b = kBlock) { return (unsigned)((n + b - 1) / b); }
+
+// grid of a grid-stride launch over n items: at most 2^20 workgroups
+// (2^28 work-items, well inside the 2^32 of one dispatch)
+inline unsigned nblk_capped(int64_t n, int b = kBlock) {
+    return (unsigned)std::min<int64_t>((n + b - 1) / b, (int64_t)1 << 20);
+}
 
 uint64_t next_pow2(uint64_t x) {
     uint64_t p = 1;
@@ -332,15 +517,15 @@ uint64_t next_pow2(uint64_t x) {
 
 namespace {
 __global__ void k_lookup(MapView v, const float* __restrict__ xyz, int64_t n, int32_t* __restrict__ out) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    out[i] = mp_nnf_lookup(v, xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2]);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        out[i] = mp_nnf_lookup(v, xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2]);
 }
 }  // namespace
 
 void mp_map_lookup_launch(const MapView& v, const float* xyz_dev, int64_t n, int32_t* gid_dev, hipStream_t s) {
     if (n <= 0) return;
-    k_lookup<<<nblk(n), kBlock, 0, s>>>(v, xyz_dev, n, gid_dev);
+    k_lookup<<<nblk_capped(n), kBlock, 0, s>>>(v, xyz_dev, n, gid_dev);
     MP_CHECK_LAUNCH();
 }
 
@@ -413,19 +598,49 @@ void mp_build_map(mp_map m, const float* xyz, int64_t n, hipStream_t s) {
     d_start.alloc(sizeof(int32_t) * (size_t)nruns);
     k_run_starts<<<nblk(n), kBlock, 0, s>>>(d_flag.as<uint32_t>(), d_rid.as<uint32_t>(), n, d_start.as<int32_t>());
     MP_CHECK_LAUNCH();
+
+    // per-point Gaussians: one candidate per point (sorted order), found
+    // through an occupancy grid of the voxel runs; per-voxel: one per run
+    const bool per_point = P.gauss_mode == MP_GAUSS_POINT;
+    DevMem occ;
+    if (per_point) {
+        if (cells > 268435456.0)
+            mp_throw(MP_E_UNSUPPORTED, "mp_map_build: per-point Gaussians need the box of map voxels <= 2^28 cells");
+        occ.alloc(sizeof(int32_t) * (size_t)cells);
+        MP_HIP(hipMemsetAsync(occ.p, 0xFF, sizeof(int32_t) * (size_t)cells, s));
+        k_occ_fill<<<nblk(nruns), kBlock, 0, s>>>(d_keys.as<uint64_t>(), d_start.as<int32_t>(), nruns,
+                                                   occ.as<int32_t>());
+        MP_CHECK_LAUNCH();
+    }
     d_keys.release();
+    const int64_t nst = per_point ? n : (int64_t)nruns;
 
     DevMem st_mu, st_n, st_vox, keep, gid;
-    st_mu.alloc(sizeof(float4) * nruns);
-    st_n.alloc(sizeof(float4) * nruns);
-    st_vox.alloc(sizeof(int3) * nruns);
-    keep.alloc(sizeof(uint32_t) * nruns);
-    gid.alloc(sizeof(uint32_t) * nruns);
-    k_voxel_stats<<<nblk(nruns, 64), 64, 0, s>>>(xyz, d_vals.as<int32_t>(), d_start.as<int32_t>(), nruns, n,
-                                                  P.min_points, d_vox.as<int3>(), 1.0f - P.cov_eps, st_mu.as<float4>(),
-                                                  st_n.as<float4>(), st_vox.as<int3>(), keep.as<uint32_t>());
-    MP_CHECK_LAUNCH();
-    mp_scan_exclusive_u32(keep.as<uint32_t>(), gid.as<uint32_t>(), nruns, d_total.as<uint32_t>(), scratch, s);
+    st_mu.alloc(sizeof(float4) * nst);
+    st_n.alloc(sizeof(float4) * nst);
+    st_vox.alloc(sizeof(int3) * nst);
+    keep.alloc(sizeof(uint32_t) * nst);
+    gid.alloc(sizeof(uint32_t) * nst);
+    if (per_point) {
+        const int3 dims = make_int3((int)nx, (int)ny, (int)nz);
+        auto launch = [&](auto kern) {
+            kern<<<nblk(n), kBlock, 0, s>>>(xyz, d_vals.as<int32_t>(), d_start.as<int32_t>(), (int64_t)nruns, n,
+                                            d_vox.as<int3>(), occ.as<int32_t>(), lo, dims, P.point_k, P.point_search,
+                                            r, P.min_points, 1.0f - P.cov_eps, st_mu.as<float4>(), st_n.as<float4>(),
+                                            st_vox.as<int3>(), keep.as<uint32_t>());
+        };
+        if (P.point_k <= 8) launch(k_point_gauss<8>);
+        else if (P.point_k <= 16) launch(k_point_gauss<16>);
+        else launch(k_point_gauss<32>);
+        MP_CHECK_LAUNCH();
+    } else {
+        k_voxel_stats<<<nblk(nruns, 64), 64, 0, s>>>(xyz, d_vals.as<int32_t>(), d_start.as<int32_t>(), nruns, n,
+                                                      P.min_points, d_vox.as<int3>(), 1.0f - P.cov_eps,
+                                                      st_mu.as<float4>(), st_n.as<float4>(), st_vox.as<int3>(),
+                                                      keep.as<uint32_t>());
+        MP_CHECK_LAUNCH();
+    }
+    mp_scan_exclusive_u32(keep.as<uint32_t>(), gid.as<uint32_t>(), nst, d_total.as<uint32_t>(), scratch, s);
     uint32_t G = 0;
     MP_HIP(hipMemcpyAsync(&G, d_total.p, 4, hipMemcpyDeviceToHost, s));
     MP_HIP(hipStreamSynchronize(s));
@@ -438,13 +653,13 @@ void mp_build_map(mp_map m, const float* xyz, int64_t n, hipStream_t s) {
     gvox.alloc(sizeof(int3) * G);
     int32_t hb2[8] = {INT32_MAX, INT32_MAX, INT32_MAX, INT32_MIN, INT32_MIN, INT32_MIN, 0, 0};
     MP_HIP(hipMemcpyAsync(d_bounds.p, hb2, sizeof(hb2), hipMemcpyHostToDevice, s));
-    k_compact<<<nblk(nruns), kBlock, 0, s>>>(keep.as<uint32_t>(), gid.as<uint32_t>(), nruns, st_mu.as<float4>(),
+    k_compact<<<nblk(nst), kBlock, 0, s>>>(keep.as<uint32_t>(), gid.as<uint32_t>(), nst, st_mu.as<float4>(),
                                               st_n.as<float4>(), st_vox.as<int3>(), m->gauss.as<float4>(),
                                               gvox.as<int3>(), d_bounds.as<int32_t>());
     MP_CHECK_LAUNCH();
     MP_HIP(hipMemcpyAsync(hb2, d_bounds.p, sizeof(hb2), hipMemcpyDeviceToHost, s));
     MP_HIP(hipStreamSynchronize(s));
-    d_vox.release(); d_vals.release(); d_flag.release(); d_rid.release(); d_start.release();
+    d_vox.release(); d_vals.release(); d_flag.release(); d_rid.release(); d_start.release(); occ.release();
     st_mu.release(); st_n.release(); st_vox.release(); keep.release(); gid.release();
 
     BandGrid bg;
@@ -463,7 +678,7 @@ void mp_build_map(mp_map m, const float* xyz, int64_t n, hipStream_t s) {
     // 32-bit byte offsets: dim_x dim_y < 2^24 and cells + 1 < 2^27)
     const double bplane = (double)bg.dim[0] * (double)bg.dim[1];
     if (backend == MP_NNF_AUTO)
-        backend = (bcells <= 67108864.0 && bplane < 16777216.0) ? MP_NNF_DENSE : MP_NNF_HASH;
+        backend = (per_point || (bcells <= 67108864.0 && bplane < 16777216.0)) ? MP_NNF_DENSE : MP_NNF_HASH;
     if (backend == MP_NNF_DENSE && (bcells > 134217726.0 || bplane >= 16777216.0))
         mp_throw(MP_E_UNSUPPORTED, "mp_map_build: dense band grid exceeds 2^27 - 2 cells or 2^24 cells per plane");
     if (backend == MP_NNF_HASH && bcells > 4294967294.0)
@@ -480,7 +695,13 @@ void mp_build_map(mp_map m, const float* xyz, int64_t n, hipStream_t s) {
         DevMem wide;
         wide.alloc(sizeof(unsigned long long) * (size_t)nc);
         MP_HIP(hipMemsetAsync(wide.p, 0xFF, sizeof(unsigned long long) * (size_t)nc, s));
-        k_band_dense<<<nblk(emits), kBlock, 0, s>>>(gvox.as<int3>(), G, R, bg, wide.as<unsigned long long>());
+        if (per_point) {
+            const float lim = (float)R * r;
+            k_band_points_dense<<<nblk_capped(emits), kBlock, 0, s>>>(gvox.as<int3>(), m->gauss.as<float4>(), G, R, r,
+                                                               lim * lim, bg, wide.as<unsigned long long>());
+        } else {
+            k_band_dense<<<nblk_capped(emits), kBlock, 0, s>>>(gvox.as<int3>(), G, R, bg, wide.as<unsigned long long>());
+        }
         MP_CHECK_LAUNCH();
         m->dense.alloc(sizeof(int32_t) * (size_t)nc);
         k_dense_finalize<<<nblk(nc), kBlock, 0, s>>>(wide.as<unsigned long long>(), nc, m->dense.as<int32_t>(),
@@ -505,10 +726,10 @@ void mp_build_map(mp_map m, const float* xyz, int64_t n, hipStream_t s) {
         tv.alloc(sizeof(unsigned long long) * wcap);
         MP_HIP(hipMemsetAsync(tk.p, 0, sizeof(unsigned long long) * wcap, s));
         MP_HIP(hipMemsetAsync(tv.p, 0xFF, sizeof(unsigned long long) * wcap, s));
-        k_band_hash<<<nblk(emits), kBlock, 0, s>>>(gvox.as<int3>(), G, R, bg, tk.as<unsigned long long>(),
+        k_band_hash<<<nblk_capped(emits), kBlock, 0, s>>>(gvox.as<int3>(), G, R, bg, tk.as<unsigned long long>(),
                                                    tv.as<unsigned long long>(), wcap - 1);
         MP_CHECK_LAUNCH();
-        k_count_slots<<<nblk((int64_t)wcap), kBlock, 0, s>>>(tk.as<unsigned long long>(), (int64_t)wcap,
+        k_count_slots<<<nblk_capped((int64_t)wcap), kBlock, 0, s>>>(tk.as<unsigned long long>(), (int64_t)wcap,
                                                               d_count.as<unsigned long long>());
         MP_CHECK_LAUNCH();
         MP_HIP(hipMemcpyAsync(&band, d_count.p, 8, hipMemcpyDeviceToHost, s));
@@ -517,7 +738,7 @@ void mp_build_map(mp_map m, const float* xyz, int64_t n, hipStream_t s) {
         if (cap > (1ull << 32)) mp_throw(MP_E_UNSUPPORTED, "mp_map_build: hash table would exceed 2^32 slots");
         m->table.alloc(sizeof(uint2) * cap);
         MP_HIP(hipMemsetAsync(m->table.p, 0, sizeof(uint2) * cap, s));
-        k_rehash<<<nblk((int64_t)wcap), kBlock, 0, s>>>(tk.as<unsigned long long>(), tv.as<unsigned long long>(),
+        k_rehash<<<nblk_capped((int64_t)wcap), kBlock, 0, s>>>(tk.as<unsigned long long>(), tv.as<unsigned long long>(),
                                                          (int64_t)wcap, bg, m->table.as<uint2>(),
                                                          (uint32_t)(cap - 1));
         MP_CHECK_LAUNCH();

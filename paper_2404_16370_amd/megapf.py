@@ -33,7 +33,8 @@ class MegaPFError(RuntimeError):
 
 class mp_map_params(C.Structure):
     _fields_ = [("voxel", C.c_float), ("nnf_radius", C.c_int32), ("min_points", C.c_int32),
-                ("cov_eps", C.c_float), ("backend", C.c_int32)]
+                ("cov_eps", C.c_float), ("backend", C.c_int32), ("gauss_mode", C.c_int32), ("point_k", C.c_int32),
+                ("point_search", C.c_int32)]
 
 
 class mp_map_info(C.Structure):
@@ -109,6 +110,7 @@ EXPORTS = ["mp_map_default_params", "mp_map_build", "mp_map_get_info", "mp_map_g
 
 MP_SCORER_PLAIN, MP_SCORER_SCOREFIELD, MP_SCORER_SURROGATE = 0, 1, 2
 MP_LIK_LAYOUT_AUTO, MP_LIK_LAYOUT_PARTICLE, MP_LIK_LAYOUT_GROUPED = 0, 1, 2
+MP_GAUSS_VOXEL, MP_GAUSS_POINT = 0, 1
 MP_LSH_TANGENT_DECOUPLED, MP_LSH_TANGENT_SE3 = 0, 1
 MP_SVGD_GRAD_APPROX, MP_SVGD_GRAD_EXACT = 0, 1
 MP_SVGD_TRANSPORT_NONE, MP_SVGD_TRANSPORT_ADJOINT = 0, 1
@@ -231,9 +233,13 @@ def mp_map_default_params():
 class Map:
     """Owner of an mp_map handle (mp_map_build / mp_map_destroy)."""
 
-    def __init__(self, xyz, voxel=0.5, nnf_radius=2, min_points=5, cov_eps=1e-3, backend=MP_NNF_AUTO, stream=None):
+    def __init__(self, xyz, voxel=0.5, nnf_radius=2, min_points=5, cov_eps=1e-3, backend=MP_NNF_AUTO, stream=None,
+                 gauss_mode=None, point_k=10, point_search=2):
         p = mp_map_default_params()
         p.voxel, p.nnf_radius, p.min_points, p.cov_eps, p.backend = voxel, nnf_radius, min_points, cov_eps, backend
+        if gauss_mode is not None:
+            p.gauss_mode = gauss_mode
+        p.point_k, p.point_search = point_k, point_search
         keep = []
         h = C.c_void_p()
         n = _nrows(xyz)

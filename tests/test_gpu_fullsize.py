@@ -95,3 +95,112 @@ def test_campus_stages(campus, O):
     q = f.posterior_query(weights=True)
     wts = q["weights"]
     assert abs(wts.sum() - 1) < 1e-4 and q["map_weight"] >= wts.max() * (1 - 1e-6)
+
+
+def _voxel_index(P, r):
+    """FP32 voxels as the library forms them, keys in (vz, vy, vx) order and a
+    stable sort of the points by key"""
+    V = np.floor(P * (np.float32(1.0) / np.float32(r))).astype(np.int64)
+    lo = V.min(0)
+    dim = V.max(0) - lo + 1
+    key = ((V[:, 2] - lo[2]) * dim[1] + (V[:, 1] - lo[1])) * dim[0] + (V[:, 0] - lo[0])
+    order = np.argsort(key, kind="stable")
+    return V, lo, dim, key, order, key[order]
+
+
+def _block(v, s, lo, dim, order, skeys):
+    """indices of the points whose voxel is within Chebyshev s of voxel v"""
+    out = []
+    for dz in range(-s, s + 1):
+        z = v[2] + dz - lo[2]
+        if z < 0 or z >= dim[2]:
+            continue
+        for dy in range(-s, s + 1):
+            y = v[1] + dy - lo[1]
+            if y < 0 or y >= dim[1]:
+                continue
+            x0, x1 = max(v[0] - s - lo[0], 0), min(v[0] + s - lo[0], dim[0] - 1)
+            if x0 > x1:
+                continue
+            base = (z * dim[1] + y) * dim[0]
+            a, b = np.searchsorted(skeys, [base + x0, base + x1 + 1])
+            out.append(order[a:b])
+    return np.concatenate(out) if out else np.zeros(0, np.int64)
+
+
+def test_campus_point_map_sampled(campus):
+    """The map of per-point Gaussians bench.py times (0.2 m cells, R = 5, 10
+    neighbours within 2 voxels) on all 20M points: sampled Gaussians against
+    FP64 neighbourhoods and eigenvectors, sampled field cells against the
+    FP64 nearest kept point to the cell's centre within R r (cases with a
+    near-tie skipped)"""
+    r, R, S_, k, minp = 0.2, 5, 2, 10, 5
+    P = np.ascontiguousarray(campus["w"]["map_xyz"], np.float32)
+    n = len(P)
+    m = M.Map(P, voxel=r, nnf_radius=R, min_points=minp, gauss_mode=M.MP_GAUSS_POINT, point_k=k, point_search=S_)
+    info = m.info()
+    print("per-point campus map", info, flush=True)
+    V, lo, dim, key, order, skeys = _voxel_index(P, r)
+    # kept points: the point and its block of (2S+1)^3 voxels hold >= min_points
+    # points (a summed-area table of the voxel counts)
+    cnt = np.bincount(key, minlength=int(np.prod(dim))).reshape(dim[2], dim[1], dim[0])
+    sat = np.zeros((dim[2] + 1, dim[1] + 1, dim[0] + 1), np.int64)
+    sat[1:, 1:, 1:] = cnt.cumsum(0).cumsum(1).cumsum(2)
+    del cnt
+    a = np.clip(V - lo - S_, 0, dim - 1)          # lower corner (x, y, z), inclusive
+    b = np.clip(V - lo + S_, 0, dim - 1) + 1      # upper corner, exclusive
+    blk = np.zeros(n, np.int64)
+    for sz in (0, 1):
+        for sy in (0, 1):
+            for sx in (0, 1):
+                z = np.where(sz, b[:, 2], a[:, 2]); y = np.where(sy, b[:, 1], a[:, 1]); x = np.where(sx, b[:, 0], a[:, 0])
+                blk += (-1) ** (3 - sz - sy - sx) * sat[z, y, x]
+    del sat
+    kept = blk >= minp
+    assert info["num_gauss"] == int(kept.sum())
+    gid_of = np.full(n, -1, np.int64)
+    ko = order[kept[order]]
+    gid_of[ko] = np.arange(len(ko))
+    g = m.gauss()
+    rng = np.random.default_rng(11)
+    P64 = P.astype(np.float64)
+    checked = 0
+    for i in rng.choice(np.nonzero(kept)[0], 300, replace=False):
+        gi = gid_of[i]
+        assert np.array_equal(g["mu"][gi], P[i])
+        c = _block(V[i], S_, lo, dim, order, skeys)
+        c = c[c != i]
+        d = np.sum((P64[c] - P64[i]) ** 2, axis=1)
+        srt = np.lexsort((c, d))
+        kk = min(k, len(c))
+        assert g["count"][gi] == kk + 1
+        ds = d[srt]
+        if len(ds) > kk and ds[kk] - ds[kk - 1] <= 1e-9 * (1 + ds[kk]):
+            continue
+        X = np.concatenate([P64[i:i + 1], P64[c[srt[:kk]]]])
+        w, U = np.linalg.eigh(np.cov(X.T, bias=True))
+        if w[1] - w[0] > 1e-4 * max(w[2], 1e-12):
+            assert abs(abs(float(g["normal"][gi].astype(np.float64) @ U[:, 0])) - 1) < 1e-5, i
+            checked += 1
+    assert checked > 200
+    # field cells around the map
+    q = (P[rng.choice(n, 400)] + rng.uniform(-1.2, 1.2, size=(400, 3))).astype(np.float32)
+    got = m.lookup(q)
+    cells = np.floor(q * (np.float32(1.0) / np.float32(r))).astype(np.int64)
+    lim = np.float64(np.float32(R) * np.float32(r))
+    agree = 0
+    for t in range(len(q)):
+        cen = (cells[t].astype(np.float32) + np.float32(0.5)) * np.float32(r)
+        c = _block(cells[t], R, lo, dim, order, skeys)
+        c = c[kept[c]]
+        d = np.sqrt(np.sum((P64[c] - cen.astype(np.float64)) ** 2, axis=1)) if len(c) else np.zeros(0)
+        if len(c) == 0 or d.min() > lim + 1e-6:
+            assert got[t] == -1
+            agree += 1
+            continue
+        j = np.lexsort((gid_of[c], d))
+        if abs(d[j[0]] - lim) < 1e-6 or (len(j) > 1 and d[j[1]] - d[j[0]] < 1e-6):
+            continue
+        assert got[t] == gid_of[c[j[0]]], t
+        agree += 1
+    assert agree > 380
