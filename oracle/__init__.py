@@ -104,6 +104,7 @@ def _declare(L):
     L.mpo_svgd.argtypes = [_f32p, C.c_int64, _f64p, _i32p, C.c_int32, C.c_float, C.c_float, C.c_int32, C.c_int32,
                            _vp, _f64p]
     L.mpo_se3_jr_inv.argtypes = [_f64p, _f64p]; L.mpo_se3_jr_inv.restype = C.c_int32
+    L.mpo_init_gauss.argtypes = [C.c_uint64, C.c_int64, _f32p, _f32p, _f64p]
     L.mpo_posterior.argtypes = [_f64p, _f64p, C.c_int64, _i32p, _f64p, C.c_int32, C.c_int32, C.c_double,
                                 C.c_double, _vp, _f64p, C.POINTER(C.c_double)]
     L.mpo_posterior.restype = C.c_int64
@@ -379,6 +380,13 @@ def posterior(prior, loglik, nbr, kval, rounds=10, tau=1.0, prior_floor=1e-30):
     best = lib().mpo_posterior(np.ascontiguousarray(prior, np.float64), np.ascontiguousarray(loglik, np.float64),
                                n, nb, kv, nb.shape[1], rounds, tau, prior_floor, _ptr(p0), post, C.byref(neff))
     return dict(p0=p0, post=post, map_index=int(best), n_eff=float(neff.value))
+
+
+def init_gauss(seed, n, mean7, cov36):
+    """Gaussian initial particles M exp(L z_i), n x 7 FP64"""
+    out = np.zeros((n, 7))
+    lib().mpo_init_gauss(seed, n, _f32(mean7), _f32(np.asarray(cov36).reshape(36)), out)
+    return out
 
 
 def chol6(A):

@@ -57,7 +57,7 @@ MPO_API void mpo_philox(const uint32_t ctr_in[4], const uint32_t key_in[2], uint
     out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
 }
 
-enum { MPO_PURPOSE_PRED = 1, MPO_PURPOSE_LSH = 2, MPO_PURPOSE_TLSH = 3, MPO_PURPOSE_INIT = 4 };
+enum { MPO_PURPOSE_PRED = 1, MPO_PURPOSE_LSH = 2, MPO_PURPOSE_TLSH = 3, MPO_PURPOSE_INIT = 4, MPO_PURPOSE_INITG = 7 };
 
 static void rng_block(uint64_t seed, uint32_t a, uint32_t b, uint32_t c, uint32_t purpose, uint32_t blk,
                       uint32_t out[4]) {
@@ -1466,8 +1466,37 @@ MPO_API int mpo_chol6(const double A[36], double L[36]) {
     return 0;
 }
 
+/* T_i dT exp(L z_i), z_i ~ N(0, I6) drawn for (i, frame) under `purpose` */
+static void predict_purpose(const float* poses, int64_t n, const float dT[7], const float cov[36], uint64_t seed,
+                            uint32_t frame, uint32_t purpose, double* poses_out);
+
 MPO_API void mpo_predict(const float* poses, int64_t n, const float dT[7], const float cov[36] /* nullable */,
                          uint64_t seed, uint32_t frame, double* poses_out /* n*7 */) {
+    predict_purpose(poses, n, dT, cov, seed, frame, MPO_PURPOSE_PRED, poses_out);
+}
+
+/* Gaussian initial particles around a pose (tracking start): T_i = M exp(L z_i)
+ * with L L^T = cov, the draw of Eq. (1)'s prediction noise taken about M
+ * (purpose 7, frame 0).  Pinned by the sample covariance of log(M^-1 T_i) and
+ * by a zero covariance. */
+MPO_API void mpo_init_gauss(uint64_t seed, int64_t n, const float mean[7], const float cov[36],
+                            double* poses_out /* n*7 */) {
+    float* P = (float*)malloc(sizeof(float) * 8 * (size_t)(n > 0 ? n : 1));
+    double nq = 0.0;
+    for (int k = 0; k < 4; ++k) nq += (double)mean[k] * (double)mean[k];
+    nq = sqrt(nq);
+    for (int64_t i = 0; i < n; ++i) {
+        for (int k = 0; k < 4; ++k) P[8 * i + k] = (float)((double)mean[k] / nq);
+        for (int k = 4; k < 7; ++k) P[8 * i + k] = mean[k];
+        P[8 * i + 7] = 0.0f;
+    }
+    const float ident[7] = {1, 0, 0, 0, 0, 0, 0};
+    predict_purpose(P, n, ident, cov, seed, 0u, MPO_PURPOSE_INITG, poses_out);
+    free(P);
+}
+
+static void predict_purpose(const float* poses, int64_t n, const float dT[7], const float cov[36], uint64_t seed,
+                            uint32_t frame, uint32_t purpose, double* poses_out) {
     double L[36];
     int noise = 0;
     if (cov) {
@@ -1484,7 +1513,7 @@ MPO_API void mpo_predict(const float* poses, int64_t n, const float dT[7], const
         se3_compose(T, D, TD);
         if (noise) {
             float z[6];
-            mpo_gauss6(seed, (uint32_t)i, frame, 0u, MPO_PURPOSE_PRED, z);
+            mpo_gauss6(seed, (uint32_t)i, frame, 0u, purpose, z);
             double dl[6];
             for (int r = 0; r < 6; ++r) {
                 double s = 0.0;

@@ -20,6 +20,8 @@
   posterior    sums to 1; uniform fixed point; K = 1 identity; two-node closed
                form of one round; shift invariance; long-double softmax
   prediction   zero covariance gives T dT; sample covariance of the noise
+  Gaussian init  zero covariance gives the (normalised) mean; sample mean and
+               covariance of log(M^-1 T_i); draws distinct from the prediction's
 """
 import math
 
@@ -281,6 +283,28 @@ def test_predict_no_noise_and_noise_covariance(O):
     deltas = np.stack([se3_log_ref(np.linalg.inv(TD) @ pose_to_M(out[i])) for i in range(0, n, 4)])
     C = np.cov(deltas.T)
     assert np.allclose(C, cov, atol=0.1 * np.abs(cov).max())
+
+
+def test_init_gauss_covariance_and_zero(O):
+    rng = np.random.default_rng(15)
+    mean = random_pose8(rng)[:7].copy()
+    mean[:4] *= 1.7                        # not unit: normalised on input
+    Z = O.init_gauss(3, 10, mean, np.zeros(36, np.float32))
+    M0 = pose_to_M(np.r_[mean[:4] / np.linalg.norm(mean[:4].astype(np.float64)), mean[4:]])
+    for i in range(10):
+        assert np.allclose(pose_to_M(Z[i]), M0, atol=1e-6)
+    A = rng.normal(size=(6, 6)) * 0.08
+    cov = (A @ A.T).astype(np.float32)
+    n = 20000
+    out = O.init_gauss(5, n, mean, cov)
+    Minv = np.linalg.inv(M0)
+    deltas = np.stack([se3_log_ref(Minv @ pose_to_M(out[i])) for i in range(0, n, 4)])
+    assert np.abs(deltas.mean(0)).max() < 0.05 * np.sqrt(np.diag(cov)).max()
+    assert np.allclose(np.cov(deltas.T), cov, atol=0.1 * np.abs(cov).max())
+    # its draws are not the prediction's (another purpose of the generator)
+    mean8 = np.r_[mean[:4] / np.linalg.norm(mean[:4]), mean[4:], 0].astype(np.float32)
+    pred = O.predict(np.tile(mean8, (4, 1)), np.array([1, 0, 0, 0, 0, 0, 0], np.float32), cov, 5, 0)
+    assert not np.allclose(pred[:4], out[:4])
 
 
 def _vee(M):
