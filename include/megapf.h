@@ -175,6 +175,10 @@ typedef struct {
                              delta^LSH and refreshes the neighbour lists once */
     int32_t svgd_grad;    /* MP_SVGD_GRAD_*: kernel gradient in the update of Eq. (5)-(6) */
     int32_t svgd_transport; /* MP_SVGD_TRANSPORT_*: tangent frame of neighbour j's term */
+    int32_t final_rescore;  /* 1: after the last SVGD update, evaluate the likelihood and the kernel
+                               values of the lists again at the final poses, so that the posterior
+                               (Sec. III-D) scores the poses it reports; 0: it scores the last
+                               iteration's (pre-update) likelihoods, as the paper's step order does */
     uint64_t seed;        /* Philox4x32-10 key */
 } mp_filter_params;
 
@@ -226,23 +230,28 @@ enum { MP_LIK_LAYOUT_AUTO = 0, MP_LIK_LAYOUT_PARTICLE = 1, MP_LIK_LAYOUT_GROUPED
  * d_max 1.0, lambda_rel 1e-3, lambda_abs 1e-6, temperature 1,
  * prior_floor 1e-30, cov_eps 1e-3, lik_chunks 0, lik_batch 0, lik_layout AUTO,
  * scorer PLAIN, sigma_s 0.03, lsh_tangent DECOUPLED, lsh_tables 1, svgd_grad
- * APPROX, svgd_transport NONE, seed 1. */
+ * APPROX, svgd_transport NONE, final_rescore 0, seed 1. */
 MP_API void mp_filter_default_params(mp_filter_params* p);
 
-enum { MP_INIT_UNIFORM_BOX = 0, MP_INIT_EXPLICIT = 1 };
+enum { MP_INIT_UNIFORM_BOX = 0, MP_INIT_EXPLICIT = 1, MP_INIT_GAUSSIAN = 2 };
 
 typedef struct {
     int32_t kind;        /* MP_INIT_* */
     float box_min[3];    /* UNIFORM_BOX: translation box; rotation uniform on SO(3) */
     float box_max[3];
     const float* poses;  /* EXPLICIT: n_particles x 7 (host or device) */
+    float mean[7];       /* GAUSSIAN: pose M the particles spread about */
+    float cov[36];       /* GAUSSIAN: 6 x 6 covariance (row-major, tangent [omega; v]) */
 } mp_init_desc;
 
 /* Create a filter on `map`: N particles, prior 1/N, neighbour lists {i},
  * frame 0 (Sec. III-A).  Uniform poses come from Philox(seed) with Shoemake's
  * uniform rotations, so they are reproducible.  Explicit quaternions are
- * normalised on input.  Errors: MP_E_ARG (params out of range, non-finite or
- * zero quaternions), MP_E_OOM. */
+ * normalised on input.  Gaussian poses are M exp(L z_i) with L L^T = cov and
+ * z_i ~ N(0, I6) from Philox(seed; i), drawn like the prediction noise of
+ * Eq. (1) (a tracking start about a known pose).  Errors: MP_E_ARG (params
+ * out of range, non-finite or zero quaternions, a covariance that is not
+ * symmetric positive semi-definite), MP_E_OOM. */
 MP_API mp_status mp_filter_init(mp_map map, const mp_filter_params* params, const mp_init_desc* init, void* stream,
                          mp_filter* out);
 
@@ -338,7 +347,10 @@ MP_API mp_status mp_stage_times(mp_filter f, float* ms_out, int32_t* counts_out)
  *   "capture_hb"  int32 (set only)
  * bytes must equal the named buffer's size.  mp_debug_stage runs one stage
  * on the current state (iteration selects the LSH frame counter; dT/cov_dT as
- * in mp_filter_step, used by MP_STAGE_PREDICT only). */
+ * in mp_filter_step, used by MP_STAGE_PREDICT only); MP_DEBUG_RESCORE runs
+ * the final re-score of a step with final_rescore (a likelihood pass and a
+ * refresh that only re-ranks the current lists). */
+enum { MP_DEBUG_RESCORE = 100 };
 MP_API mp_status mp_debug_get(mp_filter f, const char* name, void* dst, int64_t bytes, void* stream);
 MP_API mp_status mp_debug_set(mp_filter f, const char* name, const void* src, int64_t bytes, void* stream);
 MP_API mp_status mp_debug_stage(mp_filter f, int32_t stage, int32_t iteration, const float dT[7], const float cov_dT[36],

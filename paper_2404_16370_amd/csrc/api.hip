@@ -258,6 +258,7 @@ extern "C" void mp_filter_default_params(mp_filter_params* p) {
     p->lsh_tables = 1;
     p->svgd_grad = MP_SVGD_GRAD_APPROX;
     p->svgd_transport = MP_SVGD_TRANSPORT_NONE;
+    p->final_rescore = 0;
     p->seed = 1;
 }
 
@@ -288,6 +289,7 @@ static void validate_params(const mp_filter_params& p) {
     if (p.svgd_grad != MP_SVGD_GRAD_APPROX && p.svgd_grad != MP_SVGD_GRAD_EXACT) mp_throw(MP_E_ARG, "unknown svgd_grad");
     if (p.svgd_transport != MP_SVGD_TRANSPORT_NONE && p.svgd_transport != MP_SVGD_TRANSPORT_ADJOINT)
         mp_throw(MP_E_ARG, "unknown svgd_transport");
+    if (p.final_rescore != 0 && p.final_rescore != 1) mp_throw(MP_E_ARG, "final_rescore must be 0 or 1");
 }
 
 static void destroy_filter(mp_filter f) {
@@ -309,6 +311,8 @@ extern "C" mp_status mp_filter_init(mp_map map, const mp_filter_params* params, 
         const int n = params->n_particles;
         hipStream_t s = as_stream(stream);
         std::vector<float> host_poses;
+        float gmean[7], gL[36];
+        bool gnoise = false;
         if (init->kind == MP_INIT_EXPLICIT) {
             if (!init->poses) mp_throw(MP_E_ARG, "explicit init without poses");
             std::vector<float> p7((size_t)n * 7);
@@ -328,6 +332,12 @@ extern "C" mp_status mp_filter_init(mp_map map, const mp_filter_params* params, 
             if (!all_finite(init->box_min, 3) || !all_finite(init->box_max, 3)) mp_throw(MP_E_ARG, "non-finite box");
             for (int a = 0; a < 3; ++a)
                 if (init->box_max[a] < init->box_min[a]) mp_throw(MP_E_ARG, "box_max < box_min");
+        } else if (init->kind == MP_INIT_GAUSSIAN) {
+            // the mean replicated, then moved by exp(L z_i) as a prediction from it would be
+            mp_prepare_prediction(init->mean, init->cov, gmean, gL, gnoise);
+            host_poses.assign((size_t)n * 8, 0.0f);
+            for (int i = 0; i < n; ++i)
+                for (int k = 0; k < 7; ++k) host_poses[8 * (size_t)i + k] = gmean[k];
         } else {
             mp_throw(MP_E_ARG, "unknown init kind %d", init->kind);
         }
@@ -370,8 +380,12 @@ extern "C" mp_status mp_filter_init(mp_map map, const mp_filter_params* params, 
             MP_HIP(hipMemsetAsync(f->psi.p, 0, 32 * N, s));
             MP_HIP(hipMemsetAsync(f->tlsh.p, 0, 32, s));
             MP_HIP(hipMemsetAsync(f->post1.p, 0, 4 * N, s));
-            if (init->kind == MP_INIT_EXPLICIT) {
+            if (init->kind == MP_INIT_EXPLICIT || init->kind == MP_INIT_GAUSSIAN) {
                 MP_HIP(hipMemcpyAsync(f->poses[0].p, host_poses.data(), 32 * N, hipMemcpyHostToDevice, s));
+                if (init->kind == MP_INIT_GAUSSIAN) {
+                    static const float ident[7] = {1, 0, 0, 0, 0, 0, 0};
+                    mp_launch_predict(f, ident, gL, gnoise, s, true);
+                }
                 MP_HIP(hipStreamSynchronize(s));
             } else {
                 mp_launch_init_uniform(f, init->box_min, init->box_max, s);
@@ -516,6 +530,17 @@ static void run_stage(mp_filter f, int st, int it, hipStream_t s) {
     }
 }
 
+// the likelihood and the lists' kernel values at the current (final) poses:
+// one likelihood pass and a refresh that only re-ranks the current lists
+static void rescore(mp_filter f, hipStream_t s) {
+    mp_tick(f, MP_STAGE_LIK, true, s);
+    run_stage(f, MP_STAGE_LIK, f->p.svgd_iters, s);
+    mp_tick(f, MP_STAGE_LIK, false, s);
+    mp_tick(f, MP_STAGE_REFRESH, true, s);
+    mp_launch_refresh(f, s, 0);
+    mp_tick(f, MP_STAGE_REFRESH, false, s);
+}
+
 void mp_reserve_step(mp_filter f) {
     f->partial.ensure(mp_lik_partial_bytes(f));
     f->red.ensure(std::max(mp_post_scratch_bytes(f), sizeof(uint32_t) * ((size_t)f->n + 64)));
@@ -552,6 +577,7 @@ void mp_step_launches(mp_filter f, bool pred, const float dq[7], const float L[3
                 mp_tick(f, st, false, s);
             }
         }
+        if (f->p.svgd_iters > 0 && f->p.final_rescore) rescore(f, s);
         if (f->p.svgd_iters > 0) {
             mp_tick(f, MP_STAGE_POSTERIOR, true, s);
             mp_launch_posterior(f, s);
@@ -739,6 +765,10 @@ extern "C" mp_status mp_debug_stage(mp_filter f, int32_t stage, int32_t iteratio
             bool noise = false;
             mp_prepare_prediction(dT, cov_dT, dq, L, noise);
             mp_launch_predict(f, dq, L, noise, s);
+        } else if (stage == MP_DEBUG_RESCORE) {
+            if (f->scan_n < 0) mp_throw(MP_E_STATE, "no scan uploaded");
+            MP_HIP(hipMemsetAsync(f->flags.p, 0, 16, s));
+            rescore(f, s);
         } else {
             if ((stage == MP_STAGE_LIK) && f->scan_n < 0) mp_throw(MP_E_STATE, "no scan uploaded");
             if (stage == MP_STAGE_LIK) MP_HIP(hipMemsetAsync(f->flags.p, 0, 16, s));

@@ -307,7 +307,8 @@ void info_impl(void* p) {
     int64_t ev = 0;
     for (size_t i = 0; i < c.b->f.size(); ++i) {
         mp_filter f = c.b->f[i];
-        ev += (int64_t)f->n * std::max(0, f->scan_n) * f->p.svgd_iters;
+        const int passes = f->p.svgd_iters + (f->p.svgd_iters > 0 && f->p.final_rescore ? 1 : 0);
+        ev += (int64_t)f->n * std::max(0, f->scan_n) * passes;
         if (c.lb) c.lb[i] = f->p.lik_batch;
         if (c.ll) c.ll[i] = f->p.lik_layout;
     }

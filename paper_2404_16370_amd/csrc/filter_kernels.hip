@@ -218,6 +218,7 @@ struct PredArgs {
     float dq[4], dt[3];
     float L[21];  // lower-triangular Cholesky factor of the noise covariance, row-major packed
     int32_t noise;
+    uint32_t purpose;                 // generator purpose of z (prediction, or Gaussian initialisation)
     const StepDyn* __restrict__ dyn;  // captured step: frame, increment and noise from here
 };
 
@@ -238,7 +239,7 @@ __global__ __launch_bounds__(256) void k_predict(PredArgs A) {
     compose(q, t, mpdet::quat{A.dq[0], A.dq[1], A.dq[2], A.dq[3]}, make_float3(A.dt[0], A.dt[1], A.dt[2]));
     if (A.noise) {
         float z[6];
-        mpdet::gauss6(A.seed, (uint32_t)i, A.frame, 0u, mpdet::PURPOSE_PRED, z);
+        mpdet::gauss6(A.seed, (uint32_t)i, A.frame, 0u, A.purpose, z);
         float d[6];
         int p = 0;
         for (int r = 0; r < 6; ++r) {
@@ -495,8 +496,10 @@ void mp_launch_svgd(mp_filter f, hipStream_t s) {
     f->cur = 1 - f->cur;
 }
 
-void mp_launch_predict(mp_filter f, const float dT[7], const float L[36], bool noise, hipStream_t s) {
+void mp_launch_predict(mp_filter f, const float dT[7], const float L[36], bool noise, hipStream_t s,
+                       bool gauss_init) {
     PredArgs A;
+    A.purpose = gauss_init ? mpdet::PURPOSE_INIT_GAUSS : mpdet::PURPOSE_PRED;
     A.poses = f->poses[f->cur].as<float4>();
     A.n = f->n;
     A.frame = (uint32_t)f->frame;

@@ -37,7 +37,8 @@ __host__ __device__ inline u32x4 philox(uint32_t c0, uint32_t c1, uint32_t c2, u
     return r;
 }
 
-enum : uint32_t { PURPOSE_PRED = 1, PURPOSE_LSH = 2, PURPOSE_TLSH = 3, PURPOSE_INIT = 4, PURPOSE_WINIT = 5, PURPOSE_BATCH = 6 };
+enum : uint32_t { PURPOSE_PRED = 1, PURPOSE_LSH = 2, PURPOSE_TLSH = 3, PURPOSE_INIT = 4, PURPOSE_WINIT = 5, PURPOSE_BATCH = 6,
+                  PURPOSE_INIT_GAUSS = 7 };
 
 // counter = (a, b, c, purpose << 16 | block), key = seed
 __device__ inline u32x4 rng(uint64_t seed, uint32_t a, uint32_t b, uint32_t c, uint32_t purpose, uint32_t block) {

@@ -210,10 +210,14 @@ void mp_scan_walk_order(const float* xyz_dev, int32_t n, float cell, const float
 
 // filter stages
 void mp_launch_init_uniform(mp_filter f, const float lo[3], const float hi[3], hipStream_t s);
-void mp_launch_predict(mp_filter f, const float dT[7], const float L[36], bool noise, hipStream_t s);
+// prediction T dT exp(L z); `gauss_init` draws z under the Gaussian-initialisation
+// purpose instead of the prediction's (frame 0, at filter creation)
+void mp_launch_predict(mp_filter f, const float dT[7], const float L[36], bool noise, hipStream_t s,
+                       bool gauss_init = false);
 void mp_launch_lsh(mp_filter f, uint32_t frame, uint32_t it, hipStream_t s);
 void mp_launch_sort(mp_filter f, hipStream_t s);
-void mp_launch_refresh(mp_filter f, hipStream_t s);
+// window < 0: the filter's window_c; 0 re-ranks the current lists at the current poses
+void mp_launch_refresh(mp_filter f, hipStream_t s, int window = -1);
 void mp_launch_likelihood(mp_filter f, hipStream_t s);
 void mp_launch_svgd(mp_filter f, hipStream_t s);
 void mp_launch_posterior(mp_filter f, hipStream_t s);

@@ -279,7 +279,7 @@ void mp_launch_sort(mp_filter f, hipStream_t s) {
     MP_CHECK_LAUNCH();
 }
 
-void mp_launch_refresh(mp_filter f, hipStream_t s) {
+void mp_launch_refresh(mp_filter f, hipStream_t s, int window) {
     RefreshArgs A;
     A.poses = f->poses[f->cur].as<float4>();
     A.sorted = f->sorted.as<int32_t>();
@@ -290,7 +290,7 @@ void mp_launch_refresh(mp_filter f, hipStream_t s) {
     A.cnt = f->cnt.as<int32_t>();
     A.n = f->n;
     A.K = f->K;
-    A.C = f->p.window_c;
+    A.C = window < 0 ? f->p.window_c : window;
     A.sr = f->p.sigma_r;
     A.st = f->p.sigma_t;
     if (f->K <= 8) k_refresh<8><<<nblk(f->n), 256, 0, s>>>(A);

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libmegapf.so")
 
 MP_OK, MP_E_ARG, MP_E_STATE, MP_E_OOM, MP_E_HIP, MP_E_UNSUPPORTED, MP_E_NUMERIC = 0, -1, -2, -3, -4, -5, -6
 MP_NNF_AUTO, MP_NNF_HASH, MP_NNF_DENSE = 0, 1, 2
-MP_INIT_UNIFORM_BOX, MP_INIT_EXPLICIT = 0, 1
+MP_INIT_UNIFORM_BOX, MP_INIT_EXPLICIT, MP_INIT_GAUSSIAN = 0, 1, 2
 (MP_STAGE_PREDICT, MP_STAGE_LSH, MP_STAGE_SORT, MP_STAGE_REFRESH, MP_STAGE_LIK, MP_STAGE_SVGD,
  MP_STAGE_POSTERIOR, MP_STAGE_SCAN, MP_STAGE_LIK_CORE) = range(9)
 MP_NUM_STAGES = 9
@@ -52,7 +52,7 @@ class mp_filter_params(C.Structure):
                 ("prior_floor", C.c_float), ("cov_eps", C.c_float), ("lik_chunks", C.c_int32),
                 ("lik_batch", C.c_int32), ("lik_layout", C.c_int32), ("scorer", C.c_int32), ("sigma_s", C.c_float),
                 ("lsh_tangent", C.c_int32), ("lsh_tables", C.c_int32), ("svgd_grad", C.c_int32),
-                ("svgd_transport", C.c_int32), ("seed", C.c_uint64)]
+                ("svgd_transport", C.c_int32), ("final_rescore", C.c_int32), ("seed", C.c_uint64)]
 
 
 class mp_odometry_params(C.Structure):
@@ -88,7 +88,7 @@ class mp_surrogate_info(C.Structure):
 
 class mp_init_desc(C.Structure):
     _fields_ = [("kind", C.c_int32), ("box_min", C.c_float * 3), ("box_max", C.c_float * 3),
-                ("poses", C.c_void_p)]
+                ("poses", C.c_void_p), ("mean", C.c_float * 7), ("cov", C.c_float * 36)]
 
 
 class mp_posterior(C.Structure):
@@ -111,6 +111,7 @@ EXPORTS = ["mp_map_default_params", "mp_map_build", "mp_map_get_info", "mp_map_g
 MP_SCORER_PLAIN, MP_SCORER_SCOREFIELD, MP_SCORER_SURROGATE = 0, 1, 2
 MP_LIK_LAYOUT_AUTO, MP_LIK_LAYOUT_PARTICLE, MP_LIK_LAYOUT_GROUPED = 0, 1, 2
 MP_GAUSS_VOXEL, MP_GAUSS_POINT = 0, 1
+MP_DEBUG_RESCORE = 100
 MP_LSH_TANGENT_DECOUPLED, MP_LSH_TANGENT_SE3 = 0, 1
 MP_SVGD_GRAD_APPROX, MP_SVGD_GRAD_EXACT = 0, 1
 MP_SVGD_TRANSPORT_NONE, MP_SVGD_TRANSPORT_ADJOINT = 0, 1
@@ -320,12 +321,23 @@ _DEBUG_LAYOUT = {  # name -> (dtype, shape as a function of (n, K, scan_n))
 class Filter:
     """Owner of an mp_filter handle."""
 
-    def __init__(self, map_: Map, params=None, poses=None, box=None, stream=None, **kw):
+    def __init__(self, map_: Map, params=None, poses=None, box=None, stream=None, gaussian=None, **kw):
+        """poses: explicit N x 7; gaussian: (mean pose 7, covariance 6 x 6); else uniform over `box`
+        (default: the map's box)"""
         self.map = map_
         self.params = params if params is not None else mp_filter_default_params(**kw)
         init = mp_init_desc()
         keep = []
-        if poses is not None:
+        if gaussian is not None:
+            init.kind = MP_INIT_GAUSSIAN
+            mean, cov = gaussian
+            mean = np.asarray(mean, np.float32).reshape(7)
+            cov = np.asarray(cov, np.float32).reshape(36)
+            for a in range(7):
+                init.mean[a] = mean[a]
+            for a in range(36):
+                init.cov[a] = cov[a]
+        elif poses is not None:
             init.kind = MP_INIT_EXPLICIT
             p = poses
             if not hasattr(p, "data_ptr"):

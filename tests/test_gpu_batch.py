@@ -9,8 +9,9 @@ weights must agree bit for bit, for steps without prediction, with prediction
 and noise (step values uploaded to the device before each replay), with an
 odd SVGD iteration count (pose buffer copied back), with the residual-field
 scorer, with the network scorer (its likelihood kernel captured in the
-graph), on a hashed map, and after a scan of another size forces a new
-capture.
+graph), on a hashed map, on a map of per-point Gaussians, with the coupled
+LSH tangent, two hash tables, the exact kernel gradient, adjoint transport and
+the final re-score, and after a scan of another size forces a new capture.
 """
 import numpy as np
 import pytest
@@ -27,7 +28,8 @@ def world():
     dense = M.Map(w["map_xyz"], voxel=0.5)
     hashed = M.Map(w["map_xyz"], voxel=0.5, backend=M.MP_NNF_HASH)
     sur = M.Surrogate(dense, M.mp_surrogate_default_params(seed=11))
-    return dict(w=w, dense=dense, hashed=hashed, sur=sur)
+    point = M.Map(w["map_xyz"], voxel=0.2, nnf_radius=3, gauss_mode=M.MP_GAUSS_POINT)
+    return dict(w=w, dense=dense, hashed=hashed, sur=sur, point=point)
 
 
 def _poses(w, n, seed):
@@ -38,19 +40,28 @@ def _poses(w, n, seed):
     return np.concatenate([P, G]).astype(np.float32)
 
 
+VARIANTS = dict(lsh_tangent=M.MP_LSH_TANGENT_SE3, lsh_tables=2, svgd_grad=M.MP_SVGD_GRAD_EXACT,
+                svgd_transport=M.MP_SVGD_TRANSPORT_ADJOINT, final_rescore=1)
+
 SPECS = [
-    # (map, n, svgd_iters, k, scorer, scan slice)
+    # (map, n, svgd_iters, k, scorer, scan slice[, further filter parameters])
     ("dense", 1000, 3, 8, M.MP_SCORER_PLAIN, slice(0, 1000)),
     ("dense", 4096, 2, 16, M.MP_SCORER_PLAIN, slice(0, 700)),
     ("hashed", 300, 1, 8, M.MP_SCORER_SCOREFIELD, slice(100, 900)),
     ("dense", 500, 2, 8, M.MP_SCORER_SURROGATE, slice(0, 300)),
+    ("dense", 800, 3, 8, M.MP_SCORER_PLAIN, slice(0, 900), VARIANTS),
+    ("point", 600, 2, 8, M.MP_SCORER_PLAIN, slice(0, 800), dict(d_max=0.6)),
 ]
 
 
 def _make(world, spec, seed, **kw):
-    mp, n, iters, k, scorer, sl = spec
+    mp, n, iters, k, scorer, sl = spec[:6]
+    extra = dict(d_max=1.0)
+    if len(spec) > 6:
+        extra.update(spec[6])
+    extra.update(kw)
     p = M.mp_filter_default_params(n_particles=n, k=k, lsh_bits=12, svgd_iters=iters, post_iters=10, window_c=16,
-                                   d_max=1.0, seed=seed, scorer=scorer, **kw)
+                                   seed=seed, scorer=scorer, **extra)
     f = M.Filter(world[mp], p, poses=_poses(world["w"], n, seed))
     if scorer == M.MP_SCORER_SURROGATE:
         f.set_surrogate(world["sur"])

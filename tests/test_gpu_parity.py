@@ -268,13 +268,14 @@ def test_lsh_coupled_tangent_bitexact(room, O):
         assert np.array_equal(f.debug_get("head"), h)
 
 
-@pytest.mark.parametrize("K,bits", [(8, 6), (16, 4), (5, 0)])
-def test_refresh_bitexact(room, O, K, bits):
+@pytest.mark.parametrize("K,bits,win", [(8, 6, 16), (16, 4, 32), (5, 0, 10), (8, 6, 0)])
+def test_refresh_bitexact(room, O, K, bits, win):
+    # win 0: the lists re-ranked at the current poses (the final re-score)
     n = 1500
     w = room["w"]
-    rng = np.random.default_rng(K)
+    rng = np.random.default_rng(K + win)
     poses = _poses_mixed(w, n, 31 + K)
-    p = _params(n, k=K, lsh_bits=bits, window_c=2 * K)
+    p = _params(n, k=K, lsh_bits=bits, window_c=win)
     f = M.Filter(room["gpu"], p, poses=poses)
     old = np.full((K, n), -1, np.int32)
     old[0] = np.arange(n)
@@ -284,9 +285,11 @@ def test_refresh_bitexact(room, O, K, bits):
     f.debug_stage(M.MP_STAGE_LSH, 0)
     f.debug_stage(M.MP_STAGE_SORT)
     f.debug_stage(M.MP_STAGE_REFRESH)
-    codes = f.debug_get("codes")
+    info = room["gpu"].info()
+    lo = np.array(info["box_min"], np.float32); hi = np.array(info["box_max"], np.float32)
+    codes = O.lsh_codes(poses, O.lsh_frame(4001, 0, 0, lo, hi), 1.0, 5.0, 2.5, 0.3, bits, 4001, 0, 0)
     s, _, _ = O.bucket_sort(codes)
-    nbr_ref, q_ref, cnt_ref = O.refresh(poses, s, codes, K, 2 * K, 5.0, 2.5, np.ascontiguousarray(old.T))
+    nbr_ref, q_ref, cnt_ref = O.refresh(poses, s, codes, K, win, 5.0, 2.5, np.ascontiguousarray(old.T))
     nbr = f.debug_get("nbr").T
     assert np.array_equal(f.debug_get("cnt"), cnt_ref)
     assert np.array_equal(nbr, nbr_ref)
@@ -420,6 +423,51 @@ def test_predict_parity(room, O):
     ref = O.predict(poses, dT, cov, 99, 0)
     assert _rot_err(out[:, :4], ref[:, :4]).max() < 1e-5
     assert np.abs(out[:, 4:7] - ref[:, 4:7]).max() < 1e-5
+
+
+def test_gaussian_init_parity(room, O):
+    n = 5000
+    w = room["w"]
+    R, t = w["traj"][0]
+    mean = S.pose8(R, t)[:7].astype(np.float32)
+    mean[:4] *= np.float32(1.3)            # not unit: normalised on input
+    A = np.random.default_rng(8).normal(size=(6, 6)) * 0.05
+    cov = (A @ A.T).astype(np.float32)
+    f = M.Filter(room["gpu"], _params(n, seed=77), gaussian=(mean, cov))
+    out = f.debug_get("poses")
+    ref = O.init_gauss(77, n, mean, cov)
+    assert _rot_err(out[:, :4], ref[:, :4]).max() < 1e-5
+    assert np.abs(out[:, 4:7] - ref[:, 4:7]).max() < 1e-5
+    bad = cov.copy(); bad[0, 1] += 0.01
+    for c in (bad, -np.eye(6, dtype=np.float32), np.full((6, 6), np.nan, np.float32)):
+        with pytest.raises(M.MegaPFError) as e:
+            M.Filter(room["gpu"], _params(n), gaussian=(mean, c))
+        assert e.value.status == M.MP_E_ARG
+
+
+def test_final_rescore_step(room, O):
+    # with final_rescore the step ends with a likelihood pass and a window-0
+    # refresh at the final poses (both parity-tested on host inputs: the
+    # likelihood tests and the refresh test's window 0 case); the step equals
+    # the plain step followed by that re-score, bit for bit; poses unchanged
+    n, K = 2000, 8
+    w = room["w"]
+    scan = np.ascontiguousarray(w["scans"][0][:600])
+    _, scov, _ = O.scan_cov(scan, k=10)
+    poses = _poses_mixed(w, n, 71)
+    f0 = M.Filter(room["gpu"], _params(n, k=K, lsh_bits=6, svgd_iters=2, window_c=16), poses=poses)
+    f1 = M.Filter(room["gpu"], _params(n, k=K, lsh_bits=6, svgd_iters=2, window_c=16, final_rescore=1), poses=poses)
+    for f in (f0, f1):
+        f.scan_upload(scan, cov6=scov)
+        f.step()
+    times = f1.stage_times()
+    assert times["likelihood"][1] == 3 and times["refresh"][1] == 3
+    before = f0.posterior_query(weights=True)["weights"]
+    f0.debug_stage(M.MP_DEBUG_RESCORE)
+    for name in ("poses", "nbr", "kval", "psi"):
+        assert np.array_equal(f0.debug_get(name), f1.debug_get(name)), name
+    # the re-scored posterior differs from the one of the paper's order
+    assert np.abs(f1.posterior_query(weights=True)["weights"] - before).max() > 1e-6
 
 
 def test_full_step_and_errors(room, O):
