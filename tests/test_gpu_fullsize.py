@@ -49,9 +49,9 @@ def test_campus_stages(campus, O):
     f = M.Filter(campus["gpu"], p, box=(info["box_min"], info["box_max"]))
     scan = w["scans"][0]
     f.scan_upload(scan)
-    poses = f.debug_get("poses")
     lo = np.array(info["box_min"], np.float32); hi = np.array(info["box_max"], np.float32)
-    assert np.array_equal(poses, O.init_uniform(4003, N, lo, hi))
+    poses = O.init_uniform(4003, N, lo, hi)       # every oracle call below takes the oracle's poses
+    assert np.array_equal(f.debug_get("poses"), poses)
     # LSH codes, sort and bounds for all particles
     f.debug_stage(M.MP_STAGE_LSH, 0)
     codes = f.debug_get("codes")

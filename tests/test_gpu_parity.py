@@ -39,6 +39,17 @@ def _params(n, **kw):
     return M.mp_filter_default_params(**base)
 
 
+def _oracle_lists(room, O, poses, K, bits, win, it=0, seed=4001, old=None):
+    """neighbour lists and FP64 kernel values from the oracle's own LSH, sort
+    and refresh of `poses` (the GPU's chain is compared with them bit for bit)"""
+    info = room["gpu"].info()
+    lo = np.array(info["box_min"], np.float32); hi = np.array(info["box_max"], np.float32)
+    codes = O.lsh_codes(poses, O.lsh_frame(seed, 0, it, lo, hi), 1.0, 5.0, 2.5, 0.3, bits, seed, 0, it)
+    s, _, _ = O.bucket_sort(codes)
+    nbr, q, _ = O.refresh(poses, s, codes, K, win, 5.0, 2.5, old)
+    return nbr, np.where(nbr >= 0, np.exp(-q.astype(np.float64)), 0.0)
+
+
 def _poses_mixed(w, n, seed):
     """half uniform over the room, half scattered around the ground truth"""
     rng = np.random.default_rng(seed)
@@ -317,13 +328,14 @@ def test_svgd_parity(room, O):
     f.debug_stage(M.MP_STAGE_LSH, 0)
     f.debug_stage(M.MP_STAGE_SORT)
     f.debug_stage(M.MP_STAGE_REFRESH)
-    nbr = f.debug_get("nbr")
+    nbr, _ = _oracle_lists(room, O, poses, K, 4, 16)
+    assert np.array_equal(f.debug_get("nbr").T, nbr)
     psi = np.zeros((n, 8), np.float32)
     psi[:, :6] = rng.normal(scale=0.05, size=(n, 6))
     f.debug_set("psi", psi)
     f.debug_stage(M.MP_STAGE_SVGD)
     out = f.debug_get("poses")
-    _, ref = O.svgd(poses, psi[:, :6].astype(np.float64), np.ascontiguousarray(nbr.T), 5.0, 2.5)
+    _, ref = O.svgd(poses, psi[:, :6].astype(np.float64), nbr, 5.0, 2.5)
     assert _rot_err(out[:, :4], ref[:, :4]).max() < 1e-4
     assert np.abs(out[:, 4:7] - ref[:, 4:7]).max() < 1e-4
 
@@ -339,7 +351,8 @@ def test_svgd_variants_parity(room, O, grad, transport):
     f.debug_stage(M.MP_STAGE_LSH, 0)
     f.debug_stage(M.MP_STAGE_SORT)
     f.debug_stage(M.MP_STAGE_REFRESH)
-    nbr = np.ascontiguousarray(f.debug_get("nbr").T)
+    nbr, _ = _oracle_lists(room, O, poses, K, 4, 16)
+    assert np.array_equal(f.debug_get("nbr").T, nbr)
     psi = np.zeros((n, 8), np.float32)
     psi[:, :6] = rng.normal(scale=0.05, size=(n, 6))
     f.debug_set("psi", psi)
@@ -394,12 +407,12 @@ def test_posterior_parity(room, O):
     prior = rng.uniform(0.5, 1.5, n).astype(np.float32)
     prior /= prior.sum()
     f.debug_set("prior", prior)
-    nbr = f.debug_get("nbr").T
-    kv = f.debug_get("kval").T.astype(np.float64)
+    nbr, kv = _oracle_lists(room, O, poses, K, 3, 16)
+    assert np.array_equal(f.debug_get("nbr").T, nbr)
+    assert np.abs(f.debug_get("kval").T.astype(np.float64) - kv).max() < 1e-6
     f.debug_stage(M.MP_STAGE_POSTERIOR)
     post = f.debug_get("post").astype(np.float64)
-    ref = O.posterior(prior.astype(np.float64), psi[:, 6].astype(np.float64), np.ascontiguousarray(nbr),
-                      np.ascontiguousarray(kv), rounds=10)
+    ref = O.posterior(prior.astype(np.float64), psi[:, 6].astype(np.float64), nbr, kv, rounds=10)
     assert abs(post.sum() - 1) < 1e-5
     assert np.abs(post - ref["post"]).max() < 1e-6
     q = f.posterior_query()
