@@ -24,19 +24,21 @@ def world():
     return dict(w=w, m=m)
 
 
-def _filter(world, scans):
+def _filter(world, scans, O):
+    """a filter holding the scans, and the oracle's (points, covariances) of
+    the non-empty ones (asserted equal to the library's scan records)"""
     p = M.mp_filter_default_params(n_particles=64, svgd_iters=1)
     f = M.Filter(world["m"], p)
     recs = []
     for sc in scans:
-        f.scan_upload(np.ascontiguousarray(sc))
+        sc = np.ascontiguousarray(sc, np.float32)
+        f.scan_upload(sc)
         if len(sc):
-            recs.append(f.debug_get("scan").copy())
+            _, cov, _ = O.scan_cov(sc, k=10)
+            rec = f.debug_get("scan")
+            assert np.array_equal(rec[:, :3], sc) and np.array_equal(rec[:, 3:9], cov)
+            recs.append((sc, np.ascontiguousarray(cov)))
     return f, recs
-
-
-def _cov6(rec):
-    return np.ascontiguousarray(rec[:, 3:9])
 
 
 def _true_motion(w):
@@ -53,7 +55,7 @@ def _rot_err(qa, qb):
 
 def test_terms_match_oracle(world, O):
     w = world["w"]
-    f, (r0, r1) = _filter(world, w["scans"][:2])
+    f, ((p0, c0), (p1, c1)) = _filter(world, w["scans"][:2], O)
     truth = _true_motion(w)
     rng = np.random.default_rng(3)
     for k in range(3):
@@ -62,7 +64,7 @@ def test_terms_match_oracle(world, O):
         init[:4] = S.mat_to_quat(S.quat_to_mat(init[:4]) @ S.rotvec_to_mat(rng.normal(0, 0.02, 3)))
         init = init.astype(np.float32)
         res = f.odometry(init=init, iterations=0)
-        ref = O.gicp_terms(r0[:, :3], _cov6(r0), r1[:, :3], _cov6(r1), init, dmax=1.0)
+        ref = O.gicp_terms(p0, c0, p1, c1, init, dmax=1.0)
         nn = f.debug_get("odo_nn")
         assert np.array_equal(nn, ref["nn"])
         assert res["inliers"] == ref["ninl"] and ref["ninl"] > 500
@@ -77,9 +79,9 @@ def test_terms_match_oracle(world, O):
 
 def test_alignment_matches_oracle_and_truth(world, O):
     w = world["w"]
-    f, (r0, r1) = _filter(world, w["scans"][:2])
+    f, ((p0, c0), (p1, c1)) = _filter(world, w["scans"][:2], O)
     res = f.odometry(iterations=20, cov_scale=2.0)
-    ref = O.gicp_align(r0[:, :3], _cov6(r0), r1[:, :3], _cov6(r1), iters=20, dmax=1.0, cov_scale=2.0)
+    ref = O.gicp_align(p0, c0, p1, c1, iters=20, dmax=1.0, cov_scale=2.0)
     print("odometry: GPU dT %s, oracle %s, inliers %d" % (np.round(res["dT64"], 6), np.round(ref["pose"], 6),
                                                           res["inliers"]))
     assert _rot_err(res["dT64"][:4], ref["pose"][:4]) <= 1e-4
@@ -100,16 +102,16 @@ def test_alignment_matches_oracle_and_truth(world, O):
 def test_previous_scan_survives_an_empty_upload(world, O):
     w = world["w"]
     empty = np.zeros((0, 3), np.float32)
-    f, (r0, r1) = _filter(world, [w["scans"][0], empty, w["scans"][1]])
-    g, (q0, q1) = _filter(world, w["scans"][:2])
+    f, _ = _filter(world, [w["scans"][0], empty, w["scans"][1]], O)
+    g, _ = _filter(world, w["scans"][:2], O)
     a = f.odometry(iterations=5)
     b = g.odometry(iterations=5)
     assert np.array_equal(a["dT"], b["dT"]) and a["inliers"] == b["inliers"]
 
 
-def test_odometry_errors(world):
+def test_odometry_errors(world, O):
     w = world["w"]
-    f, _ = _filter(world, w["scans"][:1])
+    f, _ = _filter(world, w["scans"][:1], O)
     with pytest.raises(M.MegaPFError) as e:
         f.odometry()
     assert e.value.status == M.MP_E_STATE
