@@ -188,6 +188,30 @@ def test_training_reduces_loss(room):
     assert losses[-20:].mean() < 0.5 * losses[:5].mean()
 
 
+def test_training_gain_held_out(room, O):
+    """What the trained network gains over the same network untrained: its
+    held-out error against the exact residual field (the oracle's), on points
+    near the map surfaces and spread over the room.  The plain path it stands
+    in for has no such error and is faster (the bench reports both); this is
+    the gain of training, not a gain over the plain method."""
+    sur = room["sur"]
+    sur.set_params(_random_params(31, scale=1.0))
+    held = _samples(room["w"], 4000, 33)
+    r, g = O.residual_field(room["ora"], held, sigma_s=0.03, dmax=1.0)
+
+    def err():
+        y = sur.eval(held).astype(np.float64)
+        return np.mean(np.abs(y[:, 0] - r)), np.mean(np.linalg.norm(y[:, 1:] - g, axis=1))
+
+    e0 = err()
+    sur.set_data(_samples(room["w"], 60000, 32))
+    losses = sur.train(1500)
+    e1 = err()
+    print("held-out |dr| %.3f -> %.3f, |d grad r| %.3f -> %.3f (loss %.4g -> %.4g)"
+          % (e0[0], e1[0], e0[1], e1[1], losses[0], losses[-1]))
+    assert e1[0] < 0.5 * e0[0] and e1[1] < e0[1]
+
+
 def _lik_filter(room, n, poses, scan, scorer, **kw):
     kw.setdefault("lik_layout", M.MP_LIK_LAYOUT_AUTO)
     p = M.mp_filter_default_params(n_particles=n, k=8, lsh_bits=16, svgd_iters=1, post_iters=10, window_c=16,
