@@ -298,7 +298,8 @@ typedef struct {
 
 /* Read the representative state and, optionally, all poses (N x 7) and the
  * posterior weights (N, FP64).  Synchronises `stream`.  MP_E_NUMERIC if a
- * pose or weight is not finite. */
+ * pose or weight is not finite; unlike other errors, the requested outputs
+ * are still written then, so that the caller can find the particle. */
 MP_API mp_status mp_posterior_query(mp_filter f, mp_posterior* out, float* poses_out, double* weights_out, void* stream);
 
 /* Message of the last failing call on this thread ("" if none). */

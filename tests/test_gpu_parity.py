@@ -510,3 +510,25 @@ def test_full_step_and_errors(room, O):
     q2 = f.posterior_query(poses=True, weights=True)
     assert np.array_equal(q2["weights"], before)
     assert np.abs(q2["poses"][:, :4] - q["poses"][:, :4]).max() < 1e-5
+
+
+def test_state_and_numeric_errors(room):
+    w = room["w"]
+    m = M.Map(w["map_xyz"][:50000], voxel=0.5)
+    n = 64
+    f = M.Filter(m, _params(n), poses=_poses_mixed(w, n, 91))
+    with pytest.raises(M.MegaPFError) as e:
+        m.close()                          # a filter still uses the map
+    assert e.value.status == M.MP_E_STATE
+    # a non-finite pose in the state is reported by the next query
+    P = f.debug_get("poses")
+    P[5, 4] = np.nan
+    f.debug_set("poses", P)
+    with pytest.raises(M.MegaPFError) as e:
+        f.posterior_query(poses=True)
+    assert e.value.status == M.MP_E_NUMERIC
+    # a buffer of the wrong size is refused, the filter stays usable
+    assert M.lib().mp_debug_get(f.handle, b"poses", P.ctypes.data, P.nbytes - 4, None) == M.MP_E_ARG
+    assert f.debug_get("poses").shape == P.shape
+    f.close()
+    m.close()
