@@ -624,7 +624,7 @@ def variants_leg(M, m, wl, minfo, scans, odo, warmup=1, steps=1):
     step, and the SVGD kernel against its HBM roofline."""
     import torch
     n, K, it = wl["particles"], wl["k"], wl["svgd_iters"]
-    svgd_bytes = svgd_refresh_bytes(K)[0] * n * it
+    svgd_bytes = (28.0 + 8 * K + 56.0 * K + 28.0) * n * it   # algorithmic bytes, neighbour gathers included
     out = {}
     for name, kw in VARIANTS.items():
         p = M.mp_filter_default_params(n_particles=n, k=K, lsh_bits=wl["lsh_bits"], svgd_iters=it,
@@ -712,34 +712,37 @@ def _med_p90(v):
 
 
 def stage_roofline(stages, wl, lik_flops_launch, t_step):
-    """Each stage of one filter step against the resource that bounds it:
-    compulsory bytes per step over HBM bandwidth for the data-movement stages
-    (each array a launch touches moved once per launch; a neighbour's pose or
-    psi, gathered K times, counted once, since those gathers are served by the
-    caches), algorithmic flops over the FP32 peak for the likelihood and the
-    scan's k-NN.  `step` sums the stages' roofline times over the measured
-    step time."""
+    """Each stage of one filter step against the resource that bounds it.
+    `frac` takes the algorithmic bytes per particle of the scope table: what
+    the method must move, neighbour gathers included (prediction 56 B per
+    frame; LSH 36 B; sort 16 B per 8-bit pass + 12 B of bucket bounds;
+    refresh 28 + 4K + 32C + 32K + 8K; SVGD 28 + 8K + 56K; posterior 20 + R
+    (12K + 4)).  A fraction above 1 means the caches serve the gathers.
+    `frac_compulsory` takes the bytes each launch must move once, gathers
+    counted once.  The likelihood and the scan k-NN are set against the FP32
+    peak.  `step` sums the stages' roofline times over the measured step time."""
     n, it, K, C, R = wl["particles"], wl["svgd_iters"], wl["k"], wl["window_c"], wl["post_iters"]
     ns, passes = wl["scan_points"], (wl["lsh_bits"] + 7) // 8
+    svgd_c, refresh_c = svgd_refresh_bytes(K)
     work = {
-        "predict": ("hbm", 64.0 * n),
-        "lsh": ("hbm", 44.0 * n * it),
-        "sort": ("hbm", (16.0 * passes + 12.0) * n * it),
-        "refresh": ("hbm", svgd_refresh_bytes(K)[1] * n * it),
-        "likelihood": ("alu", lik_flops_launch * it),
-        "svgd": ("hbm", svgd_refresh_bytes(K)[0] * n * it),
-        "posterior": ("hbm", (36.0 + R * (8.0 * K + 8)) * n),
-        "scan": ("alu", 8.0 * ns * (ns - 1)),
+        "predict": ("hbm", 56.0 * n, 64.0 * n),
+        "lsh": ("hbm", 36.0 * n * it, 44.0 * n * it),
+        "sort": ("hbm", (16.0 * passes + 12.0) * n * it, (16.0 * passes + 12.0) * n * it),
+        "refresh": ("hbm", (28.0 + 4 * K + 32.0 * C + 32.0 * K + 8 * K) * n * it, refresh_c * n * it),
+        "likelihood": ("alu", lik_flops_launch * it, lik_flops_launch * it),
+        "svgd": ("hbm", (28.0 + 8 * K + 56.0 * K + 28.0) * n * it, svgd_c * n * it),
+        "posterior": ("hbm", (20.0 + R * (12.0 * K + 4)) * n, (36.0 + R * (8.0 * K + 8)) * n),
+        "scan": ("alu", 8.0 * ns * (ns - 1), 8.0 * ns * (ns - 1)),
     }
     out, t_min = {}, 0.0
-    for name, (bound, w) in work.items():
+    for name, (bound, w, wc) in work.items():
         ms = stages.get(name, (0.0, 0))[0]
         peak = PEAK_HBM if bound == "hbm" else PEAK_FP32
         t = w / peak
         t_min += t
         if ms > 0:
             out[name] = {"bound": bound, "ms": round(ms, 3), "roofline_ms": round(1e3 * t, 4),
-                         "frac": round(t / (ms * 1e-3), 4)}
+                         "frac": round(t / (ms * 1e-3), 4), "frac_compulsory": round(wc / peak / (ms * 1e-3), 4)}
     out["step"] = {"roofline_ms": round(1e3 * t_min, 3), "ms": round(1e3 * t_step, 3),
                    "frac": round(t_min / t_step, 4)}
     return out
