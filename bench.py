@@ -261,38 +261,58 @@ def train_leg(M, S, m, w, minfo, steps=50):
     return res
 
 
+SEQUENCES = {
+    # the paper's kidnap sequences (Sec. IV-A): the sensor view blocked for a
+    # while and the sensor moved meanwhile; blocked frames predict with a wide
+    # noise (the uncertainty grows), so the particles spread over the map
+    "floor": dict(particles=65536, k=16, lsh_bits=20, svgd_iters=20, window_c=32, voxel=0.5, d_max=1.0,
+                  frames=60, occlusion=(25, 31), kidnap=28, kidnap_dist=20.0, blocked=(0.8, 6.0), seed=4002),
+    # the same at the paper's outdoor scale with its 80 m / 90 deg teleport (40 frames: casting a
+    # campus scan takes seconds of CPU)
+    "campus": dict(particles=1_048_576, k=16, lsh_bits=24, svgd_iters=10, window_c=32, voxel=1.0, d_max=2.0,
+                   frames=40, occlusion=(15, 21), kidnap=18, kidnap_dist=80.0, blocked=(1.0, 25.0), seed=4003),
+}
+
+
 def sequence_main(args):
-    """Global localisation, occlusion and kidnap on the floor scene (the
-    paper's kidnap sequences, Sec. IV-A, as a synthetic analogue): 65,536
-    particles from a uniform start, 60 frames, scans blocked for frames
-    25..30 while the sensor is teleported 20 m at frame 28 (blocked frames predict with a wide noise:
-    the particles spread); each frame's
-    motion is the workload's noisy prior refined by mp_odometry when both
-    scans are there and the match keeps half the points (else the prior);
-    the maximum-posterior pose and its smoothed version (mp_smoother) against
-    the truth: convergence and recovery frames, ATE."""
+    """Global localisation, occlusion and kidnap (the paper's kidnap
+    sequences, Sec. IV-A, as a synthetic analogue) on the floor scene (65,536
+    particles, 60 frames, scans blocked for frames 25..30 while the sensor is
+    teleported 20 m at frame 28) or the campus (1,048,576 particles, 40
+    frames, blocked 15..20, teleported 80 m and 90 deg at frame 18), from a
+    uniform start; blocked frames predict with a wide noise, so the particles
+    spread.  Each frame's motion is the workload's noisy prior refined by
+    mp_odometry when both scans are there and the match keeps half the points
+    (else the prior); the maximum-posterior pose and its smoothed version
+    (mp_smoother) against the truth: convergence and recovery frames, ATE."""
+    from paper_2404_16370_amd import synth as S
+    cfg = SEQUENCES[args.scene]
+    frames = args.seq_frames if args.seq_frames else cfg["frames"]
+    occl, kid = cfg["occlusion"], cfg["kidnap"]
+    br, bt = cfg["blocked"]
+    blocked_cov = np.diag([br ** 2] * 3 + [bt ** 2] * 3).astype(np.float32)
+    t0 = time.perf_counter()
+    # the scans are cast before anything touches the GPU (the workers are forked)
+    w = S.build_workload(args.scene, frames=frames, kidnap_frame=kid, kidnap_dist=cfg["kidnap_dist"], occlusion=occl,
+                         workers=min(16, os.cpu_count() or 1),
+                         progress=lambda d, n: log("scans cast: %d of %d" % (d, n)) if d % 8 == 0 or d == n else None)
+    log("sequence generated in %.1f s" % (time.perf_counter() - t0))
     import torch
     from paper_2404_16370_amd import megapf as M
-    from paper_2404_16370_amd import synth as S
     torch.cuda.set_device(0)
-    frames, occl, kid = args.seq_frames, (25, 31), 28
-    # without observations the uncertainty grows: each blocked frame predicts
-    # with 0.8 rad and 6 m of noise per axis instead of the odometry's
-    blocked_cov = np.diag([0.8 ** 2] * 3 + [6.0 ** 2] * 3).astype(np.float32)
-    t0 = time.perf_counter()
-    w = S.build_workload("floor", frames=frames, kidnap_frame=kid, kidnap_dist=20.0, occlusion=occl)
-    log("sequence generated in %.1f s" % (time.perf_counter() - t0))
     if args.map == "point":
-        # the paper's indoor field: 0.1 m cells; coverage and inlier gate 0.5 m
-        m = M.Map(torch.from_numpy(w["map_xyz"]).cuda(), voxel=0.1, nnf_radius=5, gauss_mode=M.MP_GAUSS_POINT)
-        dmax = 0.5
+        # the paper's fields: 0.1 m cells indoors, 0.2 m outdoors; coverage and gate 5 cells
+        cell = 0.1 if args.scene == "floor" else 0.2
+        m = M.Map(torch.from_numpy(w["map_xyz"]).cuda(), voxel=cell, nnf_radius=5, gauss_mode=M.MP_GAUSS_POINT)
+        dmax = 5 * cell
     else:
-        m = M.Map(torch.from_numpy(w["map_xyz"]).cuda(), voxel=0.5)
-        dmax = 1.0
+        m = M.Map(torch.from_numpy(w["map_xyz"]).cuda(), voxel=cfg["voxel"])
+        dmax = cfg["d_max"]
     info = m.info()
     log("map: %s" % info)
-    p = M.mp_filter_default_params(n_particles=65536, k=16, lsh_bits=20, svgd_iters=20, post_iters=10, window_c=32,
-                                   d_max=dmax, seed=4002, **VARIANTS[args.variant])
+    p = M.mp_filter_default_params(n_particles=cfg["particles"], k=cfg["k"], lsh_bits=cfg["lsh_bits"],
+                                   svgd_iters=cfg["svgd_iters"], post_iters=10, window_c=cfg["window_c"],
+                                   d_max=dmax, seed=cfg["seed"], **VARIANTS[args.variant])
     f = M.Filter(m, p, box=(info["box_min"], info["box_max"]))
     sm = M.Smoother(window=5, jump_m=1.0, jump_rad=0.2)
 
@@ -322,6 +342,8 @@ def sequence_main(args):
         f.step(dT, cov)
         q = f.posterior_query()
         raw.append(err(q["map_pose"], k))
+        if k % 20 == 0:
+            log("frame %d: raw error %.3f m %.2f deg" % (k, raw[-1][0], raw[-1][1]))
         smooth.append(err(sm.push(q["map_pose"], dT), k))
         if len(scan):
             n_prev = len(scan)
@@ -353,13 +375,15 @@ def sequence_main(args):
                 "recovered_frame": first_ok(errs, occl[1])}
 
     raw_s, sm_s = summary(raw), summary(smooth)
-    res = {"metric": "global localisation, occlusion and kidnap recovery (floor, 65,536 particles)",
+    res = {"metric": "global localisation, occlusion and kidnap recovery (%s, %d particles)" % (args.scene,
+                                                                                                 cfg["particles"]),
            "value": sm_s["ate_m"] if sm_s else None, "unit": "m ATE (smoothed representative pose)", "n_gpus": 1,
            "steps": frames, "warmup": 0, "ms_per_step": 1e3 * dt / frames, "higher_is_better": False,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-           "config": {"workload": "floor: 65536 particles x 4096 scan points x 20 SVGD iterations, %d frames, "
-                                  "uniform start, scans blocked for frames %d..%d, 20 m kidnap at frame %d" %
-                                  (frames, occl[0], occl[1] - 1, kid),
+           "config": {"workload": "%s: %d particles x %d scan points x %d SVGD iterations, %d frames, "
+                                  "uniform start, scans blocked for frames %d..%d, %.0f m kidnap at frame %d" %
+                                  (args.scene, cfg["particles"], len(w["scans"][0]), cfg["svgd_iters"], frames,
+                                   occl[0], occl[1] - 1, cfg["kidnap_dist"], kid),
                       "variant": args.variant, "variant_params": VARIANTS[args.variant],
                       "map": args.map, "map_gaussians": info["num_gauss"], "d_max": dmax},
            "converged_frame": conv, "scans_return_frame": occl[1], "scored_frames": len(scored),
@@ -756,7 +780,8 @@ def main():
     ap.add_argument("--workload", default="campus",
                     choices=sorted(WORKLOADS) + ["batch", "surrogate-eval", "sequence"])
     ap.add_argument("--frames", type=int, default=30, help="surrogate-eval: filter frames")
-    ap.add_argument("--seq-frames", type=int, default=60, help="sequence: frames")
+    ap.add_argument("--seq-frames", type=int, default=0, help="sequence: frames (0: the scene's default)")
+    ap.add_argument("--scene", default="floor", choices=["floor", "campus"], help="sequence: scene")
     ap.add_argument("--train-steps", type=int, default=20000, help="surrogate-eval: Adam steps")
     ap.add_argument("--sigma-s", type=float, default=0.03, help="surrogate-eval: sensor std of the score field")
     ap.add_argument("--lr", type=float, default=1e-3, help="surrogate-eval: Adam step")

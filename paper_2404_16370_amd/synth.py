@@ -599,14 +599,20 @@ def surrogate_samples(map_xyz, lo, hi, n, seed, sigma=0.25, uniform_frac=0.1) ->
     return out[rng.permutation(n)]
 
 
+def _scan_job(args):
+    return make_scan(*args)
+
+
 def build_workload(name, map_points=None, scan_points=None, frames=None, seed_offset=0, kidnap_frame=None,
-                   kidnap_dist=None, occlusion=None):
+                   kidnap_dist=None, occlusion=None, workers=1, progress=None):
     """Scene, map points, ground-truth trajectory, scans and odometry of a workload.
 
     kidnap_frame / kidnap_dist override the workload's teleport (the odometry
     keeps reporting an ordinary step there); occlusion = (first, end) blanks
     the scans of frames first .. end - 1 (the sensor view is blocked, the
-    odometry keeps reporting the motion)."""
+    odometry keeps reporting the motion).  workers > 1 casts the scans in
+    that many processes (each scan depends only on its own seed, so the
+    result is the same); progress(done, total) is called as scans finish."""
     w = dict(WORKLOADS[name])
     if kidnap_frame is not None:
         w["kidnap_frame"] = kidnap_frame
@@ -625,12 +631,24 @@ def build_workload(name, map_points=None, scan_points=None, frames=None, seed_of
     else:
         traj = trajectory(scene, n_frames, w["step"], w["yaw_deg"], 2200 + c, w.get("kidnap_frame"),
                           kidnap_dist=w.get("kidnap_dist", 80.0))
+    jobs = {f: (scene, R, t, n_scan, w["scan_sigma"], 2300 + c + 7919 * f) for f, (R, t) in enumerate(traj)
+            if not (occlusion is not None and occlusion[0] <= f < occlusion[1])}
+    cast = {}
+    if workers > 1 and len(jobs) > 1:
+        from concurrent.futures import ProcessPoolExecutor
+        with ProcessPoolExecutor(max_workers=workers) as ex:
+            for k, (f, sc) in enumerate(zip(jobs, ex.map(_scan_job, jobs.values()))):
+                cast[f] = sc
+                if progress:
+                    progress(k + 1, len(jobs))
+    else:
+        for k, (f, a) in enumerate(jobs.items()):
+            cast[f] = _scan_job(a)
+            if progress:
+                progress(k + 1, len(jobs))
     scans, odo = [], []
     for f, (R, t) in enumerate(traj):
-        if occlusion is not None and occlusion[0] <= f < occlusion[1]:
-            scans.append(np.zeros((0, 3), np.float32))
-        else:
-            scans.append(make_scan(scene, R, t, n_scan, w["scan_sigma"], 2300 + c + 7919 * f))
+        scans.append(cast[f] if f in cast else np.zeros((0, 3), np.float32))
         if f > 0:
             kid = w.get("kidnap_frame") is not None and f == w.get("kidnap_frame")
             hint = None
