@@ -42,13 +42,20 @@ struct LshArgs {
 __global__ __launch_bounds__(256) void k_lsh(LshArgs A) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (A.dyn) A.frame = A.dyn->frame;
-    mpdet::quat qL;
-    float3 tL;
-    mpdet::random_pose(A.seed, 0u, A.frame, A.it, mpdet::PURPOSE_TLSH, A.lo, A.hi, qL, tL);
-    if (i == 0) {
-        A.tlsh[0] = qL.w; A.tlsh[1] = qL.x; A.tlsh[2] = qL.y; A.tlsh[3] = qL.z;
-        A.tlsh[4] = tL.x; A.tlsh[5] = tL.y; A.tlsh[6] = tL.z; A.tlsh[7] = 0.0f;
+    // T^LSH is the same for every particle: one lane of the workgroup draws it
+    __shared__ float sL[8];
+    if (threadIdx.x == 0) {
+        mpdet::quat q0;
+        float3 t0;
+        mpdet::random_pose(A.seed, 0u, A.frame, A.it, mpdet::PURPOSE_TLSH, A.lo, A.hi, q0, t0);
+        sL[0] = q0.w; sL[1] = q0.x; sL[2] = q0.y; sL[3] = q0.z;
+        sL[4] = t0.x; sL[5] = t0.y; sL[6] = t0.z; sL[7] = 0.0f;
+        if (blockIdx.x == 0)
+            for (int k = 0; k < 8; ++k) A.tlsh[k] = sL[k];
     }
+    __syncthreads();
+    const mpdet::quat qL{sL[0], sL[1], sL[2], sL[3]};
+    const float3 tL = make_float3(sL[4], sL[5], sL[6]);
     if (i >= A.n) return;
     const float4 q4 = A.poses[2 * i], t4 = A.poses[2 * i + 1];
     const mpdet::quat qi{q4.x, q4.y, q4.z, q4.w};
