@@ -19,7 +19,7 @@
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kItems = 16;
+constexpr int kItems = 4;
 constexpr int kTile = kThreads * kItems;
 
 __device__ inline uint32_t wave_incl_scan(uint32_t v, int lane) {
