@@ -2,9 +2,9 @@
 //
 // The radix sort distributes particles into LSH buckets (Alg. 1, distribute
 // loop) and groups map points by voxel.  Each pass handles one 8-bit digit:
-//   1. per-tile digit histograms (tile = 4096 items, LDS atomics),
+//   1. per-tile digit histograms (tile = 1024 items, LDS atomics),
 //   2. exclusive scan of the digit-major histogram matrix -> global offsets,
-//   3. stable scatter: tiles are walked in 16 rounds of 256 items; within a
+//   3. stable scatter: tiles are walked in 4 rounds of 256 items; within a
 //      wavefront the rank among lanes with the same digit comes from eight
 //      64-lane ballots (one per digit bit); per-wavefront counts are
 //      prefix-summed across the four wavefronts in LDS.
