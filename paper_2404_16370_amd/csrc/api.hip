@@ -363,7 +363,7 @@ extern "C" mp_status mp_filter_init(mp_map map, const mp_filter_params* params, 
             f->tmp_vals.alloc(4 * N);
             f->head.alloc(4 * N);
             f->end.alloc(4 * N);
-            f->runs.alloc(4 * N);
+            f->rank.alloc(4 * N);
             f->hist.alloc(mp_radix_scratch_bytes(n));
             f->nbr.alloc(4 * K * N);
             f->kval.alloc(4 * K * N);

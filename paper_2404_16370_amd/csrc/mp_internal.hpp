@@ -148,7 +148,8 @@ struct mp_filter_s {
     DevMem psi;               // N x 8 float: psi[6], loglik, inliers
     DevMem hb;                // N x 28 float (debug)
     DevMem partial;           // chunks x 28 x N float
-    DevMem codes, sorted, scodes, tmp_keys, tmp_vals, head, end, runs, hist;  // LSH / sort
+    DevMem codes, sorted, scodes, tmp_keys, tmp_vals, head, end, hist;  // LSH / sort
+    DevMem rank;   // sorted position of each particle (the refresh runs in particle order)
     DevMem nbr, kval, cnt;    // K x N, K x N, N
     DevMem prior, post0, post1;   // N float
     DevMem red;               // reduction scratch

@@ -9,7 +9,8 @@
 //                (frame, iteration); every lane derives it, lane 0 records it.
 //   sort         stable radix sort of (code, index)  -> buckets as runs
 //   k_bucket_bounds  bucket head/end per sorted position (search of the runs)
-//   k_refresh    one lane per sorted position: candidates = previous list U
+//   k_refresh    one lane per particle (its sorted position from a rank
+//                array): candidates = previous list U
 //                window of up to C bucket-mates after the particle (cyclic in
 //                its bucket); each ranked by q_ij = d^T W^K d (deterministic
 //                FP32), the K-1 smallest (q, j) kept behind the particle itself
@@ -125,6 +126,7 @@ __global__ void k_bucket_bounds(const uint32_t* __restrict__ sc, int n, int32_t*
 struct RefreshArgs {
     const float4* __restrict__ poses;
     const int32_t* __restrict__ sorted;
+    const int32_t* __restrict__ rank;   // sorted position of each particle
     const int32_t* __restrict__ head;
     const int32_t* __restrict__ end;
     int32_t* __restrict__ nbr;    // K x N
@@ -170,12 +172,23 @@ struct TopK {
     }
 };
 
+// rank[sorted[s]] = s
+__global__ void k_rank(const int32_t* __restrict__ sorted, int n, int32_t* __restrict__ rank) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const int i = sorted[s];
+    if (i >= 0 && i < n) rank[i] = s;
+}
+
+// One lane per particle, in particle order, so that the particle's pose, its
+// old list and its new list and kernel values are read and written coalesced;
+// its sorted position (rank) locates its bucket window.
 template <int KM>
 __global__ __launch_bounds__(256) void k_refresh(RefreshArgs A) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= A.n) return;
-    const int i = A.sorted[s];
-    if (i < 0 || i >= A.n) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= A.n) return;
+    const int s = A.rank[i];
+    if (s < 0 || s >= A.n || A.sorted[s] != i) return;
     const float4 qi4 = A.poses[2 * i], ti4 = A.poses[2 * i + 1];
     const mpdet::quat qi{qi4.x, qi4.y, qi4.z, qi4.w};
     const float3 ti = make_float3(ti4.x, ti4.y, ti4.z);
@@ -287,9 +300,12 @@ void mp_launch_sort(mp_filter f, hipStream_t s) {
 }
 
 void mp_launch_refresh(mp_filter f, hipStream_t s, int window) {
+    k_rank<<<nblk(f->n), 256, 0, s>>>(f->sorted.as<int32_t>(), f->n, f->rank.as<int32_t>());
+    MP_CHECK_LAUNCH();
     RefreshArgs A;
     A.poses = f->poses[f->cur].as<float4>();
     A.sorted = f->sorted.as<int32_t>();
+    A.rank = f->rank.as<int32_t>();
     A.head = f->head.as<int32_t>();
     A.end = f->end.as<int32_t>();
     A.nbr = f->nbr.as<int32_t>();
