@@ -802,8 +802,8 @@ def main():
                     help="run one plain 1 GiB device copy before timing (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build runs the hot path on a single MI355X "
-              "(multi-GPU sharding is a design note, not built); use --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the hot path runs on a single MI355X "
+              "(sharding over several GPUs is designed, not implemented); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     if args.workload == "batch":
