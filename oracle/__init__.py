@@ -75,9 +75,12 @@ def _declare(L):
     L.mpo_gauss6.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, _f32p]
     L.mpo_lsh_frame.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, _f32p, _f32p, _f32p]
     L.mpo_init_uniform.argtypes = [C.c_uint64, C.c_int64, _f32p, _f32p, _f32p]
+    L.mpo_init_uniform_range.argtypes = [C.c_uint64, C.c_int64, C.c_int64, _f32p, _f32p, _f32p]
     L.mpo_hash6.argtypes = [_i32p]; L.mpo_hash6.restype = C.c_uint32
     L.mpo_lsh_codes.argtypes = [_f32p, C.c_int64, _f32p, C.c_float, C.c_float, C.c_float, C.c_float, C.c_int,
                                 C.c_uint64, C.c_uint32, C.c_uint32, C.c_int32, _u32p, _vp]
+    L.mpo_lsh_codes_range.argtypes = [_f32p, C.c_int64, C.c_int64, _f32p, C.c_float, C.c_float, C.c_float, C.c_float,
+                                      C.c_int, C.c_uint64, C.c_uint32, C.c_uint32, C.c_int32, _u32p, _vp]
     L.mpo_eig3.argtypes = [_f64p, _f64p, _f64p]
     L.mpo_voxel_of.argtypes = [_f32p, C.c_int64, C.c_float, _i32p]
     L.mpo_map_build.argtypes = [_f32p, C.c_int64, C.c_float, C.c_int, C.c_int, C.c_float]
@@ -187,20 +190,28 @@ def lsh_frame(seed, frame, it, lo, hi):
     return T
 
 
+def init_uniform_range(seed, first, n, lo, hi):
+    out = np.zeros((n, 8), np.float32)
+    lib().mpo_init_uniform_range(seed, first, n, _f32(lo), _f32(hi), out)
+    return out
+
+
 def init_uniform(seed, n, lo, hi):
     P = np.zeros((n, 8), np.float32)
     lib().mpo_init_uniform(seed, n, _f32(lo), _f32(hi), P)
     return P
 
 
-def lsh_codes(poses8, TL, alpha, sigma_r, sigma_t, sigma_lsh, bits, seed, frame, it, want_cells=False, tangent=0):
-    """tangent 0: decoupled [log(R_L^T R_i); R_L^T (t_i - t_L)]; 1: coupled log(T_LSH^-1 T_i)"""
+def lsh_codes(poses8, TL, alpha, sigma_r, sigma_t, sigma_lsh, bits, seed, frame, it, want_cells=False, tangent=0,
+              first_index=0):
+    """tangent 0: decoupled [log(R_L^T R_i); R_L^T (t_i - t_L)]; 1: coupled log(T_LSH^-1 T_i).
+    poses8[k] is particle first_index + k (its noise is drawn for that index)"""
     P = _f32(poses8)
     n = P.shape[0]
     codes = np.zeros(n, np.uint32)
     cells = np.zeros((n, 6), np.int32) if want_cells else None
-    lib().mpo_lsh_codes(P, n, _f32(TL), alpha, sigma_r, sigma_t, sigma_lsh, bits, seed, frame, it, int(tangent), codes,
-                        _ptr(cells))
+    lib().mpo_lsh_codes_range(P, int(first_index), n, _f32(TL), alpha, sigma_r, sigma_t, sigma_lsh, bits, seed, frame,
+                              it, int(tangent), codes, _ptr(cells))
     return (codes, cells) if want_cells else codes
 
 

@@ -314,6 +314,13 @@ MPO_API void mpo_init_uniform(uint64_t seed, int64_t n, const float lo[3], const
     for (int64_t i = 0; i < n; ++i) random_pose(seed, (uint32_t)i, 0u, 0u, MPO_PURPOSE_INIT, lo, hi, poses + 8 * i);
 }
 
+/* uniform initial particles i0 .. i0 + n - 1 (a sample of a large set) */
+MPO_API void mpo_init_uniform_range(uint64_t seed, int64_t i0, int64_t n, const float lo[3], const float hi[3],
+                                    float* poses) {
+    for (int64_t k = 0; k < n; ++k)
+        random_pose(seed, (uint32_t)(i0 + k), 0u, 0u, MPO_PURPOSE_INIT, lo, hi, poses + 8 * k);
+}
+
 /* 6-D integer hash of the LSH cell (Teschner et al. 2003 style XOR of
  * products; three Teschner primes plus three fixed odd constants) */
 static const uint32_t HASH_P[6] = {73856093u, 19349663u, 83492791u, 2654435761u, 2246822519u, 3266489917u};
@@ -338,9 +345,21 @@ static int32_t floor_to_i32(float z) {
  *   tangent 1 (coupled)    log(T_LSH^-1 T_i), the SE(3) logarithm of Eq. (8).
  * Deterministic FP32.  Pinned by cells of zeta computed in FP64 (rotation
  * vectors, matrix logarithm) away from cell boundaries. */
+MPO_API void mpo_lsh_codes_range(const float* poses, int64_t i0, int64_t n, const float TL[8], float alpha,
+                                 float sigma_r, float sigma_t, float sigma_lsh, int bits, uint64_t seed, uint32_t frame,
+                                 uint32_t it, int32_t tangent, uint32_t* codes, int32_t* cells);
+
 MPO_API void mpo_lsh_codes(const float* poses, int64_t n, const float TL[8], float alpha, float sigma_r,
                            float sigma_t, float sigma_lsh, int bits, uint64_t seed, uint32_t frame, uint32_t it,
                            int32_t tangent, uint32_t* codes, int32_t* cells /* nullable n*6 */) {
+    mpo_lsh_codes_range(poses, 0, n, TL, alpha, sigma_r, sigma_t, sigma_lsh, bits, seed, frame, it, tangent, codes,
+                        cells);
+}
+
+/* the same for particles i0 .. i0 + n - 1 (poses[k] is particle i0 + k) */
+MPO_API void mpo_lsh_codes_range(const float* poses, int64_t i0, int64_t n, const float TL[8], float alpha,
+                                 float sigma_r, float sigma_t, float sigma_lsh, int bits, uint64_t seed, uint32_t frame,
+                                 uint32_t it, int32_t tangent, uint32_t* codes, int32_t* cells /* nullable n*6 */) {
     uint32_t mask = bits >= 32 ? 0xFFFFFFFFu : ((1u << bits) - 1u);
     float ar = alpha * sigma_r, at = alpha * sigma_t;
     q32 qL = {TL[0], TL[1], TL[2], TL[3]};
@@ -360,7 +379,7 @@ MPO_API void mpo_lsh_codes(const float* poses, int64_t n, const float TL[8], flo
             rotT32(RL, dt, u);
         }
         float z6[6];
-        mpo_gauss6(seed, (uint32_t)i, frame, it, MPO_PURPOSE_LSH, z6);
+        mpo_gauss6(seed, (uint32_t)(i0 + i), frame, it, MPO_PURPOSE_LSH, z6);
         int32_t c[6];
         for (int k = 0; k < 3; ++k) {
             c[k] = floor_to_i32(ar * om[k] + sigma_lsh * z6[k]);

@@ -90,3 +90,13 @@ def test_uniform_init_and_lsh_frame(O):
     T = O.lsh_frame(5, 3, 4, lo, hi)
     assert abs(np.linalg.norm(T[:4]) - 1) < 1e-6
     assert not np.array_equal(T, O.lsh_frame(5, 3, 5, lo, hi))
+
+
+def test_index_ranges_match_full_sets(O):
+    # samples of a large particle set: particle i draws with its own index
+    lo = np.array([0, 0, 0], np.float32); hi = np.array([10, 10, 3], np.float32)
+    full = O.init_uniform(5, 300, lo, hi)
+    assert np.array_equal(O.init_uniform_range(5, 120, 180, lo, hi), full[120:])
+    TL = O.lsh_frame(5, 2, 1, lo, hi)
+    codes = O.lsh_codes(full, TL, 1.0, 5.0, 2.5, 0.3, 20, 5, 2, 1)
+    assert np.array_equal(O.lsh_codes(full[120:], TL, 1.0, 5.0, 2.5, 0.3, 20, 5, 2, 1, first_index=120), codes[120:])
