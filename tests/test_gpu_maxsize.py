@@ -92,3 +92,24 @@ def test_max_particles(O):
     assert abs(q["weights"].sum() - 1.0) < 1e-4
     assert q["map_weight"] == pytest.approx(q["weights"].max(), rel=1e-6)
     f.close()
+
+
+def test_min_particles(O):
+    # the smallest filter: one particle, K = 1, one bucket; a step is a
+    # Gauss-Newton update of that particle and its weight is 1
+    w = S.build_workload("room", map_points=50_000, scan_points=300)
+    m = M.Map(w["map_xyz"], voxel=0.5)
+    R, t = w["traj"][0]
+    pose = S.pose8(R, t)[None, :].astype(np.float32)
+    p = M.mp_filter_default_params(n_particles=1, k=1, lsh_bits=0, svgd_iters=3, post_iters=2, window_c=0,
+                                   d_max=1.0, seed=3)
+    f = M.Filter(m, p, poses=pose)
+    f.scan_upload(np.ascontiguousarray(w["scans"][0]))
+    f.step()
+    q = f.posterior_query(poses=True, weights=True)
+    assert q["weights"].shape == (1,) and q["weights"][0] == pytest.approx(1.0)
+    assert q["map_index"] == 0 and np.all(np.isfinite(q["poses"]))
+    # started at the truth, the Gauss-Newton steps stay within a few cm of it
+    assert np.linalg.norm(q["poses"][0, 4:7] - pose[0, 4:7]) < 0.05
+    assert np.array_equal(f.debug_get("nbr"), np.zeros((1, 1), np.int32))
+    f.close()
