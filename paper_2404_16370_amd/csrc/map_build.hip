@@ -292,7 +292,7 @@ __global__ __launch_bounds__(256) void k_point_gauss(const float* __restrict__ x
                 }
         if (sh >= 1 && cnt == k) {
             const float b = (float)sh * r - slop;
-            if (thd < b * b) break;
+            if (b > 0.0f && thd < b * b) break;   // (b <= 0: cells too small for the bound; search on)
         }
     }
     const int m = cnt + 1;
