@@ -71,7 +71,8 @@ enum { MP_NNF_AUTO = 0, MP_NNF_HASH = 1, MP_NNF_DENSE = 2 };
  *          voxel lies within Chebyshev distance point_search (kept when that
  *          neighbourhood holds >= min_points points); the field, a grid of
  *          cell edge `voxel`, maps each cell to the kept point nearest to the
- *          cell's centre within nnf_radius * voxel (DENSE backend only). */
+ *          cell's centre within nnf_radius * voxel (nnf_radius >= 1; DENSE
+ *          backend only). */
 enum { MP_GAUSS_VOXEL = 0, MP_GAUSS_POINT = 1 };
 
 typedef struct {

@@ -141,6 +141,8 @@ extern "C" mp_status mp_map_build(const float* xyz, int64_t n, const mp_map_para
         if (params->gauss_mode == MP_GAUSS_POINT) {
             if (params->point_k < 3 || params->point_k > 32) mp_throw(MP_E_ARG, "point_k must be 3..32");
             if (params->point_search < 1 || params->point_search > 4) mp_throw(MP_E_ARG, "point_search must be 1..4");
+            if (params->nnf_radius < 1)
+                mp_throw(MP_E_ARG, "per-point Gaussians need nnf_radius >= 1 (the field reaches nnf_radius * voxel)");
             if (params->backend == MP_NNF_HASH)
                 mp_throw(MP_E_UNSUPPORTED, "per-point Gaussians take the dense field only");
         }

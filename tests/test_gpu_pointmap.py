@@ -114,7 +114,8 @@ def test_point_map_errors(pm):
     with pytest.raises(M.MegaPFError) as e:
         M.Map(xyz, voxel=0.2, gauss_mode=M.MP_GAUSS_POINT, backend=M.MP_NNF_HASH)
     assert e.value.status == M.MP_E_UNSUPPORTED
-    for kw in (dict(point_k=2), dict(point_k=33), dict(point_search=0), dict(point_search=5), dict(gauss_mode=7)):
+    for kw in (dict(point_k=2), dict(point_k=33), dict(point_search=0), dict(point_search=5), dict(gauss_mode=7),
+               dict(nnf_radius=0)):
         with pytest.raises(M.MegaPFError) as e:
             M.Map(xyz, voxel=0.2, **{"gauss_mode": M.MP_GAUSS_POINT, **kw})
         assert e.value.status == M.MP_E_ARG
