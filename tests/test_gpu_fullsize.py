@@ -5,6 +5,7 @@ one by one:
   bit-exact   map Gaussians (ids, voxels, means, normals), LSH codes of all
               particles, the complete bucket order and bounds, neighbour lists
               of 2048 sampled particles
+  1e-4        SVGD-updated poses of 256 sampled particles (rad / m)
   1e-4 rel    log-likelihoods of 256 sampled particles (inlier counts exact);
               H within 1e-4 of max|H| and b within 1e-4 of sqrt(H_ii sum c)
               per particle: the plain FP32 sums over all 8192 points of a
@@ -90,6 +91,28 @@ def test_campus_stages(campus, O):
     print("full size, FP32 sums over 8192 points: max H error %.2e of max|H|, max b error %.2e of its scale"
           % (herr.max(), berr.max()), flush=True)
     assert herr.max() <= 1e-4 and berr.max() <= 1e-4
+    # SVGD at full size (K = 16): 256 sampled particles against the oracle run
+    # on the compact set of those particles and their neighbours (the oracle's
+    # lists), with psi drawn on the host
+    psi_h = np.zeros((N, 8), np.float32)
+    psi_h[:, :6] = np.random.default_rng(7).normal(scale=0.05, size=(N, 6))
+    f.debug_set("psi", psi_h)
+    f.debug_stage(M.MP_STAGE_SVGD)
+    out = f.debug_get("poses")
+    pick = np.sort(rng.choice(N, 256, replace=False))
+    sub = nref[pick]
+    ids = np.unique(np.concatenate([pick, sub[sub >= 0]]))
+    lists = np.full((len(ids), 16), -1, np.int32)
+    lists[:, 0] = np.arange(len(ids))
+    lists[np.searchsorted(ids, pick)] = np.where(sub >= 0, np.searchsorted(ids, np.maximum(sub, 0)), -1)
+    _, ref = O.svgd(poses[ids], psi_h[ids, :6].astype(np.float64), lists, 5.0, 2.5)
+    ref = ref[np.searchsorted(ids, pick)]
+    a = out[pick, :4].astype(np.float64); a /= np.linalg.norm(a, axis=1, keepdims=True)
+    b_ = ref[:, :4] / np.linalg.norm(ref[:, :4], axis=1, keepdims=True)
+    wq = np.abs(np.sum(a * b_, axis=1))
+    vq = np.linalg.norm(a[:, :1] * b_[:, 1:] - b_[:, :1] * a[:, 1:] - np.cross(a[:, 1:], b_[:, 1:]), axis=1)
+    assert (2 * np.arctan2(vq, wq)).max() < 1e-4
+    assert np.abs(out[pick, 4:7] - ref[:, 4:7]).max() < 1e-4
     # full step: posterior is a distribution with its MAP on top
     f.step()
     q = f.posterior_query(weights=True)
