@@ -5,7 +5,8 @@ one by one:
   bit-exact   map Gaussians (ids, voxels, means, normals), LSH codes of all
               particles, the complete bucket order and bounds, neighbour lists
               of 2048 sampled particles
-  1e-4        SVGD-updated poses of 256 sampled particles (rad / m)
+  1e-4        SVGD-updated poses of 256 sampled particles (rad / m); every
+              posterior weight, relative (host log-likelihoods)
   1e-4 rel    log-likelihoods of 256 sampled particles (inlier counts exact);
               H within 1e-4 of max|H| and b within 1e-4 of sqrt(H_ii sum c)
               per particle: the plain FP32 sums over all 8192 points of a
@@ -65,7 +66,7 @@ def test_campus_stages(campus, O):
     # neighbour refresh: compare 2048 sampled particles (the oracle refreshes all, cheaply)
     f.debug_stage(M.MP_STAGE_REFRESH)
     nbr = f.debug_get("nbr").T
-    nref, _, cref = O.refresh(poses, s, ref, 16, 32, 5.0, 2.5, None)
+    nref, qref, cref = O.refresh(poses, s, ref, 16, 32, 5.0, 2.5, None)
     rng = np.random.default_rng(0)
     pick = rng.choice(N, 2048, replace=False)
     assert np.array_equal(nbr[pick], nref[pick])
@@ -96,6 +97,7 @@ def test_campus_stages(campus, O):
     # lists), with psi drawn on the host
     psi_h = np.zeros((N, 8), np.float32)
     psi_h[:, :6] = np.random.default_rng(7).normal(scale=0.05, size=(N, 6))
+    psi_h[:, 6] = np.random.default_rng(8).normal(-50.0, 3.0, N)    # log-likelihoods for the posterior below
     f.debug_set("psi", psi_h)
     f.debug_stage(M.MP_STAGE_SVGD)
     out = f.debug_get("poses")
@@ -113,6 +115,14 @@ def test_campus_stages(campus, O):
     vq = np.linalg.norm(a[:, :1] * b_[:, 1:] - b_[:, :1] * a[:, 1:] - np.cross(a[:, 1:], b_[:, 1:]), axis=1)
     assert (2 * np.arctan2(vq, wq)).max() < 1e-4
     assert np.abs(out[pick, 4:7] - ref[:, 4:7]).max() < 1e-4
+    # posterior at full size: every weight against the oracle's (its lists and
+    # FP64 kernel values, the host log-likelihoods, prior 1/N)
+    f.debug_stage(M.MP_STAGE_POSTERIOR)
+    post = f.debug_get("post").astype(np.float64)
+    kref = np.where(nref >= 0, np.exp(-qref.astype(np.float64)), 0.0)
+    pr = O.posterior(np.full(N, 1.0 / N), psi_h[:, 6].astype(np.float64), nref, kref, rounds=10)
+    assert abs(post.sum() - 1) < 1e-4
+    assert np.all(np.abs(post - pr["post"]) <= 1e-4 * pr["post"] + 1e-12), np.abs(post - pr["post"]).max()
     # full step: posterior is a distribution with its MAP on top
     f.step()
     q = f.posterior_query(weights=True)
