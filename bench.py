@@ -90,7 +90,7 @@ def cpu_baseline(wl, w, scan, budget_s=15.0):
     _, scov, _ = O.scan_cov(scan, k=10)
     from paper_2404_16370_amd import synth as S
     # particles as the workload starts them: uniform over the map box and SO(3)
-    poses = S.uniform_particles(65536, w["scene"].lo, w["scene"].hi, 3003)
+    poses = S.uniform_particles(262144, w["scene"].lo, w["scene"].hi, 3003)
     info_lo, info_hi = w["scene"].lo.astype(np.float32), w["scene"].hi.astype(np.float32)
 
     def one_iteration(P):
