@@ -20,12 +20,16 @@ constexpr int kB = 128;
 constexpr int kKMax = 32;
 constexpr int kPtsTile = 2048;
 
+// Cyclic Jacobi on a symmetric 3x3 (row-major) and the eigenvector of the
+// smallest eigenvalue (lowest index on ties).  The rotation loop is unrolled
+// so that every index into A and V is a constant and both stay in registers.
 __device__ void jacobi_min_vec(double A[9], double nrm[3]) {
     double V[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
     for (int sweep = 0; sweep < 60; ++sweep) {
         const double off = A[1] * A[1] + A[2] * A[2] + A[5] * A[5];
         const double dg = A[0] * A[0] + A[4] * A[4] + A[8] * A[8];
         if (off <= 1e-300 || off <= 1e-34 * dg) break;
+#pragma unroll
         for (int pq = 0; pq < 3; ++pq) {
             const int p = pq == 2 ? 1 : 0;
             const int q = pq == 0 ? 1 : 2;
@@ -36,16 +40,19 @@ __device__ void jacobi_min_vec(double A[9], double nrm[3]) {
             const double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
             const double c = 1.0 / sqrt(t * t + 1.0);
             const double s = t * c;
+#pragma unroll
             for (int k = 0; k < 3; ++k) {
                 const double x = A[3 * k + p], y = A[3 * k + q];
                 A[3 * k + p] = c * x - s * y;
                 A[3 * k + q] = s * x + c * y;
             }
+#pragma unroll
             for (int k = 0; k < 3; ++k) {
                 const double x = A[3 * p + k], y = A[3 * q + k];
                 A[3 * p + k] = c * x - s * y;
                 A[3 * q + k] = s * x + c * y;
             }
+#pragma unroll
             for (int k = 0; k < 3; ++k) {
                 const double x = V[3 * k + p], y = V[3 * k + q];
                 V[3 * k + p] = c * x - s * y;
@@ -53,18 +60,12 @@ __device__ void jacobi_min_vec(double A[9], double nrm[3]) {
             }
         }
     }
-    const double ev[3] = {A[0], A[4], A[8]};
-    int o[3] = {0, 1, 2};
-    for (int i = 0; i < 3; ++i)
-        for (int j = i + 1; j < 3; ++j)
-            if (ev[o[j]] < ev[o[i]]) {
-                const int tmp = o[i];
-                o[i] = o[j];
-                o[j] = tmp;
-            }
-    nrm[0] = V[o[0]];
-    nrm[1] = V[3 + o[0]];
-    nrm[2] = V[6 + o[0]];
+    int m = 0;
+    if (A[4] < A[0]) m = 1;
+    if (A[8] < (m == 1 ? A[4] : A[0])) m = 2;
+    nrm[0] = m == 0 ? V[0] : (m == 1 ? V[1] : V[2]);
+    nrm[1] = m == 0 ? V[3] : (m == 1 ? V[4] : V[5]);
+    nrm[2] = m == 0 ? V[6] : (m == 1 ? V[7] : V[8]);
 }
 
 // k nearest other scan points of each point, 16 lanes per point: lane l
@@ -149,24 +150,38 @@ __global__ __launch_bounds__(kB) void k_scan_knn_cov(const float* __restrict__ x
     if (kk + 1 < 5) {
         c6[0] = 1; c6[1] = 0; c6[2] = 0; c6[3] = 1; c6[4] = 0; c6[5] = 1;
     } else {
+        // unrolled over the list capacity so that nb is indexed by constants
+        // and stays in registers; sums in list order
         double sm[3] = {(double)pi.x, (double)pi.y, (double)pi.z};
+#pragma unroll
         for (int a = 0; a < KC; ++a) {
-            if (a >= kk) break;
-            const int j = nb[a];
-            sm[0] = sm[0] + (double)xyz[3 * j];
-            sm[1] = sm[1] + (double)xyz[3 * j + 1];
-            sm[2] = sm[2] + (double)xyz[3 * j + 2];
+            if (a < kk) {
+                const int j = nb[a];
+                sm[0] = sm[0] + (double)xyz[3 * j];
+                sm[1] = sm[1] + (double)xyz[3 * j + 1];
+                sm[2] = sm[2] + (double)xyz[3 * j + 2];
+            }
         }
         const double dn = (double)(kk + 1);
         const double mu[3] = {sm[0] / dn, sm[1] / dn, sm[2] / dn};
         double S[6] = {0, 0, 0, 0, 0, 0};
-        for (int a = -1; a < kk; ++a) {
-            const int j = a < 0 ? i : nb[a];
-            const double d0 = (double)xyz[3 * j] - mu[0];
-            const double d1 = (double)xyz[3 * j + 1] - mu[1];
-            const double d2 = (double)xyz[3 * j + 2] - mu[2];
+        {
+            const double d0 = (double)pi.x - mu[0];
+            const double d1 = (double)pi.y - mu[1];
+            const double d2 = (double)pi.z - mu[2];
             S[0] += d0 * d0; S[1] += d0 * d1; S[2] += d0 * d2;
             S[3] += d1 * d1; S[4] += d1 * d2; S[5] += d2 * d2;
+        }
+#pragma unroll
+        for (int a = 0; a < KC; ++a) {
+            if (a < kk) {
+                const int j = nb[a];
+                const double d0 = (double)xyz[3 * j] - mu[0];
+                const double d1 = (double)xyz[3 * j + 1] - mu[1];
+                const double d2 = (double)xyz[3 * j + 2] - mu[2];
+                S[0] += d0 * d0; S[1] += d0 * d1; S[2] += d0 * d2;
+                S[3] += d1 * d1; S[4] += d1 * d2; S[5] += d2 * d2;
+            }
         }
         for (int a = 0; a < 6; ++a) S[a] /= dn;
         double A[9] = {S[0], S[1], S[2], S[1], S[3], S[4], S[2], S[4], S[5]};
