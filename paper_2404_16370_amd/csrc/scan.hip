@@ -4,7 +4,7 @@
 // mu is the point itself.  Without caller covariances, Sigma is the
 // GICP-normalised covariance I - (1-eps) n n^T of the point and its k nearest
 // other scan points: k-NN by FP32 squared distance (fixed fma order, ties to
-// the lower index; scan tiles staged in LDS, 16 lanes per point), FP64 mean and 1/(k+1)
+// the lower index; scan tiles staged in LDS, 16 lanes per point, 32 points per workgroup), FP64 mean and 1/(k+1)
 // covariance summed self-first in neighbour order, FP64 cyclic Jacobi with a
 // fixed operation order.  Fewer than 5 points give Sigma = I.
 //
@@ -16,7 +16,7 @@
 
 namespace {
 
-constexpr int kB = 128;
+constexpr int kB = 512;   // 32 points per workgroup share each staged tile
 constexpr int kKMax = 32;
 constexpr int kPtsTile = 2048;
 
@@ -70,10 +70,12 @@ __device__ void jacobi_min_vec(double A[9], double nrm[3]) {
 
 // k nearest other scan points of each point, 16 lanes per point: lane l
 // keeps the KC best (d2, j) of the candidates j = l, l + 16, ... (ascending j
-// with a strict comparison, so equal distances stay in index order); the 16
-// sorted lists are then merged by k rounds of a (d2, j) minimum across the
-// group.  Then the FP64 Gaussian of the point and its neighbours.
+// with a strict comparison, so equal distances stay in index order) that do
+// not exceed a bound on the group's k-th distance; the 16 sorted lists are
+// then merged by rounds of a (d2, j) minimum across the group.  Then the
+// FP64 Gaussian of the point and its neighbours.
 constexpr int kQLanes = 16;
+constexpr int kChunk = 32;   // candidates per lane between group-bound updates
 
 template <int KC>
 __global__ __launch_bounds__(kB) void k_scan_knn_cov(const float* __restrict__ xyz, int n, int k, float eps,
@@ -81,7 +83,7 @@ __global__ __launch_bounds__(kB) void k_scan_knn_cov(const float* __restrict__ x
     __shared__ float3 tile[kPtsTile];
     const int grp = threadIdx.x / kQLanes, gl = threadIdx.x % kQLanes;
     const int i = blockIdx.x * (kB / kQLanes) + grp;
-    const bool active = i < n;   // uniform over the point's 16 lanes
+    const bool active = i < n;   // uniform over the point's lanes
     const float3 pi = active ? make_float3(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2]) : make_float3(0, 0, 0);
     const int kk = min(k, n - 1);
     float bd[KC];
@@ -91,6 +93,26 @@ __global__ __launch_bounds__(kB) void k_scan_knn_cov(const float* __restrict__ x
         bd[m] = __builtin_inff();
         bj[m] = 0x7FFFFFFF;
     }
+    // lists needed per lane to bound the group's kk-th distance (kk <= KC)
+    const int mb = kk > kQLanes ? 1 : 0;
+    float bound = __builtin_inff();
+    // Seed the bound from the 16 (mb + 1) points nearest to i in scan order
+    // (sensor order keeps them close in space): each lane measures mb + 1 of
+    // them with the same arithmetic as the search below.
+    const int nseed = kQLanes * (mb + 1);
+    if (active && n - 1 >= nseed) {
+        const int start = max(0, min(i - nseed / 2, n - 1 - nseed));
+        float own = 0.0f;
+        for (int r = 0; r <= mb; ++r) {
+            int j = start + kQLanes * r + gl;
+            j += j >= i ? 1 : 0;
+            const float dx = xyz[3 * j] - pi.x, dy = xyz[3 * j + 1] - pi.y, dz = xyz[3 * j + 2] - pi.z;
+            own = fmaxf(own, __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz)));
+        }
+#pragma unroll
+        for (int off = kQLanes / 2; off >= 1; off >>= 1) own = fmaxf(own, __shfl_xor(own, off, 64));
+        bound = own;
+    }
     for (int base = 0; base < n; base += kPtsTile) {
         const int cnt = min(kPtsTile, n - base);
         __syncthreads();
@@ -98,29 +120,41 @@ __global__ __launch_bounds__(kB) void k_scan_knn_cov(const float* __restrict__ x
             tile[t] = make_float3(xyz[3 * (base + t)], xyz[3 * (base + t) + 1], xyz[3 * (base + t) + 2]);
         __syncthreads();
         if (!active) continue;
-        for (int t = gl; t < cnt; t += kQLanes) {
-            const int j = base + t;
-            if (j == i) continue;
-            const float3 pj = tile[t];
-            const float dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
-            const float d2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
-            if (d2 < bd[KC - 1]) {
+        for (int c0 = 0; c0 < cnt; c0 += kQLanes * kChunk) {
+            const int c1 = min(cnt, c0 + kQLanes * kChunk);
+            for (int t = c0 + gl; t < c1; t += kQLanes) {
+                const int j = base + t;
+                if (j == i) continue;
+                const float3 pj = tile[t];
+                const float dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
+                const float d2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
+                if (d2 < bd[KC - 1] && d2 <= bound) {
 #pragma unroll
-                for (int m = KC - 1; m >= 1; --m) {
-                    const bool sh = d2 < bd[m - 1];
-                    const bool here = d2 < bd[m];
-                    bd[m] = sh ? bd[m - 1] : (here ? d2 : bd[m]);
-                    bj[m] = sh ? bj[m - 1] : (here ? j : bj[m]);
-                }
-                if (d2 < bd[0]) {
-                    bd[0] = d2;
-                    bj[0] = j;
+                    for (int m = KC - 1; m >= 1; --m) {
+                        const bool sh = d2 < bd[m - 1];
+                        const bool here = d2 < bd[m];
+                        bd[m] = sh ? bd[m - 1] : (here ? d2 : bd[m]);
+                        bj[m] = sh ? bj[m - 1] : (here ? j : bj[m]);
+                    }
+                    if (d2 < bd[0]) {
+                        bd[0] = d2;
+                        bj[0] = j;
+                    }
                 }
             }
+            // Group bound: every lane holds at least mb + 1 distinct candidates
+            // at or below its bd[mb], so 16 (mb + 1) >= kk candidates lie at or
+            // below the maximum over the group, and so does every one of the
+            // final kk.  Candidates above it are never needed (same lists as
+            // without the bound for the entries the merge takes).
+            float own = mb >= 1 ? bd[1] : bd[0];
+#pragma unroll
+            for (int off = kQLanes / 2; off >= 1; off >>= 1) own = fmaxf(own, __shfl_xor(own, off, 64));
+            bound = fminf(bound, own);
         }
     }
     if (!active) return;
-    // merge: round r takes the smallest head of the 16 lists and pops it
+    // merge: round r takes the smallest head of the group's lists and pops it
     int nb[KC];
 #pragma unroll
     for (int r = 0; r < KC; ++r) {
