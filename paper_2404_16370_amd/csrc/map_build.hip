@@ -115,6 +115,9 @@ __device__ void jacobi_min_vec(double A[9], double nrm[3]) {
         const double off = A[1] * A[1] + A[2] * A[2] + A[5] * A[5];
         const double dg = A[0] * A[0] + A[4] * A[4] + A[8] * A[8];
         if (off <= 1e-300 || off <= 1e-34 * dg) break;
+        // unrolled: every index into A and V is a constant (registers, not
+        // private memory)
+#pragma unroll
         for (int pq = 0; pq < 3; ++pq) {
             const int p = pq == 2 ? 1 : 0;
             const int q = pq == 0 ? 1 : 2;
@@ -125,16 +128,19 @@ __device__ void jacobi_min_vec(double A[9], double nrm[3]) {
             const double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
             const double c = 1.0 / sqrt(t * t + 1.0);
             const double s = t * c;
+#pragma unroll
             for (int k = 0; k < 3; ++k) {
                 const double x = A[3 * k + p], y = A[3 * k + q];
                 A[3 * k + p] = c * x - s * y;
                 A[3 * k + q] = s * x + c * y;
             }
+#pragma unroll
             for (int k = 0; k < 3; ++k) {
                 const double x = A[3 * p + k], y = A[3 * q + k];
                 A[3 * p + k] = c * x - s * y;
                 A[3 * q + k] = s * x + c * y;
             }
+#pragma unroll
             for (int k = 0; k < 3; ++k) {
                 const double x = V[3 * k + p], y = V[3 * k + q];
                 V[3 * k + p] = c * x - s * y;
@@ -142,18 +148,13 @@ __device__ void jacobi_min_vec(double A[9], double nrm[3]) {
             }
         }
     }
-    const double ev[3] = {A[0], A[4], A[8]};
-    int o[3] = {0, 1, 2};
-    for (int i = 0; i < 3; ++i)
-        for (int j = i + 1; j < 3; ++j)
-            if (ev[o[j]] < ev[o[i]]) {
-                const int tmp = o[i];
-                o[i] = o[j];
-                o[j] = tmp;
-            }
-    nrm[0] = V[o[0]];
-    nrm[1] = V[3 + o[0]];
-    nrm[2] = V[6 + o[0]];
+    // smallest eigenvalue, the lowest index on ties
+    int m = 0;
+    if (A[4] < A[0]) m = 1;
+    if (A[8] < (m == 1 ? A[4] : A[0])) m = 2;
+    nrm[0] = m == 0 ? V[0] : (m == 1 ? V[1] : V[2]);
+    nrm[1] = m == 0 ? V[3] : (m == 1 ? V[4] : V[5]);
+    nrm[2] = m == 0 ? V[6] : (m == 1 ? V[7] : V[8]);
 }
 
 __global__ void k_voxel_stats(const float* __restrict__ xyz, const int32_t* __restrict__ order,
