@@ -134,6 +134,30 @@ def test_scan_covariances_k_bitexact(room, O, k, n):
     assert np.array_equal(got, cov)
 
 
+@pytest.mark.parametrize("k", [10, 20])
+def test_scan_covariances_ties_and_shuffled_bitexact(room, O, k):
+    # A lattice scan has many equal distances: the neighbour lists must break
+    # ties by the lower index exactly as the oracle does, also when the scan
+    # order carries no spatial locality (the search's pruning bound is then
+    # seeded from far-apart points) and with duplicated points (distance 0).
+    g = np.stack(np.meshgrid(np.arange(14), np.arange(11), np.arange(3), indexing="ij"), -1).reshape(-1, 3)
+    lat = (0.1 * g + np.array([2.0, -1.0, 0.5])).astype(np.float32)
+    rng = np.random.default_rng(77)
+    shuffled = lat[rng.permutation(len(lat))]
+    dup = np.concatenate([lat[:200], lat[:40]])[rng.permutation(240)]
+    room_shuffled = room["w"]["scans"][0][rng.permutation(len(room["w"]["scans"][0]))]
+    for name, scan in (("lattice", lat), ("lattice shuffled", shuffled), ("duplicates", dup),
+                       ("room shuffled", room_shuffled)):
+        scan = np.ascontiguousarray(scan, dtype=np.float32)
+        print("scan k-NN ties:", name, len(scan), "k", k, flush=True)
+        f = M.Filter(room["gpu"], _params(64, scan_k=k))
+        f.scan_upload(scan)
+        rec = f.debug_get("scan")
+        _, cov, _ = O.scan_cov(scan, k=k, eps=1e-3)
+        got = np.stack([rec[:, 3], rec[:, 4], rec[:, 5], rec[:, 6], rec[:, 7], rec[:, 8]], 1)
+        assert np.array_equal(got, cov), name
+
+
 def test_scan_upload_device_and_rejects(room, O):
     import torch
     w = room["w"]
