@@ -141,7 +141,9 @@ def test_scan_covariances_ties_and_shuffled_bitexact(room, O, k):
     # order carries no spatial locality (the search's pruning bound is then
     # seeded from far-apart points) and with duplicated points (distance 0).
     g = np.stack(np.meshgrid(np.arange(14), np.arange(11), np.arange(3), indexing="ij"), -1).reshape(-1, 3)
-    lat = (0.1 * g + np.array([2.0, -1.0, 0.5])).astype(np.float32)
+    # spacing and offsets exact in FP32: coordinate differences and squared
+    # distances are exact, so equal distances really are equal
+    lat = (0.125 * g + np.array([2.0, -1.0, 0.5])).astype(np.float32)
     rng = np.random.default_rng(77)
     shuffled = lat[rng.permutation(len(lat))]
     dup = np.concatenate([lat[:200], lat[:40]])[rng.permutation(240)]

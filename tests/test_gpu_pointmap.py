@@ -8,6 +8,8 @@ paper's nearest-point field) against the CPU oracle, through the C-ABI.
               search radius (1, 4)
   1e-4 rel    log-likelihoods, H and b of the likelihood on this map (both
               launch layouts), as for the per-voxel map
+  ties        a lattice (exactly equal distances), in scan and shuffled order:
+              an open gap, marked xfail (normals of about half the points differ)
   errors      HASH backend and out-of-range point_k / point_search rejected
 The map: the room scene subsampled to 40,000 points, 0.2 m cells, R = 2.
 """
@@ -68,6 +70,29 @@ def test_point_map_variants_bitexact(pm, O, k, search, minp):
     rng = np.random.default_rng(k)
     q = xyz[rng.choice(len(xyz), 20000)] + rng.normal(scale=0.1, size=(20000, 3)).astype(np.float32)
     assert np.array_equal(g.lookup(q), o.lookup(q))
+
+
+@pytest.mark.xfail(reason="open parity gap: on an exactly tied lattice the per-point normals of about half "
+                          "the points differ from the oracle's (points, voxels and counts agree; the oracle's "
+                          "lists match brute force); cause not yet found", strict=False)
+@pytest.mark.parametrize("shuffle", [False, True])
+def test_point_map_lattice_ties_bitexact(O, shuffle):
+    # a lattice with spacing and offsets exact in FP32: every point has many
+    # neighbours at exactly equal distances and every cell centre many
+    # equidistant points; both sides break ties by the lower index
+    g = np.stack(np.meshgrid(np.arange(30), np.arange(26), np.arange(6), indexing="ij"), -1).reshape(-1, 3)
+    xyz = (0.125 * g + np.array([1.0, -2.0, 0.25])).astype(np.float32)
+    if shuffle:
+        xyz = xyz[np.random.default_rng(5).permutation(len(xyz))]
+    xyz = np.ascontiguousarray(xyz)
+    print("lattice point map", len(xyz), "shuffled", shuffle, flush=True)
+    gm = M.Map(xyz, voxel=0.25, nnf_radius=2, min_points=5, gauss_mode=M.MP_GAUSS_POINT, point_k=10, point_search=2)
+    om = O.Map(xyz, 0.25, nnf_radius=2, min_points=5, per_point=True, point_k=10, point_search=2)
+    _same_gauss(gm, om)
+    rng = np.random.default_rng(9)
+    q = rng.uniform(xyz.min(0) - 0.6, xyz.max(0) + 0.6, size=(50000, 3)).astype(np.float32)
+    q[:20000] = (np.round(q[:20000] / 0.125) * 0.125).astype(np.float32)
+    assert np.array_equal(gm.lookup(q), om.lookup(q))
 
 
 def _poses_near(w, n, seed):
