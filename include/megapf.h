@@ -333,6 +333,9 @@ MP_API mp_status mp_stage_times(mp_filter f, float* ms_out, int32_t* counts_out)
  *   "psi"     N x 8 float (psi[6], loglik, inlier count as float)
  *   "hb"      N x 28 float (H upper 21 row-major, b 6, cost) of the last
  *             likelihood pass; only written after set "capture_hb" = 1
+ *   "solve"   N int32, how the last pass solved each psi (written with "hb"):
+ *             0 FP32 Cholesky, 1 FP64 re-solve (FP32 failed or its condition
+ *             estimate exceeded 1e6), 2 both failed (psi = 0)
  *   "codes"   N uint32 LSH codes of the last LSH pass (particle order)
  *   "sorted"  N int32 particle index at each sorted position
  *   "scodes"  N uint32 codes in sorted order
@@ -357,6 +360,17 @@ MP_API mp_status mp_debug_get(mp_filter f, const char* name, void* dst, int64_t 
 MP_API mp_status mp_debug_set(mp_filter f, const char* name, const void* src, int64_t bytes, void* stream);
 MP_API mp_status mp_debug_stage(mp_filter f, int32_t stage, int32_t iteration, const float dT[7], const float cov_dT[36],
                          void* stream);
+
+/* Test output of the per-point map construction (Sec. III-C, per-point
+ * Gaussians): builds a POINT map from xyz as mp_map_build does, writes each
+ * point's neighbour list, knn_out[i * point_k + a] = index of its a-th nearest
+ * other point in the order the build ranks them (FP32 squared distance, ties
+ * to the lower index), -1 pads, and frees the map.  xyz n x 3 float32 and
+ * knn_out n x point_k int32 are host or device pointers; synchronises.
+ * Errors: MP_E_ARG for a null pointer, n <= 0 or a gauss_mode other than
+ * POINT, and every error of mp_map_build. */
+MP_API mp_status mp_debug_map_point_knn(const float* xyz, int64_t n, const mp_map_params* params, int32_t* knn_out,
+                                        void* stream);
 
 /* ------------------------------------------------------------ batch */
 /* Several independent filters (instances: different maps, particle counts,
@@ -533,6 +547,7 @@ MP_API void mp_odometry_default_params(mp_odometry_params* p);
  * uploaded). */
 MP_API mp_status mp_odometry(mp_filter f, const mp_odometry_params* params, const float init_dT[7], float dT_out[7],
                              float cov_out[36], mp_odometry_result* result, void* stream);
+
 
 /* ------------------------------------------------------------ smoothing */
 

@@ -163,6 +163,34 @@ extern "C" mp_status mp_map_build(const float* xyz, int64_t n, const mp_map_para
     });
 }
 
+extern "C" mp_status mp_debug_map_point_knn(const float* xyz, int64_t n, const mp_map_params* params,
+                                            int32_t* knn_out, void* stream) {
+    return guarded("mp_debug_map_point_knn", [&]() {
+        if (!params || !knn_out || n <= 0 || !xyz) mp_throw(MP_E_ARG, "null argument or n <= 0");
+        if (params->gauss_mode != MP_GAUSS_POINT) mp_throw(MP_E_ARG, "gauss_mode must be POINT");
+        if (params->point_k < 3 || params->point_k > 32) mp_throw(MP_E_ARG, "point_k must be 3..32");
+        if (n > (int64_t)INT32_MAX) mp_throw(MP_E_UNSUPPORTED, "more than 2^31-1 map points");
+        hipStream_t s = as_stream(stream);
+        const size_t bytes = sizeof(int32_t) * (size_t)n * (size_t)params->point_k;
+        DevMem lists;
+        lists.alloc(bytes);
+        mp_map m = new mp_map_s();
+        m->params = *params;
+        m->knn_dbg = lists.as<int32_t>();
+        try {
+            DevMem tmp;
+            const float* d = static_cast<const float*>(stage_in(xyz, sizeof(float) * 3 * (size_t)n, tmp, s));
+            mp_build_map(m, d, n, s);
+            MP_HIP(hipMemcpyAsync(knn_out, lists.p, bytes, hipMemcpyDefault, s));
+            MP_HIP(hipStreamSynchronize(s));
+        } catch (...) {
+            delete m;
+            throw;
+        }
+        delete m;
+    });
+}
+
 extern "C" mp_status mp_map_get_info(mp_map map, mp_map_info* out) {
     return guarded("mp_map_get_info", [&]() {
         if (!map || !out) mp_throw(MP_E_ARG, "null argument");
@@ -707,6 +735,10 @@ static NamedBuf lookup_buf(mp_filter f, const char* name) {
         f->hb.ensure(28 * 4 * N);
         return {f->hb.p, 28 * 4 * N, false};
     }
+    if (s == "solve") {
+        f->solve_how.ensure(4 * N);
+        return {f->solve_how.p, 4 * N, false};
+    }
     if (s == "codes") return {f->codes.p, 4 * N, true};
     if (s == "sorted") return {f->sorted.p, 4 * N, true};
     if (s == "scodes") return {f->scodes.p, 4 * N, true};
@@ -746,6 +778,7 @@ extern "C" mp_status mp_debug_set(mp_filter f, const char* name, const void* src
             fetch_host(src, 4, &v, s);
             f->capture_hb = v ? 1 : 0;
             if (f->capture_hb) f->hb.ensure(28 * 4 * (size_t)f->n);
+            if (f->capture_hb) f->solve_how.ensure(4 * (size_t)f->n);
             return;
         }
         const NamedBuf b = lookup_buf(f, name);

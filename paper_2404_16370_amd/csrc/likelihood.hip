@@ -469,6 +469,7 @@ struct SolveArgs {
     float4* __restrict__ psi;   // N x 2 float4: (psi0..3), (psi4, psi5, loglik, inliers)
     float* __restrict__ hb;     // N x 28 or null
     int32_t* __restrict__ flags; // [0]: FP64 re-solves
+    int32_t* __restrict__ how;   // N or null: 0 FP32 Cholesky, 1 FP64 re-solve, 2 both failed
     int32_t n, nchunks, ns;
     float cmax, lam_rel, lam_abs;
 };
@@ -501,6 +502,7 @@ __global__ __launch_bounds__(256) void k_solve(SolveArgs A) {
     float kappa = 0.0f;
     bool ok = chol_solve6<float>(v, v + 21, A.lam_rel, A.lam_abs, psi, kappa);
     for (int m = 0; m < 6; ++m) ok = ok && isfinite(psi[m]);
+    int how = 0;
     if (!ok || kappa > 1.0e6f) {
         double H64[21], b64[6], p64[6], k64 = 0.0;
         for (int m = 0; m < 21; ++m) H64[m] = v[m];
@@ -508,7 +510,9 @@ __global__ __launch_bounds__(256) void k_solve(SolveArgs A) {
         const bool ok64 = chol_solve6<double>(H64, b64, (double)A.lam_rel, (double)A.lam_abs, p64, k64);
         for (int m = 0; m < 6; ++m) psi[m] = ok64 ? (float)p64[m] : 0.0f;
         atomicAdd(&A.flags[0], 1);
+        how = ok64 ? 1 : 2;
     }
+    if (A.how) A.how[i] = how;
     A.psi[2 * i] = make_float4(psi[0], psi[1], psi[2], psi[3]);
     A.psi[2 * i + 1] = make_float4(psi[4], psi[5], loglik, (float)A.ns - nout);
     if (A.hb) {
@@ -632,6 +636,7 @@ void mp_launch_likelihood(mp_filter f, hipStream_t s) {
     S.order = (grouped && ns > 0) ? f->sorted.as<int32_t>() : nullptr;
     S.psi = f->psi.as<float4>();
     S.hb = f->capture_hb ? f->hb.as<float>() : nullptr;
+    S.how = f->capture_hb ? f->solve_how.as<int32_t>() : nullptr;
     S.flags = f->flags.as<int32_t>();
     S.n = n;
     S.nchunks = nch;

@@ -231,7 +231,8 @@ __global__ __launch_bounds__(256) void k_point_gauss(const float* __restrict__ x
                                                     const int3* __restrict__ vox, const int32_t* __restrict__ occ,
                                                     int3 lo, int3 dims, int k, int S, float r, int32_t min_pts,
                                                     float gicp_a, float4* __restrict__ st_mu, float4* __restrict__ st_n,
-                                                    int3* __restrict__ st_vox, uint32_t* __restrict__ keep) {
+                                                    int3* __restrict__ st_vox, uint32_t* __restrict__ keep,
+                                                    int32_t* __restrict__ knn_out) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n) return;
     const int32_t i = order[t];
@@ -268,17 +269,20 @@ __global__ __launch_bounds__(256) void k_point_gauss(const float* __restrict__ x
                                     ez = xyz[3 * (int64_t)j + 2] - pz;
                         float d = __builtin_fmaf(ex, ex, __builtin_fmaf(ey, ey, ez * ez));
                         if (!knn_less(d, j, thd, thj)) continue;
-                        int32_t jj = j;
+                        // insertion into the sorted list by selects: slot a
+                        // takes the candidate if it ranks below the old entry
+                        // a and not below entry a - 1, else entry a - 1
+                        // (slots rewritten from the top, so a - 1 is still old)
+                        bool lt[KC];
 #pragma unroll
-                        for (int a = 0; a < KC; ++a) {
-                            if (knn_less(d, jj, bd[a], bj[a])) {
-                                const float td = bd[a];
-                                const int32_t tj = bj[a];
-                                bd[a] = d;
-                                bj[a] = jj;
-                                d = td;
-                                jj = tj;
-                            }
+                        for (int a = 0; a < KC; ++a) lt[a] = knn_less(d, j, bd[a], bj[a]);
+#pragma unroll
+                        for (int a = KC - 1; a >= 0; --a) {
+                            const bool up = a > 0 && lt[a > 0 ? a - 1 : 0];
+                            const float nd = up ? bd[a > 0 ? a - 1 : 0] : d;
+                            const int32_t nj = up ? bj[a > 0 ? a - 1 : 0] : j;
+                            bd[a] = lt[a] ? nd : bd[a];
+                            bj[a] = lt[a] ? nj : bj[a];
                         }
                         cnt = min(cnt + 1, k);
                         if (cnt == k) {
@@ -295,6 +299,11 @@ __global__ __launch_bounds__(256) void k_point_gauss(const float* __restrict__ x
             const float b = (float)sh * r - slop;
             if (b > 0.0f && thd < b * b) break;   // (b <= 0: cells too small for the bound; search on)
         }
+    }
+    if (knn_out) {   // test output: the list of point i, -1 pads
+#pragma unroll
+        for (int a = 0; a < KC; ++a)
+            if (a < k) knn_out[(int64_t)i * k + a] = a < cnt ? bj[a] : -1;
     }
     const int m = cnt + 1;
     st_vox[t] = v;
@@ -628,7 +637,7 @@ void mp_build_map(mp_map m, const float* xyz, int64_t n, hipStream_t s) {
             kern<<<nblk(n), kBlock, 0, s>>>(xyz, d_vals.as<int32_t>(), d_start.as<int32_t>(), (int64_t)nruns, n,
                                             d_vox.as<int3>(), occ.as<int32_t>(), lo, dims, P.point_k, P.point_search,
                                             r, P.min_points, 1.0f - P.cov_eps, st_mu.as<float4>(), st_n.as<float4>(),
-                                            st_vox.as<int3>(), keep.as<uint32_t>());
+                                            st_vox.as<int3>(), keep.as<uint32_t>(), m->knn_dbg);
         };
         if (P.point_k <= 8) launch(k_point_gauss<8>);
         else if (P.point_k <= 16) launch(k_point_gauss<16>);

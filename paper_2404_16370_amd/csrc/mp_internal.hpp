@@ -74,6 +74,7 @@ struct mp_map_s {
     DevMem gauss, dense, drec, table, vox;   // vox: G x int3 voxel coordinates
     float box_lo[3], box_hi[3];
     int users = 0;
+    int32_t* knn_dbg = nullptr;   // test output of the per-point build: n x point_k lists (device), or null
 };
 
 // ------------------------------------------------------------ surrogate
@@ -147,6 +148,7 @@ struct mp_filter_s {
     DevMem poses[2];          // N x 8 float
     DevMem psi;               // N x 8 float: psi[6], loglik, inliers
     DevMem hb;                // N x 28 float (debug)
+    DevMem solve_how;         // N int32 (debug): 0 FP32 Cholesky, 1 FP64 re-solve, 2 both failed (psi = 0)
     DevMem partial;           // chunks x 28 x N float
     DevMem codes, sorted, scodes, tmp_keys, tmp_vals, head, end, hist;  // LSH / sort
     DevMem rank;   // sorted position of each particle (the refresh runs in particle order)

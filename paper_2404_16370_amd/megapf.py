@@ -101,7 +101,7 @@ class mp_posterior(C.Structure):
 EXPORTS = ["mp_map_default_params", "mp_map_build", "mp_map_get_info", "mp_map_get_gauss", "mp_map_lookup",
            "mp_map_destroy", "mp_filter_default_params", "mp_filter_init", "mp_filter_destroy", "mp_scan_upload",
            "mp_filter_step", "mp_posterior_query", "mp_last_error", "mp_stage_times", "mp_debug_get",
-           "mp_debug_set", "mp_debug_stage", "mp_surrogate_default_params", "mp_surrogate_create",
+           "mp_debug_set", "mp_debug_stage", "mp_debug_map_point_knn", "mp_surrogate_default_params", "mp_surrogate_create",
            "mp_surrogate_destroy", "mp_surrogate_get_info", "mp_surrogate_label", "mp_surrogate_eval",
            "mp_surrogate_set_data", "mp_surrogate_train", "mp_surrogate_grad", "mp_surrogate_get_params",
            "mp_surrogate_set_params", "mp_filter_set_surrogate", "mp_filter_set_surrogate_check", "mp_odometry_default_params", "mp_odometry", "mp_smoother_default_params",
@@ -155,6 +155,7 @@ def lib():
     L.mp_debug_get.argtypes = [vp, C.c_char_p, vp, i64, vp]
     L.mp_debug_set.argtypes = [vp, C.c_char_p, vp, i64, vp]
     L.mp_debug_stage.argtypes = [vp, i32, i32, vp, vp, vp]
+    L.mp_debug_map_point_knn.argtypes = [vp, i64, C.POINTER(mp_map_params), vp, vp]
     L.mp_surrogate_default_params.argtypes = [C.POINTER(mp_surrogate_params)]
     L.mp_surrogate_default_params.restype = None
     L.mp_surrogate_create.argtypes = [vp, C.POINTER(mp_surrogate_params), vp, C.POINTER(vp)]
@@ -285,6 +286,20 @@ class Map:
         return res
 
 
+def debug_map_point_knn(xyz, voxel, point_k=10, point_search=2, nnf_radius=2, min_points=5, cov_eps=1e-3,
+                        stream=None):
+    """Neighbour lists of a per-point map build (mp_debug_map_point_knn):
+    n x point_k int32, ranked as the build ranks them, -1 pads."""
+    p = mp_map_default_params()
+    p.voxel, p.nnf_radius, p.min_points, p.cov_eps = voxel, nnf_radius, min_points, cov_eps
+    p.gauss_mode, p.point_k, p.point_search = MP_GAUSS_POINT, point_k, point_search
+    n = _nrows(xyz)
+    keep = []
+    out = np.zeros((n, point_k), np.int32)
+    _check(lib().mp_debug_map_point_knn(_ptr(xyz, np.float32, keep), n, C.byref(p), _ptr(out), _stream(stream)))
+    return out
+
+
 # ------------------------------------------------------------------ filter
 def mp_filter_default_params(**kw):
     p = mp_filter_params()
@@ -300,6 +315,7 @@ _DEBUG_LAYOUT = {  # name -> (dtype, shape as a function of (n, K, scan_n))
     "poses": (np.float32, lambda n, K, s: (n, 8)),
     "psi": (np.float32, lambda n, K, s: (n, 8)),
     "hb": (np.float32, lambda n, K, s: (n, 28)),
+    "solve": (np.int32, lambda n, K, s: (n,)),
     "codes": (np.uint32, lambda n, K, s: (n,)),
     "sorted": (np.int32, lambda n, K, s: (n,)),
     "scodes": (np.uint32, lambda n, K, s: (n,)),

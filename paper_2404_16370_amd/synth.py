@@ -582,9 +582,13 @@ WORKLOADS = {
     "campus": dict(scene=scene_campus, map_points=20_000_000, voxel=1.0, scan_points=8192, scan_sigma=0.03,
                    particles=1_048_576, k=16, lsh_bits=24, svgd_iters=10, frames=200, step=0.5, yaw_deg=5.0,
                    kidnap_frame=100),
+    # a short sequence in the room scene (moving sensor, 5 m teleport at frame 10)
+    "room_seq": dict(scene=scene_room, map_points=200_000, voxel=0.5, scan_points=1024, scan_sigma=0.02,
+                     particles=4096, k=8, lsh_bits=16, svgd_iters=10, frames=20, step=0.3, yaw_deg=5.0,
+                     kidnap_frame=10, kidnap_dist=5.0),
 }
 
-SEEDS = {"room": 1, "floor": 2, "campus": 3}
+SEEDS = {"room": 1, "floor": 2, "campus": 3, "room_seq": 11}
 
 
 def surrogate_samples(map_xyz, lo, hi, n, seed, sigma=0.25, uniform_frac=0.1) -> np.ndarray:

@@ -72,20 +72,36 @@ def test_point_map_variants_bitexact(pm, O, k, search, minp):
     assert np.array_equal(g.lookup(q), o.lookup(q))
 
 
-@pytest.mark.xfail(reason="open parity gap: on an exactly tied lattice the per-point normals of about half "
-                          "the points differ from the oracle's (points, voxels and counts agree; the oracle's "
-                          "lists match brute force; the same lattice jittered by 1 mm and its per-voxel map "
-                          "agree exactly, so exact distance ties trigger it); cause not yet found", strict=False)
-@pytest.mark.parametrize("shuffle", [False, True])
-def test_point_map_lattice_ties_bitexact(O, shuffle):
+def _tied_lattice(shuffle):
     # a lattice with spacing and offsets exact in FP32: every point has many
-    # neighbours at exactly equal distances and every cell centre many
-    # equidistant points; both sides break ties by the lower index
+    # neighbours at exactly equal distances, and half the lattice planes lie
+    # exactly on cell faces; both sides break ties by the lower index
     g = np.stack(np.meshgrid(np.arange(30), np.arange(26), np.arange(6), indexing="ij"), -1).reshape(-1, 3)
     xyz = (0.125 * g + np.array([1.0, -2.0, 0.25])).astype(np.float32)
     if shuffle:
         xyz = xyz[np.random.default_rng(5).permutation(len(xyz))]
-    xyz = np.ascontiguousarray(xyz)
+    return np.ascontiguousarray(xyz)
+
+
+@pytest.mark.parametrize("shuffle", [False, True])
+def test_point_map_lattice_lists_bitexact(O, shuffle):
+    # the ranked neighbour list of every point, as the device build forms it,
+    # against the oracle's (brute force over the voxel cube)
+    xyz = _tied_lattice(shuffle)
+    print("lattice lists", len(xyz), "shuffled", shuffle, flush=True)
+    dev = M.debug_map_point_knn(xyz, 0.25, point_k=10, point_search=2, nnf_radius=2, min_points=5)
+    om = O.Map(xyz, 0.25, nnf_radius=2, min_points=5, per_point=True, point_k=10, point_search=2, want_knn=True)
+    bad = np.nonzero((dev != om.knn).any(1))[0]
+    if len(bad):
+        i = int(bad[0])
+        print("first differing point", i, xyz[i], "device", dev[i], "oracle", om.knn[i], flush=True)
+    assert len(bad) == 0, "%d of %d lists differ" % (len(bad), len(xyz))
+
+
+@pytest.mark.parametrize("shuffle", [False, True])
+def test_point_map_lattice_ties_bitexact(O, shuffle):
+    # the whole per-point map of the tied lattice: Gaussians, normals, field
+    xyz = _tied_lattice(shuffle)
     print("lattice point map", len(xyz), "shuffled", shuffle, flush=True)
     gm = M.Map(xyz, voxel=0.25, nnf_radius=2, min_points=5, gauss_mode=M.MP_GAUSS_POINT, point_k=10, point_search=2)
     om = O.Map(xyz, 0.25, nnf_radius=2, min_points=5, per_point=True, point_k=10, point_search=2)
