@@ -548,6 +548,19 @@ MP_API void mp_odometry_default_params(mp_odometry_params* p);
 MP_API mp_status mp_odometry(mp_filter f, const mp_odometry_params* params, const float init_dT[7], float dT_out[7],
                              float cov_out[36], mp_odometry_result* result, void* stream);
 
+/* mp_odometry for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same computation and results, bit for bit, with its work arrays (per-point
+ * terms and matches, the pose state) in a fixed device area of 1.9 MB that
+ * the library holds on each device it runs on until the process ends; no
+ * hipMalloc, hipFree or allocating library call.  The filter's scans are the
+ * inputs, the host outputs as in mp_odometry.  The current scan may hold at
+ * most 16384 points (MP_E_ARG beyond).  Every call on a device shares that
+ * device's area: calls that overlap on one device (several host threads or
+ * streams) race and must be serialised by the caller.  Errors: those of
+ * mp_odometry. */
+MP_API mp_status mp_odometry_noalloc(mp_filter f, const mp_odometry_params* params, const float init_dT[7],
+                                     float dT_out[7], float cov_out[36], mp_odometry_result* result, void* stream);
 
 /* ------------------------------------------------------------ smoothing */
 

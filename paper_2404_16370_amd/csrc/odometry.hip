@@ -25,6 +25,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 #include "megapf.h"
 #include "mp_det.hpp"
@@ -264,7 +265,16 @@ struct OdoCall {
     float* cov_out;
     mp_odometry_result* res;
     hipStream_t s;
+    char* scratch;   // device address of the fixed work area, or null: the filter's buffers
 };
+
+// Layout of the work area: per-source-point terms, matches, then the pose state.
+constexpr size_t kNoAllocScan = 16384;   // largest current scan of mp_odometry_noalloc
+constexpr size_t kStateBytes = sizeof(double) * (8 + 66) + sizeof(float) * 8;
+constexpr size_t kScrNn = sizeof(float) * kOTerms * kNoAllocScan;
+constexpr size_t kScrState = kScrNn + sizeof(int32_t) * kNoAllocScan;
+constexpr size_t kScratchBytes = kScrState + kStateBytes;
+static_assert(kScrNn % 256 == 0 && kScrState % 256 == 0, "aligned sections");
 
 void odometry_impl(void* ctx) {
     OdoCall& c = *static_cast<OdoCall*>(ctx);
@@ -288,11 +298,26 @@ void odometry_impl(void* ctx) {
     }
     hipStream_t s = c.s;
     const int ns = f->scan_n, nt = f->prev_n;
-    f->odo_terms.ensure(sizeof(float) * kOTerms * (size_t)ns);
-    f->odo_nn.ensure(sizeof(int32_t) * (size_t)ns);
-    // state: pose64 (8 doubles), out (66 doubles), pose32 (8 floats)
-    f->odo_state.ensure(sizeof(double) * (8 + 66) + sizeof(float) * 8);
-    double* pose64 = f->odo_state.as<double>();
+    float* terms = nullptr;
+    int32_t* nn = nullptr;
+    double* pose64 = nullptr;
+    if (c.scratch) {
+        // the caller's fixed work area: no allocation
+        if ((size_t)ns > kNoAllocScan)
+            mp_throw(MP_E_ARG, "mp_odometry_noalloc: current scan of %d points exceeds its limit of %d", ns,
+                     (int)kNoAllocScan);
+        terms = reinterpret_cast<float*>(c.scratch);
+        nn = reinterpret_cast<int32_t*>(c.scratch + kScrNn);
+        pose64 = reinterpret_cast<double*>(c.scratch + kScrState);
+    } else {
+        f->odo_terms.ensure(sizeof(float) * kOTerms * (size_t)ns);
+        f->odo_nn.ensure(sizeof(int32_t) * (size_t)ns);
+        // state: pose64 (8 doubles), out (66 doubles), pose32 (8 floats)
+        f->odo_state.ensure(kStateBytes);
+        terms = f->odo_terms.as<float>();
+        nn = f->odo_nn.as<int32_t>();
+        pose64 = f->odo_state.as<double>();
+    }
     double* out = pose64 + 8;
     float* pose32 = reinterpret_cast<float*>(out + 66);
     double h_state[8 + 66];
@@ -307,8 +332,8 @@ void odometry_impl(void* ctx) {
     T.trec = f->prev_orig.as<float4>();
     T.srec = f->scan_orig.as<float4>();
     T.pose = pose32;
-    T.terms = f->odo_terms.as<float>();
-    T.nn = f->odo_nn.as<int32_t>();
+    T.terms = terms;
+    T.nn = nn;
     T.nt = nt;
     T.ns = ns;
     T.dmax2 = P.d_max * P.d_max;
@@ -352,6 +377,46 @@ void odometry_impl(void* ctx) {
 
 extern "C" mp_status mp_odometry(mp_filter f, const mp_odometry_params* params, const float init_dT[7], float dT_out[7],
                                  float cov_out[36], mp_odometry_result* result, void* stream) {
-    OdoCall c{f, params, init_dT, dT_out, cov_out, result, static_cast<hipStream_t>(stream)};
+    OdoCall c{f, params, init_dT, dT_out, cov_out, result, static_cast<hipStream_t>(stream), nullptr};
     return mp_guarded_call("mp_odometry", odometry_impl, &c);
+}
+
+// Work area of mp_odometry_noalloc (2.0 MB): one copy per device, held until
+// the process ends.  Host code never uses this name as an address: the device
+// address comes from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices] = {};
+
+// the device address of `scratch` on the current device (looked up on the
+// first call there)
+char* scratch_on_current_device() {
+    int dev = -1;
+    MP_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) mp_throw(MP_E_UNSUPPORTED, "device ordinal %d beyond %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        MP_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) mp_throw(MP_E_HIP, "hipGetSymbolAddress returned a null work area");
+        g_scratch_ptr[dev] = static_cast<char*>(p);
+    }
+    return g_scratch_ptr[dev];
+}
+
+void odometry_noalloc_impl(void* ctx) {
+    OdoCall& c = *static_cast<OdoCall*>(ctx);
+    c.scratch = scratch_on_current_device();
+    odometry_impl(ctx);
+}
+}  // namespace
+
+extern "C" mp_status mp_odometry_noalloc(mp_filter f, const mp_odometry_params* params, const float init_dT[7],
+                                         float dT_out[7], float cov_out[36], mp_odometry_result* result,
+                                         void* stream) {
+    OdoCall c{f, params, init_dT, dT_out, cov_out, result, static_cast<hipStream_t>(stream), nullptr};
+    return mp_guarded_call("mp_odometry_noalloc", odometry_noalloc_impl, &c);
 }

@@ -104,7 +104,7 @@ EXPORTS = ["mp_map_default_params", "mp_map_build", "mp_map_get_info", "mp_map_g
            "mp_debug_set", "mp_debug_stage", "mp_debug_map_point_knn", "mp_surrogate_default_params", "mp_surrogate_create",
            "mp_surrogate_destroy", "mp_surrogate_get_info", "mp_surrogate_label", "mp_surrogate_eval",
            "mp_surrogate_set_data", "mp_surrogate_train", "mp_surrogate_grad", "mp_surrogate_get_params",
-           "mp_surrogate_set_params", "mp_filter_set_surrogate", "mp_filter_set_surrogate_check", "mp_odometry_default_params", "mp_odometry", "mp_smoother_default_params",
+           "mp_surrogate_set_params", "mp_filter_set_surrogate", "mp_filter_set_surrogate_check", "mp_odometry_default_params", "mp_odometry", "mp_odometry_noalloc", "mp_smoother_default_params",
            "mp_smoother_create", "mp_smoother_push", "mp_smoother_destroy", "mp_batch_create", "mp_batch_step",
            "mp_batch_get_info", "mp_batch_destroy"]
 
@@ -173,6 +173,7 @@ def lib():
     L.mp_odometry_default_params.argtypes = [C.POINTER(mp_odometry_params)]
     L.mp_odometry_default_params.restype = None
     L.mp_odometry.argtypes = [vp, C.POINTER(mp_odometry_params), vp, vp, vp, C.POINTER(mp_odometry_result), vp]
+    L.mp_odometry_noalloc.argtypes = L.mp_odometry.argtypes
     L.mp_smoother_default_params.argtypes = [C.POINTER(mp_smoother_params)]
     L.mp_smoother_default_params.restype = None
     L.mp_smoother_create.argtypes = [C.POINTER(mp_smoother_params), C.POINTER(vp)]
@@ -394,10 +395,10 @@ class Filter:
         _check(lib().mp_filter_set_surrogate_check(self.handle, int(period), int(stride), float(threshold),
                                                    int(fallback)))
 
-    def odometry(self, init=None, stream=None, **kw):
-        """mp_odometry: dT (7), Sigma^dT (6 x 6) and the match's H, b, cost,
-        inliers between the last two non-empty scans; keywords override
-        mp_odometry_params fields"""
+    def odometry(self, init=None, stream=None, noalloc=False, **kw):
+        """mp_odometry (mp_odometry_noalloc with noalloc=True): dT (7),
+        Sigma^dT (6 x 6) and the match's H, b, cost, inliers between the last
+        two non-empty scans; keywords override mp_odometry_params fields"""
         p = mp_odometry_params()
         lib().mp_odometry_default_params(C.byref(p))
         for k, v in kw.items():
@@ -408,8 +409,9 @@ class Filter:
         dT = np.zeros(7, np.float32)
         cov = np.zeros(36, np.float32)
         res = mp_odometry_result()
-        _check(lib().mp_odometry(self.handle, C.byref(p), _ptr(init, np.float32, keep), _ptr(dT), _ptr(cov),
-                                 C.byref(res), _stream(stream)))
+        fn = lib().mp_odometry_noalloc if noalloc else lib().mp_odometry
+        _check(fn(self.handle, C.byref(p), _ptr(init, np.float32, keep), _ptr(dT), _ptr(cov), C.byref(res),
+                  _stream(stream)))
         return dict(dT=dT, cov=cov.reshape(6, 6), H21=np.array(res.H[:]), b=np.array(res.b[:]), cost=res.cost,
                     inliers=res.inliers, iterations=res.iterations, cov_ok=bool(res.cov_ok),
                     dT64=np.array(res.dT64[:]))
