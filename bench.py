@@ -31,11 +31,16 @@ TRAIN_MACS = 192 * 128 * 2 + 128 * 128 * 3        # matrix-core MACs per trainin
 PEAK_HBM = 8.0e12           # bytes/s
 # FP32 operations of one likelihood evaluation in k_lik (an fma counts 2):
 #   inlier:  transform 18, voxel key 3, residual and gate 8, R^T n and R^T e 30,
-#            C 15, adjugate/det/inverse 30, Omega e and cost 20, compensated add 4,
-#            b 15, B 27, H_ww 24, H_wv 9, H_vv 6                      = 209
+#            Sherman-Morrison Omega 39 (q = P u 15, u^T q 5, beta 4, Omega 15),
+#            Omega e and cost 20, cost add 1, b 18, [mu]x Omega 27, H_ww 24,
+#            H_wv 9, H_vv 12                                           = 209
 #   outlier: transform 18, voxel key 3 (+ residual and gate 8 on an NNF hit) = 21..29
 FLOPS_INLIER = 209
 FLOPS_OUTLIER = 21
+# the method's algorithmic count per evaluation (transform 18, rotate Sigma^M
+# 90, 3x3 inverse 46, residual and cost 45, H / b blocks 75, 28 accumulations)
+FLOPS_ALGORITHMIC = 300
+PEAK_FP32_UNPACKED = 78.6e12  # one non-packed wave64 FP32 FMA per four cycles per SIMD, 2.4 GHz
 GATHER_BYTES = 32           # one Gaussian record of the dense NNF per evaluation (the cell index is computed)
 
 WORKLOADS = {
@@ -397,14 +402,16 @@ def sequence_main(args):
 LAYOUT_NAMES = {0: "auto", 1: "particle", 2: "grouped"}
 
 
-def batch_main(args):
-    """32 independent filters on 4 scenes (2 room-type, 2 floor-type), N
-    log-uniform in [4096, 262144], scans of 1024..8192 points, stepped by one
-    graph replay per step; the same instances stepped one by one for reference."""
+def batch_leg(M, S, steps, warmup, scorers=("plain",), log_fn=None):
+    """The batched serving shape: 32 independent filters on 4 scenes (2 room-type
+    maps of 200k points, 2 floor-type maps of 2M points, 0.5 m voxels), N
+    log-uniform in [4096, 262144], scans of 1024..8192 points, 10 / 20 SVGD
+    iterations, stepped by one graph replay per step (the likelihood passes of
+    every iteration as one persistent tile-queue launch); the same instances
+    stepped one by one for reference.  With "surrogate" in `scorers` the same
+    32 instances run again with the network scorer (one untrained network per
+    scene: its cost does not depend on the weights)."""
     import torch
-    from paper_2404_16370_amd import megapf as M
-    from paper_2404_16370_amd import synth as S
-    torch.cuda.set_device(0)
     rng = np.random.default_rng(5000)
     scenes = []
     t0 = time.perf_counter()
@@ -416,51 +423,86 @@ def batch_main(args):
         scan = S.make_scan(sc, S.random_rotation(r), pos, 8192, 0.02 if kind == "room" else 0.03, seed + 300)
         m = M.Map(torch.from_numpy(xyz).cuda(), voxel=0.5)
         scenes.append(dict(kind=kind, scene=sc, map=m, scan=scan))
-    log("scenes built in %.1f s" % (time.perf_counter() - t0))
+    if log_fn:
+        log_fn("batch scenes built in %.1f s" % (time.perf_counter() - t0))
     n_inst = 32
     Ns = np.exp(rng.uniform(np.log(4096), np.log(262144), n_inst)).astype(np.int64)
     NSs = rng.integers(1024, 8193, n_inst)
-    filters = []
-    for i in range(n_inst):
-        sd = scenes[i % 4]
-        iters = 10 if sd["kind"] == "room" else 20
-        p = M.mp_filter_default_params(n_particles=int(Ns[i]), k=8 if sd["kind"] == "room" else 16,
-                                       lsh_bits=16 if sd["kind"] == "room" else 20, svgd_iters=iters, post_iters=10,
-                                       window_c=16 if sd["kind"] == "room" else 32, d_max=1.0, seed=6000 + i)
-        f = M.Filter(sd["map"], p, box=(sd["scene"].lo, sd["scene"].hi))
-        f.scan_upload(np.ascontiguousarray(sd["scan"][:int(NSs[i])]))
-        filters.append(f)
-    b = M.Batch(filters, autotune=True)
-    info = b.info()
-    evals = info["evals_per_step"]
-    for k in range(args.warmup):
-        b.step()
-    torch.cuda.synchronize()
-    log("batch warm-up done (%d captures)" % b.info()["captures"])
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        b.step()
-    torch.cuda.synchronize()
-    t_graph = (time.perf_counter() - t0) / args.steps
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        for f in filters:
-            f.step()
-    torch.cuda.synchronize()
-    t_seq = (time.perf_counter() - t0) / args.steps
-    res = {"metric": "batched multi-instance filter steps: particle-point evals/s across 32 instances",
-           "value": evals / t_graph, "unit": "evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-           "ms_per_step": 1e3 * t_graph, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": "f32", "data": "synthetic",
-           "config": {"workload": "batch: 32 filters on 2 room-type (200k points) and 2 floor-type (2M points) "
+    out = {"config": {"workload": "batch: 32 filters on 2 room-type (200k points) and 2 floor-type (2M points) "
                                   "maps, N log-uniform 4096..262144 (sum %d), scans 1024..8192 points, 10 / 20 "
                                   "SVGD iterations" % int(Ns.sum())},
-           "graph_step_ms": 1e3 * t_graph, "sequential_step_ms": 1e3 * t_seq, "speedup": t_seq / t_graph,
-           "evals_per_step": evals, "lik_batch": info["lik_batch"],
-           "lik_layout": [LAYOUT_NAMES.get(v, str(v)) for v in info["lik_layout"]],
-           "particles": [int(v) for v in Ns], "scan_points": [int(v) for v in NSs],
-           "captures": b.info()["captures"]}
-    b.close()
+           "particles": [int(v) for v in Ns], "scan_points": [int(v) for v in NSs]}
+    for scorer in scorers:
+        surs = [M.Surrogate(sd["map"], M.mp_surrogate_default_params(seed=31 + j)) for j, sd in enumerate(scenes)] \
+            if scorer == "surrogate" else None
+        filters = []
+        for i in range(n_inst):
+            sd = scenes[i % 4]
+            iters = 10 if sd["kind"] == "room" else 20
+            p = M.mp_filter_default_params(n_particles=int(Ns[i]), k=8 if sd["kind"] == "room" else 16,
+                                           lsh_bits=16 if sd["kind"] == "room" else 20, svgd_iters=iters,
+                                           post_iters=10, window_c=16 if sd["kind"] == "room" else 32, d_max=1.0,
+                                           seed=6000 + i,
+                                           scorer=M.MP_SCORER_SURROGATE if surs else M.MP_SCORER_PLAIN)
+            f = M.Filter(sd["map"], p, box=(sd["scene"].lo, sd["scene"].hi))
+            if surs:
+                f.set_surrogate(surs[i % 4])
+            f.scan_upload(np.ascontiguousarray(sd["scan"][:int(NSs[i])]))
+            filters.append(f)
+        b = M.Batch(filters, autotune=True)
+        for k in range(warmup):
+            b.step()
+        torch.cuda.synchronize()
+        info = b.info()
+        evals = info["evals_per_step"]
+        t0 = time.perf_counter()
+        for k in range(steps):
+            b.step()
+        torch.cuda.synchronize()
+        t_graph = (time.perf_counter() - t0) / steps
+        t0 = time.perf_counter()
+        for k in range(steps):
+            for f in filters:
+                f.step()
+        torch.cuda.synchronize()
+        t_seq = (time.perf_counter() - t0) / steps
+        out[scorer] = {"evals_per_s": evals / t_graph, "graph_step_ms": 1e3 * t_graph,
+                       "sequential_step_ms": 1e3 * t_seq, "speedup_vs_sequential": t_seq / t_graph,
+                       "evals_per_step": evals, "instances_in_queue": info["queued_instances"],
+                       "queue_gather_batch": info["queue_batch"], "queue_workgroups": info["queue_workgroups"],
+                       "queue_tiles_per_step": info["queue_tiles_per_step"],
+                       "lik_layout": [LAYOUT_NAMES.get(v, str(v)) for v in info["lik_layout"]],
+                       "captures": info["captures"]}
+        if log_fn:
+            log_fn("batch %s: %.1f ms per graph step, %.3g evals/s (%.1f ms stepped one by one)" % (
+                scorer, 1e3 * t_graph, evals / t_graph, 1e3 * t_seq))
+        b.close()
+        for f in filters:
+            if surs:
+                f.set_surrogate(None)
+            f.close()
+        if surs:
+            for su in surs:
+                su.close()
+    for sd in scenes:
+        sd["map"].close()
+    return out
+
+
+def batch_main(args):
+    """The batched serving shape with both scorers (see batch_leg)."""
+    import torch
+    from paper_2404_16370_amd import megapf as M
+    from paper_2404_16370_amd import synth as S
+    torch.cuda.set_device(0)
+    leg = batch_leg(M, S, args.steps, args.warmup, scorers=("plain", "surrogate"), log_fn=log)
+    res = {"metric": "batched multi-instance filter steps: particle-point evals/s across 32 instances",
+           "value": leg["plain"]["evals_per_s"], "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": leg["plain"]["graph_step_ms"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic", "config": leg["config"],
+           "plain": leg["plain"], "surrogate": leg["surrogate"],
+           "surrogate_vs_plain": leg["surrogate"]["evals_per_s"] / leg["plain"]["evals_per_s"],
+           "particles": leg["particles"], "scan_points": leg["scan_points"]}
     print(json.dumps(res), flush=True)
 
 
@@ -798,6 +840,8 @@ def main():
                     help="sequence: per-voxel Gaussians (0.5 m) or per-point Gaussians (0.1 m field)")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the leg timing the LSH tangent / tables and SVGD gradient / transport variants")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the leg stepping 32 filters of the batched serving shape (plain scorer)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 1 GiB device copy before timing (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -915,7 +959,11 @@ def main():
                      "frac": achieved / PEAK_FP32, "traffic": measured_traffic(args.workload),
                      "kernel": "k_lik_grp (grouped layout)", "launch_ms": t_launch * 1e3,
                      "logical_gather_GBps": evals_iter * GATHER_BYTES / t_launch / 1e9,
-                     "logical_gather_frac_of_hbm": evals_iter * GATHER_BYTES / t_launch / PEAK_HBM},
+                     "logical_gather_frac_of_hbm": evals_iter * GATHER_BYTES / t_launch / PEAK_HBM,
+                     "flops_per_eval": {"kernel_inlier": FLOPS_INLIER, "kernel_outlier": FLOPS_OUTLIER,
+                                        "algorithmic": FLOPS_ALGORITHMIC},
+                     "frac_at_algorithmic_flops": evals_iter * FLOPS_ALGORITHMIC / t_launch / PEAK_FP32,
+                     "frac_of_unpacked_fp32_peak": achieved / PEAK_FP32_UNPACKED},
         "posterior": {"map_weight": q["map_weight"], "n_eff": q["n_eff"], "sum_w": float(q["weights"].sum())},
         "paper_context": {"filter_steps_per_s": round(1000.0 / 90.8, 2), "hardware": "NVIDIA A100",
                           "note": "the paper's 1,048,576-particle indoor run (90.8 ms per frame); its scan size and "
@@ -934,6 +982,9 @@ def main():
                                 "device_bytes": minfo["device_bytes"], "d_max": 2.0 * wl["voxel"]}
         res["map_per_point"] = point_map_leg(M, xyz, wl, scans, odo)
     res["odometry"] = odometry_leg(M, m, w, scans, not args.no_cpu_baseline)
+    if not args.no_batch:
+        f.close()
+        res["batch"] = batch_leg(M, S, 2, 1, scorers=("plain",), log_fn=log)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(wl, w, w["scans"][-1], args.cpu_budget)
     print(json.dumps(res), flush=True)

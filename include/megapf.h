@@ -389,14 +389,26 @@ typedef struct {
     int32_t n_instances;
     int32_t captures;        /* graphs captured so far */
     int64_t evals_per_step;  /* particle-point evaluations of one batch step */
+    int32_t queued_instances;   /* instances whose likelihood runs in the tile queue (first iteration) */
+    int32_t queue_batch;        /* gather batch of the queue kernel */
+    int32_t queue_workgroups;   /* workgroups of the persistent launch */
+    int32_t pad;
+    int64_t queue_tiles_per_step; /* tiles (256 particles x 1024 scan points) per step through the queues */
 } mp_batch_info;
 
-/* autotune != 0 times the likelihood launch of each instance for every
- * (lik_layout, lik_batch) candidate (PARTICLE with 2, 4, 8, 16; GROUPED with
- * 2, 4, 8) and keeps the fastest in the instance's parameters (speed only:
- * the per-point arithmetic is the same; sums are ordered differently by the
- * two layouts).  Every filter needs a scan uploaded.  Errors: MP_E_ARG,
- * MP_E_STATE (no scan, a filter given twice, SURROGATE scorer without a network). */
+/* Instances with the PLAIN scorer on a dense-field map get lik_layout =
+ * GROUPED: in every correction iteration their likelihood passes run as one
+ * persistent launch (a fixed grid of workgroups taking tiles of 256 particles
+ * x 1024 scan points of all these instances, in instance order, from an
+ * atomic work queue); the other instances launch their own
+ * likelihood kernels on their branch.  autotune != 0 times the queue kernel
+ * for each gather batch (2, 4, 8) and keeps the fastest, and times the
+ * likelihood launch of every other PLAIN instance for each (lik_layout,
+ * lik_batch) candidate (PARTICLE with 2, 4, 8, 16; GROUPED with 2, 4, 8) and
+ * keeps the fastest in its parameters (speed only: the per-point arithmetic is
+ * the same; sums are ordered differently by the two layouts).  Every filter
+ * needs a scan uploaded.  Errors: MP_E_ARG, MP_E_STATE (no scan, a filter
+ * given twice, SURROGATE scorer without a network). */
 MP_API mp_status mp_batch_create(const mp_filter* filters, int32_t n, int32_t autotune, void* stream, mp_batch* out);
 
 /* One step of every instance.  dT: n x 7 (NULL: no prediction for any

@@ -577,7 +577,7 @@ void mp_reserve_step(mp_filter f) {
     f->hist.ensure(mp_radix_scratch_bytes(f->n));
 }
 
-void mp_step_launches(mp_filter f, bool pred, const float dq[7], const float L[36], bool noise, hipStream_t s) {
+void mp_step_begin(mp_filter f, bool pred, const float dq[7], const float L[36], bool noise, hipStream_t s) {
     mp_fill_u32(f->flags.p, 0u, 4, s);
     // a captured step always holds the prediction node; it reads whether to
     // predict from the step values
@@ -588,32 +588,47 @@ void mp_step_launches(mp_filter f, bool pred, const float dq[7], const float L[3
         mp_launch_predict(f, pred ? dq : ident, pred ? L : zero, pred && noise, s);
         mp_tick(f, MP_STAGE_PREDICT, false, s);
     }
-    if (f->scan_n > 0) {
-        // per iteration, in the order of Table II: neighbour list update
-        // (LSH, sort, refresh; once per hash table, table l of iteration it
-        // drawing with counter it * tables + l), likelihood evaluation,
-        // particle state update
-        const int tables = std::max(1, f->p.lsh_tables);
-        for (int it = 0; it < f->p.svgd_iters; ++it) {
-            for (int l = 0; l < tables; ++l)
-                for (int st : {MP_STAGE_LSH, MP_STAGE_SORT, MP_STAGE_REFRESH}) {
-                    mp_tick(f, st, true, s);
-                    run_stage(f, st, it * tables + l, s);
-                    mp_tick(f, st, false, s);
-                }
-            for (int st : {MP_STAGE_LIK, MP_STAGE_SVGD}) {
-                mp_tick(f, st, true, s);
-                run_stage(f, st, it, s);
-                mp_tick(f, st, false, s);
-            }
+}
+
+// per iteration, in the order of Table II: neighbour list update (LSH, sort,
+// refresh; once per hash table, table l of iteration it drawing with counter
+// it * tables + l), likelihood evaluation, particle state update
+void mp_step_iter_nbr(mp_filter f, int it, hipStream_t s) {
+    const int tables = std::max(1, f->p.lsh_tables);
+    for (int l = 0; l < tables; ++l)
+        for (int st : {MP_STAGE_LSH, MP_STAGE_SORT, MP_STAGE_REFRESH}) {
+            mp_tick(f, st, true, s);
+            run_stage(f, st, it * tables + l, s);
+            mp_tick(f, st, false, s);
         }
-        if (f->p.svgd_iters > 0 && f->p.final_rescore) rescore(f, s);
-        if (f->p.svgd_iters > 0) {
-            mp_tick(f, MP_STAGE_POSTERIOR, true, s);
-            mp_launch_posterior(f, s);
-            mp_tick(f, MP_STAGE_POSTERIOR, false, s);
+}
+
+void mp_step_iter_svgd(mp_filter f, int it, hipStream_t s) {
+    mp_tick(f, MP_STAGE_SVGD, true, s);
+    run_stage(f, MP_STAGE_SVGD, it, s);
+    mp_tick(f, MP_STAGE_SVGD, false, s);
+}
+
+void mp_step_end(mp_filter f, hipStream_t s) {
+    if (f->scan_n <= 0 || f->p.svgd_iters <= 0) return;
+    if (f->p.final_rescore) rescore(f, s);
+    mp_tick(f, MP_STAGE_POSTERIOR, true, s);
+    mp_launch_posterior(f, s);
+    mp_tick(f, MP_STAGE_POSTERIOR, false, s);
+}
+
+void mp_step_launches(mp_filter f, bool pred, const float dq[7], const float L[36], bool noise, hipStream_t s) {
+    mp_step_begin(f, pred, dq, L, noise, s);
+    if (f->scan_n > 0) {
+        for (int it = 0; it < f->p.svgd_iters; ++it) {
+            mp_step_iter_nbr(f, it, s);
+            mp_tick(f, MP_STAGE_LIK, true, s);
+            run_stage(f, MP_STAGE_LIK, it, s);
+            mp_tick(f, MP_STAGE_LIK, false, s);
+            mp_step_iter_svgd(f, it, s);
         }
     }
+    mp_step_end(f, s);
 }
 
 extern "C" mp_status mp_filter_step(mp_filter f, const float dT[7], const float cov_dT[36], void* stream) {

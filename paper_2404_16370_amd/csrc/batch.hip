@@ -42,6 +42,14 @@ struct mp_batch_s {
     };
     std::vector<Shape> shape;
     int32_t captures = 0;
+    // persistent likelihood: per iteration one tile queue over the instances
+    // whose pass is GROUPED / PLAIN; tables written after each capture
+    std::vector<hipEvent_t> pre;        // per instance: its lists are ready
+    hipEvent_t lik_done = nullptr;
+    DevMem qtab, qfirst, qcount;        // [round][instance] args, [round][instance + 1] first tiles, [round] counters
+    int32_t qbatch = 2, qgrid = 0;      // gather batch and workgroups of the queue kernel
+    int32_t queued = 0;                 // instances in the queue of the first round
+    int64_t queue_tiles = 0;            // tiles per step through the queues
 };
 
 namespace {
@@ -52,6 +60,8 @@ void release(mp_batch b) {
     for (hipStream_t s : b->branch) (void)hipStreamDestroy(s);
     if (b->cap) (void)hipStreamDestroy(b->cap);
     for (hipEvent_t e : b->join) (void)hipEventDestroy(e);
+    for (hipEvent_t e : b->pre) (void)hipEventDestroy(e);
+    if (b->lik_done) (void)hipEventDestroy(b->lik_done);
     if (b->fork) (void)hipEventDestroy(b->fork);
     if (b->uploaded) (void)hipEventDestroy(b->uploaded);
     if (b->host_dyn) (void)hipHostFree(b->host_dyn);
@@ -96,21 +106,83 @@ void capture(mp_batch b, hipStream_t caller) {
         b->graph = nullptr;
     }
     b->shape.clear();
+    const size_t n = b->f.size();
+    int rounds = 0;
+    for (mp_filter f : b->f)
+        if (f->scan_n > 0) rounds = std::max(rounds, f->p.svgd_iters);
+    const size_t argb = mp_lik_args_bytes();
+    b->qtab.ensure(std::max<size_t>(1, (size_t)rounds * n) * argb);
+    b->qfirst.ensure(sizeof(int32_t) * std::max<size_t>(1, (size_t)rounds * (n + 1)));
+    b->qcount.ensure(sizeof(int32_t) * std::max(1, rounds));
+    if (b->qgrid <= 0) b->qgrid = mp_lik_queue_grid(b->qbatch);
+    std::vector<char> htab((size_t)rounds * n * argb);
+    std::vector<int32_t> hfirst((size_t)rounds * (n + 1), 0);
+    std::vector<int> start(n);
+    for (size_t i = 0; i < n; ++i) start[i] = b->f[i]->cur;
+    b->queued = 0;
+    b->queue_tiles = 0;
     MP_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     try {
         MP_HIP(hipEventRecord(b->fork, s));
-        for (size_t i = 0; i < b->f.size(); ++i) {
+        for (size_t i = 0; i < n; ++i) {
             mp_filter f = b->f[i];
-            hipStream_t bs = b->branch[i];
-            MP_HIP(hipStreamWaitEvent(bs, b->fork, 0));
-            const int start = f->cur;
+            MP_HIP(hipStreamWaitEvent(b->branch[i], b->fork, 0));
+            start[i] = f->cur;
             b->shape.push_back(shape_of(f));
             f->capturing = true;
             f->dyn = b->dyn.as<StepDyn>() + i;
-            mp_step_launches(f, false, nullptr, nullptr, false, bs);
-            if (f->cur != start) {
-                mp_copy_poses(f, f->cur, start, bs);
-                f->cur = start;
+            mp_step_begin(f, false, nullptr, nullptr, false, b->branch[i]);
+        }
+        // the correction iterations in lock step: every instance's lists, then
+        // one persistent launch over the tiles of all queued likelihood passes,
+        // then each instance's solve and SVGD update
+        for (int it = 0; it < rounds; ++it) {
+            std::vector<size_t> queued;
+            int32_t tiles = 0;
+            for (size_t i = 0; i < n; ++i) {
+                mp_filter f = b->f[i];
+                if (f->scan_n <= 0 || it >= f->p.svgd_iters) continue;
+                hipStream_t bs = b->branch[i];
+                mp_step_iter_nbr(f, it, bs);
+                int32_t t = 0;
+                char* slot = htab.data() + ((size_t)it * n + queued.size()) * argb;
+                if (mp_lik_queue_plan(f, slot, &t)) {
+                    hfirst[(size_t)it * (n + 1) + queued.size()] = tiles;
+                    tiles += t;
+                    queued.push_back(i);
+                    MP_HIP(hipEventRecord(b->pre[i], bs));
+                    MP_HIP(hipStreamWaitEvent(s, b->pre[i], 0));
+                } else {
+                    mp_launch_likelihood(f, bs);
+                }
+            }
+            if (!queued.empty()) {
+                int32_t* counter = b->qcount.as<int32_t>() + it;
+                mp_fill_u32(counter, 0u, 1, s);
+                mp_launch_lik_queue(b->qtab.as<char>() + (size_t)it * n * argb,
+                                    b->qfirst.as<int32_t>() + (size_t)it * (n + 1), counter, (int)queued.size(),
+                                    tiles, b->qbatch, b->qgrid, s);
+                MP_HIP(hipEventRecord(b->lik_done, s));
+                for (size_t i : queued) {
+                    MP_HIP(hipStreamWaitEvent(b->branch[i], b->lik_done, 0));
+                    mp_lik_queue_solve(b->f[i], b->branch[i]);
+                }
+                if (it == 0) b->queued = (int32_t)queued.size();
+                b->queue_tiles += tiles;
+            }
+            for (size_t i = 0; i < n; ++i) {
+                mp_filter f = b->f[i];
+                if (f->scan_n <= 0 || it >= f->p.svgd_iters) continue;
+                mp_step_iter_svgd(f, it, b->branch[i]);
+            }
+        }
+        for (size_t i = 0; i < n; ++i) {
+            mp_filter f = b->f[i];
+            hipStream_t bs = b->branch[i];
+            mp_step_end(f, bs);
+            if (f->cur != start[i]) {
+                mp_copy_poses(f, f->cur, start[i], bs);
+                f->cur = start[i];
             }
             f->capturing = false;
             f->dyn = nullptr;
@@ -118,9 +190,10 @@ void capture(mp_batch b, hipStream_t caller) {
             MP_HIP(hipStreamWaitEvent(s, b->join[i], 0));
         }
     } catch (...) {
-        for (mp_filter f : b->f) {
-            f->capturing = false;
-            f->dyn = nullptr;
+        for (size_t i = 0; i < n; ++i) {
+            b->f[i]->capturing = false;
+            b->f[i]->dyn = nullptr;
+            b->f[i]->cur = start[i];
         }
         hipGraph_t g = nullptr;
         (void)hipStreamEndCapture(s, &g);
@@ -130,6 +203,13 @@ void capture(mp_batch b, hipStream_t caller) {
     }
     MP_HIP(hipStreamEndCapture(s, &b->graph));
     MP_HIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    // the queue tables hold pointers and sizes that stay fixed while the graph does
+    if (rounds > 0) {
+        MP_HIP(hipMemcpyAsync(b->qtab.p, htab.data(), htab.size(), hipMemcpyHostToDevice, caller));
+        MP_HIP(hipMemcpyAsync(b->qfirst.p, hfirst.data(), sizeof(int32_t) * hfirst.size(), hipMemcpyHostToDevice,
+                              caller));
+        MP_HIP(hipStreamSynchronize(caller));
+    }
     b->captures++;
 }
 
@@ -178,6 +258,63 @@ void autotune(mp_filter f, hipStream_t s) {
     (void)hipEventDestroy(e1);
 }
 
+bool queue_eligible(mp_filter f) {
+    return f->p.scorer == MP_SCORER_PLAIN && f->map->view.backend == MP_NNF_DENSE;
+}
+
+// time the persistent likelihood over the instances' current passes for each
+// gather batch and keep the fastest (speed only: a lane's points and their
+// order are the same for every batch)
+void tune_queue(mp_batch b, hipStream_t s) {
+    const size_t n = b->f.size(), argb = mp_lik_args_bytes();
+    std::vector<char> tab(n * argb);
+    std::vector<int32_t> first(n + 1, 0);
+    int32_t tiles = 0, q = 0;
+    for (mp_filter f : b->f) {
+        int32_t t = 0;
+        if (mp_lik_queue_plan(f, tab.data() + (size_t)q * argb, &t)) {
+            first[q++] = tiles;
+            tiles += t;
+        }
+    }
+    if (q == 0) return;
+    DevMem dtab, dfirst, dcnt;
+    dtab.alloc(tab.size());
+    dfirst.alloc(sizeof(int32_t) * first.size());
+    dcnt.alloc(sizeof(int32_t));
+    MP_HIP(hipMemcpyAsync(dtab.p, tab.data(), tab.size(), hipMemcpyHostToDevice, s));
+    MP_HIP(hipMemcpyAsync(dfirst.p, first.data(), sizeof(int32_t) * first.size(), hipMemcpyHostToDevice, s));
+    hipEvent_t e0, e1;
+    MP_HIP(hipEventCreate(&e0));
+    MP_HIP(hipEventCreate(&e1));
+    float best = 1e30f;
+    try {
+        for (int batch : {2, 4, 8}) {
+            const int grid = mp_lik_queue_grid(batch);
+            for (int rep = 0; rep < 3; ++rep) {   // the first is a warm-up
+                if (rep == 1) MP_HIP(hipEventRecord(e0, s));
+                mp_fill_u32(dcnt.p, 0u, 1, s);
+                mp_launch_lik_queue(dtab.p, dfirst.as<int32_t>(), dcnt.as<int32_t>(), q, tiles, batch, grid, s);
+            }
+            MP_HIP(hipEventRecord(e1, s));
+            MP_HIP(hipEventSynchronize(e1));
+            float ms = 0.0f;
+            MP_HIP(hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best) {
+                best = ms;
+                b->qbatch = batch;
+                b->qgrid = grid;
+            }
+        }
+    } catch (...) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        throw;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+}
+
 }  // namespace
 
 mp_status mp_guarded_call(const char* where, void (*fn)(void*), void* ctx);
@@ -209,15 +346,26 @@ void create_impl(void* p) {
             hipEvent_t e;
             MP_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
             b->join.push_back(e);
+            MP_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+            b->pre.push_back(e);
         }
         MP_HIP(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
         MP_HIP(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming));
         MP_HIP(hipEventCreateWithFlags(&b->uploaded, hipEventDisableTiming));
+        MP_HIP(hipEventCreateWithFlags(&b->lik_done, hipEventDisableTiming));
         MP_HIP(hipHostMalloc(reinterpret_cast<void**>(&b->host_dyn), sizeof(StepDyn) * (size_t)c.n,
                              hipHostMallocDefault));
         b->dyn.alloc(sizeof(StepDyn) * (size_t)c.n);
-        if (c.tune)
-            for (mp_filter f : b->f) autotune(f, c.s);
+        // PLAIN instances on dense maps take the GROUPED layout, so that their
+        // likelihood passes join the persistent tile queue; the others keep
+        // their own launches (autotuned per instance)
+        for (mp_filter f : b->f)
+            if (queue_eligible(f)) f->p.lik_layout = MP_LIK_LAYOUT_GROUPED;
+        if (c.tune) {
+            for (mp_filter f : b->f)
+                if (!queue_eligible(f)) autotune(f, c.s);
+            tune_queue(b, c.s);
+        }
         MP_HIP(hipStreamSynchronize(c.s));
     } catch (...) {
         release(b);
@@ -313,6 +461,10 @@ void info_impl(void* p) {
         if (c.ll) c.ll[i] = f->p.lik_layout;
     }
     c.out->evals_per_step = ev;
+    c.out->queued_instances = c.b->queued;
+    c.out->queue_batch = c.b->qbatch;
+    c.out->queue_workgroups = c.b->qgrid;
+    c.out->queue_tiles_per_step = c.b->queue_tiles;
 }
 void destroy_impl(void* p) {
     mp_batch b = static_cast<mp_batch>(p);

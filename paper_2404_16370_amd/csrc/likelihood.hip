@@ -28,6 +28,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 
 #include "mp_det.hpp"
 #include "mp_internal.hpp"
@@ -355,13 +356,11 @@ constexpr int kGChunk = 1024;
 constexpr int kGThreads = 512;
 constexpr int kGParticles = 256;
 
+// One tile of the grouped layout: scan chunk `chunk` (kGChunk points) against
+// the kGParticles particles of sorted block `pblk`; the whole workgroup takes
+// part (it stages the chunk in `tile`).
 template <int BACKEND, int BATCH, int SC>
-__global__ __launch_bounds__(kGThreads) void k_lik_grp(LikArgs A) {
-    __shared__ float4 tile[kGChunk * 3];
-    const int nb = A.nbx * A.nchunks;
-    const int logical = remap_xcd(blockIdx.x, nb);
-    const int chunk = logical / A.nbx;
-    const int pblk = logical - chunk * A.nbx;
+__device__ __forceinline__ void grp_tile(const LikArgs& A, const int chunk, const int pblk, float4* tile) {
     const int k0 = chunk * kGChunk;
     const int cnt = min(kGChunk, A.ns - k0);
     // the whole chunk is staged; records past the scan's end are zero (a
@@ -447,6 +446,60 @@ __global__ __launch_bounds__(kGThreads) void k_lik_grp(LikArgs A) {
 #pragma unroll
             for (int m = 0; m < kNumPartial; ++m) out[(size_t)m * A.n] = v[m];
         }
+    }
+}
+
+template <int BACKEND, int BATCH, int SC>
+__global__ __launch_bounds__(kGThreads) void k_lik_grp(LikArgs A) {
+    __shared__ float4 tile[kGChunk * 3];
+    const int nb = A.nbx * A.nchunks;
+    const int logical = remap_xcd(blockIdx.x, nb);
+    const int chunk = logical / A.nbx;
+    grp_tile<BACKEND, BATCH, SC>(A, chunk, logical - chunk * A.nbx, tile);
+}
+
+// Persistent likelihood over the tiles of several filters (one pass each,
+// dense field maps): a fixed grid of workgroups takes tiles from a queue (an
+// atomic counter, zero at launch) until none is left.  Tile t belongs to the last instance whose
+// first tile is <= t; within an instance, tiles run chunk-major as in
+// k_lik_grp.  Results equal k_lik_grp's on each instance bit for bit (same
+// tile arithmetic, same partial layout).
+struct LikQueueArgs {
+    const LikArgs* __restrict__ tab;    // per instance
+    const int32_t* __restrict__ first;  // first tile of each instance (ascending)
+    int32_t* __restrict__ counter;      // next tile to take
+    int32_t n_inst, tiles;
+};
+
+template <int BATCH>
+__global__ __launch_bounds__(kGThreads) void k_lik_queue(LikQueueArgs Q) {
+    __shared__ float4 tile[kGChunk * 3];
+    __shared__ int32_t next;
+    for (;;) {
+        if (threadIdx.x == 0) next = atomicAdd(Q.counter, 1);
+        __syncthreads();
+        const int t = __builtin_amdgcn_readfirstlane(next);
+        __syncthreads();   // `next` is read by every wave before thread 0 overwrites it
+        if (t >= Q.tiles) break;
+        int lo = 0, hi = Q.n_inst - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (Q.first[mid] <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        // the table is read-only while the kernel runs: its words are read
+        // through the constant address space, so that the uniform arguments
+        // land in scalar registers
+        typedef const __attribute__((address_space(4))) uint32_t ConstWord;
+        static_assert(sizeof(LikArgs) % 4 == 0, "word copy");
+        LikArgs A;
+        ConstWord* src = (ConstWord*)(Q.tab + lo);
+        uint32_t* dst = reinterpret_cast<uint32_t*>(&A);
+#pragma unroll
+        for (int wd = 0; wd < (int)(sizeof(LikArgs) / 4); ++wd) dst[wd] = src[wd];
+        const int local = t - Q.first[lo];
+        const int chunk = local / A.nbx;
+        grp_tile<MP_NNF_DENSE, BATCH, MP_SCORER_PLAIN>(A, chunk, local - chunk * A.nbx, tile);
     }
 }
 
@@ -556,19 +609,30 @@ size_t mp_lik_partial_bytes(mp_filter f) {
     return sizeof(float) * (size_t)kNumPartial * (size_t)nch * (size_t)f->n;
 }
 
-void mp_launch_likelihood(mp_filter f, hipStream_t s) {
-    // the scorer of this step: SURROGATE runs as PLAIN while its check has it fall back
-    const int scorer = (f->p.scorer == MP_SCORER_SURROGATE && f->sur_fallback) ? (int)MP_SCORER_PLAIN : f->p.scorer;
+namespace {
+// arguments of one likelihood pass on the filter's current state
+struct LikPlan {
+    LikArgs A;
+    int scorer;    // of this pass: SURROGATE runs as PLAIN while its check has it fall back
+    int nch;       // scan chunks (partials per particle)
+    bool grouped;  // GROUPED layout: partials indexed by sorted position
+};
+
+LikPlan lik_plan(mp_filter f) {
+    LikPlan P;
+    P.scorer = (f->p.scorer == MP_SCORER_SURROGATE && f->sur_fallback) ? (int)MP_SCORER_PLAIN : f->p.scorer;
+    if (P.scorer == MP_SCORER_SURROGATE && !f->sur)
+        mp_throw(MP_E_STATE, "SURROGATE scorer without a network (mp_filter_set_surrogate)");
     const int n = f->n;
     const int ns = f->scan_n;
-    const bool grouped = lik_grouped(f) && scorer != MP_SCORER_SURROGATE;
-    const int nbx = grouped ? (n + kGParticles - 1) / kGParticles : (n + kLanes - 1) / kLanes;
+    P.grouped = lik_grouped(f) && P.scorer != MP_SCORER_SURROGATE;
+    const int nbx = P.grouped ? (n + kGParticles - 1) / kGParticles : (n + kLanes - 1) / kLanes;
     int clen = 0;
-    int nch = lik_chunks(f, clen);
-    f->lik_chunks = nch;
+    P.nch = lik_chunks(f, clen);
+    f->lik_chunks = P.nch;
     f->lik_chunk_len = clen;
     f->partial.ensure(mp_lik_partial_bytes(f));
-    LikArgs A;
+    LikArgs& A = P.A;
     A.map = f->map->view;
     A.poses = f->poses[f->cur].as<float4>();
     A.order = f->sorted.as<int32_t>();
@@ -577,7 +641,7 @@ void mp_launch_likelihood(mp_filter f, hipStream_t s) {
     A.n = n;
     A.ns = ns;
     A.chunk_len = std::max(1, clen);
-    A.nchunks = nch;
+    A.nchunks = P.nch;
     A.nbx = nbx;
     A.dmax2 = f->p.d_max * f->p.d_max;
     A.cmax = f->p.c_max;
@@ -585,8 +649,40 @@ void mp_launch_likelihood(mp_filter f, hipStream_t s) {
     A.ib = 1.0f / (1.0f + A.sig2);
     A.r_floor = 1e-2f;
     A.r_out = mp_residual_r_out(f->p.d_max, f->p.sigma_s, f->map->params.cov_eps);
-    if (scorer == MP_SCORER_SURROGATE && !f->sur)
-        mp_throw(MP_E_STATE, "SURROGATE scorer without a network (mp_filter_set_surrogate)");
+    return P;
+}
+
+// psi, log-likelihood and inliers from the pass's chunk partials
+void lik_solve(mp_filter f, bool grouped, int nch, hipStream_t s) {
+    const int n = f->n;
+    const int ns = f->scan_n;
+    SolveArgs S;
+    S.partial = f->partial.as<float>();
+    S.order = (grouped && ns > 0) ? f->sorted.as<int32_t>() : nullptr;
+    S.psi = f->psi.as<float4>();
+    S.hb = f->capture_hb ? f->hb.as<float>() : nullptr;
+    S.how = f->capture_hb ? f->solve_how.as<int32_t>() : nullptr;
+    S.flags = f->flags.as<int32_t>();
+    S.n = n;
+    S.nchunks = nch;
+    S.ns = ns;
+    S.cmax = f->p.c_max;
+    S.lam_rel = f->p.lambda_rel;
+    S.lam_abs = f->p.lambda_abs;
+    k_solve<<<(n + 255) / 256, 256, 0, s>>>(S);
+    MP_CHECK_LAUNCH();
+}
+}  // namespace
+
+void mp_launch_likelihood(mp_filter f, hipStream_t s) {
+    LikPlan P = lik_plan(f);
+    const LikArgs& A = P.A;
+    const int scorer = P.scorer;
+    const int n = f->n;
+    const int ns = f->scan_n;
+    const bool grouped = P.grouped;
+    const int nbx = A.nbx;
+    int nch = P.nch;
     if (ns > 0 && scorer == MP_SCORER_SURROGATE) {
         nch = 1;
         f->lik_chunks = 1;
@@ -631,19 +727,53 @@ void mp_launch_likelihood(mp_filter f, hipStream_t s) {
         mp_fill_u32(A.partial, 0u, (size_t)kNumPartial * n, s);
         nch = 1;
     }
-    SolveArgs S;
-    S.partial = f->partial.as<float>();
-    S.order = (grouped && ns > 0) ? f->sorted.as<int32_t>() : nullptr;
-    S.psi = f->psi.as<float4>();
-    S.hb = f->capture_hb ? f->hb.as<float>() : nullptr;
-    S.how = f->capture_hb ? f->solve_how.as<int32_t>() : nullptr;
-    S.flags = f->flags.as<int32_t>();
-    S.n = n;
-    S.nchunks = nch;
-    S.ns = ns;
-    S.cmax = f->p.c_max;
-    S.lam_rel = f->p.lambda_rel;
-    S.lam_abs = f->p.lambda_abs;
-    k_solve<<<(n + 255) / 256, 256, 0, s>>>(S);
+    lik_solve(f, grouped, nch, s);
+}
+
+// ------------------------------------------------------------ tile queue
+size_t mp_lik_args_bytes() { return sizeof(LikArgs); }
+
+bool mp_lik_queue_plan(mp_filter f, void* args_out, int32_t* tiles) {
+    if (f->scan_n <= 0) return false;
+    const LikPlan P = lik_plan(f);
+    if (!P.grouped || P.scorer != MP_SCORER_PLAIN || P.A.map.backend != MP_NNF_DENSE) return false;
+    std::memcpy(args_out, &P.A, sizeof(LikArgs));
+    *tiles = P.A.nbx * P.nch;
+    return true;
+}
+
+void mp_lik_queue_solve(mp_filter f, hipStream_t s) {
+    const LikPlan P = lik_plan(f);
+    lik_solve(f, P.grouped, P.nch, s);
+}
+
+static int queue_batch(int batch) { return batch == 8 ? 8 : (batch == 4 ? 4 : 2); }
+
+int mp_lik_queue_grid(int batch) {
+    int dev = 0, cus = 0, per_cu = 0;
+    MP_HIP(hipGetDevice(&dev));
+    MP_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    switch (queue_batch(batch)) {
+        case 8: MP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_lik_queue<8>, kGThreads, 0)); break;
+        case 4: MP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_lik_queue<4>, kGThreads, 0)); break;
+        default: MP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_lik_queue<2>, kGThreads, 0)); break;
+    }
+    return std::max(1, cus) * std::max(1, per_cu);
+}
+
+void mp_launch_lik_queue(const void* tab_dev, const int32_t* first_dev, int32_t* counter_dev, int n_inst, int tiles,
+                         int batch, int grid, hipStream_t s) {
+    LikQueueArgs Q;
+    Q.tab = static_cast<const LikArgs*>(tab_dev);
+    Q.first = first_dev;
+    Q.counter = counter_dev;
+    Q.n_inst = n_inst;
+    Q.tiles = tiles;
+    const unsigned g = (unsigned)std::max(1, std::min(grid, tiles));
+    switch (queue_batch(batch)) {
+        case 8: k_lik_queue<8><<<g, kGThreads, 0, s>>>(Q); break;
+        case 4: k_lik_queue<4><<<g, kGThreads, 0, s>>>(Q); break;
+        default: k_lik_queue<2><<<g, kGThreads, 0, s>>>(Q); break;
+    }
     MP_CHECK_LAUNCH();
 }

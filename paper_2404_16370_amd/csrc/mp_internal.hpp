@@ -222,6 +222,20 @@ void mp_launch_sort(mp_filter f, hipStream_t s);
 // window < 0: the filter's window_c; 0 re-ranks the current lists at the current poses
 void mp_launch_refresh(mp_filter f, hipStream_t s, int window = -1);
 void mp_launch_likelihood(mp_filter f, hipStream_t s);
+// Likelihood passes of several filters through one persistent tile queue
+// (GROUPED layout, PLAIN scorer, dense field): the plan of a pass (false if it cannot
+// join a queue), the solve that follows the queue, the queue launch.
+size_t mp_lik_args_bytes();
+bool mp_lik_queue_plan(mp_filter f, void* args_out, int32_t* tiles);
+void mp_lik_queue_solve(mp_filter f, hipStream_t s);
+int mp_lik_queue_grid(int batch);
+void mp_launch_lik_queue(const void* tab_dev, const int32_t* first_dev, int32_t* counter_dev, int n_inst, int tiles,
+                         int batch, int grid, hipStream_t s);
+// the phases of mp_step_launches (a batch interleaves them across filters)
+void mp_step_begin(mp_filter f, bool pred, const float dq[7], const float L[36], bool noise, hipStream_t s);
+void mp_step_iter_nbr(mp_filter f, int it, hipStream_t s);
+void mp_step_iter_svgd(mp_filter f, int it, hipStream_t s);
+void mp_step_end(mp_filter f, hipStream_t s);
 void mp_launch_svgd(mp_filter f, hipStream_t s);
 void mp_launch_posterior(mp_filter f, hipStream_t s);
 void mp_launch_reset_lists(mp_filter f, hipStream_t s);

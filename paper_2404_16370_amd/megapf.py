@@ -70,7 +70,9 @@ class mp_smoother_params(C.Structure):
 
 
 class mp_batch_info(C.Structure):
-    _fields_ = [("n_instances", C.c_int32), ("captures", C.c_int32), ("evals_per_step", C.c_int64)]
+    _fields_ = [("n_instances", C.c_int32), ("captures", C.c_int32), ("evals_per_step", C.c_int64),
+                ("queued_instances", C.c_int32), ("queue_batch", C.c_int32), ("queue_workgroups", C.c_int32),
+                ("pad", C.c_int32), ("queue_tiles_per_step", C.c_int64)]
 
 
 class mp_surrogate_params(C.Structure):
@@ -600,7 +602,9 @@ class Batch:
         ll = np.zeros(len(self.filters), np.int32)
         _check(lib().mp_batch_get_info(self.handle, C.byref(i), _ptr(lb), _ptr(ll)))
         return dict(n_instances=i.n_instances, captures=i.captures, evals_per_step=i.evals_per_step,
-                    lik_batch=[int(x) for x in lb], lik_layout=[int(x) for x in ll])
+                    lik_batch=[int(x) for x in lb], lik_layout=[int(x) for x in ll],
+                    queued_instances=i.queued_instances, queue_batch=i.queue_batch,
+                    queue_workgroups=i.queue_workgroups, queue_tiles_per_step=i.queue_tiles_per_step)
 
 
 class Smoother:
