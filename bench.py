@@ -134,7 +134,18 @@ def cpu_baseline(wl, w, scan, budget_s=15.0):
                        "workload's particles x %d scan points, %.1f s; scaled to %d particles x %d iterations "
                        "(posterior and prediction not included)" %
                        (m, wl["scan_points"], dt, wl["particles"], wl["svgd_iters"])),
-            "evals_per_s": evals / dt, "map_build_s": t_map, "single_core": single}
+            "evals_per_s": evals / dt, "map_build_s": t_map, "single_core": single, "cpu_model": cpu_model()}
+
+
+def cpu_model():
+    """the host CPU's model name (from /proc/cpuinfo)"""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.lower().startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def odometry_leg(M, m, w, scans, cpu):
@@ -294,6 +305,10 @@ def sequence_main(args):
     cfg = SEQUENCES[args.scene]
     frames = args.seq_frames if args.seq_frames else cfg["frames"]
     occl, kid = cfg["occlusion"], cfg["kidnap"]
+    if args.kidnap_frame:
+        # the teleport at another frame, the view blocked from 3 frames before it to 3 after
+        kid = args.kidnap_frame
+        occl = (kid - (cfg["kidnap"] - cfg["occlusion"][0]), kid + (cfg["occlusion"][1] - cfg["kidnap"]))
     br, bt = cfg["blocked"]
     blocked_cov = np.diag([br ** 2] * 3 + [bt ** 2] * 3).astype(np.float32)
     t0 = time.perf_counter()
@@ -660,6 +675,12 @@ def surrogate_eval_main(args):
            "final_error_m_deg": fin,
            "added_error_vs_plain": {"m": fin["surrogate"][0] - fin["plain"][0],
                                     "deg": fin["surrogate"][1] - fin["plain"][1]},
+           "gate": {"added_error_max_m": 0.05, "added_error_max_deg": 0.5,
+                    "network_alone_passed": bool(fin["surrogate"][0] - fin["plain"][0] <= 0.05 and
+                                                 fin["surrogate"][1] - fin["plain"][1] <= 0.5),
+                    "checked_passed": bool(fin["surrogate_checked"][0] - fin["plain"][0] <= 0.05 and
+                                           fin["surrogate_checked"][1] - fin["plain"][1] <= 0.5),
+                    "checked_ran_network_frames": frames - int(runs["surrogate_checked"]["fallback_steps"])},
            "checked": {"added_error_vs_plain": {"m": fin["surrogate_checked"][0] - fin["plain"][0],
                                                 "deg": fin["surrogate_checked"][1] - fin["plain"][1]},
                        "fallback_frames": runs["surrogate_checked"]["fallback_steps"],
@@ -821,9 +842,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="campus",
                     choices=sorted(WORKLOADS) + ["batch", "surrogate-eval", "sequence"])
-    ap.add_argument("--frames", type=int, default=30, help="surrogate-eval: filter frames")
+    ap.add_argument("--frames", type=int, default=50, help="surrogate-eval: filter frames")
     ap.add_argument("--seq-frames", type=int, default=0, help="sequence: frames (0: the scene's default)")
     ap.add_argument("--scene", default="floor", choices=["floor", "campus"], help="sequence: scene")
+    ap.add_argument("--kidnap-frame", type=int, default=0,
+                    help="sequence: frame of the teleport (0: the scene's default); the blocked frames move with it")
     ap.add_argument("--train-steps", type=int, default=20000, help="surrogate-eval: Adam steps")
     ap.add_argument("--sigma-s", type=float, default=0.03, help="surrogate-eval: sensor std of the score field")
     ap.add_argument("--lr", type=float, default=1e-3, help="surrogate-eval: Adam step")

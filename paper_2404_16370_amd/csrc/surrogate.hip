@@ -495,59 +495,63 @@ struct RedArgs {
     int32_t bp;
 };
 
-__device__ __forceinline__ float wave_sum64(float v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
 
-// One thread per sample of the chunk; each sum is reduced across the wave by
-// shuffles, then the 8 wave partials are added in a fixed order.
+// One workgroup per chunk of kRedChunk samples, one thread per output of
+// dW3 (thread t: row t / 4, output t % 4); threads 0..127 also sum db2 and
+// db1, threads 0..3 db3 and thread 4 the squared error.  The chunk's rows are
+// staged through LDS kSub samples at a time; every sum runs over the samples
+// in ascending order (the result does not depend on the launch).
 constexpr int kRedThreads = kRedChunk;
+constexpr int kSub = 64;
+static_assert(kRedThreads == 4 * kD2, "one thread per dW3 entry");
 __global__ __launch_bounds__(kRedThreads) void k_reduce_small(RedArgs A) {
-    __shared__ float red[kRedThreads / 64][kL3Len];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int b = blockIdx.x * kRedChunk + threadIdx.x;
-    const float4 d = A.dY[b];
-    const bf16x8* h2 = reinterpret_cast<const bf16x8*>(A.H2 + (size_t)b * kD2);
-    const bf16x8* z2 = reinterpret_cast<const bf16x8*>(A.dZ2 + (size_t)b * kD2);
-    for (int c8 = 0; c8 < kD2 / 8; ++c8) {
-        const bf16x8 hv = h2[c8], zv = z2[c8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int j = 8 * c8 + q;
-            const float h = (float)hv[q];
-            const float w0 = wave_sum64(h * d.x), w1 = wave_sum64(h * d.y);
-            const float w2 = wave_sum64(h * d.z), w3 = wave_sum64(h * d.w);
-            const float s2 = wave_sum64((float)zv[q]);
-            const float s1 = wave_sum64((float)A.dZ1T[(size_t)j * A.bp + b]);
-            if (lane == 0) {
-                red[wv][kL3W3 + 4 * j] = w0;
-                red[wv][kL3W3 + 4 * j + 1] = w1;
-                red[wv][kL3W3 + 4 * j + 2] = w2;
-                red[wv][kL3W3 + 4 * j + 3] = w3;
-                red[wv][kL3B2 + j] = s2;
-                red[wv][kL3B1 + j] = s1;
+    __shared__ bf16x8 sh2[kSub * kD2 / 8];
+    __shared__ bf16x8 sz2[kSub * kD2 / 8];
+    __shared__ float4 sdy[kSub];
+    __shared__ float sse[kSub];
+    const int t = threadIdx.x;
+    const int j = t >> 2, c = t & 3;
+    const int b0 = blockIdx.x * kRedChunk;
+    float w3 = 0.0f, g2 = 0.0f, g1 = 0.0f, g3 = 0.0f, e = 0.0f;
+    for (int sb = 0; sb < kRedChunk; sb += kSub) {
+        __syncthreads();
+        const bf16x8* h2 = reinterpret_cast<const bf16x8*>(A.H2 + (size_t)(b0 + sb) * kD2);
+        const bf16x8* z2 = reinterpret_cast<const bf16x8*>(A.dZ2 + (size_t)(b0 + sb) * kD2);
+        for (int q = t; q < kSub * kD2 / 8; q += kRedThreads) {
+            sh2[q] = h2[q];
+            sz2[q] = z2[q];
+        }
+        if (t < kSub) {
+            sdy[t] = A.dY[b0 + sb + t];
+            sse[t] = A.sse[b0 + sb + t];
+        }
+        __syncthreads();
+        const __bf16* H = reinterpret_cast<const __bf16*>(sh2);
+        const __bf16* Z = reinterpret_cast<const __bf16*>(sz2);
+        for (int b = 0; b < kSub; ++b) {
+            const float4 d = sdy[b];
+            const float dc = c == 0 ? d.x : (c == 1 ? d.y : (c == 2 ? d.z : d.w));
+            w3 = __builtin_fmaf((float)H[b * kD2 + j], dc, w3);
+            if (t < kD2) g2 += (float)Z[b * kD2 + t];
+            if (t < 4) {
+                const float dt = t == 0 ? d.x : (t == 1 ? d.y : (t == 2 ? d.z : d.w));
+                g3 += dt;
             }
+            if (t == 4) e += sse[b];
         }
     }
-    const float e0 = wave_sum64(d.x), e1 = wave_sum64(d.y), e2 = wave_sum64(d.z), e3 = wave_sum64(d.w);
-    const float se = wave_sum64(A.sse[b]);
-    if (lane == 0) {
-        red[wv][kL3B3] = e0;
-        red[wv][kL3B3 + 1] = e1;
-        red[wv][kL3B3 + 2] = e2;
-        red[wv][kL3B3 + 3] = e3;
-        red[wv][kL3SSE] = se;
+    if (t < kD2) {
+        const __bf16* z1 = A.dZ1T + (size_t)t * A.bp + b0;
+        for (int b = 0; b < kRedChunk; ++b) g1 += (float)z1[b];
     }
-    __syncthreads();
     float* o = A.out + (size_t)blockIdx.x * kL3Len;
-    for (int item = threadIdx.x; item < kL3Len; item += blockDim.x) {
-        float acc = 0.0f;
-#pragma unroll
-        for (int w = 0; w < kRedThreads / 64; ++w) acc += red[w][item];
-        o[item] = acc;
+    o[kL3W3 + 4 * j + c] = w3;
+    if (t < kD2) {
+        o[kL3B2 + t] = g2;
+        o[kL3B1 + t] = g1;
     }
+    if (t < 4) o[kL3B3 + t] = g3;
+    if (t == 4) o[kL3SSE] = e;
 }
 
 struct AdamArgs {
@@ -564,28 +568,51 @@ struct AdamArgs {
     PublishArgs W;
 };
 
-__global__ void k_adam(AdamArgs A) {
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q == 0 && A.loss_out) {
+// Gradient of every parameter from the chunk partials, then the Adam update.
+// A workgroup takes kAdamQ consecutive parameters; its kAdamSub thread rows
+// sum every kAdamSub-th chunk (coalesced reads of kAdamQ neighbours), and
+// the row sums are added in a fixed order.
+constexpr int kAdamQ = 32, kAdamSub = 8;
+__global__ __launch_bounds__(kAdamQ * kAdamSub) void k_adam(AdamArgs A) {
+    __shared__ float part[kAdamSub][kAdamQ];
+    const int qi = threadIdx.x % kAdamQ, sub = threadIdx.x / kAdamQ;
+    const int q = blockIdx.x * kAdamQ + qi;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && A.loss_out) {
         float s = 0.0f;
         for (int z = 0; z < A.nsplit; ++z) s += A.pl3[(size_t)z * kL3Len + kL3SSE];
         *A.loss_out = s * A.inv_n;
     }
-    if (q >= kNParams) return;
     float g = 0.0f;
-    if (q < kOffB1) {
-        for (int z = 0; z < A.nsplit; ++z) g += A.pw1[(size_t)z * (kD0 * kD1) + q];
-    } else if (q < kOffW2) {
-        for (int z = 0; z < A.nsplit; ++z) g += A.pl3[(size_t)z * kL3Len + kL3B1 + (q - kOffB1)];
-    } else if (q < kOffB2) {
-        for (int z = 0; z < A.nsplit; ++z) g += A.pw2[(size_t)z * (kD1 * kD2) + (q - kOffW2)];
-    } else if (q < kOffW3) {
-        for (int z = 0; z < A.nsplit; ++z) g += A.pl3[(size_t)z * kL3Len + kL3B2 + (q - kOffB2)];
-    } else if (q < kOffB3) {
-        for (int z = 0; z < A.nsplit; ++z) g += A.pl3[(size_t)z * kL3Len + kL3W3 + (q - kOffW3)];
-    } else {
-        for (int z = 0; z < A.nsplit; ++z) g += A.pl3[(size_t)z * kL3Len + kL3B3 + (q - kOffB3)];
+    if (q < kNParams) {
+        const float* src;
+        size_t stride;
+        if (q < kOffB1) {
+            src = A.pw1 + q;
+            stride = (size_t)kD0 * kD1;
+        } else if (q < kOffW2) {
+            src = A.pl3 + kL3B1 + (q - kOffB1);
+            stride = kL3Len;
+        } else if (q < kOffB2) {
+            src = A.pw2 + (q - kOffW2);
+            stride = (size_t)kD1 * kD2;
+        } else if (q < kOffW3) {
+            src = A.pl3 + kL3B2 + (q - kOffB2);
+            stride = kL3Len;
+        } else if (q < kOffB3) {
+            src = A.pl3 + kL3W3 + (q - kOffW3);
+            stride = kL3Len;
+        } else {
+            src = A.pl3 + kL3B3 + (q - kOffB3);
+            stride = kL3Len;
+        }
+        for (int z = sub; z < A.nsplit; z += kAdamSub) g += src[(size_t)z * stride];
     }
+    part[sub][qi] = g;
+    __syncthreads();
+    if (sub != 0 || q >= kNParams) return;
+    g = 0.0f;
+#pragma unroll
+    for (int r = 0; r < kAdamSub; ++r) g += part[r][qi];
     A.G[q] = g;
     if (!A.update) return;
     const float m = __builtin_fmaf(A.beta1, A.Mo[q], (1.0f - A.beta1) * g);
@@ -1028,7 +1055,7 @@ void mp_sur_grad_step(mp_surrogate S, int32_t n_real, bool update, float lr, flo
     A.c1 = (float)(1.0 - std::pow((double)S->p.beta1, t));
     A.c2 = (float)(1.0 - std::pow((double)S->p.beta2, t));
     A.W = publish_args(S);
-    k_adam<<<(kNParams + 255) / 256, 256, 0, s>>>(A);
+    k_adam<<<(kNParams + kAdamQ - 1) / kAdamQ, kAdamQ * kAdamSub, 0, s>>>(A);
     MP_CHECK_LAUNCH();
     if (update) S->info.steps += 1;
 }
