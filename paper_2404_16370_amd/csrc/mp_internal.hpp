@@ -84,10 +84,11 @@ struct mp_surrogate_s {
     mp_surrogate_info info{};
     DevMem P, Mo, Vo, G;            // FP32 weights, Adam moments, last gradient
     DevMem img;                     // inference image (bf16 fragments, FP32 biases and frequencies)
-    DevMem w1t, w2t, w2n, w3b;      // bf16 copies for the training products
+    DevMem img2;                    // W2 fragments of the training's input-gradient product
+    DevMem w3b;                     // bf16 copy of W3 (training's output-layer gradient)
     DevMem dxyz, dlab;              // training set: points, scaled labels (float4)
     int32_t cap = 0;                // padded batch rows the work buffers hold
-    DevMem bxyz, btgt, X, XT, Z1, H1, H1T, Z2, H2, dY, sse, dZ2, dZ2T, dZ1T;
+    DevMem bxyz, btgt, XT, H1T, H2T, dY, sse, dZ2T, dZ1T;   // per-batch activations, unit-major
     DevMem pw1, pw2, pl3;           // split-K and chunk partial sums
     DevMem losses;                  // per-step loss (float)
     int cus = 1;                    // compute units of the device (persistent-grid size)

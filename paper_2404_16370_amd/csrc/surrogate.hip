@@ -24,10 +24,15 @@
 // permuted to match the accumulator layout; the weight fragments are stored
 // in the same permuted order.
 //
-// Training runs each product as a general bf16 "NT" GEMM (both operands
-// K-contiguous) with activations kept in HBM in the layouts the backward
-// products need; weight gradients are split-K partial sums reduced in a fixed
-// order by the Adam kernel, so a step is deterministic.
+// Training: one fused kernel runs the forward and the backward pass of 32
+// samples per wave in the inference layout (features, both hidden layers,
+// output, loss, the output layer's gradient and the input gradient of layer
+// 2 on the matrix cores, the pre-activations kept in registers) and writes
+// only what the weight gradients need, unit-major: features, H1, H2, dZ2,
+// dZ1 (bf16) and dY.  The weight gradients of layers 1 and 2 are bf16 "NT"
+// GEMMs over the samples (split-K partial sums per chunk of 512 samples),
+// the small ones (W3, biases, loss) chunk sums; the Adam kernel reduces the
+// partials in a fixed order, so a step is deterministic.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -57,6 +62,7 @@ constexpr int kImgB3 = kImgB2 + 512;               // 4 f32
 constexpr int kImgFQ = kImgB3 + 16;                // 32 f32 frequencies
 constexpr int kImgBytes = kImgFQ + 128;
 static_assert(kImgBytes == MP_SUR_IMAGE_BYTES, "image size");
+constexpr int kImg2Bytes = 4 * 8 * 64 * 16;        // [4 row tiles][8 k-steps][64 lanes][8] bf16
 static_assert(kImgBytes % 16 == 0, "image in uint4 units");
 
 // per-chunk sums of the small reductions: dW3 (512), db3 (4), db2 (128), db1 (128), squared error (1)
@@ -104,6 +110,15 @@ __host__ __device__ inline int frag2_index(int i, int o) {  // W2[i][o]
     hid_slot(i, s2, h, j);
     return (((o >> 5) * 8 + s2) * 64 + (o & 31) + 32 * h) * 8 + j;
 }
+// W2[i][o] as the A operand of the input gradient dH1 = W2 dZ2 (rows = layer-1
+// units i, k = layer-2 units o in the accumulator order of layer 2)
+__host__ __device__ inline int frag2b_index(int i, int o) {
+    int s2, h, j;
+    hid_slot(o, s2, h, j);
+    return (((i >> 5) * 8 + s2) * 64 + (i & 31) + 32 * h) * 8 + j;
+}
+// the hidden unit of register jj of accumulator row tile r in lane half h
+__host__ __device__ inline int acc_unit(int r, int jj, int h) { return 32 * r + 8 * (jj >> 2) + 4 * h + (jj & 3); }
 __host__ __device__ inline int frag3_index(int i, int o) {  // W3[i][o]
     int s2, h, j;
     hid_slot(i, s2, h, j);
@@ -245,11 +260,9 @@ __global__ void k_init_weights(float* __restrict__ P, uint64_t seed) {
 }
 
 struct PublishArgs {
-    __bf16* w1t;  // [128][192]
-    __bf16* w2t;  // [128 out][128 in]
-    __bf16* w2n;  // [128 in][128 out]
     __bf16* w3b;  // [128][4]
     char* img;
+    __bf16* img2;
 };
 
 __device__ __forceinline__ void publish(const PublishArgs& W, int q, float w) {
@@ -259,15 +272,13 @@ __device__ __forceinline__ void publish(const PublishArgs& W, int q, float w) {
     __bf16* f3 = reinterpret_cast<__bf16*>(W.img + kImgF3);
     if (q < kOffB1) {
         const int f = q / kD1, o = q % kD1;
-        W.w1t[o * kD0 + f] = wb;
         f1[frag1_index(f, o)] = wb;
     } else if (q < kOffW2) {
         reinterpret_cast<float*>(W.img + kImgB1)[q - kOffB1] = w;
     } else if (q < kOffB2) {
         const int i = (q - kOffW2) / kD2, o = (q - kOffW2) % kD2;
-        W.w2t[o * kD1 + i] = wb;
-        W.w2n[i * kD2 + o] = wb;
         f2[frag2_index(i, o)] = wb;
+        W.img2[frag2b_index(i, o)] = wb;
     } else if (q < kOffW3) {
         reinterpret_cast<float*>(W.img + kImgB2)[q - kOffB2] = w;
     } else if (q < kOffB3) {
@@ -317,56 +328,16 @@ __global__ void k_draw_batch(BatchArgs A) {
     A.btgt[b] = A.dlab[idx];
 }
 
-struct FeatArgs {
-    const float* __restrict__ xyz;
-    __bf16* __restrict__ X;    // [bp][192]
-    __bf16* __restrict__ XT;   // [192][bp]
-    int32_t bp;
-    float lo[3], inv[3];
-    float fq[32];
-};
-
-__global__ void k_features(FeatArgs A) {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= A.bp) return;
-    __bf16* row = A.X + (size_t)b * kD0;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const float x = (A.xyz[3 * b + a] - A.lo[a]) * A.inv[a];
-#pragma unroll 4
-        for (int l = 0; l < 32; l += 4) {
-            bf16x8 v;
-            __bf16 s0, c0, s1, c1, s2, c2, s3, c3;
-            feature_pair(A.fq[l], x, s0, c0);
-            feature_pair(A.fq[l + 1], x, s1, c1);
-            feature_pair(A.fq[l + 2], x, s2, c2);
-            feature_pair(A.fq[l + 3], x, s3, c3);
-            v = bf16x8{s0, c0, s1, c1, s2, c2, s3, c3};
-            const int f = 2 * (a * 32 + l);
-            *reinterpret_cast<bf16x8*>(row + f) = v;
-#pragma unroll
-            for (int j = 0; j < 8; ++j) A.XT[(size_t)(f + j) * A.bp + b] = v[j];
-        }
-    }
-}
-
-enum { EPI_ACT = 0, EPI_BACK = 1, EPI_PARTIAL = 2 };
-
 struct GemmArgs {
     const __bf16* __restrict__ A;  // [M][K]
     const __bf16* __restrict__ B;  // [N][K]
     int32_t M, N, K, kslice;
-    const float* __restrict__ bias;  // EPI_ACT: [N]
-    float* __restrict__ Z;           // EPI_ACT: pre-activation [M][N] (FP32)
-    __bf16* __restrict__ H;          // EPI_ACT: silu(Z) [M][N]
-    __bf16* __restrict__ HT;         // EPI_ACT (optional), EPI_BACK: [N][M]
-    const float* __restrict__ Zin;   // EPI_BACK: pre-activation [M][N]
-    float* __restrict__ out;         // EPI_PARTIAL: [slices][M][N]
+    float* __restrict__ out;         // [slices][M][N]
 };
 
-// C[m][n] = sum_k A[m][k] B[n][k]; block tile 64 x 128, four waves of 32 x 64.
+// Partial products over K slices: out[z][m][n] = sum over k in slice z of
+// A[m][k] B[n][k]; block tile 64 x 128, four waves of 32 x 64.
 // Requires M % 64 == 0, N % 128 == 0, K % 16 == 0, kslice % 16 == 0.
-template <int EPI>
 __global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int r = lane & 31, h = lane >> 5;
@@ -391,167 +362,273 @@ __global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int mb = m0 + 8 * q + 4 * h;   // rows mb .. mb + 3 in registers 4q .. 4q + 3
-            if (EPI == EPI_PARTIAL) {
-                float* o = g.out + ((size_t)blockIdx.z * g.M + mb) * g.N + n;
+            float* o = g.out + ((size_t)blockIdx.z * g.M + mb) * g.N + n;
 #pragma unroll
-                for (int i = 0; i < 4; ++i) o[(size_t)i * g.N] = c[4 * q + i];
-            } else if (EPI == EPI_ACT) {
-                __bf16 hv[4];
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const float z = c[4 * q + i] + g.bias[n];
-                    g.Z[(size_t)(mb + i) * g.N + n] = z;
-                    hv[i] = (__bf16)silu_f(z);
-                    g.H[(size_t)(mb + i) * g.N + n] = hv[i];
-                }
-                if (g.HT) {
-                    __bf16* t = g.HT + (size_t)n * g.M + mb;
-                    t[0] = hv[0];
-                    t[1] = hv[1];
-                    t[2] = hv[2];
-                    t[3] = hv[3];
-                }
-            } else {
-                __bf16* t = g.HT + (size_t)n * g.M + mb;
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const float z = g.Zin[(size_t)(mb + i) * g.N + n];
-                    t[i] = (__bf16)(c[4 * q + i] * silu_grad_f(z));
-                }
-            }
+            for (int i = 0; i < 4; ++i) o[(size_t)i * g.N] = c[4 * q + i];
         }
     }
 }
 
-// Output layer forward and backward, one thread per sample: y = h2 W3 + b3,
-// squared error, dy = 2 (y - t) / n, dz2 = (W3 dy) silu'(z2) rounded to bf16.
-struct L3Args {
-    const __bf16* __restrict__ H2;    // [bp][128]
-    const float* __restrict__ Z2;     // [bp][128]
-    const __bf16* __restrict__ w3b;   // [128][4]
-    const float* __restrict__ b3;     // [4] (FP32 master)
-    const float4* __restrict__ tgt;   // [bp]
-    float4* __restrict__ dY;          // [bp]
-    float* __restrict__ sse;          // [bp]
-    __bf16* __restrict__ dZ2;         // [bp][128]
-    __bf16* __restrict__ dZ2T;        // [128][bp]
+// ------------------------------------------------------------ training step
+// Forward and backward pass of the batch, 32 samples per wave and call (the
+// inference layout of mlp32, with tile 0's outputs in lane half 0).  Rounding
+// points as in the reference definition of the training: features, H1, H2,
+// dZ2 and dZ1 in bf16; pre-activations, outputs, dY and dH2 in FP32.
+constexpr int kTrainThreads = 256;   // 4 waves, one per SIMD: Z1, Z2 and two accumulators live at once
+struct TrainArgs {
+    const uint4* __restrict__ img;     // inference image
+    const uint4* __restrict__ img2;    // W2 fragments of the input gradient
+    const __bf16* __restrict__ w3b;    // [128][4]
+    const float* __restrict__ xyz;     // [bp][3]
+    const float4* __restrict__ tgt;    // [bp] scaled targets
+    __bf16* __restrict__ XT;           // [192][bp] features
+    __bf16* __restrict__ H1T;          // [128][bp]
+    __bf16* __restrict__ H2T;          // [128][bp]
+    __bf16* __restrict__ dZ2T;         // [128][bp]
+    __bf16* __restrict__ dZ1T;         // [128][bp]
+    float4* __restrict__ dY;           // [bp] 2 (y - t) / n (0 for padding rows)
+    float* __restrict__ sse;           // [bp] squared error (0 for padding rows)
     int32_t bp, n_real;
     float two_over_n;
+    float lo[3], inv[3];
 };
 
-__global__ __launch_bounds__(256) void k_out_layer(L3Args A) {
-    __shared__ float w3[kD2 * 4];
-    for (int q = threadIdx.x; q < kD2 * 4; q += blockDim.x) w3[q] = (float)A.w3b[q];
+__global__ __launch_bounds__(kTrainThreads) void k_train_fb(TrainArgs A) {
+    __shared__ uint4 simg[kImgBytes / 16];
+    __shared__ uint4 simg2[kImg2Bytes / 16];
+    __shared__ float w3s[kD2 * 4];
+    for (int q = threadIdx.x; q < kImgBytes / 16; q += blockDim.x) simg[q] = A.img[q];
+    for (int q = threadIdx.x; q < kImg2Bytes / 16; q += blockDim.x) simg2[q] = A.img2[q];
+    for (int q = threadIdx.x; q < kD2 * 4; q += blockDim.x) w3s[q] = (float)A.w3b[q];
     __syncthreads();
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= A.bp) return;
-    const bool valid = b < A.n_real;
-    const bf16x8* hrow = reinterpret_cast<const bf16x8*>(A.H2 + (size_t)b * kD2);
-    float y0 = A.b3[0], y1 = A.b3[1], y2 = A.b3[2], y3 = A.b3[3];
-    for (int c = 0; c < kD2 / 8; ++c) {
-        const bf16x8 hv = hrow[c];
+    const char* img = reinterpret_cast<const char*>(simg);
+    const bf16x8* f1 = reinterpret_cast<const bf16x8*>(img + kImgF1);
+    const bf16x8* f2 = reinterpret_cast<const bf16x8*>(img + kImgF2);
+    const bf16x8* f3 = reinterpret_cast<const bf16x8*>(img + kImgF3);
+    const bf16x8* f2b = reinterpret_cast<const bf16x8*>(simg2);
+    const float* b1 = reinterpret_cast<const float*>(img + kImgB1);
+    const float* b2 = reinterpret_cast<const float*>(img + kImgB2);
+    const float* b3 = reinterpret_cast<const float*>(img + kImgB3);
+    const float* fq = reinterpret_cast<const float*>(img + kImgFQ);
+    const int lane = threadIdx.x & 63, m = lane & 31, h = lane >> 5;
+    const int nw = kTrainThreads / 64;
+    const int tiles = A.bp / 32;
+    // rows x bp < 2^31 (bp <= 2^20)
+    for (int t = blockIdx.x * nw + (threadIdx.x >> 6); t < tiles; t += gridDim.x * nw) {
+        const int b = 32 * t + m;   // this lane's sample (both lane halves)
+        // the row stride as an opaque value of this iteration: the ~350 store
+        // offsets below are formed where they are used, not hoisted out of the
+        // loop into registers
+        int bp = A.bp;
+        asm volatile("" : "+s"(bp));
+        __bf16* const xt = A.XT + b;
+        __bf16* const h1t = A.H1T + b;
+        __bf16* const h2t = A.H2T + b;
+        __bf16* const dz2t = A.dZ2T + b;
+        __bf16* const dz1t = A.dZ1T + b;
+        float x[3];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const float hj = (float)hv[j];
-            const float* w = w3 + 4 * (8 * c + j);
-            y0 = __builtin_fmaf(hj, w[0], y0);
-            y1 = __builtin_fmaf(hj, w[1], y1);
-            y2 = __builtin_fmaf(hj, w[2], y2);
-            y3 = __builtin_fmaf(hj, w[3], y3);
-        }
-    }
-    const float4 t = A.tgt[b];
-    const float r0 = y0 - t.x, r1 = y1 - t.y, r2 = y2 - t.z, r3 = y3 - t.w;
-    const float e = valid ? __builtin_fmaf(r0, r0, __builtin_fmaf(r1, r1, __builtin_fmaf(r2, r2, r3 * r3))) : 0.0f;
-    const float k = valid ? A.two_over_n : 0.0f;
-    const float d0 = r0 * k, d1 = r1 * k, d2 = r2 * k, d3 = r3 * k;
-    A.sse[b] = e;
-    A.dY[b] = make_float4(d0, d1, d2, d3);
-    const float* z = A.Z2 + (size_t)b * kD2;
-    bf16x8* drow = reinterpret_cast<bf16x8*>(A.dZ2 + (size_t)b * kD2);
-    for (int c = 0; c < kD2 / 8; ++c) {
-        bf16x8 v;
+        for (int a = 0; a < 3; ++a) x[a] = (A.xyz[3 * b + a] - A.lo[a]) * A.inv[a];
+        // layer 1: Z1 = W1^T x + b1 (kept), features written unit-major
+        f32x16 z1[4];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const int i = 8 * c + j;
-            const float* w = w3 + 4 * i;
-            const float dh = __builtin_fmaf(w[0], d0, __builtin_fmaf(w[1], d1, __builtin_fmaf(w[2], d2, w[3] * d3)));
-            v[j] = (__bf16)(dh * silu_grad_f(z[i]));
-            A.dZ2T[(size_t)i * A.bp + b] = v[j];
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int jj = 0; jj < 16; ++jj) z1[r][jj] = b1[acc_unit(r, jj, h)];
+#pragma unroll
+        for (int sk = 0; sk < 12; ++sk) {
+            const float4 fr = *reinterpret_cast<const float4*>(fq + 8 * (sk & 3) + 4 * h);
+            const float xs = x[sk >> 2];
+            __bf16 v0, v1, v2, v3, v4, v5, v6, v7;
+            feature_pair(fr.x, xs, v0, v1);
+            feature_pair(fr.y, xs, v2, v3);
+            feature_pair(fr.z, xs, v4, v5);
+            feature_pair(fr.w, xs, v6, v7);
+            const bf16x8 bx = bf16x8{v0, v1, v2, v3, v4, v5, v6, v7};
+#pragma unroll
+            for (int j = 0; j < 8; ++j) xt[(16 * sk + 8 * h + j) * bp] = bx[j];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) z1[r] = mfma32(f1[(r * 12 + sk) * 64 + lane], bx, z1[r]);
         }
-        drow[c] = v;
+        bf16x8 hb[8];
+#pragma unroll
+        for (int s2 = 0; s2 < 8; ++s2)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int r = s2 >> 1, jj = 8 * (s2 & 1) + j;
+                hb[s2][j] = (__bf16)silu_f(z1[r][jj]);
+                h1t[acc_unit(r, jj, h) * bp] = hb[s2][j];
+            }
+        // layer 2: Z2 = W2^T H1 + b2 (kept)
+        f32x16 z2[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int jj = 0; jj < 16; ++jj) z2[r][jj] = b2[acc_unit(r, jj, h)];
+#pragma unroll
+        for (int s2 = 0; s2 < 8; ++s2)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) z2[r] = mfma32(f2[(r * 8 + s2) * 64 + lane], hb[s2], z2[r]);
+#pragma unroll
+        for (int s2 = 0; s2 < 8; ++s2)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int r = s2 >> 1, jj = 8 * (s2 & 1) + j;
+                hb[s2][j] = (__bf16)silu_f(z2[r][jj]);
+                h2t[acc_unit(r, jj, h) * bp] = hb[s2][j];
+            }
+        // output layer: rows 0..3 of the product, held by lane half 0
+        f32x16 o = {};
+        const bf16x8 zero = {};
+#pragma unroll
+        for (int s2 = 0; s2 < 8; ++s2) o = mfma32(m < 4 ? f3[(s2 * 4 + m) * 2 + h] : zero, hb[s2], o);
+        float y[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) y[c] = __shfl(o[c] + b3[c], m, 64);   // from lane m (half 0)
+        const float4 tg = A.tgt[b];
+        const bool valid = b < A.n_real;
+        const float r0 = y[0] - tg.x, r1 = y[1] - tg.y, r2 = y[2] - tg.z, r3 = y[3] - tg.w;
+        const float e = valid ? __builtin_fmaf(r0, r0, __builtin_fmaf(r1, r1, __builtin_fmaf(r2, r2, r3 * r3))) : 0.0f;
+        const float kk = valid ? A.two_over_n : 0.0f;
+        const float d0 = r0 * kk, d1 = r1 * kk, d2 = r2 * kk, d3 = r3 * kk;
+        if (h == 0) {
+            A.dY[b] = make_float4(d0, d1, d2, d3);
+            A.sse[b] = e;
+        }
+        // dZ2 = (W3 dY) silu'(Z2) in bf16: the B operand of the input gradient
+        bf16x8 dz[8];
+#pragma unroll
+        for (int s2 = 0; s2 < 8; ++s2)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int r = s2 >> 1, jj = 8 * (s2 & 1) + j;
+                const int u = acc_unit(r, jj, h);
+                const float* w = w3s + 4 * u;
+                const float dh = __builtin_fmaf(w[0], d0, __builtin_fmaf(w[1], d1, __builtin_fmaf(w[2], d2, w[3] * d3)));
+                dz[s2][j] = (__bf16)(dh * silu_grad_f(z2[r][jj]));
+                dz2t[u * bp] = dz[s2][j];
+            }
+        // dH1 = W2 dZ2, dZ1 = dH1 silu'(Z1) in bf16
+        f32x16 g[4] = {};
+#pragma unroll
+        for (int s2 = 0; s2 < 8; ++s2)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) g[r] = mfma32(f2b[(r * 8 + s2) * 64 + lane], dz[s2], g[r]);
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int jj = 0; jj < 16; ++jj)
+                dz1t[acc_unit(r, jj, h) * bp] = (__bf16)(g[r][jj] * silu_grad_f(z1[r][jj]));
     }
 }
 
-// Per-chunk sums over kRedChunk samples: dW3 = sum h2 dy, db3 = sum dy,
-// db2 = sum dz2, db1 = sum dz1, squared error.
+// Per-chunk sums over kRedChunk samples from the unit-major activations:
+// dW3 = sum h2 dy, db3 = sum dy, db2 = sum dz2, db1 = sum dz1, squared error.
 struct RedArgs {
-    const __bf16* __restrict__ H2;    // [bp][128]
+    const __bf16* __restrict__ H2T;   // [128][bp]
     const float4* __restrict__ dY;    // [bp]
     const float* __restrict__ sse;    // [bp]
-    const __bf16* __restrict__ dZ2;   // [bp][128]
+    const __bf16* __restrict__ dZ2T;  // [128][bp]
     const __bf16* __restrict__ dZ1T;  // [128][bp]
     float* __restrict__ out;          // [chunks][kL3Len]
     int32_t bp;
 };
 
-
-// One workgroup per chunk of kRedChunk samples, one thread per output of
-// dW3 (thread t: row t / 4, output t % 4); threads 0..127 also sum db2 and
-// db1, threads 0..3 db3 and thread 4 the squared error.  The chunk's rows are
-// staged through LDS kSub samples at a time; every sum runs over the samples
-// in ascending order (the result does not depend on the launch).
-constexpr int kRedThreads = kRedChunk;
-constexpr int kSub = 64;
-static_assert(kRedThreads == 4 * kD2, "one thread per dW3 entry");
+// One workgroup per chunk; thread t takes unit u = t / 8 and part q = t % 8
+// of the chunk's samples (64 samples: eight 16-byte loads of each unit-major
+// row, all issued before they are used): partial dW3[u][0..3], db2[u] and
+// db1[u] over its part; the eight parts are added in a fixed order, and db3
+// and the squared error by the first wave in a fixed order (the result does
+// not depend on the launch).
+constexpr int kRedParts = 8;
+constexpr int kRedThreads = kD2 * kRedParts;
+constexpr int kPart = kRedChunk / kRedParts;
+static_assert(kPart % 8 == 0 && kRedThreads <= 1024, "reduction shape");
 __global__ __launch_bounds__(kRedThreads) void k_reduce_small(RedArgs A) {
-    __shared__ bf16x8 sh2[kSub * kD2 / 8];
-    __shared__ bf16x8 sz2[kSub * kD2 / 8];
-    __shared__ float4 sdy[kSub];
-    __shared__ float sse[kSub];
+    __shared__ float4 sdy[kRedChunk];
+    __shared__ float sse[kRedChunk];
+    __shared__ float part[kRedParts][kD2][6];   // part, unit, (dW3 0..3, db2, db1)
     const int t = threadIdx.x;
-    const int j = t >> 2, c = t & 3;
+    const int u = t / kRedParts, q = t % kRedParts;
     const int b0 = blockIdx.x * kRedChunk;
-    float w3 = 0.0f, g2 = 0.0f, g1 = 0.0f, g3 = 0.0f, e = 0.0f;
-    for (int sb = 0; sb < kRedChunk; sb += kSub) {
-        __syncthreads();
-        const bf16x8* h2 = reinterpret_cast<const bf16x8*>(A.H2 + (size_t)(b0 + sb) * kD2);
-        const bf16x8* z2 = reinterpret_cast<const bf16x8*>(A.dZ2 + (size_t)(b0 + sb) * kD2);
-        for (int q = t; q < kSub * kD2 / 8; q += kRedThreads) {
-            sh2[q] = h2[q];
-            sz2[q] = z2[q];
-        }
-        if (t < kSub) {
-            sdy[t] = A.dY[b0 + sb + t];
-            sse[t] = A.sse[b0 + sb + t];
-        }
-        __syncthreads();
-        const __bf16* H = reinterpret_cast<const __bf16*>(sh2);
-        const __bf16* Z = reinterpret_cast<const __bf16*>(sz2);
-        for (int b = 0; b < kSub; ++b) {
-            const float4 d = sdy[b];
-            const float dc = c == 0 ? d.x : (c == 1 ? d.y : (c == 2 ? d.z : d.w));
-            w3 = __builtin_fmaf((float)H[b * kD2 + j], dc, w3);
-            if (t < kD2) g2 += (float)Z[b * kD2 + t];
-            if (t < 4) {
-                const float dt = t == 0 ? d.x : (t == 1 ? d.y : (t == 2 ? d.z : d.w));
-                g3 += dt;
-            }
-            if (t == 4) e += sse[b];
-        }
+    for (int b = t; b < kRedChunk; b += kRedThreads) {
+        sdy[b] = A.dY[b0 + b];
+        sse[b] = A.sse[b0 + b];
     }
-    if (t < kD2) {
-        const __bf16* z1 = A.dZ1T + (size_t)t * A.bp + b0;
-        for (int b = 0; b < kRedChunk; ++b) g1 += (float)z1[b];
+    const size_t bp = (size_t)A.bp;
+    const int s0 = q * kPart;
+    const bf16x8* h2 = reinterpret_cast<const bf16x8*>(A.H2T + (size_t)u * bp + b0 + s0);
+    const bf16x8* z2 = reinterpret_cast<const bf16x8*>(A.dZ2T + (size_t)u * bp + b0 + s0);
+    const bf16x8* z1 = reinterpret_cast<const bf16x8*>(A.dZ1T + (size_t)u * bp + b0 + s0);
+    bf16x8 hv[kPart / 8], zv2[kPart / 8], zv1[kPart / 8];
+#pragma unroll
+    for (int v = 0; v < kPart / 8; ++v) {
+        hv[v] = h2[v];
+        zv2[v] = z2[v];
+        zv1[v] = z1[v];
     }
+    __syncthreads();
+    float w0 = 0.0f, w1 = 0.0f, w2 = 0.0f, w3 = 0.0f, g2 = 0.0f, g1 = 0.0f;
+#pragma unroll
+    for (int v = 0; v < kPart / 8; ++v)
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const float4 d = sdy[s0 + 8 * v + k];
+            const float hh = (float)hv[v][k];
+            w0 = __builtin_fmaf(hh, d.x, w0);
+            w1 = __builtin_fmaf(hh, d.y, w1);
+            w2 = __builtin_fmaf(hh, d.z, w2);
+            w3 = __builtin_fmaf(hh, d.w, w3);
+            g2 += (float)zv2[v][k];
+            g1 += (float)zv1[v][k];
+        }
+    part[q][u][0] = w0;
+    part[q][u][1] = w1;
+    part[q][u][2] = w2;
+    part[q][u][3] = w3;
+    part[q][u][4] = g2;
+    part[q][u][5] = g1;
+    __syncthreads();
     float* o = A.out + (size_t)blockIdx.x * kL3Len;
-    o[kL3W3 + 4 * j + c] = w3;
-    if (t < kD2) {
-        o[kL3B2 + t] = g2;
-        o[kL3B1 + t] = g1;
+    if (t < kD2 * 6) {   // unit t / 6, quantity t % 6
+        const int uu = t / 6, c = t % 6;
+        float acc = 0.0f;
+#pragma unroll
+        for (int r = 0; r < kRedParts; ++r) acc += part[r][uu][c];
+        if (c < 4) o[kL3W3 + 4 * uu + c] = acc;
+        else if (c == 4) o[kL3B2 + uu] = acc;
+        else o[kL3B1 + uu] = acc;
     }
-    if (t < 4) o[kL3B3 + t] = g3;
-    if (t == 4) o[kL3SSE] = e;
+    if (t < 64) {
+        // db3 and the squared error: lane l sums samples 8 l .. 8 l + 7, then
+        // a fixed butterfly over the wave
+        float4 d3 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        float e = 0.0f;
+#pragma unroll
+        for (int k = 0; k < kRedChunk / 64; ++k) {
+            const float4 d = sdy[(kRedChunk / 64) * t + k];
+            d3.x += d.x;
+            d3.y += d.y;
+            d3.z += d.z;
+            d3.w += d.w;
+            e += sse[(kRedChunk / 64) * t + k];
+        }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            d3.x += __shfl_xor(d3.x, off, 64);
+            d3.y += __shfl_xor(d3.y, off, 64);
+            d3.z += __shfl_xor(d3.z, off, 64);
+            d3.w += __shfl_xor(d3.w, off, 64);
+            e += __shfl_xor(e, off, 64);
+        }
+        if (t == 0) {
+            o[kL3B3] = d3.x;
+            o[kL3B3 + 1] = d3.y;
+            o[kL3B3 + 2] = d3.z;
+            o[kL3B3 + 3] = d3.w;
+            o[kL3SSE] = e;
+        }
+    }
 }
 
 struct AdamArgs {
@@ -779,11 +856,9 @@ int num_cus() {
 
 PublishArgs publish_args(mp_surrogate S) {
     PublishArgs W;
-    W.w1t = S->w1t.as<__bf16>();
-    W.w2t = S->w2t.as<__bf16>();
-    W.w2n = S->w2n.as<__bf16>();
     W.w3b = S->w3b.as<__bf16>();
     W.img = S->img.as<char>();
+    W.img2 = S->img2.as<__bf16>();
     return W;
 }
 
@@ -850,9 +925,7 @@ void mp_sur_alloc(mp_surrogate S, hipStream_t s) {
     S->Vo.alloc(sizeof(float) * kNParams);
     S->G.alloc(sizeof(float) * kNParams);
     S->img.alloc(kImgBytes);
-    S->w1t.alloc(2 * kD0 * kD1);
-    S->w2t.alloc(2 * kD1 * kD2);
-    S->w2n.alloc(2 * kD1 * kD2);
+    S->img2.alloc(kImg2Bytes);
     S->w3b.alloc(2 * kD2 * 4);
     MP_HIP(hipMemsetAsync(S->img.p, 0, kImgBytes, s));
     MP_HIP(hipMemcpyAsync(S->img.as<char>() + kImgFQ, S->info.freqs, sizeof(float) * 32, hipMemcpyHostToDevice, s));
@@ -923,16 +996,11 @@ void mp_sur_ensure_batch(mp_surrogate S, int64_t cap) {
     const size_t b = (size_t)bp;
     S->bxyz.alloc(sizeof(float) * 3 * b);
     S->btgt.alloc(sizeof(float) * 4 * b);
-    S->X.alloc(2 * kD0 * b);
     S->XT.alloc(2 * kD0 * b);
-    S->Z1.alloc(sizeof(float) * kD1 * b);
-    S->H1.alloc(2 * kD1 * b);
     S->H1T.alloc(2 * kD1 * b);
-    S->Z2.alloc(sizeof(float) * kD2 * b);
-    S->H2.alloc(2 * kD2 * b);
+    S->H2T.alloc(2 * kD2 * b);
     S->dY.alloc(sizeof(float) * 4 * b);
     S->sse.alloc(sizeof(float) * b);
-    S->dZ2.alloc(2 * kD2 * b);
     S->dZ2T.alloc(2 * kD2 * b);
     S->dZ1T.alloc(2 * kD1 * b);
     const size_t ns = b / kRedChunk;
@@ -947,75 +1015,38 @@ void mp_sur_ensure_batch(mp_surrogate S, int64_t cap) {
 void mp_sur_grad_step(mp_surrogate S, int32_t n_real, bool update, float lr, float* loss_dev, hipStream_t s) {
     const int32_t bp = padded_rows(n_real);
     if (bp > S->cap) mp_throw(MP_E_STATE, "surrogate batch buffers too small");
-    FeatArgs F;
-    F.xyz = S->bxyz.as<float>();
-    F.X = S->X.as<__bf16>();
-    F.XT = S->XT.as<__bf16>();
-    F.bp = bp;
+    TrainArgs T;
+    T.img = S->img.as<uint4>();
+    T.img2 = S->img2.as<uint4>();
+    T.w3b = S->w3b.as<__bf16>();
+    T.xyz = S->bxyz.as<float>();
+    T.tgt = S->btgt.as<float4>();
+    T.XT = S->XT.as<__bf16>();
+    T.H1T = S->H1T.as<__bf16>();
+    T.H2T = S->H2T.as<__bf16>();
+    T.dZ2T = S->dZ2T.as<__bf16>();
+    T.dZ1T = S->dZ1T.as<__bf16>();
+    T.dY = S->dY.as<float4>();
+    T.sse = S->sse.as<float>();
+    T.bp = bp;
+    T.n_real = n_real;
+    T.two_over_n = (float)(2.0 / (double)n_real);
     for (int a = 0; a < 3; ++a) {
-        F.lo[a] = S->info.lo[a];
-        F.inv[a] = S->info.inv_ext[a];
+        T.lo[a] = S->info.lo[a];
+        T.inv[a] = S->info.inv_ext[a];
     }
-    for (int l = 0; l < 32; ++l) F.fq[l] = S->info.freqs[l];
-    k_features<<<(bp + 255) / 256, 256, 0, s>>>(F);
-    MP_CHECK_LAUNCH();
-    const float* P = S->P.as<float>();
-
-    GemmArgs g{};
-    // Z1 = X W1 (+ b1), H1 = silu(Z1), H1T
-    g.A = S->X.as<__bf16>();
-    g.B = S->w1t.as<__bf16>();
-    g.M = bp; g.N = kD1; g.K = kD0; g.kslice = kD0;
-    g.bias = P + kOffB1;
-    g.Z = S->Z1.as<float>();
-    g.H = S->H1.as<__bf16>();
-    g.HT = S->H1T.as<__bf16>();
-    k_gemm_nt<EPI_ACT><<<dim3(bp / 64, 1, 1), 256, 0, s>>>(g);
-    MP_CHECK_LAUNCH();
-    // Z2 = H1 W2 (+ b2), H2 = silu(Z2)
-    g = GemmArgs{};
-    g.A = S->H1.as<__bf16>();
-    g.B = S->w2t.as<__bf16>();
-    g.M = bp; g.N = kD2; g.K = kD1; g.kslice = kD1;
-    g.bias = P + kOffB2;
-    g.Z = S->Z2.as<float>();
-    g.H = S->H2.as<__bf16>();
-    g.HT = nullptr;
-    k_gemm_nt<EPI_ACT><<<dim3(bp / 64, 1, 1), 256, 0, s>>>(g);
-    MP_CHECK_LAUNCH();
-    // output layer and its backward
-    L3Args L;
-    L.H2 = S->H2.as<__bf16>();
-    L.Z2 = S->Z2.as<float>();
-    L.w3b = S->w3b.as<__bf16>();
-    L.b3 = P + kOffB3;
-    L.tgt = S->btgt.as<float4>();
-    L.dY = S->dY.as<float4>();
-    L.sse = S->sse.as<float>();
-    L.dZ2 = S->dZ2.as<__bf16>();
-    L.dZ2T = S->dZ2T.as<__bf16>();
-    L.bp = bp;
-    L.n_real = n_real;
-    L.two_over_n = (float)(2.0 / (double)n_real);
-    k_out_layer<<<bp / 256, 256, 0, s>>>(L);
-    MP_CHECK_LAUNCH();
-    // dZ1 = (dZ2 W2^T) silu'(Z1), stored transposed
-    g = GemmArgs{};
-    g.A = S->dZ2.as<__bf16>();
-    g.B = S->w2n.as<__bf16>();
-    g.M = bp; g.N = kD1; g.K = kD2; g.kslice = kD2;
-    g.Zin = S->Z1.as<float>();
-    g.HT = S->dZ1T.as<__bf16>();
-    k_gemm_nt<EPI_BACK><<<dim3(bp / 64, 1, 1), 256, 0, s>>>(g);
+    const int tiles = bp / 32;
+    const int blocks = std::max(1, std::min(S->cus, (tiles + kTrainThreads / 64 - 1) / (kTrainThreads / 64)));
+    k_train_fb<<<blocks, kTrainThreads, 0, s>>>(T);
     MP_CHECK_LAUNCH();
     const int nsplit = bp / kRedChunk;
     // dW2 = H1^T dZ2 (split over samples)
-    g = GemmArgs{};
+    GemmArgs g{};
     g.A = S->H1T.as<__bf16>();
     g.B = S->dZ2T.as<__bf16>();
     g.M = kD1; g.N = kD2; g.K = bp; g.kslice = kRedChunk;
     g.out = S->pw2.as<float>();
-    k_gemm_nt<EPI_PARTIAL><<<dim3(kD1 / 64, kD2 / 128, nsplit), 256, 0, s>>>(g);
+    k_gemm_nt<<<dim3(kD1 / 64, kD2 / 128, nsplit), 256, 0, s>>>(g);
     MP_CHECK_LAUNCH();
     // dW1 = X^T dZ1
     g = GemmArgs{};
@@ -1023,13 +1054,13 @@ void mp_sur_grad_step(mp_surrogate S, int32_t n_real, bool update, float lr, flo
     g.B = S->dZ1T.as<__bf16>();
     g.M = kD0; g.N = kD1; g.K = bp; g.kslice = kRedChunk;
     g.out = S->pw1.as<float>();
-    k_gemm_nt<EPI_PARTIAL><<<dim3(kD0 / 64, kD1 / 128, nsplit), 256, 0, s>>>(g);
+    k_gemm_nt<<<dim3(kD0 / 64, kD1 / 128, nsplit), 256, 0, s>>>(g);
     MP_CHECK_LAUNCH();
     RedArgs R;
-    R.H2 = S->H2.as<__bf16>();
+    R.H2T = S->H2T.as<__bf16>();
     R.dY = S->dY.as<float4>();
     R.sse = S->sse.as<float>();
-    R.dZ2 = S->dZ2.as<__bf16>();
+    R.dZ2T = S->dZ2T.as<__bf16>();
     R.dZ1T = S->dZ1T.as<__bf16>();
     R.out = S->pl3.as<float>();
     R.bp = bp;
