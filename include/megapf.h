@@ -280,7 +280,10 @@ MP_API mp_status mp_scan_upload(mp_filter f, const float* xyz, const float* cov6
  *   log-sum-exp, post_iters propagation rounds, renormalisation, argmax.
  * Asynchronous; nothing synchronises the host.  Errors: MP_E_STATE before the
  * first mp_scan_upload, MP_E_ARG for non-finite dT/cov_dT or a covariance that
- * is not positive semi-definite. */
+ * is not positive semi-definite, MP_E_OOM when the step's work buffers (sized
+ * by the particle count and the scan: 116 bytes per particle per 1024 scan
+ * points for the likelihood's partial sums) cannot be allocated; in every
+ * error case nothing has been launched and the filter is unchanged. */
 MP_API mp_status mp_filter_step(mp_filter f, const float dT[7], const float cov_dT[36], void* stream);
 
 typedef struct {

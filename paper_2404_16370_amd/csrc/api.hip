@@ -641,6 +641,9 @@ extern "C" mp_status mp_filter_step(mp_filter f, const float dT[7], const float 
         float dq[7], L[36];
         bool noise = false;
         if (dT) mp_prepare_prediction(dT, cov_dT, dq, L, noise);
+        // every work buffer of the step is sized before anything is launched,
+        // so that a failed allocation leaves the filter as it was
+        mp_reserve_step(f);
         for (int st = 0; st < MP_NUM_STAGES; ++st)
             if (st != MP_STAGE_SCAN) f->ev_count[st] = 0;
         // check of the learned scorer (before the step, on the current particles)

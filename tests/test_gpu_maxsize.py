@@ -113,3 +113,30 @@ def test_min_particles(O):
     assert np.linalg.norm(q["poses"][0, 4:7] - pose[0, 4:7]) < 0.05
     assert np.array_equal(f.debug_get("nbr"), np.zeros((1, 1), np.int32))
     f.close()
+
+
+def test_out_of_memory_leaves_filter_usable():
+    # 2^26 particles and a 65,536-point scan: the likelihood's partial sums
+    # alone (64 chunks x 29 floats per particle) need 498 GB, more than the
+    # device holds; the step fails with MP_E_OOM before launching anything,
+    # and the same filter then steps with a small scan
+    w = S.build_workload("room", map_points=200_000, scan_points=1000)
+    m = M.Map(w["map_xyz"], voxel=0.5)
+    info = m.info()
+    p = M.mp_filter_default_params(n_particles=N, k=8, lsh_bits=24, svgd_iters=1, post_iters=1, window_c=8,
+                                   d_max=1.0, seed=SEED)
+    f = M.Filter(m, p, box=(info["box_min"], info["box_max"]))
+    reps = 66
+    big = np.concatenate([w["scans"][0] + np.float32(0.01 * r) for r in range(reps)])[:65536]
+    f.scan_upload(np.ascontiguousarray(big.astype(np.float32)))
+    head = f.debug_get("poses")[:4096].copy()
+    print("stepping %d particles with a %d-point scan (expecting MP_E_OOM)" % (N, len(big)), flush=True)
+    with pytest.raises(M.MegaPFError) as e:
+        f.step()
+    assert e.value.status == M.MP_E_OOM
+    assert np.array_equal(f.debug_get("poses")[:4096], head)
+    f.scan_upload(np.ascontiguousarray(w["scans"][0][:256]))
+    f.step()
+    q = f.posterior_query()
+    assert q["frame"] == 1 and np.isfinite(q["map_weight"])
+    f.close()
