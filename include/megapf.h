@@ -352,6 +352,11 @@ MP_API mp_status mp_stage_times(mp_filter f, float* ms_out, int32_t* counts_out)
  *   "scan_walk" the same records in the likelihood's walk order (Morton order
  *             of the points on a grid of half the map voxel)
  *   "tlsh"    8 float T^LSH of the last LSH pass
+ *   "sort_wait" uint32, 0 after a good bucket sort; 1 if a workgroup of the
+ *             last one stopped waiting for the digit counts of the tiles
+ *             before it (its wait is bounded), 2 if a key's sorted place fell
+ *             outside the output (keys changed during the sort); then that
+ *             sort's order is wrong
  *   "capture_hb"  int32 (set only)
  * bytes must equal the named buffer's size.  mp_debug_stage runs one stage
  * on the current state (iteration selects the LSH frame counter; dT/cov_dT as
@@ -374,6 +379,19 @@ MP_API mp_status mp_debug_stage(mp_filter f, int32_t stage, int32_t iteration, c
  * POINT, and every error of mp_map_build. */
 MP_API mp_status mp_debug_map_point_knn(const float* xyz, int64_t n, const mp_map_params* params, int32_t* knn_out,
                                         void* stream);
+
+/* Test access to the stable radix sort that distributes particles into LSH
+ * buckets (Alg. 1, distribute loop): sorts keys[0..n), each below 2^bits
+ * (bits 1..32; the sort makes one pass per 8 bits), equal keys keeping their
+ * input order, and writes the sorted keys to keys_out and, for each sorted
+ * position, the input index of its key to order_out.  keys (n uint32), keys_out (n uint32) and
+ * order_out (n int32) are host or device pointers; synchronises.  Errors:
+ * MP_E_ARG for a null pointer, n <= 0 or bits outside 1..32,
+ * MP_E_UNSUPPORTED for n >= 2^30, MP_E_HIP if a workgroup stopped waiting
+ * for the digit counts of the tiles before it (its wait is bounded) or a
+ * key's place fell outside the output. */
+MP_API mp_status mp_debug_sort_u32(const uint32_t* keys, int64_t n, int32_t bits, uint32_t* keys_out,
+                                   int32_t* order_out, void* stream);
 
 /* ------------------------------------------------------------ batch */
 /* Several independent filters (instances: different maps, particle counts,

@@ -191,6 +191,41 @@ extern "C" mp_status mp_debug_map_point_knn(const float* xyz, int64_t n, const m
     });
 }
 
+namespace {
+__global__ void k_iota(int32_t* v, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) v[i] = (int32_t)i;
+}
+}  // namespace
+
+extern "C" mp_status mp_debug_sort_u32(const uint32_t* keys, int64_t n, int32_t bits, uint32_t* keys_out,
+                                       int32_t* order_out, void* stream) {
+    return guarded("mp_debug_sort_u32", [&]() {
+        if (!keys || !keys_out || !order_out || n <= 0) mp_throw(MP_E_ARG, "null argument or n <= 0");
+        if (bits < 1 || bits > 32) mp_throw(MP_E_ARG, "bits must be 1..32");
+        if (n >= ((int64_t)1 << 30)) mp_throw(MP_E_UNSUPPORTED, "2^30 or more keys");
+        hipStream_t s = as_stream(stream);
+        DevMem k, k2, v, v2, scratch;
+        k.alloc(sizeof(uint32_t) * (size_t)n);
+        k2.alloc(sizeof(uint32_t) * (size_t)n);
+        v.alloc(sizeof(int32_t) * (size_t)n);
+        v2.alloc(sizeof(int32_t) * (size_t)n);
+        scratch.alloc(mp_radix_scratch_bytes(n));
+        mp_fill_u32(mp_radix_wait_flag(scratch), 0u, 1, s);
+        MP_HIP(hipMemcpyAsync(k.p, keys, sizeof(uint32_t) * (size_t)n, hipMemcpyDefault, s));
+        k_iota<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(v.as<int32_t>(), n);
+        MP_CHECK_LAUNCH();
+        mp_radix_sort_u32(k.as<uint32_t>(), v.as<int32_t>(), k2.as<uint32_t>(), v2.as<int32_t>(), n, bits, scratch, s);
+        uint32_t waited = 0;
+        MP_HIP(hipMemcpyAsync(keys_out, k.p, sizeof(uint32_t) * (size_t)n, hipMemcpyDefault, s));
+        MP_HIP(hipMemcpyAsync(order_out, v.p, sizeof(int32_t) * (size_t)n, hipMemcpyDefault, s));
+        MP_HIP(hipMemcpyAsync(&waited, mp_radix_wait_flag(scratch), 4, hipMemcpyDeviceToHost, s));
+        MP_HIP(hipStreamSynchronize(s));
+        if (waited == 1) mp_throw(MP_E_HIP, "a sort workgroup stopped waiting for its predecessors' digit counts");
+        if (waited) mp_throw(MP_E_HIP, "a key's sorted place fell outside the output");
+    });
+}
+
 extern "C" mp_status mp_map_get_info(mp_map map, mp_map_info* out) {
     return guarded("mp_map_get_info", [&]() {
         if (!map || !out) mp_throw(MP_E_ARG, "null argument");
@@ -772,6 +807,7 @@ static NamedBuf lookup_buf(mp_filter f, const char* name) {
     if (s == "scan_walk") return {f->scan.p, f->scan_n > 0 ? 48 * (size_t)f->scan_n : 0, false};
     if (s == "odo_nn") return {f->odo_nn.p, f->odo_nn.p && f->scan_n > 0 ? 4 * (size_t)f->scan_n : 0, false};
     if (s == "tlsh") return {f->tlsh.p, 32, false};
+    if (s == "sort_wait") return {f->hist.p ? (void*)mp_radix_wait_flag(f->hist) : nullptr, f->hist.p ? 4u : 0u, false};
     mp_throw(MP_E_ARG, "unknown buffer '%s'", s.c_str());
 }
 

@@ -195,6 +195,11 @@ int mp_radix_passes(int64_t n, int bits);
 // the result is in (keys_alt, vals_alt)
 void mp_radix_sort_u32_inplace_parity(uint32_t* keys, int32_t* vals, uint32_t* keys_alt, int32_t* vals_alt, int64_t n,
                                       int bits, DevMem& scratch, hipStream_t s);
+// device word of a 32-bit sort's scratch, zero after a good sort: 1 if a
+// workgroup stopped waiting for its predecessors' counts, 2 if a key's place
+// fell outside the output (its input changed while it ran); neither is
+// expected, and the output of that sort is then wrong
+uint32_t* mp_radix_wait_flag(DevMem& scratch);
 
 // map (map_build.hip)
 void mp_build_map(mp_map m, const float* xyz_dev, int64_t n, hipStream_t s);

@@ -103,7 +103,7 @@ class mp_posterior(C.Structure):
 EXPORTS = ["mp_map_default_params", "mp_map_build", "mp_map_get_info", "mp_map_get_gauss", "mp_map_lookup",
            "mp_map_destroy", "mp_filter_default_params", "mp_filter_init", "mp_filter_destroy", "mp_scan_upload",
            "mp_filter_step", "mp_posterior_query", "mp_last_error", "mp_stage_times", "mp_debug_get",
-           "mp_debug_set", "mp_debug_stage", "mp_debug_map_point_knn", "mp_surrogate_default_params", "mp_surrogate_create",
+           "mp_debug_set", "mp_debug_stage", "mp_debug_map_point_knn", "mp_debug_sort_u32", "mp_surrogate_default_params", "mp_surrogate_create",
            "mp_surrogate_destroy", "mp_surrogate_get_info", "mp_surrogate_label", "mp_surrogate_eval",
            "mp_surrogate_set_data", "mp_surrogate_train", "mp_surrogate_grad", "mp_surrogate_get_params",
            "mp_surrogate_set_params", "mp_filter_set_surrogate", "mp_filter_set_surrogate_check", "mp_odometry_default_params", "mp_odometry", "mp_odometry_noalloc", "mp_smoother_default_params",
@@ -158,6 +158,7 @@ def lib():
     L.mp_debug_set.argtypes = [vp, C.c_char_p, vp, i64, vp]
     L.mp_debug_stage.argtypes = [vp, i32, i32, vp, vp, vp]
     L.mp_debug_map_point_knn.argtypes = [vp, i64, C.POINTER(mp_map_params), vp, vp]
+    L.mp_debug_sort_u32.argtypes = [vp, i64, i32, vp, vp, vp]
     L.mp_surrogate_default_params.argtypes = [C.POINTER(mp_surrogate_params)]
     L.mp_surrogate_default_params.restype = None
     L.mp_surrogate_create.argtypes = [vp, C.POINTER(mp_surrogate_params), vp, C.POINTER(vp)]
@@ -303,6 +304,17 @@ def debug_map_point_knn(xyz, voxel, point_k=10, point_search=2, nnf_radius=2, mi
     return out
 
 
+def debug_sort_u32(keys, bits, stream=None):
+    """Stable sort of uint32 keys by their low `bits` bits with the library's
+    bucket sort (mp_debug_sort_u32): (sorted keys, input index of each)."""
+    keep = []
+    n = _nrows(keys)
+    ko = np.zeros(n, np.uint32)
+    order = np.zeros(n, np.int32)
+    _check(lib().mp_debug_sort_u32(_ptr(keys, np.uint32, keep), n, bits, _ptr(ko), _ptr(order), _stream(stream)))
+    return ko, order
+
+
 # ------------------------------------------------------------------ filter
 def mp_filter_default_params(**kw):
     p = mp_filter_params()
@@ -334,6 +346,7 @@ _DEBUG_LAYOUT = {  # name -> (dtype, shape as a function of (n, K, scan_n))
     "scan_walk": (np.float32, lambda n, K, s: (s, 12)),
     "odo_nn": (np.int32, lambda n, K, s: (s,)),
     "tlsh": (np.float32, lambda n, K, s: (8,)),
+    "sort_wait": (np.uint32, lambda n, K, s: (1,)),
 }
 
 
