@@ -1013,5 +1013,23 @@ def main():
     print(json.dumps(res), flush=True)
 
 
+def log_children():
+    """Processes this run started that are still alive at its end (none are
+    expected): named on stderr so that a leftover can be traced."""
+    try:
+        import psutil
+        kids = psutil.Process().children(recursive=True)
+    except Exception:
+        return
+    for k in kids:
+        try:
+            log("child process still alive at exit: pid %d %s" % (k.pid, " ".join(k.cmdline())[:200]))
+        except Exception:
+            pass
+    if not kids:
+        log("no child processes alive at exit")
+
+
 if __name__ == "__main__":
     main()
+    log_children()
