@@ -90,6 +90,7 @@ struct mp_surrogate_s {
     int32_t cap = 0;                // padded batch rows the work buffers hold
     DevMem bxyz, btgt, XT, H1T, H2T, dY, sse, dZ2T, dZ1T;   // per-batch activations, unit-major
     DevMem pw1, pw2, pl3;           // split-K and chunk partial sums
+    DevMem pf;                      // per-workgroup partial gradients of the fused step
     DevMem losses;                  // per-step loss (float)
     int cus = 1;                    // compute units of the device (persistent-grid size)
     int users = 0;

@@ -702,6 +702,327 @@ __global__ __launch_bounds__(kAdamQ * kAdamSub) void k_adam(AdamArgs A) {
     publish(A.W, q, w);
 }
 
+// ------------------------------------------------------------ fused training step
+// One gradient evaluation of the batch in one launch.  A workgroup of four
+// waves takes 32-sample tiles; wave w owns the 32-unit block w of both hidden
+// layers, and its fragments of W1^T (rows: layer-1 units of the block), W2^T
+// (rows: layer-2 units) and W2 (rows: layer-1 units, for the input gradient)
+// stay in registers for the whole launch.  Per tile the activations pass
+// through LDS as sample-major rows: features, H1 and dZ2 shared by the four
+// waves, H2 and dZ1 of each wave's own block.  The weight gradients are
+// products over samples: their operands are read from those rows eight
+// samples at a time (slot i of lane half h at k-step kq is sample
+// 16 kq + 8 h + i on both sides), and each wave accumulates its share (the
+// dW1 columns, dW2 rows and dW3 rows of its block) in accumulation registers
+// over the workgroup's tiles.  The workgroup writes one partial gradient and
+// its squared error; the Adam kernel adds the partials in a fixed order.
+// Rounding points as in k_train_fb: features, H1, H2, dZ2 and dZ1 in bf16;
+// pre-activations, outputs, dY and dH2 in FP32; dY enters the dW3 product as
+// a bf16 pair (hi + lo).
+constexpr int kFThreads = 256;
+constexpr int kXS = kD0 + 8;   // feature row stride (bf16): 400 B
+constexpr int kHS = kD1 + 8;   // hidden row stride (bf16): 272 B
+constexpr int kOS = 32 + 8;    // own-block row stride (bf16): 80 B
+constexpr int kFPart = kNParams + 1;   // partial gradient + squared error of a workgroup
+
+struct FusedArgs {
+    const uint4* __restrict__ img;     // inference image: W1^T, W2^T fragments; b1, b2, b3; frequencies
+    const uint4* __restrict__ img2;    // W2 fragments of the input gradient
+    const __bf16* __restrict__ w3b;    // [128][4]
+    const float* __restrict__ xyz;     // [bp][3]
+    const float4* __restrict__ tgt;    // [bp] scaled targets
+    float* __restrict__ part;          // [gridDim.x][kFPart]
+    int32_t tiles, n_real;
+    float two_over_n;
+    float lo[3], inv[3];
+};
+
+__device__ __forceinline__ void store4(__bf16* p, float a, float b, float c, float d) {
+    typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
+    *reinterpret_cast<bf16x4*>(p) = bf16x4{(__bf16)a, (__bf16)b, (__bf16)c, (__bf16)d};
+}
+
+__global__ __launch_bounds__(kFThreads) void k_train_fused(FusedArgs A) {
+    __shared__ __attribute__((aligned(16))) __bf16 xs[32 * kXS];
+    __shared__ __attribute__((aligned(16))) __bf16 h1s[32 * kHS];
+    __shared__ __attribute__((aligned(16))) __bf16 dz2s[32 * kHS];
+    __shared__ __attribute__((aligned(16))) __bf16 h2o[4][32 * kOS];
+    __shared__ __attribute__((aligned(16))) __bf16 dz1o[4][32 * kOS];
+    __shared__ float ys[4][32][4];
+    __shared__ float dys[32][4];
+    __shared__ float w3s[kD2 * 4];
+    __shared__ float bias[kD1 + kD2 + 4];
+    __shared__ __attribute__((aligned(16))) float fqs[32];
+    const char* img = reinterpret_cast<const char*>(A.img);
+    for (int q = threadIdx.x; q < kD2 * 4; q += kFThreads) w3s[q] = (float)A.w3b[q];
+    for (int q = threadIdx.x; q < kD1; q += kFThreads) {
+        bias[q] = reinterpret_cast<const float*>(img + kImgB1)[q];
+        bias[kD1 + q] = reinterpret_cast<const float*>(img + kImgB2)[q];
+    }
+    if (threadIdx.x < 4) bias[kD1 + kD2 + threadIdx.x] = reinterpret_cast<const float*>(img + kImgB3)[threadIdx.x];
+    if (threadIdx.x < 32) fqs[threadIdx.x] = reinterpret_cast<const float*>(img + kImgFQ)[threadIdx.x];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, m = lane & 31, h = lane >> 5;
+    // this wave's weight fragments
+    const bf16x8* f1 = reinterpret_cast<const bf16x8*>(img + kImgF1);
+    const bf16x8* f2 = reinterpret_cast<const bf16x8*>(img + kImgF2);
+    const bf16x8* f2b = reinterpret_cast<const bf16x8*>(A.img2);
+    bf16x8 a1[12], a2[8], a2b[8];
+#pragma unroll
+    for (int sk = 0; sk < 12; ++sk) a1[sk] = f1[(w * 12 + sk) * 64 + lane];
+#pragma unroll
+    for (int s2 = 0; s2 < 8; ++s2) {
+        a2[s2] = f2[(w * 8 + s2) * 64 + lane];
+        a2b[s2] = f2b[(w * 8 + s2) * 64 + lane];
+    }
+    f32x16 g1[6], g2[4], g3;
+#pragma unroll
+    for (int r = 0; r < 6; ++r) g1[r] = f32x16{};
+#pragma unroll
+    for (int r = 0; r < 4; ++r) g2[r] = f32x16{};
+    g3 = f32x16{};
+    float db1 = 0.0f, db2 = 0.0f, sse = 0.0f;
+    float db3[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    __syncthreads();
+    for (int t = blockIdx.x; t < A.tiles; t += gridDim.x) {
+        const int b = 32 * t + m;   // this lane's sample
+        float x[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) x[a] = (A.xyz[3 * b + a] - A.lo[a]) * A.inv[a];
+        // features of k-steps 3w .. 3w + 2 (axis sk / 4, frequencies 8 (sk % 4) + 4 h + 0..3)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const int sk = 3 * w + q;
+            const float4 fr = *reinterpret_cast<const float4*>(fqs + 8 * (sk & 3) + 4 * h);
+            const int ax = sk >> 2;
+            const float xv = ax == 0 ? x[0] : (ax == 1 ? x[1] : x[2]);
+            __bf16 v0, v1, v2, v3, v4, v5, v6, v7;
+            feature_pair(fr.x, xv, v0, v1);
+            feature_pair(fr.y, xv, v2, v3);
+            feature_pair(fr.z, xv, v4, v5);
+            feature_pair(fr.w, xv, v6, v7);
+            *reinterpret_cast<bf16x8*>(xs + m * kXS + 16 * sk + 8 * h) = bf16x8{v0, v1, v2, v3, v4, v5, v6, v7};
+        }
+        __syncthreads();
+        // layer 1 of the block: Z1 = W1^T x + b1 (kept), H1 to the shared rows
+        f32x16 z1;
+#pragma unroll
+        for (int jj = 0; jj < 16; ++jj) z1[jj] = bias[acc_unit(w, jj, h)];
+#pragma unroll
+        for (int sk = 0; sk < 12; ++sk)
+            z1 = mfma32(a1[sk], *reinterpret_cast<const bf16x8*>(xs + m * kXS + 16 * sk + 8 * h), z1);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            store4(h1s + m * kHS + 32 * w + 8 * q + 4 * h, silu_f(z1[4 * q]), silu_f(z1[4 * q + 1]),
+                   silu_f(z1[4 * q + 2]), silu_f(z1[4 * q + 3]));
+        __syncthreads();
+        // layer 2 of the block: Z2 = W2^T H1 + b2 (kept); H2 of the block; the
+        // block's share of the output layer
+        f32x16 z2;
+#pragma unroll
+        for (int jj = 0; jj < 16; ++jj) z2[jj] = bias[kD1 + acc_unit(w, jj, h)];
+#pragma unroll
+        for (int s2 = 0; s2 < 8; ++s2) {
+            const __bf16* r = h1s + m * kHS + 32 * (s2 >> 1) + 16 * (s2 & 1) + 4 * h;
+            typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
+            const bf16x4 lo4 = *reinterpret_cast<const bf16x4*>(r);
+            const bf16x4 hi4 = *reinterpret_cast<const bf16x4*>(r + 8);
+            z2 = mfma32(a2[s2], bf16x8{lo4[0], lo4[1], lo4[2], lo4[3], hi4[0], hi4[1], hi4[2], hi4[3]}, z2);
+        }
+        float y0 = 0.0f, y1 = 0.0f, y2 = 0.0f, y3 = 0.0f;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            float hv[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int jj = 4 * q + i;
+                hv[i] = (float)(__bf16)silu_f(z2[jj]);
+                const float* wv = w3s + 4 * acc_unit(w, jj, h);
+                y0 = __builtin_fmaf(wv[0], hv[i], y0);
+                y1 = __builtin_fmaf(wv[1], hv[i], y1);
+                y2 = __builtin_fmaf(wv[2], hv[i], y2);
+                y3 = __builtin_fmaf(wv[3], hv[i], y3);
+            }
+            store4(h2o[w] + m * kOS + 8 * q + 4 * h, hv[0], hv[1], hv[2], hv[3]);
+        }
+        y0 += __shfl_xor(y0, 32, 64);
+        y1 += __shfl_xor(y1, 32, 64);
+        y2 += __shfl_xor(y2, 32, 64);
+        y3 += __shfl_xor(y3, 32, 64);
+        if (h == 0) {
+            ys[w][m][0] = y0;
+            ys[w][m][1] = y1;
+            ys[w][m][2] = y2;
+            ys[w][m][3] = y3;
+        }
+        __syncthreads();
+        // loss and dY of the tile's samples (the four blocks' shares added in order)
+        float yv[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            yv[c] = bias[kD1 + kD2 + c] + (((ys[0][m][c] + ys[1][m][c]) + ys[2][m][c]) + ys[3][m][c]);
+        const float4 tg = A.tgt[b];
+        const bool valid = b < A.n_real;
+        const float r0 = yv[0] - tg.x, r1 = yv[1] - tg.y, r2 = yv[2] - tg.z, r3 = yv[3] - tg.w;
+        const float e = valid ? __builtin_fmaf(r0, r0, __builtin_fmaf(r1, r1, __builtin_fmaf(r2, r2, r3 * r3))) : 0.0f;
+        const float kk = valid ? A.two_over_n : 0.0f;
+        const float d0 = r0 * kk, d1 = r1 * kk, d2 = r2 * kk, d3 = r3 * kk;
+        if (w == 0 && h == 0) {
+            sse += e;
+            db3[0] += d0;
+            db3[1] += d1;
+            db3[2] += d2;
+            db3[3] += d3;
+            dys[m][0] = d0;
+            dys[m][1] = d1;
+            dys[m][2] = d2;
+            dys[m][3] = d3;
+        }
+        // dZ2 = (W3 dY) silu'(Z2) of the block, to the shared rows
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            float dv[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int jj = 4 * q + i;
+                const float* wv = w3s + 4 * acc_unit(w, jj, h);
+                const float dh = __builtin_fmaf(wv[0], d0, __builtin_fmaf(wv[1], d1, __builtin_fmaf(wv[2], d2, wv[3] * d3)));
+                dv[i] = dh * silu_grad_f(z2[jj]);
+            }
+            store4(dz2s + m * kHS + 32 * w + 8 * q + 4 * h, dv[0], dv[1], dv[2], dv[3]);
+        }
+        __syncthreads();
+        // dH1 = W2 dZ2 of the block, dZ1 = dH1 silu'(Z1) to the block's rows
+        f32x16 g = {};
+#pragma unroll
+        for (int s2 = 0; s2 < 8; ++s2) {
+            const __bf16* r = dz2s + m * kHS + 32 * (s2 >> 1) + 16 * (s2 & 1) + 4 * h;
+            typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
+            const bf16x4 lo4 = *reinterpret_cast<const bf16x4*>(r);
+            const bf16x4 hi4 = *reinterpret_cast<const bf16x4*>(r + 8);
+            g = mfma32(a2b[s2], bf16x8{lo4[0], lo4[1], lo4[2], lo4[3], hi4[0], hi4[1], hi4[2], hi4[3]}, g);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            store4(dz1o[w] + m * kOS + 8 * q + 4 * h, g[4 * q] * silu_grad_f(z1[4 * q]),
+                   g[4 * q + 1] * silu_grad_f(z1[4 * q + 1]), g[4 * q + 2] * silu_grad_f(z1[4 * q + 2]),
+                   g[4 * q + 3] * silu_grad_f(z1[4 * q + 3]));
+        // the block's dZ1 rows are read back by this wave only
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // weight gradients: products over the tile's samples
+#pragma unroll
+        for (int kq = 0; kq < 2; ++kq) {
+            const int s0 = 16 * kq + 8 * h;
+            bf16x8 bz1, ah, a3, bhi, blo;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                bz1[i] = dz1o[w][(s0 + i) * kOS + m];
+                ah[i] = h1s[(s0 + i) * kHS + 32 * w + m];
+                a3[i] = h2o[w][(s0 + i) * kOS + m];
+                const float d = m < 4 ? dys[s0 + i][m & 3] : 0.0f;
+                bhi[i] = (__bf16)d;
+                blo[i] = (__bf16)(d - (float)bhi[i]);
+                db1 += (float)bz1[i];
+            }
+#pragma unroll
+            for (int rb = 0; rb < 6; ++rb) {
+                bf16x8 ax;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) ax[i] = xs[(s0 + i) * kXS + 32 * rb + m];
+                g1[rb] = mfma32(ax, bz1, g1[rb]);
+            }
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb) {
+                bf16x8 bz;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) bz[i] = dz2s[(s0 + i) * kHS + 32 * cb + m];
+                if (cb == w) {
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) db2 += (float)bz[i];
+                }
+                g2[cb] = mfma32(ah, bz, g2[cb]);
+            }
+            g3 = mfma32(a3, bhi, g3);
+            g3 = mfma32(a3, blo, g3);
+        }
+        __syncthreads();   // the tile's rows are read; the next tile overwrites them
+    }
+    // this workgroup's partial gradient, in parameter order
+    float* out = A.part + (size_t)blockIdx.x * kFPart;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const int row = 8 * (j >> 2) + 4 * h + (j & 3);   // accumulator row of register j
+#pragma unroll
+        for (int rb = 0; rb < 6; ++rb) out[kOffW1 + (32 * rb + row) * kD1 + 32 * w + m] = g1[rb][j];
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) out[kOffW2 + (32 * w + row) * kD2 + 32 * cb + m] = g2[cb][j];
+        if (m < 4) out[kOffW3 + (32 * w + row) * 4 + m] = g3[j];
+    }
+    db1 += __shfl_xor(db1, 32, 64);
+    db2 += __shfl_xor(db2, 32, 64);
+    if (h == 0) {
+        out[kOffB1 + 32 * w + m] = db1;
+        out[kOffB2 + 32 * w + m] = db2;
+    }
+    if (w == 0) {
+#pragma unroll
+        for (int off = 16; off >= 1; off >>= 1) {
+            sse += __shfl_xor(sse, off, 64);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) db3[c] += __shfl_xor(db3[c], off, 64);
+        }
+        if (lane == 0) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) out[kOffB3 + c] = db3[c];
+            out[kNParams] = sse;
+        }
+    }
+}
+
+// Gradient of every parameter from the workgroups' partials (added in a fixed
+// order), the loss, then the Adam update.
+struct AdamSumArgs {
+    float* __restrict__ P;
+    float* __restrict__ Mo;
+    float* __restrict__ Vo;
+    float* __restrict__ G;
+    const float* __restrict__ part;   // [nparts][kFPart]
+    float* __restrict__ loss_out;     // one float
+    int32_t nparts, update;
+    float inv_n, lr, beta1, beta2, eps, c1, c2;
+    PublishArgs W;
+};
+
+__global__ __launch_bounds__(kAdamQ * kAdamSub) void k_adam_sum(AdamSumArgs A) {
+    __shared__ float part[kAdamSub][kAdamQ];
+    const int qi = threadIdx.x % kAdamQ, sub = threadIdx.x / kAdamQ;
+    const int q = blockIdx.x * kAdamQ + qi;   // parameter; kNParams: the squared error
+    float g = 0.0f;
+    if (q <= kNParams)
+        for (int z = sub; z < A.nparts; z += kAdamSub) g += A.part[(size_t)z * kFPart + q];
+    part[sub][qi] = g;
+    __syncthreads();
+    if (sub != 0 || q > kNParams) return;
+    g = 0.0f;
+#pragma unroll
+    for (int r = 0; r < kAdamSub; ++r) g += part[r][qi];
+    if (q == kNParams) {
+        if (A.loss_out) *A.loss_out = g * A.inv_n;
+        return;
+    }
+    A.G[q] = g;
+    if (!A.update) return;
+    const float m = __builtin_fmaf(A.beta1, A.Mo[q], (1.0f - A.beta1) * g);
+    const float v = __builtin_fmaf(A.beta2, A.Vo[q], (1.0f - A.beta2) * g * g);
+    A.Mo[q] = m;
+    A.Vo[q] = v;
+    const float mh = m / A.c1, vh = v / A.c2;
+    const float w = A.P[q] - A.lr * mh / (sqrtf(vh) + A.eps);
+    A.P[q] = w;
+    publish(A.W, q, w);
+}
+
 // ------------------------------------------------------------ inference kernels
 constexpr int kInferThreads = 512;   // 8 waves: two per SIMD share one LDS copy of the weights
 
@@ -1007,6 +1328,7 @@ void mp_sur_ensure_batch(mp_surrogate S, int64_t cap) {
     S->pw1.alloc(sizeof(float) * ns * kD0 * kD1);
     S->pw2.alloc(sizeof(float) * ns * kD1 * kD2);
     S->pl3.alloc(sizeof(float) * ns * kL3Len);
+    S->pf.ensure(sizeof(float) * (size_t)std::max(1, S->cus) * kFPart);
     S->cap = bp;
 }
 
@@ -1015,67 +1337,31 @@ void mp_sur_ensure_batch(mp_surrogate S, int64_t cap) {
 void mp_sur_grad_step(mp_surrogate S, int32_t n_real, bool update, float lr, float* loss_dev, hipStream_t s) {
     const int32_t bp = padded_rows(n_real);
     if (bp > S->cap) mp_throw(MP_E_STATE, "surrogate batch buffers too small");
-    TrainArgs T;
-    T.img = S->img.as<uint4>();
-    T.img2 = S->img2.as<uint4>();
-    T.w3b = S->w3b.as<__bf16>();
-    T.xyz = S->bxyz.as<float>();
-    T.tgt = S->btgt.as<float4>();
-    T.XT = S->XT.as<__bf16>();
-    T.H1T = S->H1T.as<__bf16>();
-    T.H2T = S->H2T.as<__bf16>();
-    T.dZ2T = S->dZ2T.as<__bf16>();
-    T.dZ1T = S->dZ1T.as<__bf16>();
-    T.dY = S->dY.as<float4>();
-    T.sse = S->sse.as<float>();
-    T.bp = bp;
-    T.n_real = n_real;
-    T.two_over_n = (float)(2.0 / (double)n_real);
+    FusedArgs F;
+    F.img = S->img.as<uint4>();
+    F.img2 = S->img2.as<uint4>();
+    F.w3b = S->w3b.as<__bf16>();
+    F.xyz = S->bxyz.as<float>();
+    F.tgt = S->btgt.as<float4>();
+    F.part = S->pf.as<float>();
+    F.tiles = bp / 32;
+    F.n_real = n_real;
+    F.two_over_n = (float)(2.0 / (double)n_real);
     for (int a = 0; a < 3; ++a) {
-        T.lo[a] = S->info.lo[a];
-        T.inv[a] = S->info.inv_ext[a];
+        F.lo[a] = S->info.lo[a];
+        F.inv[a] = S->info.inv_ext[a];
     }
-    const int tiles = bp / 32;
-    const int blocks = std::max(1, std::min(S->cus, (tiles + kTrainThreads / 64 - 1) / (kTrainThreads / 64)));
-    k_train_fb<<<blocks, kTrainThreads, 0, s>>>(T);
+    const int groups = std::max(1, std::min(S->cus, F.tiles));
+    k_train_fused<<<groups, kFThreads, 0, s>>>(F);
     MP_CHECK_LAUNCH();
-    const int nsplit = bp / kRedChunk;
-    // dW2 = H1^T dZ2 (split over samples)
-    GemmArgs g{};
-    g.A = S->H1T.as<__bf16>();
-    g.B = S->dZ2T.as<__bf16>();
-    g.M = kD1; g.N = kD2; g.K = bp; g.kslice = kRedChunk;
-    g.out = S->pw2.as<float>();
-    k_gemm_nt<<<dim3(kD1 / 64, kD2 / 128, nsplit), 256, 0, s>>>(g);
-    MP_CHECK_LAUNCH();
-    // dW1 = X^T dZ1
-    g = GemmArgs{};
-    g.A = S->XT.as<__bf16>();
-    g.B = S->dZ1T.as<__bf16>();
-    g.M = kD0; g.N = kD1; g.K = bp; g.kslice = kRedChunk;
-    g.out = S->pw1.as<float>();
-    k_gemm_nt<<<dim3(kD0 / 64, kD1 / 128, nsplit), 256, 0, s>>>(g);
-    MP_CHECK_LAUNCH();
-    RedArgs R;
-    R.H2T = S->H2T.as<__bf16>();
-    R.dY = S->dY.as<float4>();
-    R.sse = S->sse.as<float>();
-    R.dZ2T = S->dZ2T.as<__bf16>();
-    R.dZ1T = S->dZ1T.as<__bf16>();
-    R.out = S->pl3.as<float>();
-    R.bp = bp;
-    k_reduce_small<<<nsplit, kRedThreads, 0, s>>>(R);
-    MP_CHECK_LAUNCH();
-    AdamArgs A;
+    AdamSumArgs A;
     A.P = S->P.as<float>();
     A.Mo = S->Mo.as<float>();
     A.Vo = S->Vo.as<float>();
     A.G = S->G.as<float>();
-    A.pw1 = S->pw1.as<float>();
-    A.pw2 = S->pw2.as<float>();
-    A.pl3 = S->pl3.as<float>();
+    A.part = S->pf.as<float>();
     A.loss_out = loss_dev;
-    A.nsplit = nsplit;
+    A.nparts = groups;
     A.update = update ? 1 : 0;
     A.inv_n = (float)(1.0 / (double)n_real);
     A.lr = lr;
@@ -1086,7 +1372,7 @@ void mp_sur_grad_step(mp_surrogate S, int32_t n_real, bool update, float lr, flo
     A.c1 = (float)(1.0 - std::pow((double)S->p.beta1, t));
     A.c2 = (float)(1.0 - std::pow((double)S->p.beta2, t));
     A.W = publish_args(S);
-    k_adam<<<(kNParams + kAdamQ - 1) / kAdamQ, kAdamQ * kAdamSub, 0, s>>>(A);
+    k_adam_sum<<<(kFPart + kAdamQ - 1) / kAdamQ, kAdamQ * kAdamSub, 0, s>>>(A);
     MP_CHECK_LAUNCH();
     if (update) S->info.steps += 1;
 }
