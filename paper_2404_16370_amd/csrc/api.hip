@@ -1035,8 +1035,7 @@ extern "C" mp_status mp_surrogate_train(mp_surrogate sur, int32_t steps, float* 
             const int64_t t = sur->info.steps;   // steps taken before this one
             const double frac = std::min(1.0, (double)t / (double)p.total_steps);
             const double lr = p.lr_min + 0.5 * ((double)p.lr - p.lr_min) * (1.0 + std::cos(M_PI * frac));
-            mp_sur_draw_batch(sur, n_real, full, (uint32_t)t, s);
-            mp_sur_grad_step(sur, n_real, true, (float)lr, sur->losses.as<float>() + k, s);
+            mp_sur_train_step(sur, n_real, full, (uint32_t)t, (float)lr, sur->losses.as<float>() + k, s);
         }
         if (loss_out) {
             MP_HIP(hipMemcpyAsync(loss_out, sur->losses.p, sizeof(float) * (size_t)steps, hipMemcpyDeviceToHost, s));

@@ -276,4 +276,7 @@ float mp_sur_check(mp_filter f, int32_t pstride, hipStream_t s);
 void mp_sur_ensure_batch(mp_surrogate S, int64_t cap);
 void mp_sur_draw_batch(mp_surrogate S, int32_t n_real, bool full, uint32_t step, hipStream_t s);
 void mp_sur_grad_step(mp_surrogate S, int32_t n_real, bool update, float lr, float* loss_dev, hipStream_t s);
+// one Adam step on a batch drawn from the training set (step counter `step`)
+void mp_sur_train_step(mp_surrogate S, int32_t n_real, bool full, uint32_t step, float lr, float* loss_dev,
+                       hipStream_t s);
 void mp_sur_likelihood(mp_filter f, float* partial, hipStream_t s);

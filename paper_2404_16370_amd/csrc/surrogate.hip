@@ -722,20 +722,48 @@ __global__ __launch_bounds__(kAdamQ * kAdamSub) void k_adam(AdamArgs A) {
 constexpr int kFThreads = 256;
 constexpr int kXS = kD0 + 8;   // feature row stride (bf16): 400 B
 constexpr int kHS = kD1 + 8;   // hidden row stride (bf16): 272 B
-constexpr int kOS = 32 + 8;    // own-block row stride (bf16): 80 B
+constexpr int kTS = 32 + 8;    // transposed row stride (bf16, one unit's 32 samples): 80 B
 constexpr int kFPart = kNParams + 1;   // partial gradient + squared error of a workgroup
+constexpr int kFPartPad = (kFPart + 3) / 4 * 4;   // partial row stride: 16-byte aligned rows
 
 struct FusedArgs {
     const uint4* __restrict__ img;     // inference image: W1^T, W2^T fragments; b1, b2, b3; frequencies
     const uint4* __restrict__ img2;    // W2 fragments of the input gradient
     const __bf16* __restrict__ w3b;    // [128][4]
-    const float* __restrict__ xyz;     // [bp][3]
-    const float4* __restrict__ tgt;    // [bp] scaled targets
-    float* __restrict__ part;          // [gridDim.x][kFPart]
-    int32_t tiles, n_real;
+    const float* __restrict__ xyz;     // staged batch [bp][3] (draw == 0; zero rows past n_real)
+    const float4* __restrict__ tgt;    // staged scaled targets [bp]
+    const float* __restrict__ dxyz;    // training set (draw == 1): points
+    const float4* __restrict__ dlab;   // scaled labels
+    float* __restrict__ part;          // [gridDim.x][kFPartPad]
+    int64_t n_data;
+    int32_t tiles, n_real, draw, full;
+    uint32_t step;
+    uint64_t seed;
     float two_over_n;
     float lo[3], inv[3];
 };
+
+// Sample b of the batch: the staged row, or drawn from the training set as
+// k_draw_batch draws it (the whole set in order when it fits the batch, else
+// index floor(x n / 2^64) of a Philox draw x); zero past n_real.
+__device__ __forceinline__ void fused_sample(const FusedArgs& A, int b, float4& p, float4& tg) {
+    p = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    tg = p;
+    if (!A.draw) {
+        p = make_float4(A.xyz[3 * b], A.xyz[3 * b + 1], A.xyz[3 * b + 2], 0.0f);
+        tg = A.tgt[b];
+        return;
+    }
+    if (b >= A.n_real) return;
+    int64_t idx = b;
+    if (!A.full) {
+        const mpdet::u32x4 r = mpdet::rng(A.seed, (uint32_t)b, A.step, 0u, mpdet::PURPOSE_BATCH, 0u);
+        const uint64_t x = ((uint64_t)r.v[1] << 32) | r.v[0];
+        idx = (int64_t)__umul64hi(x, (uint64_t)A.n_data);
+    }
+    p = make_float4(A.dxyz[3 * idx], A.dxyz[3 * idx + 1], A.dxyz[3 * idx + 2], 0.0f);
+    tg = A.dlab[idx];
+}
 
 __device__ __forceinline__ void store4(__bf16* p, float a, float b, float c, float d) {
     typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
@@ -743,16 +771,20 @@ __device__ __forceinline__ void store4(__bf16* p, float a, float b, float c, flo
 }
 
 __global__ __launch_bounds__(kFThreads) void k_train_fused(FusedArgs A) {
-    __shared__ __attribute__((aligned(16))) __bf16 xs[32 * kXS];
-    __shared__ __attribute__((aligned(16))) __bf16 h1s[32 * kHS];
+    __shared__ __attribute__((aligned(16))) __bf16 xs[32 * kXS];    // [sample][feature]
+    __shared__ __attribute__((aligned(16))) __bf16 h1s[32 * kHS];   // [sample][unit]
     __shared__ __attribute__((aligned(16))) __bf16 dz2s[32 * kHS];
-    __shared__ __attribute__((aligned(16))) __bf16 h2o[4][32 * kOS];
-    __shared__ __attribute__((aligned(16))) __bf16 dz1o[4][32 * kOS];
+    __shared__ __attribute__((aligned(16))) __bf16 xT[kD0 * kTS];   // the same, [feature][sample]
+    __shared__ __attribute__((aligned(16))) __bf16 h1T[kD1 * kTS];  // [unit][sample]
+    __shared__ __attribute__((aligned(16))) __bf16 dz2T[kD2 * kTS];
+    __shared__ __attribute__((aligned(16))) __bf16 h2T[kD2 * kTS];
+    __shared__ __attribute__((aligned(16))) __bf16 dz1T[kD1 * kTS];
     __shared__ float ys[4][32][4];
     __shared__ float dys[32][4];
     __shared__ float w3s[kD2 * 4];
     __shared__ float bias[kD1 + kD2 + 4];
     __shared__ __attribute__((aligned(16))) float fqs[32];
+    __shared__ float4 sxyz[2][32], stgt[2][32];   // the samples of the tile and of the next one
     const char* img = reinterpret_cast<const char*>(A.img);
     for (int q = threadIdx.x; q < kD2 * 4; q += kFThreads) w3s[q] = (float)A.w3b[q];
     for (int q = threadIdx.x; q < kD1; q += kFThreads) {
@@ -782,12 +814,28 @@ __global__ __launch_bounds__(kFThreads) void k_train_fused(FusedArgs A) {
     g3 = f32x16{};
     float db1 = 0.0f, db2 = 0.0f, sse = 0.0f;
     float db3[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (w == 0 && h == 0 && (int)blockIdx.x < A.tiles) {
+        float4 p, tg;
+        fused_sample(A, 32 * blockIdx.x + m, p, tg);
+        sxyz[0][m] = p;
+        stgt[0][m] = tg;
+    }
     __syncthreads();
-    for (int t = blockIdx.x; t < A.tiles; t += gridDim.x) {
+    int it = 0;
+    for (int t = blockIdx.x; t < A.tiles; t += gridDim.x, ++it) {
+        const int cur = it & 1;
+        // the next tile's samples, requested by one half-wave now and stored
+        // at the end of this tile (the other buffer's readers finished before
+        // the last barrier; the stores are read after this tile's last one)
+        const bool fetch = w == 0 && h == 0 && t + (int)gridDim.x < A.tiles;
+        float4 nxt_p, nxt_t;
+        if (fetch) fused_sample(A, 32 * (t + gridDim.x) + m, nxt_p, nxt_t);
         const int b = 32 * t + m;   // this lane's sample
+        const float4 pm = sxyz[cur][m];
         float x[3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) x[a] = (A.xyz[3 * b + a] - A.lo[a]) * A.inv[a];
+        x[0] = (pm.x - A.lo[0]) * A.inv[0];
+        x[1] = (pm.y - A.lo[1]) * A.inv[1];
+        x[2] = (pm.z - A.lo[2]) * A.inv[2];
         // features of k-steps 3w .. 3w + 2 (axis sk / 4, frequencies 8 (sk % 4) + 4 h + 0..3)
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
@@ -801,6 +849,15 @@ __global__ __launch_bounds__(kFThreads) void k_train_fused(FusedArgs A) {
             feature_pair(fr.z, xv, v4, v5);
             feature_pair(fr.w, xv, v6, v7);
             *reinterpret_cast<bf16x8*>(xs + m * kXS + 16 * sk + 8 * h) = bf16x8{v0, v1, v2, v3, v4, v5, v6, v7};
+            __bf16* xt = xT + (16 * sk + 8 * h) * kTS + m;
+            xt[0] = v0;
+            xt[kTS] = v1;
+            xt[2 * kTS] = v2;
+            xt[3 * kTS] = v3;
+            xt[4 * kTS] = v4;
+            xt[5 * kTS] = v5;
+            xt[6 * kTS] = v6;
+            xt[7 * kTS] = v7;
         }
         __syncthreads();
         // layer 1 of the block: Z1 = W1^T x + b1 (kept), H1 to the shared rows
@@ -810,10 +867,20 @@ __global__ __launch_bounds__(kFThreads) void k_train_fused(FusedArgs A) {
 #pragma unroll
         for (int sk = 0; sk < 12; ++sk)
             z1 = mfma32(a1[sk], *reinterpret_cast<const bf16x8*>(xs + m * kXS + 16 * sk + 8 * h), z1);
+        float s1[16];   // sigmoid(Z1), kept for silu'
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-            store4(h1s + m * kHS + 32 * w + 8 * q + 4 * h, silu_f(z1[4 * q]), silu_f(z1[4 * q + 1]),
-                   silu_f(z1[4 * q + 2]), silu_f(z1[4 * q + 3]));
+        for (int jj = 0; jj < 16; ++jj) s1[jj] = sigmoid_f(z1[jj]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            float hv[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int jj = 4 * q + i;
+                hv[i] = z1[jj] * s1[jj];
+                h1T[acc_unit(w, jj, h) * kTS + m] = (__bf16)hv[i];
+            }
+            store4(h1s + m * kHS + 32 * w + 8 * q + 4 * h, hv[0], hv[1], hv[2], hv[3]);
+        }
         __syncthreads();
         // layer 2 of the block: Z2 = W2^T H1 + b2 (kept); H2 of the block; the
         // block's share of the output layer
@@ -828,21 +895,21 @@ __global__ __launch_bounds__(kFThreads) void k_train_fused(FusedArgs A) {
             const bf16x4 hi4 = *reinterpret_cast<const bf16x4*>(r + 8);
             z2 = mfma32(a2[s2], bf16x8{lo4[0], lo4[1], lo4[2], lo4[3], hi4[0], hi4[1], hi4[2], hi4[3]}, z2);
         }
+        float s2v[16];   // sigmoid(Z2), kept for silu'
+#pragma unroll
+        for (int jj = 0; jj < 16; ++jj) s2v[jj] = sigmoid_f(z2[jj]);
         float y0 = 0.0f, y1 = 0.0f, y2 = 0.0f, y3 = 0.0f;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            float hv[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int jj = 4 * q + i;
-                hv[i] = (float)(__bf16)silu_f(z2[jj]);
-                const float* wv = w3s + 4 * acc_unit(w, jj, h);
-                y0 = __builtin_fmaf(wv[0], hv[i], y0);
-                y1 = __builtin_fmaf(wv[1], hv[i], y1);
-                y2 = __builtin_fmaf(wv[2], hv[i], y2);
-                y3 = __builtin_fmaf(wv[3], hv[i], y3);
-            }
-            store4(h2o[w] + m * kOS + 8 * q + 4 * h, hv[0], hv[1], hv[2], hv[3]);
+        for (int jj = 0; jj < 16; ++jj) {
+            const int u = acc_unit(w, jj, h);
+            const __bf16 hb = (__bf16)(z2[jj] * s2v[jj]);
+            h2T[u * kTS + m] = hb;
+            const float hv = (float)hb;
+            const float* wv = w3s + 4 * u;
+            y0 = __builtin_fmaf(wv[0], hv, y0);
+            y1 = __builtin_fmaf(wv[1], hv, y1);
+            y2 = __builtin_fmaf(wv[2], hv, y2);
+            y3 = __builtin_fmaf(wv[3], hv, y3);
         }
         y0 += __shfl_xor(y0, 32, 64);
         y1 += __shfl_xor(y1, 32, 64);
@@ -860,7 +927,7 @@ __global__ __launch_bounds__(kFThreads) void k_train_fused(FusedArgs A) {
 #pragma unroll
         for (int c = 0; c < 4; ++c)
             yv[c] = bias[kD1 + kD2 + c] + (((ys[0][m][c] + ys[1][m][c]) + ys[2][m][c]) + ys[3][m][c]);
-        const float4 tg = A.tgt[b];
+        const float4 tg = stgt[cur][m];
         const bool valid = b < A.n_real;
         const float r0 = yv[0] - tg.x, r1 = yv[1] - tg.y, r2 = yv[2] - tg.z, r3 = yv[3] - tg.w;
         const float e = valid ? __builtin_fmaf(r0, r0, __builtin_fmaf(r1, r1, __builtin_fmaf(r2, r2, r3 * r3))) : 0.0f;
@@ -884,9 +951,11 @@ __global__ __launch_bounds__(kFThreads) void k_train_fused(FusedArgs A) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int jj = 4 * q + i;
-                const float* wv = w3s + 4 * acc_unit(w, jj, h);
+                const int u = acc_unit(w, jj, h);
+                const float* wv = w3s + 4 * u;
                 const float dh = __builtin_fmaf(wv[0], d0, __builtin_fmaf(wv[1], d1, __builtin_fmaf(wv[2], d2, wv[3] * d3)));
-                dv[i] = dh * silu_grad_f(z2[jj]);
+                dv[i] = dh * (s2v[jj] * __builtin_fmaf(z2[jj], 1.0f - s2v[jj], 1.0f));
+                dz2T[u * kTS + m] = (__bf16)dv[i];
             }
             store4(dz2s + m * kHS + 32 * w + 8 * q + 4 * h, dv[0], dv[1], dv[2], dv[3]);
         }
@@ -902,10 +971,8 @@ __global__ __launch_bounds__(kFThreads) void k_train_fused(FusedArgs A) {
             g = mfma32(a2b[s2], bf16x8{lo4[0], lo4[1], lo4[2], lo4[3], hi4[0], hi4[1], hi4[2], hi4[3]}, g);
         }
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-            store4(dz1o[w] + m * kOS + 8 * q + 4 * h, g[4 * q] * silu_grad_f(z1[4 * q]),
-                   g[4 * q + 1] * silu_grad_f(z1[4 * q + 1]), g[4 * q + 2] * silu_grad_f(z1[4 * q + 2]),
-                   g[4 * q + 3] * silu_grad_f(z1[4 * q + 3]));
+        for (int jj = 0; jj < 16; ++jj)
+            dz1T[acc_unit(w, jj, h) * kTS + m] = (__bf16)(g[jj] * (s1[jj] * __builtin_fmaf(z1[jj], 1.0f - s1[jj], 1.0f)));
         // the block's dZ1 rows are read back by this wave only
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -914,29 +981,23 @@ __global__ __launch_bounds__(kFThreads) void k_train_fused(FusedArgs A) {
 #pragma unroll
         for (int kq = 0; kq < 2; ++kq) {
             const int s0 = 16 * kq + 8 * h;
-            bf16x8 bz1, ah, a3, bhi, blo;
+            const bf16x8 bz1 = *reinterpret_cast<const bf16x8*>(dz1T + (32 * w + m) * kTS + s0);
+            const bf16x8 ah = *reinterpret_cast<const bf16x8*>(h1T + (32 * w + m) * kTS + s0);
+            const bf16x8 a3 = *reinterpret_cast<const bf16x8*>(h2T + (32 * w + m) * kTS + s0);
+            bf16x8 bhi, blo;
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
-                bz1[i] = dz1o[w][(s0 + i) * kOS + m];
-                ah[i] = h1s[(s0 + i) * kHS + 32 * w + m];
-                a3[i] = h2o[w][(s0 + i) * kOS + m];
                 const float d = m < 4 ? dys[s0 + i][m & 3] : 0.0f;
                 bhi[i] = (__bf16)d;
                 blo[i] = (__bf16)(d - (float)bhi[i]);
                 db1 += (float)bz1[i];
             }
 #pragma unroll
-            for (int rb = 0; rb < 6; ++rb) {
-                bf16x8 ax;
-#pragma unroll
-                for (int i = 0; i < 8; ++i) ax[i] = xs[(s0 + i) * kXS + 32 * rb + m];
-                g1[rb] = mfma32(ax, bz1, g1[rb]);
-            }
+            for (int rb = 0; rb < 6; ++rb)
+                g1[rb] = mfma32(*reinterpret_cast<const bf16x8*>(xT + (32 * rb + m) * kTS + s0), bz1, g1[rb]);
 #pragma unroll
             for (int cb = 0; cb < 4; ++cb) {
-                bf16x8 bz;
-#pragma unroll
-                for (int i = 0; i < 8; ++i) bz[i] = dz2s[(s0 + i) * kHS + 32 * cb + m];
+                const bf16x8 bz = *reinterpret_cast<const bf16x8*>(dz2T + (32 * cb + m) * kTS + s0);
                 if (cb == w) {
 #pragma unroll
                     for (int i = 0; i < 8; ++i) db2 += (float)bz[i];
@@ -946,10 +1007,14 @@ __global__ __launch_bounds__(kFThreads) void k_train_fused(FusedArgs A) {
             g3 = mfma32(a3, bhi, g3);
             g3 = mfma32(a3, blo, g3);
         }
+        if (fetch) {
+            sxyz[cur ^ 1][m] = nxt_p;
+            stgt[cur ^ 1][m] = nxt_t;
+        }
         __syncthreads();   // the tile's rows are read; the next tile overwrites them
     }
     // this workgroup's partial gradient, in parameter order
-    float* out = A.part + (size_t)blockIdx.x * kFPart;
+    float* out = A.part + (size_t)blockIdx.x * kFPartPad;
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
         const int row = 8 * (j >> 2) + 4 * h + (j & 3);   // accumulator row of register j
@@ -987,34 +1052,72 @@ struct AdamSumArgs {
     float* __restrict__ Mo;
     float* __restrict__ Vo;
     float* __restrict__ G;
-    const float* __restrict__ part;   // [nparts][kFPart]
+    const float* __restrict__ part;   // [nparts][kFPartPad]
     float* __restrict__ loss_out;     // one float
     int32_t nparts, update;
     float inv_n, lr, beta1, beta2, eps, c1, c2;
     PublishArgs W;
 };
 
-__global__ __launch_bounds__(kAdamQ * kAdamSub) void k_adam_sum(AdamSumArgs A) {
-    __shared__ float part[kAdamSub][kAdamQ];
-    const int qi = threadIdx.x % kAdamQ, sub = threadIdx.x / kAdamQ;
-    const int q = blockIdx.x * kAdamQ + qi;   // parameter; kNParams: the squared error
-    float g = 0.0f;
-    if (q <= kNParams)
-        for (int z = sub; z < A.nparts; z += kAdamSub) g += A.part[(size_t)z * kFPart + q];
-    part[sub][qi] = g;
-    __syncthreads();
-    if (sub != 0 || q > kNParams) return;
-    g = 0.0f;
+// A workgroup takes 4 x kSumQ consecutive parameters (the squared error is
+// the last "parameter"); thread (quad, row) reads four consecutive partials
+// of every kSumRows-th workgroup at once; the rows' sums are added in order.
+constexpr int kSumQ = 32, kSumRows = 8;
+__global__ __launch_bounds__(kSumQ * kSumRows) void k_adam_sum(AdamSumArgs A) {
+    __shared__ float4 part[kSumRows][kSumQ];
+    const int qi = threadIdx.x % kSumQ, row = threadIdx.x / kSumQ;
+    const int q0 = 4 * (blockIdx.x * kSumQ + qi);   // first of this thread's four parameters
+    float4 g = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (q0 < kFPart) {
+        float4 acc[4];
 #pragma unroll
-    for (int r = 0; r < kAdamSub; ++r) g += part[r][qi];
+        for (int u = 0; u < 4; ++u) acc[u] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        int z = row;
+        for (; z + 3 * kSumRows < A.nparts; z += 4 * kSumRows) {
+            float4 v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                v[u] = *reinterpret_cast<const float4*>(A.part + (size_t)(z + u * kSumRows) * kFPartPad + q0);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                acc[u].x += v[u].x;
+                acc[u].y += v[u].y;
+                acc[u].z += v[u].z;
+                acc[u].w += v[u].w;
+            }
+        }
+        for (; z < A.nparts; z += kSumRows) {
+            const float4 v = *reinterpret_cast<const float4*>(A.part + (size_t)z * kFPartPad + q0);
+            acc[0].x += v.x;
+            acc[0].y += v.y;
+            acc[0].z += v.z;
+            acc[0].w += v.w;
+        }
+        g.x = (acc[0].x + acc[1].x) + (acc[2].x + acc[3].x);
+        g.y = (acc[0].y + acc[1].y) + (acc[2].y + acc[3].y);
+        g.z = (acc[0].z + acc[1].z) + (acc[2].z + acc[3].z);
+        g.w = (acc[0].w + acc[1].w) + (acc[2].w + acc[3].w);
+    }
+    part[row][qi] = g;
+    __syncthreads();
+    // thread (quad, row) finishes parameter q0 + row of quad qi (rows 0..3)
+    if (row >= 4) return;
+    const int q = q0 + row;
+    if (q >= kFPart) return;
+    float gq = 0.0f;
+#pragma unroll
+    for (int r = 0; r < kSumRows; ++r) {
+        const float4 v = part[r][qi];
+        gq += row == 0 ? v.x : (row == 1 ? v.y : (row == 2 ? v.z : v.w));
+    }
     if (q == kNParams) {
-        if (A.loss_out) *A.loss_out = g * A.inv_n;
+        if (A.loss_out) *A.loss_out = gq * A.inv_n;
         return;
     }
-    A.G[q] = g;
+    A.G[q] = gq;
     if (!A.update) return;
-    const float m = __builtin_fmaf(A.beta1, A.Mo[q], (1.0f - A.beta1) * g);
-    const float v = __builtin_fmaf(A.beta2, A.Vo[q], (1.0f - A.beta2) * g * g);
+    const float m = __builtin_fmaf(A.beta1, A.Mo[q], (1.0f - A.beta1) * gq);
+    const float v = __builtin_fmaf(A.beta2, A.Vo[q], (1.0f - A.beta2) * gq * gq);
     A.Mo[q] = m;
     A.Vo[q] = v;
     const float mh = m / A.c1, vh = v / A.c2;
@@ -1328,13 +1431,17 @@ void mp_sur_ensure_batch(mp_surrogate S, int64_t cap) {
     S->pw1.alloc(sizeof(float) * ns * kD0 * kD1);
     S->pw2.alloc(sizeof(float) * ns * kD1 * kD2);
     S->pl3.alloc(sizeof(float) * ns * kL3Len);
-    S->pf.ensure(sizeof(float) * (size_t)std::max(1, S->cus) * kFPart);
+    S->pf.ensure(sizeof(float) * (size_t)std::max(1, S->cus) * kFPartPad);
     S->cap = bp;
 }
 
 // One gradient evaluation over the staged batch (bxyz, btgt; n_real rows),
 // optionally followed by an Adam step with learning rate lr.
-void mp_sur_grad_step(mp_surrogate S, int32_t n_real, bool update, float lr, float* loss_dev, hipStream_t s) {
+// One gradient evaluation over n_real samples, staged (bxyz, btgt) or drawn
+// from the training set with step counter `step`, optionally followed by an
+// Adam step with learning rate lr.
+static void fused_step(mp_surrogate S, int32_t n_real, bool draw, bool full, uint32_t step, bool update, float lr,
+                       float* loss_dev, hipStream_t s) {
     const int32_t bp = padded_rows(n_real);
     if (bp > S->cap) mp_throw(MP_E_STATE, "surrogate batch buffers too small");
     FusedArgs F;
@@ -1343,7 +1450,14 @@ void mp_sur_grad_step(mp_surrogate S, int32_t n_real, bool update, float lr, flo
     F.w3b = S->w3b.as<__bf16>();
     F.xyz = S->bxyz.as<float>();
     F.tgt = S->btgt.as<float4>();
+    F.dxyz = S->dxyz.as<float>();
+    F.dlab = S->dlab.as<float4>();
     F.part = S->pf.as<float>();
+    F.n_data = S->info.n_data;
+    F.draw = draw ? 1 : 0;
+    F.full = full ? 1 : 0;
+    F.step = step;
+    F.seed = S->p.seed;
     F.tiles = bp / 32;
     F.n_real = n_real;
     F.two_over_n = (float)(2.0 / (double)n_real);
@@ -1372,9 +1486,18 @@ void mp_sur_grad_step(mp_surrogate S, int32_t n_real, bool update, float lr, flo
     A.c1 = (float)(1.0 - std::pow((double)S->p.beta1, t));
     A.c2 = (float)(1.0 - std::pow((double)S->p.beta2, t));
     A.W = publish_args(S);
-    k_adam_sum<<<(kFPart + kAdamQ - 1) / kAdamQ, kAdamQ * kAdamSub, 0, s>>>(A);
+    k_adam_sum<<<(kFPart + 4 * kSumQ - 1) / (4 * kSumQ), kSumQ * kSumRows, 0, s>>>(A);
     MP_CHECK_LAUNCH();
     if (update) S->info.steps += 1;
+}
+
+void mp_sur_grad_step(mp_surrogate S, int32_t n_real, bool update, float lr, float* loss_dev, hipStream_t s) {
+    fused_step(S, n_real, false, false, 0u, update, lr, loss_dev, s);
+}
+
+void mp_sur_train_step(mp_surrogate S, int32_t n_real, bool full, uint32_t step, float lr, float* loss_dev,
+                       hipStream_t s) {
+    fused_step(S, n_real, true, full, step, true, lr, loss_dev, s);
 }
 
 void mp_sur_draw_batch(mp_surrogate S, int32_t n_real, bool full, uint32_t step, hipStream_t s) {
