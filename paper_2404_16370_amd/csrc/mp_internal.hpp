@@ -88,9 +88,8 @@ struct mp_surrogate_s {
     DevMem w3b;                     // bf16 copy of W3 (training's output-layer gradient)
     DevMem dxyz, dlab;              // training set: points, scaled labels (float4)
     int32_t cap = 0;                // padded batch rows the work buffers hold
-    DevMem bxyz, btgt, XT, H1T, H2T, dY, sse, dZ2T, dZ1T;   // per-batch activations, unit-major
-    DevMem pw1, pw2, pl3;           // split-K and chunk partial sums
-    DevMem pf;                      // per-workgroup partial gradients of the fused step
+    DevMem bxyz, btgt;              // a batch staged by the caller (mp_surrogate_grad)
+    DevMem pf;                      // per-workgroup partial gradients of the training step
     DevMem losses;                  // per-step loss (float)
     int cus = 1;                    // compute units of the device (persistent-grid size)
     int users = 0;
@@ -274,7 +273,6 @@ void mp_sur_eval(mp_surrogate S, const float* xyz_dev, int64_t n, float* out4_de
 // by every pstride-th particle (synchronises the stream)
 float mp_sur_check(mp_filter f, int32_t pstride, hipStream_t s);
 void mp_sur_ensure_batch(mp_surrogate S, int64_t cap);
-void mp_sur_draw_batch(mp_surrogate S, int32_t n_real, bool full, uint32_t step, hipStream_t s);
 void mp_sur_grad_step(mp_surrogate S, int32_t n_real, bool update, float lr, float* loss_dev, hipStream_t s);
 // one Adam step on a batch drawn from the training set (step counter `step`)
 void mp_sur_train_step(mp_surrogate S, int32_t n_real, bool full, uint32_t step, float lr, float* loss_dev,

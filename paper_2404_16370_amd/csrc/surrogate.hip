@@ -24,15 +24,14 @@
 // permuted to match the accumulator layout; the weight fragments are stored
 // in the same permuted order.
 //
-// Training: one fused kernel runs the forward and the backward pass of 32
-// samples per wave in the inference layout (features, both hidden layers,
-// output, loss, the output layer's gradient and the input gradient of layer
-// 2 on the matrix cores, the pre-activations kept in registers) and writes
-// only what the weight gradients need, unit-major: features, H1, H2, dZ2,
-// dZ1 (bf16) and dY.  The weight gradients of layers 1 and 2 are bf16 "NT"
-// GEMMs over the samples (split-K partial sums per chunk of 512 samples),
-// the small ones (W3, biases, loss) chunk sums; the Adam kernel reduces the
-// partials in a fixed order, so a step is deterministic.
+// Training: one launch evaluates the gradient of the whole batch.  Each
+// workgroup (4 waves) takes 32-sample tiles; wave w owns the 32-unit block w
+// of both hidden layers, so its weight fragments stay in registers, the
+// activations of a tile pass through LDS (sample-major rows for the next
+// layer's operands, unit-major rows for the products over samples), and the
+// weight gradients accumulate in each wave's accumulation registers over the
+// workgroup's tiles.  One partial gradient per workgroup is written; the Adam
+// kernel adds the partials in a fixed order, so a step is deterministic.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -65,9 +64,7 @@ static_assert(kImgBytes == MP_SUR_IMAGE_BYTES, "image size");
 constexpr int kImg2Bytes = 4 * 8 * 64 * 16;        // [4 row tiles][8 k-steps][64 lanes][8] bf16
 static_assert(kImgBytes % 16 == 0, "image in uint4 units");
 
-// per-chunk sums of the small reductions: dW3 (512), db3 (4), db2 (128), db1 (128), squared error (1)
-constexpr int kL3W3 = 0, kL3B3 = 512, kL3B2 = 516, kL3B1 = 644, kL3SSE = 772, kL3Len = 773;
-constexpr int kRedChunk = 512;  // samples per reduction chunk; also the split-K slice
+constexpr int kBatchPad = 512;  // the batch is padded to a multiple of this many rows (zero rows)
 
 __device__ __forceinline__ f32x16 mfma32(const bf16x8 a, const bf16x8 b, const f32x16 c) {
     return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
@@ -296,412 +293,6 @@ __global__ void k_publish(const float* __restrict__ P, PublishArgs W) {
     publish(W, q, P[q]);
 }
 
-// ------------------------------------------------------------ training kernels
-struct BatchArgs {
-    const float* __restrict__ dxyz;
-    const float4* __restrict__ dlab;
-    float* __restrict__ bxyz;
-    float4* __restrict__ btgt;
-    int64_t n_data;
-    int32_t n_real, bp, full;
-    uint32_t step;
-    uint64_t seed;
-};
-
-__global__ void k_draw_batch(BatchArgs A) {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= A.bp) return;
-    if (b >= A.n_real) {
-        A.bxyz[3 * b] = A.bxyz[3 * b + 1] = A.bxyz[3 * b + 2] = 0.0f;
-        A.btgt[b] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        return;
-    }
-    int64_t idx = b;
-    if (!A.full) {
-        const mpdet::u32x4 r = mpdet::rng(A.seed, (uint32_t)b, A.step, 0u, mpdet::PURPOSE_BATCH, 0u);
-        const uint64_t x = ((uint64_t)r.v[1] << 32) | r.v[0];
-        idx = (int64_t)__umul64hi(x, (uint64_t)A.n_data);   // floor(x n / 2^64), uniform in [0, n)
-    }
-    A.bxyz[3 * b] = A.dxyz[3 * idx];
-    A.bxyz[3 * b + 1] = A.dxyz[3 * idx + 1];
-    A.bxyz[3 * b + 2] = A.dxyz[3 * idx + 2];
-    A.btgt[b] = A.dlab[idx];
-}
-
-struct GemmArgs {
-    const __bf16* __restrict__ A;  // [M][K]
-    const __bf16* __restrict__ B;  // [N][K]
-    int32_t M, N, K, kslice;
-    float* __restrict__ out;         // [slices][M][N]
-};
-
-// Partial products over K slices: out[z][m][n] = sum over k in slice z of
-// A[m][k] B[n][k]; block tile 64 x 128, four waves of 32 x 64.
-// Requires M % 64 == 0, N % 128 == 0, K % 16 == 0, kslice % 16 == 0.
-__global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int r = lane & 31, h = lane >> 5;
-    const int m0 = blockIdx.x * 64 + (wave & 1) * 32;
-    const int n0 = blockIdx.y * 128 + (wave >> 1) * 64;
-    const int kb = blockIdx.z * g.kslice;
-    const int ke = min(g.K, kb + g.kslice);
-    const bf16x8* pa = reinterpret_cast<const bf16x8*>(g.A + (size_t)(m0 + r) * g.K + 8 * h);
-    const bf16x8* pb0 = reinterpret_cast<const bf16x8*>(g.B + (size_t)(n0 + r) * g.K + 8 * h);
-    const bf16x8* pb1 = reinterpret_cast<const bf16x8*>(g.B + (size_t)(n0 + 32 + r) * g.K + 8 * h);
-    f32x16 c0 = {}, c1 = {};
-    for (int k = kb; k < ke; k += 16) {
-        const int kq = k >> 3;
-        const bf16x8 a = pa[kq], b0 = pb0[kq], b1 = pb1[kq];
-        c0 = mfma32(a, b0, c0);
-        c1 = mfma32(a, b1, c1);
-    }
-#pragma unroll
-    for (int half = 0; half < 2; ++half) {
-        const f32x16& c = half ? c1 : c0;
-        const int n = n0 + 32 * half + r;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int mb = m0 + 8 * q + 4 * h;   // rows mb .. mb + 3 in registers 4q .. 4q + 3
-            float* o = g.out + ((size_t)blockIdx.z * g.M + mb) * g.N + n;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) o[(size_t)i * g.N] = c[4 * q + i];
-        }
-    }
-}
-
-// ------------------------------------------------------------ training step
-// Forward and backward pass of the batch, 32 samples per wave and call (the
-// inference layout of mlp32, with tile 0's outputs in lane half 0).  Rounding
-// points as in the reference definition of the training: features, H1, H2,
-// dZ2 and dZ1 in bf16; pre-activations, outputs, dY and dH2 in FP32.
-constexpr int kTrainThreads = 256;   // 4 waves, one per SIMD: Z1, Z2 and two accumulators live at once
-struct TrainArgs {
-    const uint4* __restrict__ img;     // inference image
-    const uint4* __restrict__ img2;    // W2 fragments of the input gradient
-    const __bf16* __restrict__ w3b;    // [128][4]
-    const float* __restrict__ xyz;     // [bp][3]
-    const float4* __restrict__ tgt;    // [bp] scaled targets
-    __bf16* __restrict__ XT;           // [192][bp] features
-    __bf16* __restrict__ H1T;          // [128][bp]
-    __bf16* __restrict__ H2T;          // [128][bp]
-    __bf16* __restrict__ dZ2T;         // [128][bp]
-    __bf16* __restrict__ dZ1T;         // [128][bp]
-    float4* __restrict__ dY;           // [bp] 2 (y - t) / n (0 for padding rows)
-    float* __restrict__ sse;           // [bp] squared error (0 for padding rows)
-    int32_t bp, n_real;
-    float two_over_n;
-    float lo[3], inv[3];
-};
-
-__global__ __launch_bounds__(kTrainThreads) void k_train_fb(TrainArgs A) {
-    __shared__ uint4 simg[kImgBytes / 16];
-    __shared__ uint4 simg2[kImg2Bytes / 16];
-    __shared__ float w3s[kD2 * 4];
-    for (int q = threadIdx.x; q < kImgBytes / 16; q += blockDim.x) simg[q] = A.img[q];
-    for (int q = threadIdx.x; q < kImg2Bytes / 16; q += blockDim.x) simg2[q] = A.img2[q];
-    for (int q = threadIdx.x; q < kD2 * 4; q += blockDim.x) w3s[q] = (float)A.w3b[q];
-    __syncthreads();
-    const char* img = reinterpret_cast<const char*>(simg);
-    const bf16x8* f1 = reinterpret_cast<const bf16x8*>(img + kImgF1);
-    const bf16x8* f2 = reinterpret_cast<const bf16x8*>(img + kImgF2);
-    const bf16x8* f3 = reinterpret_cast<const bf16x8*>(img + kImgF3);
-    const bf16x8* f2b = reinterpret_cast<const bf16x8*>(simg2);
-    const float* b1 = reinterpret_cast<const float*>(img + kImgB1);
-    const float* b2 = reinterpret_cast<const float*>(img + kImgB2);
-    const float* b3 = reinterpret_cast<const float*>(img + kImgB3);
-    const float* fq = reinterpret_cast<const float*>(img + kImgFQ);
-    const int lane = threadIdx.x & 63, m = lane & 31, h = lane >> 5;
-    const int nw = kTrainThreads / 64;
-    const int tiles = A.bp / 32;
-    // rows x bp < 2^31 (bp <= 2^20)
-    for (int t = blockIdx.x * nw + (threadIdx.x >> 6); t < tiles; t += gridDim.x * nw) {
-        const int b = 32 * t + m;   // this lane's sample (both lane halves)
-        // the row stride as an opaque value of this iteration: the ~350 store
-        // offsets below are formed where they are used, not hoisted out of the
-        // loop into registers
-        int bp = A.bp;
-        asm volatile("" : "+s"(bp));
-        __bf16* const xt = A.XT + b;
-        __bf16* const h1t = A.H1T + b;
-        __bf16* const h2t = A.H2T + b;
-        __bf16* const dz2t = A.dZ2T + b;
-        __bf16* const dz1t = A.dZ1T + b;
-        float x[3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) x[a] = (A.xyz[3 * b + a] - A.lo[a]) * A.inv[a];
-        // layer 1: Z1 = W1^T x + b1 (kept), features written unit-major
-        f32x16 z1[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-#pragma unroll
-            for (int jj = 0; jj < 16; ++jj) z1[r][jj] = b1[acc_unit(r, jj, h)];
-#pragma unroll
-        for (int sk = 0; sk < 12; ++sk) {
-            const float4 fr = *reinterpret_cast<const float4*>(fq + 8 * (sk & 3) + 4 * h);
-            const float xs = x[sk >> 2];
-            __bf16 v0, v1, v2, v3, v4, v5, v6, v7;
-            feature_pair(fr.x, xs, v0, v1);
-            feature_pair(fr.y, xs, v2, v3);
-            feature_pair(fr.z, xs, v4, v5);
-            feature_pair(fr.w, xs, v6, v7);
-            const bf16x8 bx = bf16x8{v0, v1, v2, v3, v4, v5, v6, v7};
-#pragma unroll
-            for (int j = 0; j < 8; ++j) xt[(16 * sk + 8 * h + j) * bp] = bx[j];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) z1[r] = mfma32(f1[(r * 12 + sk) * 64 + lane], bx, z1[r]);
-        }
-        bf16x8 hb[8];
-#pragma unroll
-        for (int s2 = 0; s2 < 8; ++s2)
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int r = s2 >> 1, jj = 8 * (s2 & 1) + j;
-                hb[s2][j] = (__bf16)silu_f(z1[r][jj]);
-                h1t[acc_unit(r, jj, h) * bp] = hb[s2][j];
-            }
-        // layer 2: Z2 = W2^T H1 + b2 (kept)
-        f32x16 z2[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-#pragma unroll
-            for (int jj = 0; jj < 16; ++jj) z2[r][jj] = b2[acc_unit(r, jj, h)];
-#pragma unroll
-        for (int s2 = 0; s2 < 8; ++s2)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) z2[r] = mfma32(f2[(r * 8 + s2) * 64 + lane], hb[s2], z2[r]);
-#pragma unroll
-        for (int s2 = 0; s2 < 8; ++s2)
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int r = s2 >> 1, jj = 8 * (s2 & 1) + j;
-                hb[s2][j] = (__bf16)silu_f(z2[r][jj]);
-                h2t[acc_unit(r, jj, h) * bp] = hb[s2][j];
-            }
-        // output layer: rows 0..3 of the product, held by lane half 0
-        f32x16 o = {};
-        const bf16x8 zero = {};
-#pragma unroll
-        for (int s2 = 0; s2 < 8; ++s2) o = mfma32(m < 4 ? f3[(s2 * 4 + m) * 2 + h] : zero, hb[s2], o);
-        float y[4];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) y[c] = __shfl(o[c] + b3[c], m, 64);   // from lane m (half 0)
-        const float4 tg = A.tgt[b];
-        const bool valid = b < A.n_real;
-        const float r0 = y[0] - tg.x, r1 = y[1] - tg.y, r2 = y[2] - tg.z, r3 = y[3] - tg.w;
-        const float e = valid ? __builtin_fmaf(r0, r0, __builtin_fmaf(r1, r1, __builtin_fmaf(r2, r2, r3 * r3))) : 0.0f;
-        const float kk = valid ? A.two_over_n : 0.0f;
-        const float d0 = r0 * kk, d1 = r1 * kk, d2 = r2 * kk, d3 = r3 * kk;
-        if (h == 0) {
-            A.dY[b] = make_float4(d0, d1, d2, d3);
-            A.sse[b] = e;
-        }
-        // dZ2 = (W3 dY) silu'(Z2) in bf16: the B operand of the input gradient
-        bf16x8 dz[8];
-#pragma unroll
-        for (int s2 = 0; s2 < 8; ++s2)
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int r = s2 >> 1, jj = 8 * (s2 & 1) + j;
-                const int u = acc_unit(r, jj, h);
-                const float* w = w3s + 4 * u;
-                const float dh = __builtin_fmaf(w[0], d0, __builtin_fmaf(w[1], d1, __builtin_fmaf(w[2], d2, w[3] * d3)));
-                dz[s2][j] = (__bf16)(dh * silu_grad_f(z2[r][jj]));
-                dz2t[u * bp] = dz[s2][j];
-            }
-        // dH1 = W2 dZ2, dZ1 = dH1 silu'(Z1) in bf16
-        f32x16 g[4] = {};
-#pragma unroll
-        for (int s2 = 0; s2 < 8; ++s2)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) g[r] = mfma32(f2b[(r * 8 + s2) * 64 + lane], dz[s2], g[r]);
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-#pragma unroll
-            for (int jj = 0; jj < 16; ++jj)
-                dz1t[acc_unit(r, jj, h) * bp] = (__bf16)(g[r][jj] * silu_grad_f(z1[r][jj]));
-    }
-}
-
-// Per-chunk sums over kRedChunk samples from the unit-major activations:
-// dW3 = sum h2 dy, db3 = sum dy, db2 = sum dz2, db1 = sum dz1, squared error.
-struct RedArgs {
-    const __bf16* __restrict__ H2T;   // [128][bp]
-    const float4* __restrict__ dY;    // [bp]
-    const float* __restrict__ sse;    // [bp]
-    const __bf16* __restrict__ dZ2T;  // [128][bp]
-    const __bf16* __restrict__ dZ1T;  // [128][bp]
-    float* __restrict__ out;          // [chunks][kL3Len]
-    int32_t bp;
-};
-
-// One workgroup per chunk; thread t takes unit u = t / 8 and part q = t % 8
-// of the chunk's samples (64 samples: eight 16-byte loads of each unit-major
-// row, all issued before they are used): partial dW3[u][0..3], db2[u] and
-// db1[u] over its part; the eight parts are added in a fixed order, and db3
-// and the squared error by the first wave in a fixed order (the result does
-// not depend on the launch).
-constexpr int kRedParts = 8;
-constexpr int kRedThreads = kD2 * kRedParts;
-constexpr int kPart = kRedChunk / kRedParts;
-static_assert(kPart % 8 == 0 && kRedThreads <= 1024, "reduction shape");
-__global__ __launch_bounds__(kRedThreads) void k_reduce_small(RedArgs A) {
-    __shared__ float4 sdy[kRedChunk];
-    __shared__ float sse[kRedChunk];
-    __shared__ float part[kRedParts][kD2][6];   // part, unit, (dW3 0..3, db2, db1)
-    const int t = threadIdx.x;
-    const int u = t / kRedParts, q = t % kRedParts;
-    const int b0 = blockIdx.x * kRedChunk;
-    for (int b = t; b < kRedChunk; b += kRedThreads) {
-        sdy[b] = A.dY[b0 + b];
-        sse[b] = A.sse[b0 + b];
-    }
-    const size_t bp = (size_t)A.bp;
-    const int s0 = q * kPart;
-    const bf16x8* h2 = reinterpret_cast<const bf16x8*>(A.H2T + (size_t)u * bp + b0 + s0);
-    const bf16x8* z2 = reinterpret_cast<const bf16x8*>(A.dZ2T + (size_t)u * bp + b0 + s0);
-    const bf16x8* z1 = reinterpret_cast<const bf16x8*>(A.dZ1T + (size_t)u * bp + b0 + s0);
-    bf16x8 hv[kPart / 8], zv2[kPart / 8], zv1[kPart / 8];
-#pragma unroll
-    for (int v = 0; v < kPart / 8; ++v) {
-        hv[v] = h2[v];
-        zv2[v] = z2[v];
-        zv1[v] = z1[v];
-    }
-    __syncthreads();
-    float w0 = 0.0f, w1 = 0.0f, w2 = 0.0f, w3 = 0.0f, g2 = 0.0f, g1 = 0.0f;
-#pragma unroll
-    for (int v = 0; v < kPart / 8; ++v)
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const float4 d = sdy[s0 + 8 * v + k];
-            const float hh = (float)hv[v][k];
-            w0 = __builtin_fmaf(hh, d.x, w0);
-            w1 = __builtin_fmaf(hh, d.y, w1);
-            w2 = __builtin_fmaf(hh, d.z, w2);
-            w3 = __builtin_fmaf(hh, d.w, w3);
-            g2 += (float)zv2[v][k];
-            g1 += (float)zv1[v][k];
-        }
-    part[q][u][0] = w0;
-    part[q][u][1] = w1;
-    part[q][u][2] = w2;
-    part[q][u][3] = w3;
-    part[q][u][4] = g2;
-    part[q][u][5] = g1;
-    __syncthreads();
-    float* o = A.out + (size_t)blockIdx.x * kL3Len;
-    if (t < kD2 * 6) {   // unit t / 6, quantity t % 6
-        const int uu = t / 6, c = t % 6;
-        float acc = 0.0f;
-#pragma unroll
-        for (int r = 0; r < kRedParts; ++r) acc += part[r][uu][c];
-        if (c < 4) o[kL3W3 + 4 * uu + c] = acc;
-        else if (c == 4) o[kL3B2 + uu] = acc;
-        else o[kL3B1 + uu] = acc;
-    }
-    if (t < 64) {
-        // db3 and the squared error: lane l sums samples 8 l .. 8 l + 7, then
-        // a fixed butterfly over the wave
-        float4 d3 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        float e = 0.0f;
-#pragma unroll
-        for (int k = 0; k < kRedChunk / 64; ++k) {
-            const float4 d = sdy[(kRedChunk / 64) * t + k];
-            d3.x += d.x;
-            d3.y += d.y;
-            d3.z += d.z;
-            d3.w += d.w;
-            e += sse[(kRedChunk / 64) * t + k];
-        }
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) {
-            d3.x += __shfl_xor(d3.x, off, 64);
-            d3.y += __shfl_xor(d3.y, off, 64);
-            d3.z += __shfl_xor(d3.z, off, 64);
-            d3.w += __shfl_xor(d3.w, off, 64);
-            e += __shfl_xor(e, off, 64);
-        }
-        if (t == 0) {
-            o[kL3B3] = d3.x;
-            o[kL3B3 + 1] = d3.y;
-            o[kL3B3 + 2] = d3.z;
-            o[kL3B3 + 3] = d3.w;
-            o[kL3SSE] = e;
-        }
-    }
-}
-
-struct AdamArgs {
-    float* __restrict__ P;
-    float* __restrict__ Mo;
-    float* __restrict__ Vo;
-    float* __restrict__ G;
-    const float* __restrict__ pw1;   // [nsplit][192][128]
-    const float* __restrict__ pw2;   // [nsplit][128][128]
-    const float* __restrict__ pl3;   // [nsplit][kL3Len]
-    float* __restrict__ loss_out;    // one float
-    int32_t nsplit, update;
-    float inv_n, lr, beta1, beta2, eps, c1, c2;
-    PublishArgs W;
-};
-
-// Gradient of every parameter from the chunk partials, then the Adam update.
-// A workgroup takes kAdamQ consecutive parameters; its kAdamSub thread rows
-// sum every kAdamSub-th chunk (coalesced reads of kAdamQ neighbours), and
-// the row sums are added in a fixed order.
-constexpr int kAdamQ = 32, kAdamSub = 8;
-__global__ __launch_bounds__(kAdamQ * kAdamSub) void k_adam(AdamArgs A) {
-    __shared__ float part[kAdamSub][kAdamQ];
-    const int qi = threadIdx.x % kAdamQ, sub = threadIdx.x / kAdamQ;
-    const int q = blockIdx.x * kAdamQ + qi;
-    if (blockIdx.x == 0 && threadIdx.x == 0 && A.loss_out) {
-        float s = 0.0f;
-        for (int z = 0; z < A.nsplit; ++z) s += A.pl3[(size_t)z * kL3Len + kL3SSE];
-        *A.loss_out = s * A.inv_n;
-    }
-    float g = 0.0f;
-    if (q < kNParams) {
-        const float* src;
-        size_t stride;
-        if (q < kOffB1) {
-            src = A.pw1 + q;
-            stride = (size_t)kD0 * kD1;
-        } else if (q < kOffW2) {
-            src = A.pl3 + kL3B1 + (q - kOffB1);
-            stride = kL3Len;
-        } else if (q < kOffB2) {
-            src = A.pw2 + (q - kOffW2);
-            stride = (size_t)kD1 * kD2;
-        } else if (q < kOffW3) {
-            src = A.pl3 + kL3B2 + (q - kOffB2);
-            stride = kL3Len;
-        } else if (q < kOffB3) {
-            src = A.pl3 + kL3W3 + (q - kOffW3);
-            stride = kL3Len;
-        } else {
-            src = A.pl3 + kL3B3 + (q - kOffB3);
-            stride = kL3Len;
-        }
-        for (int z = sub; z < A.nsplit; z += kAdamSub) g += src[(size_t)z * stride];
-    }
-    part[sub][qi] = g;
-    __syncthreads();
-    if (sub != 0 || q >= kNParams) return;
-    g = 0.0f;
-#pragma unroll
-    for (int r = 0; r < kAdamSub; ++r) g += part[r][qi];
-    A.G[q] = g;
-    if (!A.update) return;
-    const float m = __builtin_fmaf(A.beta1, A.Mo[q], (1.0f - A.beta1) * g);
-    const float v = __builtin_fmaf(A.beta2, A.Vo[q], (1.0f - A.beta2) * g * g);
-    A.Mo[q] = m;
-    A.Vo[q] = v;
-    const float mh = m / A.c1, vh = v / A.c2;
-    const float w = A.P[q] - A.lr * mh / (sqrtf(vh) + A.eps);
-    A.P[q] = w;
-    publish(A.W, q, w);
-}
-
 // ------------------------------------------------------------ fused training step
 // One gradient evaluation of the batch in one launch.  A workgroup of four
 // waves takes 32-sample tiles; wave w owns the 32-unit block w of both hidden
@@ -716,7 +307,7 @@ __global__ __launch_bounds__(kAdamQ * kAdamSub) void k_adam(AdamArgs A) {
 // dW1 columns, dW2 rows and dW3 rows of its block) in accumulation registers
 // over the workgroup's tiles.  The workgroup writes one partial gradient and
 // its squared error; the Adam kernel adds the partials in a fixed order.
-// Rounding points as in k_train_fb: features, H1, H2, dZ2 and dZ1 in bf16;
+// Rounding points: features, H1, H2, dZ2 and dZ1 in bf16;
 // pre-activations, outputs, dY and dH2 in FP32; dY enters the dW3 product as
 // a bf16 pair (hi + lo).
 constexpr int kFThreads = 256;
@@ -743,9 +334,9 @@ struct FusedArgs {
     float lo[3], inv[3];
 };
 
-// Sample b of the batch: the staged row, or drawn from the training set as
-// k_draw_batch draws it (the whole set in order when it fits the batch, else
-// index floor(x n / 2^64) of a Philox draw x); zero past n_real.
+// Sample b of the batch: the staged row, or drawn from the training set (the
+// whole set in order when it fits the batch, else index floor(x n / 2^64) of
+// a Philox draw x keyed by the step counter); zero past n_real.
 __device__ __forceinline__ void fused_sample(const FusedArgs& A, int b, float4& p, float4& tg) {
     p = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     tg = p;
@@ -1412,7 +1003,7 @@ void mp_sur_eval(mp_surrogate S, const float* xyz_dev, int64_t n, float* out4_de
 }
 
 // padded batch rows: a multiple of the reduction chunk
-static int32_t padded_rows(int64_t n) { return (int32_t)((n + kRedChunk - 1) / kRedChunk * kRedChunk); }
+static int32_t padded_rows(int64_t n) { return (int32_t)((n + kBatchPad - 1) / kBatchPad * kBatchPad); }
 
 void mp_sur_ensure_batch(mp_surrogate S, int64_t cap) {
     const int32_t bp = padded_rows(cap);
@@ -1420,23 +1011,10 @@ void mp_sur_ensure_batch(mp_surrogate S, int64_t cap) {
     const size_t b = (size_t)bp;
     S->bxyz.alloc(sizeof(float) * 3 * b);
     S->btgt.alloc(sizeof(float) * 4 * b);
-    S->XT.alloc(2 * kD0 * b);
-    S->H1T.alloc(2 * kD1 * b);
-    S->H2T.alloc(2 * kD2 * b);
-    S->dY.alloc(sizeof(float) * 4 * b);
-    S->sse.alloc(sizeof(float) * b);
-    S->dZ2T.alloc(2 * kD2 * b);
-    S->dZ1T.alloc(2 * kD1 * b);
-    const size_t ns = b / kRedChunk;
-    S->pw1.alloc(sizeof(float) * ns * kD0 * kD1);
-    S->pw2.alloc(sizeof(float) * ns * kD1 * kD2);
-    S->pl3.alloc(sizeof(float) * ns * kL3Len);
     S->pf.ensure(sizeof(float) * (size_t)std::max(1, S->cus) * kFPartPad);
     S->cap = bp;
 }
 
-// One gradient evaluation over the staged batch (bxyz, btgt; n_real rows),
-// optionally followed by an Adam step with learning rate lr.
 // One gradient evaluation over n_real samples, staged (bxyz, btgt) or drawn
 // from the training set with step counter `step`, optionally followed by an
 // Adam step with learning rate lr.
@@ -1498,22 +1076,6 @@ void mp_sur_grad_step(mp_surrogate S, int32_t n_real, bool update, float lr, flo
 void mp_sur_train_step(mp_surrogate S, int32_t n_real, bool full, uint32_t step, float lr, float* loss_dev,
                        hipStream_t s) {
     fused_step(S, n_real, true, full, step, true, lr, loss_dev, s);
-}
-
-void mp_sur_draw_batch(mp_surrogate S, int32_t n_real, bool full, uint32_t step, hipStream_t s) {
-    BatchArgs B;
-    B.dxyz = S->dxyz.as<float>();
-    B.dlab = S->dlab.as<float4>();
-    B.bxyz = S->bxyz.as<float>();
-    B.btgt = S->btgt.as<float4>();
-    B.n_data = S->info.n_data;
-    B.n_real = n_real;
-    B.bp = padded_rows(n_real);
-    B.full = full ? 1 : 0;
-    B.step = step;
-    B.seed = S->p.seed;
-    k_draw_batch<<<(B.bp + 255) / 256, 256, 0, s>>>(B);
-    MP_CHECK_LAUNCH();
 }
 
 void mp_sur_likelihood(mp_filter f, float* partial, hipStream_t s) {
