@@ -426,6 +426,8 @@ extern "C" mp_status mp_filter_init(mp_map map, const mp_filter_params* params, 
             f->scodes.alloc(4 * N);
             f->tmp_keys.alloc(4 * N);
             f->tmp_vals.alloc(4 * N);
+            f->lkeys.alloc(4 * N);
+            f->lorder.alloc(4 * N);
             f->head.alloc(4 * N);
             f->end.alloc(4 * N);
             f->rank.alloc(4 * N);

@@ -146,7 +146,7 @@ void capture(mp_batch b, hipStream_t caller) {
                 mp_step_iter_nbr(f, it, bs);
                 int32_t t = 0;
                 char* slot = htab.data() + ((size_t)it * n + queued.size()) * argb;
-                if (mp_lik_queue_plan(f, slot, &t)) {
+                if (mp_lik_queue_plan(f, slot, &t, bs)) {
                     hfirst[(size_t)it * (n + 1) + queued.size()] = tiles;
                     tiles += t;
                     queued.push_back(i);
@@ -272,7 +272,7 @@ void tune_queue(mp_batch b, hipStream_t s) {
     int32_t tiles = 0, q = 0;
     for (mp_filter f : b->f) {
         int32_t t = 0;
-        if (mp_lik_queue_plan(f, tab.data() + (size_t)q * argb, &t)) {
+        if (mp_lik_queue_plan(f, tab.data() + (size_t)q * argb, &t, s)) {
             first[q++] = tiles;
             tiles += t;
         }

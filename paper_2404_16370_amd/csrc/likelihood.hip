@@ -575,6 +575,24 @@ __global__ __launch_bounds__(256) void k_solve(SolveArgs A) {
     }
 }
 
+
+// Morton key (8 bits per axis over the map box, z y x interleaved from the
+// top bit) of each particle's translation, and the particle's index
+__global__ void k_walk_keys(const float4* __restrict__ poses, int n, float lo0, float lo1, float lo2, float s0,
+                            float s1, float s2, uint32_t* __restrict__ keys, int32_t* __restrict__ idx) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float4 t = poses[2 * i + 1];
+    const float c0 = fminf(fmaxf((t.x - lo0) * s0, 0.0f), 255.0f);
+    const float c1 = fminf(fmaxf((t.y - lo1) * s1, 0.0f), 255.0f);
+    const float c2 = fminf(fmaxf((t.z - lo2) * s2, 0.0f), 255.0f);
+    const uint32_t x = (uint32_t)c0, y = (uint32_t)c1, z = (uint32_t)c2;   // NaN -> 0
+    uint32_t key = 0;
+#pragma unroll
+    for (int b = 7; b >= 0; --b) key = (key << 3) | (((z >> b) & 1u) << 2) | (((y >> b) & 1u) << 1) | ((x >> b) & 1u);
+    keys[i] = key;
+    idx[i] = i;
+}
 }  // namespace
 
 // layout of the likelihood launch: lane per particle, or 16 lanes per particle
@@ -582,6 +600,44 @@ static bool lik_grouped(mp_filter f) {
     if (f->p.lik_layout == MP_LIK_LAYOUT_PARTICLE) return false;
     if (f->p.lik_layout == MP_LIK_LAYOUT_GROUPED) return true;
     return f->n >= 2048 && f->scan_n >= 512;
+}
+
+// Walk order of the particles in a likelihood pass.  With enough work per
+// pass the particles are visited in Morton order of their translations, so
+// that the workgroups running at once (and each XCD's contiguous share of
+// them) gather records of one part of the map: 26.6 -> 24.6 ms per launch at
+// 1M x 8192 against the LSH order, whose adjacent codes are not neighbours in
+// space while the particles are spread.  The order changes no particle's sums.
+static bool lik_spatial(mp_filter f, int scorer) {
+    return scorer != MP_SCORER_SURROGATE && lik_grouped(f) && (int64_t)f->n * (int64_t)f->scan_n >= (1LL << 27);
+}
+
+static const int32_t* lik_order(mp_filter f, int scorer) {
+    return lik_spatial(f, scorer) ? f->lorder.as<int32_t>() : f->sorted.as<int32_t>();
+}
+
+// the spatial walk order of the current poses into lorder (a stable sort of
+// the 24-bit keys: ties keep ascending particle index); the LSH sort's
+// ping-pong buffers and scratch are free while the likelihood runs
+static void lik_prepare_order(mp_filter f, int scorer, hipStream_t s) {
+    if (!lik_spatial(f, scorer)) return;
+    const int n = f->n;
+    float lo[3], sc[3];
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = f->lsh_lo[a];
+        sc[a] = 256.0f / std::max(1e-3f, f->lsh_hi[a] - f->lsh_lo[a]);
+    }
+    constexpr int kBits = 24;
+    // start on the side that makes the last pass land in (lkeys, lorder)
+    const bool odd = mp_radix_passes(n, kBits) % 2 == 1;
+    uint32_t* k0 = odd ? f->tmp_keys.as<uint32_t>() : f->lkeys.as<uint32_t>();
+    int32_t* v0 = odd ? f->tmp_vals.as<int32_t>() : f->lorder.as<int32_t>();
+    uint32_t* k1 = odd ? f->lkeys.as<uint32_t>() : f->tmp_keys.as<uint32_t>();
+    int32_t* v1 = odd ? f->lorder.as<int32_t>() : f->tmp_vals.as<int32_t>();
+    k_walk_keys<<<(n + 255) / 256, 256, 0, s>>>(f->poses[f->cur].as<float4>(), n, lo[0], lo[1], lo[2], sc[0], sc[1],
+                                                 sc[2], k0, v0);
+    MP_CHECK_LAUNCH();
+    mp_radix_sort_u32_inplace_parity(k0, v0, k1, v1, n, kBits, f->hist, s);
 }
 
 // scan-point chunks per particle tile and the chunk length
@@ -635,7 +691,7 @@ LikPlan lik_plan(mp_filter f) {
     LikArgs& A = P.A;
     A.map = f->map->view;
     A.poses = f->poses[f->cur].as<float4>();
-    A.order = f->sorted.as<int32_t>();
+    A.order = lik_order(f, P.scorer);
     A.scan = f->scan.as<float4>();
     A.partial = f->partial.as<float>();
     A.n = n;
@@ -652,13 +708,14 @@ LikPlan lik_plan(mp_filter f) {
     return P;
 }
 
-// psi, log-likelihood and inliers from the pass's chunk partials
-void lik_solve(mp_filter f, bool grouped, int nch, hipStream_t s) {
+// psi, log-likelihood and inliers from the pass's chunk partials (GROUPED:
+// indexed by position in the pass's walk order)
+void lik_solve(mp_filter f, bool grouped, int nch, const int32_t* order, hipStream_t s) {
     const int n = f->n;
     const int ns = f->scan_n;
     SolveArgs S;
     S.partial = f->partial.as<float>();
-    S.order = (grouped && ns > 0) ? f->sorted.as<int32_t>() : nullptr;
+    S.order = (grouped && ns > 0) ? order : nullptr;
     S.psi = f->psi.as<float4>();
     S.hb = f->capture_hb ? f->hb.as<float>() : nullptr;
     S.how = f->capture_hb ? f->solve_how.as<int32_t>() : nullptr;
@@ -676,6 +733,7 @@ void lik_solve(mp_filter f, bool grouped, int nch, hipStream_t s) {
 
 void mp_launch_likelihood(mp_filter f, hipStream_t s) {
     LikPlan P = lik_plan(f);
+    lik_prepare_order(f, P.scorer, s);
     const LikArgs& A = P.A;
     const int scorer = P.scorer;
     const int n = f->n;
@@ -727,16 +785,17 @@ void mp_launch_likelihood(mp_filter f, hipStream_t s) {
         mp_fill_u32(A.partial, 0u, (size_t)kNumPartial * n, s);
         nch = 1;
     }
-    lik_solve(f, grouped, nch, s);
+    lik_solve(f, grouped, nch, A.order, s);
 }
 
 // ------------------------------------------------------------ tile queue
 size_t mp_lik_args_bytes() { return sizeof(LikArgs); }
 
-bool mp_lik_queue_plan(mp_filter f, void* args_out, int32_t* tiles) {
+bool mp_lik_queue_plan(mp_filter f, void* args_out, int32_t* tiles, hipStream_t s) {
     if (f->scan_n <= 0) return false;
     const LikPlan P = lik_plan(f);
     if (!P.grouped || P.scorer != MP_SCORER_PLAIN || P.A.map.backend != MP_NNF_DENSE) return false;
+    lik_prepare_order(f, P.scorer, s);
     std::memcpy(args_out, &P.A, sizeof(LikArgs));
     *tiles = P.A.nbx * P.nch;
     return true;
@@ -744,7 +803,7 @@ bool mp_lik_queue_plan(mp_filter f, void* args_out, int32_t* tiles) {
 
 void mp_lik_queue_solve(mp_filter f, hipStream_t s) {
     const LikPlan P = lik_plan(f);
-    lik_solve(f, P.grouped, P.nch, s);
+    lik_solve(f, P.grouped, P.nch, P.A.order, s);
 }
 
 static int queue_batch(int batch) { return batch == 8 ? 8 : (batch == 4 ? 4 : 2); }

@@ -152,6 +152,7 @@ struct mp_filter_s {
     DevMem solve_how;         // N int32 (debug): 0 FP32 Cholesky, 1 FP64 re-solve, 2 both failed (psi = 0)
     DevMem partial;           // chunks x 28 x N float
     DevMem codes, sorted, scodes, tmp_keys, tmp_vals, head, end, hist;  // LSH / sort
+    DevMem lkeys, lorder;     // the likelihood's walk order: Morton keys, particle per position
     DevMem rank;   // sorted position of each particle (the refresh runs in particle order)
     DevMem nbr, kval, cnt;    // K x N, K x N, N
     DevMem prior, post0, post1;   // N float
@@ -230,9 +231,10 @@ void mp_launch_refresh(mp_filter f, hipStream_t s, int window = -1);
 void mp_launch_likelihood(mp_filter f, hipStream_t s);
 // Likelihood passes of several filters through one persistent tile queue
 // (GROUPED layout, PLAIN scorer, dense field): the plan of a pass (false if it cannot
-// join a queue), the solve that follows the queue, the queue launch.
+// join a queue; otherwise the pass's walk order is launched on s), the solve that
+// follows the queue, the queue launch.
 size_t mp_lik_args_bytes();
-bool mp_lik_queue_plan(mp_filter f, void* args_out, int32_t* tiles);
+bool mp_lik_queue_plan(mp_filter f, void* args_out, int32_t* tiles, hipStream_t s);
 void mp_lik_queue_solve(mp_filter f, hipStream_t s);
 int mp_lik_queue_grid(int batch);
 void mp_launch_lik_queue(const void* tab_dev, const int32_t* first_dev, int32_t* counter_dev, int n_inst, int tiles,
