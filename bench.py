@@ -800,8 +800,8 @@ def _med_p90(v):
 
 def stage_roofline(stages, wl, lik_flops_launch, t_step):
     """Each stage of one filter step against the resource that bounds it.
-    `frac` takes the algorithmic bytes per particle of the scope table: what
-    the method must move, neighbour gathers included (prediction 56 B per
+    `frac` takes the algorithmic bytes per particle: what the method must
+    move, neighbour gathers included (prediction 56 B per
     frame; LSH 36 B; sort 16 B per 8-bit pass + 12 B of bucket bounds;
     refresh 28 + 4K + 32C + 32K + 8K; SVGD 28 + 8K + 56K; posterior 20 + R
     (12K + 4)).  A fraction above 1 means the caches serve the gathers.

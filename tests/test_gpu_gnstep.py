@@ -127,7 +127,7 @@ def test_psi_per_particle(room, O, layout, n, nscan):
     ko, rel, ok = _check_psi(psi[:, :6], hb, how, ref, 1e-3, 1e-6, "layout %d" % layout)
     # Marquardt damping keeps the scaled system's condition below about 6 / lam_rel
     assert np.all(ko[ok] < 1e4) and np.all(how == 0)
-    # the survey's FP32 estimate: about kappa 1e-7 relative; with the FP32
+    # an FP32 solve is good to about kappa x 1e-7 relative; with the FP32
     # sums' own error (a few 1e-6 of the largest entry) 1e-3 covers every particle
     assert rel[ok].max() < 1e-3, rel[ok].max()
 
