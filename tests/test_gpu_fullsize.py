@@ -63,6 +63,8 @@ def test_campus_stages(campus, O):
     s, h, e = O.bucket_sort(ref)
     assert np.array_equal(f.debug_get("sorted"), s)
     assert np.array_equal(f.debug_get("head"), h) and np.array_equal(f.debug_get("end"), e)
+    # no workgroup of the sort stopped waiting for its predecessors' digit counts
+    assert f.debug_get("sort_wait")[0] == 0
     # neighbour refresh: compare 2048 sampled particles (the oracle refreshes all, cheaply)
     f.debug_stage(M.MP_STAGE_REFRESH)
     nbr = f.debug_get("nbr").T
