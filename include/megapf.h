@@ -583,10 +583,10 @@ MP_API mp_status mp_odometry(mp_filter f, const mp_odometry_params* params, cons
 
 /* mp_odometry for callers that cannot allocate device memory (code under HIP
  * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
- * same computation and results, bit for bit, with its work arrays (per-point
- * terms and matches, the pose state) in a fixed device area of 1.9 MB that
- * the library holds on each device it runs on until the process ends; no
- * hipMalloc, hipFree or allocating library call.  The filter's scans are the
+ * same computation and results, bit for bit, with its work arrays (match
+ * keys, matches, per-workgroup sums, the pose state) in a fixed device area
+ * of 0.21 MB that the library holds on each device it runs on until the
+ * process ends; no hipMalloc, hipFree or allocating library call.  The filter's scans are the
  * inputs, the host outputs as in mp_odometry.  The current scan may hold at
  * most 16384 points (MP_E_ARG beyond).  Every call on a device shares that
  * device's area: calls that overlap on one device (several host threads or

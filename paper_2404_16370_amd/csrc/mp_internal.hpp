@@ -165,7 +165,7 @@ struct mp_filter_s {
     DevMem prev_orig;         // the previous non-empty scan's records (caller order), for odometry
     int32_t prev_n = 0;       // its points (0: none yet)
     int32_t orig_n = 0;       // points of the records in scan_orig (the last non-empty scan)
-    DevMem odo_terms, odo_nn, odo_state;   // odometry work arrays
+    DevMem odo_key, odo_nn, odo_part, odo_state;   // odometry work arrays
     DevMem scan_cov;          // n x 6 float staging of caller covariances
     DevMem scan_work;         // walk-order keys and work arrays (4n words) + lo/bad (4 floats)
     DevMem scan_sort;         // radix-sort scratch of the walk order

@@ -17,9 +17,15 @@
 // dT <- dT exp(psi) (FP64 pose, FP32 copy for the next evaluation).  After
 // the last update the terms are evaluated once more: Sigma^dT = scale H^-1.
 //
-// Launch shape: 16 lanes per source point (each scans every 16th target
-// point of LDS tiles of 2048), the 16 running minima merged by shuffles;
-// one workgroup reduces the per-point terms and takes the step.
+// Launch shape per iteration: the neighbour search over a grid of (source
+// block, target block) pairs, each target block staged in LDS and read as
+// broadcasts, one source point per lane; a block's minimum goes into the
+// point's 64-bit key (distance bits, index) by an atomic minimum, which for
+// non-negative distances is the lowest distance and, among equal ones, the
+// lowest index, whatever the order of the blocks.  Then one lane per source
+// point forms its terms and each workgroup sums its points' terms in FP64 in
+// a fixed order; one workgroup adds the workgroups' sums in order and takes
+// the step.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -34,68 +40,71 @@
 
 namespace {
 
-constexpr int kOL = 16;        // lanes per source point
-constexpr int kOB = 256;       // threads per workgroup
-constexpr int kOTile = 2048;   // target points per LDS tile
-constexpr int kOTerms = 28;    // H (21), b (6), cost per source point
+constexpr int kNnThreads = 256;   // source points per search workgroup
+constexpr int kNnTargets = 512;   // target points per search workgroup (LDS)
+constexpr int kTB = 256;          // source points per terms workgroup
+constexpr int kOTerms = 29;       // H (21), b (6), cost, inlier count per source point
+constexpr int kSumGroups = 8;     // terms of a workgroup summed in 8 runs of kTB / 8 points
+constexpr uint64_t kNoMatch = ~0ull;
 
-struct OdoTermArgs {
+__device__ __forceinline__ float3 odo_point(const float* pose, const mpdet::mat3& Rm, const float4 r) {
+    return mpdet::xform(Rm.m, make_float3(pose[4], pose[5], pose[6]), make_float3(r.x, r.y, r.z));
+}
+
+struct OdoNnArgs {
     const float4* __restrict__ trec;   // previous scan records (3 float4 per point)
     const float4* __restrict__ srec;   // current scan records
     const float* __restrict__ pose;    // FP32 pose (qw, qx, qy, qz, tx, ty, tz, 0)
-    float* __restrict__ terms;         // ns x 28
-    int32_t* __restrict__ nn;          // ns: target index or -1
+    unsigned long long* __restrict__ key;   // ns: (distance bits << 32) | index, kNoMatch before the search
     int32_t nt, ns;
+};
+
+__global__ __launch_bounds__(kNnThreads) void k_odo_nn(OdoNnArgs A) {
+    __shared__ float3 tile[kNnTargets];
+    const int j0 = blockIdx.y * kNnTargets;
+    const int cnt = min(kNnTargets, A.nt - j0);
+    for (int u = threadIdx.x; u < cnt; u += kNnThreads) {
+        const float4 r = A.trec[3 * (j0 + u)];
+        tile[u] = make_float3(r.x, r.y, r.z);
+    }
+    __syncthreads();
+    const int k = blockIdx.x * kNnThreads + threadIdx.x;
+    if (k >= A.ns) return;
+    const mpdet::mat3 Rm = mpdet::qmat(mpdet::quat{A.pose[0], A.pose[1], A.pose[2], A.pose[3]});
+    const float3 p = odo_point(A.pose, Rm, A.srec[3 * k]);
+    float bd = __builtin_inff();
+    int bj = j0;
+    for (int u = 0; u < cnt; ++u) {   // ascending j, strict <: the lower index wins ties
+        const float3 q = tile[u];
+        const float dx = q.x - p.x, dy = q.y - p.y, dz = q.z - p.z;
+        const float d2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
+        if (d2 < bd) {
+            bd = d2;
+            bj = j0 + u;
+        }
+    }
+    // d2 >= +0 (a sum of squares, never -0): its bits order as the values do
+    atomicMin(A.key + k, ((unsigned long long)__float_as_uint(bd) << 32) | (uint32_t)bj);
+}
+
+struct OdoTermArgs {
+    const float4* __restrict__ trec;
+    const float4* __restrict__ srec;
+    const float* __restrict__ pose;
+    unsigned long long* __restrict__ key;   // read, then reset to kNoMatch for the next search
+    int32_t* __restrict__ nn;          // ns: target index or -1
+    double* __restrict__ part;         // per workgroup: kOTerms FP64 sums
+    int32_t ns;
     float dmax2;
 };
 
-__global__ __launch_bounds__(kOB) void k_odo_terms(OdoTermArgs A) {
-    __shared__ float3 tile[kOTile];
-    const int grp = threadIdx.x / kOL, gl = threadIdx.x % kOL;
-    const int k = blockIdx.x * (kOB / kOL) + grp;
-    const bool active = k < A.ns;   // uniform over the point's 16 lanes
-    const mpdet::mat3 Rm = mpdet::qmat(mpdet::quat{A.pose[0], A.pose[1], A.pose[2], A.pose[3]});
-    const float3 t = make_float3(A.pose[4], A.pose[5], A.pose[6]);
-    const float4 s0 = active ? A.srec[3 * k] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+// The GICP terms of one source point given its nearest target (zero for an
+// outlier); t[28] is the inlier count.
+__device__ __forceinline__ void odo_point_terms(const OdoTermArgs& A, const mpdet::mat3& Rm, const int k,
+                                                const int bj, float t[kOTerms]) {
+    const float4 s0 = A.srec[3 * k];
     const float3 mu = make_float3(s0.x, s0.y, s0.z);
-    const float3 p = mpdet::xform(Rm.m, t, mu);
-    float bd = __builtin_inff();
-    int bj = 0x7FFFFFFF;
-    for (int base = 0; base < A.nt; base += kOTile) {
-        const int cnt = min(kOTile, A.nt - base);
-        __syncthreads();
-        for (int u = threadIdx.x; u < cnt; u += kOB) {
-            const float4 r = A.trec[3 * (base + u)];
-            tile[u] = make_float3(r.x, r.y, r.z);
-        }
-        __syncthreads();
-        if (!active) continue;
-        for (int u = gl; u < cnt; u += kOL) {   // ascending j, strict <: the lower index wins ties
-            const float3 q = tile[u];
-            const float dx = q.x - p.x, dy = q.y - p.y, dz = q.z - p.z;
-            const float d2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
-            if (d2 < bd) {
-                bd = d2;
-                bj = base + u;
-            }
-        }
-    }
-#pragma unroll
-    for (int off = kOL / 2; off >= 1; off >>= 1) {
-        const float od = __shfl_xor(bd, off, 64);
-        const int oj = __shfl_xor(bj, off, 64);
-        const bool take = od < bd || (od == bd && oj < bj);
-        bd = take ? od : bd;
-        bj = take ? oj : bj;
-    }
-    if (!active || gl != 0) return;
-    float* out = A.terms + (size_t)kOTerms * k;
-    const bool inl = bj != 0x7FFFFFFF && bd <= A.dmax2;
-    A.nn[k] = inl ? bj : -1;
-    if (!inl) {
-        for (int m = 0; m < kOTerms; ++m) out[m] = 0.0f;
-        return;
-    }
+    const float3 p = odo_point(A.pose, Rm, s0);
     const float4 t0 = A.trec[3 * bj], t1 = A.trec[3 * bj + 1], t2 = A.trec[3 * bj + 2];
     const float4 s1 = A.srec[3 * k + 1], s2 = A.srec[3 * k + 2];
     const float3 eb = mpdet::rot_t(Rm, make_float3(t0.x - p.x, t0.y - p.y, t0.z - p.z));
@@ -128,9 +137,48 @@ __global__ __launch_bounds__(kOB) void k_odo_terms(OdoTermArgs A) {
         for (int c = 0; c < 6; ++c) OJ[r][c] = O[r][0] * J[0][c] + O[r][1] * J[1][c] + O[r][2] * J[2][c];
     int q = 0;
     for (int r = 0; r < 6; ++r)
-        for (int c = r; c < 6; ++c) out[q++] = J[0][r] * OJ[0][c] + J[1][r] * OJ[1][c] + J[2][r] * OJ[2][c];
-    for (int r = 0; r < 6; ++r) out[21 + r] = J[0][r] * w[0] + J[1][r] * w[1] + J[2][r] * w[2];
-    out[27] = e[0] * w[0] + e[1] * w[1] + e[2] * w[2];
+        for (int c = r; c < 6; ++c) t[q++] = J[0][r] * OJ[0][c] + J[1][r] * OJ[1][c] + J[2][r] * OJ[2][c];
+    for (int r = 0; r < 6; ++r) t[21 + r] = J[0][r] * w[0] + J[1][r] * w[1] + J[2][r] * w[2];
+    t[27] = e[0] * w[0] + e[1] * w[1] + e[2] * w[2];
+    t[28] = 1.0f;
+}
+
+// One lane per source point: its match, its terms into LDS, then the
+// workgroup's FP64 sums in a fixed order (kSumGroups runs of consecutive
+// points per term, then the runs in order).
+__global__ __launch_bounds__(kTB) void k_odo_terms(OdoTermArgs A) {
+    __shared__ float tt[kOTerms][kTB];
+    __shared__ double run[kOTerms][kSumGroups];
+    const int k = blockIdx.x * kTB + threadIdx.x;
+    float t[kOTerms];
+    for (int m = 0; m < kOTerms; ++m) t[m] = 0.0f;
+    if (k < A.ns) {
+        const unsigned long long key = A.key[k];
+        A.key[k] = kNoMatch;
+        const float bd = __uint_as_float((uint32_t)(key >> 32));
+        const int bj = (int)(uint32_t)key;
+        const bool inl = key != kNoMatch && bd <= A.dmax2;
+        A.nn[k] = inl ? bj : -1;
+        if (inl) {
+            const mpdet::mat3 Rm = mpdet::qmat(mpdet::quat{A.pose[0], A.pose[1], A.pose[2], A.pose[3]});
+            odo_point_terms(A, Rm, k, bj, t);
+        }
+    }
+    for (int m = 0; m < kOTerms; ++m) tt[m][threadIdx.x] = t[m];
+    __syncthreads();
+    constexpr int kRun = kTB / kSumGroups;
+    for (int q = threadIdx.x; q < kOTerms * kSumGroups; q += kTB) {
+        const int m = q / kSumGroups, g = q % kSumGroups;
+        double acc = 0.0;
+        for (int i = 0; i < kRun; ++i) acc += (double)tt[m][g * kRun + i];
+        run[m][g] = acc;
+    }
+    __syncthreads();
+    if (threadIdx.x < kOTerms) {
+        double acc = 0.0;
+        for (int g = 0; g < kSumGroups; ++g) acc += run[threadIdx.x][g];
+        A.part[(size_t)blockIdx.x * kOTerms + threadIdx.x] = acc;
+    }
 }
 
 // SE(3) exponential of [omega; v] (FP64): unit quaternion + translation V v
@@ -161,41 +209,23 @@ __device__ void se3_exp_d(const double xi[6], double T[7]) {
 }
 
 struct OdoStepArgs {
-    const float* __restrict__ terms;
-    const int32_t* __restrict__ nn;
+    const double* __restrict__ part;   // nparts x kOTerms workgroup sums
     double* __restrict__ pose64;   // 7
     float* __restrict__ pose32;    // 8
     double* __restrict__ out;      // final: H 21, b 6, cost, inliers, cov 36, ok
-    int32_t ns, final_eval;
+    int32_t nparts, final_eval;
     double lam_rel, lam_abs, cov_scale;
 };
 
-__device__ inline double wave_sum_d(double v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
-// One workgroup: FP64 sums of the per-point terms (each thread a fixed
-// stride of points, then a fixed butterfly), then the step or the covariance.
-__global__ __launch_bounds__(256) void k_odo_step(OdoStepArgs A) {
-    __shared__ double red[4][kOTerms + 1];
-    __shared__ double tot[kOTerms + 1];
-    double acc[kOTerms + 1];
-    for (int m = 0; m <= kOTerms; ++m) acc[m] = 0.0;
-    for (int k = threadIdx.x; k < A.ns; k += 256) {
-        const float* v = A.terms + (size_t)kOTerms * k;
-        for (int m = 0; m < kOTerms; ++m) acc[m] += (double)v[m];
-        acc[kOTerms] += A.nn[k] >= 0 ? 1.0 : 0.0;
+// One workgroup: the workgroup sums added in order, then the step or the
+// covariance.
+__global__ __launch_bounds__(64) void k_odo_step(OdoStepArgs A) {
+    __shared__ double tot[kOTerms];
+    if (threadIdx.x < kOTerms) {
+        double acc = 0.0;
+        for (int g = 0; g < A.nparts; ++g) acc += A.part[(size_t)g * kOTerms + threadIdx.x];
+        tot[threadIdx.x] = acc;
     }
-    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int m = 0; m <= kOTerms; ++m) {
-        const double s = wave_sum_d(acc[m]);
-        if (lane == 0) red[wv][m] = s;
-    }
-    __syncthreads();
-    if (threadIdx.x <= kOTerms) tot[threadIdx.x] = ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) +
-                                                     red[3][threadIdx.x];
     __syncthreads();
     if (threadIdx.x != 0) return;
     const double* H = tot;
@@ -228,7 +258,7 @@ __global__ __launch_bounds__(256) void k_odo_step(OdoStepArgs A) {
     }
     for (int m = 0; m < 27; ++m) A.out[m] = tot[m];
     A.out[27] = tot[27];
-    A.out[28] = tot[kOTerms];
+    A.out[28] = tot[28];
     // Sigma = scale H^-1: column j solves H x = e_j (the undamped solve with b = -e_j)
     bool ok = true;
     for (int jc = 0; jc < 6; ++jc) {
@@ -268,13 +298,16 @@ struct OdoCall {
     char* scratch;   // device address of the fixed work area, or null: the filter's buffers
 };
 
-// Layout of the work area: per-source-point terms, matches, then the pose state.
+// Layout of the work area: match keys, matches, workgroup sums, then the
+// pose state.
 constexpr size_t kNoAllocScan = 16384;   // largest current scan of mp_odometry_noalloc
 constexpr size_t kStateBytes = sizeof(double) * (8 + 66) + sizeof(float) * 8;
-constexpr size_t kScrNn = sizeof(float) * kOTerms * kNoAllocScan;
-constexpr size_t kScrState = kScrNn + sizeof(int32_t) * kNoAllocScan;
+constexpr size_t kScrNn = sizeof(unsigned long long) * kNoAllocScan;
+constexpr size_t kScrPart = kScrNn + sizeof(int32_t) * kNoAllocScan;
+constexpr size_t kScrState = kScrPart + sizeof(double) * kOTerms * (kNoAllocScan / kTB);
 constexpr size_t kScratchBytes = kScrState + kStateBytes;
-static_assert(kScrNn % 256 == 0 && kScrState % 256 == 0, "aligned sections");
+static_assert(kNoAllocScan % kTB == 0, "whole workgroups");
+static_assert(kScrNn % 256 == 0 && kScrPart % 256 == 0 && kScrState % 256 == 0, "aligned sections");
 
 void odometry_impl(void* ctx) {
     OdoCall& c = *static_cast<OdoCall*>(ctx);
@@ -298,24 +331,29 @@ void odometry_impl(void* ctx) {
     }
     hipStream_t s = c.s;
     const int ns = f->scan_n, nt = f->prev_n;
-    float* terms = nullptr;
+    const int nparts = (ns + kTB - 1) / kTB;
+    unsigned long long* key = nullptr;
     int32_t* nn = nullptr;
+    double* part = nullptr;
     double* pose64 = nullptr;
     if (c.scratch) {
         // the caller's fixed work area: no allocation
         if ((size_t)ns > kNoAllocScan)
             mp_throw(MP_E_ARG, "mp_odometry_noalloc: current scan of %d points exceeds its limit of %d", ns,
                      (int)kNoAllocScan);
-        terms = reinterpret_cast<float*>(c.scratch);
+        key = reinterpret_cast<unsigned long long*>(c.scratch);
         nn = reinterpret_cast<int32_t*>(c.scratch + kScrNn);
+        part = reinterpret_cast<double*>(c.scratch + kScrPart);
         pose64 = reinterpret_cast<double*>(c.scratch + kScrState);
     } else {
-        f->odo_terms.ensure(sizeof(float) * kOTerms * (size_t)ns);
+        f->odo_key.ensure(sizeof(unsigned long long) * (size_t)ns);
         f->odo_nn.ensure(sizeof(int32_t) * (size_t)ns);
+        f->odo_part.ensure(sizeof(double) * kOTerms * (size_t)nparts);
         // state: pose64 (8 doubles), out (66 doubles), pose32 (8 floats)
         f->odo_state.ensure(kStateBytes);
-        terms = f->odo_terms.as<float>();
+        key = f->odo_key.as<unsigned long long>();
         nn = f->odo_nn.as<int32_t>();
+        part = f->odo_part.as<double>();
         pose64 = f->odo_state.as<double>();
     }
     double* out = pose64 + 8;
@@ -328,31 +366,41 @@ void odometry_impl(void* ctx) {
     h_pose32[7] = 0.0f;
     MP_HIP(hipMemcpyAsync(pose64, h_state, sizeof(h_state), hipMemcpyHostToDevice, s));
     MP_HIP(hipMemcpyAsync(pose32, h_pose32, sizeof(h_pose32), hipMemcpyHostToDevice, s));
+    // every key starts unmatched; each terms pass leaves them so again
+    mp_fill_u32(key, 0xFFFFFFFFu, 2 * (size_t)ns, s);
+    OdoNnArgs Q;
+    Q.trec = f->prev_orig.as<float4>();
+    Q.srec = f->scan_orig.as<float4>();
+    Q.pose = pose32;
+    Q.key = key;
+    Q.nt = nt;
+    Q.ns = ns;
     OdoTermArgs T;
-    T.trec = f->prev_orig.as<float4>();
-    T.srec = f->scan_orig.as<float4>();
+    T.trec = Q.trec;
+    T.srec = Q.srec;
     T.pose = pose32;
-    T.terms = terms;
+    T.key = key;
     T.nn = nn;
-    T.nt = nt;
+    T.part = part;
     T.ns = ns;
     T.dmax2 = P.d_max * P.d_max;
     OdoStepArgs U;
-    U.terms = T.terms;
-    U.nn = T.nn;
+    U.part = part;
     U.pose64 = pose64;
     U.pose32 = pose32;
     U.out = out;
-    U.ns = ns;
+    U.nparts = nparts;
     U.lam_rel = P.lambda_rel;
     U.lam_abs = P.lambda_abs;
     U.cov_scale = P.cov_scale;
-    const unsigned grid = (unsigned)((ns + kOB / kOL - 1) / (kOB / kOL));
+    const dim3 nn_grid((unsigned)((ns + kNnThreads - 1) / kNnThreads), (unsigned)((nt + kNnTargets - 1) / kNnTargets));
     for (int it = 0; it <= P.iterations; ++it) {
-        k_odo_terms<<<grid, kOB, 0, s>>>(T);
+        k_odo_nn<<<nn_grid, kNnThreads, 0, s>>>(Q);
+        MP_CHECK_LAUNCH();
+        k_odo_terms<<<(unsigned)nparts, kTB, 0, s>>>(T);
         MP_CHECK_LAUNCH();
         U.final_eval = it == P.iterations ? 1 : 0;
-        k_odo_step<<<1, 256, 0, s>>>(U);
+        k_odo_step<<<1, 64, 0, s>>>(U);
         MP_CHECK_LAUNCH();
     }
     MP_HIP(hipMemcpyAsync(h_state, pose64, sizeof(h_state), hipMemcpyDeviceToHost, s));
@@ -381,7 +429,7 @@ extern "C" mp_status mp_odometry(mp_filter f, const mp_odometry_params* params, 
     return mp_guarded_call("mp_odometry", odometry_impl, &c);
 }
 
-// Work area of mp_odometry_noalloc (2.0 MB): one copy per device, held until
+// Work area of mp_odometry_noalloc (0.21 MB): one copy per device, held until
 // the process ends.  Host code never uses this name as an address: the device
 // address comes from hipGetSymbolAddress, once per device.
 static __device__ __align__(256) char scratch[kScratchBytes];
