@@ -31,16 +31,15 @@ TRAIN_MACS = 192 * 128 * 2 + 128 * 128 * 3        # matrix-core MACs per trainin
 PEAK_HBM = 8.0e12           # bytes/s
 # FP32 operations of one likelihood evaluation in k_lik (an fma counts 2):
 #   inlier:  transform 18, voxel key 3, residual and gate 8, R^T n and R^T e 30,
-#            Sherman-Morrison Omega 39 (q = P u 15, u^T q 5, beta 4, Omega 15),
-#            Omega e and cost 20, cost add 1, b 18, [mu]x Omega 27, H_ww 24,
-#            H_wv 9, H_vv 12                                           = 209
+#            Sherman-Morrison Omega 42 (D u 15, q = u - D u 3, u^T D u 5,
+#            beta 4, Omega 15), Omega e and cost 20, cost add 1, b 18,
+#            [mu]x Omega 27, H_ww 24, H_wv 9, H_vv 12                  = 212
 #   outlier: transform 18, voxel key 3 (+ residual and gate 8 on an NNF hit) = 21..29
-FLOPS_INLIER = 209
+FLOPS_INLIER = 212
 FLOPS_OUTLIER = 21
 # the method's algorithmic count per evaluation (transform 18, rotate Sigma^M
 # 90, 3x3 inverse 46, residual and cost 45, H / b blocks 75, 28 accumulations)
 FLOPS_ALGORITHMIC = 300
-PEAK_FP32_UNPACKED = 78.6e12  # one non-packed wave64 FP32 FMA per four cycles per SIMD, 2.4 GHz
 GATHER_BYTES = 32           # one Gaussian record of the dense NNF per evaluation (the cell index is computed)
 
 WORKLOADS = {
@@ -985,8 +984,7 @@ def main():
                      "logical_gather_frac_of_hbm": evals_iter * GATHER_BYTES / t_launch / PEAK_HBM,
                      "flops_per_eval": {"kernel_inlier": FLOPS_INLIER, "kernel_outlier": FLOPS_OUTLIER,
                                         "algorithmic": FLOPS_ALGORITHMIC},
-                     "frac_at_algorithmic_flops": evals_iter * FLOPS_ALGORITHMIC / t_launch / PEAK_FP32,
-                     "frac_of_unpacked_fp32_peak": achieved / PEAK_FP32_UNPACKED},
+                     "frac_at_algorithmic_flops": evals_iter * FLOPS_ALGORITHMIC / t_launch / PEAK_FP32},
         "posterior": {"map_weight": q["map_weight"], "n_eff": q["n_eff"], "sum_w": float(q["weights"].sum())},
         "paper_context": {"filter_steps_per_s": round(1000.0 / 90.8, 2), "hardware": "NVIDIA A100",
                           "note": "the paper's 1,048,576-particle indoor run (90.8 ms per frame); its scan size and "

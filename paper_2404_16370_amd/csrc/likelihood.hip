@@ -94,11 +94,15 @@ __device__ __forceinline__ void add_cost(Acc& S, float y) {
     }
 }
 
-// Staged scan record: r0 = (mu, P00), r1 = (P01, P02, P11, P12), r2 = (P22, ..)
-// with P = (Sigma^S + I)^-1.  In the body frame C = Sigma^S + I - a u u^T
-// (u = R^T n), so Omega = C^-1 = P + beta q q^T with q = P u and
-// beta = a / (1 - a u^T q) (Sherman-Morrison; 1 - a u^T q > 0 whenever C is
-// positive definite).
+// Staged scan record: r0 = (mu, P00), r1 = (P01, P02, P11, P12),
+// r2 = (P22, D00, D11, D22) with P = (Sigma^S + I)^-1 and D = I - P =
+// Sigma^S P (its off-diagonal entries are -P_ij).  In the body frame
+// C = Sigma^S + I - a u u^T (u = R^T n), so Omega = C^-1 = P + beta q q^T with
+// q = P u = u - D u and beta = a / (1 - a u^T P u) (Sherman-Morrison).  The
+// denominator is the small eigenvalue-like term of C along u: formed as
+// 1 - a u^T P u it loses about 10 bits to cancellation when Sigma^S is thin
+// along u, so it is taken as lam_n + a u^T D u with lam_n = 1 - a |n|^2 from
+// the map record (the same quantity for |u| = |n|, both terms non-negative).
 template <bool KAHAN>
 __device__ __forceinline__ void accumulate(Acc& S, const mpdet::mat3& Rm, const float a, const float dmax2,
                                            const float cmax, const float4 r0, const float4 r1, const float4 r2,
@@ -111,11 +115,12 @@ __device__ __forceinline__ void accumulate(Acc& S, const mpdet::mat3& Rm, const 
     const float3 u = mpdet::rot_t(Rm, make_float3(gn.x, gn.y, gn.z));
     const float3 eb = mpdet::rot_t(Rm, make_float3(ex, ey, ez));
     const float p00 = r0.w, p01 = r1.x, p02 = r1.y, p11 = r1.z, p12 = r1.w, p22 = r2.x;
-    const float q0 = __builtin_fmaf(p00, u.x, __builtin_fmaf(p01, u.y, p02 * u.z));
-    const float q1 = __builtin_fmaf(p01, u.x, __builtin_fmaf(p11, u.y, p12 * u.z));
-    const float q2 = __builtin_fmaf(p02, u.x, __builtin_fmaf(p12, u.y, p22 * u.z));
-    const float uq = __builtin_fmaf(u.x, q0, __builtin_fmaf(u.y, q1, u.z * q2));
-    const float beta = a * __builtin_amdgcn_rcpf(__builtin_fmaf(-a, uq, 1.0f));
+    const float du0 = __builtin_fmaf(r2.y, u.x, __builtin_fmaf(-p01, u.y, -p02 * u.z));
+    const float du1 = __builtin_fmaf(-p01, u.x, __builtin_fmaf(r2.z, u.y, -p12 * u.z));
+    const float du2 = __builtin_fmaf(-p02, u.x, __builtin_fmaf(-p12, u.y, r2.w * u.z));
+    const float q0 = u.x - du0, q1 = u.y - du1, q2 = u.z - du2;
+    const float udu = __builtin_fmaf(u.x, du0, __builtin_fmaf(u.y, du1, u.z * du2));
+    const float beta = a * __builtin_amdgcn_rcpf(__builtin_fmaf(a, udu, gn.w));
     const float v0 = beta * q0, v1 = beta * q1, v2 = beta * q2;
     const float o00 = __builtin_fmaf(v0, q0, p00), o01 = __builtin_fmaf(v0, q1, p01);
     const float o02 = __builtin_fmaf(v0, q2, p02), o11 = __builtin_fmaf(v1, q1, p11);
@@ -159,10 +164,13 @@ __device__ __forceinline__ void accumulate(Acc& S, const mpdet::mat3& Rm, const 
     S.h[19] = __builtin_fmaf(m, o12, S.h[19]); S.h[20] = __builtin_fmaf(m, o22, S.h[20]);
 }
 
-// (Sigma^S + I)^-1 of a raw scan record r0 = (mu, S00), r1 = (S01, S02, S11,
-// S12), r2 = (S22, ..), written back into the same slots (adjugate / det; the
-// eigenvalues of Sigma^S + I are >= 1 for a positive semi-definite Sigma^S).
+// P = (Sigma^S + I)^-1 of a raw scan record r0 = (mu, S00), r1 = (S01, S02,
+// S11, S12), r2 = (S22, ..), written back into the same slots (adjugate / det;
+// the eigenvalues of Sigma^S + I are >= 1 for a positive semi-definite
+// Sigma^S), and the diagonal of D = Sigma^S P into r2.yzw (formed from
+// Sigma^S, not as 1 - P_ii).
 __device__ __forceinline__ void stage_inverse(float4& r0, float4& r1, float4& r2) {
+    const float s00 = r0.w, s01 = r1.x, s02 = r1.y, s11 = r1.z, s12 = r1.w, s22 = r2.x;
     const float c00 = r0.w + 1.0f, c01 = r1.x, c02 = r1.y, c11 = r1.z + 1.0f, c12 = r1.w, c22 = r2.x + 1.0f;
     const float i00 = __builtin_fmaf(c11, c22, -c12 * c12);
     const float i01 = __builtin_fmaf(c02, c12, -c01 * c22);
@@ -171,9 +179,12 @@ __device__ __forceinline__ void stage_inverse(float4& r0, float4& r1, float4& r2
     const float i12 = __builtin_fmaf(c01, c02, -c00 * c12);
     const float i22 = __builtin_fmaf(c00, c11, -c01 * c01);
     const float rd = 1.0f / __builtin_fmaf(c00, i00, __builtin_fmaf(c01, i01, c02 * i02));
-    r0.w = i00 * rd;
-    r1 = make_float4(i01 * rd, i02 * rd, i11 * rd, i12 * rd);
-    r2.x = i22 * rd;
+    const float p00 = i00 * rd, p01 = i01 * rd, p02 = i02 * rd, p11 = i11 * rd, p12 = i12 * rd, p22 = i22 * rd;
+    r0.w = p00;
+    r1 = make_float4(p01, p02, p11, p12);
+    r2 = make_float4(p22, __builtin_fmaf(s00, p00, __builtin_fmaf(s01, p01, s02 * p02)),
+                     __builtin_fmaf(s01, p01, __builtin_fmaf(s11, p11, s12 * p12)),
+                     __builtin_fmaf(s02, p02, __builtin_fmaf(s12, p12, s22 * p22)));
 }
 
 // Residual-field scorer (rank-1 Gauss-Newton on r = sqrt(s)):

@@ -436,9 +436,10 @@ __global__ void k_dense_records(const int32_t* __restrict__ dense, int64_t ncell
         drec[2 * c + 1] = gauss[2 * (int64_t)g + 1];
     } else {
         // no Gaussian: a mean 1e15 m away fails every residual gate, while
-        // squares and products of the residual stay finite in FP32
+        // squares and products of the residual stay finite in FP32; no normal
+        // (lam_n = 1 - a |0|^2 = 1 keeps the masked Omega finite)
         drec[2 * c] = make_float4(kFarMean, kFarMean, kFarMean, 0.0f);
-        drec[2 * c + 1] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        drec[2 * c + 1] = make_float4(0.0f, 0.0f, 0.0f, 1.0f);
     }
 }
 
