@@ -193,7 +193,7 @@ def odometry_leg(M, m, w, scans, cpu):
            "motion_deg": [q["motion_deg"] for q in pairs], "inliers": [q["inliers"] for q in pairs],
            "roofline": {"bound": "alu", "achieved": evals * 8 / t_med / 1e12, "peak": PEAK_FP32 / 1e12,
                         "unit": "TFLOP/s", "frac": evals * 8 / t_med / PEAK_FP32, "traffic": None,
-                        "kernel": "k_odo_terms + k_odo_step, 21 evaluations (8 flops per distance)"}}
+                        "kernel": "k_odo_nn + k_odo_terms + k_odo_step, 21 evaluations (8 flops per distance)"}}
     if cpu:
         import oracle as O
         dt, worst = [], 0.0
