@@ -41,7 +41,7 @@
 namespace {
 
 constexpr int kNnThreads = 256;   // source points per search workgroup
-constexpr int kNnTargets = 512;   // target points per search workgroup (LDS)
+constexpr int kNnTargets = 256;   // target points per search workgroup (LDS)
 constexpr int kTB = 256;          // source points per terms workgroup
 constexpr int kOTerms = 29;       // H (21), b (6), cost, inlier count per source point
 constexpr int kSumGroups = 8;     // terms of a workgroup summed in 8 runs of kTB / 8 points
