@@ -231,3 +231,37 @@ def test_chained_iteration(room, O, n, K, bits, win):
     wq = f.posterior_query(weights=True)["weights"]
     assert abs(wq.sum() - 1.0) < 1e-6
     assert np.abs(wq - post["post"]).max() < 1e-5
+
+
+@pytest.mark.parametrize("layout", [M.MP_LIK_LAYOUT_GROUPED, M.MP_LIK_LAYOUT_PARTICLE])
+def test_thin_scan_covariances_precision(room, O, layout):
+    """Scan covariances from the k-NN of points on walls are thin along the
+    wall normal, and particles near the true pose see most points as inliers
+    on those walls: the Sherman-Morrison denominator of Omega, the small
+    eigenvalue-like term of Sigma^M + R Sigma^S R^T along the normal, is then
+    about 1e-3 of its parts.  Formed as lam_n + a u^T D u it keeps FP32
+    accuracy (log-likelihood and H within a few 1e-6 of the FP64 oracle);
+    formed as 1 - a u^T P u it lost about 10 bits (8e-5).  The bound 2e-5
+    separates the two."""
+    w = room["w"]
+    scan = np.ascontiguousarray(w["scans"][0])
+    _, scov, _ = O.scan_cov(scan, k=10)
+    R, t = w["traj"][0]
+    poses = S.gaussian_particles(1024, S.pose8(R, t), 0.05, 0.1, 7).astype(np.float32)
+    p = M.mp_filter_default_params(n_particles=1024, k=8, lsh_bits=16, svgd_iters=1, window_c=16, d_max=1.0,
+                                   c_max=9.0, lik_layout=layout, seed=4001)
+    f = M.Filter(room["gpu"], p, poses=poses)
+    f.scan_upload(scan, cov6=scov)
+    f.debug_set("capture_hb", 1)
+    f.debug_stage(M.MP_STAGE_LIK)
+    psi, hb = f.debug_get("psi"), f.debug_get("hb")
+    ref = O.likelihood(room["ora"], scan, scov, poses, dmax=1.0, cmax=9.0)
+    assert np.array_equal(psi[:, 7].astype(np.int64), ref["ninl"].astype(np.int64))
+    assert np.median(ref["ninl"]) > 0.8 * len(scan)      # mostly inliers, as intended
+    ell = np.abs(psi[:, 6].astype(np.float64) - ref["loglik"]) / np.maximum(1.0, np.abs(ref["loglik"]))
+    H = hb[:, :21].astype(np.float64)
+    eh = np.abs(H - ref["H21"]).max(1) / np.abs(ref["H21"]).max(1)
+    print("layout %d: log-likelihood rel err max %.3g, H err max %.3g of max |H|" % (layout, ell.max(), eh.max()),
+          flush=True)
+    assert ell.max() < 2e-5, ell.max()
+    assert eh.max() < 2e-5, eh.max()
